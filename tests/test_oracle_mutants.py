@@ -1,0 +1,92 @@
+"""Plant plausible mistakes in copies of the C oracle and check the pins catch each.
+
+Every mutant is a one-place edit of oracle/ig_oracle.c compiled into a temporary
+library; the pins of test_oracle_pins (worked example, exhaustive enumeration)
+must fail on it.  This runs on the CPU only.
+"""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "ig_oracle.c")
+
+MUTANTS = {
+    # Eq. 6 operands transposed: "r inside b" instead of "b inside r"
+    "subset_transposed": ("if ((b[k] & r[k]) != b[k]) return 0;", "if ((b[k] & r[k]) != r[k]) return 0;"),
+    # Eq. 2 with |b| instead of |b|^2
+    "weight_not_squared": ("m->S[c][p] = (int64_t)f * (int64_t)len * (int64_t)len;",
+                           "m->S[c][p] = (int64_t)f * (int64_t)len;"),
+    # Eq. 1 without the records themselves
+    "no_signatures": ("if (is_empty(X + i * K, K)) continue;\n        memcpy",
+                      "if (1) continue;\n        memcpy"),
+    # support counted in the other class
+    "support_other_class": ("uint32_t f = support(b, Xc, nc, K);", "uint32_t f = support(b, Xo, no, K);"),
+    # Eq. 5 bit order reversed inside a word
+    "msb_first": ("out[i * K + bit / 64] |= (uint64_t)1 << (bit % 64);",
+                  "out[i * K + bit / 64] |= (uint64_t)1 << (63 - bit % 64);"),
+    # Eq. 4 with the classes exchanged
+    "scores_swapped": ("if (subset(m->words[1] + p * K, x, K)) a += m->S[1][p];",
+                       "if (subset(m->words[1] + p * K, x, K)) nn += m->S[1][p];"),
+    # Eq. 3 against the same class
+    "coherence_same_class": ("rc = fit_class(Xs[c], ns[c], Xs[1 - c], ns[1 - c], K, m, c);",
+                             "rc = fit_class(Xs[c], ns[c], Xs[c], ns[c], K, m, c);"),
+    # feature offsets off by one
+    "offset_off_by_one": ("for (uint32_t f = 0; f < d; ++f) { off[f] = acc; acc += nbins[f]; }",
+                          "for (uint32_t f = 0; f < d; ++f) { acc += nbins[f]; off[f] = acc - 1; }"),
+    # pairs restricted to neighbours
+    "pairs_neighbours_only": ("for (uint64_t j = i + 1; j < n; ++j) {\n            uint64_t *b = rows + m * K;",
+                              "for (uint64_t j = i + 1; j < n && j < i + 2; ++j) {\n            uint64_t *b = rows + m * K;"),
+    # first-cover position counted from zero
+    "t_off_by_one": ("if (subset(b, Xo + t * K, K)) return t + 1;", "if (subset(b, Xo + t * K, K)) return t + 2;"),
+}
+
+
+def _run_pins():
+    """Return True when every pin passes with the currently loaded oracle library."""
+    try:
+        pins.test_worked_example_c_oracle()
+        for s in range(12):
+            pins.test_exhaustive_enumeration(s)
+        pins.test_pack_bit_order()
+        pins.test_one_and_two_records()
+    except (AssertionError, oracle.OracleError):
+        return False
+    return True
+
+
+@pytest.fixture(scope="module")
+def src_text():
+    return open(SRC).read()
+
+
+def test_pins_pass_on_unmodified_oracle():
+    assert _run_pins()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, src_text, tmp_path):
+    old, new = MUTANTS[name]
+    assert src_text.count(old) == 1, f"mutation site of {name} not found exactly once"
+    mut = src_text.replace(old, new)
+    c_path = tmp_path / "mut.c"
+    so_path = tmp_path / "libmut.so"
+    c_path.write_text(mut)
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", str(so_path),
+                    str(c_path)], check=True)
+    saved = oracle._lib
+    try:
+        oracle._lib = None
+        path_saved = oracle.build_oracle.LIB
+        oracle.build_oracle.LIB = str(so_path)
+        oracle.lib()
+        caught = not _run_pins()
+    finally:
+        oracle.build_oracle.LIB = path_saved
+        oracle._lib = saved
+    assert caught, f"mutant {name} passed every pin"
