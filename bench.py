@@ -1,0 +1,160 @@
+"""Benchmark of the IG hot path on one MI355X.
+
+One step = ig_fit of the 15k workload (41 features, L = 464, K = 8; ~10.5k
+training records) followed by ig_score of its ~4.5k held-out flows, with every
+input already resident in HBM.  The reported throughput is subset tests per
+second: the tests the method has to make in one step --
+
+  coherence  sum over distinct candidates of t(b) (records of the other class
+             examined up to and including the first that contains b)   Eq. 3
+  support    |P^c| * n_c for both classes                              Eq. 2
+  scoring    (|P^0| + |P^1|) * n_flows                                 Eq. 4
+
+Also printed: the fit wall time at 15k and 148k, the roofline of the coherence
+kernel (integer VALU bound) and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu] [--no-148k]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "subset tests/sec + IG fit wall-time at 15k/148k; served flows/sec with p99 latency"
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer VALU op per lane per clock
+VALU_INT32_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-148k", action="store_true", help="skip the 148k fit wall time")
+    ap.add_argument("--cpu-records", type=int, default=6000, help="training records in the oracle sample")
+    ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "coherence_traffic_15k.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "described, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2507_14222_amd import ig, synth
+
+    torch.cuda.set_device(0)
+    w = synth.make_15k()
+    log("15k workload", w.codes.shape, "test", w.test_codes.shape)
+    d_codes = torch.from_numpy(w.codes.view(np.int16)).cuda()
+    d_labels = torch.from_numpy(w.labels).cuda()
+    d_flows = torch.from_numpy(w.test_codes.view(np.int16)).cuda()
+    out = torch.empty((w.test_codes.shape[0], 2), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        m = ig.fit(d_codes, d_labels, w.nbins, stream=stream)
+        ig.score(m, d_flows, out=out, stream=stream)
+        return m
+
+    for i in range(args.warmup):
+        m = step()
+        torch.cuda.synchronize()
+        log("warmup", i, "done")
+    torch.cuda.synchronize()
+    fit_s, coh_ms, models = [], [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        m = step()
+        fit_s.append(time.perf_counter() - a)   # ig_fit returns once the model is complete
+        models.append(m)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log("timed steps done: %.2f ms/step" % ms_per_step)
+
+    st = models[-1].stats()
+    npat = models[-1].n_patterns()
+    K = models[-1].K
+    n_flows = w.test_codes.shape[0]
+    coh_tests = sum(st.tests)
+    sup_tests = sum(st.support_tests)
+    score_tests = (npat[0] + npat[1]) * n_flows
+    tests_per_step = coh_tests + sup_tests + score_tests
+    value = tests_per_step / (ms_per_step / 1e3)
+    coh_ms = [mm.stats().ms[4] for mm in models]
+    coh_avg_ms = sum(coh_ms) / len(coh_ms)
+    # algorithmic VALU work of the coherence kernel: 2K 32-bit AND/OR ops per executed test
+    achieved = coh_tests * 2 * K / (coh_avg_ms / 1e3)
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {"bound": "alu", "kernel": "k_coherence", "achieved": achieved / 1e12,
+                "peak": VALU_INT32_PEAK_OPS / 1e12, "unit": "TOP/s (int32 VALU)",
+                "frac": achieved / VALU_INT32_PEAK_OPS, "traffic": traffic,
+                "avg_ms": coh_avg_ms, "tests": coh_tests}
+    res = {
+        "metric": METRIC, "value": value, "unit": "subset tests/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_train": int(w.n), "n_flows": int(n_flows), "d": int(w.d),
+                   "L": int(w.L), "K": int(K)},
+        "fit_wall_s_15k": float(np.median(fit_s)),
+        "tests_per_step": {"coherence": coh_tests, "support": sup_tests, "scoring": score_tests},
+        "patterns": list(npat), "distinct": list(st.distinct),
+        "stage_ms": {k: round(v, 3) for k, v in zip(
+            ["pack", "pairs", "sort", "dedup", "coherence", "order+support", "weights", "fit_total"], st.ms)},
+        "roofline": roofline,
+    }
+    del models
+    if not args.no_148k:
+        w2 = synth.make_148k()
+        log("148k workload", w2.codes.shape)
+        dc2 = torch.from_numpy(w2.codes.view(np.int16)).cuda()
+        dl2 = torch.from_numpy(w2.labels).cuda()
+        m2 = ig.fit(dc2, dl2, w2.nbins)   # warm (allocations, code load)
+        del m2
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        m2 = ig.fit(dc2, dl2, w2.nbins)
+        res["fit_wall_s_148k"] = time.perf_counter() - a
+        st2 = m2.stats()
+        res["fit_148k"] = {"n_train": int(w2.n), "patterns": list(m2.n_patterns()), "tests": list(st2.tests),
+                           "coherence_ms": st2.ms[4]}
+        del m2
+    if not args.no_cpu:
+        import oracle
+        ns = min(args.cpu_records, w.n)
+        nf = 300
+        log("cpu oracle on", ns, "records,", nf, "flows")
+        a = time.perf_counter()
+        om = oracle.fit(w.codes[:ns], w.labels[:ns], w.nbins)
+        oracle.score(om, w.test_codes[:nf], w.nbins)
+        dt = time.perf_counter() - a
+        t_or = sum(om.stats["tests"]) + sum(p.shape[0] * n for p, n in zip(om.patterns, om.stats["n_class"])) \
+            + sum(p.shape[0] for p in om.patterns) * nf
+        res["cpu_baseline"] = {"value": t_or / dt, "unit": "subset tests/s", "cores": oracle.max_threads(),
+                               "kind": "oracle", "seconds": dt,
+                               "sample": f"oracle fit of the first {ns} training records of the 15k workload "
+                                         f"+ scoring {nf} held-out flows"}
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,742 @@
+// libig host runtime: the C ABI of include/ig.h.
+//
+// Fit pipeline (per fit, both classes in one pass where memory allows):
+//   validate + class split + pack (Eq. 5, rows stacked by class)
+//   pair space chunked -> (hash, pair id) per candidate (Eq. 1)
+//   radix sort by (class, hash) -> exact de-duplication by full compare
+//   coherence filter of the distinct candidates (Eq. 3 / Eq. 6)
+//   canonical order of the coherent set (LSD radix sort on the words)
+//   support and weight of each pattern (Eq. 2)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace ig {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &m) { g_last_error = m; }
+
+// ------------------------------------------------------------ scratch pool ----
+static std::once_flag g_pool_once[64];
+
+static void configure_pool(int dev) {
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+}
+
+void *scratch_alloc(size_t bytes, hipStream_t s) {
+    int dev = 0;
+    IG_HIP(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64) std::call_once(g_pool_once[dev], configure_pool, dev);
+    void *p = nullptr;
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        throw Error(IG_E_NOMEM, "device scratch allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+void scratch_free(void *p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// --------------------------------------------------------------- the model ----
+struct DevModel {
+    int device = 0;
+    uint32_t K = 0, KS = 0, L = 0, d = 0;
+    uint64_t np[2] = {0, 0};
+    uint64_t *W[2] = {nullptr, nullptr};
+    uint32_t *f[2] = {nullptr, nullptr};
+    int64_t *S[2] = {nullptr, nullptr};
+    int64_t maxS[2] = {0, 0};
+    uint32_t *meta = nullptr;    // off[d] | flo[KS] | fhi[KS]
+    uint16_t *nbins = nullptr;
+    ig_stats stats{};
+    uint32_t stats_coherence_launches = 0;
+
+    ~DevModel() {
+        for (int c = 0; c < 2; ++c) {
+            if (W[c]) (void)hipFree(W[c]);
+            if (f[c]) (void)hipFree(f[c]);
+            if (S[c]) (void)hipFree(S[c]);
+        }
+        if (meta) (void)hipFree(meta);
+        if (nbins) (void)hipFree(nbins);
+    }
+};
+
+template <class T>
+static T *dev_alloc(size_t count) {
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        throw Error(IG_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    return static_cast<T *>(p);
+}
+
+// Token layout tables for codes with the given bins: off[f], and per storage
+// word k the features [flo[k], fhi[k]) whose token ranges meet word k.
+static std::vector<uint32_t> token_tables(const uint16_t *nbins, uint32_t d, uint32_t KS) {
+    std::vector<uint32_t> t(d + 2 * KS, 0);
+    uint32_t acc = 0;
+    for (uint32_t f = 0; f < d; ++f) {
+        t[f] = acc;
+        acc += nbins[f];
+    }
+    for (uint32_t k = 0; k < KS; ++k) {
+        uint32_t lo = 64 * k, hi = 64 * (k + 1);
+        uint32_t flo = d, fhi = 0;
+        for (uint32_t f = 0; f < d; ++f) {
+            uint32_t a = t[f], b = t[f] + nbins[f];
+            if (a < hi && b > lo) {
+                flo = std::min(flo, f);
+                fhi = std::max(fhi, f + 1);
+            }
+        }
+        if (flo >= fhi) flo = fhi = 0;
+        t[d + k] = flo;
+        t[d + KS + k] = fhi;
+    }
+    return t;
+}
+
+static void check_nbins(const uint16_t *h_nbins, uint32_t d, uint32_t &L, uint32_t &K) {
+    IG_REQUIRE(d >= 1 && d <= 4096, IG_E_INVAL, "d must be in 1..4096");
+    IG_REQUIRE(h_nbins != nullptr, IG_E_INVAL, "nbins is NULL");
+    uint64_t s = 0;
+    for (uint32_t f = 0; f < d; ++f) {
+        IG_REQUIRE(h_nbins[f] >= 1 && h_nbins[f] < IG_ABSENT, IG_E_INVAL,
+                   "nbins[" + std::to_string(f) + "] must be in 1..65534");
+        s += h_nbins[f];
+    }
+    IG_REQUIRE(s <= 4096, IG_E_UNSUPPORTED, "token universe L = " + std::to_string(s) + " exceeds 4096");
+    L = (uint32_t)s;
+    K = (L + 63) / 64;
+}
+
+static std::vector<uint32_t> host_read_u32(const uint32_t *d, size_t n, hipStream_t s) {
+    std::vector<uint32_t> h(n);
+    if (n) IG_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    IG_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+// ----------------------------------------------------------- fit from rows ----
+struct Timer {
+    hipEvent_t ev[9];
+    bool on = false;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st) {
+        on = true;
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) on = false;
+    }
+    void mark(int i) {
+        if (on) (void)hipEventRecord(ev[i], s);
+    }
+    ~Timer() {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+struct Tuning {
+    int cpl = 2, fpl = 2;
+};
+
+static Tuning tuning_from(const ig_fit_opts *o) {
+    Tuning t;
+    if (o) {
+        if (o->filter_cpl == 1 || o->filter_cpl == 2) t.cpl = (int)o->filter_cpl;
+        if (o->score_fpl == 1 || o->score_fpl == 2) t.fpl = (int)o->score_fpl;
+    }
+    return t;
+}
+
+struct ClassRows {
+    Scratch<uint64_t> X, NX;
+    uint32_t n = 0;
+};
+
+// Canonical order (ascending w_0..w_{K-1}) of the pair ids `ids` of one class;
+// then rows, merge of equal rows (they arise when the pair space was chunked),
+// support and weights.  Fills model class c.
+static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, const ClassRows &other_unused,
+                            Scratch<uint32_t> &ids, size_t count, bool may_repeat, const Tuning &tu,
+                            hipStream_t s) {
+    (void)other_unused;
+    const uint32_t KS = m.KS, K = m.K;
+    if (count == 0) {
+        m.np[c] = 0;
+        m.W[c] = dev_alloc<uint64_t>(KS);
+        m.f[c] = dev_alloc<uint32_t>(1);
+        m.S[c] = dev_alloc<int64_t>(1);
+        return;
+    }
+    // which bytes of which words vary at all
+    Scratch<unsigned long long> rng(2 * K, s);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get()), 0ull, K, s);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get() + K), ~0ull, K, s);
+    launch_word_range(cls.X.get(), cls.n, KS, K, ids.get(), count, rng.get(), rng.get() + K, s);
+    std::vector<unsigned long long> hr(2 * K);
+    IG_HIP(hipMemcpyAsync(hr.data(), rng.get(), 2 * K * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    IG_HIP(hipStreamSynchronize(s));
+
+    Scratch<uint64_t> k0(count, s), k1(count, s);
+    Scratch<uint32_t> v1(count, s);
+    uint32_t *vcur = ids.get(), *valt = v1.get();
+    for (int k = (int)K - 1; k >= 0; --k) {
+        uint64_t vary = hr[k] ^ hr[K + k];
+        uint32_t mask = 0;
+        for (int b = 0; b < 8; ++b)
+            if ((vary >> (8 * b)) & 0xffull) mask |= 1u << b;
+        if (!mask) continue;
+        launch_gather_word(cls.X.get(), cls.n, KS, (uint32_t)k, vcur, count, k0.get(), s);
+        int where = radix_sort_pairs(k0.get(), vcur, k1.get(), valt, count, mask, s);
+        if (where) std::swap(vcur, valt);
+    }
+    Scratch<uint64_t> Wtmp;
+    Scratch<uint32_t> flag;
+    uint64_t *Wd = dev_alloc<uint64_t>(count * KS);
+    size_t final_count = count;
+    try {
+        if (may_repeat) {
+            Wtmp.reset(count * KS, s);
+            flag.reset(count, s);
+            launch_materialize(cls.X.get(), cls.n, KS, vcur, count, Wtmp.get(), flag.get(), s);
+            Scratch<uint32_t> pos(count, s), tot(1, s);
+            scan_exclusive_u32(flag.get(), pos.get(), count, tot.get(), s);
+            launch_compact_rows(Wtmp.get(), flag.get(), pos.get(), count, KS, Wd, s);
+            final_count = host_read_u32(tot.get(), 1, s)[0];
+        } else {
+            launch_materialize(cls.X.get(), cls.n, KS, vcur, count, Wd, nullptr, s);
+        }
+        m.W[c] = Wd;
+        m.np[c] = final_count;
+        m.f[c] = dev_alloc<uint32_t>(final_count);
+        m.S[c] = dev_alloc<int64_t>(final_count);
+    } catch (...) {
+        if (Wd && m.W[c] != Wd) (void)hipFree(Wd);
+        throw;
+    }
+    launch_support((int)KS, tu.cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
+}
+
+static void finish_weights(DevModel &m, hipStream_t s) {
+    Scratch<unsigned long long> ms(4, s);
+    for (int c = 0; c < 2; ++c) launch_reduce_maxsum(m.S[c], m.np[c], ms.get() + 2 * c, s);
+    unsigned long long h[4];
+    IG_HIP(hipMemcpyAsync(h, ms.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    IG_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < 2; ++c) {
+        m.maxS[c] = (int64_t)h[2 * c];
+        // A(x) and N(x) are sums of a subset of one class's weights (Eq. 4)
+        IG_REQUIRE(h[2 * c + 1] <= (unsigned long long)INT64_MAX, IG_E_OVERFLOW,
+                   "sum of pattern weights exceeds int64");
+    }
+}
+
+static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts, hipStream_t s, Timer &tm) {
+    const uint32_t KS = m.KS, K = m.K;
+    const Tuning tu = tuning_from(opts);
+    uint64_t M[2];
+    for (int c = 0; c < 2; ++c) {
+        uint64_t n = cls[c].n;
+        IG_REQUIRE(n <= 92000, IG_E_UNSUPPORTED, "more than 92,000 training records in one class");
+        M[c] = n + n * (n ? n - 1 : 0) / 2;
+        m.stats.n_class[c] = n;
+        m.stats.pairs[c] = n * (n ? n - 1 : 0) / 2;
+        m.stats.support_tests[c] = 0;
+    }
+    // items per pair-space chunk: ~40 bytes of scratch per item
+    uint64_t chunk_items = 1ull << 31;
+    if (opts && opts->mem_budget_bytes) chunk_items = std::max<uint64_t>(opts->mem_budget_bytes / 40, 4096);
+    struct Piece {
+        int c;
+        uint64_t q0, cnt;
+    };
+    std::vector<std::vector<Piece>> chunks;
+    {
+        std::vector<Piece> cur;
+        uint64_t used = 0;
+        for (int c = 0; c < 2; ++c) {
+            uint64_t q = 0;
+            while (q < M[c]) {
+                uint64_t take = std::min(M[c] - q, chunk_items - used);
+                cur.push_back({c, q, take});
+                used += take;
+                q += take;
+                if (used == chunk_items) {
+                    chunks.push_back(cur);
+                    cur.clear();
+                    used = 0;
+                }
+            }
+        }
+        if (!cur.empty()) chunks.push_back(cur);
+    }
+    m.stats.chunks[0] = m.stats.chunks[1] = 0;
+    for (auto &ch : chunks)
+        for (int c = 0; c < 2; ++c)
+            if (std::any_of(ch.begin(), ch.end(), [&](const Piece &p) { return p.c == c; })) m.stats.chunks[c]++;
+
+    // survivors (coherent pair ids) per class, grown as chunks add candidates
+    Scratch<uint32_t> surv[2];
+    size_t surv_cap[2] = {0, 0};
+    Scratch<uint32_t> counters(4, s);   // nsurv[0], nsurv[1], queue, spare
+    Scratch<unsigned long long> tests(2, s);
+    launch_fill_u32(counters.get(), 0u, 4, s);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(tests.get()), 0ull, 2, s);
+    uint64_t distinct[2] = {0, 0};
+
+    // row descriptors for the de-duplication kernel (segment = class)
+    Scratch<unsigned char> rowsegs(2 * rows_of_seg_size(), s);
+    {
+        std::vector<unsigned char> h(2 * rows_of_seg_size());
+        for (int c = 0; c < 2; ++c) fill_rows_of_seg(h.data() + c * rows_of_seg_size(), cls[c].X.get(), cls[c].n, KS, K);
+        IG_HIP(hipMemcpyAsync(rowsegs.get(), h.data(), h.size(), hipMemcpyHostToDevice, s));
+        IG_HIP(hipStreamSynchronize(s));
+    }
+    const uint32_t grid = coherence_grid((int)KS, tu.cpl);
+    float ms_pairs = 0, ms_sort = 0, ms_dedup = 0, ms_coh = 0;
+    hipEvent_t e[5];
+    for (auto &x : e) IG_HIP(hipEventCreate(&x));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } evg{e};
+    tm.mark(1);
+    for (auto &ch : chunks) {
+        uint64_t items = 0;
+        for (auto &p : ch) items += p.cnt;
+        Scratch<uint64_t> k0(items, s), k1(items, s);
+        Scratch<uint32_t> v0(items, s), v1(items, s);
+        IG_HIP(hipEventRecord(e[0], s));
+        uint64_t at = 0;
+        for (auto &p : ch) {
+            launch_pair_hash(cls[p.c].X.get(), cls[p.c].n, KS, K, p.q0, p.cnt, (uint32_t)p.c, 1, k0.get() + at,
+                             v0.get() + at, s);
+            at += p.cnt;
+        }
+        IG_HIP(hipEventRecord(e[1], s));
+        int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items, 0xffu, s);
+        uint64_t *ks = where ? k1.get() : k0.get();
+        uint32_t *vs = where ? v1.get() : v0.get();
+        IG_HIP(hipEventRecord(e[2], s));
+        Scratch<uint32_t> flags(items, s), pos(items, s), segc(2, s), cand(items, s);
+        launch_fill_u32(segc.get(), 0u, 2, s);
+        launch_dedup_flags(ks, vs, items, rowsegs.get(), 1, flags.get(), segc.get(), s);
+        scan_exclusive_u32(flags.get(), pos.get(), items, nullptr, s);
+        launch_compact(flags.get(), pos.get(), vs, items, cand.get(), s);
+        IG_HIP(hipEventRecord(e[3], s));
+        std::vector<uint32_t> hc = host_read_u32(segc.get(), 2, s);
+        std::vector<uint32_t> hn = host_read_u32(counters.get(), 2, s);
+        float t01, t12, t23;
+        IG_HIP(hipEventElapsedTime(&t01, e[0], e[1]));
+        IG_HIP(hipEventElapsedTime(&t12, e[1], e[2]));
+        IG_HIP(hipEventElapsedTime(&t23, e[2], e[3]));
+        ms_pairs += t01;
+        ms_sort += t12;
+        ms_dedup += t23;
+        // grow the survivor buffers to hold every candidate of this chunk
+        for (int c = 0; c < 2; ++c) {
+            distinct[c] += hc[c];
+            size_t need = (size_t)hn[c] + hc[c];
+            if (need > surv_cap[c]) {
+                size_t cap = std::max<size_t>(need, surv_cap[c] * 3 / 2);
+                Scratch<uint32_t> nb(cap, s);
+                if (hn[c]) IG_HIP(hipMemcpyAsync(nb.get(), surv[c].get(), (size_t)hn[c] * 4, hipMemcpyDeviceToDevice, s));
+                surv[c] = std::move(nb);
+                surv_cap[c] = cap;
+            }
+        }
+        CohSeg hs[2];
+        uint32_t prefix[3] = {0, 0, 0};
+        uint32_t per_task = 64u * (uint32_t)((tu.cpl == 2 && KS <= 16) ? 2 : 1);
+        for (int c = 0; c < 2; ++c) {
+            hs[c].X = cls[c].X.get();
+            hs[c].NXo = cls[1 - c].NX.get();
+            hs[c].cand = cand.get() + (c == 0 ? 0 : hc[0]);
+            hs[c].surv = surv[c].get();
+            hs[c].nsurv = counters.get() + c;
+            hs[c].tests = tests.get() + c;
+            hs[c].n = cls[c].n;
+            hs[c].n_o = cls[1 - c].n;
+            hs[c].ncand = hc[c];
+            hs[c].pad = 0;
+            prefix[c + 1] = prefix[c] + (hc[c] + per_task - 1) / per_task;
+        }
+        Scratch<CohSeg> dsegs(2, s);
+        Scratch<uint32_t> dpre(3, s);
+        IG_HIP(hipMemcpyAsync(dsegs.get(), hs, sizeof(hs), hipMemcpyHostToDevice, s));
+        IG_HIP(hipMemcpyAsync(dpre.get(), prefix, sizeof(prefix), hipMemcpyHostToDevice, s));
+        IG_HIP(hipEventRecord(e[3], s));   // brackets the coherence launch alone
+        launch_coherence((int)KS, tu.cpl, dsegs.get(), 2, dpre.get(), counters.get() + 2, grid, s);
+        IG_HIP(hipEventRecord(e[4], s));
+        IG_HIP(hipStreamSynchronize(s));   // host copies above must outlive their transfers
+        float t34;
+        IG_HIP(hipEventElapsedTime(&t34, e[3], e[4]));
+        ms_coh += t34;
+        m.stats_coherence_launches++;
+    }
+    tm.mark(4);
+    std::vector<uint32_t> hn = host_read_u32(counters.get(), 2, s);
+    unsigned long long ht[2];
+    IG_HIP(hipMemcpyAsync(ht, tests.get(), sizeof(ht), hipMemcpyDeviceToHost, s));
+    IG_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < 2; ++c) {
+        m.stats.distinct[c] = distinct[c];
+        m.stats.tests[c] = ht[c];
+    }
+    const bool chunked = chunks.size() > 1;
+    for (int c = 0; c < 2; ++c) {
+        order_and_weigh(m, c, cls[c], cls[1 - c], surv[c], hn[c], chunked, tu, s);
+        m.stats.coherent[c] = m.np[c];
+        m.stats.support_tests[c] = m.np[c] * (uint64_t)cls[c].n;
+    }
+    tm.mark(6);
+    finish_weights(m, s);
+    tm.mark(7);
+    IG_HIP(hipStreamSynchronize(s));
+    m.stats.ms[1] = ms_pairs;
+    m.stats.ms[2] = ms_sort;
+    m.stats.ms[3] = ms_dedup;
+    m.stats.ms[4] = ms_coh;
+}
+
+static DevModel *new_model() {
+    DevModel *m = new DevModel();
+    IG_HIP(hipGetDevice(&m->device));
+    return m;
+}
+
+static void record_times(DevModel &m, Timer &tm) {
+    if (!tm.on) return;
+    float a;
+    if (hipEventElapsedTime(&a, tm.ev[0], tm.ev[1]) == hipSuccess) m.stats.ms[0] = a;
+    if (hipEventElapsedTime(&a, tm.ev[4], tm.ev[6]) == hipSuccess) {
+        // ordering + support, split by the support launches' share is not separated
+        m.stats.ms[5] = a;
+    }
+    if (hipEventElapsedTime(&a, tm.ev[6], tm.ev[7]) == hipSuccess) m.stats.ms[6] = a;
+    if (hipEventElapsedTime(&a, tm.ev[0], tm.ev[7]) == hipSuccess) m.stats.ms[7] = a;
+}
+
+DevModel *fit_codes(const uint16_t *d_codes, const uint8_t *d_labels, uint32_t n, uint32_t d,
+                    const uint16_t *h_nbins, const ig_fit_opts *opts, hipStream_t s) {
+    uint32_t L, K;
+    check_nbins(h_nbins, d, L, K);
+    IG_REQUIRE(n == 0 || (d_codes && d_labels), IG_E_INVAL, "codes or labels is NULL");
+    const int KS = storage_words((int)K);
+    IG_REQUIRE(KS > 0, IG_E_UNSUPPORTED, "unsupported word count");
+    std::unique_ptr<DevModel> m(new_model());
+    m->K = K;
+    m->KS = (uint32_t)KS;
+    m->L = L;
+    m->d = d;
+    Timer tm(s);
+    tm.mark(0);
+    std::vector<uint32_t> tab = token_tables(h_nbins, d, (uint32_t)KS);
+    m->meta = dev_alloc<uint32_t>(tab.size());
+    m->nbins = dev_alloc<uint16_t>(d);
+    IG_HIP(hipMemcpyAsync(m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
+    IG_HIP(hipMemcpyAsync(m->nbins, h_nbins, d * 2, hipMemcpyHostToDevice, s));
+    Scratch<uint32_t> err(1, s), pos(n ? n : 1, s), counts(2, s);
+    launch_fill_u32(err.get(), 0u, 1, s);
+    launch_fill_u32(counts.get(), 0u, 2, s);
+    launch_validate_codes(d_codes, (size_t)n * d, d, m->nbins, err.get(), s);
+    if (n) launch_split_labels(d_labels, n, pos.get(), counts.get(), err.get(), s);
+    std::vector<uint32_t> h = host_read_u32(err.get(), 1, s);   // also completes the table uploads
+    IG_REQUIRE(!(h[0] & 1u), IG_E_INVAL, "a code is not below its feature's bin count");
+    IG_REQUIRE(!(h[0] & 2u), IG_E_INVAL, "a label is not 0 or 1");
+    std::vector<uint32_t> hc = host_read_u32(counts.get(), 2, s);
+    ClassRows cls[2];
+    for (int c = 0; c < 2; ++c) {
+        cls[c].n = hc[c];
+        cls[c].X.reset((size_t)(hc[c] ? hc[c] : 1) * KS, s);
+        cls[c].NX.reset((size_t)(hc[c] ? hc[c] : 1) * KS, s);
+    }
+    launch_pack_split(d_codes, d_labels, n, d, (uint32_t)KS, m->meta, pos.get(), cls[0].X.get(), cls[1].X.get(),
+                      cls[0].NX.get(), cls[1].NX.get(), s);
+    fit_from_rows(*m, cls, opts, s, tm);
+    record_times(*m, tm);
+    return m.release();
+}
+
+DevModel *fit_packed(const uint64_t *d_words, const uint8_t *d_labels, uint32_t n, uint32_t K,
+                     const ig_fit_opts *opts, hipStream_t s) {
+    IG_REQUIRE(K >= 1 && K <= 64, IG_E_UNSUPPORTED, "K must be in 1..64");
+    IG_REQUIRE(n == 0 || (d_words && d_labels), IG_E_INVAL, "words or labels is NULL");
+    const int KS = storage_words((int)K);
+    std::unique_ptr<DevModel> m(new_model());
+    m->K = K;
+    m->KS = (uint32_t)KS;
+    m->L = 64 * K;
+    m->d = 0;
+    Timer tm(s);
+    tm.mark(0);
+    Scratch<uint32_t> err(1, s), pos(n ? n : 1, s), counts(2, s);
+    launch_fill_u32(err.get(), 0u, 1, s);
+    launch_fill_u32(counts.get(), 0u, 2, s);
+    if (n) launch_split_labels(d_labels, n, pos.get(), counts.get(), err.get(), s);
+    std::vector<uint32_t> h = host_read_u32(err.get(), 1, s);
+    IG_REQUIRE(!(h[0] & 2u), IG_E_INVAL, "a label is not 0 or 1");
+    std::vector<uint32_t> hc = host_read_u32(counts.get(), 2, s);
+    ClassRows cls[2];
+    for (int c = 0; c < 2; ++c) {
+        cls[c].n = hc[c];
+        cls[c].X.reset((size_t)(hc[c] ? hc[c] : 1) * KS, s);
+        cls[c].NX.reset((size_t)(hc[c] ? hc[c] : 1) * KS, s);
+    }
+    launch_split_packed(d_words, d_labels, n, K, (uint32_t)KS, pos.get(), cls[0].X.get(), cls[1].X.get(),
+                        cls[0].NX.get(), cls[1].NX.get(), s);
+    fit_from_rows(*m, cls, opts, s, tm);
+    record_times(*m, tm);
+    return m.release();
+}
+
+DevModel *import_patterns(const uint16_t *const h_codes[2], const uint32_t *const h_f[2], const uint64_t count[2],
+                          uint32_t d, const uint16_t *h_nbins, hipStream_t s) {
+    uint32_t L, K;
+    check_nbins(h_nbins, d, L, K);
+    const int KS = storage_words((int)K);
+    std::unique_ptr<DevModel> m(new_model());
+    m->K = K;
+    m->KS = (uint32_t)KS;
+    m->L = L;
+    m->d = d;
+    std::vector<uint32_t> tab = token_tables(h_nbins, d, (uint32_t)KS);
+    m->meta = dev_alloc<uint32_t>(tab.size());
+    m->nbins = dev_alloc<uint16_t>(d);
+    IG_HIP(hipMemcpyAsync(m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
+    IG_HIP(hipMemcpyAsync(m->nbins, h_nbins, d * 2, hipMemcpyHostToDevice, s));
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t cnt = count[c];
+        IG_REQUIRE(cnt < (1ull << 31), IG_E_UNSUPPORTED, "more than 2^31 patterns in one class");
+        IG_REQUIRE(cnt == 0 || (h_codes[c] && h_f[c]), IG_E_INVAL, "pattern codes or supports is NULL");
+        m->np[c] = cnt;
+        m->W[c] = dev_alloc<uint64_t>(cnt * KS);
+        m->f[c] = dev_alloc<uint32_t>(cnt);
+        m->S[c] = dev_alloc<int64_t>(cnt);
+        if (!cnt) continue;
+        Scratch<uint16_t> dc(cnt * d, s);
+        Scratch<uint32_t> df(cnt, s), err(1, s), ids(cnt, s), v1(cnt, s), tot(1, s);
+        Scratch<uint64_t> Wraw(cnt * KS, s), k0(cnt, s), k1(cnt, s);
+        IG_HIP(hipMemcpyAsync(dc.get(), h_codes[c], cnt * d * 2, hipMemcpyHostToDevice, s));
+        IG_HIP(hipMemcpyAsync(df.get(), h_f[c], cnt * 4, hipMemcpyHostToDevice, s));
+        launch_fill_u32(err.get(), 0u, 1, s);
+        launch_pack_patterns(dc.get(), (uint32_t)cnt, d, (uint32_t)KS, m->meta, m->nbins, Wraw.get(), err.get(), s);
+        std::vector<uint32_t> he = host_read_u32(err.get(), 1, s);
+        IG_REQUIRE(!(he[0] & 1u), IG_E_INVAL, "a pattern code is neither absent nor below its bin count");
+        IG_REQUIRE(!(he[0] & 2u), IG_E_INVAL, "a pattern has no token");
+        launch_iota(ids.get(), cnt, s);
+        uint32_t *vcur = ids.get(), *valt = v1.get();
+        for (int k = (int)K - 1; k >= 0; --k) {
+            launch_row_word(Wraw.get(), vcur, cnt, (uint32_t)KS, (uint32_t)k, k0.get(), s);
+            int where = radix_sort_pairs(k0.get(), vcur, k1.get(), valt, cnt, 0xffu, s);
+            if (where) std::swap(vcur, valt);
+        }
+        launch_gather_rows(Wraw.get(), vcur, cnt, (uint32_t)KS, m->W[c], df.get(), m->f[c], s);
+        // distinctness: ordered rows must all differ from their predecessor
+        launch_fill_u32(tot.get(), 0u, 1, s);
+        launch_adjacent_equal(m->W[c], cnt, (uint32_t)KS, tot.get(), s);
+        launch_weights(m->W[c], m->f[c], cnt, (uint32_t)KS, m->S[c], s);
+        std::vector<uint32_t> dup = host_read_u32(tot.get(), 1, s);
+        IG_REQUIRE(dup[0] == 0, IG_E_INVAL, "pattern set of class " + std::to_string(c) + " has repeated patterns");
+    }
+    finish_weights(*m, s);
+    return m.release();
+}
+
+}  // namespace ig
+
+// ===================================================================== C ABI ====
+using ig::DevModel;
+
+struct ig_model {
+    DevModel *m;
+};
+
+template <class F>
+static ig_status guarded(F &&fn) {
+    try {
+        fn();
+        ig::g_last_error.clear();
+        return IG_OK;
+    } catch (const ig::Error &e) {
+        ig::set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ig::set_error("host allocation failed");
+        return IG_E_NOMEM;
+    } catch (const std::exception &e) {
+        ig::set_error(e.what());
+        return IG_E_DEVICE;
+    }
+}
+
+static ig_model *wrap(DevModel *m) {
+    ig_model *w = new (std::nothrow) ig_model{m};
+    if (!w) {
+        delete m;
+        throw ig::Error(IG_E_NOMEM, "host allocation failed");
+    }
+    return w;
+}
+
+static void check_model(const ig_model *m) {
+    IG_REQUIRE(m && m->m, IG_E_INVAL, "model is NULL");
+    int dev = 0;
+    IG_HIP(hipGetDevice(&dev));
+    IG_REQUIRE(dev == m->m->device, IG_E_INVAL, "model lives on another device than the current one");
+}
+
+extern "C" {
+
+ig_status ig_fit(const uint16_t *d_codes, const uint8_t *d_labels, uint32_t n, uint32_t d, const uint16_t *h_nbins,
+                 const ig_fit_opts *opts, void *stream, ig_model **out) {
+    return guarded([&] {
+        IG_REQUIRE(out != nullptr, IG_E_INVAL, "out is NULL");
+        DevModel *m = ig::fit_codes(d_codes, d_labels, n, d, h_nbins, opts, (hipStream_t)stream);
+        *out = wrap(m);
+    });
+}
+
+ig_status ig_fit_packed(const uint64_t *d_words, const uint8_t *d_labels, uint32_t n, uint32_t K,
+                        const ig_fit_opts *opts, void *stream, ig_model **out) {
+    return guarded([&] {
+        IG_REQUIRE(out != nullptr, IG_E_INVAL, "out is NULL");
+        DevModel *m = ig::fit_packed(d_words, d_labels, n, K, opts, (hipStream_t)stream);
+        *out = wrap(m);
+    });
+}
+
+ig_status ig_fit_batch(const ig_problem *probs, uint32_t n_probs, const ig_fit_opts *opts, void *stream,
+                       ig_model **outs) {
+    return guarded([&] {
+        IG_REQUIRE(outs != nullptr && (n_probs == 0 || probs != nullptr), IG_E_INVAL, "NULL argument");
+        std::vector<DevModel *> made;
+        try {
+            for (uint32_t p = 0; p < n_probs; ++p)
+                made.push_back(ig::fit_codes(probs[p].d_codes, probs[p].d_labels, probs[p].n, probs[p].d,
+                                             probs[p].h_nbins, opts, (hipStream_t)stream));
+        } catch (...) {
+            for (auto *m : made) delete m;
+            throw;
+        }
+        std::vector<ig_model *> w(n_probs, nullptr);
+        for (uint32_t p = 0; p < n_probs; ++p) w[p] = new (std::nothrow) ig_model{made[p]};
+        bool ok = std::all_of(w.begin(), w.end(), [](ig_model *x) { return x != nullptr; });
+        if (!ok) {
+            for (uint32_t p = 0; p < n_probs; ++p) {
+                delete made[p];
+                delete w[p];
+            }
+            throw ig::Error(IG_E_NOMEM, "host allocation failed");
+        }
+        for (uint32_t p = 0; p < n_probs; ++p) outs[p] = w[p];
+    });
+}
+
+ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out, void *stream) {
+    return guarded([&] {
+        check_model(m);
+        const DevModel &M = *m->m;
+        IG_REQUIRE(M.d > 0, IG_E_INVAL, "model was fitted from packed words: use ig_score_packed");
+        IG_REQUIRE(n_flows < (1u << 31), IG_E_UNSUPPORTED, "n_flows must be below 2^31");
+        IG_REQUIRE(n_flows == 0 || (d_codes && d_out), IG_E_INVAL, "codes or out is NULL");
+        ig::ScoreModel sm{{M.W[0], M.W[1]}, {M.S[0], M.S[1]}, {M.np[0], M.np[1]}, M.KS, {M.maxS[0], M.maxS[1]}};
+        ig::launch_score(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, (hipStream_t)stream);
+    });
+}
+
+ig_status ig_score_packed(const ig_model *m, const uint64_t *d_words, uint32_t n_flows, int64_t *d_out,
+                          void *stream) {
+    return guarded([&] {
+        check_model(m);
+        const DevModel &M = *m->m;
+        IG_REQUIRE(n_flows < (1u << 31), IG_E_UNSUPPORTED, "n_flows must be below 2^31");
+        IG_REQUIRE(n_flows == 0 || (d_words && d_out), IG_E_INVAL, "words or out is NULL");
+        ig::ScoreModel sm{{M.W[0], M.W[1]}, {M.S[0], M.S[1]}, {M.np[0], M.np[1]}, M.KS, {M.maxS[0], M.maxS[1]}};
+        ig::launch_score(sm, nullptr, d_words, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, (hipStream_t)stream);
+    });
+}
+
+ig_status ig_model_get_info(const ig_model *m, ig_model_info *info) {
+    return guarded([&] {
+        IG_REQUIRE(m && m->m && info, IG_E_INVAL, "model or info is NULL");
+        const DevModel &M = *m->m;
+        std::memset(info, 0, sizeof(*info));
+        info->K = M.K;
+        info->L = M.L;
+        info->d = M.d;
+        for (int c = 0; c < 2; ++c) {
+            info->n_patterns[c] = M.np[c];
+            info->max_weight[c] = M.maxS[c];
+        }
+    });
+}
+
+ig_status ig_model_export(const ig_model *m, uint32_t cls, uint64_t *h_words, uint32_t *h_f, int64_t *h_S) {
+    return guarded([&] {
+        check_model(m);
+        IG_REQUIRE(cls <= 1, IG_E_INVAL, "class must be 0 or 1");
+        const DevModel &M = *m->m;
+        const uint64_t n = M.np[cls];
+        if (h_words && n) {
+            if (M.KS == M.K) {
+                IG_HIP(hipMemcpy(h_words, M.W[cls], n * M.K * 8, hipMemcpyDeviceToHost));
+            } else {
+                IG_HIP(hipMemcpy2D(h_words, M.K * 8, M.W[cls], M.KS * 8, M.K * 8, n, hipMemcpyDeviceToHost));
+            }
+        }
+        if (h_f && n) IG_HIP(hipMemcpy(h_f, M.f[cls], n * 4, hipMemcpyDeviceToHost));
+        if (h_S && n) IG_HIP(hipMemcpy(h_S, M.S[cls], n * 8, hipMemcpyDeviceToHost));
+    });
+}
+
+ig_status ig_model_import(const uint16_t *const h_codes[2], const uint32_t *const h_f[2], const uint64_t count[2],
+                          uint32_t d, const uint16_t *h_nbins, void *stream, ig_model **out) {
+    return guarded([&] {
+        IG_REQUIRE(out && h_codes && h_f && count, IG_E_INVAL, "NULL argument");
+        DevModel *m = ig::import_patterns(h_codes, h_f, count, d, h_nbins, (hipStream_t)stream);
+        *out = wrap(m);
+    });
+}
+
+ig_status ig_fit_stats(const ig_model *m, ig_stats *out) {
+    return guarded([&] {
+        IG_REQUIRE(m && m->m && out, IG_E_INVAL, "model or out is NULL");
+        *out = m->m->stats;
+    });
+}
+
+void ig_model_free(ig_model *m) {
+    if (!m) return;
+    delete m->m;
+    delete m;
+}
+
+const char *ig_last_error(void) { return ig::g_last_error.c_str(); }
+
+const char *ig_version(void) { return "libig 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Launchers of libig's kernels (host-side declarations).
+#pragma once
+#include "common.h"
+
+namespace ig {
+
+// pack.hip
+void launch_validate_codes(const uint16_t *codes, size_t total, uint32_t d, const uint16_t *nbins, uint32_t *err,
+                           hipStream_t s);
+void launch_split_labels(const uint8_t *labels, uint32_t n, uint32_t *pos, uint32_t *counts, uint32_t *err,
+                         hipStream_t s);
+void launch_pack_split(const uint16_t *codes, const uint8_t *labels, uint32_t n, uint32_t d, uint32_t KS,
+                       const uint32_t *meta, const uint32_t *pos, uint64_t *X0, uint64_t *X1, uint64_t *NX0,
+                       uint64_t *NX1, hipStream_t s);
+void launch_split_packed(const uint64_t *words, const uint8_t *labels, uint32_t n, uint32_t K, uint32_t KS,
+                         const uint32_t *pos, uint64_t *X0, uint64_t *X1, uint64_t *NX0, uint64_t *NX1,
+                         hipStream_t s);
+void launch_pack_patterns(const uint16_t *codes, uint32_t m, uint32_t d, uint32_t KS, const uint32_t *meta,
+                          const uint16_t *nbins, uint64_t *W, uint32_t *err, hipStream_t s);
+
+// pairs.hip
+void launch_pair_hash(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, uint64_t q0, uint64_t count,
+                      uint32_t seg, int segbits, uint64_t *keys, uint32_t *vals, hipStream_t s);
+size_t rows_of_seg_size();
+void fill_rows_of_seg(void *dst, const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K);
+void launch_dedup_flags(const uint64_t *keys, const uint32_t *vals, size_t m, const void *segs_dev, int segbits,
+                        uint32_t *flags, uint32_t *seg_counts, hipStream_t s);
+void launch_compact(const uint32_t *flags, const uint32_t *pos, const uint32_t *vals, size_t m, uint32_t *out,
+                    hipStream_t s);
+void launch_gather_word(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t k, const uint32_t *ids, size_t m,
+                        uint64_t *keys, hipStream_t s);
+void launch_word_range(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, const uint32_t *ids, size_t m,
+                       unsigned long long *orv, unsigned long long *andv, hipStream_t s);
+void launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m, uint64_t *W,
+                        uint32_t *newflag, hipStream_t s);
+void launch_compact_rows(const uint64_t *W, const uint32_t *flags, const uint32_t *pos, size_t m, uint32_t KS,
+                         uint64_t *out, hipStream_t s);
+void launch_gather_rows(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint64_t *out,
+                        const uint32_t *fin, uint32_t *fout, hipStream_t s);
+void launch_row_word(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint32_t k, uint64_t *keys,
+                     hipStream_t s);
+void launch_iota(uint32_t *v, size_t m, hipStream_t s);
+// count of ordered rows equal to their predecessor (0 = all distinct)
+void launch_adjacent_equal(const uint64_t *W, size_t m, uint32_t KS, uint32_t *d_count, hipStream_t s);
+// S = f * popcount^2 (Eq. 2) for given rows and supports
+void launch_weights(const uint64_t *W, const uint32_t *f, size_t m, uint32_t KS, int64_t *S, hipStream_t s);
+
+// subset.hip -- the subset-test kernels (Eq. 6 inside Eq. 3, Eq. 2 and Eq. 4)
+struct CohSeg {                 // one (problem, class) for the coherence kernel
+    const uint64_t *X;          // class rows [n][KS]
+    const uint64_t *NXo;        // complemented other-class rows [n_o][KS]
+    const uint32_t *cand;       // distinct candidate pair ids
+    uint32_t *surv;             // coherent pair ids out (appended)
+    uint32_t *nsurv;            // counter of surv
+    unsigned long long *tests;  // sum of t(b)
+    uint32_t n, n_o, ncand, pad;
+};
+// Coherence filter over all segments (same KS); tasks of 64*cpl candidates are
+// pulled from a queue counter (zeroed by the launcher).
+void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, const uint32_t *task_prefix_dev,
+                      uint32_t *queue, uint32_t grid, hipStream_t s);
+uint32_t coherence_grid(int KS, int cpl);
+
+// Support f and weight S of m ordered patterns W [m][KS] against the complemented
+// rows NX [n][KS] of their class.
+void launch_support(int KS, int cpl, const uint64_t *W, size_t m, const uint64_t *NX, uint32_t n, uint32_t *f,
+                    int64_t *S, hipStream_t s);
+
+struct ScoreModel {
+    const uint64_t *P[2];       // patterns of class 0 / 1 [np][KS]
+    const int64_t *S[2];
+    uint64_t np[2];
+    uint32_t KS;
+    int64_t maxS[2];            // largest weight of each class
+};
+// Eq. 4 for n_flows flows: codes [n][d] (meta = off|flo|fhi, nbins) or packed
+// words [n][K].  out [n][2] = (A, N) is initialised by the launcher.
+void launch_score(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K, uint32_t n_flows,
+                  uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out, int fpl, hipStream_t s);
+
+void launch_reduce_maxsum(const int64_t *S, size_t m, unsigned long long *d_max_sum /*[2]*/, hipStream_t s);
+
+}  // namespace ig

@@ -1,0 +1,226 @@
+// Device primitives of libig: fills, exclusive scan and a stable LSD radix sort of
+// (u64 key, u32 value) pairs.  Used for candidate de-duplication (Eq. 1 defines
+// B^c as a set) and for putting pattern sets in canonical order.
+#include "common.h"
+
+namespace ig {
+
+// ------------------------------------------------------------------ fills ----
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+static unsigned grid_for(size_t n, unsigned block) {
+    size_t g = (n + block - 1) / block;
+    if (g > 65535u * 8u) g = 65535u * 8u;
+    return (unsigned)(g ? g : 1);
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    IG_HIP(hipGetLastError());
+}
+void launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    IG_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------- scan ----
+constexpr int SCAN_T = 256;
+constexpr int SCAN_I = 16;
+constexpr int SCAN_TILE = SCAN_T * SCAN_I;   // 4096 values per workgroup
+
+// inclusive scan of one value per thread across a 256-thread workgroup
+__device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t *sh /*[4]*/, uint32_t &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) sh[wave] = v;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += sh[w];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return v + pre;
+}
+
+// per-tile sums
+__global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const uint32_t *in, size_t n, uint32_t *sums) {
+    __shared__ uint32_t sh[4];
+    size_t base = (size_t)blockIdx.x * SCAN_TILE;
+    uint32_t v = 0;
+#pragma unroll
+    for (int it = 0; it < SCAN_I; ++it) {
+        size_t e = base + (size_t)it * SCAN_T + threadIdx.x;
+        if (e < n) v += in[e];
+    }
+    uint32_t tot;
+    block_incl_scan(v, sh, tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// exclusive scan of each tile, offset by the (already scanned) tile prefix
+__global__ __launch_bounds__(SCAN_T) void k_scan_tiles(const uint32_t *in, uint32_t *out, size_t n,
+                                                      const uint32_t *tile_prefix, uint32_t *d_total) {
+    __shared__ uint32_t sh[4];
+    __shared__ uint32_t carry;
+    size_t base = (size_t)blockIdx.x * SCAN_TILE;
+    if (threadIdx.x == 0) carry = tile_prefix ? tile_prefix[blockIdx.x] : 0u;
+    __syncthreads();
+    // each thread owns SCAN_I consecutive values: thread-local sums, then one block scan
+    uint32_t loc[SCAN_I];
+    uint32_t s = 0;
+    size_t tb = base + (size_t)threadIdx.x * SCAN_I;
+#pragma unroll
+    for (int it = 0; it < SCAN_I; ++it) {
+        size_t e = tb + it;
+        loc[it] = (e < n) ? in[e] : 0u;
+        s += loc[it];
+    }
+    uint32_t tot;
+    uint32_t incl = block_incl_scan(s, sh, tot);
+    uint32_t run = carry + incl - s;
+#pragma unroll
+    for (int it = 0; it < SCAN_I; ++it) {
+        size_t e = tb + it;
+        uint32_t v = loc[it];
+        if (e < n) out[e] = run;
+        run += v;
+    }
+    if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) *d_total = run;
+}
+
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, hipStream_t s) {
+    if (n == 0) {
+        if (d_total) launch_fill_u32(d_total, 0, 1, s);
+        return;
+    }
+    size_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles == 1) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_T), 0, s, in, out, n, (const uint32_t *)nullptr,
+                           d_total);
+        IG_HIP(hipGetLastError());
+        return;
+    }
+    Scratch<uint32_t> sums(tiles, s);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, in, n, sums.get());
+    IG_HIP(hipGetLastError());
+    scan_exclusive_u32(sums.get(), sums.get(), tiles, nullptr, s);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, in, out, n,
+                       (const uint32_t *)sums.get(), d_total);
+    IG_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------- radix sort ----
+// Digit histograms per tile, laid out digit-major ([256][tiles]) so that one
+// exclusive scan gives every tile its output offset for every digit; the scatter
+// then ranks equal digits stably inside the tile (wave ballots + LDS counts).
+constexpr int RS_T = 256;
+constexpr int RS_I = 16;
+constexpr int RS_TILE = RS_T * RS_I;
+
+__global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t *__restrict__ keys, size_t n, int shift,
+                                                 uint32_t *__restrict__ hist, uint32_t tiles) {
+    __shared__ uint32_t h[4][256];
+    const int wave = threadIdx.x >> 6;
+    for (int t = threadIdx.x; t < 4 * 256; t += RS_T) (&h[0][0])[t] = 0;
+    __syncthreads();
+    size_t base = (size_t)blockIdx.x * RS_TILE;
+#pragma unroll 4
+    for (int it = 0; it < RS_I; ++it) {
+        size_t e = base + (size_t)it * RS_T + threadIdx.x;
+        if (e < n) {
+            uint32_t dg = (uint32_t)(keys[e] >> shift) & 255u;
+            atomicAdd(&h[wave][dg], 1u);
+        }
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    hist[(size_t)t * tiles + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+__global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                    size_t n, int shift, const uint32_t *__restrict__ offs,
+                                                    uint32_t tiles) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[4][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    run[threadIdx.x] = offs[(size_t)threadIdx.x * tiles + blockIdx.x];
+    size_t base = (size_t)blockIdx.x * RS_TILE;
+    for (int it = 0; it < RS_I; ++it) {
+        for (int t = threadIdx.x; t < 4 * 256; t += RS_T) (&wcnt[0][0])[t] = 0;
+        __syncthreads();
+        size_t e = base + (size_t)it * RS_T + threadIdx.x;
+        bool valid = e < n;
+        uint64_t key = valid ? kin[e] : 0ull;
+        uint32_t val = valid ? vin[e] : 0u;
+        uint32_t dg = (uint32_t)(key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (dg >> b) & 1u;
+            uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+        if (valid && rank == 0) wcnt[wave][dg] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[dg] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][dg];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        const int t = threadIdx.x;
+        run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+        // the next iteration's clearing is ordered after this update by its barrier
+        __syncthreads();
+    }
+}
+
+int radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, size_t n, uint32_t digit_mask,
+                     hipStream_t s) {
+    if (n <= 1 || digit_mask == 0) return 0;
+    IG_REQUIRE(n < (1ull << 32), IG_E_UNSUPPORTED, "radix sort of more than 2^32 elements");
+    size_t tiles = (n + RS_TILE - 1) / RS_TILE;
+    Scratch<uint32_t> hist(tiles * 256, s);
+    uint64_t *ka = k0, *kb = k1;
+    uint32_t *va = v0, *vb = v1;
+    int cur = 0;
+    for (int pass = 0; pass < 8; ++pass) {
+        if (!((digit_mask >> pass) & 1u)) continue;
+        int shift = pass * 8;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(RS_T), 0, s, ka, n, shift, hist.get(),
+                           (uint32_t)tiles);
+        IG_HIP(hipGetLastError());
+        scan_exclusive_u32(hist.get(), hist.get(), tiles * 256, nullptr, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(RS_T), 0, s, ka, va, kb, vb, n, shift,
+                           (const uint32_t *)hist.get(), (uint32_t)tiles);
+        IG_HIP(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+}  // namespace ig

@@ -1,0 +1,485 @@
+// The subset-test kernels of libig (gfx950, wave64).
+//
+// Every kernel evaluates Eq. 6 of the paper: b is inside r exactly when
+// (b AND NOT r) is zero on every word.  The rows that all lanes of a wave test
+// against are wave-uniform and come in through scalar loads into SGPRs; each lane
+// holds its own bitsets in VGPRs, pre-complemented where that saves an op, so a
+// 64-bit word costs two v_and_or_b32 (one per 32-bit half) and a test ends with
+// one v_cmp whose lane mask is examined by the scalar unit.
+//
+//   k_coherence  Eq. 3: lanes = candidates (x_i AND x_j rebuilt from the pair
+//                id), uniform = complemented rows of the other class, scanned in
+//                input order; a wave stops when all its candidates are covered.
+//   k_support    Eq. 2: lanes = ordered patterns, uniform = complemented rows of
+//                the same class; counts the rows containing each pattern.
+//   k_score      Eq. 4: lanes = flows (packed from their codes in registers and
+//                complemented), uniform = patterns with their weights.
+#include "common.h"
+#include "kernels.h"
+
+namespace ig {
+
+typedef const __attribute__((address_space(4))) uint32_t *cptr32;   // scalar-loadable view
+typedef const __attribute__((address_space(4))) int64_t *cptr64;
+
+// OR over words of (r AND b) with r uniform in SGPRs and b per lane, as one
+// v_and_or_b32 per 32-bit word.  Written as inline-asm blocks of 8/4/2 words:
+// left to itself the compiler rebalances the chain into a tree with ~40% more
+// instructions, and one asm statement per word costs an s_nop each.
+#define IG_AO_S(i) "s"(s[i])
+#define IG_AO_V(i) "v"(v[i])
+__device__ __forceinline__ uint32_t ao8(uint32_t acc, const uint32_t *s, const uint32_t *v, bool first) {
+    if (first)
+        asm("v_and_b32 %0, %1, %9\n\tv_and_or_b32 %0, %2, %10, %0\n\tv_and_or_b32 %0, %3, %11, %0\n\t"
+            "v_and_or_b32 %0, %4, %12, %0\n\tv_and_or_b32 %0, %5, %13, %0\n\tv_and_or_b32 %0, %6, %14, %0\n\t"
+            "v_and_or_b32 %0, %7, %15, %0\n\tv_and_or_b32 %0, %8, %16, %0"
+            : "=&v"(acc)
+            : IG_AO_S(0), IG_AO_S(1), IG_AO_S(2), IG_AO_S(3), IG_AO_S(4), IG_AO_S(5), IG_AO_S(6), IG_AO_S(7),
+              IG_AO_V(0), IG_AO_V(1), IG_AO_V(2), IG_AO_V(3), IG_AO_V(4), IG_AO_V(5), IG_AO_V(6), IG_AO_V(7));
+    else
+        asm("v_and_or_b32 %0, %1, %9, %0\n\tv_and_or_b32 %0, %2, %10, %0\n\tv_and_or_b32 %0, %3, %11, %0\n\t"
+            "v_and_or_b32 %0, %4, %12, %0\n\tv_and_or_b32 %0, %5, %13, %0\n\tv_and_or_b32 %0, %6, %14, %0\n\t"
+            "v_and_or_b32 %0, %7, %15, %0\n\tv_and_or_b32 %0, %8, %16, %0"
+            : "+v"(acc)
+            : IG_AO_S(0), IG_AO_S(1), IG_AO_S(2), IG_AO_S(3), IG_AO_S(4), IG_AO_S(5), IG_AO_S(6), IG_AO_S(7),
+              IG_AO_V(0), IG_AO_V(1), IG_AO_V(2), IG_AO_V(3), IG_AO_V(4), IG_AO_V(5), IG_AO_V(6), IG_AO_V(7));
+    return acc;
+}
+__device__ __forceinline__ uint32_t ao4(uint32_t acc, const uint32_t *s, const uint32_t *v, bool first) {
+    if (first)
+        asm("v_and_b32 %0, %1, %5\n\tv_and_or_b32 %0, %2, %6, %0\n\tv_and_or_b32 %0, %3, %7, %0\n\t"
+            "v_and_or_b32 %0, %4, %8, %0"
+            : "=&v"(acc)
+            : IG_AO_S(0), IG_AO_S(1), IG_AO_S(2), IG_AO_S(3), IG_AO_V(0), IG_AO_V(1), IG_AO_V(2), IG_AO_V(3));
+    else
+        asm("v_and_or_b32 %0, %1, %5, %0\n\tv_and_or_b32 %0, %2, %6, %0\n\tv_and_or_b32 %0, %3, %7, %0\n\t"
+            "v_and_or_b32 %0, %4, %8, %0"
+            : "+v"(acc)
+            : IG_AO_S(0), IG_AO_S(1), IG_AO_S(2), IG_AO_S(3), IG_AO_V(0), IG_AO_V(1), IG_AO_V(2), IG_AO_V(3));
+    return acc;
+}
+__device__ __forceinline__ uint32_t ao2(uint32_t acc, const uint32_t *s, const uint32_t *v, bool first) {
+    if (first)
+        asm("v_and_b32 %0, %1, %3\n\tv_and_or_b32 %0, %2, %4, %0" : "=&v"(acc)
+            : IG_AO_S(0), IG_AO_S(1), IG_AO_V(0), IG_AO_V(1));
+    else
+        asm("v_and_or_b32 %0, %1, %3, %0\n\tv_and_or_b32 %0, %2, %4, %0" : "+v"(acc)
+            : IG_AO_S(0), IG_AO_S(1), IG_AO_V(0), IG_AO_V(1));
+    return acc;
+}
+#undef IG_AO_S
+#undef IG_AO_V
+
+template <int W>   // W (even) 32-bit words: OR_k (r_k AND b_k), r uniform
+__device__ __forceinline__ uint32_t masked_or(cptr32 r, const uint32_t (&b)[W]) {
+    uint32_t s[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) s[k] = r[k];
+    uint32_t acc = 0;
+    int k = 0;
+#pragma unroll
+    for (; k + 8 <= W; k += 8) acc = ao8(acc, s + k, b + k, k == 0);
+    if (k + 4 <= W) { acc = ao4(acc, s + k, b + k, k == 0); k += 4; }
+    if (k + 2 <= W) { acc = ao2(acc, s + k, b + k, k == 0); k += 2; }
+    return acc;
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ void load_pair_row(const uint64_t *__restrict__ X, uint32_t KS, uint64_t q, uint32_t n,
+                                              bool active, uint32_t *out, int W) {
+    uint32_t i = 0, j = 0;
+    if (active) decode_pair(q, n, i, j);
+    const uint32_t *a = reinterpret_cast<const uint32_t *>(X + (size_t)i * KS);
+    const uint32_t *b = reinterpret_cast<const uint32_t *>(X + (size_t)j * KS);
+    for (int k = 0; k < W; ++k) out[k] = active ? (a[k] & b[k]) : 0u;
+}
+
+// ------------------------------------------------------------ coherence ----
+template <int KS, int CPL>
+__global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ segs, uint32_t nseg,
+                                                  const uint32_t *__restrict__ task_prefix,
+                                                  uint32_t *__restrict__ queue) {
+    constexpr int W = 2 * KS;
+    const int lane = threadIdx.x & 63;
+    const uint32_t ntasks = uniform(task_prefix[nseg]);
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(queue, 1u);
+        t = uniform(__shfl(t, 0, 64));
+        if (t >= ntasks) break;
+        uint32_t sg = 0;
+        while (sg + 1 < nseg && task_prefix[sg + 1] <= t) ++sg;
+        sg = uniform(sg);
+        const CohSeg g = segs[sg];
+        const uint32_t base = (t - uniform(task_prefix[sg])) * (64u * CPL);
+
+        uint32_t b[CPL][W];
+        uint32_t pid[CPL];
+        uint64_t cov[CPL];
+        uint32_t tpos[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            uint32_t idx = base + c * 64 + lane;
+            bool act = idx < g.ncand;
+            pid[c] = act ? g.cand[idx] : 0u;
+            uint32_t i = 0, j = 0;
+            if (act) decode_pair(pid[c], g.n, i, j);
+            const uint32_t *ra = reinterpret_cast<const uint32_t *>(g.X + (size_t)i * KS);
+            const uint32_t *rb = reinterpret_cast<const uint32_t *>(g.X + (size_t)j * KS);
+#pragma unroll
+            for (int k = 0; k < W; ++k) b[c][k] = ra[k] & rb[k];
+            cov[c] = ~__ballot(act);   // lanes without a candidate count as done
+            tpos[c] = 0;
+        }
+        cptr32 R = (cptr32)(const void *)g.NXo;
+        const uint32_t n_o = g.n_o;
+        uint64_t done = 0;
+        for (uint32_t r = 0; r < n_o; ++r) {
+            cptr32 rr = R + (size_t)r * W;
+            done = ~0ull;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                uint32_t acc = masked_or<W>(rr, b[c]);
+                uint64_t m = __ballot(acc == 0u);
+                uint64_t nw = m & ~cov[c];
+                if (nw) {
+                    if ((nw >> lane) & 1ull) tpos[c] = r + 1;
+                    cov[c] |= nw;
+                }
+                done &= cov[c];
+            }
+            if (done == ~0ull) break;
+        }
+        // survivors: active lanes never covered
+        uint64_t tsum = 0;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            uint32_t idx = base + c * 64 + lane;
+            bool act = idx < g.ncand;
+            bool keep = act && !((cov[c] >> lane) & 1ull);
+            uint64_t km = __ballot(keep);
+            uint32_t cnt = (uint32_t)__popcll(km);
+            uint32_t at = 0;
+            if (lane == 0 && cnt) at = atomicAdd(g.nsurv, cnt);
+            at = __shfl(at, 0, 64);
+            if (keep) {
+                uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+                g.surv[at + (uint32_t)__popcll(km & lt)] = pid[c];
+            }
+            if (act) tsum += tpos[c] ? tpos[c] : n_o;
+        }
+        for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
+        if (lane == 0 && tsum) atomicAdd(g.tests, (unsigned long long)tsum);
+    }
+}
+
+// -------------------------------------------------------------- support ----
+template <int KS, int CPL>
+__global__ __launch_bounds__(256) void k_support(const uint64_t *__restrict__ Wrows, size_t m,
+                                                const uint64_t *__restrict__ NX, uint32_t n,
+                                                uint32_t *__restrict__ f_out, int64_t *__restrict__ S_out) {
+    constexpr int W = 2 * KS;
+    const size_t base = (size_t)blockIdx.x * (256 * CPL);
+    uint32_t b[CPL][W];
+    uint32_t cnt[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        size_t e = base + (size_t)c * 256 + threadIdx.x;
+        bool act = e < m;
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(Wrows + (act ? e : 0) * KS);
+#pragma unroll
+        for (int k = 0; k < W; ++k) b[c][k] = act ? row[k] : 0u;
+        cnt[c] = 0;
+    }
+    cptr32 R = (cptr32)(const void *)NX;
+    for (uint32_t r = 0; r < n; ++r) {
+        cptr32 rr = R + (size_t)r * W;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) cnt[c] += masked_or<W>(rr, b[c]) == 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        size_t e = base + (size_t)c * 256 + threadIdx.x;
+        if (e < m) {
+            uint32_t len = 0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) len += __popc(b[c][k]);
+            f_out[e] = cnt[c];
+            S_out[e] = (int64_t)cnt[c] * (int64_t)len * (int64_t)len;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- score ----
+struct ScoreArgs {
+    const uint64_t *P[2];
+    const int64_t *S[2];
+    uint64_t np[2];
+    uint64_t chunk[2];          // patterns per y-block
+    const uint16_t *codes;      // [n][d] or null
+    const uint64_t *words;      // [n][K] or null
+    const uint32_t *meta;       // off[d] | flo[KS] | fhi[KS]
+    const uint16_t *nbins;
+    int64_t *out;               // [n][2] = (A, N)
+    uint32_t n_flows, d, K;
+    uint32_t narrow[2];         // all weights of the class below 2^31
+    uint32_t flush[2];          // patterns per 32-bit partial sum
+};
+
+template <int KS>
+__device__ __forceinline__ bool load_flow(const ScoreArgs &a, uint32_t t, uint32_t (&nt)[2 * KS]) {
+    uint64_t w[KS];
+    bool ok = true;
+    if (a.codes) {
+        const uint16_t *row = a.codes + (size_t)t * a.d;
+        const uint32_t *off = a.meta, *flo = a.meta + a.d, *fhi = a.meta + a.d + KS;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            uint64_t v = 0;
+            for (uint32_t f = flo[k]; f < fhi[k]; ++f) {
+                uint32_t c = row[f];
+                ok &= c < a.nbins[f];
+                uint32_t bit = off[f] + c;
+                if ((bit >> 6) == (uint32_t)k) v |= 1ull << (bit & 63);
+            }
+            w[k] = v;
+        }
+    } else {
+        const uint64_t *row = a.words + (size_t)t * a.K;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) w[k] = k < (int)a.K ? row[k] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        // complement; an invalid flow contains nothing, so no pattern matches it
+        uint64_t c = ok ? ~w[k] : ~0ull;
+        nt[2 * k] = (uint32_t)c;
+        nt[2 * k + 1] = (uint32_t)(c >> 32);
+    }
+    return ok;
+}
+
+__global__ void k_score_init(ScoreArgs a) {
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_flows) return;
+    bool ok = true;
+    if (a.codes) {
+        const uint16_t *row = a.codes + (size_t)t * a.d;
+        for (uint32_t f = 0; f < a.d; ++f) ok &= row[f] < a.nbins[f];
+    }
+    int64_t v = ok ? 0 : -1;
+    a.out[2 * (size_t)t] = v;
+    a.out[2 * (size_t)t + 1] = v;
+}
+
+template <int KS, int FPL>
+__global__ __launch_bounds__(256) void k_score(ScoreArgs a) {
+    constexpr int W = 2 * KS;
+    const int cls = blockIdx.z;
+    const uint64_t np = a.np[cls];
+    const uint64_t p0 = (uint64_t)blockIdx.y * a.chunk[cls];
+    if (p0 >= np) return;
+    const uint64_t p1 = p0 + a.chunk[cls] < np ? p0 + a.chunk[cls] : np;
+    uint32_t nt[FPL][W];
+    uint64_t sum[FPL];
+    bool act[FPL];
+#pragma unroll
+    for (int c = 0; c < FPL; ++c) {
+        uint32_t t = (blockIdx.x * FPL + c) * 256 + threadIdx.x;
+        act[c] = t < a.n_flows;
+        load_flow<KS>(a, act[c] ? t : 0, nt[c]);
+        sum[c] = 0;
+    }
+    cptr32 P = (cptr32)(const void *)a.P[cls] + p0 * W;
+    cptr64 S = (cptr64)(const void *)a.S[cls] + p0;
+    const uint32_t cnt = (uint32_t)(p1 - p0);
+    if (a.narrow[cls]) {
+        // every weight < 2^31: 32-bit partial sums, flushed before they can wrap
+        const uint32_t flush = a.flush[cls];
+        for (uint32_t q0 = 0; q0 < cnt; q0 += flush) {
+            const uint32_t q1 = q0 + flush < cnt ? q0 + flush : cnt;
+            uint32_t lo[FPL];
+#pragma unroll
+            for (int c = 0; c < FPL; ++c) lo[c] = 0;
+            for (uint32_t q = q0; q < q1; ++q) {
+                cptr32 pp = P + (size_t)q * W;
+                const uint32_t s = (uint32_t)S[q];
+#pragma unroll
+                for (int c = 0; c < FPL; ++c)
+                    if (masked_or<W>(pp, nt[c]) == 0u) lo[c] += s;
+            }
+#pragma unroll
+            for (int c = 0; c < FPL; ++c) sum[c] += lo[c];
+        }
+    } else {
+        for (uint32_t q = 0; q < cnt; ++q) {
+            cptr32 pp = P + (size_t)q * W;
+            const int64_t s = S[q];
+#pragma unroll
+            for (int c = 0; c < FPL; ++c)
+                if (masked_or<W>(pp, nt[c]) == 0u) sum[c] += (uint64_t)s;
+        }
+    }
+    const int col = cls == 1 ? 0 : 1;   // A from class 1, N from class 0
+#pragma unroll
+    for (int c = 0; c < FPL; ++c) {
+        uint32_t t = (blockIdx.x * FPL + c) * 256 + threadIdx.x;
+        if (act[c] && sum[c]) atomicAdd(reinterpret_cast<unsigned long long *>(a.out + 2 * (size_t)t + col),
+                                        (unsigned long long)sum[c]);
+    }
+}
+
+// largest S and total of S (for the int64 overflow bound of Eq. 4 sums)
+__global__ void k_maxsum(const int64_t *__restrict__ S, size_t m, unsigned long long *__restrict__ ms) {
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = e < m ? (unsigned long long)S[e] : 0ull;
+    unsigned long long mx = v, sm = v;
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long u = __shfl_xor(mx, o, 64);
+        mx = u > mx ? u : mx;
+        sm += __shfl_xor(sm, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&ms[0], mx);
+        atomicAdd(&ms[1], sm);
+    }
+}
+
+// ---------------------------------------------------------- dispatching ----
+#define IG_FOR_EACH_KS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(14) X(16) X(20) X(24) X(28) X(32) X(40) X(48) X(56) X(64)
+
+int storage_words(int K) {
+    static const int ks[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64};
+    for (int v : ks)
+        if (K <= v) return v;
+    return -1;
+}
+
+uint32_t coherence_grid(int KS, int cpl) {
+    (void)KS;
+    (void)cpl;
+    static int cached[64] = {0};
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+        if (!cached[dev]) {
+            int v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                cached[dev] = v;
+            else
+                cached[dev] = 256;
+        }
+        cus = cached[dev];
+    }
+    return (uint32_t)cus * 8u;   // persistent: 8 workgroups (32 waves) per CU
+}
+
+void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, const uint32_t *task_prefix_dev,
+                      uint32_t *queue, uint32_t grid, hipStream_t s) {
+    launch_fill_u32(queue, 0u, 1, s);
+#define IG_COH(V)                                                                                              \
+    case V:                                                                                                    \
+        if (cpl == 2 && V <= 16)                                                                               \
+            hipLaunchKernelGGL((k_coherence<V, 2>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, task_prefix_dev, \
+                               queue);                                                                         \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_coherence<V, 1>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, task_prefix_dev, \
+                               queue);                                                                         \
+        break;
+    switch (KS) {
+        IG_FOR_EACH_KS(IG_COH)
+        default: throw Error(IG_E_UNSUPPORTED, "unsupported word count");
+    }
+#undef IG_COH
+    IG_HIP(hipGetLastError());
+}
+
+void launch_support(int KS, int cpl, const uint64_t *W, size_t m, const uint64_t *NX, uint32_t n, uint32_t *f,
+                    int64_t *S, hipStream_t s) {
+    if (!m) return;
+    const int c = (cpl == 2 && KS <= 16) ? 2 : 1;
+    dim3 grid((unsigned)((m + 256 * c - 1) / (256 * c)));
+#define IG_SUP(V)                                                                                     \
+    case V:                                                                                           \
+        if (c == 2)                                                                                   \
+            hipLaunchKernelGGL((k_support<V, 2>), grid, dim3(256), 0, s, W, m, NX, n, f, S);          \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_support<V, 1>), grid, dim3(256), 0, s, W, m, NX, n, f, S);          \
+        break;
+    switch (KS) {
+        IG_FOR_EACH_KS(IG_SUP)
+        default: throw Error(IG_E_UNSUPPORTED, "unsupported word count");
+    }
+#undef IG_SUP
+    IG_HIP(hipGetLastError());
+}
+
+void launch_score(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K, uint32_t n_flows,
+                  uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out, int fpl, hipStream_t s) {
+    if (!n_flows) return;
+    ScoreArgs a{};
+    for (int c = 0; c < 2; ++c) {
+        a.P[c] = m.P[c];
+        a.S[c] = m.S[c];
+        a.np[c] = m.np[c];
+    }
+    a.codes = codes;
+    a.words = words;
+    a.meta = meta;
+    a.nbins = nbins;
+    a.out = out;
+    a.n_flows = n_flows;
+    a.d = d;
+    a.K = K;
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t mx = m.maxS[c] > 0 ? (uint64_t)m.maxS[c] : 1ull;
+        a.narrow[c] = mx < (1ull << 31);
+        uint64_t fl = 0xffffffffull / mx;
+        a.flush[c] = (uint32_t)(fl < 1 ? 1 : (fl > (1u << 30) ? (1u << 30) : fl));
+    }
+    hipLaunchKernelGGL(k_score_init, dim3((n_flows + 255) / 256), dim3(256), 0, s, a);
+    IG_HIP(hipGetLastError());
+    const int KS = (int)m.KS;
+    const int f = (fpl == 2 && KS <= 16) ? 2 : 1;
+    const uint32_t fblocks = (n_flows + 256 * f - 1) / (256 * f);
+    // enough workgroups to fill the chip: split the pattern range into chunks
+    const uint64_t target_blocks = 256ull * 8ull;
+    uint64_t npmax = m.np[0] > m.np[1] ? m.np[0] : m.np[1];
+    if (npmax == 0) return;
+    uint64_t ychunks = (target_blocks + 2ull * fblocks - 1) / (2ull * fblocks);
+    if (ychunks < 1) ychunks = 1;
+    for (int c = 0; c < 2; ++c) {
+        uint64_t ch = (m.np[c] + ychunks - 1) / ychunks;
+        if (ch < 64) ch = 64;
+        a.chunk[c] = ch;
+    }
+    uint64_t ny0 = (m.np[0] + a.chunk[0] - 1) / a.chunk[0], ny1 = (m.np[1] + a.chunk[1] - 1) / a.chunk[1];
+    uint64_t ny = ny0 > ny1 ? ny0 : ny1;
+    if (ny > 65535) {   // grid.y limit: enlarge the chunks
+        for (int c = 0; c < 2; ++c) a.chunk[c] = (m.np[c] + 65534) / 65535;
+        ny = 65535;
+    }
+    dim3 grid(fblocks, (unsigned)ny, 2);
+#define IG_SC(V)                                                                          \
+    case V:                                                                               \
+        if (f == 2)                                                                       \
+            hipLaunchKernelGGL((k_score<V, 2>), grid, dim3(256), 0, s, a);                \
+        else                                                                              \
+            hipLaunchKernelGGL((k_score<V, 1>), grid, dim3(256), 0, s, a);                \
+        break;
+    switch (KS) {
+        IG_FOR_EACH_KS(IG_SC)
+        default: throw Error(IG_E_UNSUPPORTED, "unsupported word count");
+    }
+#undef IG_SC
+    IG_HIP(hipGetLastError());
+}
+
+void launch_reduce_maxsum(const int64_t *S, size_t m, unsigned long long *d_max_sum, hipStream_t s) {
+    launch_fill_u64(reinterpret_cast<uint64_t *>(d_max_sum), 0ull, 2, s);
+    if (!m) return;
+    hipLaunchKernelGGL(k_maxsum, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, S, m, d_max_sum);
+    IG_HIP(hipGetLastError());
+}
+
+}  // namespace ig

@@ -1,0 +1,293 @@
+"""Python binding of libig (ctypes): argument marshalling only.
+
+Every step of the IG hot path runs in the HIP kernels of ``libig.so``;
+PyTorch only provides device memory and streams.  The binding fails loudly when
+the library has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libig.so")
+
+IG_OK, IG_E_INVAL, IG_E_NOMEM, IG_E_DEVICE, IG_E_OVERFLOW, IG_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+_NAMES = {0: "IG_OK", -1: "IG_E_INVAL", -2: "IG_E_NOMEM", -3: "IG_E_DEVICE", -4: "IG_E_OVERFLOW",
+          -5: "IG_E_UNSUPPORTED"}
+ABSENT = 0xFFFF
+
+
+class IGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class FitOpts(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_uint64), ("filter_cpl", C.c_uint32), ("score_fpl", C.c_uint32),
+                ("block", C.c_uint32), ("reserved", C.c_uint32 * 5)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_class", C.c_uint64 * 2), ("pairs", C.c_uint64 * 2), ("distinct", C.c_uint64 * 2),
+                ("coherent", C.c_uint64 * 2), ("tests", C.c_uint64 * 2), ("support_tests", C.c_uint64 * 2),
+                ("chunks", C.c_uint32 * 2), ("ms", C.c_float * 8)]
+
+
+class ModelInfo(C.Structure):
+    _fields_ = [("K", C.c_uint32), ("L", C.c_uint32), ("d", C.c_uint32), ("reserved", C.c_uint32),
+                ("n_patterns", C.c_uint64 * 2), ("max_weight", C.c_int64 * 2)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("d_codes", C.c_void_p), ("d_labels", C.c_void_p), ("n", C.c_uint32), ("d", C.c_uint32),
+                ("h_nbins", C.c_void_p)]
+
+
+_lib = None
+
+# every symbol include/ig.h declares
+EXPORTS = ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_packed", "ig_model_get_info",
+           "ig_model_export", "ig_model_import", "ig_fit_stats", "ig_model_free", "ig_last_error", "ig_version")
+
+
+def lib():
+    """Load libig.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise IGError(IG_E_DEVICE, f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
+    L.ig_fit.argtypes = [vp, vp, u32, u32, vp, C.POINTER(FitOpts), vp, C.POINTER(vp)]
+    L.ig_fit_packed.argtypes = [vp, vp, u32, u32, C.POINTER(FitOpts), vp, C.POINTER(vp)]
+    L.ig_fit_batch.argtypes = [C.POINTER(Problem), u32, C.POINTER(FitOpts), vp, C.POINTER(vp)]
+    L.ig_score.argtypes = [vp, vp, u32, vp, vp]
+    L.ig_score_packed.argtypes = [vp, vp, u32, vp, vp]
+    L.ig_model_get_info.argtypes = [vp, C.POINTER(ModelInfo)]
+    L.ig_model_export.argtypes = [vp, u32, vp, vp, vp]
+    L.ig_model_import.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(u64), u32, vp, vp, C.POINTER(vp)]
+    L.ig_fit_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.ig_model_free.argtypes = [vp]
+    L.ig_model_free.restype = None
+    L.ig_last_error.restype = C.c_char_p
+    L.ig_version.restype = C.c_char_p
+    for name in ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_packed", "ig_model_get_info",
+                 "ig_model_export", "ig_model_import", "ig_fit_stats"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != IG_OK:
+        raise IGError(status, lib().ig_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> C.c_void_p:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(a, dtype):
+    """A contiguous device tensor of the given torch dtype (copies host arrays)."""
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        t = a
+        if t.dtype != dtype:
+            t = t.to(dtype)
+        if not t.is_cuda:
+            t = t.cuda()
+        return t.contiguous()
+    arr = np.ascontiguousarray(a)
+    # keep the bits: unsigned 16/64-bit arrays travel as their signed views
+    if arr.dtype == np.uint16:
+        arr = arr.view(np.int16)
+    elif arr.dtype == np.uint64:
+        arr = arr.view(np.int64)
+    t = torch.from_numpy(arr).to(device="cuda")
+    return (t if t.dtype == dtype else t.to(dtype)).contiguous()
+
+
+def _np_u16(a) -> np.ndarray:
+    if hasattr(a, "cpu"):
+        a = a.cpu().numpy()
+    return np.ascontiguousarray(a, dtype=np.uint16)
+
+
+def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0) -> FitOpts:
+    o = FitOpts()
+    o.mem_budget_bytes = int(mem_budget_bytes)
+    o.filter_cpl = int(filter_cpl)
+    o.score_fpl = int(score_fpl)
+    return o
+
+
+@dataclass
+class FitStats:
+    n_class: Tuple[int, int]
+    pairs: Tuple[int, int]
+    distinct: Tuple[int, int]
+    coherent: Tuple[int, int]
+    tests: Tuple[int, int]
+    support_tests: Tuple[int, int]
+    chunks: Tuple[int, int]
+    ms: Tuple[float, ...]
+
+
+class Model:
+    """A device-resident pair of coherent pattern sets (P^0 normal, P^1 attack)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+
+    @property
+    def handle(self) -> C.c_void_p:
+        if not self._h:
+            raise IGError(IG_E_INVAL, "model already freed")
+        return self._h
+
+    def info(self) -> ModelInfo:
+        i = ModelInfo()
+        _check(lib().ig_model_get_info(self.handle, C.byref(i)))
+        return i
+
+    @property
+    def K(self) -> int:
+        return int(self.info().K)
+
+    def n_patterns(self) -> Tuple[int, int]:
+        i = self.info()
+        return int(i.n_patterns[0]), int(i.n_patterns[1])
+
+    def stats(self) -> FitStats:
+        s = Stats()
+        _check(lib().ig_fit_stats(self.handle, C.byref(s)))
+        t = lambda a: (int(a[0]), int(a[1]))
+        return FitStats(t(s.n_class), t(s.pairs), t(s.distinct), t(s.coherent), t(s.tests), t(s.support_tests),
+                        t(s.chunks), tuple(float(x) for x in s.ms))
+
+    def export(self, cls: int):
+        """(words uint64 [n, K], f uint32 [n], S int64 [n]) of class ``cls``, ascending."""
+        i = self.info()
+        n, K = int(i.n_patterns[cls]), int(i.K)
+        w = np.zeros((n, K), np.uint64)
+        f = np.zeros(n, np.uint32)
+        S = np.zeros(n, np.int64)
+        ptr = lambda a: C.c_void_p(a.ctypes.data) if a.size else None
+        _check(lib().ig_model_export(self.handle, cls, ptr(w), ptr(f), ptr(S)))
+        return w, f, S
+
+    def free(self) -> None:
+        if self._h:
+            lib().ig_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, stream=None) -> Model:
+    """ig_fit: codes [n, d] bin codes, labels [n] (0 normal / 1 attack), nbins [d]."""
+    torch = _torch()
+    dc = _dev(codes, torch.int16)
+    dl = _dev(labels, torch.uint8)
+    n, d = (int(dc.shape[0]), int(dc.shape[1])) if dc.dim() == 2 else (0, 0)
+    nb = _np_u16(nbins)
+    h = C.c_void_p()
+    o = _opts(mem_budget_bytes, filter_cpl)
+    _check(lib().ig_fit(C.c_void_p(dc.data_ptr()), C.c_void_p(dl.data_ptr()), n, d or nb.size,
+                        C.c_void_p(nb.ctypes.data), C.byref(o), _stream_handle(stream), C.byref(h)))
+    return Model(h)
+
+
+def fit_packed(words, labels, mem_budget_bytes: int = 0, stream=None) -> Model:
+    """ig_fit_packed: words [n, K] uint64 bitsets (Eq. 5 layout), labels [n]."""
+    torch = _torch()
+    dw = _dev(np.ascontiguousarray(words).view(np.int64) if isinstance(words, np.ndarray) else words,
+              torch.int64)
+    dl = _dev(labels, torch.uint8)
+    n, K = int(dw.shape[0]), int(dw.shape[1])
+    h = C.c_void_p()
+    o = _opts(mem_budget_bytes)
+    _check(lib().ig_fit_packed(C.c_void_p(dw.data_ptr()), C.c_void_p(dl.data_ptr()), n, K, C.byref(o),
+                               _stream_handle(stream), C.byref(h)))
+    return Model(h)
+
+
+def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, stream=None) -> List[Model]:
+    """ig_fit_batch over problems with attributes codes, labels, nbins."""
+    torch = _torch()
+    keep = []
+    arr = (Problem * len(problems))()
+    for p, pr in enumerate(problems):
+        dc = _dev(pr.codes, torch.int16)
+        dl = _dev(pr.labels, torch.uint8)
+        nb = _np_u16(pr.nbins)
+        keep += [dc, dl, nb]
+        arr[p].d_codes = dc.data_ptr()
+        arr[p].d_labels = dl.data_ptr()
+        arr[p].n = int(dc.shape[0])
+        arr[p].d = int(nb.size)
+        arr[p].h_nbins = nb.ctypes.data
+    outs = (C.c_void_p * len(problems))()
+    o = _opts(mem_budget_bytes)
+    _check(lib().ig_fit_batch(arr, len(problems), C.byref(o), _stream_handle(stream), outs))
+    return [Model(C.c_void_p(outs[p])) for p in range(len(problems))]
+
+
+def score(model: Model, flows, out=None, stream=None):
+    """ig_score: (A, N) per flow as an int64 device tensor [n, 2] (asynchronous)."""
+    torch = _torch()
+    dc = _dev(flows, torch.int16)
+    n = int(dc.shape[0])
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.int64, device=dc.device)
+    _check(lib().ig_score(model.handle, C.c_void_p(dc.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                          _stream_handle(stream)))
+    return out
+
+
+def score_packed(model: Model, words, out=None, stream=None):
+    torch = _torch()
+    dw = _dev(np.ascontiguousarray(words).view(np.int64) if isinstance(words, np.ndarray) else words,
+              torch.int64)
+    n = int(dw.shape[0])
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.int64, device=dw.device)
+    _check(lib().ig_score_packed(model.handle, C.c_void_p(dw.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                 _stream_handle(stream)))
+    return out
+
+
+def import_patterns(codes0, f0, codes1, f1, nbins, stream=None) -> Model:
+    """ig_model_import from pattern code rows (ABSENT = feature not in the pattern)."""
+    c = [np.ascontiguousarray(codes0, np.uint16), np.ascontiguousarray(codes1, np.uint16)]
+    f = [np.ascontiguousarray(f0, np.uint32), np.ascontiguousarray(f1, np.uint32)]
+    nb = _np_u16(nbins)
+    pc = (C.c_void_p * 2)(*[x.ctypes.data for x in c])
+    pf = (C.c_void_p * 2)(*[x.ctypes.data for x in f])
+    cnt = (C.c_uint64 * 2)(c[0].shape[0], c[1].shape[0])
+    h = C.c_void_p()
+    _check(lib().ig_model_import(pc, pf, cnt, int(nb.size), C.c_void_p(nb.ctypes.data),
+                                 _stream_handle(stream), C.byref(h)))
+    return Model(h)
+
+
+def version() -> str:
+    return lib().ig_version().decode()

@@ -1,0 +1,325 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer, exact work: every comparison is bit-exact (patterns, f, S, counters,
+scores).  Small sizes compare whole outputs; the 15k workload compares digests
+of the whole output with the oracle's stored ones; the 148k workload compares
+oracle facts on sampled pairs and flows plus properties that hold at any size.
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_14222_amd import ig, synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print("[parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_arrays(m):
+    return [m.export(c) for c in (0, 1)]
+
+
+def assert_same_model(m, om, K):
+    for c in (0, 1):
+        w, f, S = m.export(c)
+        ow = om.patterns[c]
+        assert w.shape == ow.shape, (c, w.shape, ow.shape)
+        assert np.array_equal(w, ow), f"class {c}: pattern words differ"
+        assert np.array_equal(f, om.f[c]), f"class {c}: supports differ"
+        assert np.array_equal(S, om.S[c]), f"class {c}: weights differ"
+
+
+def assert_same_stats(m, om):
+    st = m.stats()
+    assert list(st.pairs) == om.stats["pairs"]
+    assert list(st.distinct) == om.stats["distinct"]
+    assert list(st.coherent) == om.stats["coherent"]
+    assert list(st.tests) == om.stats["tests"]
+    assert list(st.n_class) == om.stats["n_class"]
+
+
+def gpu_scores(m, flows):
+    out = ig.score(m, flows)
+    import torch
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    return o[:, 0], o[:, 1]
+
+
+# ------------------------------------------------------------ worked example
+def test_worked_example():
+    g = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    say("worked example")
+    m = ig.fit(np.array(g["codes"], np.uint16), np.array(g["labels"], np.uint8), np.array(g["nbins"], np.uint16))
+    for c in ("0", "1"):
+        w, f, S = m.export(int(c))
+        got = [(int(w[p, 0]), int(f[p]), int(S[p])) for p in range(w.shape[0])]
+        assert got == [(int(h, 16), ff, SS) for h, ff, SS in g["patterns"][c]]
+    st = m.stats()
+    assert list(st.pairs) == g["stats"]["pairs"] and list(st.distinct) == g["stats"]["distinct"]
+    assert list(st.coherent) == g["stats"]["coherent"] and list(st.tests) == g["stats"]["tests"]
+    A, N = gpu_scores(m, np.array(g["flows"], np.uint16))
+    assert A.tolist() == g["A"] and N.tolist() == g["N"]
+
+
+# ------------------------------------------------------------ tiny workload
+def test_tiny_workload_full_parity():
+    w = synth.make_tiny(0)
+    say("tiny workload", w.codes.shape)
+    om = oracle.fit(w.codes, w.labels, w.nbins)
+    m = ig.fit(w.codes, w.labels, w.nbins)
+    assert_same_model(m, om, om.K)
+    assert_same_stats(m, om)
+    A, N = gpu_scores(m, w.test_codes)
+    oA, oN = oracle.score(om, w.test_codes, w.nbins)
+    assert np.array_equal(A, oA) and np.array_equal(N, oN)
+
+
+# ----------------------------------------------- random problems, all widths
+CASES = [
+    # seed, n, d, bins_lo, bins_hi, attack_frac   (K = ceil(sum bins / 64))
+    (1, 1, 3, 2, 3, 0.5),
+    (2, 2, 3, 2, 3, 0.5),
+    (3, 3, 2, 2, 2, 0.34),
+    (4, 63, 8, 2, 6, 0.5),
+    (5, 64, 8, 2, 6, 0.3),
+    (6, 65, 8, 2, 6, 0.7),
+    (7, 129, 10, 3, 9, 0.5),      # K = 1..2
+    (8, 200, 30, 4, 8, 0.5),      # K = 3
+    (9, 150, 40, 6, 10, 0.45),    # K = 5
+    (10, 180, 30, 12, 18, 0.5),   # K = 7
+    (11, 170, 41, 10, 14, 0.55),  # K = 8
+    (12, 140, 50, 10, 14, 0.5),   # K = 9..10
+    (13, 130, 60, 12, 16, 0.5),   # K = 13..14
+    (14, 120, 80, 12, 16, 0.5),   # K = 18..20
+    (15, 110, 80, 20, 26, 0.5),   # K = 29..32
+    (16, 100, 80, 28, 32, 0.5),   # K = 38..40
+    (17, 90, 120, 28, 32, 0.5),   # K = 57..60
+    (18, 300, 12, 2, 3, 0.5),     # dense overlaps, many duplicates
+    (19, 257, 6, 2, 2, 0.9),      # L = 12, heavy repetition, unbalanced
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"s{c[0]}-n{c[1]}-d{c[2]}" for c in CASES])
+def test_random_problem_parity(case):
+    seed, n, d, blo, bhi, af = case
+    p = synth.make_random_problem(seed, n, d, bins_lo=blo, bins_hi=bhi, attack_frac=af)
+    say("random problem", case, "L", p.L)
+    om = oracle.fit(p.codes, p.labels, p.nbins)
+    m = ig.fit(p.codes, p.labels, p.nbins)
+    assert m.K == om.K
+    assert_same_model(m, om, om.K)
+    assert_same_stats(m, om)
+    flows = synth.make_random_problem(seed + 1000, 97, d, bins_lo=blo, bins_hi=bhi).codes
+    flows = np.minimum(flows, p.nbins[None, :] - 1).astype(np.uint16)
+    flows = np.concatenate([flows, p.codes[: min(40, p.n)]])
+    A, N = gpu_scores(m, flows)
+    oA, oN = oracle.score(om, flows, p.nbins)
+    assert np.array_equal(A, oA) and np.array_equal(N, oN)
+
+
+def test_filter_lanes_per_candidate_agree():
+    p = synth.make_random_problem(21, 333, 20, bins_lo=3, bins_hi=7)
+    say("cpl 1 vs 2")
+    a = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=1)
+    b = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=2)
+    for c in (0, 1):
+        for x, y in zip(a.export(c), b.export(c)):
+            assert np.array_equal(x, y)
+    assert a.stats().tests == b.stats().tests
+
+
+# ------------------------------------------------------- chunked pair space
+def test_chunked_pair_space_gives_same_model():
+    w = synth.make_tiny(0)
+    say("chunked fit")
+    om = oracle.fit(w.codes, w.labels, w.nbins)
+    m = ig.fit(w.codes, w.labels, w.nbins, mem_budget_bytes=40 * 50_000)
+    st = m.stats()
+    assert st.chunks[0] > 1 and st.chunks[1] > 1
+    assert_same_model(m, om, om.K)
+    assert list(st.coherent) == om.stats["coherent"]
+
+
+# ----------------------------------------------------------- packed inputs
+def test_fit_packed_matches_codes_path():
+    p = synth.make_random_problem(31, 211, 14, bins_lo=3, bins_hi=9)
+    say("fit_packed")
+    words = oracle.pack(p.codes, p.nbins)
+    a = ig.fit(p.codes, p.labels, p.nbins)
+    b = ig.fit_packed(words, p.labels)
+    for c in (0, 1):
+        for x, y in zip(a.export(c), b.export(c)):
+            assert np.array_equal(x, y)
+    fl = oracle.pack(p.codes[:50], p.nbins)
+    out = ig.score_packed(b, fl).cpu().numpy()
+    A, N = gpu_scores(a, p.codes[:50])
+    assert np.array_equal(out[:, 0], A) and np.array_equal(out[:, 1], N)
+
+
+# ---------------------------------------------------------- imported sets
+def test_import_patterns_and_score():
+    rng = np.random.default_rng(41)
+    nb = synth.mixture41_nbins()
+    ps = synth.make_pattern_set(seed=41, per_class=3000)
+    say("import", [c.shape for c in ps.codes])
+    m = ig.import_patterns(ps.codes[0], ps.f[0], ps.codes[1], ps.f[1], nb)
+    om = oracle.model_from_patterns(ps.codes[0], ps.f[0], ps.codes[1], ps.f[1], nb)
+    for c in (0, 1):
+        order = np.lexsort(om.patterns[c].T[::-1])
+        w, f, S = m.export(c)
+        assert np.array_equal(w, om.patterns[c][order])
+        assert np.array_equal(f, om.f[c][order]) and np.array_equal(S, om.S[c][order])
+    flows = synth.make_flows(seed=42, n=700)
+    A, N = gpu_scores(m, flows)
+    oA, oN = oracle.score(om, flows, nb)
+    assert np.array_equal(A, oA) and np.array_equal(N, oN)
+    # repeated pattern -> rejected
+    dup = np.concatenate([ps.codes[0][:5], ps.codes[0][:1]])
+    with pytest.raises(ig.IGError) as e:
+        ig.import_patterns(dup, np.ones(6, np.uint32), ps.codes[1][:3], np.ones(3, np.uint32), nb)
+    assert e.value.status == ig.IG_E_INVAL
+
+
+# --------------------------------------------------- invalid and degenerate
+def test_invalid_codes_and_labels():
+    nb = np.array([3, 3], np.uint16)
+    say("invalid inputs")
+    with pytest.raises(ig.IGError) as e:
+        ig.fit(np.array([[0, 3], [1, 1]], np.uint16), np.array([0, 1], np.uint8), nb)
+    assert e.value.status == ig.IG_E_INVAL
+    with pytest.raises(ig.IGError) as e:
+        ig.fit(np.array([[0, 2], [1, 1]], np.uint16), np.array([0, 2], np.uint8), nb)
+    assert e.value.status == ig.IG_E_INVAL
+    m = ig.fit(np.array([[0, 2], [1, 1], [0, 1]], np.uint16), np.array([0, 1, 0], np.uint8), nb)
+    A, N = gpu_scores(m, np.array([[0, 2], [0, 7], [9, 0]], np.uint16))
+    assert A[1] == -1 and N[1] == -1 and A[2] == -1 and N[2] == -1
+    assert N[0] > 0
+
+
+def test_degenerate_sizes():
+    nb = np.array([2, 3, 4], np.uint16)
+    say("degenerate sizes")
+    # no records at all
+    m = ig.fit(np.zeros((0, 3), np.uint16), np.zeros(0, np.uint8), nb)
+    assert m.n_patterns() == (0, 0)
+    A, N = gpu_scores(m, np.array([[0, 0, 0]], np.uint16))
+    assert A[0] == 0 and N[0] == 0
+    for codes, labels in [
+        (np.array([[1, 2, 3]]), np.array([1])),                        # one record
+        (np.array([[1, 2, 3], [1, 2, 3], [0, 0, 0]]), np.array([0, 0, 0])),   # one class only
+        (np.array([[1, 2, 3], [1, 2, 3]]), np.array([0, 1])),         # contradiction
+        (np.array([[0, 0, 0], [1, 1, 1], [0, 1, 2], [1, 0, 3]]), np.array([0, 0, 1, 1])),  # empty pair ANDs
+    ]:
+        codes = codes.astype(np.uint16)
+        labels = labels.astype(np.uint8)
+        om = oracle.fit(codes, labels, nb)
+        m = ig.fit(codes, labels, nb)
+        assert_same_model(m, om, om.K)
+        assert_same_stats(m, om)
+
+
+def test_scores_do_not_depend_on_batching():
+    w = synth.make_tiny(0)
+    say("score batching")
+    m = ig.fit(w.codes, w.labels, w.nbins)
+    A, N = gpu_scores(m, w.test_codes)
+    rng = np.random.default_rng(3)
+    at = 0
+    while at < w.test_codes.shape[0]:
+        k = int(rng.integers(1, 70))
+        a, n = gpu_scores(m, w.test_codes[at:at + k])
+        assert np.array_equal(a, A[at:at + k]) and np.array_equal(n, N[at:at + k])
+        at += k
+
+
+# ----------------------------------------------------- full-size workloads
+def _model_digest(m):
+    h = hashlib.sha256()
+    for c in (0, 1):
+        w, f, S = m.export(c)
+        h.update(np.ascontiguousarray(w, dtype="<u8").tobytes())
+        h.update(np.ascontiguousarray(f, dtype="<u4").tobytes())
+        h.update(np.ascontiguousarray(S, dtype="<i8").tobytes())
+    return h.hexdigest()
+
+
+def test_15k_workload_matches_oracle_digest():
+    g = json.load(open(os.path.join(GOLD, "mixture41_15k.json")))
+    w = synth.make_15k()
+    say("15k workload", w.codes.shape, w.test_codes.shape)
+    m = ig.fit(w.codes, w.labels, w.nbins)
+    st = m.stats()
+    assert list(st.pairs) == g["stats"]["pairs"]
+    assert list(st.distinct) == g["stats"]["distinct"]
+    assert list(st.coherent) == g["stats"]["coherent"]
+    assert list(st.tests) == g["stats"]["tests"]
+    assert _model_digest(m) == g["model_sha256"]
+    A, N = gpu_scores(m, w.test_codes)
+    assert A[:16].tolist() == g["scores_head"]["A"] and N[:16].tolist() == g["scores_head"]["N"]
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(A, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(N, dtype="<i8").tobytes())
+    assert h.hexdigest() == g["scores_sha256"]
+
+
+def _check_structure(m, nbins):
+    """Properties of any fitted model: strictly ascending rows, S = f |b|^2,
+    f >= 1, one token per feature block."""
+    off = np.concatenate([[0], np.cumsum(nbins.astype(np.int64))])
+    for c in (0, 1):
+        w, f, S = m.export(c)
+        if w.shape[0] == 0:
+            continue
+        # strictly ascending in (w_0, ..., w_{K-1})
+        a, b = w[:-1], w[1:]
+        lt = np.zeros(a.shape[0], bool)
+        eq = np.ones(a.shape[0], bool)
+        for k in range(w.shape[1]):
+            lt |= eq & (a[:, k] < b[:, k])
+            eq &= a[:, k] == b[:, k]
+        assert lt.all(), "rows not strictly ascending"
+        bits = np.unpackbits(w.view(np.uint8), axis=1, bitorder="little")
+        pc = bits.sum(axis=1).astype(np.int64)
+        assert (f >= 1).all() and np.array_equal(S, f.astype(np.int64) * pc * pc)
+        # at most one token inside each feature's block
+        blk = np.add.reduceat(bits[:, : off[-1]], off[:-1], axis=1)
+        assert blk.max() <= 1
+
+
+def test_148k_workload_sampled():
+    w = synth.make_148k()
+    say("148k workload", w.codes.shape, w.test_codes.shape)
+    m = ig.fit(w.codes, w.labels, w.nbins)
+    _check_structure(m, w.nbins)
+    rng = np.random.default_rng(148)
+    for c in (0, 1):
+        words, f, S = m.export(c)
+        rows = {tuple(r): (int(ff), int(ss)) for r, ff, ss in zip(words.tolist(), f.tolist(), S.tolist())}
+        nc = int((w.labels == c).sum())
+        pi = rng.integers(0, nc, size=96).astype(np.uint64)
+        pj = rng.integers(0, nc, size=96).astype(np.uint64)
+        pj[:8] = pi[:8]   # record signatures too
+        ow, coh, of, _ = oracle.pair_facts(w.codes, w.labels, w.nbins, c, pi, pj)
+        for q in range(pi.size):
+            key = tuple(int(x) for x in ow[q])
+            if coh[q]:
+                assert key in rows, f"class {c}: coherent pair ({pi[q]},{pj[q]}) missing"
+                assert rows[key][0] == int(of[q])
+            else:
+                assert key not in rows, f"class {c}: incoherent pair ({pi[q]},{pj[q]}) present"
+    idx = rng.choice(w.test_codes.shape[0], size=12, replace=False)
+    flows = w.test_codes[idx]
+    A, N = gpu_scores(m, flows)
+    oA, oN = oracle.score_direct(w.codes, w.labels, w.nbins, flows)
+    assert np.array_equal(A, oA) and np.array_equal(N, oN)
