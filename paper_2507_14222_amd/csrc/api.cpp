@@ -158,6 +158,7 @@ struct Timer {
 
 struct Tuning {
     int cpl = 2, fpl = 2;
+    bool input_order = false;
 };
 
 static Tuning tuning_from(const ig_fit_opts *o) {
@@ -165,6 +166,7 @@ static Tuning tuning_from(const ig_fit_opts *o) {
     if (o) {
         if (o->filter_cpl == 1 || o->filter_cpl == 2) t.cpl = (int)o->filter_cpl;
         if (o->score_fpl == 1 || o->score_fpl == 2) t.fpl = (int)o->score_fpl;
+        t.input_order = o->scan_order == 1;
     }
     return t;
 }
@@ -299,9 +301,9 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     // survivors (coherent pair ids) per class, grown as chunks add candidates
     Scratch<uint32_t> surv[2];
     size_t surv_cap[2] = {0, 0};
-    Scratch<uint32_t> counters(4, s);   // nsurv[0], nsurv[1], queue, spare
+    Scratch<uint32_t> counters(8, s);   // nsurv[0], nsurv[1], queue, spare, next[0], next[1]
     Scratch<unsigned long long> tests(2, s);
-    launch_fill_u32(counters.get(), 0u, 4, s);
+    launch_fill_u32(counters.get(), 0u, 8, s);
     launch_fill_u64(reinterpret_cast<uint64_t *>(tests.get()), 0ull, 2, s);
     uint64_t distinct[2] = {0, 0};
 
@@ -341,10 +343,10 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         uint64_t *ks = where ? k1.get() : k0.get();
         uint32_t *vs = where ? v1.get() : v0.get();
         IG_HIP(hipEventRecord(e[2], s));
-        Scratch<uint32_t> flags(items, s), pos(items, s), segc(2, s), cand(items, s);
-        launch_fill_u32(segc.get(), 0u, 2, s);
+        Scratch<uint32_t> flags(items, s), pos(items, s), segc(2, s), cand(items, s), tot(1, s);
         launch_dedup_flags(ks, vs, items, rowsegs.get(), 1, flags.get(), segc.get(), s);
-        scan_exclusive_u32(flags.get(), pos.get(), items, nullptr, s);
+        scan_exclusive_u32(flags.get(), pos.get(), items, tot.get(), s);
+        launch_seg_counts(ks, items, pos.get(), tot.get(), 1, 2, segc.get(), s);
         launch_compact(flags.get(), pos.get(), vs, items, cand.get(), s);
         IG_HIP(hipEventRecord(e[3], s));
         std::vector<uint32_t> hc = host_read_u32(segc.get(), 2, s);
@@ -381,15 +383,30 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
             hs[c].n = cls[c].n;
             hs[c].n_o = cls[1 - c].n;
             hs[c].ncand = hc[c];
-            hs[c].pad = 0;
+            hs[c].n_o_pad = pad_rows(cls[1 - c].n);
+            hs[c].next = counters.get() + 4 + c;
             prefix[c + 1] = prefix[c] + (hc[c] + per_task - 1) / per_task;
         }
+        // refill kernel: waves start on the segments in proportion to their dense work
+        uint32_t wave_seg[3] = {0, 0, 0};
+        {
+            const double w0 = (double)hc[0] * std::max<uint32_t>(cls[1].n, 1);
+            const double w1 = (double)hc[1] * std::max<uint32_t>(cls[0].n, 1);
+            const uint32_t waves = grid * 4;
+            wave_seg[1] = (w0 + w1) > 0 ? (uint32_t)(waves * (w0 / (w0 + w1))) : 0;
+            wave_seg[2] = waves;
+        }
         Scratch<CohSeg> dsegs(2, s);
-        Scratch<uint32_t> dpre(3, s);
+        Scratch<uint32_t> dpre(3, s), dws(3, s);
         IG_HIP(hipMemcpyAsync(dsegs.get(), hs, sizeof(hs), hipMemcpyHostToDevice, s));
         IG_HIP(hipMemcpyAsync(dpre.get(), prefix, sizeof(prefix), hipMemcpyHostToDevice, s));
+        IG_HIP(hipMemcpyAsync(dws.get(), wave_seg, sizeof(wave_seg), hipMemcpyHostToDevice, s));
+        launch_fill_u32(counters.get() + 4, 0u, 2, s);
         IG_HIP(hipEventRecord(e[3], s));   // brackets the coherence launch alone
-        launch_coherence((int)KS, tu.cpl, dsegs.get(), 2, dpre.get(), counters.get() + 2, grid, s);
+        if (tu.input_order)
+            launch_coherence((int)KS, tu.cpl, dsegs.get(), 2, dpre.get(), counters.get() + 2, grid, s);
+        else
+            launch_coherence_refill((int)KS, tu.cpl, dsegs.get(), 2, dws.get(), grid, s);
         IG_HIP(hipEventRecord(e[4], s));
         IG_HIP(hipStreamSynchronize(s));   // host copies above must outlive their transfers
         float t34;
@@ -420,6 +437,20 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     m.stats.ms[2] = ms_sort;
     m.stats.ms[3] = ms_dedup;
     m.stats.ms[4] = ms_coh;
+}
+
+// Class rows with room for the refill kernel's padding: rows n..pad_rows(n)-1
+// are empty sets (X = 0, NX = all ones), which never contain a candidate.
+static void alloc_class_rows(ClassRows cls[2], const uint32_t *counts, uint32_t KS, hipStream_t s) {
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t n = counts[c];
+        const size_t rows = std::max<uint32_t>(pad_rows(n), 1);
+        cls[c].n = n;
+        cls[c].X.reset(rows * KS, s);
+        cls[c].NX.reset(rows * KS, s);
+        launch_fill_u64(cls[c].X.get() + (size_t)n * KS, 0ull, (rows - n) * KS, s);
+        launch_fill_u64(cls[c].NX.get() + (size_t)n * KS, ~0ull, (rows - n) * KS, s);
+    }
 }
 
 static DevModel *new_model() {
@@ -469,11 +500,7 @@ DevModel *fit_codes(const uint16_t *d_codes, const uint8_t *d_labels, uint32_t n
     IG_REQUIRE(!(h[0] & 2u), IG_E_INVAL, "a label is not 0 or 1");
     std::vector<uint32_t> hc = host_read_u32(counts.get(), 2, s);
     ClassRows cls[2];
-    for (int c = 0; c < 2; ++c) {
-        cls[c].n = hc[c];
-        cls[c].X.reset((size_t)(hc[c] ? hc[c] : 1) * KS, s);
-        cls[c].NX.reset((size_t)(hc[c] ? hc[c] : 1) * KS, s);
-    }
+    alloc_class_rows(cls, hc.data(), (uint32_t)KS, s);
     launch_pack_split(d_codes, d_labels, n, d, (uint32_t)KS, m->meta, pos.get(), cls[0].X.get(), cls[1].X.get(),
                       cls[0].NX.get(), cls[1].NX.get(), s);
     fit_from_rows(*m, cls, opts, s, tm);
@@ -501,11 +528,7 @@ DevModel *fit_packed(const uint64_t *d_words, const uint8_t *d_labels, uint32_t 
     IG_REQUIRE(!(h[0] & 2u), IG_E_INVAL, "a label is not 0 or 1");
     std::vector<uint32_t> hc = host_read_u32(counts.get(), 2, s);
     ClassRows cls[2];
-    for (int c = 0; c < 2; ++c) {
-        cls[c].n = hc[c];
-        cls[c].X.reset((size_t)(hc[c] ? hc[c] : 1) * KS, s);
-        cls[c].NX.reset((size_t)(hc[c] ? hc[c] : 1) * KS, s);
-    }
+    alloc_class_rows(cls, hc.data(), (uint32_t)KS, s);
     launch_split_packed(d_words, d_labels, n, K, (uint32_t)KS, pos.get(), cls[0].X.get(), cls[1].X.get(),
                         cls[0].NX.get(), cls[1].NX.get(), s);
     fit_from_rows(*m, cls, opts, s, tm);

@@ -88,7 +88,31 @@ __global__ void k_dedup_flags(const uint64_t *__restrict__ keys, const uint32_t 
         }
         flags[e] = rep;
     }
-    if (rep) atomicAdd(&seg_counts[seg], 1u);
+}
+
+// Distinct candidates per segment from the scan of the flags: the keys are
+// sorted with the segment id in their top bits, so segment s occupies one
+// contiguous range, found by binary search (no atomics).
+__global__ void k_seg_counts(const uint64_t *__restrict__ keys, size_t m, const uint32_t *__restrict__ pos,
+                             const uint32_t *__restrict__ total, int segbits, uint32_t nseg,
+                             uint32_t *__restrict__ seg_counts) {
+    uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    auto lower = [&](uint64_t v) -> size_t {   // first index with key >= v
+        size_t lo = 0, hi = m;
+        while (lo < hi) {
+            size_t mid = (lo + hi) >> 1;
+            if (keys[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const uint64_t a = (uint64_t)s << (64 - segbits);
+    const size_t ia = lower(a);
+    const size_t ib = (s + 1 < (1u << segbits)) ? lower((uint64_t)(s + 1) << (64 - segbits)) : m;
+    const uint32_t pa = ia < m ? pos[ia] : *total;
+    const uint32_t pb = ib < m ? pos[ib] : *total;
+    seg_counts[s] = pb - pa;
 }
 
 __global__ void k_compact(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
@@ -107,26 +131,42 @@ __global__ void k_gather_word(const uint64_t *__restrict__ X, uint32_t n, uint32
     keys[e] = X[(size_t)i * KS + k] & X[(size_t)j * KS + k];
 }
 
-// OR and AND of every word over the candidates ids[0..m): constant bits need no sort pass.
-__global__ void k_word_range(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS, uint32_t K,
-                             const uint32_t *__restrict__ ids, size_t m, unsigned long long *__restrict__ orv,
-                             unsigned long long *__restrict__ andv) {
-    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t i = 0, j = 0;
-    bool valid = e < m;
-    if (valid) decode_pair(ids[e], n, i, j);
-    for (uint32_t k = 0; k < K; ++k) {
-        uint64_t w = valid ? (X[(size_t)i * KS + k] & X[(size_t)j * KS + k]) : 0ull;
-        uint64_t wa = valid ? w : ~0ull;
-        // wave-level reduction first
-        for (int o = 32; o > 0; o >>= 1) {
-            w |= __shfl_xor(w, o, 64);
-            wa &= __shfl_xor(wa, o, 64);
+// OR and AND of every word over the candidates ids[0..m): constant bits need no
+// sort pass.  A bounded grid strides over the ids; each workgroup reduces in
+// registers and LDS and adds one atomic per word.
+__global__ __launch_bounds__(256) void k_word_range(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS, uint32_t K,
+                                                   const uint32_t *__restrict__ ids, size_t m,
+                                                   unsigned long long *__restrict__ orv,
+                                                   unsigned long long *__restrict__ andv) {
+    __shared__ unsigned long long sor[4][64], sand[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t k0 = 0; k0 < K; k0 += 64) {
+        const uint32_t kk = K - k0 < 64 ? K - k0 : 64;
+        // per-thread partials for words k0 + (0..kk), one word at a time to bound registers
+        for (uint32_t k = 0; k < kk; ++k) {
+            uint64_t o = 0, a = ~0ull;
+            for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+                uint32_t i, j;
+                decode_pair(ids[e], n, i, j);
+                uint64_t w = X[(size_t)i * KS + k0 + k] & X[(size_t)j * KS + k0 + k];
+                o |= w;
+                a &= w;
+            }
+            for (int sh = 32; sh > 0; sh >>= 1) {
+                o |= __shfl_xor(o, sh, 64);
+                a &= __shfl_xor(a, sh, 64);
+            }
+            if (lane == 0) { sor[wave][k] = o; sand[wave][k] = a; }
         }
-        if ((threadIdx.x & 63) == 0) {
-            atomicOr(&orv[k], (unsigned long long)w);
-            atomicAnd(&andv[k], (unsigned long long)wa);
+        __syncthreads();
+        if (threadIdx.x < kk) {
+            const int k = threadIdx.x;
+            unsigned long long o = sor[0][k] | sor[1][k] | sor[2][k] | sor[3][k];
+            unsigned long long a = sand[0][k] & sand[1][k] & sand[2][k] & sand[3][k];
+            atomicOr(&orv[k0 + k], o);
+            atomicAnd(&andv[k0 + k], a);
         }
+        __syncthreads();
     }
 }
 
@@ -215,6 +255,18 @@ void launch_dedup_flags(const uint64_t *keys, const uint32_t *vals, size_t m, co
     IG_HIP(hipGetLastError());
 }
 
+void launch_seg_counts(const uint64_t *keys, size_t m, const uint32_t *pos, const uint32_t *total, int segbits,
+                       uint32_t nseg, uint32_t *seg_counts, hipStream_t s) {
+    if (!nseg) return;
+    if (!m) {
+        launch_fill_u32(seg_counts, 0u, nseg, s);
+        return;
+    }
+    hipLaunchKernelGGL(k_seg_counts, dim3((nseg + 63) / 64), dim3(64), 0, s, keys, m, pos, total, segbits, nseg,
+                       seg_counts);
+    IG_HIP(hipGetLastError());
+}
+
 size_t rows_of_seg_size() { return sizeof(RowsOfSeg); }
 void fill_rows_of_seg(void *dst, const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K) {
     RowsOfSeg r{X, n, KS, K};
@@ -238,7 +290,9 @@ void launch_gather_word(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t k, 
 void launch_word_range(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, const uint32_t *ids, size_t m,
                        unsigned long long *orv, unsigned long long *andv, hipStream_t s) {
     if (!m) return;
-    hipLaunchKernelGGL(k_word_range, blocks_for(m), dim3(256), 0, s, X, n, KS, K, ids, m, orv, andv);
+    unsigned g = (unsigned)((m + 255) / 256);
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_word_range, dim3(g), dim3(256), 0, s, X, n, KS, K, ids, m, orv, andv);
     IG_HIP(hipGetLastError());
 }
 

@@ -21,6 +21,10 @@ namespace ig {
 
 typedef const __attribute__((address_space(4))) uint32_t *cptr32;   // scalar-loadable view
 typedef const __attribute__((address_space(4))) int64_t *cptr64;
+typedef const __attribute__((address_space(1))) uint32_t *gptr32;    // global (not flat) loads
+
+__device__ __forceinline__ gptr32 global_rows(const uint64_t *p) { return (gptr32)(const void *)p; }
+__device__ __forceinline__ uint32_t from_lane0(uint32_t v) { return __builtin_amdgcn_readlane(v, 0); }
 
 // OR over words of (r AND b) with r uniform in SGPRs and b per lane, as one
 // v_and_or_b32 per 32-bit word.  Written as inline-asm blocks of 8/4/2 words:
@@ -103,10 +107,12 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
     constexpr int W = 2 * KS;
     const int lane = threadIdx.x & 63;
     const uint32_t ntasks = uniform(task_prefix[nseg]);
+    unsigned long long *tests_at = nullptr;   // sum of t(b) kept per wave, flushed per segment
+    uint64_t tests_acc = 0;
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(queue, 1u);
-        t = uniform(__shfl(t, 0, 64));
+        t = from_lane0(t);
         if (t >= ntasks) break;
         uint32_t sg = 0;
         while (sg + 1 < nseg && task_prefix[sg + 1] <= t) ++sg;
@@ -122,11 +128,11 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
         for (int c = 0; c < CPL; ++c) {
             uint32_t idx = base + c * 64 + lane;
             bool act = idx < g.ncand;
-            pid[c] = act ? g.cand[idx] : 0u;
+            pid[c] = act ? ((const __attribute__((address_space(1))) uint32_t *)(const void *)g.cand)[idx] : 0u;
             uint32_t i = 0, j = 0;
             if (act) decode_pair(pid[c], g.n, i, j);
-            const uint32_t *ra = reinterpret_cast<const uint32_t *>(g.X + (size_t)i * KS);
-            const uint32_t *rb = reinterpret_cast<const uint32_t *>(g.X + (size_t)j * KS);
+            gptr32 ra = global_rows(g.X + (size_t)i * KS);
+            gptr32 rb = global_rows(g.X + (size_t)j * KS);
 #pragma unroll
             for (int k = 0; k < W; ++k) b[c][k] = ra[k] & rb[k];
             cov[c] = ~__ballot(act);   // lanes without a candidate count as done
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
             uint32_t cnt = (uint32_t)__popcll(km);
             uint32_t at = 0;
             if (lane == 0 && cnt) at = atomicAdd(g.nsurv, cnt);
-            at = __shfl(at, 0, 64);
+            at = from_lane0(at);
             if (keep) {
                 uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
                 g.surv[at + (uint32_t)__popcll(km & lt)] = pid[c];
@@ -170,8 +176,163 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
             if (act) tsum += tpos[c] ? tpos[c] : n_o;
         }
         for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
-        if (lane == 0 && tsum) atomicAdd(g.tests, (unsigned long long)tsum);
+        if (g.tests != tests_at) {
+            if (lane == 0 && tests_acc) atomicAdd(tests_at, (unsigned long long)tests_acc);
+            tests_at = g.tests;
+            tests_acc = 0;
+        }
+        tests_acc += tsum;
     }
+    if (lane == 0 && tests_acc) atomicAdd(tests_at, (unsigned long long)tests_acc);
+}
+
+// ----------------------------------------------------- coherence, refill ----
+template <int KS, int CPL>
+__global__ __launch_bounds__(256) void k_coherence_refill(const CohSeg *__restrict__ segs, uint32_t nseg,
+                                                         const uint32_t *__restrict__ wave_seg) {
+    constexpr int W = 2 * KS;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint32_t gw = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    uint32_t sg = 0;
+    while (sg + 1 < nseg && wave_seg[sg + 1] <= gw) ++sg;
+    sg = uniform(sg);
+    unsigned long long *tests_at = nullptr;
+    uint64_t tests_acc = 0;
+    for (uint32_t visit = 0; visit < nseg; ++visit, sg = (sg + 1 == nseg) ? 0u : sg + 1) {
+        const CohSeg g = segs[sg];
+        if (g.ncand == 0) continue;
+        if (g.tests != tests_at) {
+            if (lane == 0 && tests_acc) atomicAdd(tests_at, (unsigned long long)tests_acc);
+            tests_at = g.tests;
+            tests_acc = 0;
+        }
+        const uint32_t nchunks = g.n_o_pad / COH_CHUNK;
+        uint64_t tsum = 0;   // this lane's t(b) total for the segment
+        uint32_t b[CPL][W];
+        uint32_t pid[CPL], start[CPL], left[CPL], tfirst[CPL];
+        uint64_t live[CPL], cov[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            live[c] = 0;
+            cov[c] = 0;
+            pid[c] = start[c] = left[c] = tfirst[c] = 0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) b[c][k] = 0;
+        }
+        // wave-private reservoir [res_lo, res_hi) of candidate indices, topped up
+        // from the segment queue RESERVE at a time (one atomic per block)
+        constexpr uint32_t RESERVE = 128;
+        uint32_t res_lo = 0, res_hi = 0;
+        bool queue_done = false, exhausted = false;
+        uint32_t r0 = 0;
+        for (;;) {
+            // give every empty slot the next candidate of the segment
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const uint64_t dead = ~live[c];
+                if (dead && !exhausted) {
+                    const uint32_t nd = (uint32_t)__popcll(dead);
+                    const uint32_t rank = (uint32_t)__popcll(dead & lt);
+                    const uint32_t avail = res_hi - res_lo;
+                    uint32_t nb_lo = 0, nb_hi = 0;
+                    if (avail < nd && !queue_done) {
+                        uint32_t base = 0;
+                        if (lane == 0) base = atomicAdd(g.next, RESERVE);
+                        base = from_lane0(base);
+                        nb_lo = base < g.ncand ? base : g.ncand;
+                        nb_hi = base + RESERVE < g.ncand ? base + RESERVE : g.ncand;
+                        if (base + RESERVE >= g.ncand) queue_done = true;
+                    }
+                    uint32_t idx;
+                    bool ok;
+                    if (rank < avail) {
+                        idx = res_lo + rank;
+                        ok = true;
+                    } else {
+                        idx = nb_lo + (rank - avail);
+                        ok = idx < nb_hi;
+                    }
+                    const bool got = ((dead >> lane) & 1ull) && ok;
+                    const uint32_t take_old = avail < nd ? avail : nd;
+                    if (nb_hi > nb_lo) {
+                        const uint32_t want = nd - take_old, have = nb_hi - nb_lo;
+                        res_lo = nb_lo + (want < have ? want : have);
+                        res_hi = nb_hi;
+                    } else {
+                        res_lo += take_old;
+                    }
+                    exhausted = queue_done && res_lo >= res_hi;
+                    if (got) {
+                        pid[c] = ((const __attribute__((address_space(1))) uint32_t *)(const void *)g.cand)[idx];
+                        uint32_t i, j;
+                        decode_pair(pid[c], g.n, i, j);
+                        gptr32 ra = global_rows(g.X + (size_t)i * KS);
+                        gptr32 rb = global_rows(g.X + (size_t)j * KS);
+#pragma unroll
+                        for (int k = 0; k < W; ++k) b[c][k] = ra[k] & rb[k];
+                        start[c] = r0;
+                        left[c] = nchunks;
+                    }
+                    const uint64_t gm = __ballot(got);
+                    live[c] |= gm;
+                    cov[c] &= ~gm;
+                }
+            }
+            uint64_t any = 0;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) any |= live[c];
+            if (!any) break;   // segment drained
+            if (nchunks) {
+                r0 = uniform(r0);
+                cptr32 R = (cptr32)(const void *)g.NXo + (size_t)r0 * W;
+                for (uint32_t rr = 0; rr < COH_CHUNK; ++rr) {
+                    cptr32 row = R + (size_t)rr * W;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const uint32_t acc = masked_or<W>(row, b[c]);
+                        const uint64_t nw = __ballot(acc == 0u) & live[c] & ~cov[c];
+                        if (nw) {
+                            if ((nw >> lane) & 1ull) tfirst[c] = r0 + rr;
+                            cov[c] |= nw;
+                        }
+                    }
+                }
+                r0 += COH_CHUNK;
+                if (r0 == g.n_o_pad) r0 = 0;
+            }
+            // retire slots that are covered or have seen every record
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const bool me_live = (live[c] >> lane) & 1ull;
+                if (me_live && nchunks) left[c] -= 1;
+                const uint64_t fin = live[c] & (cov[c] | __ballot(me_live && left[c] == 0));
+                if (fin) {
+                    const bool me = (fin >> lane) & 1ull;
+                    const bool covered = (cov[c] >> lane) & 1ull;
+                    const bool keep = me && !covered;
+                    if (me)
+                        tsum += keep ? g.n_o
+                                     : (tfirst[c] >= start[c] ? tfirst[c] - start[c] + 1
+                                                              : g.n_o - start[c] + tfirst[c] + 1);
+                    const uint64_t km = __ballot(keep);
+                    if (km) {
+                        uint32_t at = 0;
+                        if (lane == 0) at = atomicAdd(g.nsurv, (uint32_t)__popcll(km));
+                        at = from_lane0(at);
+                        if (keep) g.surv[at + (uint32_t)__popcll(km & lt)] = pid[c];
+                    }
+                    live[c] &= ~fin;
+                    cov[c] &= ~fin;
+                }
+            }
+        }
+        // per-lane counts of this segment, reduced once
+        uint64_t ts = tsum;
+        for (int o = 32; o > 0; o >>= 1) ts += __shfl_xor(ts, o, 64);
+        tests_acc += ts;
+    }
+    if (lane == 0 && tests_acc) atomicAdd(tests_at, (unsigned long long)tests_acc);
 }
 
 // -------------------------------------------------------------- support ----
@@ -330,19 +491,30 @@ __global__ __launch_bounds__(256) void k_score(ScoreArgs a) {
     }
 }
 
-// largest S and total of S (for the int64 overflow bound of Eq. 4 sums)
-__global__ void k_maxsum(const int64_t *__restrict__ S, size_t m, unsigned long long *__restrict__ ms) {
-    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long v = e < m ? (unsigned long long)S[e] : 0ull;
-    unsigned long long mx = v, sm = v;
+// largest S and total of S (for the int64 overflow bound of Eq. 4 sums); a
+// bounded grid strides over S and adds one atomic pair per workgroup
+__global__ __launch_bounds__(256) void k_maxsum(const int64_t *__restrict__ S, size_t m,
+                                               unsigned long long *__restrict__ ms) {
+    __shared__ unsigned long long smx[4], ssm[4];
+    unsigned long long mx = 0, sm = 0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+        unsigned long long v = (unsigned long long)S[e];
+        mx = v > mx ? v : mx;
+        sm += v;
+    }
     for (int o = 32; o > 0; o >>= 1) {
         unsigned long long u = __shfl_xor(mx, o, 64);
         mx = u > mx ? u : mx;
         sm += __shfl_xor(sm, o, 64);
     }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(&ms[0], mx);
-        atomicAdd(&ms[1], sm);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { smx[wave] = mx; ssm[wave] = sm; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = smx[0], b = ssm[0];
+        for (int w = 1; w < 4; ++w) { a = smx[w] > a ? smx[w] : a; b += ssm[w]; }
+        atomicMax(&ms[0], a);
+        atomicAdd(&ms[1], b);
     }
 }
 
@@ -391,6 +563,23 @@ void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, co
         default: throw Error(IG_E_UNSUPPORTED, "unsupported word count");
     }
 #undef IG_COH
+    IG_HIP(hipGetLastError());
+}
+
+void launch_coherence_refill(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, const uint32_t *wave_seg_dev,
+                             uint32_t grid, hipStream_t s) {
+#define IG_COHR(V)                                                                                             \
+    case V:                                                                                                    \
+        if (cpl == 2 && V <= 16)                                                                               \
+            hipLaunchKernelGGL((k_coherence_refill<V, 2>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, wave_seg_dev); \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_coherence_refill<V, 1>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, wave_seg_dev); \
+        break;
+    switch (KS) {
+        IG_FOR_EACH_KS(IG_COHR)
+        default: throw Error(IG_E_UNSUPPORTED, "unsupported word count");
+    }
+#undef IG_COHR
     IG_HIP(hipGetLastError());
 }
 
@@ -443,7 +632,7 @@ void launch_score(const ScoreModel &m, const uint16_t *codes, const uint64_t *wo
     const int f = (fpl == 2 && KS <= 16) ? 2 : 1;
     const uint32_t fblocks = (n_flows + 256 * f - 1) / (256 * f);
     // enough workgroups to fill the chip: split the pattern range into chunks
-    const uint64_t target_blocks = 256ull * 8ull;
+    const uint64_t target_blocks = 256ull * 32ull;   // ~8 waves per SIMD
     uint64_t npmax = m.np[0] > m.np[1] ? m.np[0] : m.np[1];
     if (npmax == 0) return;
     uint64_t ychunks = (target_blocks + 2ull * fblocks - 1) / (2ull * fblocks);
@@ -478,7 +667,9 @@ void launch_score(const ScoreModel &m, const uint16_t *codes, const uint64_t *wo
 void launch_reduce_maxsum(const int64_t *S, size_t m, unsigned long long *d_max_sum, hipStream_t s) {
     launch_fill_u64(reinterpret_cast<uint64_t *>(d_max_sum), 0ull, 2, s);
     if (!m) return;
-    hipLaunchKernelGGL(k_maxsum, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, S, m, d_max_sum);
+    unsigned g = (unsigned)((m + 255) / 256);
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_maxsum, dim3(g), dim3(256), 0, s, S, m, d_max_sum);
     IG_HIP(hipGetLastError());
 }
 
