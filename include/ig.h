@@ -68,14 +68,7 @@ typedef struct {
                                    (0 = tuned default; 1 or 2)                        */
     uint32_t score_fpl;         /* flows per lane of the scoring kernel (0, 1 or 2)  */
     uint32_t block;             /* reserved (workgroups are 256 threads)              */
-    uint32_t scan_order;        /* coherence scan of the other class (Eq. 3):
-                                   0 = each candidate scans the other class cyclically
-                                       from where its lane slot joined, and finished
-                                       slots are refilled (default, fastest);
-                                   1 = every candidate scans in input order, so that
-                                       ig_stats.tests is the sum of t(b) in input order.
-                                   Both give the same patterns.                       */
-    uint32_t reserved[4];
+    uint32_t reserved[5];
 } ig_fit_opts;
 
 /* Counters and timings of a fit (Section 3.3 stages). */
@@ -87,7 +80,7 @@ typedef struct {
     uint64_t tests[2];       /* sum over distinct candidates of t(b): the records of
                                 the other class examined up to and including the
                                 first that contains b (all of them when none does),
-                                in the scan order of ig_fit_opts.scan_order          */
+                                scanning the other class in input order              */
     uint64_t support_tests[2]; /* |P^c| * n_c subset tests of Eq. 2                  */
     uint32_t chunks[2];      /* pair-space chunks used for the class                 */
     float ms[8];             /* device time per stage: 0 pack, 1 pairs+hash, 2 sort,

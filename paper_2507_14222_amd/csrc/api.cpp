@@ -66,7 +66,6 @@ struct DevModel {
     uint32_t *meta = nullptr;    // off[d] | flo[KS] | fhi[KS]
     uint16_t *nbins = nullptr;
     ig_stats stats{};
-    uint32_t stats_coherence_launches = 0;
 
     ~DevModel() {
         for (int c = 0; c < 2; ++c) {
@@ -157,8 +156,7 @@ struct Timer {
 };
 
 struct Tuning {
-    int cpl = 2, fpl = 2;
-    bool input_order = false;
+    int cpl = 1, fpl = 2;   // coherence: one candidate per lane measured fastest
 };
 
 static Tuning tuning_from(const ig_fit_opts *o) {
@@ -166,7 +164,6 @@ static Tuning tuning_from(const ig_fit_opts *o) {
     if (o) {
         if (o->filter_cpl == 1 || o->filter_cpl == 2) t.cpl = (int)o->filter_cpl;
         if (o->score_fpl == 1 || o->score_fpl == 2) t.fpl = (int)o->score_fpl;
-        t.input_order = o->scan_order == 1;
     }
     return t;
 }
@@ -237,7 +234,7 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, const Clas
         if (Wd && m.W[c] != Wd) (void)hipFree(Wd);
         throw;
     }
-    launch_support((int)KS, tu.cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
+    launch_support((int)KS, 2, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
 }
 
 static void finish_weights(DevModel &m, hipStream_t s) {
@@ -252,6 +249,14 @@ static void finish_weights(DevModel &m, hipStream_t s) {
         IG_REQUIRE(h[2 * c + 1] <= (unsigned long long)INT64_MAX, IG_E_OVERFLOW,
                    "sum of pattern weights exceeds int64");
     }
+}
+
+// Ends of the coherence phases over the other class's records.  One phase (the
+// whole class) measured fastest: splitting the scan lets covered candidates stop
+// earlier, but each extra phase reloads the survivors and appends them through a
+// shared counter, which cost more than the idle lanes it saved.
+static std::vector<uint32_t> coherence_phases(uint32_t max_other) {
+    return std::vector<uint32_t>{std::max<uint32_t>(max_other, 1)};
 }
 
 static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts, hipStream_t s, Timer &tm) {
@@ -301,9 +306,9 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     // survivors (coherent pair ids) per class, grown as chunks add candidates
     Scratch<uint32_t> surv[2];
     size_t surv_cap[2] = {0, 0};
-    Scratch<uint32_t> counters(8, s);   // nsurv[0], nsurv[1], queue, spare, next[0], next[1]
+    Scratch<uint32_t> counters(4, s);   // nsurv[0], nsurv[1], queue, spare
     Scratch<unsigned long long> tests(2, s);
-    launch_fill_u32(counters.get(), 0u, 8, s);
+    launch_fill_u32(counters.get(), 0u, 4, s);
     launch_fill_u64(reinterpret_cast<uint64_t *>(tests.get()), 0ull, 2, s);
     uint64_t distinct[2] = {0, 0};
 
@@ -370,49 +375,64 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
                 surv_cap[c] = cap;
             }
         }
-        CohSeg hs[2];
-        uint32_t prefix[3] = {0, 0, 0};
-        uint32_t per_task = 64u * (uint32_t)((tu.cpl == 2 && KS <= 16) ? 2 : 1);
-        for (int c = 0; c < 2; ++c) {
-            hs[c].X = cls[c].X.get();
-            hs[c].NXo = cls[1 - c].NX.get();
-            hs[c].cand = cand.get() + (c == 0 ? 0 : hc[0]);
-            hs[c].surv = surv[c].get();
-            hs[c].nsurv = counters.get() + c;
-            hs[c].tests = tests.get() + c;
-            hs[c].n = cls[c].n;
-            hs[c].n_o = cls[1 - c].n;
-            hs[c].ncand = hc[c];
-            hs[c].n_o_pad = pad_rows(cls[1 - c].n);
-            hs[c].next = counters.get() + 4 + c;
-            prefix[c + 1] = prefix[c] + (hc[c] + per_task - 1) / per_task;
-        }
-        // refill kernel: waves start on the segments in proportion to their dense work
-        uint32_t wave_seg[3] = {0, 0, 0};
+        // coherence in phases over the other class's records (input order); the
+        // uncovered ids ping-pong between the de-duplication output and `alt`
+        const std::vector<uint32_t> bounds = coherence_phases(std::max(cls[0].n, cls[1].n));
+        Scratch<uint32_t> alt(std::max<size_t>((size_t)hc[0] + hc[1], 1), s);
+        Scratch<uint32_t> pcount(2 * 2 * bounds.size(), s);   // per phase, per class: output counter
+        launch_fill_u32(pcount.get(), 0u, 2 * 2 * bounds.size(), s);
+        std::vector<CohSeg> hs;
+        std::vector<uint32_t> seg_first, seg_count;   // slice of hs used by each phase
         {
-            const double w0 = (double)hc[0] * std::max<uint32_t>(cls[1].n, 1);
-            const double w1 = (double)hc[1] * std::max<uint32_t>(cls[0].n, 1);
-            const uint32_t waves = grid * 4;
-            wave_seg[1] = (w0 + w1) > 0 ? (uint32_t)(waves * (w0 / (w0 + w1))) : 0;
-            wave_seg[2] = waves;
+            uint32_t *cur[2] = {cand.get(), cand.get() + hc[0]};
+            uint32_t *nxt[2] = {alt.get(), alt.get() + hc[0]};
+            const uint32_t *curcnt[2] = {segc.get(), segc.get() + 1};
+            uint32_t r_begin = 0;
+            for (size_t p = 0; p < bounds.size(); ++p) {
+                const uint32_t r_end = bounds[p];
+                seg_first.push_back((uint32_t)hs.size());
+                for (int c = 0; c < 2; ++c) {
+                    const uint32_t n_o = cls[1 - c].n;
+                    if (r_begin >= n_o && !(r_begin == 0 && n_o == 0)) continue;   // finished earlier
+                    const bool last = r_end >= n_o;
+                    CohSeg g{};
+                    g.X = cls[c].X.get();
+                    g.NXo = cls[1 - c].NX.get();
+                    g.cand = cur[c];
+                    g.ncand = curcnt[c];
+                    g.out = last ? surv[c].get() : nxt[c];
+                    g.nout = last ? counters.get() + c : pcount.get() + 4 * p + c;
+                    g.tests = tests.get() + c;
+                    g.n = cls[c].n;
+                    g.n_o = n_o;
+                    hs.push_back(g);
+                    if (!last) {
+                        curcnt[c] = pcount.get() + 4 * p + c;
+                        std::swap(cur[c], nxt[c]);
+                    }
+                }
+                seg_count.push_back((uint32_t)hs.size() - seg_first.back());
+                r_begin = r_end;
+            }
         }
-        Scratch<CohSeg> dsegs(2, s);
-        Scratch<uint32_t> dpre(3, s), dws(3, s);
-        IG_HIP(hipMemcpyAsync(dsegs.get(), hs, sizeof(hs), hipMemcpyHostToDevice, s));
-        IG_HIP(hipMemcpyAsync(dpre.get(), prefix, sizeof(prefix), hipMemcpyHostToDevice, s));
-        IG_HIP(hipMemcpyAsync(dws.get(), wave_seg, sizeof(wave_seg), hipMemcpyHostToDevice, s));
-        launch_fill_u32(counters.get() + 4, 0u, 2, s);
-        IG_HIP(hipEventRecord(e[3], s));   // brackets the coherence launch alone
-        if (tu.input_order)
-            launch_coherence((int)KS, tu.cpl, dsegs.get(), 2, dpre.get(), counters.get() + 2, grid, s);
-        else
-            launch_coherence_refill((int)KS, tu.cpl, dsegs.get(), 2, dws.get(), grid, s);
+        Scratch<CohSeg> dsegs(std::max<size_t>(hs.size(), 1), s);
+        if (!hs.empty())
+            IG_HIP(hipMemcpyAsync(dsegs.get(), hs.data(), hs.size() * sizeof(CohSeg), hipMemcpyHostToDevice, s));
+        IG_HIP(hipEventRecord(e[3], s));   // brackets the coherence phases
+        {
+            uint32_t r_begin = 0;
+            for (size_t p = 0; p < bounds.size(); ++p) {
+                if (seg_count[p])
+                    launch_coherence((int)KS, tu.cpl, dsegs.get() + seg_first[p], seg_count[p], r_begin, bounds[p],
+                                     counters.get() + 2, grid, s);
+                r_begin = bounds[p];
+            }
+        }
         IG_HIP(hipEventRecord(e[4], s));
         IG_HIP(hipStreamSynchronize(s));   // host copies above must outlive their transfers
         float t34;
         IG_HIP(hipEventElapsedTime(&t34, e[3], e[4]));
         ms_coh += t34;
-        m.stats_coherence_launches++;
     }
     tm.mark(4);
     std::vector<uint32_t> hn = host_read_u32(counters.get(), 2, s);
@@ -439,17 +459,12 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     m.stats.ms[4] = ms_coh;
 }
 
-// Class rows with room for the refill kernel's padding: rows n..pad_rows(n)-1
-// are empty sets (X = 0, NX = all ones), which never contain a candidate.
 static void alloc_class_rows(ClassRows cls[2], const uint32_t *counts, uint32_t KS, hipStream_t s) {
     for (int c = 0; c < 2; ++c) {
-        const uint32_t n = counts[c];
-        const size_t rows = std::max<uint32_t>(pad_rows(n), 1);
-        cls[c].n = n;
+        const size_t rows = std::max<uint32_t>(counts[c], 1);
+        cls[c].n = counts[c];
         cls[c].X.reset(rows * KS, s);
         cls[c].NX.reset(rows * KS, s);
-        launch_fill_u64(cls[c].X.get() + (size_t)n * KS, 0ull, (rows - n) * KS, s);
-        launch_fill_u64(cls[c].NX.get() + (size_t)n * KS, ~0ull, (rows - n) * KS, s);
     }
 }
 

@@ -49,33 +49,21 @@ void launch_adjacent_equal(const uint64_t *W, size_t m, uint32_t KS, uint32_t *d
 void launch_weights(const uint64_t *W, const uint32_t *f, size_t m, uint32_t KS, int64_t *S, hipStream_t s);
 
 // subset.hip -- the subset-test kernels (Eq. 6 inside Eq. 3, Eq. 2 and Eq. 4)
-struct CohSeg {                 // one (problem, class) for the coherence kernel
+struct CohSeg {                 // one (problem, class) for one coherence phase
     const uint64_t *X;          // class rows [n][KS]
-    const uint64_t *NXo;        // complemented other-class rows [n_o_pad][KS]; rows >= n_o are all ones
-    const uint32_t *cand;       // distinct candidate pair ids
-    uint32_t *surv;             // coherent pair ids out (appended)
-    uint32_t *nsurv;            // counter of surv
+    const uint64_t *NXo;        // complemented other-class rows [n_o][KS]
+    const uint32_t *cand;       // input: candidate pair ids still uncovered
+    const uint32_t *ncand;      // device count of cand
+    uint32_t *out;              // output: ids uncovered by this phase (appended)
+    uint32_t *nout;             // device counter of out
     unsigned long long *tests;  // sum of t(b)
-    uint32_t *next;             // candidate queue of the segment (refill kernel; zeroed before launch)
-    uint32_t n, n_o, ncand, n_o_pad;
+    uint32_t n, n_o;
 };
-#ifndef IG_COH_CHUNK
-#define IG_COH_CHUNK 64
-#endif
-constexpr uint32_t COH_CHUNK = IG_COH_CHUNK;   // records per refill step; other-class rows are padded to a multiple
-inline uint32_t pad_rows(uint32_t n) { return (n + COH_CHUNK - 1) / COH_CHUNK * COH_CHUNK; }
-
-// Coherence filter over all segments (same KS), other class scanned in input
-// order for every candidate; tasks of 64*cpl candidates are pulled from a queue
-// counter (zeroed by the launcher).
-void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, const uint32_t *task_prefix_dev,
+// One phase of the coherence filter (Eq. 3) over all segments (same KS): other-
+// class records [r_begin, r_end) in input order.  Tasks of 64*cpl candidates are
+// pulled from `queue` (zeroed by the launcher).
+void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, uint32_t r_begin, uint32_t r_end,
                       uint32_t *queue, uint32_t grid, hipStream_t s);
-// Coherence filter with lane refill: each lane slot scans the other class
-// cyclically in chunks of COH_CHUNK rows from the chunk where it joined; finished
-// slots take the next candidate of the segment.  wave_seg[s] = first wave that
-// starts on segment s (waves move on to the next segment when theirs is drained).
-void launch_coherence_refill(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, const uint32_t *wave_seg_dev,
-                             uint32_t grid, hipStream_t s);
 uint32_t coherence_grid(int KS, int cpl);
 
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented

@@ -100,13 +100,24 @@ __device__ __forceinline__ void load_pair_row(const uint64_t *__restrict__ X, ui
 }
 
 // ------------------------------------------------------------ coherence ----
+// One phase of the coherence filter: the candidates of each segment's input list
+// are tested against other-class records [r_begin, r_end) in input order.  A
+// candidate covered at record r is dropped and adds t(b) = r + 1 to the segment's
+// test count; an uncovered one is appended to the output list -- the next
+// phase's input, or the coherent set when the phase reaches the last record.
+// Phases keep lanes busy: a wave stops when its candidates are covered or the
+// phase ends, so a covered candidate idles at most until the end of its phase.
 template <int KS, int CPL>
-__global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ segs, uint32_t nseg,
-                                                  const uint32_t *__restrict__ task_prefix,
-                                                  uint32_t *__restrict__ queue) {
+__global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ segs, uint32_t nseg, uint32_t r_begin,
+                                                  uint32_t r_end, uint32_t *__restrict__ queue) {
     constexpr int W = 2 * KS;
+    constexpr uint32_t PER_TASK = 64u * CPL;
     const int lane = threadIdx.x & 63;
-    const uint32_t ntasks = uniform(task_prefix[nseg]);
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    // tasks of every segment, from the input counts left on the device by the previous step
+    uint32_t ntasks = 0;
+    for (uint32_t sg = 0; sg < nseg; ++sg) ntasks += (uniform(*segs[sg].ncand) + PER_TASK - 1) / PER_TASK;
+    ntasks = uniform(ntasks);
     unsigned long long *tests_at = nullptr;   // sum of t(b) kept per wave, flushed per segment
     uint64_t tests_acc = 0;
     for (;;) {
@@ -114,11 +125,20 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
         if (lane == 0) t = atomicAdd(queue, 1u);
         t = from_lane0(t);
         if (t >= ntasks) break;
-        uint32_t sg = 0;
-        while (sg + 1 < nseg && task_prefix[sg + 1] <= t) ++sg;
+        uint32_t sg = 0, first = 0, ncand = 0;
+        for (;; ++sg) {
+            ncand = uniform(*segs[sg].ncand);
+            const uint32_t nt = (ncand + PER_TASK - 1) / PER_TASK;
+            if (t < first + nt) break;
+            first += nt;
+        }
         sg = uniform(sg);
         const CohSeg g = segs[sg];
-        const uint32_t base = (t - uniform(task_prefix[sg])) * (64u * CPL);
+        const uint32_t base = (t - first) * PER_TASK;
+        const uint32_t n_o = g.n_o;
+        const uint32_t rb = r_begin < n_o ? r_begin : n_o;
+        const uint32_t re = r_end < n_o ? r_end : n_o;
+        const bool last = r_end >= n_o;
 
         uint32_t b[CPL][W];
         uint32_t pid[CPL];
@@ -126,29 +146,26 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
         uint32_t tpos[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            uint32_t idx = base + c * 64 + lane;
-            bool act = idx < g.ncand;
+            const uint32_t idx = base + c * 64 + lane;
+            const bool act = idx < ncand;
             pid[c] = act ? ((const __attribute__((address_space(1))) uint32_t *)(const void *)g.cand)[idx] : 0u;
             uint32_t i = 0, j = 0;
             if (act) decode_pair(pid[c], g.n, i, j);
             gptr32 ra = global_rows(g.X + (size_t)i * KS);
-            gptr32 rb = global_rows(g.X + (size_t)j * KS);
+            gptr32 rb2 = global_rows(g.X + (size_t)j * KS);
 #pragma unroll
-            for (int k = 0; k < W; ++k) b[c][k] = ra[k] & rb[k];
+            for (int k = 0; k < W; ++k) b[c][k] = ra[k] & rb2[k];
             cov[c] = ~__ballot(act);   // lanes without a candidate count as done
             tpos[c] = 0;
         }
         cptr32 R = (cptr32)(const void *)g.NXo;
-        const uint32_t n_o = g.n_o;
-        uint64_t done = 0;
-        for (uint32_t r = 0; r < n_o; ++r) {
+        for (uint32_t r = rb; r < re; ++r) {
             cptr32 rr = R + (size_t)r * W;
-            done = ~0ull;
+            uint64_t done = ~0ull;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                uint32_t acc = masked_or<W>(rr, b[c]);
-                uint64_t m = __ballot(acc == 0u);
-                uint64_t nw = m & ~cov[c];
+                const uint32_t acc = masked_or<W>(rr, b[c]);
+                const uint64_t nw = __ballot(acc == 0u) & ~cov[c];
                 if (nw) {
                     if ((nw >> lane) & 1ull) tpos[c] = r + 1;
                     cov[c] |= nw;
@@ -157,23 +174,21 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
             }
             if (done == ~0ull) break;
         }
-        // survivors: active lanes never covered
         uint64_t tsum = 0;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            uint32_t idx = base + c * 64 + lane;
-            bool act = idx < g.ncand;
-            bool keep = act && !((cov[c] >> lane) & 1ull);
-            uint64_t km = __ballot(keep);
-            uint32_t cnt = (uint32_t)__popcll(km);
-            uint32_t at = 0;
-            if (lane == 0 && cnt) at = atomicAdd(g.nsurv, cnt);
-            at = from_lane0(at);
-            if (keep) {
-                uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-                g.surv[at + (uint32_t)__popcll(km & lt)] = pid[c];
+            const uint32_t idx = base + c * 64 + lane;
+            const bool act = idx < ncand;
+            const bool keep = act && !((cov[c] >> lane) & 1ull);
+            const uint64_t km = __ballot(keep);
+            if (km) {
+                uint32_t at = 0;
+                if (lane == 0) at = atomicAdd(g.nout, (uint32_t)__popcll(km));
+                at = from_lane0(at);
+                if (keep) g.out[at + (uint32_t)__popcll(km & lt)] = pid[c];
             }
-            if (act) tsum += tpos[c] ? tpos[c] : n_o;
+            if (act && tpos[c]) tsum += tpos[c];
+            if (keep && last) tsum += n_o;
         }
         for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o, 64);
         if (g.tests != tests_at) {
@@ -182,155 +197,6 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
             tests_acc = 0;
         }
         tests_acc += tsum;
-    }
-    if (lane == 0 && tests_acc) atomicAdd(tests_at, (unsigned long long)tests_acc);
-}
-
-// ----------------------------------------------------- coherence, refill ----
-template <int KS, int CPL>
-__global__ __launch_bounds__(256) void k_coherence_refill(const CohSeg *__restrict__ segs, uint32_t nseg,
-                                                         const uint32_t *__restrict__ wave_seg) {
-    constexpr int W = 2 * KS;
-    const int lane = threadIdx.x & 63;
-    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const uint32_t gw = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    uint32_t sg = 0;
-    while (sg + 1 < nseg && wave_seg[sg + 1] <= gw) ++sg;
-    sg = uniform(sg);
-    unsigned long long *tests_at = nullptr;
-    uint64_t tests_acc = 0;
-    for (uint32_t visit = 0; visit < nseg; ++visit, sg = (sg + 1 == nseg) ? 0u : sg + 1) {
-        const CohSeg g = segs[sg];
-        if (g.ncand == 0) continue;
-        if (g.tests != tests_at) {
-            if (lane == 0 && tests_acc) atomicAdd(tests_at, (unsigned long long)tests_acc);
-            tests_at = g.tests;
-            tests_acc = 0;
-        }
-        const uint32_t nchunks = g.n_o_pad / COH_CHUNK;
-        uint64_t tsum = 0;   // this lane's t(b) total for the segment
-        uint32_t b[CPL][W];
-        uint32_t pid[CPL], start[CPL], left[CPL], tfirst[CPL];
-        uint64_t live[CPL], cov[CPL];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            live[c] = 0;
-            cov[c] = 0;
-            pid[c] = start[c] = left[c] = tfirst[c] = 0;
-#pragma unroll
-            for (int k = 0; k < W; ++k) b[c][k] = 0;
-        }
-        // wave-private reservoir [res_lo, res_hi) of candidate indices, topped up
-        // from the segment queue RESERVE at a time (one atomic per block)
-        constexpr uint32_t RESERVE = 128;
-        uint32_t res_lo = 0, res_hi = 0;
-        bool queue_done = false, exhausted = false;
-        uint32_t r0 = 0;
-        for (;;) {
-            // give every empty slot the next candidate of the segment
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const uint64_t dead = ~live[c];
-                if (dead && !exhausted) {
-                    const uint32_t nd = (uint32_t)__popcll(dead);
-                    const uint32_t rank = (uint32_t)__popcll(dead & lt);
-                    const uint32_t avail = res_hi - res_lo;
-                    uint32_t nb_lo = 0, nb_hi = 0;
-                    if (avail < nd && !queue_done) {
-                        uint32_t base = 0;
-                        if (lane == 0) base = atomicAdd(g.next, RESERVE);
-                        base = from_lane0(base);
-                        nb_lo = base < g.ncand ? base : g.ncand;
-                        nb_hi = base + RESERVE < g.ncand ? base + RESERVE : g.ncand;
-                        if (base + RESERVE >= g.ncand) queue_done = true;
-                    }
-                    uint32_t idx;
-                    bool ok;
-                    if (rank < avail) {
-                        idx = res_lo + rank;
-                        ok = true;
-                    } else {
-                        idx = nb_lo + (rank - avail);
-                        ok = idx < nb_hi;
-                    }
-                    const bool got = ((dead >> lane) & 1ull) && ok;
-                    const uint32_t take_old = avail < nd ? avail : nd;
-                    if (nb_hi > nb_lo) {
-                        const uint32_t want = nd - take_old, have = nb_hi - nb_lo;
-                        res_lo = nb_lo + (want < have ? want : have);
-                        res_hi = nb_hi;
-                    } else {
-                        res_lo += take_old;
-                    }
-                    exhausted = queue_done && res_lo >= res_hi;
-                    if (got) {
-                        pid[c] = ((const __attribute__((address_space(1))) uint32_t *)(const void *)g.cand)[idx];
-                        uint32_t i, j;
-                        decode_pair(pid[c], g.n, i, j);
-                        gptr32 ra = global_rows(g.X + (size_t)i * KS);
-                        gptr32 rb = global_rows(g.X + (size_t)j * KS);
-#pragma unroll
-                        for (int k = 0; k < W; ++k) b[c][k] = ra[k] & rb[k];
-                        start[c] = r0;
-                        left[c] = nchunks;
-                    }
-                    const uint64_t gm = __ballot(got);
-                    live[c] |= gm;
-                    cov[c] &= ~gm;
-                }
-            }
-            uint64_t any = 0;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) any |= live[c];
-            if (!any) break;   // segment drained
-            if (nchunks) {
-                r0 = uniform(r0);
-                cptr32 R = (cptr32)(const void *)g.NXo + (size_t)r0 * W;
-                for (uint32_t rr = 0; rr < COH_CHUNK; ++rr) {
-                    cptr32 row = R + (size_t)rr * W;
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        const uint32_t acc = masked_or<W>(row, b[c]);
-                        const uint64_t nw = __ballot(acc == 0u) & live[c] & ~cov[c];
-                        if (nw) {
-                            if ((nw >> lane) & 1ull) tfirst[c] = r0 + rr;
-                            cov[c] |= nw;
-                        }
-                    }
-                }
-                r0 += COH_CHUNK;
-                if (r0 == g.n_o_pad) r0 = 0;
-            }
-            // retire slots that are covered or have seen every record
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const bool me_live = (live[c] >> lane) & 1ull;
-                if (me_live && nchunks) left[c] -= 1;
-                const uint64_t fin = live[c] & (cov[c] | __ballot(me_live && left[c] == 0));
-                if (fin) {
-                    const bool me = (fin >> lane) & 1ull;
-                    const bool covered = (cov[c] >> lane) & 1ull;
-                    const bool keep = me && !covered;
-                    if (me)
-                        tsum += keep ? g.n_o
-                                     : (tfirst[c] >= start[c] ? tfirst[c] - start[c] + 1
-                                                              : g.n_o - start[c] + tfirst[c] + 1);
-                    const uint64_t km = __ballot(keep);
-                    if (km) {
-                        uint32_t at = 0;
-                        if (lane == 0) at = atomicAdd(g.nsurv, (uint32_t)__popcll(km));
-                        at = from_lane0(at);
-                        if (keep) g.surv[at + (uint32_t)__popcll(km & lt)] = pid[c];
-                    }
-                    live[c] &= ~fin;
-                    cov[c] &= ~fin;
-                }
-            }
-        }
-        // per-lane counts of this segment, reduced once
-        uint64_t ts = tsum;
-        for (int o = 32; o > 0; o >>= 1) ts += __shfl_xor(ts, o, 64);
-        tests_acc += ts;
     }
     if (lane == 0 && tests_acc) atomicAdd(tests_at, (unsigned long long)tests_acc);
 }
@@ -546,40 +412,21 @@ uint32_t coherence_grid(int KS, int cpl) {
     return (uint32_t)cus * 8u;   // persistent: 8 workgroups (32 waves) per CU
 }
 
-void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, const uint32_t *task_prefix_dev,
+void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, uint32_t r_begin, uint32_t r_end,
                       uint32_t *queue, uint32_t grid, hipStream_t s) {
     launch_fill_u32(queue, 0u, 1, s);
 #define IG_COH(V)                                                                                              \
     case V:                                                                                                    \
         if (cpl == 2 && V <= 16)                                                                               \
-            hipLaunchKernelGGL((k_coherence<V, 2>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, task_prefix_dev, \
-                               queue);                                                                         \
+            hipLaunchKernelGGL((k_coherence<V, 2>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, r_begin, r_end, queue); \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_coherence<V, 1>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, task_prefix_dev, \
-                               queue);                                                                         \
+            hipLaunchKernelGGL((k_coherence<V, 1>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, r_begin, r_end, queue); \
         break;
     switch (KS) {
         IG_FOR_EACH_KS(IG_COH)
         default: throw Error(IG_E_UNSUPPORTED, "unsupported word count");
     }
 #undef IG_COH
-    IG_HIP(hipGetLastError());
-}
-
-void launch_coherence_refill(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, const uint32_t *wave_seg_dev,
-                             uint32_t grid, hipStream_t s) {
-#define IG_COHR(V)                                                                                             \
-    case V:                                                                                                    \
-        if (cpl == 2 && V <= 16)                                                                               \
-            hipLaunchKernelGGL((k_coherence_refill<V, 2>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, wave_seg_dev); \
-        else                                                                                                   \
-            hipLaunchKernelGGL((k_coherence_refill<V, 1>), dim3(grid), dim3(256), 0, s, segs_dev, nseg, wave_seg_dev); \
-        break;
-    switch (KS) {
-        IG_FOR_EACH_KS(IG_COHR)
-        default: throw Error(IG_E_UNSUPPORTED, "unsupported word count");
-    }
-#undef IG_COHR
     IG_HIP(hipGetLastError());
 }
 

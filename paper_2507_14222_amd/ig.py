@@ -30,7 +30,7 @@ class IGError(RuntimeError):
 
 class FitOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_uint64), ("filter_cpl", C.c_uint32), ("score_fpl", C.c_uint32),
-                ("block", C.c_uint32), ("scan_order", C.c_uint32), ("reserved", C.c_uint32 * 4)]
+                ("block", C.c_uint32), ("reserved", C.c_uint32 * 5)]
 
 
 class Stats(C.Structure):
@@ -127,12 +127,11 @@ def _np_u16(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.uint16)
 
 
-def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, scan_order: int = 0) -> FitOpts:
+def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0) -> FitOpts:
     o = FitOpts()
     o.mem_budget_bytes = int(mem_budget_bytes)
     o.filter_cpl = int(filter_cpl)
     o.score_fpl = int(score_fpl)
-    o.scan_order = int(scan_order)
     return o
 
 
@@ -203,17 +202,15 @@ class Model:
             pass
 
 
-def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, scan_order: int = 0,
-        stream=None) -> Model:
-    """ig_fit: codes [n, d] bin codes, labels [n] (0 normal / 1 attack), nbins [d].
-    scan_order=1 scans the other class in input order (exact input-order t(b) counts)."""
+def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, stream=None) -> Model:
+    """ig_fit: codes [n, d] bin codes, labels [n] (0 normal / 1 attack), nbins [d]."""
     torch = _torch()
     dc = _dev(codes, torch.int16)
     dl = _dev(labels, torch.uint8)
     n, d = (int(dc.shape[0]), int(dc.shape[1])) if dc.dim() == 2 else (0, 0)
     nb = _np_u16(nbins)
     h = C.c_void_p()
-    o = _opts(mem_budget_bytes, filter_cpl, scan_order=scan_order)
+    o = _opts(mem_budget_bytes, filter_cpl)
     _check(lib().ig_fit(C.c_void_p(dc.data_ptr()), C.c_void_p(dl.data_ptr()), n, d or nb.size,
                         C.c_void_p(nb.ctypes.data), C.byref(o), _stream_handle(stream), C.byref(h)))
     return Model(h)

@@ -39,20 +39,14 @@ def assert_same_model(m, om, K):
         assert np.array_equal(S, om.S[c]), f"class {c}: weights differ"
 
 
-def assert_same_stats(m, om, input_order=True):
-    """Counters equal the oracle's; t(b) sums only when the other class was
-    scanned in input order, else they lie between coherent*n_o and distinct*n_o."""
+def assert_same_stats(m, om):
+    """Counters equal the oracle's, including the input-order sums of t(b)."""
     st = m.stats()
     assert list(st.pairs) == om.stats["pairs"]
     assert list(st.distinct) == om.stats["distinct"]
     assert list(st.coherent) == om.stats["coherent"]
     assert list(st.n_class) == om.stats["n_class"]
-    if input_order:
-        assert list(st.tests) == om.stats["tests"]
-    else:
-        for c in (0, 1):
-            n_o = om.stats["n_class"][1 - c]
-            assert om.stats["coherent"][c] * n_o <= st.tests[c] <= om.stats["distinct"][c] * n_o
+    assert list(st.tests) == om.stats["tests"]
 
 
 def gpu_scores(m, flows):
@@ -67,8 +61,7 @@ def gpu_scores(m, flows):
 def test_worked_example():
     g = json.load(open(os.path.join(GOLD, "worked_example.json")))
     say("worked example")
-    m = ig.fit(np.array(g["codes"], np.uint16), np.array(g["labels"], np.uint8), np.array(g["nbins"], np.uint16),
-               scan_order=1)
+    m = ig.fit(np.array(g["codes"], np.uint16), np.array(g["labels"], np.uint8), np.array(g["nbins"], np.uint16))
     for c in ("0", "1"):
         w, f, S = m.export(int(c))
         got = [(int(w[p, 0]), int(f[p]), int(S[p])) for p in range(w.shape[0])]
@@ -85,12 +78,9 @@ def test_tiny_workload_full_parity():
     w = synth.make_tiny(0)
     say("tiny workload", w.codes.shape)
     om = oracle.fit(w.codes, w.labels, w.nbins)
-    m1 = ig.fit(w.codes, w.labels, w.nbins, scan_order=1)
-    assert_same_model(m1, om, om.K)
-    assert_same_stats(m1, om)
     m = ig.fit(w.codes, w.labels, w.nbins)
     assert_same_model(m, om, om.K)
-    assert_same_stats(m, om, input_order=False)
+    assert_same_stats(m, om)
     A, N = gpu_scores(m, w.test_codes)
     oA, oN = oracle.score(om, w.test_codes, w.nbins)
     assert np.array_equal(A, oA) and np.array_equal(N, oN)
@@ -127,13 +117,10 @@ def test_random_problem_parity(case):
     p = synth.make_random_problem(seed, n, d, bins_lo=blo, bins_hi=bhi, attack_frac=af)
     say("random problem", case, "L", p.L)
     om = oracle.fit(p.codes, p.labels, p.nbins)
-    m1 = ig.fit(p.codes, p.labels, p.nbins, scan_order=1)
-    assert m1.K == om.K
-    assert_same_model(m1, om, om.K)
-    assert_same_stats(m1, om)
     m = ig.fit(p.codes, p.labels, p.nbins)
+    assert m.K == om.K
     assert_same_model(m, om, om.K)
-    assert_same_stats(m, om, input_order=False)
+    assert_same_stats(m, om)
     flows = synth.make_random_problem(seed + 1000, 97, d, bins_lo=blo, bins_hi=bhi).codes
     flows = np.minimum(flows, p.nbins[None, :] - 1).astype(np.uint16)
     flows = np.concatenate([flows, p.codes[: min(40, p.n)]])
@@ -145,14 +132,11 @@ def test_random_problem_parity(case):
 def test_filter_lanes_per_candidate_agree():
     p = synth.make_random_problem(21, 333, 20, bins_lo=3, bins_hi=7)
     say("cpl 1 vs 2")
-    a = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=1, scan_order=1)
-    b = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=2, scan_order=1)
-    c1 = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=1)
-    c2 = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=2)
+    a = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=1)
+    b = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=2)
     for c in (0, 1):
-        for m in (b, c1, c2):
-            for x, y in zip(a.export(c), m.export(c)):
-                assert np.array_equal(x, y)
+        for x, y in zip(a.export(c), b.export(c)):
+            assert np.array_equal(x, y)
     assert a.stats().tests == b.stats().tests
 
 
@@ -241,10 +225,9 @@ def test_degenerate_sizes():
         codes = codes.astype(np.uint16)
         labels = labels.astype(np.uint8)
         om = oracle.fit(codes, labels, nb)
-        for order in (0, 1):
-            m = ig.fit(codes, labels, nb, scan_order=order)
-            assert_same_model(m, om, om.K)
-            assert_same_stats(m, om, input_order=order == 1)
+        m = ig.fit(codes, labels, nb)
+        assert_same_model(m, om, om.K)
+        assert_same_stats(m, om)
 
 
 def test_scores_do_not_depend_on_batching():
@@ -276,15 +259,12 @@ def test_15k_workload_matches_oracle_digest():
     g = json.load(open(os.path.join(GOLD, "mixture41_15k.json")))
     w = synth.make_15k()
     say("15k workload", w.codes.shape, w.test_codes.shape)
-    m1 = ig.fit(w.codes, w.labels, w.nbins, scan_order=1)
-    assert list(m1.stats().tests) == g["stats"]["tests"]
-    assert _model_digest(m1) == g["model_sha256"]
-    del m1
     m = ig.fit(w.codes, w.labels, w.nbins)   # the configuration the benchmark times
     st = m.stats()
     assert list(st.pairs) == g["stats"]["pairs"]
     assert list(st.distinct) == g["stats"]["distinct"]
     assert list(st.coherent) == g["stats"]["coherent"]
+    assert list(st.tests) == g["stats"]["tests"]
     assert _model_digest(m) == g["model_sha256"]
     A, N = gpu_scores(m, w.test_codes)
     assert A[:16].tolist() == g["scores_head"]["A"] and N[:16].tolist() == g["scores_head"]["N"]
