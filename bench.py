@@ -48,6 +48,73 @@ def counted_traffic(path):
     return int(vals["bytes_per_launch"])
 
 
+def measure_serving(seconds):
+    """Served scoring: 10^6 patterns per class resident, Poisson arrivals of
+    requests of 1..4096 flows; continuous batching vs one request at a time."""
+    import numpy as np
+    import torch
+
+    from paper_2507_14222_amd import ig, synth
+    from paper_2507_14222_amd.serve import Server, drive, serve_one_at_a_time
+
+    log("serving: building 2 x 10^6 patterns")
+    ps = synth.make_pattern_set()
+    model = ig.import_patterns(ps.codes[0], ps.f[0], ps.codes[1], ps.f[1], ps.nbins)
+    pool = synth.make_flows(n=200000)
+    out = {"patterns": list(model.n_patterns()), "rates": []}
+
+    def one_rate(rate, n_req, seed):
+        reqs = synth.make_requests(seed, rate, n_req, pool.shape[0])
+        codes = [pool[r.start:r.start + r.size] for r in reqs]
+        arr = [r.arrival_s for r in reqs]
+        return codes, arr
+
+    # warm: code objects, pinned buffers
+    codes, arr = one_rate(1e5, 20, 99)
+    with Server(model, n_slots=4, max_batch_flows=16384) as srv:
+        for f in [srv.submit(c) for c in codes]:
+            f.result()
+    for rate, seed in ((1e4, 11), (1e5, 12), (5e5, 13), (1e6, 14)):
+        n_req = int(max(100, rate * seconds / 492))
+        codes, arr = one_rate(rate, n_req, seed)
+        with Server(model, n_slots=4, max_batch_flows=16384) as srv:
+            futs, t0 = drive(srv, codes, arr)
+            for f in futs:
+                f.result()
+            done = srv.completed
+            batches = srv.batches
+        lat = np.array([r.t_done - r.t_arrival for r in done])
+        flows = sum(c.shape[0] for c in codes)
+        span = max(r.t_done for r in done) - t0
+        out["rates"].append({"offered_flows_per_s": rate, "requests": n_req, "flows": flows,
+                             "served_flows_per_s": flows / span, "batches": batches,
+                             "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                             "p99_ms": float(np.percentile(lat, 99) * 1e3)})
+        log("serving", out["rates"][-1])
+    # one request at a time at the middle rate
+    codes, arr = one_rate(1e5, int(max(100, 1e5 * seconds / 492)), 12)
+    _, lat1 = serve_one_at_a_time(model, codes, arr)
+    flows = sum(c.shape[0] for c in codes)
+    span = arr[-1] + lat1[-1]
+    lat1 = np.array(lat1)
+    out["one_at_a_time"] = {"offered_flows_per_s": 1e5, "requests": len(codes), "flows": flows,
+                            "served_flows_per_s": flows / span,
+                            "p50_ms": float(np.percentile(lat1, 50) * 1e3),
+                            "p99_ms": float(np.percentile(lat1, 99) * 1e3)}
+    # saturated throughput: every request queued at once
+    codes, arr = one_rate(1e6, 2000, 15)
+    with Server(model, n_slots=4, max_batch_flows=16384) as srv:
+        t0 = time.perf_counter()
+        for f in [srv.submit(c) for c in codes]:
+            f.result()
+        dt = time.perf_counter() - t0
+    out["saturated_flows_per_s"] = sum(c.shape[0] for c in codes) / dt
+    log("serving saturated", out["saturated_flows_per_s"])
+    del model
+    torch.cuda.synchronize()
+    return out
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -59,6 +126,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-148k", action="store_true", help="skip the 148k fit wall time")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-scoring measurement")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="offered load duration per rate")
     ap.add_argument("--cpu-records", type=int, default=7000, help="training records in the oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB, 4 times (calibrates HBM byte counters)")
@@ -162,6 +231,8 @@ def main():
         res["fit_148k"] = {"n_train": int(w2.n), "patterns": list(m2.n_patterns()), "tests": list(st2.tests),
                            "coherence_ms": st2.ms[4]}
         del m2
+    if not args.no_serve:
+        res["serve"] = measure_serving(args.serve_seconds)
     if not args.no_cpu:
         import oracle
         ns = min(args.cpu_records, w.n)
