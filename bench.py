@@ -48,6 +48,73 @@ def counted_traffic(path):
     return int(vals["bytes_per_launch"])
 
 
+def measure_batch():
+    """64 problems (n 500..20,000, d 20..80, bins 4..32): ig_fit_batch against 64
+    plain ig_fit calls.  The 64 models hold ~2.2e9 patterns, more than HBM, so both
+    runs go through memory-sized slices of the problem list; each model is reduced
+    to its device digest and freed."""
+    import numpy as np
+    import torch
+
+    from paper_2507_14222_amd import ig, synth, tune
+
+    probs = synth.make_batch()
+    table = tune.load(os.path.join(ROOT, "paper_2507_14222_amd", "tuning_gfx950.json"))
+    dev = [(torch.from_numpy(p.codes.view(np.int16)).cuda(), torch.from_numpy(p.labels).cuda(), p.nbins)
+           for p in probs]
+
+    class P:
+        def __init__(self, c, l, nb):
+            self.codes, self.labels, self.nbins = c, l, nb
+
+    def est_bytes(p):
+        n1 = int(p.labels.sum())
+        n0 = p.n - n1
+        K = tune.ig_storage_words((p.L + 63) // 64)
+        return (n0 * (n0 + 1) // 2 + n1 * (n1 + 1) // 2) * (K * 8 + 12)
+
+    slices, cur, acc = [], [], 0
+    for i, p in enumerate(probs):
+        b = est_bytes(p)
+        if cur and acc + b > 90e9:
+            slices.append(cur)
+            cur, acc = [], 0
+        cur.append(i)
+        acc += b
+    slices.append(cur)
+    log("batch: %d problems in %d slices" % (len(probs), len(slices)))
+    tests = 0
+    dig_b, dig_s = {}, {}
+    torch.cuda.synchronize()
+    t_batch = 0.0
+    for sl in slices:
+        a = time.perf_counter()
+        ms = ig.fit_batch([P(*dev[i]) for i in sl], tune=table)
+        t_batch += time.perf_counter() - a
+        for i, m in zip(sl, ms):
+            st = m.stats()
+            tests += sum(st.tests) + sum(st.support_tests)
+            dig_b[i] = (m.digest(0), m.digest(1), tuple(st.coherent))
+            m.free()
+        log("batched slice of", len(sl), "done")
+    t_seq = 0.0
+    for i in range(len(probs)):
+        a = time.perf_counter()
+        m = ig.fit(*dev[i], tune=table)
+        t_seq += time.perf_counter() - a
+        st = m.stats()
+        dig_s[i] = (m.digest(0), m.digest(1), tuple(st.coherent))
+        m.free()
+    same = all(dig_b[i] == dig_s[i] for i in range(len(probs)))
+    pats = sum(sum(dig_b[i][2]) for i in dig_b)
+    return {"workload": "64 problems (seed 3)", "problems": len(probs), "slices": len(slices),
+            "patterns": pats, "subset_tests": tests,
+            "batched_s": t_batch, "sequential_s": t_seq,
+            "batched_tests_per_s": tests / t_batch, "sequential_tests_per_s": tests / t_seq,
+            "batched_problems_per_s": len(probs) / t_batch, "sequential_problems_per_s": len(probs) / t_seq,
+            "identical": same, "tuning_rows": len(table or [])}
+
+
 def measure_serving(seconds):
     """Served scoring: 10^6 patterns per class resident, Poisson arrivals of
     requests of 1..4096 flows; continuous batching vs one request at a time."""
@@ -129,6 +196,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-scoring measurement")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="offered load duration per rate")
     ap.add_argument("--cpu-records", type=int, default=7000, help="training records in the oracle sample")
+    ap.add_argument("--batch", action="store_true",
+                    help="only run the 64-problem workload: batched fit vs 64 plain fits")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB, 4 times (calibrates HBM byte counters)")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "k_coherence_15k_traffic.txt"))
@@ -152,6 +221,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 1 << 30, "copies": 4}))
+        return
+    if args.batch:
+        print(json.dumps(measure_batch()), flush=True)
         return
     w = synth.make_15k()
     log("15k workload", w.codes.shape, "test", w.test_codes.shape)

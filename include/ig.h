@@ -59,16 +59,31 @@ typedef enum {
 
 typedef struct ig_model ig_model;   /* opaque; owns the device-resident pattern sets */
 
+/* One row of a tuning table (written by the project's autotuner): the launch
+ * shape to use for problems stored with `ks` words and at least `min_pairs`
+ * same-class pairs.  The matching row with the largest min_pairs wins; a row with
+ * ks = 0 matches any width.  Tuning never changes results. */
+typedef struct {
+    uint32_t ks;             /* storage words (0 = any)                               */
+    uint32_t min_pairs;      /* smallest problem (pairs of both classes) it covers   */
+    uint32_t filter_cpl;     /* coherence kernel: candidates per lane, 1 or 2        */
+    uint32_t grid_per_cu;    /* coherence kernel: workgroups per compute unit, 1..32 */
+    uint32_t support_cpl;    /* support kernel: patterns per lane, 1 or 2            */
+    uint32_t reserved[3];
+} ig_tune_entry;
+
 /* Optional knobs of a fit.  Zero-initialise and set what is needed. */
 typedef struct {
     uint64_t mem_budget_bytes;  /* 0: no limit.  Otherwise the pair space of a class
                                    is processed in chunks so that the fit's scratch
                                    stays near this many bytes (results unchanged).   */
     uint32_t filter_cpl;        /* candidates per lane of the coherence kernel
-                                   (0 = tuned default; 1 or 2)                        */
-    uint32_t score_fpl;         /* flows per lane of the scoring kernel (0, 1 or 2)  */
+                                   (0 = tuned default; 1 or 2); overrides the table   */
+    uint32_t score_fpl;         /* reserved                                           */
     uint32_t block;             /* reserved (workgroups are 256 threads)              */
-    uint32_t reserved[5];
+    uint32_t n_tune;            /* rows in `tune`                                     */
+    const ig_tune_entry *tune;  /* host tuning table (may be NULL)                    */
+    uint32_t reserved[2];
 } ig_fit_opts;
 
 /* Counters and timings of a fit (Section 3.3 stages). */
@@ -84,7 +99,9 @@ typedef struct {
     uint64_t support_tests[2]; /* |P^c| * n_c subset tests of Eq. 2                  */
     uint32_t chunks[2];      /* pair-space chunks used for the class                 */
     float ms[8];             /* device time per stage: 0 pack, 1 pairs+hash, 2 sort,
-                                3 dedup, 4 coherence, 5 order, 6 support, 7 total    */
+                                3 dedup, 4 coherence, 5 order, 6 support, 7 total
+                                (batched fits: a group's shared stages are split
+                                over its problems by their share of the pairs)       */
 } ig_stats;
 
 typedef struct {
@@ -124,11 +141,15 @@ ig_status ig_fit_packed(const uint64_t *d_words, const uint8_t *d_labels, uint32
                         const ig_fit_opts *opts, void *stream, ig_model **out);
 
 /* ---------------------------------------------------------------------------
- * ig_fit_batch -- n_probs independent fits (problems of any size and width)
- * through one captured launch sequence per memory-sized group of problems.
- * outs[p] receives exactly the model ig_fit would build for probs[p] (same
- * patterns, f, S, counters).  All problems are validated first; on any error no
- * model is returned and outs is untouched.
+ * ig_fit_batch -- n_probs independent fits (problems of any size and width).
+ * Problems are grouped by word width and by memory; for each group, pair
+ * enumeration, one radix sort, one de-duplication and one coherence launch
+ * over every (problem, class) of the group run as a single captured HIP graph,
+ * followed by ordering and support per problem.  A problem too large for a group
+ * is fitted on its own as by ig_fit.  outs[p] receives exactly the model ig_fit
+ * would build for probs[p] (same patterns, f, S, counters).  All problems are
+ * validated first; on any error no model is returned and outs is untouched.
+ * Synchronises `stream` before returning.
  * ------------------------------------------------------------------------- */
 ig_status ig_fit_batch(const ig_problem *probs, uint32_t n_probs, const ig_fit_opts *opts,
                        void *stream, ig_model **outs);
@@ -168,6 +189,11 @@ ig_status ig_model_export(const ig_model *m, uint32_t cls, uint64_t *h_words, ui
 ig_status ig_model_import(const uint16_t *const h_codes[2], const uint32_t *const h_f[2],
                           const uint64_t count[2], uint32_t d, const uint16_t *h_nbins,
                           void *stream, ig_model **out);
+
+/* Order-dependent 64-bit digest of class `cls` (rows, f and S in canonical
+ * order), computed on the device: compares models that are too large to copy
+ * out.  Equal models give equal digests.  Synchronous. */
+ig_status ig_model_digest(const ig_model *m, uint32_t cls, uint64_t *out);
 
 /* Counters and stage timings of the fit that built the model (zeros for an
  * imported model). */

@@ -139,32 +139,57 @@ static std::vector<uint32_t> host_read_u32(const uint32_t *d, size_t n, hipStrea
 
 // ----------------------------------------------------------- fit from rows ----
 struct Timer {
-    hipEvent_t ev[9];
+    hipEvent_t ev[9] = {};
+    bool marked[9] = {};
     bool on = false;
     hipStream_t s;
     explicit Timer(hipStream_t st) : s(st) {
         on = true;
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess) on = false;
+        (void)hipGetLastError();
     }
     void mark(int i) {
-        if (on) (void)hipEventRecord(ev[i], s);
+        if (on && hipEventRecord(ev[i], s) == hipSuccess) marked[i] = true;
+    }
+    // milliseconds between two recorded events (false when either was not recorded)
+    bool elapsed(int a, int b, float &ms) const {
+        if (!on || !marked[a] || !marked[b]) return false;
+        return hipEventElapsedTime(&ms, ev[a], ev[b]) == hipSuccess;
     }
     ~Timer() {
-        for (auto &e : ev) (void)hipEventDestroy(e);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
 struct Tuning {
-    int cpl = 1, fpl = 2;   // coherence: one candidate per lane measured fastest
+    int cpl = 1;               // coherence: candidates per lane (one measured fastest at 15k)
+    uint32_t grid_per_cu = 8;  // coherence: persistent workgroups per CU
+    int support_cpl = 2;       // support: patterns per lane
 };
 
-static Tuning tuning_from(const ig_fit_opts *o) {
+// Launch shape for a problem stored with KS words and `pairs` same-class pairs:
+// the matching row of the tuning table with the largest min_pairs (an exact KS
+// match beats ks = 0), then the explicit filter_cpl override.
+static Tuning tuning_for(const ig_fit_opts *o, uint32_t KS, uint64_t pairs) {
     Tuning t;
-    if (o) {
-        if (o->filter_cpl == 1 || o->filter_cpl == 2) t.cpl = (int)o->filter_cpl;
-        if (o->score_fpl == 1 || o->score_fpl == 2) t.fpl = (int)o->score_fpl;
+    if (o && o->tune && o->n_tune) {
+        const ig_tune_entry *best = nullptr;
+        for (uint32_t i = 0; i < o->n_tune; ++i) {
+            const ig_tune_entry &e = o->tune[i];
+            if ((e.ks != 0 && e.ks != KS) || e.min_pairs > pairs) continue;
+            if (!best || (best->ks == 0 && e.ks != 0) ||
+                ((best->ks != 0) == (e.ks != 0) && e.min_pairs > best->min_pairs))
+                best = &e;
+        }
+        if (best) {
+            if (best->filter_cpl == 1 || best->filter_cpl == 2) t.cpl = (int)best->filter_cpl;
+            if (best->grid_per_cu >= 1 && best->grid_per_cu <= 32) t.grid_per_cu = best->grid_per_cu;
+            if (best->support_cpl == 1 || best->support_cpl == 2) t.support_cpl = (int)best->support_cpl;
+        }
     }
+    if (o && (o->filter_cpl == 1 || o->filter_cpl == 2)) t.cpl = (int)o->filter_cpl;
     return t;
 }
 
@@ -176,10 +201,9 @@ struct ClassRows {
 // Canonical order (ascending w_0..w_{K-1}) of the pair ids `ids` of one class;
 // then rows, merge of equal rows (they arise when the pair space was chunked),
 // support and weights.  Fills model class c.
-static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, const ClassRows &other_unused,
-                            Scratch<uint32_t> &ids, size_t count, bool may_repeat, const Tuning &tu,
-                            hipStream_t s) {
-    (void)other_unused;
+static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *ids, size_t count,
+                            bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
+                            int support_mark = -1) {
     const uint32_t KS = m.KS, K = m.K;
     if (count == 0) {
         m.np[c] = 0;
@@ -192,14 +216,14 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, const Clas
     Scratch<unsigned long long> rng(2 * K, s);
     launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get()), 0ull, K, s);
     launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get() + K), ~0ull, K, s);
-    launch_word_range(cls.X.get(), cls.n, KS, K, ids.get(), count, rng.get(), rng.get() + K, s);
+    launch_word_range(cls.X.get(), cls.n, KS, K, ids, count, rng.get(), rng.get() + K, s);
     std::vector<unsigned long long> hr(2 * K);
     IG_HIP(hipMemcpyAsync(hr.data(), rng.get(), 2 * K * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     IG_HIP(hipStreamSynchronize(s));
 
     Scratch<uint64_t> k0(count, s), k1(count, s);
     Scratch<uint32_t> v1(count, s);
-    uint32_t *vcur = ids.get(), *valt = v1.get();
+    uint32_t *vcur = ids, *valt = v1.get();
     for (int k = (int)K - 1; k >= 0; --k) {
         uint64_t vary = hr[k] ^ hr[K + k];
         uint32_t mask = 0;
@@ -234,7 +258,8 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, const Clas
         if (Wd && m.W[c] != Wd) (void)hipFree(Wd);
         throw;
     }
-    launch_support((int)KS, 2, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
+    if (tm && support_mark >= 0) tm->mark(support_mark);
+    launch_support((int)KS, tu.support_cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
 }
 
 static void finish_weights(DevModel &m, hipStream_t s) {
@@ -261,7 +286,8 @@ static std::vector<uint32_t> coherence_phases(uint32_t max_other) {
 
 static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts, hipStream_t s, Timer &tm) {
     const uint32_t KS = m.KS, K = m.K;
-    const Tuning tu = tuning_from(opts);
+    const Tuning tu = tuning_for(opts, KS, (uint64_t)cls[0].n * (cls[0].n ? cls[0].n - 1 : 0) / 2 +
+                                               (uint64_t)cls[1].n * (cls[1].n ? cls[1].n - 1 : 0) / 2);
     uint64_t M[2];
     for (int c = 0; c < 2; ++c) {
         uint64_t n = cls[c].n;
@@ -320,7 +346,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         IG_HIP(hipMemcpyAsync(rowsegs.get(), h.data(), h.size(), hipMemcpyHostToDevice, s));
         IG_HIP(hipStreamSynchronize(s));
     }
-    const uint32_t grid = coherence_grid((int)KS, tu.cpl);
+    const uint32_t grid = coherence_grid(tu.grid_per_cu);
     float ms_pairs = 0, ms_sort = 0, ms_dedup = 0, ms_coh = 0;
     hipEvent_t e[5];
     for (auto &x : e) IG_HIP(hipEventCreate(&x));
@@ -399,6 +425,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
                     g.X = cls[c].X.get();
                     g.NXo = cls[1 - c].NX.get();
                     g.cand = cur[c];
+                    g.cand_off = nullptr;
                     g.ncand = curcnt[c];
                     g.out = last ? surv[c].get() : nxt[c];
                     g.nout = last ? counters.get() + c : pcount.get() + 4 * p + c;
@@ -445,9 +472,10 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     }
     const bool chunked = chunks.size() > 1;
     for (int c = 0; c < 2; ++c) {
-        order_and_weigh(m, c, cls[c], cls[1 - c], surv[c], hn[c], chunked, tu, s);
+        order_and_weigh(m, c, cls[c], surv[c].get(), hn[c], chunked, tu, s, &tm, c == 0 ? 5 : 8);
         m.stats.coherent[c] = m.np[c];
         m.stats.support_tests[c] = m.np[c] * (uint64_t)cls[c].n;
+        if (c == 0) tm.mark(3);   // end of class 0's support
     }
     tm.mark(6);
     finish_weights(m, s);
@@ -474,16 +502,17 @@ static DevModel *new_model() {
     return m;
 }
 
+// Stage times from the fit's events: 0 start, 1 packed, 4 coherence done,
+// 5 class-0 support start, 3 class-0 support end, 8 class-1 support start,
+// 6 class-1 support end, 7 done.
 static void record_times(DevModel &m, Timer &tm) {
-    if (!tm.on) return;
-    float a;
-    if (hipEventElapsedTime(&a, tm.ev[0], tm.ev[1]) == hipSuccess) m.stats.ms[0] = a;
-    if (hipEventElapsedTime(&a, tm.ev[4], tm.ev[6]) == hipSuccess) {
-        // ordering + support, split by the support launches' share is not separated
-        m.stats.ms[5] = a;
+    float a, b, c0, c1;
+    if (tm.elapsed(0, 1, a)) m.stats.ms[0] = a;
+    if (tm.elapsed(5, 3, c0) && tm.elapsed(8, 6, c1)) {
+        m.stats.ms[6] = c0 + c1;
+        if (tm.elapsed(4, 6, b)) m.stats.ms[5] = b - c0 - c1;
     }
-    if (hipEventElapsedTime(&a, tm.ev[6], tm.ev[7]) == hipSuccess) m.stats.ms[6] = a;
-    if (hipEventElapsedTime(&a, tm.ev[0], tm.ev[7]) == hipSuccess) m.stats.ms[7] = a;
+    if (tm.elapsed(0, 7, a)) m.stats.ms[7] = a;
 }
 
 DevModel *fit_codes(const uint16_t *d_codes, const uint8_t *d_labels, uint32_t n, uint32_t d,
@@ -604,6 +633,269 @@ DevModel *import_patterns(const uint16_t *const h_codes[2], const uint32_t *cons
     return m.release();
 }
 
+
+// ------------------------------------------------------------ batched fit ----
+// A library-owned stream per device for captured sequences (a caller's stream
+// may be the legacy default stream, which cannot be captured).
+static std::mutex g_batch_mu;
+
+static hipStream_t internal_stream() {
+    static hipStream_t st[64] = {};
+    int dev = 0;
+    IG_HIP(hipGetDevice(&dev));
+    IG_REQUIRE(dev >= 0 && dev < 64, IG_E_UNSUPPORTED, "device index beyond 63");
+    if (!st[dev]) IG_HIP(hipStreamCreateWithFlags(&st[dev], hipStreamNonBlocking));
+    return st[dev];
+}
+
+struct BProb {
+    uint32_t n = 0, d = 0, K = 0, KS = 0, L = 0;
+    const uint16_t *codes = nullptr;
+    const uint8_t *labels = nullptr;
+    const uint16_t *nbins = nullptr;
+    std::unique_ptr<DevModel> m;
+    ClassRows cls[2];
+    uint64_t M[2] = {0, 0};
+    Scratch<uint32_t> err, pos, counts;
+    uint64_t pairs() const {
+        return (uint64_t)cls[0].n * (cls[0].n ? cls[0].n - 1 : 0) / 2 +
+               (uint64_t)cls[1].n * (cls[1].n ? cls[1].n - 1 : 0) / 2;
+    }
+};
+
+struct GraphGuard {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~GraphGuard() {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+// Enumeration, one radix sort, one de-duplication and one coherence launch for
+// every (problem, class) of the group, captured and launched as one graph; then
+// ordering and support per problem.  All problems have the same KS.
+static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStream_t s) {
+    const uint32_t KS = G[0]->KS;
+    const uint32_t nseg = 2 * (uint32_t)G.size();
+    int segbits = 1;
+    while ((1u << segbits) < nseg) ++segbits;
+    std::vector<uint64_t> off(nseg + 1, 0);
+    uint32_t max_other = 1;
+    uint64_t group_pairs = 0;
+    for (uint32_t g = 0; g < G.size(); ++g) {
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t sg = 2 * g + c;
+            off[sg + 1] = off[sg] + G[g]->M[c];
+            max_other = std::max(max_other, G[g]->cls[1 - c].n);
+        }
+        group_pairs += G[g]->pairs();
+    }
+    const size_t items = off[nseg];
+    IG_REQUIRE(items < (1ull << 32), IG_E_UNSUPPORTED, "group of more than 2^32 candidates");
+    const Tuning tu = tuning_for(opts, KS, group_pairs / std::max<size_t>(G.size(), 1));
+    const size_t cap = std::max<size_t>(items, 1);
+    Scratch<uint64_t> k0(cap, s), k1(cap, s);
+    Scratch<uint32_t> v0(cap, s), v1(cap, s), flags(cap, s), pos(cap, s), cand(cap, s), surv(cap, s);
+    Scratch<uint32_t> tot(1, s), segc(nseg, s), segoff(nseg, s), cnt(nseg + 1, s);
+    Scratch<unsigned long long> tests(nseg, s);
+    Scratch<uint32_t> rws(radix_ws_size(cap), s), sws(scan_ws_size(cap), s);
+    Scratch<unsigned char> rowsegs(nseg * rows_of_seg_size(), s);
+    Scratch<CohSeg> cohsegs(nseg, s);
+    {
+        std::vector<unsigned char> hr(nseg * rows_of_seg_size());
+        std::vector<CohSeg> hc(nseg);
+        for (uint32_t g = 0; g < G.size(); ++g)
+            for (int c = 0; c < 2; ++c) {
+                const uint32_t sg = 2 * g + c;
+                fill_rows_of_seg(hr.data() + sg * rows_of_seg_size(), G[g]->cls[c].X.get(), G[g]->cls[c].n, KS,
+                                 G[g]->K);
+                CohSeg &h = hc[sg];
+                h = CohSeg{};
+                h.X = G[g]->cls[c].X.get();
+                h.NXo = G[g]->cls[1 - c].NX.get();
+                h.cand = cand.get();
+                h.cand_off = segoff.get() + sg;
+                h.ncand = segc.get() + sg;
+                h.out = surv.get() + off[sg];
+                h.nout = cnt.get() + sg;
+                h.tests = tests.get() + sg;
+                h.n = G[g]->cls[c].n;
+                h.n_o = G[g]->cls[1 - c].n;
+            }
+        IG_HIP(hipMemcpyAsync(rowsegs.get(), hr.data(), hr.size(), hipMemcpyHostToDevice, s));
+        IG_HIP(hipMemcpyAsync(cohsegs.get(), hc.data(), hc.size() * sizeof(CohSeg), hipMemcpyHostToDevice, s));
+        IG_HIP(hipStreamSynchronize(s));   // nothing may be in flight on s when capture begins
+    }
+    const uint32_t grid = coherence_grid(tu.grid_per_cu);
+    GraphGuard gg;
+    IG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+        launch_fill_u32(cnt.get(), 0u, nseg + 1, s);
+        launch_fill_u64(reinterpret_cast<uint64_t *>(tests.get()), 0ull, nseg, s);
+        for (uint32_t g = 0; g < G.size(); ++g)
+            for (int c = 0; c < 2; ++c) {
+                const uint32_t sg = 2 * g + c;
+                launch_pair_hash(G[g]->cls[c].X.get(), G[g]->cls[c].n, KS, G[g]->K, 0, G[g]->M[c], sg, segbits,
+                                 k0.get() + off[sg], v0.get() + off[sg], s);
+            }
+        const int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items, 0xffu, s, rws.get());
+        uint64_t *ks = where ? k1.get() : k0.get();
+        uint32_t *vs = where ? v1.get() : v0.get();
+        launch_dedup_flags(ks, vs, items, rowsegs.get(), segbits, flags.get(), nullptr, s);
+        scan_exclusive_u32(flags.get(), pos.get(), items, tot.get(), s, sws.get());
+        launch_seg_counts(ks, items, pos.get(), tot.get(), segbits, nseg, segc.get(), s, segoff.get());
+        launch_compact(flags.get(), pos.get(), vs, items, cand.get(), s);
+        launch_coherence((int)KS, tu.cpl, cohsegs.get(), nseg, 0, max_other, cnt.get() + nseg, grid, s);
+    } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(s, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        throw;
+    }
+    IG_HIP(hipStreamEndCapture(s, &gg.g));
+    IG_HIP(hipGraphInstantiate(&gg.x, gg.g, nullptr, nullptr, 0));
+    hipEvent_t e0, e1;
+    IG_HIP(hipEventCreate(&e0));
+    IG_HIP(hipEventCreate(&e1));
+    IG_HIP(hipEventRecord(e0, s));
+    IG_HIP(hipGraphLaunch(gg.x, s));
+    IG_HIP(hipEventRecord(e1, s));
+    IG_HIP(hipStreamSynchronize(s));
+    float graph_ms = 0;
+    (void)hipEventElapsedTime(&graph_ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::vector<uint32_t> hdist = host_read_u32(segc.get(), nseg, s);
+    std::vector<uint32_t> hsurv = host_read_u32(cnt.get(), nseg, s);
+    std::vector<unsigned long long> htests(nseg);
+    IG_HIP(hipMemcpyAsync(htests.data(), tests.get(), nseg * 8, hipMemcpyDeviceToHost, s));
+    IG_HIP(hipStreamSynchronize(s));
+    for (uint32_t g = 0; g < G.size(); ++g) {
+        DevModel &m = *G[g]->m;
+        const Tuning tp = tuning_for(opts, KS, G[g]->pairs());
+        Timer tm(s);
+        tm.mark(4);
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t sg = 2 * g + c;
+            m.stats.n_class[c] = G[g]->cls[c].n;
+            m.stats.pairs[c] = G[g]->M[c] - G[g]->cls[c].n;
+            m.stats.distinct[c] = hdist[sg];
+            m.stats.tests[c] = htests[sg];
+            m.stats.chunks[c] = G[g]->M[c] ? 1 : 0;
+            order_and_weigh(m, c, G[g]->cls[c], surv.get() + off[sg], hsurv[sg], false, tp, s, &tm,
+                            c == 0 ? 5 : 8);
+            m.stats.coherent[c] = m.np[c];
+            m.stats.support_tests[c] = m.np[c] * (uint64_t)G[g]->cls[c].n;
+            if (c == 0) tm.mark(3);
+        }
+        tm.mark(6);
+        finish_weights(m, s);
+        tm.mark(7);
+        IG_HIP(hipStreamSynchronize(s));
+        record_times(m, tm);
+        // the group's captured stages, split by this problem's share of the pairs
+        const double share = group_pairs ? (double)G[g]->pairs() / (double)group_pairs : 0.0;
+        m.stats.ms[4] = (float)(graph_ms * share);
+        m.stats.ms[1] = m.stats.ms[2] = m.stats.ms[3] = 0.0f;
+    }
+}
+
+void fit_batch(const ig_problem *probs, uint32_t np, const ig_fit_opts *opts, hipStream_t user,
+               std::vector<DevModel *> &out) {
+    std::vector<BProb> P(np);
+    for (uint32_t p = 0; p < np; ++p) {
+        BProb &b = P[p];
+        uint32_t L, K;
+        check_nbins(probs[p].h_nbins, probs[p].d, L, K);
+        IG_REQUIRE(probs[p].n == 0 || (probs[p].d_codes && probs[p].d_labels), IG_E_INVAL,
+                   "problem " + std::to_string(p) + ": codes or labels is NULL");
+        b.n = probs[p].n;
+        b.d = probs[p].d;
+        b.L = L;
+        b.K = K;
+        b.KS = (uint32_t)storage_words((int)K);
+        b.codes = probs[p].d_codes;
+        b.labels = probs[p].d_labels;
+        b.nbins = probs[p].h_nbins;
+    }
+    IG_HIP(hipStreamSynchronize(user));   // inputs produced on the caller's stream are complete
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    hipStream_t s = internal_stream();
+    // validate, split and pack every problem (one synchronisation for all checks)
+    for (auto &b : P) {
+        b.m.reset(new_model());
+        b.m->K = b.K;
+        b.m->KS = b.KS;
+        b.m->L = b.L;
+        b.m->d = b.d;
+        std::vector<uint32_t> tab = token_tables(b.nbins, b.d, b.KS);
+        b.m->meta = dev_alloc<uint32_t>(tab.size());
+        b.m->nbins = dev_alloc<uint16_t>(b.d);
+        IG_HIP(hipMemcpyAsync(b.m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
+        IG_HIP(hipMemcpyAsync(b.m->nbins, b.nbins, b.d * 2, hipMemcpyHostToDevice, s));
+        IG_HIP(hipStreamSynchronize(s));   // the host table must outlive its copy
+        b.err.reset(1, s);
+        b.pos.reset(b.n ? b.n : 1, s);
+        b.counts.reset(2, s);
+        launch_fill_u32(b.err.get(), 0u, 1, s);
+        launch_fill_u32(b.counts.get(), 0u, 2, s);
+        launch_validate_codes(b.codes, (size_t)b.n * b.d, b.d, b.m->nbins, b.err.get(), s);
+        if (b.n) launch_split_labels(b.labels, b.n, b.pos.get(), b.counts.get(), b.err.get(), s);
+    }
+    std::vector<uint32_t> herr(np), hcnt(2 * (size_t)np);
+    for (uint32_t p = 0; p < np; ++p) {
+        IG_HIP(hipMemcpyAsync(&herr[p], P[p].err.get(), 4, hipMemcpyDeviceToHost, s));
+        IG_HIP(hipMemcpyAsync(&hcnt[2 * p], P[p].counts.get(), 8, hipMemcpyDeviceToHost, s));
+    }
+    IG_HIP(hipStreamSynchronize(s));
+    for (uint32_t p = 0; p < np; ++p) {
+        IG_REQUIRE(!(herr[p] & 1u), IG_E_INVAL, "problem " + std::to_string(p) + ": a code is not below its bin count");
+        IG_REQUIRE(!(herr[p] & 2u), IG_E_INVAL, "problem " + std::to_string(p) + ": a label is not 0 or 1");
+        IG_REQUIRE(hcnt[2 * p] <= 92000 && hcnt[2 * p + 1] <= 92000, IG_E_UNSUPPORTED,
+                   "problem " + std::to_string(p) + ": more than 92,000 training records in one class");
+    }
+    for (uint32_t p = 0; p < np; ++p) {
+        BProb &b = P[p];
+        alloc_class_rows(b.cls, &hcnt[2 * p], b.KS, s);
+        launch_pack_split(b.codes, b.labels, b.n, b.d, b.KS, b.m->meta, b.pos.get(), b.cls[0].X.get(),
+                          b.cls[1].X.get(), b.cls[0].NX.get(), b.cls[1].NX.get(), s);
+        for (int c = 0; c < 2; ++c) {
+            const uint64_t n = b.cls[c].n;
+            b.M[c] = n + n * (n ? n - 1 : 0) / 2;
+        }
+    }
+    // groups: same storage width, at most 64 problems, bounded scratch
+    uint64_t group_items = 1ull << 30;
+    if (opts && opts->mem_budget_bytes) group_items = std::max<uint64_t>(opts->mem_budget_bytes / 40, 4096);
+    std::vector<uint32_t> order(np);
+    for (uint32_t p = 0; p < np; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return P[a].KS < P[b].KS; });
+    std::vector<BProb *> G;
+    uint64_t G_items = 0;
+    auto flush = [&]() {
+        if (!G.empty()) run_group(G, opts, s);
+        G.clear();
+        G_items = 0;
+    };
+    for (uint32_t idx : order) {
+        BProb &b = P[idx];
+        const uint64_t it = b.M[0] + b.M[1];
+        if (it > group_items) {   // on its own, with the plain (chunking) path
+            Timer tm(s);
+            tm.mark(0);
+            fit_from_rows(*b.m, b.cls, opts, s, tm);
+            record_times(*b.m, tm);
+            continue;
+        }
+        if (!G.empty() && (G[0]->KS != b.KS || G.size() == 64 || G_items + it > group_items)) flush();
+        G.push_back(&b);
+        G_items += it;
+    }
+    flush();
+    IG_HIP(hipStreamSynchronize(s));
+    for (auto &b : P) out.push_back(b.m.release());
+}
 }  // namespace ig
 
 // ===================================================================== C ABI ====
@@ -673,9 +965,7 @@ ig_status ig_fit_batch(const ig_problem *probs, uint32_t n_probs, const ig_fit_o
         IG_REQUIRE(outs != nullptr && (n_probs == 0 || probs != nullptr), IG_E_INVAL, "NULL argument");
         std::vector<DevModel *> made;
         try {
-            for (uint32_t p = 0; p < n_probs; ++p)
-                made.push_back(ig::fit_codes(probs[p].d_codes, probs[p].d_labels, probs[p].n, probs[p].d,
-                                             probs[p].h_nbins, opts, (hipStream_t)stream));
+            ig::fit_batch(probs, n_probs, opts, (hipStream_t)stream, made);
         } catch (...) {
             for (auto *m : made) delete m;
             throw;
@@ -691,6 +981,21 @@ ig_status ig_fit_batch(const ig_problem *probs, uint32_t n_probs, const ig_fit_o
             throw ig::Error(IG_E_NOMEM, "host allocation failed");
         }
         for (uint32_t p = 0; p < n_probs; ++p) outs[p] = w[p];
+    });
+}
+
+ig_status ig_model_digest(const ig_model *m, uint32_t cls, uint64_t *out) {
+    return guarded([&] {
+        check_model(m);
+        IG_REQUIRE(cls <= 1 && out, IG_E_INVAL, "class must be 0 or 1 and out non-NULL");
+        const DevModel &M = *m->m;
+        hipStream_t s = nullptr;
+        ig::Scratch<unsigned long long> d(1, s);
+        ig::launch_digest(M.W[cls], M.f[cls], M.S[cls], M.np[cls], M.KS, M.K, d.get(), s);
+        unsigned long long h = 0;
+        IG_HIP(hipMemcpyAsync(&h, d.get(), 8, hipMemcpyDeviceToHost, s));
+        IG_HIP(hipStreamSynchronize(s));
+        *out = h;
     });
 }
 

@@ -103,14 +103,19 @@ __device__ __forceinline__ void decode_pair(uint64_t q, uint32_t n, uint32_t &i,
 void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 
-// exclusive prefix sum of n u32 values (out may alias in); total written to *d_total if non-null
-void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, hipStream_t s);
+// exclusive prefix sum of n u32 values (out may alias in); total written to *d_total if
+// non-null.  ws: scan_ws_size(n) u32 of scratch, or null to allocate it on the stream.
+size_t scan_ws_size(size_t n);
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, hipStream_t s,
+                        uint32_t *ws = nullptr);
 
-// LSD radix sort of (key, val) pairs on the bit range [lo_bit, hi_bit) of the keys,
-// 8 bits per pass, stable.  Ping-pongs between (k0,v0) and (k1,v1); returns 0 when
-// the result is in (k0,v0), 1 when in (k1,v1).  digit_mask bit p set = pass p
-// (bits [8p, 8p+8)) must run; clear bits mark digits known to be constant.
+// Stable LSD radix sort of (u64 key, u32 val) pairs, 8 bits per pass.  Ping-pongs
+// between (k0,v0) and (k1,v1); returns 0 when the result is in (k0,v0), 1 when in
+// (k1,v1).  digit_mask bit p set = pass p (bits [8p, 8p+8)) runs; clear bits mark
+// digits known to be constant.  ws: radix_ws_size(n) u32 of scratch, or null to
+// allocate it on the stream (a captured sequence must pass it).
+size_t radix_ws_size(size_t n);
 int radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, size_t n,
-                     uint32_t digit_mask, hipStream_t s);
+                     uint32_t digit_mask, hipStream_t s, uint32_t *ws = nullptr);
 
 }  // namespace ig

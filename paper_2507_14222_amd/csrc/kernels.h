@@ -27,7 +27,7 @@ void launch_dedup_flags(const uint64_t *keys, const uint32_t *vals, size_t m, co
                         uint32_t *flags, uint32_t *seg_counts, hipStream_t s);
 // distinct candidates per segment from the exclusive scan `pos` (and its total)
 void launch_seg_counts(const uint64_t *keys, size_t m, const uint32_t *pos, const uint32_t *total, int segbits,
-                       uint32_t nseg, uint32_t *seg_counts, hipStream_t s);
+                       uint32_t nseg, uint32_t *seg_counts, hipStream_t s, uint32_t *seg_offsets = nullptr);
 void launch_compact(const uint32_t *flags, const uint32_t *pos, const uint32_t *vals, size_t m, uint32_t *out,
                     hipStream_t s);
 void launch_gather_word(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t k, const uint32_t *ids, size_t m,
@@ -53,6 +53,7 @@ struct CohSeg {                 // one (problem, class) for one coherence phase
     const uint64_t *X;          // class rows [n][KS]
     const uint64_t *NXo;        // complemented other-class rows [n_o][KS]
     const uint32_t *cand;       // input: candidate pair ids still uncovered
+    const uint32_t *cand_off;   // if non-null, the ids start at cand + *cand_off
     const uint32_t *ncand;      // device count of cand
     uint32_t *out;              // output: ids uncovered by this phase (appended)
     uint32_t *nout;             // device counter of out
@@ -64,7 +65,11 @@ struct CohSeg {                 // one (problem, class) for one coherence phase
 // pulled from `queue` (zeroed by the launcher).
 void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, uint32_t r_begin, uint32_t r_end,
                       uint32_t *queue, uint32_t grid, hipStream_t s);
-uint32_t coherence_grid(int KS, int cpl);
+// persistent grid of the coherence kernel: grid_per_cu workgroups per compute unit
+uint32_t coherence_grid(uint32_t grid_per_cu);
+// order-dependent digest of rows [m][KS] (first K words), f and S
+void launch_digest(const uint64_t *W, const uint32_t *f, const int64_t *S, size_t m, uint32_t KS, uint32_t K,
+                   unsigned long long *out, hipStream_t s);
 
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented
 // rows NX [n][KS] of their class.

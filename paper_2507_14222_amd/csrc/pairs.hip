@@ -95,7 +95,7 @@ __global__ void k_dedup_flags(const uint64_t *__restrict__ keys, const uint32_t 
 // contiguous range, found by binary search (no atomics).
 __global__ void k_seg_counts(const uint64_t *__restrict__ keys, size_t m, const uint32_t *__restrict__ pos,
                              const uint32_t *__restrict__ total, int segbits, uint32_t nseg,
-                             uint32_t *__restrict__ seg_counts) {
+                             uint32_t *__restrict__ seg_counts, uint32_t *__restrict__ seg_offsets) {
     uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nseg) return;
     auto lower = [&](uint64_t v) -> size_t {   // first index with key >= v
@@ -113,6 +113,7 @@ __global__ void k_seg_counts(const uint64_t *__restrict__ keys, size_t m, const 
     const uint32_t pa = ia < m ? pos[ia] : *total;
     const uint32_t pb = ib < m ? pos[ib] : *total;
     seg_counts[s] = pb - pa;
+    if (seg_offsets) seg_offsets[s] = pa;
 }
 
 __global__ void k_compact(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
@@ -256,14 +257,15 @@ void launch_dedup_flags(const uint64_t *keys, const uint32_t *vals, size_t m, co
 }
 
 void launch_seg_counts(const uint64_t *keys, size_t m, const uint32_t *pos, const uint32_t *total, int segbits,
-                       uint32_t nseg, uint32_t *seg_counts, hipStream_t s) {
+                       uint32_t nseg, uint32_t *seg_counts, hipStream_t s, uint32_t *seg_offsets) {
     if (!nseg) return;
     if (!m) {
         launch_fill_u32(seg_counts, 0u, nseg, s);
+        if (seg_offsets) launch_fill_u32(seg_offsets, 0u, nseg, s);
         return;
     }
     hipLaunchKernelGGL(k_seg_counts, dim3((nseg + 63) / 64), dim3(64), 0, s, keys, m, pos, total, segbits, nseg,
-                       seg_counts);
+                       seg_counts, seg_offsets);
     IG_HIP(hipGetLastError());
 }
 

@@ -102,7 +102,17 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_tiles(const uint32_t *in, uint3
     if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) *d_total = run;
 }
 
-void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, hipStream_t s) {
+size_t scan_ws_size(size_t n) {
+    size_t total = 0;
+    while (n > (size_t)SCAN_TILE) {
+        n = (n + SCAN_TILE - 1) / SCAN_TILE;
+        total += n;
+    }
+    return total + 1;
+}
+
+static void scan_with_ws(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, uint32_t *ws,
+                         hipStream_t s) {
     if (n == 0) {
         if (d_total) launch_fill_u32(d_total, 0, 1, s);
         return;
@@ -114,13 +124,23 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d
         IG_HIP(hipGetLastError());
         return;
     }
-    Scratch<uint32_t> sums(tiles, s);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, in, n, sums.get());
+    uint32_t *sums = ws;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, in, n, sums);
     IG_HIP(hipGetLastError());
-    scan_exclusive_u32(sums.get(), sums.get(), tiles, nullptr, s);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, in, out, n,
-                       (const uint32_t *)sums.get(), d_total);
+    scan_with_ws(sums, sums, tiles, nullptr, ws + tiles, s);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, in, out, n, (const uint32_t *)sums,
+                       d_total);
     IG_HIP(hipGetLastError());
+}
+
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, hipStream_t s,
+                        uint32_t *ws) {
+    if (ws) {
+        scan_with_ws(in, out, n, d_total, ws, s);
+        return;
+    }
+    Scratch<uint32_t> own(scan_ws_size(n), s);
+    scan_with_ws(in, out, n, d_total, own.get(), s);
 }
 
 // ------------------------------------------------------------- radix sort ----
@@ -197,24 +217,33 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t *__restrict_
     }
 }
 
+size_t radix_ws_size(size_t n) {
+    const size_t tiles = (n + RS_TILE - 1) / RS_TILE;
+    return tiles * 256 + scan_ws_size(tiles * 256);
+}
+
 int radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, size_t n, uint32_t digit_mask,
-                     hipStream_t s) {
+                     hipStream_t s, uint32_t *ws) {
     if (n <= 1 || digit_mask == 0) return 0;
     IG_REQUIRE(n < (1ull << 32), IG_E_UNSUPPORTED, "radix sort of more than 2^32 elements");
-    size_t tiles = (n + RS_TILE - 1) / RS_TILE;
-    Scratch<uint32_t> hist(tiles * 256, s);
+    const size_t tiles = (n + RS_TILE - 1) / RS_TILE;
+    Scratch<uint32_t> own;
+    if (!ws) {
+        own.reset(radix_ws_size(n), s);
+        ws = own.get();
+    }
+    uint32_t *hist = ws, *scan_ws = ws + tiles * 256;
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
     int cur = 0;
     for (int pass = 0; pass < 8; ++pass) {
         if (!((digit_mask >> pass) & 1u)) continue;
         int shift = pass * 8;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(RS_T), 0, s, ka, n, shift, hist.get(),
-                           (uint32_t)tiles);
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(RS_T), 0, s, ka, n, shift, hist, (uint32_t)tiles);
         IG_HIP(hipGetLastError());
-        scan_exclusive_u32(hist.get(), hist.get(), tiles * 256, nullptr, s);
+        scan_exclusive_u32(hist, hist, tiles * 256, nullptr, s, scan_ws);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(RS_T), 0, s, ka, va, kb, vb, n, shift,
-                           (const uint32_t *)hist.get(), (uint32_t)tiles);
+                           (const uint32_t *)hist, (uint32_t)tiles);
         IG_HIP(hipGetLastError());
         std::swap(ka, kb);
         std::swap(va, vb);

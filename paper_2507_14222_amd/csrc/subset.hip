@@ -134,6 +134,7 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
         }
         sg = uniform(sg);
         const CohSeg g = segs[sg];
+        const uint32_t *cand = g.cand + (g.cand_off ? uniform(*g.cand_off) : 0u);
         const uint32_t base = (t - first) * PER_TASK;
         const uint32_t n_o = g.n_o;
         const uint32_t rb = r_begin < n_o ? r_begin : n_o;
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
         for (int c = 0; c < CPL; ++c) {
             const uint32_t idx = base + c * 64 + lane;
             const bool act = idx < ncand;
-            pid[c] = act ? ((const __attribute__((address_space(1))) uint32_t *)(const void *)g.cand)[idx] : 0u;
+            pid[c] = act ? ((const __attribute__((address_space(1))) uint32_t *)(const void *)cand)[idx] : 0u;
             uint32_t i = 0, j = 0;
             if (act) decode_pair(pid[c], g.n, i, j);
             gptr32 ra = global_rows(g.X + (size_t)i * KS);
@@ -394,9 +395,7 @@ int storage_words(int K) {
     return -1;
 }
 
-uint32_t coherence_grid(int KS, int cpl) {
-    (void)KS;
-    (void)cpl;
+uint32_t coherence_grid(uint32_t grid_per_cu) {
     static int cached[64] = {0};
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
@@ -409,7 +408,9 @@ uint32_t coherence_grid(int KS, int cpl) {
         }
         cus = cached[dev];
     }
-    return (uint32_t)cus * 8u;   // persistent: 8 workgroups (32 waves) per CU
+    if (grid_per_cu < 1) grid_per_cu = 1;
+    if (grid_per_cu > 32) grid_per_cu = 32;
+    return (uint32_t)cus * grid_per_cu;   // persistent workgroups of 4 waves
 }
 
 void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, uint32_t r_begin, uint32_t r_end,
@@ -508,6 +509,45 @@ void launch_score(const ScoreModel &m, const uint16_t *codes, const uint64_t *wo
         default: throw Error(IG_E_UNSUPPORTED, "unsupported word count");
     }
 #undef IG_SC
+    IG_HIP(hipGetLastError());
+}
+
+// Digest: sum over rows e of mix(e, row words, f, S).  Addition modulo 2^64 makes the
+// result independent of thread order; mixing in e makes it depend on row order.
+__device__ __forceinline__ uint64_t dmix(uint64_t h) {
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    h *= 0xc4ceb9fe1a85ec53ull;
+    h ^= h >> 33;
+    return h;
+}
+
+__global__ __launch_bounds__(256) void k_digest(const uint64_t *__restrict__ W, const uint32_t *__restrict__ f,
+                                               const int64_t *__restrict__ S, size_t m, uint32_t KS, uint32_t K,
+                                               unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long part[4];
+    unsigned long long acc = 0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+        uint64_t h = dmix(e + 0x9e3779b97f4a7c15ull);
+        for (uint32_t k = 0; k < K; ++k) h = dmix(h ^ W[e * KS + k]);
+        h = dmix(h ^ f[e]);
+        h = dmix(h ^ (uint64_t)S[e]);
+        acc += h;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+void launch_digest(const uint64_t *W, const uint32_t *f, const int64_t *S, size_t m, uint32_t KS, uint32_t K,
+                   unsigned long long *out, hipStream_t s) {
+    launch_fill_u64(reinterpret_cast<uint64_t *>(out), 0ull, 1, s);
+    if (!m) return;
+    unsigned g = (unsigned)((m + 255) / 256);
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(k_digest, dim3(g), dim3(256), 0, s, W, f, S, m, KS, K, out);
     IG_HIP(hipGetLastError());
 }
 

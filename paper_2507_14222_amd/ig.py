@@ -28,9 +28,15 @@ class IGError(RuntimeError):
         self.status = status
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("ks", C.c_uint32), ("min_pairs", C.c_uint32), ("filter_cpl", C.c_uint32),
+                ("grid_per_cu", C.c_uint32), ("support_cpl", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+
+
 class FitOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_uint64), ("filter_cpl", C.c_uint32), ("score_fpl", C.c_uint32),
-                ("block", C.c_uint32), ("reserved", C.c_uint32 * 5)]
+                ("block", C.c_uint32), ("n_tune", C.c_uint32), ("tune", C.POINTER(TuneEntry)),
+                ("reserved", C.c_uint32 * 2)]
 
 
 class Stats(C.Structure):
@@ -53,7 +59,8 @@ _lib = None
 
 # every symbol include/ig.h declares
 EXPORTS = ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_packed", "ig_model_get_info",
-           "ig_model_export", "ig_model_import", "ig_fit_stats", "ig_model_free", "ig_last_error", "ig_version")
+           "ig_model_export", "ig_model_import", "ig_model_digest", "ig_fit_stats", "ig_model_free",
+           "ig_last_error", "ig_version")
 
 
 def lib():
@@ -74,12 +81,13 @@ def lib():
     L.ig_model_export.argtypes = [vp, u32, vp, vp, vp]
     L.ig_model_import.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(u64), u32, vp, vp, C.POINTER(vp)]
     L.ig_fit_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.ig_model_digest.argtypes = [vp, u32, C.POINTER(u64)]
     L.ig_model_free.argtypes = [vp]
     L.ig_model_free.restype = None
     L.ig_last_error.restype = C.c_char_p
     L.ig_version.restype = C.c_char_p
     for name in ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_packed", "ig_model_get_info",
-                 "ig_model_export", "ig_model_import", "ig_fit_stats"):
+                 "ig_model_export", "ig_model_import", "ig_model_digest", "ig_fit_stats"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -127,11 +135,20 @@ def _np_u16(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.uint16)
 
 
-def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0) -> FitOpts:
+def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tune=None) -> FitOpts:
+    """Fit options; `tune` is a list of dicts with the fields of ig_tune_entry."""
     o = FitOpts()
     o.mem_budget_bytes = int(mem_budget_bytes)
     o.filter_cpl = int(filter_cpl)
     o.score_fpl = int(score_fpl)
+    if tune:
+        arr = (TuneEntry * len(tune))()
+        for i, e in enumerate(tune):
+            for k in ("ks", "min_pairs", "filter_cpl", "grid_per_cu", "support_cpl"):
+                setattr(arr[i], k, int(e.get(k, 0)))
+        o.n_tune = len(tune)
+        o.tune = C.cast(arr, C.POINTER(TuneEntry))
+        o._keep = arr   # keep the table alive with the options
     return o
 
 
@@ -190,6 +207,12 @@ class Model:
         _check(lib().ig_model_export(self.handle, cls, ptr(w), ptr(f), ptr(S)))
         return w, f, S
 
+    def digest(self, cls: int) -> int:
+        """Device-computed digest of class ``cls`` (rows, f, S in canonical order)."""
+        h = C.c_uint64()
+        _check(lib().ig_model_digest(self.handle, cls, C.byref(h)))
+        return int(h.value)
+
     def free(self) -> None:
         if self._h:
             lib().ig_model_free(self._h)
@@ -202,7 +225,7 @@ class Model:
             pass
 
 
-def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, stream=None) -> Model:
+def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tune=None, stream=None) -> Model:
     """ig_fit: codes [n, d] bin codes, labels [n] (0 normal / 1 attack), nbins [d]."""
     torch = _torch()
     dc = _dev(codes, torch.int16)
@@ -210,7 +233,7 @@ def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, st
     n, d = (int(dc.shape[0]), int(dc.shape[1])) if dc.dim() == 2 else (0, 0)
     nb = _np_u16(nbins)
     h = C.c_void_p()
-    o = _opts(mem_budget_bytes, filter_cpl)
+    o = _opts(mem_budget_bytes, filter_cpl, tune=tune)
     _check(lib().ig_fit(C.c_void_p(dc.data_ptr()), C.c_void_p(dl.data_ptr()), n, d or nb.size,
                         C.c_void_p(nb.ctypes.data), C.byref(o), _stream_handle(stream), C.byref(h)))
     return Model(h)
@@ -230,7 +253,7 @@ def fit_packed(words, labels, mem_budget_bytes: int = 0, stream=None) -> Model:
     return Model(h)
 
 
-def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, stream=None) -> List[Model]:
+def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, tune=None, stream=None) -> List[Model]:
     """ig_fit_batch over problems with attributes codes, labels, nbins."""
     torch = _torch()
     keep = []
@@ -246,7 +269,7 @@ def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, stream=None) -> Lis
         arr[p].d = int(nb.size)
         arr[p].h_nbins = nb.ctypes.data
     outs = (C.c_void_p * len(problems))()
-    o = _opts(mem_budget_bytes)
+    o = _opts(mem_budget_bytes, tune=tune)
     _check(lib().ig_fit_batch(arr, len(problems), C.byref(o), _stream_handle(stream), outs))
     return [Model(C.c_void_p(outs[p])) for p in range(len(problems))]
 

@@ -94,6 +94,10 @@ class Server:
 
     def __init__(self, model: Optional[ig.Model], n_slots: int = 4, max_batch_flows: int = 16384,
                  mem_budget_bytes: int = 0, d: Optional[int] = None, executor=None):
+        import sys
+        # the dispatcher shares the interpreter with the callers: hand the lock over often
+        if sys.getswitchinterval() > 0.0005:
+            sys.setswitchinterval(0.0005)
         if model is not None:
             info = model.info()
             if info.d == 0:
@@ -251,8 +255,9 @@ def drive(server: Server, requests: Sequence[np.ndarray], arrivals: Sequence[flo
             now = time.perf_counter()
             if now >= target:
                 break
-            if target - now > 0.002:
-                time.sleep(target - now - 0.001)
+            # sleep rather than spin: a spinning thread would hold the interpreter
+            # lock against the dispatcher for a whole switch interval
+            time.sleep(min(target - now, 0.0002))
         futs.append(server.submit(codes, t_arrival=target))
     return futs, t0
 

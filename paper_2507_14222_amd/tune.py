@@ -1,0 +1,95 @@
+"""Autotuner for the launch shapes of libig's fit kernels.
+
+For each storage width KS and problem-size bucket it fits a seeded synthetic
+problem of that width and size with every candidate shape and keeps the fastest
+(coherence: candidates per lane x workgroups per CU, timed by the library's own
+event pair around the coherence launch; support: patterns per lane, timed by its
+event pair).  The result is a table of ig_tune_entry rows, cached as JSON and
+passed to ig_fit / ig_fit_batch.  Tuning never changes results.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, List, Optional
+
+import numpy as np
+
+from . import ig, synth
+
+COHERENCE_SHAPES = [(cpl, g) for cpl in (1, 2) for g in (4, 8, 16)]
+SUPPORT_CPL = (1, 2)
+
+
+def _problem_for(ks: int, n: int, seed: int) -> synth.Problem:
+    """A Dirichlet(0.5) problem whose token universe needs exactly `ks` storage words."""
+    rng = np.random.default_rng(seed)
+    target_L = max(2, 64 * ks - 32)            # inside the width bucket
+    d = int(np.clip(target_L // 16, 2, 80))
+    nbins = np.full(d, target_L // d)
+    nbins[: target_L - int(nbins.sum())] += 1
+    return synth.make_problem(rng, n, d, nbins.astype(np.int64), 0.5)
+
+
+def _time(p, tune, reps: int):
+    best_c = best_s = float("inf")
+    for _ in range(reps):
+        m = ig.fit(p.codes, p.labels, p.nbins, tune=tune)
+        st = m.stats()
+        best_c = min(best_c, st.ms[4])
+        best_s = min(best_s, st.ms[6])
+        m.free()
+    return best_c, best_s
+
+
+def autotune(widths: Iterable[int], sizes=(1200, 5000), reps: int = 2, seed: int = 7) -> Dict:
+    """Measure every shape on each (width, size) bucket; returns the table and the timings."""
+    entries: List[Dict] = []
+    measured = []
+    for ks in sorted(set(int(w) for w in widths)):
+        for n in sizes:
+            p = _problem_for(ks, n, seed + ks * 1000 + n)
+            n1 = int(p.labels.sum())
+            n0 = p.n - n1
+            pairs = n0 * (n0 - 1) // 2 + n1 * (n1 - 1) // 2
+            rows = []
+            for cpl, g in COHERENCE_SHAPES:
+                for scpl in SUPPORT_CPL:
+                    t = [{"ks": ks, "min_pairs": 0, "filter_cpl": cpl, "grid_per_cu": g, "support_cpl": scpl}]
+                    c_ms, s_ms = _time(p, t, reps)
+                    rows.append((cpl, g, scpl, c_ms, s_ms))
+            best_coh = min(rows, key=lambda r: r[3])
+            best_sup = min(rows, key=lambda r: r[4])
+            lo = 0 if n == min(sizes) else pairs
+            entries.append({"ks": ks, "min_pairs": int(lo), "filter_cpl": best_coh[0],
+                            "grid_per_cu": best_coh[1], "support_cpl": best_sup[2]})
+            measured.append({"ks": ks, "n": n, "pairs": int(pairs),
+                             "shapes": [dict(zip(("filter_cpl", "grid_per_cu", "support_cpl", "coherence_ms",
+                                                  "support_ms"), r)) for r in rows]})
+    return {"arch": "gfx950", "entries": entries, "measured": measured}
+
+
+def save(table: Dict, path: str) -> None:
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1)
+
+
+def load(path: str) -> Optional[List[Dict]]:
+    """Tuning rows from a cache file, or None when there is none."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    return t.get("entries")
+
+
+def widths_of(problems) -> List[int]:
+    return sorted(set(ig_storage_words((p.L + 63) // 64) for p in problems))
+
+
+def ig_storage_words(K: int) -> int:
+    """The compiled storage width that holds K words (same rule as the library)."""
+    for v in (1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64):
+        if K <= v:
+            return v
+    raise ValueError("K beyond 64")
