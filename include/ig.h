@@ -83,7 +83,13 @@ typedef struct {
     uint32_t block;             /* reserved (workgroups are 256 threads)              */
     uint32_t n_tune;            /* rows in `tune`                                     */
     const ig_tune_entry *tune;  /* host tuning table (may be NULL)                    */
-    uint32_t reserved[2];
+    uint32_t coherence_mfma;    /* 1: coherence as a dense 0/1 contraction on the
+                                   matrix cores (fp4 operands, fp32 accumulation;
+                                   exact; K <= 8 words).  Same patterns; no early
+                                   exit, so ig_stats.tests counts every pair of
+                                   candidate and other-class record.  0: the VALU
+                                   path with early exit (default).                  */
+    uint32_t reserved;
 } ig_fit_opts;
 
 /* Counters and timings of a fit (Section 3.3 stages). */

@@ -347,6 +347,15 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         IG_HIP(hipStreamSynchronize(s));
     }
     const uint32_t grid = coherence_grid(tu.grid_per_cu);
+    const bool use_mfma = opts && opts->coherence_mfma == 1;
+    IG_REQUIRE(!use_mfma || KS <= 8, IG_E_UNSUPPORTED, "the matrix-core coherence path handles up to 8 words");
+    Scratch<uint4> frag[2];   // per class c: the other class's records as the A operand
+    uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
+    if (use_mfma)
+        for (int c = 0; c < 2; ++c) {
+            frag[c].reset(std::max<size_t>((size_t)mfma_record_tiles(cls[1 - c].n) * KS * 64, 1), s);
+            launch_mfma_records(cls[1 - c].NX.get(), cls[1 - c].n, KS, frag[c].get(), s);
+        }
     float ms_pairs = 0, ms_sort = 0, ms_dedup = 0, ms_coh = 0;
     hipEvent_t e[5];
     for (auto &x : e) IG_HIP(hipEventCreate(&x));
@@ -392,14 +401,35 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         // grow the survivor buffers to hold every candidate of this chunk
         for (int c = 0; c < 2; ++c) {
             distinct[c] += hc[c];
-            size_t need = (size_t)hn[c] + hc[c];
+            const size_t have = use_mfma ? (size_t)mfma_surv[c] : (size_t)hn[c];
+            size_t need = have + hc[c];
             if (need > surv_cap[c]) {
                 size_t cap = std::max<size_t>(need, surv_cap[c] * 3 / 2);
                 Scratch<uint32_t> nb(cap, s);
-                if (hn[c]) IG_HIP(hipMemcpyAsync(nb.get(), surv[c].get(), (size_t)hn[c] * 4, hipMemcpyDeviceToDevice, s));
+                if (have) IG_HIP(hipMemcpyAsync(nb.get(), surv[c].get(), have * 4, hipMemcpyDeviceToDevice, s));
                 surv[c] = std::move(nb);
                 surv_cap[c] = cap;
             }
+        }
+        if (use_mfma) {
+            IG_HIP(hipEventRecord(e[3], s));
+            for (int c = 0; c < 2; ++c) {
+                if (!hc[c]) continue;
+                Scratch<uint32_t> keep(hc[c], s), kpos(hc[c], s), ktot(1, s);
+                uint32_t *cc = cand.get() + (c == 0 ? 0 : hc[0]);
+                launch_coherence_mfma((int)KS, cc, hc[c], cls[c].X.get(), cls[c].n, frag[c].get(), cls[1 - c].n,
+                                      keep.get(), s);
+                scan_exclusive_u32(keep.get(), kpos.get(), hc[c], ktot.get(), s);
+                launch_compact(keep.get(), kpos.get(), cc, hc[c], surv[c].get() + mfma_surv[c], s);
+                mfma_surv[c] += host_read_u32(ktot.get(), 1, s)[0];
+                mfma_tests[c] += (uint64_t)hc[c] * cls[1 - c].n;
+            }
+            IG_HIP(hipEventRecord(e[4], s));
+            IG_HIP(hipStreamSynchronize(s));
+            float tm34;
+            IG_HIP(hipEventElapsedTime(&tm34, e[3], e[4]));
+            ms_coh += tm34;
+            continue;
         }
         // coherence in phases over the other class's records (input order); the
         // uncovered ids ping-pong between the de-duplication output and `alt`
@@ -466,6 +496,11 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     unsigned long long ht[2];
     IG_HIP(hipMemcpyAsync(ht, tests.get(), sizeof(ht), hipMemcpyDeviceToHost, s));
     IG_HIP(hipStreamSynchronize(s));
+    if (use_mfma)
+        for (int c = 0; c < 2; ++c) {
+            hn[c] = (uint32_t)mfma_surv[c];
+            ht[c] = mfma_tests[c];
+        }
     for (int c = 0; c < 2; ++c) {
         m.stats.distinct[c] = distinct[c];
         m.stats.tests[c] = ht[c];

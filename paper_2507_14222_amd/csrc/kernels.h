@@ -71,6 +71,15 @@ uint32_t coherence_grid(uint32_t grid_per_cu);
 void launch_digest(const uint64_t *W, const uint32_t *f, const int64_t *S, size_t m, uint32_t KS, uint32_t K,
                    unsigned long long *out, hipStream_t s);
 
+// Coherence on the matrix cores (fp4 0/1 contraction, dense, KS <= 8): keep[i] =
+// 1 when candidate cand[i] lies in none of the n_o other-class records.  frag is
+// the records' operand layout from launch_mfma_records (mfma_record_tiles(n_o) *
+// KS * 64 uint4).
+uint32_t mfma_record_tiles(uint32_t n);
+void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *frag, hipStream_t s);
+void launch_coherence_mfma(int KS, const uint32_t *cand, uint32_t ncand, const uint64_t *X, uint32_t n,
+                           const uint4 *frag, uint32_t n_o, uint32_t *keep, hipStream_t s);
+
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented
 // rows NX [n][KS] of their class.
 void launch_support(int KS, int cpl, const uint64_t *W, size_t m, const uint64_t *NX, uint32_t n, uint32_t *f,

@@ -202,6 +202,114 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
     if (lane == 0 && tests_acc) atomicAdd(tests_at, (unsigned long long)tests_acc);
 }
 
+// ------------------------------------------------ coherence as a contraction ----
+// The coherence test as a dense matrix product on the matrix cores:
+// V[r][b] = sum over tokens of (NOT r)[token] * b[token] counts the tokens of
+// candidate b missing from record r; b is covered when some V is 0 (Eq. 6).  The
+// 0/1 operands are exact in fp4 (e2m1: 1.0 = 0x2) and every V <= 512 is exact in
+// the fp32 accumulators.  One v_mfma_scale_f32_32x32x64_f8f6f4 covers 64 tokens
+// (one 64-bit word): lanes l and l+32 of a row / column supply its two 32-bit
+// halves.  Records are the A operand (rows), candidates the B operand (columns).
+typedef int v8i_t __attribute__((ext_vector_type(8)));
+typedef float v16f_t __attribute__((ext_vector_type(16)));
+
+// 8 bits -> 8 nibbles, bit i -> nibble i = (bit ? 1.0 : 0) in e2m1
+__device__ __forceinline__ uint32_t spread8(uint32_t b) {
+    uint32_t x = b & 0xffu;
+    x = (x | (x << 12)) & 0x000f000fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    x = (x | (x << 3)) & 0x11111111u;
+    return x << 1;
+}
+
+// Other-class records, complemented, in the A-operand layout of each 32-record
+// tile: frag[(tile * KS + word) * 64 + lane] = the 32 nibbles of half (lane/32) of
+// word `word` of record tile*32 + lane%32.  Rows past n are all ones (the empty
+// record), which never contain a candidate.
+__global__ void k_mfma_records(const uint64_t *__restrict__ NX, uint32_t n, uint32_t KS, uint32_t ntiles,
+                               uint4 *__restrict__ frag) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (size_t)ntiles * KS * 64) return;
+    const uint32_t lane = (uint32_t)(g % 64), word = (uint32_t)((g / 64) % KS), tile = (uint32_t)(g / (64 * KS));
+    const uint32_t r = tile * 32 + lane % 32;
+    const uint32_t d = r < n ? (uint32_t)(NX[(size_t)r * KS + word] >> (32 * (lane / 32))) : 0xffffffffu;
+    frag[g] = make_uint4(spread8(d), spread8(d >> 8), spread8(d >> 16), spread8(d >> 24));
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_coherence_mfma(const uint32_t *__restrict__ cand, uint32_t ncand,
+                                                       const uint64_t *__restrict__ X, uint32_t n,
+                                                       const uint4 *__restrict__ frag, uint32_t ntiles,
+                                                       uint32_t *__restrict__ keep) {
+    __shared__ uint4 tile_frag[KS * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
+    const uint32_t cidx = blockIdx.x * 128u + wave * 32u + col;
+    const bool act = cidx < ncand;
+    v8i_t b[KS];
+    {
+        uint32_t i = 0, j = 0;
+        if (act) decode_pair(cand[cidx], n, i, j);
+        const uint32_t *ra = reinterpret_cast<const uint32_t *>(X + (size_t)i * KS);
+        const uint32_t *rb = reinterpret_cast<const uint32_t *>(X + (size_t)j * KS);
+#pragma unroll
+        for (int w = 0; w < KS; ++w) {
+            // inactive columns: all ones, so their result is ignored anyway
+            const uint32_t d = act ? (ra[2 * w + half] & rb[2 * w + half]) : 0xffffffffu;
+            b[w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
+                         0, 0, 0, 0};
+        }
+    }
+    bool covered = false;
+    for (uint32_t t = 0; t < ntiles; ++t) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < KS * 64; q += 256) tile_frag[q] = frag[(size_t)t * KS * 64 + q];
+        __syncthreads();
+        v16f_t acc = {0};
+#pragma unroll
+        for (int w = 0; w < KS; ++w) {
+            const uint4 a4 = tile_frag[w * 64 + lane];
+            const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+            acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[w], acc, 4, 4, 0, 127, 0, 127);
+        }
+        bool z = false;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) z |= acc[r] == 0.0f;
+        covered |= z;
+    }
+    // the two halves of the wave hold different record rows of the same column
+    const uint64_t m = __ballot(covered);
+    const bool col_covered = ((m >> col) & 1ull) | ((m >> (col + 32)) & 1ull);
+    if (half == 0 && act) keep[cidx] = col_covered ? 0u : 1u;
+}
+
+uint32_t mfma_record_tiles(uint32_t n) { return (n + 31) / 32; }
+
+void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *frag, hipStream_t s) {
+    const uint32_t ntiles = mfma_record_tiles(n);
+    const size_t total = (size_t)ntiles * KS * 64;
+    if (!total) return;
+    hipLaunchKernelGGL(k_mfma_records, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, NX, n, KS, ntiles,
+                       frag);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_coherence_mfma(int KS, const uint32_t *cand, uint32_t ncand, const uint64_t *X, uint32_t n,
+                           const uint4 *frag, uint32_t n_o, uint32_t *keep, hipStream_t s) {
+    if (!ncand) return;
+    const dim3 grid((ncand + 127) / 128);
+    const uint32_t ntiles = mfma_record_tiles(n_o);
+#define IG_MF(V)                                                                                             \
+    case V:                                                                                                  \
+        hipLaunchKernelGGL((k_coherence_mfma<V>), grid, dim3(256), 0, s, cand, ncand, X, n, frag, ntiles, keep); \
+        break;
+    switch (KS) {
+        IG_MF(1) IG_MF(2) IG_MF(3) IG_MF(4) IG_MF(5) IG_MF(6) IG_MF(7) IG_MF(8)
+        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core coherence path handles up to 8 words");
+    }
+#undef IG_MF
+    IG_HIP(hipGetLastError());
+}
+
 // -------------------------------------------------------------- support ----
 template <int KS, int CPL>
 __global__ __launch_bounds__(256) void k_support(const uint64_t *__restrict__ Wrows, size_t m,

@@ -36,7 +36,7 @@ class TuneEntry(C.Structure):
 class FitOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_uint64), ("filter_cpl", C.c_uint32), ("score_fpl", C.c_uint32),
                 ("block", C.c_uint32), ("n_tune", C.c_uint32), ("tune", C.POINTER(TuneEntry)),
-                ("reserved", C.c_uint32 * 2)]
+                ("coherence_mfma", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Stats(C.Structure):
@@ -135,9 +135,11 @@ def _np_u16(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.uint16)
 
 
-def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tune=None) -> FitOpts:
+def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tune=None,
+          coherence_mfma: bool = False) -> FitOpts:
     """Fit options; `tune` is a list of dicts with the fields of ig_tune_entry."""
     o = FitOpts()
+    o.coherence_mfma = 1 if coherence_mfma else 0
     o.mem_budget_bytes = int(mem_budget_bytes)
     o.filter_cpl = int(filter_cpl)
     o.score_fpl = int(score_fpl)
@@ -225,7 +227,8 @@ class Model:
             pass
 
 
-def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tune=None, stream=None) -> Model:
+def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tune=None,
+        coherence_mfma: bool = False, stream=None) -> Model:
     """ig_fit: codes [n, d] bin codes, labels [n] (0 normal / 1 attack), nbins [d]."""
     torch = _torch()
     dc = _dev(codes, torch.int16)
@@ -233,7 +236,7 @@ def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tu
     n, d = (int(dc.shape[0]), int(dc.shape[1])) if dc.dim() == 2 else (0, 0)
     nb = _np_u16(nbins)
     h = C.c_void_p()
-    o = _opts(mem_budget_bytes, filter_cpl, tune=tune)
+    o = _opts(mem_budget_bytes, filter_cpl, tune=tune, coherence_mfma=coherence_mfma)
     _check(lib().ig_fit(C.c_void_p(dc.data_ptr()), C.c_void_p(dl.data_ptr()), n, d or nb.size,
                         C.c_void_p(nb.ctypes.data), C.byref(o), _stream_handle(stream), C.byref(h)))
     return Model(h)

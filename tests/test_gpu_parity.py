@@ -324,3 +324,30 @@ def test_148k_workload_sampled():
     A, N = gpu_scores(m, flows)
     oA, oN = oracle.score_direct(w.codes, w.labels, w.nbins, flows)
     assert np.array_equal(A, oA) and np.array_equal(N, oN)
+
+
+# ------------------------------------------- coherence on the matrix cores
+MFMA_CASES = [c for c in CASES if c[0] in (1, 2, 4, 6, 7, 8, 9, 10, 11, 18, 19)]   # K <= 8
+
+
+@pytest.mark.parametrize("case", MFMA_CASES, ids=[f"s{c[0]}" for c in MFMA_CASES])
+def test_matrix_core_coherence_matches_oracle(case):
+    seed, n, d, blo, bhi, af = case
+    p = synth.make_random_problem(seed, n, d, bins_lo=blo, bins_hi=bhi, attack_frac=af)
+    say("mfma coherence", case)
+    om = oracle.fit(p.codes, p.labels, p.nbins)
+    m = ig.fit(p.codes, p.labels, p.nbins, coherence_mfma=True)
+    assert_same_model(m, om, om.K)
+    st = m.stats()
+    assert list(st.coherent) == om.stats["coherent"] and list(st.distinct) == om.stats["distinct"]
+    for c in (0, 1):   # dense: every candidate against every other-class record
+        assert st.tests[c] == om.stats["distinct"][c] * om.stats["n_class"][1 - c]
+
+
+def test_matrix_core_coherence_15k_digest():
+    g = json.load(open(os.path.join(GOLD, "mixture41_15k.json")))
+    w = synth.make_15k()
+    say("mfma coherence 15k")
+    m = ig.fit(w.codes, w.labels, w.nbins, coherence_mfma=True)
+    assert list(m.stats().coherent) == g["stats"]["coherent"]
+    assert _model_digest(m) == g["model_sha256"]
