@@ -203,7 +203,7 @@ struct ClassRows {
 // support and weights.  Fills model class c.
 static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *ids, size_t count,
                             bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
-                            int support_mark = -1) {
+                            int support_mark = -1, const uint4 *own_frag = nullptr) {
     const uint32_t KS = m.KS, K = m.K;
     if (count == 0) {
         m.np[c] = 0;
@@ -259,7 +259,10 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         throw;
     }
     if (tm && support_mark >= 0) tm->mark(support_mark);
-    launch_support((int)KS, tu.support_cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
+    if (own_frag)
+        launch_support_mfma((int)KS, m.W[c], final_count, own_frag, cls.n, m.f[c], m.S[c], s);
+    else
+        launch_support((int)KS, tu.support_cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
 }
 
 static void finish_weights(DevModel &m, hipStream_t s) {
@@ -507,7 +510,9 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     }
     const bool chunked = chunks.size() > 1;
     for (int c = 0; c < 2; ++c) {
-        order_and_weigh(m, c, cls[c], surv[c].get(), hn[c], chunked, tu, s, &tm, c == 0 ? 5 : 8);
+        // frag[1 - c] holds class c's own records (it is class 1-c's coherence operand)
+        order_and_weigh(m, c, cls[c], surv[c].get(), hn[c], chunked, tu, s, &tm, c == 0 ? 5 : 8,
+                        use_mfma ? frag[1 - c].get() : nullptr);
         m.stats.coherent[c] = m.np[c];
         m.stats.support_tests[c] = m.np[c] * (uint64_t)cls[c].n;
         if (c == 0) tm.mark(3);   // end of class 0's support

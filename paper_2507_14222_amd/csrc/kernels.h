@@ -80,6 +80,10 @@ void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *fra
 void launch_coherence_mfma(int KS, const uint32_t *cand, uint32_t ncand, const uint64_t *X, uint32_t n,
                            const uint4 *frag, uint32_t n_o, uint32_t *keep, hipStream_t s);
 
+// Support on the matrix cores: frag = the class's own records (launch_mfma_records).
+void launch_support_mfma(int KS, const uint64_t *W, size_t m, const uint4 *frag, uint32_t n, uint32_t *f,
+                         int64_t *S, hipStream_t s);
+
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented
 // rows NX [n][KS] of their class.
 void launch_support(int KS, int cpl, const uint64_t *W, size_t m, const uint64_t *NX, uint32_t n, uint32_t *f,

@@ -282,6 +282,70 @@ __global__ __launch_bounds__(256) void k_coherence_mfma(const uint32_t *__restri
     if (half == 0 && act) keep[cidx] = col_covered ? 0u : 1u;
 }
 
+// Support (Eq. 2) as the same contraction: f(b) = number of same-class records
+// r with V[r][b] = 0.  Ordered pattern rows are the B operand; frag holds the
+// class's own complemented records (launch_mfma_records of that class).
+template <int KS>
+__global__ __launch_bounds__(256) void k_support_mfma(const uint64_t *__restrict__ Wrows, uint32_t m,
+                                                     const uint4 *__restrict__ frag, uint32_t ntiles,
+                                                     uint32_t *__restrict__ f_out, int64_t *__restrict__ S_out) {
+    __shared__ uint4 tile_frag[KS * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
+    const uint32_t e = blockIdx.x * 128u + wave * 32u + col;
+    const bool act = e < m;
+    v8i_t b[KS];
+    uint32_t len = 0;
+    {
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(Wrows + (size_t)(act ? e : 0) * KS);
+#pragma unroll
+        for (int w = 0; w < KS; ++w) {
+            const uint32_t d = act ? row[2 * w + half] : 0xffffffffu;
+            len += __popc(d);
+            b[w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
+                         0, 0, 0, 0};
+        }
+    }
+    uint32_t cnt = 0;
+    for (uint32_t t = 0; t < ntiles; ++t) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < KS * 64; q += 256) tile_frag[q] = frag[(size_t)t * KS * 64 + q];
+        __syncthreads();
+        v16f_t acc = {0};
+#pragma unroll
+        for (int w = 0; w < KS; ++w) {
+            const uint4 a4 = tile_frag[w * 64 + lane];
+            const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+            acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[w], acc, 4, 4, 0, 127, 0, 127);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cnt += acc[r] == 0.0f;
+    }
+    // the two halves hold different record rows (and token halves) of the same column
+    cnt += __shfl_xor(cnt, 32, 64);
+    len += __shfl_xor(len, 32, 64);
+    if (half == 0 && act) {
+        f_out[e] = cnt;
+        S_out[e] = (int64_t)cnt * (int64_t)len * (int64_t)len;
+    }
+}
+
+void launch_support_mfma(int KS, const uint64_t *W, size_t m, const uint4 *frag, uint32_t n, uint32_t *f,
+                         int64_t *S, hipStream_t s) {
+    if (!m) return;
+    const dim3 grid((unsigned)((m + 127) / 128));
+    const uint32_t ntiles = (n + 31) / 32;
+#define IG_SMF(V)                                                                                          \
+    case V:                                                                                                \
+        hipLaunchKernelGGL((k_support_mfma<V>), grid, dim3(256), 0, s, W, (uint32_t)m, frag, ntiles, f, S); \
+        break;
+    switch (KS) {
+        IG_SMF(1) IG_SMF(2) IG_SMF(3) IG_SMF(4) IG_SMF(5) IG_SMF(6) IG_SMF(7) IG_SMF(8)
+        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core support path handles up to 8 words");
+    }
+#undef IG_SMF
+    IG_HIP(hipGetLastError());
+}
+
 uint32_t mfma_record_tiles(uint32_t n) { return (n + 31) / 32; }
 
 void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *frag, hipStream_t s) {
