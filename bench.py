@@ -27,12 +27,15 @@ sys.path.insert(0, ROOT)
 METRIC = "subset tests/sec + IG fit wall-time at 15k/148k; served flows/sec with p99 latency"
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer VALU op per lane per clock
 VALU_INT32_PEAK_OPS = 256 * 64 * 2.4e9
+# MI355X dense fp4 matrix-core peak (operations: 2 per multiply-add)
+MFMA_FP4_PEAK_OPS = 10.1e15
 HBM_PEAK_GBS = 8000.0
 
 
-def counted_traffic(path):
-    """HBM bytes per coherence launch from the committed rocprofv3 counter summary,
-    or None when the summary is missing or the kernel source changed since."""
+def counted_traffic(path, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
+    or None when the summary is missing, covers another kernel, or the kernel
+    source changed since the counters were taken."""
     import hashlib
     if not os.path.exists(path):
         return None
@@ -44,6 +47,8 @@ def counted_traffic(path):
     src = os.path.join(ROOT, "paper_2507_14222_amd", "csrc", "subset.hip")
     now = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if vals.get("kernel_source_sha256_16") != now or "bytes_per_launch" not in vals:
+        return None
+    if vals.get("kernel") != kernel:
         return None
     return int(vals["bytes_per_launch"])
 
@@ -200,7 +205,7 @@ def main():
                     help="only run the 64-problem workload: batched fit vs 64 plain fits")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB, 4 times (calibrates HBM byte counters)")
-    ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "k_coherence_15k_traffic.txt"))
+    ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "dominant_kernel_15k_traffic.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -233,9 +238,15 @@ def main():
     out = torch.empty((w.test_codes.shape[0], 2), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
 
+    score_ev = []
+
     def step():
         m = ig.fit(d_codes, d_labels, w.nbins, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         ig.score(m, d_flows, out=out, stream=stream)
+        e1.record(stream)
+        score_ev.append((e0, e1))
         return m
 
     for i in range(args.warmup):
@@ -243,7 +254,7 @@ def main():
         torch.cuda.synchronize()
         log("warmup", i, "done")
     torch.cuda.synchronize()
-    fit_s, coh_ms, models = [], [], []
+    fit_s, models = [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
         a = time.perf_counter()
@@ -258,21 +269,44 @@ def main():
     st = models[-1].stats()
     npat = models[-1].n_patterns()
     K = models[-1].K
+    L = int(w.L)
     n_flows = w.test_codes.shape[0]
-    coh_tests = sum(st.tests)
+    # the method's subset tests: sum of t(b) in input order (from one untimed fit on the
+    # early-exit path), |P^c| * n_c support tests and |P| * n_flows scoring tests
+    ref = ig.fit(d_codes, d_labels, w.nbins, kernels="valu", stream=stream)
+    coh_tests = sum(ref.stats().tests)
+    del ref
     sup_tests = sum(st.support_tests)
     score_tests = (npat[0] + npat[1]) * n_flows
     tests_per_step = coh_tests + sup_tests + score_tests
     value = tests_per_step / (ms_per_step / 1e3)
-    coh_ms = [mm.stats().ms[4] for mm in models]
-    coh_avg_ms = sum(coh_ms) / len(coh_ms)
-    # algorithmic VALU work of the coherence kernel: 2K 32-bit AND/OR ops per executed test
-    achieved = coh_tests * 2 * K / (coh_avg_ms / 1e3)
-    traffic = counted_traffic(args.traffic)
-    roofline = {"bound": "alu", "kernel": "k_coherence", "achieved": achieved / 1e12,
-                "peak": VALU_INT32_PEAK_OPS / 1e12, "unit": "TOP/s (int32 VALU)",
-                "frac": achieved / VALU_INT32_PEAK_OPS, "traffic": traffic,
-                "avg_ms": coh_avg_ms, "tests": coh_tests}
+    on_mfma = sum(st.tests) != coh_tests            # dense count: the matrix-core kernels ran
+    coh_ms = sum(mm.stats().ms[4] for mm in models) / len(models)
+    sup_ms = sum(mm.stats().ms[6] for mm in models) / len(models)
+    score_ms = sum(a.elapsed_time(b) for a, b in score_ev[-len(models):]) / len(models)
+    n_cls = list(st.n_class)
+    kernels = {}
+    if on_mfma:
+        dense = sum(st.tests)                           # every (candidate, other-class record) pair
+        kernels["k_coherence_mfma"] = {"bound": "mfma", "ms": coh_ms, "ops": 2.0 * L * dense,
+                                       "peak": MFMA_FP4_PEAK_OPS, "unit": "TFLOP/s (fp4 dense)"}
+        kernels["k_support_mfma"] = {"bound": "mfma", "ms": sup_ms, "ops": 2.0 * L * sup_tests,
+                                     "peak": MFMA_FP4_PEAK_OPS, "unit": "TFLOP/s (fp4 dense)"}
+    else:
+        kernels["k_coherence"] = {"bound": "alu", "ms": coh_ms, "ops": 2.0 * K * coh_tests,
+                                  "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
+        kernels["k_support"] = {"bound": "alu", "ms": sup_ms, "ops": 2.0 * K * sup_tests,
+                                "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
+    kernels["k_score"] = {"bound": "alu", "ms": score_ms, "ops": 2.0 * K * score_tests,
+                          "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
+    for k, v in kernels.items():
+        v["achieved"] = v["ops"] / (v["ms"] / 1e3) / 1e12
+        v["frac"] = v["ops"] / (v["ms"] / 1e3) / v["peak"]
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    d = kernels[dom]
+    roofline = {"bound": d["bound"], "kernel": dom, "achieved": d["achieved"], "peak": d["peak"] / 1e12,
+                "unit": d["unit"], "frac": d["frac"], "traffic": counted_traffic(args.traffic, dom),
+                "avg_ms": d["ms"]}
     res = {
         "metric": METRIC, "value": value, "unit": "subset tests/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -284,8 +318,10 @@ def main():
         "tests_per_step": {"coherence": coh_tests, "support": sup_tests, "scoring": score_tests},
         "patterns": list(npat), "distinct": list(st.distinct),
         "stage_ms": {k: round(v, 3) for k, v in zip(
-            ["pack", "pairs", "sort", "dedup", "coherence", "order+support", "weights", "fit_total"], st.ms)},
+            ["pack", "pairs", "sort", "dedup", "coherence", "order", "support", "fit_total"], st.ms)},
         "roofline": roofline,
+        "kernels": {k: {"ms": round(v["ms"], 3), "achieved": round(v["achieved"], 2), "frac": round(v["frac"], 4),
+                        "bound": v["bound"]} for k, v in kernels.items()},
     }
     del models
     if not args.no_148k:

@@ -83,12 +83,16 @@ typedef struct {
     uint32_t block;             /* reserved (workgroups are 256 threads)              */
     uint32_t n_tune;            /* rows in `tune`                                     */
     const ig_tune_entry *tune;  /* host tuning table (may be NULL)                    */
-    uint32_t coherence_mfma;    /* 1: coherence as a dense 0/1 contraction on the
-                                   matrix cores (fp4 operands, fp32 accumulation;
-                                   exact; K <= 8 words).  Same patterns; no early
-                                   exit, so ig_stats.tests counts every pair of
-                                   candidate and other-class record.  0: the VALU
-                                   path with early exit (default).                  */
+    uint32_t coherence_mfma;    /* coherence (Eq. 3) and support (Eq. 2) kernels:
+                                   0 = automatic: matrix cores when K <= 8 words,
+                                       else the VALU path;
+                                   1 = matrix cores (K <= 8): a dense 0/1 contraction
+                                       with fp4 operands and fp32 accumulation, exact;
+                                       no early exit, so ig_stats.tests counts every
+                                       (candidate, other-class record) pair;
+                                   2 = VALU path: AND-NOT chains with early exit in
+                                       input order (ig_stats.tests = sum of t(b)).
+                                   All give the same patterns, f and S.             */
     uint32_t reserved;
 } ig_fit_opts;
 
@@ -98,10 +102,11 @@ typedef struct {
     uint64_t pairs[2];       /* n_c (n_c - 1) / 2                                    */
     uint64_t distinct[2];    /* distinct non-empty members of B^c (Eq. 1)            */
     uint64_t coherent[2];    /* |P^c| (Eq. 3)                                        */
-    uint64_t tests[2];       /* sum over distinct candidates of t(b): the records of
-                                the other class examined up to and including the
-                                first that contains b (all of them when none does),
-                                scanning the other class in input order              */
+    uint64_t tests[2];       /* subset tests made by the coherence kernel: on the VALU
+                                path the sum over distinct candidates of t(b), the
+                                other-class records examined in input order up to and
+                                including the first that contains b (all of them when
+                                none does); on the matrix cores every pair           */
     uint64_t support_tests[2]; /* |P^c| * n_c subset tests of Eq. 2                  */
     uint32_t chunks[2];      /* pair-space chunks used for the class                 */
     float ms[8];             /* device time per stage: 0 pack, 1 pairs+hash, 2 sort,

@@ -350,8 +350,10 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         IG_HIP(hipStreamSynchronize(s));
     }
     const uint32_t grid = coherence_grid(tu.grid_per_cu);
-    const bool use_mfma = opts && opts->coherence_mfma == 1;
-    IG_REQUIRE(!use_mfma || KS <= 8, IG_E_UNSUPPORTED, "the matrix-core coherence path handles up to 8 words");
+    const uint32_t mode = opts ? opts->coherence_mfma : 0u;
+    IG_REQUIRE(mode <= 2, IG_E_INVAL, "coherence_mfma must be 0, 1 or 2");
+    IG_REQUIRE(mode != 1 || KS <= 8, IG_E_UNSUPPORTED, "the matrix-core coherence path handles up to 8 words");
+    const bool use_mfma = mode == 1 || (mode == 0 && KS <= 8);
     Scratch<uint4> frag[2];   // per class c: the other class's records as the A operand
     uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
     if (use_mfma)

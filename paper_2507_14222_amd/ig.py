@@ -136,10 +136,11 @@ def _np_u16(a) -> np.ndarray:
 
 
 def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tune=None,
-          coherence_mfma: bool = False) -> FitOpts:
-    """Fit options; `tune` is a list of dicts with the fields of ig_tune_entry."""
+          kernels: str = "auto") -> FitOpts:
+    """Fit options; `tune` is a list of dicts with the fields of ig_tune_entry;
+    kernels = "auto" | "mfma" | "valu" selects the coherence/support kernels."""
     o = FitOpts()
-    o.coherence_mfma = 1 if coherence_mfma else 0
+    o.coherence_mfma = {"auto": 0, "mfma": 1, "valu": 2}[kernels]
     o.mem_budget_bytes = int(mem_budget_bytes)
     o.filter_cpl = int(filter_cpl)
     o.score_fpl = int(score_fpl)
@@ -228,7 +229,7 @@ class Model:
 
 
 def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tune=None,
-        coherence_mfma: bool = False, stream=None) -> Model:
+        kernels: str = "auto", stream=None) -> Model:
     """ig_fit: codes [n, d] bin codes, labels [n] (0 normal / 1 attack), nbins [d]."""
     torch = _torch()
     dc = _dev(codes, torch.int16)
@@ -236,7 +237,7 @@ def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tu
     n, d = (int(dc.shape[0]), int(dc.shape[1])) if dc.dim() == 2 else (0, 0)
     nb = _np_u16(nbins)
     h = C.c_void_p()
-    o = _opts(mem_budget_bytes, filter_cpl, tune=tune, coherence_mfma=coherence_mfma)
+    o = _opts(mem_budget_bytes, filter_cpl, tune=tune, kernels=kernels)
     _check(lib().ig_fit(C.c_void_p(dc.data_ptr()), C.c_void_p(dl.data_ptr()), n, d or nb.size,
                         C.c_void_p(nb.ctypes.data), C.byref(o), _stream_handle(stream), C.byref(h)))
     return Model(h)
@@ -256,7 +257,8 @@ def fit_packed(words, labels, mem_budget_bytes: int = 0, stream=None) -> Model:
     return Model(h)
 
 
-def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, tune=None, stream=None) -> List[Model]:
+def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, tune=None, kernels: str = "auto",
+              stream=None) -> List[Model]:
     """ig_fit_batch over problems with attributes codes, labels, nbins."""
     torch = _torch()
     keep = []
@@ -272,7 +274,7 @@ def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, tune=None, stream=N
         arr[p].d = int(nb.size)
         arr[p].h_nbins = nb.ctypes.data
     outs = (C.c_void_p * len(problems))()
-    o = _opts(mem_budget_bytes, tune=tune)
+    o = _opts(mem_budget_bytes, tune=tune, kernels=kernels)
     _check(lib().ig_fit_batch(arr, len(problems), C.byref(o), _stream_handle(stream), outs))
     return [Model(C.c_void_p(outs[p])) for p in range(len(problems))]
 

@@ -1,5 +1,7 @@
 """Autotuner for the launch shapes of libig's fit kernels.
 
+The shapes tuned are those of the VALU coherence and support kernels (the path
+for widths beyond the matrix-core kernels' 8 words, and the batched graph).
 For each storage width KS and problem-size bucket it fits a seeded synthetic
 problem of that width and size with every candidate shape and keeps the fastest
 (coherence: candidates per lane x workgroups per CU, timed by the library's own
@@ -34,7 +36,7 @@ def _problem_for(ks: int, n: int, seed: int) -> synth.Problem:
 def _time(p, tune, reps: int):
     best_c = best_s = float("inf")
     for _ in range(reps):
-        m = ig.fit(p.codes, p.labels, p.nbins, tune=tune)
+        m = ig.fit(p.codes, p.labels, p.nbins, tune=tune, kernels="valu")
         st = m.stats()
         best_c = min(best_c, st.ms[4])
         best_s = min(best_s, st.ms[6])

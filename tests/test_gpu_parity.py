@@ -61,7 +61,8 @@ def gpu_scores(m, flows):
 def test_worked_example():
     g = json.load(open(os.path.join(GOLD, "worked_example.json")))
     say("worked example")
-    m = ig.fit(np.array(g["codes"], np.uint16), np.array(g["labels"], np.uint8), np.array(g["nbins"], np.uint16))
+    m = ig.fit(np.array(g["codes"], np.uint16), np.array(g["labels"], np.uint8), np.array(g["nbins"], np.uint16),
+               kernels="valu")
     for c in ("0", "1"):
         w, f, S = m.export(int(c))
         got = [(int(w[p, 0]), int(f[p]), int(S[p])) for p in range(w.shape[0])]
@@ -78,9 +79,11 @@ def test_tiny_workload_full_parity():
     w = synth.make_tiny(0)
     say("tiny workload", w.codes.shape)
     om = oracle.fit(w.codes, w.labels, w.nbins)
-    m = ig.fit(w.codes, w.labels, w.nbins)
+    m = ig.fit(w.codes, w.labels, w.nbins, kernels="valu")
     assert_same_model(m, om, om.K)
     assert_same_stats(m, om)
+    m = ig.fit(w.codes, w.labels, w.nbins)   # default kernels
+    assert_same_model(m, om, om.K)
     A, N = gpu_scores(m, w.test_codes)
     oA, oN = oracle.score(om, w.test_codes, w.nbins)
     assert np.array_equal(A, oA) and np.array_equal(N, oN)
@@ -117,10 +120,12 @@ def test_random_problem_parity(case):
     p = synth.make_random_problem(seed, n, d, bins_lo=blo, bins_hi=bhi, attack_frac=af)
     say("random problem", case, "L", p.L)
     om = oracle.fit(p.codes, p.labels, p.nbins)
-    m = ig.fit(p.codes, p.labels, p.nbins)
+    m = ig.fit(p.codes, p.labels, p.nbins, kernels="valu")
     assert m.K == om.K
     assert_same_model(m, om, om.K)
     assert_same_stats(m, om)
+    m = ig.fit(p.codes, p.labels, p.nbins)   # default kernels (matrix cores when K <= 8)
+    assert_same_model(m, om, om.K)
     flows = synth.make_random_problem(seed + 1000, 97, d, bins_lo=blo, bins_hi=bhi).codes
     flows = np.minimum(flows, p.nbins[None, :] - 1).astype(np.uint16)
     flows = np.concatenate([flows, p.codes[: min(40, p.n)]])
@@ -132,8 +137,8 @@ def test_random_problem_parity(case):
 def test_filter_lanes_per_candidate_agree():
     p = synth.make_random_problem(21, 333, 20, bins_lo=3, bins_hi=7)
     say("cpl 1 vs 2")
-    a = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=1)
-    b = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=2)
+    a = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=1, kernels="valu")
+    b = ig.fit(p.codes, p.labels, p.nbins, filter_cpl=2, kernels="valu")
     for c in (0, 1):
         for x, y in zip(a.export(c), b.export(c)):
             assert np.array_equal(x, y)
@@ -225,9 +230,10 @@ def test_degenerate_sizes():
         codes = codes.astype(np.uint16)
         labels = labels.astype(np.uint8)
         om = oracle.fit(codes, labels, nb)
-        m = ig.fit(codes, labels, nb)
+        m = ig.fit(codes, labels, nb, kernels="valu")
         assert_same_model(m, om, om.K)
         assert_same_stats(m, om)
+        assert_same_model(ig.fit(codes, labels, nb), om, om.K)
 
 
 def test_scores_do_not_depend_on_batching():
@@ -259,12 +265,15 @@ def test_15k_workload_matches_oracle_digest():
     g = json.load(open(os.path.join(GOLD, "mixture41_15k.json")))
     w = synth.make_15k()
     say("15k workload", w.codes.shape, w.test_codes.shape)
+    m = ig.fit(w.codes, w.labels, w.nbins, kernels="valu")
+    assert list(m.stats().tests) == g["stats"]["tests"]
+    assert _model_digest(m) == g["model_sha256"]
+    del m
     m = ig.fit(w.codes, w.labels, w.nbins)   # the configuration the benchmark times
     st = m.stats()
     assert list(st.pairs) == g["stats"]["pairs"]
     assert list(st.distinct) == g["stats"]["distinct"]
     assert list(st.coherent) == g["stats"]["coherent"]
-    assert list(st.tests) == g["stats"]["tests"]
     assert _model_digest(m) == g["model_sha256"]
     A, N = gpu_scores(m, w.test_codes)
     assert A[:16].tolist() == g["scores_head"]["A"] and N[:16].tolist() == g["scores_head"]["N"]
@@ -336,7 +345,7 @@ def test_matrix_core_coherence_matches_oracle(case):
     p = synth.make_random_problem(seed, n, d, bins_lo=blo, bins_hi=bhi, attack_frac=af)
     say("mfma coherence", case)
     om = oracle.fit(p.codes, p.labels, p.nbins)
-    m = ig.fit(p.codes, p.labels, p.nbins, coherence_mfma=True)
+    m = ig.fit(p.codes, p.labels, p.nbins, kernels="mfma")
     assert_same_model(m, om, om.K)
     st = m.stats()
     assert list(st.coherent) == om.stats["coherent"] and list(st.distinct) == om.stats["distinct"]
@@ -348,6 +357,6 @@ def test_matrix_core_coherence_15k_digest():
     g = json.load(open(os.path.join(GOLD, "mixture41_15k.json")))
     w = synth.make_15k()
     say("mfma coherence 15k")
-    m = ig.fit(w.codes, w.labels, w.nbins, coherence_mfma=True)
+    m = ig.fit(w.codes, w.labels, w.nbins, kernels="mfma")
     assert list(m.stats().coherent) == g["stats"]["coherent"]
     assert _model_digest(m) == g["model_sha256"]
