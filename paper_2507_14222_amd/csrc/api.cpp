@@ -65,6 +65,8 @@ struct DevModel {
     int64_t maxS[2] = {0, 0};
     uint32_t *meta = nullptr;    // off[d] | flo[KS] | fhi[KS]
     uint16_t *nbins = nullptr;
+    uint4 *frag[2] = {nullptr, nullptr};   // matrix-core scoring operands (KS <= 8)
+    uint32_t *sc[2] = {nullptr, nullptr};
     ig_stats stats{};
 
     ~DevModel() {
@@ -72,6 +74,10 @@ struct DevModel {
             if (W[c]) (void)hipFree(W[c]);
             if (f[c]) (void)hipFree(f[c]);
             if (S[c]) (void)hipFree(S[c]);
+        }
+        for (int c = 0; c < 2; ++c) {
+            if (frag[c]) (void)hipFree(frag[c]);
+            if (sc[c]) (void)hipFree(sc[c]);
         }
         if (meta) (void)hipFree(meta);
         if (nbins) (void)hipFree(nbins);
@@ -265,6 +271,20 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         launch_support((int)KS, tu.support_cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
 }
 
+// Matrix-core scoring operands of a finished model: when its rows fit the
+// 8-word kernels and every weight is below 2^28 (sixteen of them sum without
+// wrapping in 32 bits).  Otherwise scoring stays on the VALU kernel.
+static void build_score_operands(DevModel &m, hipStream_t s) {
+    if (m.KS > 8 || m.maxS[0] >= (1ll << 28) || m.maxS[1] >= (1ll << 28)) return;
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t ntiles = (m.np[c] + 31) / 32;
+        m.frag[c] = dev_alloc<uint4>(ntiles * m.KS * 64);
+        m.sc[c] = dev_alloc<uint32_t>(ntiles * 32);
+        launch_mfma_patterns(m.W[c], m.S[c], (uint32_t)m.np[c], m.KS, m.frag[c], m.sc[c], s);
+    }
+    IG_HIP(hipStreamSynchronize(s));
+}
+
 static void finish_weights(DevModel &m, hipStream_t s) {
     Scratch<unsigned long long> ms(4, s);
     for (int c = 0; c < 2; ++c) launch_reduce_maxsum(m.S[c], m.np[c], ms.get() + 2 * c, s);
@@ -277,6 +297,7 @@ static void finish_weights(DevModel &m, hipStream_t s) {
         IG_REQUIRE(h[2 * c + 1] <= (unsigned long long)INT64_MAX, IG_E_OVERFLOW,
                    "sum of pattern weights exceeds int64");
     }
+    build_score_operands(m, s);
 }
 
 // Ends of the coherence phases over the other class's records.  One phase (the
@@ -1048,8 +1069,12 @@ ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows,
         IG_REQUIRE(M.d > 0, IG_E_INVAL, "model was fitted from packed words: use ig_score_packed");
         IG_REQUIRE(n_flows < (1u << 31), IG_E_UNSUPPORTED, "n_flows must be below 2^31");
         IG_REQUIRE(n_flows == 0 || (d_codes && d_out), IG_E_INVAL, "codes or out is NULL");
-        ig::ScoreModel sm{{M.W[0], M.W[1]}, {M.S[0], M.S[1]}, {M.np[0], M.np[1]}, M.KS, {M.maxS[0], M.maxS[1]}};
-        ig::launch_score(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, (hipStream_t)stream);
+        ig::ScoreModel sm{{M.W[0], M.W[1]}, {M.S[0], M.S[1]}, {M.np[0], M.np[1]}, M.KS, {M.maxS[0], M.maxS[1]},
+                          {M.frag[0], M.frag[1]}, {M.sc[0], M.sc[1]}};
+        if (M.frag[0] && M.frag[1])
+            ig::launch_score_mfma(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, (hipStream_t)stream);
+        else
+            ig::launch_score(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, (hipStream_t)stream);
     });
 }
 
@@ -1060,8 +1085,12 @@ ig_status ig_score_packed(const ig_model *m, const uint64_t *d_words, uint32_t n
         const DevModel &M = *m->m;
         IG_REQUIRE(n_flows < (1u << 31), IG_E_UNSUPPORTED, "n_flows must be below 2^31");
         IG_REQUIRE(n_flows == 0 || (d_words && d_out), IG_E_INVAL, "words or out is NULL");
-        ig::ScoreModel sm{{M.W[0], M.W[1]}, {M.S[0], M.S[1]}, {M.np[0], M.np[1]}, M.KS, {M.maxS[0], M.maxS[1]}};
-        ig::launch_score(sm, nullptr, d_words, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, (hipStream_t)stream);
+        ig::ScoreModel sm{{M.W[0], M.W[1]}, {M.S[0], M.S[1]}, {M.np[0], M.np[1]}, M.KS, {M.maxS[0], M.maxS[1]},
+                          {M.frag[0], M.frag[1]}, {M.sc[0], M.sc[1]}};
+        if (M.frag[0] && M.frag[1])
+            ig::launch_score_mfma(sm, nullptr, d_words, M.K, n_flows, M.d, M.meta, M.nbins, d_out, (hipStream_t)stream);
+        else
+            ig::launch_score(sm, nullptr, d_words, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, (hipStream_t)stream);
     });
 }
 

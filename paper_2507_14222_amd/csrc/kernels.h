@@ -95,7 +95,17 @@ struct ScoreModel {
     uint64_t np[2];
     uint32_t KS;
     int64_t maxS[2];            // largest weight of each class
+    const uint4 *frag[2];       // matrix-core operands of the patterns (or null)
+    const uint32_t *sc[2];      // their weights in accumulator order
 };
+// Scoring on the matrix cores (KS <= 8, every weight < 2^28): patterns pre-expanded
+// by launch_mfma_patterns into frag (ceil(m/32) * KS * 64 uint4) and sc
+// (ceil(m/32) * 32 u32).
+void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, uint4 *frag, uint32_t *sc,
+                          hipStream_t s);
+void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K,
+                       uint32_t n_flows, uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out,
+                       hipStream_t s);
 // Eq. 4 for n_flows flows: codes [n][d] (meta = off|flo|fhi, nbins) or packed
 // words [n][K].  out [n][2] = (A, N) is initialised by the launcher.
 void launch_score(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K, uint32_t n_flows,

@@ -346,6 +346,137 @@ void launch_support_mfma(int KS, const uint64_t *W, size_t m, const uint4 *frag,
     IG_HIP(hipGetLastError());
 }
 
+// Scoring (Eq. 4) as the same contraction: V[b][t] = sum over tokens of
+// b[token] * (NOT t)[token] is 0 exactly when pattern b lies inside flow t.
+// Patterns are the A operand (rows), pre-expanded per model with their weights in
+// accumulator order; flows are the B operand (columns), packed from their codes,
+// complemented and expanded in registers.  Accumulator register r of lane half h
+// holds row (r / 4) * 8 + 4 h + r % 4 of the 32-row tile.
+__device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return (r >> 2) * 8 + half * 4 + (r & 3); }
+
+// frag[(tile * KS + w) * 64 + lane] = nibbles of half (lane/32) of word w of row
+// tile*32 + lane%32 (empty past m); sc[(tile * 2 + half) * 16 + r] = weight of the
+// row held in accumulator r of lane half `half` (0 past m).
+__global__ void k_mfma_patterns(const uint64_t *__restrict__ W, const int64_t *__restrict__ S, uint32_t m,
+                                uint32_t KS, uint32_t ntiles, uint4 *__restrict__ frag, uint32_t *__restrict__ sc) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < (size_t)ntiles * KS * 64) {
+        const uint32_t lane = (uint32_t)(g % 64), w = (uint32_t)((g / 64) % KS), tile = (uint32_t)(g / (64 * KS));
+        const uint32_t row = tile * 32 + lane % 32;
+        const uint32_t d = row < m ? (uint32_t)(W[(size_t)row * KS + w] >> (32 * (lane / 32))) : 0u;
+        frag[g] = make_uint4(spread8(d), spread8(d >> 8), spread8(d >> 16), spread8(d >> 24));
+    }
+    if (g < (size_t)ntiles * 32) {
+        const uint32_t tile = (uint32_t)(g / 32), half = (uint32_t)((g / 16) % 2), r = (uint32_t)(g % 16);
+        const uint32_t row = tile * 32 + acc_row(half, r);
+        sc[g] = row < m ? (uint32_t)S[row] : 0u;
+    }
+}
+
+struct ScoreMfmaArgs {
+    const uint4 *frag[2];
+    const uint32_t *sc[2];
+    uint32_t ntiles[2];
+    uint32_t chunk;             // pattern tiles per workgroup
+    const uint16_t *codes;      // [n][d] or null
+    const uint64_t *words;      // [n][K] or null
+    const uint32_t *meta;
+    const uint16_t *nbins;
+    int64_t *out;
+    uint32_t n_flows, d, K;
+};
+
+template <int KS>
+__global__ __launch_bounds__(512) void k_score_mfma(ScoreMfmaArgs a) {
+    constexpr int FB = 2;   // flow column sets per wave
+    __shared__ uint4 tile_frag[KS * 64];
+    __shared__ uint32_t tile_s[32];
+    const int cls = blockIdx.z;
+    const uint32_t t0 = blockIdx.y * a.chunk;
+    if (t0 >= a.ntiles[cls]) return;   // uniform over the workgroup
+    const uint32_t t1 = t0 + a.chunk < a.ntiles[cls] ? t0 + a.chunk : a.ntiles[cls];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
+    v8i_t b[FB][KS];
+    uint64_t sum[FB];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        const uint32_t t = blockIdx.x * (8 * FB * 32) + wave * (FB * 32) + f * 32 + col;
+        const bool act = t < a.n_flows;
+        uint64_t wd[KS];
+        bool ok = act;
+        if (act && a.codes) {
+            const uint16_t *row = a.codes + (size_t)t * a.d;
+            const uint32_t *off = a.meta, *flo = a.meta + a.d, *fhi = a.meta + a.d + KS;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                uint64_t v = 0;
+                for (uint32_t ft = flo[k]; ft < fhi[k]; ++ft) {
+                    const uint32_t c = row[ft];
+                    ok &= c < a.nbins[ft];
+                    const uint32_t bit = off[ft] + c;
+                    if ((bit >> 6) == (uint32_t)k) v |= 1ull << (bit & 63);
+                }
+                wd[k] = v;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < KS; ++k) wd[k] = (act && k < (int)a.K) ? a.words[(size_t)t * a.K + k] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            // NOT t; an inactive or invalid flow is the empty set, which contains no pattern
+            const uint64_t nt = ok ? ~wd[k] : ~0ull;
+            const uint32_t dwd = (uint32_t)(nt >> (32 * half));
+            b[f][k] = v8i_t{(int)spread8(dwd), (int)spread8(dwd >> 8), (int)spread8(dwd >> 16),
+                            (int)spread8(dwd >> 24), 0, 0, 0, 0};
+        }
+        sum[f] = 0;
+    }
+    const uint4 *frag = a.frag[cls];
+    const uint32_t *sc = a.sc[cls];
+    for (uint32_t t = t0; t < t1; ++t) {
+        __syncthreads();
+        if (threadIdx.x < KS * 64) tile_frag[threadIdx.x] = frag[(size_t)t * KS * 64 + threadIdx.x];
+        if (threadIdx.x < 32) tile_s[threadIdx.x] = sc[(size_t)t * 32 + threadIdx.x];
+        __syncthreads();
+        uint32_t s16[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s16[r] = tile_s[half * 16 + r];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            v16f_t acc = {0};
+#pragma unroll
+            for (int w = 0; w < KS; ++w) {
+                const uint4 a4 = tile_frag[w * 64 + lane];
+                const v8i_t av = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, b[f][w], acc, 4, 4, 0, 127, 0, 127);
+            }
+            uint32_t lo = 0;   // 16 weights below 2^28 each: no wrap
+#pragma unroll
+            for (int r = 0; r < 16; ++r) lo += acc[r] == 0.0f ? s16[r] : 0u;
+            sum[f] += lo;
+        }
+    }
+    const int colsel = cls == 1 ? 0 : 1;   // A from class 1, N from class 0
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        uint64_t v = sum[f] + __shfl_xor(sum[f], 32, 64);   // the two halves hold different rows
+        const uint32_t t = blockIdx.x * (8 * FB * 32) + wave * (FB * 32) + f * 32 + col;
+        if (half == 0 && t < a.n_flows && v)
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.out + 2 * (size_t)t + colsel), (unsigned long long)v);
+    }
+}
+
+void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, uint4 *frag, uint32_t *sc,
+                          hipStream_t s) {
+    const uint32_t ntiles = (m + 31) / 32;
+    const size_t total = (size_t)ntiles * KS * 64;
+    if (!total) return;
+    hipLaunchKernelGGL(k_mfma_patterns, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, W, S, m, KS, ntiles,
+                       frag, sc);
+    IG_HIP(hipGetLastError());
+}
+
 uint32_t mfma_record_tiles(uint32_t n) { return (n + 31) / 32; }
 
 void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *frag, hipStream_t s) {
@@ -729,6 +860,56 @@ void launch_reduce_maxsum(const int64_t *S, size_t m, unsigned long long *d_max_
     unsigned g = (unsigned)((m + 255) / 256);
     if (g > 1024) g = 1024;
     hipLaunchKernelGGL(k_maxsum, dim3(g), dim3(256), 0, s, S, m, d_max_sum);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K,
+                       uint32_t n_flows, uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out,
+                       hipStream_t s) {
+    if (!n_flows) return;
+    ScoreArgs ia{};
+    ia.codes = codes;
+    ia.words = words;
+    ia.meta = meta;
+    ia.nbins = nbins;
+    ia.out = out;
+    ia.n_flows = n_flows;
+    ia.d = d;
+    ia.K = K;
+    hipLaunchKernelGGL(k_score_init, dim3((n_flows + 255) / 256), dim3(256), 0, s, ia);
+    IG_HIP(hipGetLastError());
+    ScoreMfmaArgs a{};
+    for (int c = 0; c < 2; ++c) {
+        a.frag[c] = m.frag[c];
+        a.sc[c] = m.sc[c];
+        a.ntiles[c] = (uint32_t)((m.np[c] + 31) / 32);
+    }
+    a.codes = codes;
+    a.words = words;
+    a.meta = meta;
+    a.nbins = nbins;
+    a.out = out;
+    a.n_flows = n_flows;
+    a.d = d;
+    a.K = K;
+    const uint32_t fblocks = (n_flows + 511) / 512;
+    const uint32_t maxt = a.ntiles[0] > a.ntiles[1] ? a.ntiles[0] : a.ntiles[1];
+    if (!maxt) return;
+    uint32_t ychunks = (2048 + 2 * fblocks - 1) / (2 * fblocks);
+    if (ychunks > maxt) ychunks = maxt;
+    if (ychunks > 65535) ychunks = 65535;
+    a.chunk = (maxt + ychunks - 1) / ychunks;
+    const uint32_t ny = (maxt + a.chunk - 1) / a.chunk;
+    dim3 grid(fblocks, ny, 2);
+#define IG_SCM(V)                                                                    \
+    case V:                                                                          \
+        hipLaunchKernelGGL((k_score_mfma<V>), grid, dim3(512), 0, s, a);            \
+        break;
+    switch ((int)m.KS) {
+        IG_SCM(1) IG_SCM(2) IG_SCM(3) IG_SCM(4) IG_SCM(5) IG_SCM(6) IG_SCM(7) IG_SCM(8)
+        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core scoring path handles up to 8 words");
+    }
+#undef IG_SCM
     IG_HIP(hipGetLastError());
 }
 
