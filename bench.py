@@ -297,8 +297,12 @@ def main():
                                   "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
         kernels["k_support"] = {"bound": "alu", "ms": sup_ms, "ops": 2.0 * K * sup_tests,
                                 "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
-    kernels["k_score"] = {"bound": "alu", "ms": score_ms, "ops": 2.0 * K * score_tests,
-                          "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
+    if models[-1].score_on_matrix_cores:
+        kernels["k_score_mfma"] = {"bound": "mfma", "ms": score_ms, "ops": 2.0 * L * score_tests,
+                                   "peak": MFMA_FP4_PEAK_OPS, "unit": "TFLOP/s (fp4 dense)"}
+    else:
+        kernels["k_score"] = {"bound": "alu", "ms": score_ms, "ops": 2.0 * K * score_tests,
+                              "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
     for k, v in kernels.items():
         v["achieved"] = v["ops"] / (v["ms"] / 1e3) / 1e12
         v["frac"] = v["ops"] / (v["ms"] / 1e3) / v["peak"]

@@ -119,10 +119,15 @@ typedef struct {
     uint32_t K;              /* words per bitset                                     */
     uint32_t L;              /* token universe size                                  */
     uint32_t d;              /* features (0 for a model fitted from packed words)    */
-    uint32_t reserved;
+    uint32_t flags;          /* IG_MODEL_* bits                                      */
     uint64_t n_patterns[2];  /* |P^0|, |P^1|                                         */
     int64_t max_weight[2];   /* largest S of each class                              */
 } ig_model_info;
+
+/* ig_model_info.flags: ig_score evaluates Eq. 4 on the matrix cores (models of at
+ * most 8 words whose weights are all below 2^28); otherwise on the vector ALUs.
+ * Both give identical scores. */
+#define IG_MODEL_SCORE_MFMA 1u
 
 /* One problem of a batched fit. */
 typedef struct {

@@ -1102,6 +1102,7 @@ ig_status ig_model_get_info(const ig_model *m, ig_model_info *info) {
         info->K = M.K;
         info->L = M.L;
         info->d = M.d;
+        info->flags = (M.frag[0] && M.frag[1]) ? IG_MODEL_SCORE_MFMA : 0u;
         for (int c = 0; c < 2; ++c) {
             info->n_patterns[c] = M.np[c];
             info->max_weight[c] = M.maxS[c];

@@ -222,6 +222,86 @@ __device__ __forceinline__ uint32_t spread8(uint32_t b) {
     return x << 1;
 }
 
+// Streaming A-operand tiles through LDS.  The tiles [t0, t1) of a fragment array
+// (KS * 64 uint4 per 32-row tile, optionally 32 u32 of per-row data) pass through
+// two LDS buffers of G tiles each: while the waves multiply the tiles of one
+// buffer, the next G tiles are already on their way from memory into the other
+// buffer (global_load_lds_dwordx4: memory to LDS without registers, lane l of a
+// wave writing bytes [16 l, 16 l + 16) of the wave's 1 KB slice); one barrier per
+// G tiles.  Loads past t1 are clamped to the last element of the range (no
+// branches; the copies are never read).
+typedef uint32_t v4u_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void load_to_lds16(const v4u_t *src, v4u_t *wave_slice) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                     (__attribute__((address_space(3))) void *)wave_slice, 16, 0, 0);
+}
+
+template <int KS, int G, int NT, class Body>
+__device__ __forceinline__ void stream_tiles(const uint4 *__restrict__ frag_in, const uint32_t *__restrict__ side,
+                                             uint32_t t0, uint32_t t1, uint4 *lds_in, uint32_t *lds_side, Body body) {
+    constexpr int N = G * KS * 64;            // uint4 per group, a multiple of 64: whole waves
+    constexpr int PER = (N + NT - 1) / NT;    // per thread
+    constexpr int NS = G * 32;                // side words per group
+    constexpr int SPER = (NS + NT - 1) / NT;
+    const v4u_t *frag = reinterpret_cast<const v4u_t *>(frag_in);
+    v4u_t *lds = reinterpret_cast<v4u_t *>(lds_in);
+    const uint32_t lane = threadIdx.x & 63, wave_base = threadIdx.x & ~63u;
+    uint32_t rs[SPER];
+    auto fetch = [&](uint32_t t, int buf) __attribute__((always_inline)) {
+        const uint32_t avail = (t1 - t) * (KS * 64);
+        const uint32_t last = (avail < (uint32_t)N ? avail : (uint32_t)N) - 1;
+        const v4u_t *src = frag + (size_t)t * (KS * 64);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t q0 = wave_base + i * NT;   // first slot of this wave's slice
+            if (q0 < (uint32_t)N) {
+                const uint32_t q = q0 + lane;
+                load_to_lds16(src + (q < last ? q : last), lds + buf * N + q0);
+            }
+        }
+        if (side) {
+            const uint32_t savail = (t1 - t) * 32u;
+            const uint32_t slast = (savail < (uint32_t)NS ? savail : (uint32_t)NS) - 1;
+#pragma unroll
+            for (int i = 0; i < SPER; ++i) {
+                const uint32_t q = threadIdx.x + i * NT;
+                rs[i] = side[(size_t)t * 32 + (q < slast ? q : slast)];
+            }
+        }
+    };
+    auto store_side = [&](int buf) __attribute__((always_inline)) {
+        if (side) {
+            uint32_t *sdst = lds_side + buf * NS;
+#pragma unroll
+            for (int i = 0; i < SPER; ++i) {
+                const uint32_t q = threadIdx.x + i * NT;
+                if (q < (uint32_t)NS) sdst[q] = rs[i];
+            }
+        }
+    };
+    auto landed = []() __attribute__((always_inline)) { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); };
+    fetch(t0, 0);
+    store_side(0);
+    landed();
+    __syncthreads();
+    int buf = 0;
+    for (uint32_t t = t0; t < t1; t += G) {
+        const bool more = t + G < t1;
+        // the other buffer was last read before the previous barrier
+        if (more) fetch(t + G, buf ^ 1);
+        const uint32_t ng = t1 - t < (uint32_t)G ? t1 - t : (uint32_t)G;
+        for (uint32_t g = 0; g < ng; ++g)
+            body(lds_in + buf * N + g * (KS * 64), side ? lds_side + buf * NS + g * 32 : nullptr);
+        if (more) {
+            store_side(buf ^ 1);
+            landed();
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+}
+
 // Other-class records, complemented, in the A-operand layout of each 32-record
 // tile: frag[(tile * KS + word) * 64 + lane] = the 32 nibbles of half (lane/32) of
 // word `word` of record tile*32 + lane%32.  Rows past n are all ones (the empty
@@ -236,107 +316,142 @@ __global__ void k_mfma_records(const uint64_t *__restrict__ NX, uint32_t n, uint
     frag[g] = make_uint4(spread8(d), spread8(d >> 8), spread8(d >> 16), spread8(d >> 24));
 }
 
+// One workgroup: 8 waves x 2 column sets x 32 candidates = 512 candidates; each
+// wave keeps its candidates' B operands in registers for the whole scan.
+constexpr int MF_NT = 512;                  // threads per matrix-core workgroup
+constexpr int MF_FB = 2;                    // 32-column sets per wave
+constexpr int MF_COLS = MF_NT / 64 * MF_FB * 32;
+// two workgroups per CU (4 waves per SIMD: at most 128 VGPRs each, 2 x 64 KB of LDS),
+// so that one workgroup's waves multiply while the other's wait at a barrier
+constexpr int MF_WAVES_PER_SIMD = 4;
 template <int KS>
-__global__ __launch_bounds__(256) void k_coherence_mfma(const uint32_t *__restrict__ cand, uint32_t ncand,
-                                                       const uint64_t *__restrict__ X, uint32_t n,
-                                                       const uint4 *__restrict__ frag, uint32_t ntiles,
-                                                       uint32_t *__restrict__ keep) {
-    __shared__ uint4 tile_frag[KS * 64];
+constexpr int mf_group() { return 32 / KS > 0 ? 32 / KS : 1; }   // tiles per LDS buffer (32 KB)
+
+template <int KS>
+__global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_coherence_mfma(const uint32_t *__restrict__ cand, uint32_t ncand,
+                                                          const uint64_t *__restrict__ X, uint32_t n,
+                                                          const uint4 *__restrict__ frag, uint32_t ntiles,
+                                                          uint32_t *__restrict__ keep) {
+    constexpr int G = mf_group<KS>();
+    __shared__ uint4 lds[2 * G * KS * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
-    const uint32_t cidx = blockIdx.x * 128u + wave * 32u + col;
-    const bool act = cidx < ncand;
-    v8i_t b[KS];
-    {
-        uint32_t i = 0, j = 0;
-        if (act) decode_pair(cand[cidx], n, i, j);
+    v8i_t b[MF_FB][KS];
+    uint32_t cidx[MF_FB];
+#pragma unroll
+    for (int f = 0; f < MF_FB; ++f) {
+        cidx[f] = blockIdx.x * MF_COLS + wave * (MF_FB * 32) + f * 32 + col;
+        const bool act = cidx[f] < ncand;
+        // loads without branches (inactive columns read candidate 0), so that they overlap
+        uint32_t i, j;
+        decode_pair(cand[act ? cidx[f] : 0u], n, i, j);
         const uint32_t *ra = reinterpret_cast<const uint32_t *>(X + (size_t)i * KS);
         const uint32_t *rb = reinterpret_cast<const uint32_t *>(X + (size_t)j * KS);
 #pragma unroll
         for (int w = 0; w < KS; ++w) {
             // inactive columns: all ones, so their result is ignored anyway
-            const uint32_t d = act ? (ra[2 * w + half] & rb[2 * w + half]) : 0xffffffffu;
-            b[w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
-                         0, 0, 0, 0};
+            const uint32_t va = ra[2 * w + half], vb = rb[2 * w + half];
+            const uint32_t d = act ? (va & vb) : 0xffffffffu;
+            b[f][w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
+                            0, 0, 0, 0};
         }
     }
-    bool covered = false;
-    for (uint32_t t = 0; t < ntiles; ++t) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < KS * 64; q += 256) tile_frag[q] = frag[(size_t)t * KS * 64 + q];
-        __syncthreads();
-        v16f_t acc = {0};
+    bool covered[MF_FB] = {};
+    if (ntiles)
+        stream_tiles<KS, G, MF_NT>(frag, nullptr, 0, ntiles, lds, nullptr, [&](const uint4 *tf, const uint32_t *) __attribute__((always_inline)) {
+            v16f_t acc[MF_FB];
 #pragma unroll
-        for (int w = 0; w < KS; ++w) {
-            const uint4 a4 = tile_frag[w * 64 + lane];
-            const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
-            acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[w], acc, 4, 4, 0, 127, 0, 127);
-        }
-        bool z = false;
+            for (int f = 0; f < MF_FB; ++f) acc[f] = v16f_t{0};
 #pragma unroll
-        for (int r = 0; r < 16; ++r) z |= acc[r] == 0.0f;
-        covered |= z;
+            for (int w = 0; w < KS; ++w) {
+                const uint4 a4 = tf[w * 64 + lane];
+                const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+#pragma unroll
+                for (int f = 0; f < MF_FB; ++f)
+                    acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
+            }
+#pragma unroll
+            for (int f = 0; f < MF_FB; ++f) {
+                bool z = false;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) z |= acc[f][r] == 0.0f;
+                covered[f] |= z;
+            }
+        });
+#pragma unroll
+    for (int f = 0; f < MF_FB; ++f) {
+        // the two halves of the wave hold different record rows of the same column
+        const uint64_t m = __ballot(covered[f]);
+        const bool col_covered = ((m >> col) & 1ull) | ((m >> (col + 32)) & 1ull);
+        if (half == 0 && cidx[f] < ncand) keep[cidx[f]] = col_covered ? 0u : 1u;
     }
-    // the two halves of the wave hold different record rows of the same column
-    const uint64_t m = __ballot(covered);
-    const bool col_covered = ((m >> col) & 1ull) | ((m >> (col + 32)) & 1ull);
-    if (half == 0 && act) keep[cidx] = col_covered ? 0u : 1u;
 }
 
 // Support (Eq. 2) as the same contraction: f(b) = number of same-class records
 // r with V[r][b] = 0.  Ordered pattern rows are the B operand; frag holds the
 // class's own complemented records (launch_mfma_records of that class).
 template <int KS>
-__global__ __launch_bounds__(256) void k_support_mfma(const uint64_t *__restrict__ Wrows, uint32_t m,
-                                                     const uint4 *__restrict__ frag, uint32_t ntiles,
-                                                     uint32_t *__restrict__ f_out, int64_t *__restrict__ S_out) {
-    __shared__ uint4 tile_frag[KS * 64];
+__global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_support_mfma(const uint64_t *__restrict__ Wrows, uint32_t m,
+                                                        const uint4 *__restrict__ frag, uint32_t ntiles,
+                                                        uint32_t *__restrict__ f_out, int64_t *__restrict__ S_out) {
+    constexpr int G = mf_group<KS>();
+    __shared__ uint4 lds[2 * G * KS * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
-    const uint32_t e = blockIdx.x * 128u + wave * 32u + col;
-    const bool act = e < m;
-    v8i_t b[KS];
-    uint32_t len = 0;
-    {
-        const uint32_t *row = reinterpret_cast<const uint32_t *>(Wrows + (size_t)(act ? e : 0) * KS);
+    v8i_t b[MF_FB][KS];
+    uint32_t e[MF_FB], len[MF_FB], cnt[MF_FB];
+#pragma unroll
+    for (int f = 0; f < MF_FB; ++f) {
+        e[f] = blockIdx.x * MF_COLS + wave * (MF_FB * 32) + f * 32 + col;
+        const bool act = e[f] < m;
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(Wrows + (size_t)(act ? e[f] : 0) * KS);
+        len[f] = 0;
+        cnt[f] = 0;
 #pragma unroll
         for (int w = 0; w < KS; ++w) {
-            const uint32_t d = act ? row[2 * w + half] : 0xffffffffu;
-            len += __popc(d);
-            b[w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
-                         0, 0, 0, 0};
+            const uint32_t v = row[2 * w + half];   // unconditional: the loads overlap
+            const uint32_t d = act ? v : 0xffffffffu;
+            len[f] += __popc(d);
+            b[f][w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
+                            0, 0, 0, 0};
         }
     }
-    uint32_t cnt = 0;
-    for (uint32_t t = 0; t < ntiles; ++t) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < KS * 64; q += 256) tile_frag[q] = frag[(size_t)t * KS * 64 + q];
-        __syncthreads();
-        v16f_t acc = {0};
+    if (ntiles)
+        stream_tiles<KS, G, MF_NT>(frag, nullptr, 0, ntiles, lds, nullptr, [&](const uint4 *tf, const uint32_t *) __attribute__((always_inline)) {
+            v16f_t acc[MF_FB];
 #pragma unroll
-        for (int w = 0; w < KS; ++w) {
-            const uint4 a4 = tile_frag[w * 64 + lane];
-            const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
-            acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[w], acc, 4, 4, 0, 127, 0, 127);
+            for (int f = 0; f < MF_FB; ++f) acc[f] = v16f_t{0};
+#pragma unroll
+            for (int w = 0; w < KS; ++w) {
+                const uint4 a4 = tf[w * 64 + lane];
+                const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+#pragma unroll
+                for (int f = 0; f < MF_FB; ++f)
+                    acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
+            }
+#pragma unroll
+            for (int f = 0; f < MF_FB; ++f)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) cnt[f] += acc[f][r] == 0.0f;
+        });
+#pragma unroll
+    for (int f = 0; f < MF_FB; ++f) {
+        // the two halves hold different record rows (and token halves) of the same column
+        const uint32_t c = cnt[f] + __shfl_xor(cnt[f], 32, 64);
+        const uint32_t l = len[f] + __shfl_xor(len[f], 32, 64);
+        if (half == 0 && e[f] < m) {
+            f_out[e[f]] = c;
+            S_out[e[f]] = (int64_t)c * (int64_t)l * (int64_t)l;
         }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) cnt += acc[r] == 0.0f;
-    }
-    // the two halves hold different record rows (and token halves) of the same column
-    cnt += __shfl_xor(cnt, 32, 64);
-    len += __shfl_xor(len, 32, 64);
-    if (half == 0 && act) {
-        f_out[e] = cnt;
-        S_out[e] = (int64_t)cnt * (int64_t)len * (int64_t)len;
     }
 }
 
 void launch_support_mfma(int KS, const uint64_t *W, size_t m, const uint4 *frag, uint32_t n, uint32_t *f,
                          int64_t *S, hipStream_t s) {
     if (!m) return;
-    const dim3 grid((unsigned)((m + 127) / 128));
+    const dim3 grid((unsigned)((m + MF_COLS - 1) / MF_COLS));
     const uint32_t ntiles = (n + 31) / 32;
-#define IG_SMF(V)                                                                                          \
-    case V:                                                                                                \
-        hipLaunchKernelGGL((k_support_mfma<V>), grid, dim3(256), 0, s, W, (uint32_t)m, frag, ntiles, f, S); \
+#define IG_SMF(V)                                                                                            \
+    case V:                                                                                                  \
+        hipLaunchKernelGGL((k_support_mfma<V>), grid, dim3(MF_NT), 0, s, W, (uint32_t)m, frag, ntiles, f, S); \
         break;
     switch (KS) {
         IG_SMF(1) IG_SMF(2) IG_SMF(3) IG_SMF(4) IG_SMF(5) IG_SMF(6) IG_SMF(7) IG_SMF(8)
@@ -378,6 +493,8 @@ struct ScoreMfmaArgs {
     const uint32_t *sc[2];
     uint32_t ntiles[2];
     uint32_t chunk;             // pattern tiles per workgroup
+    uint32_t groups[2];         // tile ranges of each class
+    uint32_t fblocks;           // workgroups over the flows
     const uint16_t *codes;      // [n][d] or null
     const uint64_t *words;      // [n][K] or null
     const uint32_t *meta;
@@ -386,21 +503,29 @@ struct ScoreMfmaArgs {
     uint32_t n_flows, d, K;
 };
 
+// Workgroup (range, flow block): the fblocks workgroups that read the same range
+// of pattern tiles get ids that differ by multiples of 8, so they are dispatched
+// to one XCD and share its L2.
 template <int KS>
-__global__ __launch_bounds__(512) void k_score_mfma(ScoreMfmaArgs a) {
-    constexpr int FB = 2;   // flow column sets per wave
-    __shared__ uint4 tile_frag[KS * 64];
-    __shared__ uint32_t tile_s[32];
-    const int cls = blockIdx.z;
-    const uint32_t t0 = blockIdx.y * a.chunk;
-    if (t0 >= a.ntiles[cls]) return;   // uniform over the workgroup
+__global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_score_mfma(ScoreMfmaArgs a) {
+    constexpr int G = mf_group<KS>();
+    __shared__ uint4 lds[2 * G * KS * 64];
+    __shared__ uint32_t lds_s[2 * G * 32];
+    const uint32_t id = blockIdx.x, xcd = id % 8, seq = id / 8;
+    const uint32_t range = (seq / a.fblocks) * 8 + xcd, fb = seq % a.fblocks;
+    if (range >= a.groups[0] + a.groups[1]) return;   // uniform over the workgroup
+    const int cls = range < a.groups[0] ? 0 : 1;
+    const uint32_t t0 = (cls ? range - a.groups[0] : range) * a.chunk;
     const uint32_t t1 = t0 + a.chunk < a.ntiles[cls] ? t0 + a.chunk : a.ntiles[cls];
+    if (t0 >= t1) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
-    v8i_t b[FB][KS];
-    uint64_t sum[FB];
+    v8i_t b[MF_FB][KS];
+    uint64_t sum[MF_FB];
+    uint32_t tf[MF_FB];
 #pragma unroll
-    for (int f = 0; f < FB; ++f) {
-        const uint32_t t = blockIdx.x * (8 * FB * 32) + wave * (FB * 32) + f * 32 + col;
+    for (int f = 0; f < MF_FB; ++f) {
+        const uint32_t t = fb * MF_COLS + wave * (MF_FB * 32) + f * 32 + col;
+        tf[f] = t;
         const bool act = t < a.n_flows;
         uint64_t wd[KS];
         bool ok = act;
@@ -432,38 +557,36 @@ __global__ __launch_bounds__(512) void k_score_mfma(ScoreMfmaArgs a) {
         }
         sum[f] = 0;
     }
-    const uint4 *frag = a.frag[cls];
-    const uint32_t *sc = a.sc[cls];
-    for (uint32_t t = t0; t < t1; ++t) {
-        __syncthreads();
-        if (threadIdx.x < KS * 64) tile_frag[threadIdx.x] = frag[(size_t)t * KS * 64 + threadIdx.x];
-        if (threadIdx.x < 32) tile_s[threadIdx.x] = sc[(size_t)t * 32 + threadIdx.x];
-        __syncthreads();
+    stream_tiles<KS, G, MF_NT>(a.frag[cls], a.sc[cls], t0, t1, lds, lds_s, [&](const uint4 *tile, const uint32_t *ws) __attribute__((always_inline)) {
+        v16f_t acc[MF_FB];
+#pragma unroll
+        for (int f = 0; f < MF_FB; ++f) acc[f] = v16f_t{0};
+#pragma unroll
+        for (int w = 0; w < KS; ++w) {
+            const uint4 a4 = tile[w * 64 + lane];
+            const v8i_t av = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+#pragma unroll
+            for (int f = 0; f < MF_FB; ++f)
+                acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
+        }
         uint32_t s16[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) s16[r] = tile_s[half * 16 + r];
+        for (int r = 0; r < 16; ++r) s16[r] = ws[half * 16 + r];
 #pragma unroll
-        for (int f = 0; f < FB; ++f) {
-            v16f_t acc = {0};
-#pragma unroll
-            for (int w = 0; w < KS; ++w) {
-                const uint4 a4 = tile_frag[w * 64 + lane];
-                const v8i_t av = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
-                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, b[f][w], acc, 4, 4, 0, 127, 0, 127);
-            }
+        for (int f = 0; f < MF_FB; ++f) {
             uint32_t lo = 0;   // 16 weights below 2^28 each: no wrap
 #pragma unroll
-            for (int r = 0; r < 16; ++r) lo += acc[r] == 0.0f ? s16[r] : 0u;
+            for (int r = 0; r < 16; ++r) lo += acc[f][r] == 0.0f ? s16[r] : 0u;
             sum[f] += lo;
         }
-    }
+    });
     const int colsel = cls == 1 ? 0 : 1;   // A from class 1, N from class 0
 #pragma unroll
-    for (int f = 0; f < FB; ++f) {
-        uint64_t v = sum[f] + __shfl_xor(sum[f], 32, 64);   // the two halves hold different rows
-        const uint32_t t = blockIdx.x * (8 * FB * 32) + wave * (FB * 32) + f * 32 + col;
-        if (half == 0 && t < a.n_flows && v)
-            atomicAdd(reinterpret_cast<unsigned long long *>(a.out + 2 * (size_t)t + colsel), (unsigned long long)v);
+    for (int f = 0; f < MF_FB; ++f) {
+        const uint64_t v = sum[f] + __shfl_xor(sum[f], 32, 64);   // the two halves hold different rows
+        if (half == 0 && tf[f] < a.n_flows && v)
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.out + 2 * (size_t)tf[f] + colsel),
+                      (unsigned long long)v);
     }
 }
 
@@ -491,11 +614,11 @@ void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *fra
 void launch_coherence_mfma(int KS, const uint32_t *cand, uint32_t ncand, const uint64_t *X, uint32_t n,
                            const uint4 *frag, uint32_t n_o, uint32_t *keep, hipStream_t s) {
     if (!ncand) return;
-    const dim3 grid((ncand + 127) / 128);
+    const dim3 grid((ncand + MF_COLS - 1) / MF_COLS);
     const uint32_t ntiles = mfma_record_tiles(n_o);
-#define IG_MF(V)                                                                                             \
-    case V:                                                                                                  \
-        hipLaunchKernelGGL((k_coherence_mfma<V>), grid, dim3(256), 0, s, cand, ncand, X, n, frag, ntiles, keep); \
+#define IG_MF(V)                                                                                               \
+    case V:                                                                                                    \
+        hipLaunchKernelGGL((k_coherence_mfma<V>), grid, dim3(MF_NT), 0, s, cand, ncand, X, n, frag, ntiles, keep); \
         break;
     switch (KS) {
         IG_MF(1) IG_MF(2) IG_MF(3) IG_MF(4) IG_MF(5) IG_MF(6) IG_MF(7) IG_MF(8)
@@ -892,18 +1015,21 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     a.n_flows = n_flows;
     a.d = d;
     a.K = K;
-    const uint32_t fblocks = (n_flows + 511) / 512;
-    const uint32_t maxt = a.ntiles[0] > a.ntiles[1] ? a.ntiles[0] : a.ntiles[1];
-    if (!maxt) return;
-    uint32_t ychunks = (2048 + 2 * fblocks - 1) / (2 * fblocks);
-    if (ychunks > maxt) ychunks = maxt;
-    if (ychunks > 65535) ychunks = 65535;
-    a.chunk = (maxt + ychunks - 1) / ychunks;
-    const uint32_t ny = (maxt + a.chunk - 1) / a.chunk;
-    dim3 grid(fblocks, ny, 2);
+    a.fblocks = (n_flows + MF_COLS - 1) / MF_COLS;
+    const uint32_t tiles = a.ntiles[0] + a.ntiles[1];
+    if (!tiles) return;
+    // about 2048 workgroups in all: several per CU, short tail
+    uint32_t ranges = (2048 + a.fblocks - 1) / a.fblocks;
+    if (ranges > tiles) ranges = tiles;
+    a.chunk = (tiles + ranges - 1) / ranges;
+    a.groups[0] = (a.ntiles[0] + a.chunk - 1) / a.chunk;
+    a.groups[1] = (a.ntiles[1] + a.chunk - 1) / a.chunk;
+    const uint64_t nr = ((uint64_t)a.groups[0] + a.groups[1] + 7) / 8 * 8;
+    IG_REQUIRE(nr * a.fblocks < (1ull << 31), IG_E_UNSUPPORTED, "too many flows for one scoring launch");
+    const dim3 grid((unsigned)(nr * a.fblocks));
 #define IG_SCM(V)                                                                    \
     case V:                                                                          \
-        hipLaunchKernelGGL((k_score_mfma<V>), grid, dim3(512), 0, s, a);            \
+        hipLaunchKernelGGL((k_score_mfma<V>), grid, dim3(MF_NT), 0, s, a);          \
         break;
     switch ((int)m.KS) {
         IG_SCM(1) IG_SCM(2) IG_SCM(3) IG_SCM(4) IG_SCM(5) IG_SCM(6) IG_SCM(7) IG_SCM(8)

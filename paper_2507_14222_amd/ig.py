@@ -20,6 +20,7 @@ IG_OK, IG_E_INVAL, IG_E_NOMEM, IG_E_DEVICE, IG_E_OVERFLOW, IG_E_UNSUPPORTED = 0,
 _NAMES = {0: "IG_OK", -1: "IG_E_INVAL", -2: "IG_E_NOMEM", -3: "IG_E_DEVICE", -4: "IG_E_OVERFLOW",
           -5: "IG_E_UNSUPPORTED"}
 ABSENT = 0xFFFF
+IG_MODEL_SCORE_MFMA = 1   # ModelInfo.flags: scoring runs on the matrix cores
 
 
 class IGError(RuntimeError):
@@ -46,7 +47,7 @@ class Stats(C.Structure):
 
 
 class ModelInfo(C.Structure):
-    _fields_ = [("K", C.c_uint32), ("L", C.c_uint32), ("d", C.c_uint32), ("reserved", C.c_uint32),
+    _fields_ = [("K", C.c_uint32), ("L", C.c_uint32), ("d", C.c_uint32), ("flags", C.c_uint32),
                 ("n_patterns", C.c_uint64 * 2), ("max_weight", C.c_int64 * 2)]
 
 
@@ -187,6 +188,10 @@ class Model:
     @property
     def K(self) -> int:
         return int(self.info().K)
+
+    @property
+    def score_on_matrix_cores(self) -> bool:
+        return bool(self.info().flags & IG_MODEL_SCORE_MFMA)
 
     def n_patterns(self) -> Tuple[int, int]:
         i = self.info()

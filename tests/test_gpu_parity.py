@@ -126,6 +126,8 @@ def test_random_problem_parity(case):
     assert_same_stats(m, om)
     m = ig.fit(p.codes, p.labels, p.nbins)   # default kernels (matrix cores when K <= 8)
     assert_same_model(m, om, om.K)
+    info = m.info()
+    assert m.score_on_matrix_cores == (om.K <= 8 and max(info.max_weight) < 2 ** 28)
     flows = synth.make_random_problem(seed + 1000, 97, d, bins_lo=blo, bins_hi=bhi).codes
     flows = np.minimum(flows, p.nbins[None, :] - 1).astype(np.uint16)
     flows = np.concatenate([flows, p.codes[: min(40, p.n)]])
