@@ -67,6 +67,8 @@ struct DevModel {
     uint16_t *nbins = nullptr;
     uint4 *frag[2] = {nullptr, nullptr};   // matrix-core scoring operands (KS <= 8)
     uint32_t *sc[2] = {nullptr, nullptr};
+    KeyPiece *pieces = nullptr;            // compressed sort keys (fits from codes), or null
+    uint32_t npieces = 0, nkeys = 0;
     ig_stats stats{};
 
     ~DevModel() {
@@ -81,6 +83,7 @@ struct DevModel {
         }
         if (meta) (void)hipFree(meta);
         if (nbins) (void)hipFree(nbins);
+        if (pieces) (void)hipFree(pieces);
     }
 };
 
@@ -120,6 +123,52 @@ static std::vector<uint32_t> token_tables(const uint16_t *nbins, uint32_t d, uin
         t[d + KS + k] = fhi;
     }
     return t;
+}
+
+// Pieces of the compressed sort keys (see KeyPiece): every (feature, word) overlap,
+// most significant first -- words ascending, higher bits first within a word --
+// each taking ceil(log2(width + 1)) key bits; a piece never straddles key words.
+// Returns the number of key words, or 0 when compression would not save a word.
+static uint32_t key_pieces(const uint16_t *nbins, uint32_t d, uint32_t K, std::vector<KeyPiece> &out) {
+    out.clear();
+    uint32_t off = 0;
+    for (uint32_t f = 0; f < d; ++f) {
+        const uint32_t a = off, b = off + nbins[f];
+        for (uint32_t t = a; t < b;) {
+            const uint32_t w = t / 64, hi = std::min(b, 64 * (w + 1));
+            KeyPiece p{};
+            p.word = (uint8_t)w;
+            p.lo = (uint8_t)(t % 64);
+            p.width = (uint8_t)(hi - t);
+            out.push_back(p);
+            t = hi;
+        }
+        off = b;
+    }
+    std::sort(out.begin(), out.end(), [](const KeyPiece &x, const KeyPiece &y) {
+        return x.word != y.word ? x.word < y.word : x.lo > y.lo;
+    });
+    uint32_t kw = 0, used = 0;
+    for (KeyPiece &p : out) {
+        const uint32_t cb = 32 - __builtin_clz((uint32_t)p.width);   // codes 0..width
+        if (used + cb > 64) { ++kw; used = 0; }
+        p.kw = (uint8_t)kw;
+        p.shift = (uint8_t)(64 - used - cb);
+        used += cb;
+    }
+    const uint32_t nk = out.empty() ? 0 : kw + 1;
+    return nk < K ? nk : 0;
+}
+
+static void set_key_pieces(DevModel &m, const uint16_t *h_nbins, uint32_t d, hipStream_t s) {
+    std::vector<KeyPiece> pc;
+    const uint32_t nk = key_pieces(h_nbins, d, m.K, pc);
+    if (!nk) return;
+    m.pieces = dev_alloc<KeyPiece>(pc.size());
+    IG_HIP(hipMemcpyAsync(m.pieces, pc.data(), pc.size() * sizeof(KeyPiece), hipMemcpyHostToDevice, s));
+    IG_HIP(hipStreamSynchronize(s));   // pc must outlive its copy
+    m.npieces = (uint32_t)pc.size();
+    m.nkeys = nk;
 }
 
 static void check_nbins(const uint16_t *h_nbins, uint32_t d, uint32_t &L, uint32_t &K) {
@@ -218,27 +267,69 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         m.S[c] = dev_alloc<int64_t>(1);
         return;
     }
-    // which bytes of which words vary at all
-    Scratch<unsigned long long> rng(2 * K, s);
-    launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get()), 0ull, K, s);
-    launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get() + K), ~0ull, K, s);
-    launch_word_range(cls.X.get(), cls.n, KS, K, ids, count, rng.get(), rng.get() + K, s);
-    std::vector<unsigned long long> hr(2 * K);
-    IG_HIP(hipMemcpyAsync(hr.data(), rng.get(), 2 * K * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    IG_HIP(hipStreamSynchronize(s));
-
-    Scratch<uint64_t> k0(count, s), k1(count, s);
-    Scratch<uint32_t> v1(count, s);
-    uint32_t *vcur = ids, *valt = v1.get();
-    for (int k = (int)K - 1; k >= 0; --k) {
-        uint64_t vary = hr[k] ^ hr[K + k];
+    auto byte_mask = [](unsigned long long orv, unsigned long long andv) {
+        const uint64_t vary = orv ^ andv;   // bits that differ somewhere
         uint32_t mask = 0;
         for (int b = 0; b < 8; ++b)
             if ((vary >> (8 * b)) & 0xffull) mask |= 1u << b;
-        if (!mask) continue;
-        launch_gather_word(cls.X.get(), cls.n, KS, (uint32_t)k, vcur, count, k0.get(), s);
-        int where = radix_sort_pairs(k0.get(), vcur, k1.get(), valt, count, mask, s);
-        if (where) std::swap(vcur, valt);
+        return mask;
+    };
+    Scratch<uint64_t> k0, k1;
+    Scratch<uint32_t> v1, sorted_ids;
+    uint32_t *vcur = ids, *valt = nullptr;
+    if (m.pieces) {
+        // compressed keys: LSD radix sort of a permutation over the key words
+        const uint32_t nk = m.nkeys;
+        Scratch<uint64_t> keys((size_t)nk * count, s);
+        launch_compress_keys(cls.X.get(), cls.n, KS, ids, count, m.pieces, m.npieces, keys.get(), s);
+        Scratch<unsigned long long> rng(2 * nk, s);
+        launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get()), 0ull, nk, s);
+        launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get() + nk), ~0ull, nk, s);
+        launch_key_range(keys.get(), nk, count, rng.get(), rng.get() + nk, s);
+        std::vector<unsigned long long> hr(2 * nk);
+        IG_HIP(hipMemcpyAsync(hr.data(), rng.get(), 2 * nk * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        IG_HIP(hipStreamSynchronize(s));
+        Scratch<uint32_t> perm(count, s), palt(count, s);
+        k1.reset(count, s);
+        k0.reset(count, s);
+        launch_iota(perm.get(), count, s);
+        uint32_t *pcur = perm.get(), *pnext = palt.get();
+        bool identity = true;   // pcur is still the identity permutation
+        for (int k = (int)nk - 1; k >= 0; --k) {
+            const uint32_t mask = byte_mask(hr[k], hr[nk + k]);
+            if (!mask) continue;
+            uint64_t *kin = keys.get() + (size_t)k * count;   // consumed: the sort may overwrite it
+            if (!identity) {
+                launch_permute_u64(kin, pcur, count, k0.get(), s);
+                kin = k0.get();
+            }
+            const int where = radix_sort_pairs(kin, pcur, k1.get(), pnext, count, mask, s);
+            if (where) std::swap(pcur, pnext);
+            identity = false;
+        }
+        sorted_ids.reset(count, s);
+        launch_permute_u32(ids, pcur, count, sorted_ids.get(), s);
+        vcur = sorted_ids.get();
+    } else {
+        // which bytes of which words vary at all
+        Scratch<unsigned long long> rng(2 * K, s);
+        launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get()), 0ull, K, s);
+        launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get() + K), ~0ull, K, s);
+        launch_word_range(cls.X.get(), cls.n, KS, K, ids, count, rng.get(), rng.get() + K, s);
+        std::vector<unsigned long long> hr(2 * K);
+        IG_HIP(hipMemcpyAsync(hr.data(), rng.get(), 2 * K * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        IG_HIP(hipStreamSynchronize(s));
+        k0.reset(count, s);
+        k1.reset(count, s);
+        v1.reset(count, s);
+        valt = v1.get();
+        for (int k = (int)K - 1; k >= 0; --k) {
+            const uint32_t mask = byte_mask(hr[k], hr[K + k]);
+            if (!mask) continue;
+            launch_gather_word(cls.X.get(), cls.n, KS, (uint32_t)k, vcur, count, k0.get(), s);
+            int where = radix_sort_pairs(k0.get(), vcur, k1.get(), valt, count, mask, s);
+            if (where) std::swap(vcur, valt);
+        }
     }
     Scratch<uint64_t> Wtmp;
     Scratch<uint32_t> flag;
@@ -597,6 +688,7 @@ DevModel *fit_codes(const uint16_t *d_codes, const uint8_t *d_labels, uint32_t n
     m->nbins = dev_alloc<uint16_t>(d);
     IG_HIP(hipMemcpyAsync(m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
     IG_HIP(hipMemcpyAsync(m->nbins, h_nbins, d * 2, hipMemcpyHostToDevice, s));
+    set_key_pieces(*m, h_nbins, d, s);
     Scratch<uint32_t> err(1, s), pos(n ? n : 1, s), counts(2, s);
     launch_fill_u32(err.get(), 0u, 1, s);
     launch_fill_u32(counts.get(), 0u, 2, s);
@@ -898,6 +990,7 @@ void fit_batch(const ig_problem *probs, uint32_t np, const ig_fit_opts *opts, hi
         IG_HIP(hipMemcpyAsync(b.m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
         IG_HIP(hipMemcpyAsync(b.m->nbins, b.nbins, b.d * 2, hipMemcpyHostToDevice, s));
         IG_HIP(hipStreamSynchronize(s));   // the host table must outlive its copy
+        set_key_pieces(*b.m, b.nbins, b.d, s);
         b.err.reset(1, s);
         b.pos.reset(b.n ? b.n : 1, s);
         b.counts.reset(2, s);

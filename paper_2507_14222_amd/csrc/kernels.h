@@ -43,6 +43,26 @@ void launch_gather_rows(const uint64_t *W, const uint32_t *ids, size_t m, uint32
 void launch_row_word(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint32_t k, uint64_t *keys,
                      hipStream_t s);
 void launch_iota(uint32_t *v, size_t m, hipStream_t s);
+
+// Compressed sort keys of patterns of a fit from codes.  Inside one 64-bit word
+// the tokens of one feature form a piece with at most one set bit in any pattern
+// (a record has one bin per feature and an intersection keeps at most that one).
+// A piece's code is 0 when empty, else 1 + the index of its set bit; the codes,
+// most significant piece first (words ascending, higher bits first within a
+// word), are packed into key words kw = 0, 1, ...  Comparing key words as
+// unsigned (kw0, kw1, ...) orders patterns exactly as comparing (w0, w1, ...).
+struct KeyPiece {
+    uint8_t word, lo, width, kw, shift, pad[3];   // bits [lo, lo+width) of word -> kw << shift
+};
+// keys[k * m + e] = key word k of pattern ids[e]
+void launch_compress_keys(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m,
+                          const KeyPiece *pieces, uint32_t npieces, uint64_t *keys, hipStream_t s);
+// OR and AND of each of nk key arrays of length m (orv/andv preset to 0 / ~0)
+void launch_key_range(const uint64_t *keys, uint32_t nk, size_t m, unsigned long long *orv,
+                      unsigned long long *andv, hipStream_t s);
+// out[e] = src[perm[e]]
+void launch_permute_u64(const uint64_t *src, const uint32_t *perm, size_t m, uint64_t *out, hipStream_t s);
+void launch_permute_u32(const uint32_t *src, const uint32_t *perm, size_t m, uint32_t *out, hipStream_t s);
 // count of ordered rows equal to their predecessor (0 = all distinct)
 void launch_adjacent_equal(const uint64_t *W, size_t m, uint32_t KS, uint32_t *d_count, hipStream_t s);
 // S = f * popcount^2 (Eq. 2) for given rows and supports

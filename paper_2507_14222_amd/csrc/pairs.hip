@@ -344,4 +344,96 @@ void launch_iota(uint32_t *v, size_t m, hipStream_t s) {
     IG_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------ compressed sort keys ----
+// Pieces come sorted by key word, then significance, so each lane walks them in
+// order: a row word is loaded when the piece list reaches it, a key word is
+// written when the list leaves it.  The piece list is uniform over the wave.
+__global__ __launch_bounds__(256) void k_compress_keys(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS,
+                                                      const uint32_t *__restrict__ ids, size_t m,
+                                                      const KeyPiece *__restrict__ pieces, uint32_t npieces,
+                                                      uint64_t *__restrict__ keys) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    uint32_t i, j;
+    decode_pair(ids[e], n, i, j);
+    const uint64_t *ra = X + (size_t)i * KS, *rb = X + (size_t)j * KS;
+    uint32_t cur_word = 0xffffffffu, cur_kw = 0;
+    uint64_t word = 0, acc = 0;
+    for (uint32_t p = 0; p < npieces; ++p) {
+        const KeyPiece g = pieces[p];
+        if (g.word != cur_word) {
+            cur_word = g.word;
+            word = ra[cur_word] & rb[cur_word];
+        }
+        if (g.kw != cur_kw) {
+            keys[(size_t)cur_kw * m + e] = acc;
+            acc = 0;
+            cur_kw = g.kw;
+        }
+        const uint64_t x = (word >> g.lo) & (g.width >= 64 ? ~0ull : ((1ull << g.width) - 1));
+        const uint64_t code = x ? (uint64_t)__ffsll((unsigned long long)x) : 0ull;
+        acc |= code << g.shift;
+    }
+    keys[(size_t)cur_kw * m + e] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_key_range(const uint64_t *__restrict__ keys, size_t m,
+                                                  unsigned long long *__restrict__ orv,
+                                                  unsigned long long *__restrict__ andv) {
+    __shared__ unsigned long long so[4], sa[4];
+    const uint32_t k = blockIdx.y;
+    const uint64_t *kk = keys + (size_t)k * m;
+    uint64_t o = 0, a = ~0ull;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t v = kk[e];
+        o |= v;
+        a &= v;
+    }
+    for (int sh = 32; sh > 0; sh >>= 1) {
+        o |= __shfl_xor(o, sh, 64);
+        a &= __shfl_xor(a, sh, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { so[wave] = o; sa[wave] = a; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicOr(&orv[k], so[0] | so[1] | so[2] | so[3]);
+        atomicAnd(&andv[k], sa[0] & sa[1] & sa[2] & sa[3]);
+    }
+}
+
+template <class T>
+__global__ void k_permute(const T *__restrict__ src, const uint32_t *__restrict__ perm, size_t m, T *__restrict__ out) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) out[e] = src[perm[e]];
+}
+
+void launch_compress_keys(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m,
+                          const KeyPiece *pieces, uint32_t npieces, uint64_t *keys, hipStream_t s) {
+    if (!m) return;
+    hipLaunchKernelGGL(k_compress_keys, blocks_for(m), dim3(256), 0, s, X, n, KS, ids, m, pieces, npieces, keys);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_key_range(const uint64_t *keys, uint32_t nk, size_t m, unsigned long long *orv,
+                      unsigned long long *andv, hipStream_t s) {
+    if (!m || !nk) return;
+    unsigned g = (unsigned)((m + 255) / 256);
+    if (g > 256) g = 256;
+    hipLaunchKernelGGL(k_key_range, dim3(g, nk), dim3(256), 0, s, keys, m, orv, andv);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_permute_u64(const uint64_t *src, const uint32_t *perm, size_t m, uint64_t *out, hipStream_t s) {
+    if (!m) return;
+    hipLaunchKernelGGL(k_permute<uint64_t>, blocks_for(m), dim3(256), 0, s, src, perm, m, out);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_permute_u32(const uint32_t *src, const uint32_t *perm, size_t m, uint32_t *out, hipStream_t s) {
+    if (!m) return;
+    hipLaunchKernelGGL(k_permute<uint32_t>, blocks_for(m), dim3(256), 0, s, src, perm, m, out);
+    IG_HIP(hipGetLastError());
+}
+
 }  // namespace ig
