@@ -15,6 +15,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -26,32 +27,128 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string &m) { g_last_error = m; }
 
-// ------------------------------------------------------------ scratch pool ----
-static std::once_flag g_pool_once[64];
+// ----------------------------------------------------------- scratch cache ----
+// Scratch comes from a per-device cache of device blocks: allocating and freeing
+// multi-hundred-MB buffers through the runtime cost milliseconds of host time per
+// call, during which the GPU idles between the stages of a fit.  A freed block
+// keeps an event recorded on the freeing stream; whoever takes the block next
+// makes its own stream wait for that event first (free when it is the same
+// stream).  Blocks go back to the runtime only when an allocation fails (the
+// cache is emptied and the allocation retried) or the cached bytes pass a cap.
+namespace {
+struct CachedBlock {
+    void *p;
+    size_t bytes;
+    int dev;
+    hipEvent_t ev;
+};
+struct ScratchCache {
+    std::mutex mu;
+    std::vector<CachedBlock> free_blocks;
+    std::unordered_map<void *, std::pair<size_t, int>> live;   // block -> (bytes, device)
+    std::vector<hipEvent_t> spare_events[64];
+    size_t cached_bytes[64] = {};
+};
+ScratchCache &cache() {
+    static ScratchCache *c = new ScratchCache();   // never destroyed: frees may run at exit
+    return *c;
+}
+constexpr size_t kCacheCap = 32ull << 30;   // cached free bytes per device
 
-static void configure_pool(int dev) {
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+size_t round_bytes(size_t b) {
+    if (b <= 4096) return 4096;
+    const int lg = 63 - __builtin_clzll((unsigned long long)(b - 1));
+    const size_t step = (size_t)1 << (lg - 3);   // eight sizes per power of two
+    return (b + step - 1) / step * step;
+}
+
+// release cached blocks of `dev` (caller holds the lock) until at most `keep` bytes remain
+void release_cached(ScratchCache &c, int dev, size_t keep) {
+    std::sort(c.free_blocks.begin(), c.free_blocks.end(),
+              [](const CachedBlock &x, const CachedBlock &y) { return x.bytes < y.bytes; });
+    for (size_t i = c.free_blocks.size(); i-- > 0 && c.cached_bytes[dev] > keep;) {
+        CachedBlock b = c.free_blocks[i];
+        if (b.dev != dev) continue;
+        (void)hipEventSynchronize(b.ev);
+        (void)hipFree(b.p);
+        c.spare_events[dev].push_back(b.ev);
+        c.cached_bytes[dev] -= b.bytes;
+        c.free_blocks.erase(c.free_blocks.begin() + (ptrdiff_t)i);
     }
 }
+}  // namespace
 
 void *scratch_alloc(size_t bytes, hipStream_t s) {
     int dev = 0;
     IG_HIP(hipGetDevice(&dev));
-    if (dev >= 0 && dev < 64) std::call_once(g_pool_once[dev], configure_pool, dev);
+    IG_REQUIRE(dev >= 0 && dev < 64, IG_E_UNSUPPORTED, "device index above 63");
+    const size_t want = round_bytes(bytes ? bytes : 1);
+    ScratchCache &c = cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    size_t best = SIZE_MAX, bi = 0;
+    for (size_t i = 0; i < c.free_blocks.size(); ++i) {
+        const CachedBlock &b = c.free_blocks[i];
+        if (b.dev == dev && b.bytes >= want && b.bytes <= 2 * want && b.bytes < best) {
+            best = b.bytes;
+            bi = i;
+        }
+    }
+    if (best != SIZE_MAX) {
+        CachedBlock b = c.free_blocks[bi];
+        IG_HIP(hipStreamWaitEvent(s, b.ev, 0));
+        c.free_blocks.erase(c.free_blocks.begin() + (ptrdiff_t)bi);
+        c.spare_events[dev].push_back(b.ev);
+        c.cached_bytes[dev] -= b.bytes;
+        c.live[b.p] = {b.bytes, dev};
+        return b.p;
+    }
     void *p = nullptr;
-    hipError_t e = hipMallocAsync(&p, bytes, s);
+    hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess || !p) {
         (void)hipGetLastError();
-        throw Error(IG_E_NOMEM, "device scratch allocation of " + std::to_string(bytes) + " bytes failed");
+        release_cached(c, dev, 0);
+        e = hipMalloc(&p, want);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            throw Error(IG_E_NOMEM, "device scratch allocation of " + std::to_string(bytes) + " bytes failed");
+        }
     }
+    c.live[p] = {want, dev};
     return p;
 }
 
-void scratch_free(void *p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+void scratch_free(void *p, hipStream_t s) noexcept {
+    if (!p) return;
+    ScratchCache &c = cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;
+    const size_t bytes = it->second.first;
+    const int dev = it->second.second;
+    c.live.erase(it);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(s, &cap);
+    hipEvent_t ev = nullptr;
+    if (cap == hipStreamCaptureStatusNone) {
+        if (!c.spare_events[dev].empty()) {
+            ev = c.spare_events[dev].back();
+            c.spare_events[dev].pop_back();
+        } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            ev = nullptr;
+        }
+    }
+    if (!ev || hipEventRecord(ev, s) != hipSuccess) {
+        // no event to order a later user after this stream's work: wait here instead
+        (void)hipGetLastError();
+        if (ev) c.spare_events[dev].push_back(ev);
+        if (cap == hipStreamCaptureStatusNone) (void)hipStreamSynchronize(s);
+        (void)hipFree(p);
+        return;
+    }
+    c.free_blocks.push_back({p, bytes, dev, ev});
+    c.cached_bytes[dev] += bytes;
+    if (c.cached_bytes[dev] > kCacheCap) release_cached(c, dev, kCacheCap / 2);
 }
 
 // --------------------------------------------------------------- the model ----
@@ -399,6 +496,11 @@ static std::vector<uint32_t> coherence_phases(uint32_t max_other) {
     return std::vector<uint32_t>{std::max<uint32_t>(max_other, 1)};
 }
 
+// Bytes of the (class, hash) keys that the de-duplication sorts on: 1 class bit and
+// 39 hash bits.  Distinct intersections that share a key are told apart by the
+// full comparison; at 2^24 distinct per class about 2^8 pairs of them do.
+constexpr int kPairKeyBytes = 5;
+
 static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts, hipStream_t s, Timer &tm) {
     const uint32_t KS = m.KS, K = m.K;
     const Tuning tu = tuning_for(opts, KS, (uint64_t)cls[0].n * (cls[0].n ? cls[0].n - 1 : 0) / 2 +
@@ -492,11 +594,12 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         uint64_t at = 0;
         for (auto &p : ch) {
             launch_pair_hash(cls[p.c].X.get(), cls[p.c].n, KS, K, p.q0, p.cnt, (uint32_t)p.c, 1, k0.get() + at,
-                             v0.get() + at, s);
+                             v0.get() + at, s, kPairKeyBytes);
             at += p.cnt;
         }
         IG_HIP(hipEventRecord(e[1], s));
-        int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items, 0xffu, s);
+        int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items,
+                                     0xffu & ~((1u << (8 - kPairKeyBytes)) - 1), s);
         uint64_t *ks = where ? k1.get() : k0.get();
         uint32_t *vs = where ? v1.get() : v0.get();
         IG_HIP(hipEventRecord(e[2], s));

@@ -31,10 +31,11 @@ struct Error : std::runtime_error {
     } while (0)
 
 // ------------------------------------------------------------ device memory ----
-// Stream-ordered scratch (hipMallocAsync on the call's stream).  The default pool
-// keeps freed blocks, so repeated fits reuse memory without new device allocations.
+// Stream-ordered scratch from a per-device block cache: a block freed on one
+// stream is handed to a later allocation only after that allocation's stream
+// has been made to wait for the freeing stream's work.
 void *scratch_alloc(size_t bytes, hipStream_t s);
-void scratch_free(void *p, hipStream_t s);
+void scratch_free(void *p, hipStream_t s) noexcept;
 
 template <class T>
 struct Scratch {
@@ -54,9 +55,7 @@ struct Scratch {
         p = nullptr;
         n = 0;
     }
-    ~Scratch() {
-        if (p) (void)hipFreeAsync(p, s);
-    }
+    ~Scratch() { scratch_free(p, s); }
     Scratch(const Scratch &) = delete;
     Scratch &operator=(const Scratch &) = delete;
     Scratch(Scratch &&o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }

@@ -19,8 +19,10 @@ void launch_pack_patterns(const uint16_t *codes, uint32_t m, uint32_t d, uint32_
                           const uint16_t *nbins, uint64_t *W, uint32_t *err, hipStream_t s);
 
 // pairs.hip
+// key_bytes: only the top key_bytes bytes of each key are kept (the rest zero), so a
+// radix sort needs only that many passes; equal keys are compared in full anyway.
 void launch_pair_hash(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, uint64_t q0, uint64_t count,
-                      uint32_t seg, int segbits, uint64_t *keys, uint32_t *vals, hipStream_t s);
+                      uint32_t seg, int segbits, uint64_t *keys, uint32_t *vals, hipStream_t s, int key_bytes = 8);
 size_t rows_of_seg_size();
 void fill_rows_of_seg(void *dst, const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K);
 void launch_dedup_flags(const uint64_t *keys, const uint32_t *vals, size_t m, const void *segs_dev, int segbits,

@@ -20,11 +20,11 @@ __device__ __forceinline__ uint64_t mix64(uint64_t h) {
     return h;
 }
 
-// keys[e] = (segment id in the top `segbits` bits) | (hash of b >> segbits),
-// vals[e] = q, for q in [q0, q0 + count).  Empty intersections get the
-// sentinel (~0, ~0) and are dropped by the de-duplication.
+// keys[e] = (segment id in the top `segbits` bits) | (hash of b >> segbits), with
+// the bits under `keep` cleared, vals[e] = q, for q in [q0, q0 + count).  Empty
+// intersections get the sentinel (~0, ~0) and are dropped by the de-duplication.
 __global__ void k_pair_hash(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS, uint32_t K, uint64_t q0,
-                            uint64_t count, uint64_t seg_hi, int segbits, uint64_t *__restrict__ keys,
+                            uint64_t count, uint64_t seg_hi, int segbits, uint64_t keep, uint64_t *__restrict__ keys,
                             uint32_t *__restrict__ vals) {
     uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
@@ -40,7 +40,7 @@ __global__ void k_pair_hash(const uint64_t *__restrict__ X, uint32_t n, uint32_t
         h = mix64(h ^ b) + 0x632be59bd9b4e019ull;
     }
     if (any) {
-        keys[e] = seg_hi | (h >> segbits);
+        keys[e] = (seg_hi | (h >> segbits)) & keep;
         vals[e] = (uint32_t)q;
     } else {
         keys[e] = ~0ull;
@@ -240,11 +240,12 @@ __global__ void k_weights(const uint64_t *__restrict__ W, const uint32_t *__rest
 static dim3 blocks_for(size_t n, unsigned bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
 void launch_pair_hash(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, uint64_t q0, uint64_t count,
-                      uint32_t seg, int segbits, uint64_t *keys, uint32_t *vals, hipStream_t s) {
+                      uint32_t seg, int segbits, uint64_t *keys, uint32_t *vals, hipStream_t s, int key_bytes) {
     if (!count) return;
     uint64_t seg_hi = (uint64_t)seg << (64 - segbits);
-    hipLaunchKernelGGL(k_pair_hash, blocks_for(count), dim3(256), 0, s, X, n, KS, K, q0, count, seg_hi, segbits, keys,
-                       vals);
+    const uint64_t keep = key_bytes >= 8 ? ~0ull : ~((1ull << (64 - 8 * key_bytes)) - 1);
+    hipLaunchKernelGGL(k_pair_hash, blocks_for(count), dim3(256), 0, s, X, n, KS, K, q0, count, seg_hi, segbits, keep,
+                       keys, vals);
     IG_HIP(hipGetLastError());
 }
 
