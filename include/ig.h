@@ -84,14 +84,19 @@ typedef struct {
     uint32_t n_tune;            /* rows in `tune`                                     */
     const ig_tune_entry *tune;  /* host tuning table (may be NULL)                    */
     uint32_t coherence_mfma;    /* coherence (Eq. 3) and support (Eq. 2) kernels:
-                                   0 = automatic: matrix cores when K <= 8 words,
-                                       else the VALU path;
-                                   1 = matrix cores (K <= 8): a dense 0/1 contraction
-                                       with fp4 operands and fp32 accumulation, exact;
-                                       no early exit, so ig_stats.tests counts every
-                                       (candidate, other-class record) pair;
+                                   0 = automatic: matrix cores when the operands fit
+                                       8 words, else the VALU path;
+                                   1 = matrix cores: a dense 0/1 contraction with fp4
+                                       operands and fp32 accumulation, exact; no early
+                                       exit, so ig_stats.tests counts every (candidate,
+                                       other-class record) pair.  Fits from codes use
+                                       factored tokens (each feature as mixed-radix
+                                       digits, one-hot per digit: 288 instead of 464
+                                       tokens for 41 features of ~11 bins), else the
+                                       K one-hot words; at most 8 words;
                                    2 = VALU path: AND-NOT chains with early exit in
-                                       input order (ig_stats.tests = sum of t(b)).
+                                       input order (ig_stats.tests = sum of t(b));
+                                   3 = matrix cores on the one-hot words (K <= 8).
                                    All give the same patterns, f and S.             */
     uint32_t reserved;
 } ig_fit_opts;
@@ -120,14 +125,20 @@ typedef struct {
     uint32_t L;              /* token universe size                                  */
     uint32_t d;              /* features (0 for a model fitted from packed words)    */
     uint32_t flags;          /* IG_MODEL_* bits                                      */
+    uint32_t mfma_tokens;    /* tokens per row of the matrix-core operands: the
+                                factored count, or L when they are one-hot           */
+    uint32_t mfma_words;     /* 64-token words per row of those operands             */
     uint64_t n_patterns[2];  /* |P^0|, |P^1|                                         */
     int64_t max_weight[2];   /* largest S of each class                              */
 } ig_model_info;
 
-/* ig_model_info.flags: ig_score evaluates Eq. 4 on the matrix cores (models of at
- * most 8 words whose weights are all below 2^28); otherwise on the vector ALUs.
- * Both give identical scores. */
+/* ig_model_info.flags.  IG_MODEL_SCORE_MFMA: ig_score evaluates Eq. 4 on the
+ * matrix cores (operands of at most 8 words, every weight below 2^28), otherwise
+ * on the vector ALUs; both give identical scores.  IG_MODEL_FACTORED: those
+ * operands use factored tokens; ig_score_packed (whose words may hold several
+ * bins of a feature) then runs on the vector ALUs. */
 #define IG_MODEL_SCORE_MFMA 1u
+#define IG_MODEL_FACTORED 2u
 
 /* One problem of a batched fit. */
 typedef struct {

@@ -166,7 +166,13 @@ struct DevModel {
     uint32_t *sc[2] = {nullptr, nullptr};
     KeyPiece *pieces = nullptr;            // compressed sort keys (fits from codes), or null
     uint32_t npieces = 0, nkeys = 0;
+    void *fac = nullptr;                   // factored-token table (features | digits | word starts)
+    FactorView fv;                         // fv.KF = 0: matrix-core operands stay one-hot
+    uint32_t fac_tokens = 0;               // tokens of the factored form
+    bool score_factored = false;           // frag/sc hold factored operand rows
     ig_stats stats{};
+
+    uint32_t KO() const { return fv.KF ? fv.KF : KS; }
 
     ~DevModel() {
         for (int c = 0; c < 2; ++c) {
@@ -181,6 +187,7 @@ struct DevModel {
         if (meta) (void)hipFree(meta);
         if (nbins) (void)hipFree(nbins);
         if (pieces) (void)hipFree(pieces);
+        if (fac) (void)hipFree(fac);
     }
 };
 
@@ -266,6 +273,134 @@ static void set_key_pieces(DevModel &m, const uint16_t *h_nbins, uint32_t d, hip
     IG_HIP(hipStreamSynchronize(s));   // pc must outlive its copy
     m.npieces = (uint32_t)pc.size();
     m.nkeys = nk;
+}
+
+// Radices of the digits of a feature with nb bins: the smallest sum of radices
+// (each >= 2) whose product is at least nb; a feature with one bin needs none (every
+// row of a fit holds it).
+static std::vector<uint32_t> digit_radices(uint32_t nb) {
+    static std::mutex mu;
+    static std::vector<uint32_t> cost{0, 0}, first{0, 0};   // per bin count: min sum, first radix
+    std::lock_guard<std::mutex> lock(mu);
+    for (uint32_t v = (uint32_t)cost.size(); v <= nb; ++v) {
+        uint32_t bc = v, bq = v;
+        for (uint32_t q = 2; q < v; ++q) {
+            const uint32_t c = q + cost[(v + q - 1) / q];
+            if (c < bc) { bc = c; bq = q; }
+        }
+        cost.push_back(bc);
+        first.push_back(bq);
+    }
+    std::vector<uint32_t> r;
+    for (uint32_t v = nb; v > 1; v = (v + first[v] - 1) / first[v]) r.push_back(first[v]);
+    return r;
+}
+
+// Factored-token table of a fit from codes (see FactorView), used when it needs at
+// most 8 words and fewer words than the one-hot packing.  Digits never straddle a
+// 64-bit word, so a feature's digits touch at most two words.
+static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, hipStream_t s) {
+    std::vector<FacFeature> feat(d);
+    std::vector<uint64_t> mask;
+    uint32_t off = 0, word = 0, used = 0, tokens = 0;
+    for (uint32_t f = 0; f < d; ++f) {
+        const uint32_t nb = h_nbins[f];
+        const std::vector<uint32_t> qs = digit_radices(nb);
+        // place the digits: (word, first bit) of each
+        std::vector<std::pair<uint32_t, uint32_t>> at;
+        for (uint32_t q : qs) {
+            if (used + q > 64) { ++word; used = 0; }
+            at.push_back({word, used});
+            used += q;
+            tokens += q;
+        }
+        if (word >= 8) return;   // more than 8 words: not worth a factored form
+        FacFeature ft{};
+        ft.off = (uint16_t)off;
+        ft.nb = (uint16_t)nb;
+        ft.w0 = (uint8_t)(at.empty() ? 0 : at.front().first);
+        ft.nw = (uint8_t)(at.empty() ? 0 : at.back().first - at.front().first + 1);
+        ft.mask = (uint32_t)mask.size();
+        for (uint32_t c = 0; c < nb && ft.nw; ++c) {
+            uint64_t part[2] = {0, 0};
+            uint32_t rest = c;   // digits from the least significant (last) one
+            for (size_t i = qs.size(); i-- > 0;) {
+                const uint32_t dg = rest % qs[i];
+                rest /= qs[i];
+                part[at[i].first - ft.w0] |= 1ull << (at[i].second + dg);
+            }
+            for (uint32_t w = 0; w < ft.nw; ++w) mask.push_back(part[w]);
+        }
+        feat[f] = ft;
+        off += nb;
+    }
+    const uint32_t KF = tokens ? word + 1 : 0;
+    if (KF == 0 || KF >= m.K) return;
+    // pieces: each feature cut at one-hot word boundaries
+    std::vector<std::vector<FacPiece>> by_word(m.K);
+    for (uint32_t f = 0; f < d; ++f) {
+        const FacFeature &ft = feat[f];
+        if (!ft.nw) continue;
+        for (uint32_t t = ft.off; t < (uint32_t)ft.off + ft.nb;) {
+            const uint32_t w = t / 64, hi = std::min<uint32_t>(ft.off + ft.nb, 64 * (w + 1));
+            FacPiece p{};
+            p.lo = (uint8_t)(t % 64);
+            p.width = (uint8_t)(hi - t);
+            p.w0 = ft.w0;
+            p.nw = ft.nw;
+            p.base = (uint16_t)(t - ft.off);
+            p.mask = ft.mask;
+            by_word[w].push_back(p);
+            t = hi;
+        }
+    }
+    std::vector<FacPiece> piece;
+    std::vector<uint32_t> pbeg(m.K + 1, 0);
+    for (uint32_t w = 0; w < m.K; ++w) {
+        pbeg[w] = (uint32_t)piece.size();
+        piece.insert(piece.end(), by_word[w].begin(), by_word[w].end());
+    }
+    pbeg[m.K] = (uint32_t)piece.size();
+    std::vector<uint32_t> fbeg(KF + 1, d), fend(KF + 1, 0);
+    for (uint32_t f = 0; f < d; ++f)
+        for (uint32_t w = feat[f].w0; w < (uint32_t)feat[f].w0 + feat[f].nw; ++w) {
+            fbeg[w] = std::min(fbeg[w], f);
+            fend[w] = std::max(fend[w], f + 1);
+        }
+    for (uint32_t w = 0; w <= KF; ++w)
+        if (fbeg[w] >= fend[w]) fbeg[w] = fend[w] = 0;
+    // one device block: masks | features | pieces | fbeg | fend | pbeg (8-byte aligned parts)
+    auto al8 = [](size_t b) { return (b + 7) / 8 * 8; };
+    const size_t mb = mask.size() * 8, fb = al8(feat.size() * sizeof(FacFeature)),
+                 pb = al8(piece.size() * sizeof(FacPiece)), ib = al8((KF + 1) * 4), kb = al8((m.K + 1) * 4);
+    std::vector<char> host(mb + fb + pb + 2 * ib + kb, 0);
+    size_t at = 0;
+    auto put = [&](const void *src, size_t bytes, size_t span) {
+        std::memcpy(host.data() + at, src, bytes);
+        const size_t here = at;
+        at += span;
+        return here;
+    };
+    const size_t o_mask = put(mask.data(), mb, mb);
+    const size_t o_feat = put(feat.data(), feat.size() * sizeof(FacFeature), fb);
+    const size_t o_piece = put(piece.data(), piece.size() * sizeof(FacPiece), pb);
+    const size_t o_fbeg = put(fbeg.data(), (KF + 1) * 4, ib);
+    const size_t o_fend = put(fend.data(), (KF + 1) * 4, ib);
+    const size_t o_pbeg = put(pbeg.data(), (m.K + 1) * 4, kb);
+    char *dev = dev_alloc<char>(host.size());
+    m.fac = dev;
+    IG_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    IG_HIP(hipStreamSynchronize(s));   // host must outlive its copy
+    m.fv.mask = reinterpret_cast<const uint64_t *>(dev + o_mask);
+    m.fv.feat = reinterpret_cast<const FacFeature *>(dev + o_feat);
+    m.fv.piece = reinterpret_cast<const FacPiece *>(dev + o_piece);
+    m.fv.fbeg = reinterpret_cast<const uint32_t *>(dev + o_fbeg);
+    m.fv.fend = reinterpret_cast<const uint32_t *>(dev + o_fend);
+    m.fv.pbeg = reinterpret_cast<const uint32_t *>(dev + o_pbeg);
+    m.fv.d = d;
+    m.fv.KF = KF;
+    m.fv.nmask = (uint32_t)mask.size();
+    m.fac_tokens = tokens;
 }
 
 static void check_nbins(const uint16_t *h_nbins, uint32_t d, uint32_t &L, uint32_t &K) {
@@ -355,7 +490,8 @@ struct ClassRows {
 // support and weights.  Fills model class c.
 static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *ids, size_t count,
                             bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
-                            int support_mark = -1, const uint4 *own_frag = nullptr) {
+                            int support_mark = -1, const uint4 *own_frag = nullptr,
+                            const FactorView &mfma_view = FactorView{}) {
     const uint32_t KS = m.KS, K = m.K;
     if (count == 0) {
         m.np[c] = 0;
@@ -453,9 +589,14 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         throw;
     }
     if (tm && support_mark >= 0) tm->mark(support_mark);
-    if (own_frag)
-        launch_support_mfma((int)KS, m.W[c], final_count, own_frag, cls.n, m.f[c], m.S[c], s);
-    else
+    if (own_frag) {
+        // f on the matrix cores against the class's own records, then S = f |b|^2
+        const uint32_t KO = mfma_view.KF ? mfma_view.KF : KS;
+        Scratch<uint64_t> B(final_count * KO, s);
+        launch_operand_rows(nullptr, 0, nullptr, m.W[c], KS, final_count, mfma_view, false, B.get(), s);
+        launch_contain_mfma((int)KO, true, B.get(), final_count, own_frag, cls.n, m.f[c], s);
+        launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
+    } else
         launch_support((int)KS, tu.support_cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
 }
 
@@ -463,13 +604,17 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
 // 8-word kernels and every weight is below 2^28 (sixteen of them sum without
 // wrapping in 32 bits).  Otherwise scoring stays on the VALU kernel.
 static void build_score_operands(DevModel &m, hipStream_t s) {
-    if (m.KS > 8 || m.maxS[0] >= (1ll << 28) || m.maxS[1] >= (1ll << 28)) return;
+    const uint32_t KO = m.KO();
+    if (KO > 8 || m.maxS[0] >= (1ll << 28) || m.maxS[1] >= (1ll << 28)) return;
     for (int c = 0; c < 2; ++c) {
         const uint64_t ntiles = (m.np[c] + 31) / 32;
-        m.frag[c] = dev_alloc<uint4>(ntiles * m.KS * 64);
+        m.frag[c] = dev_alloc<uint4>(ntiles * KO * 64);
         m.sc[c] = dev_alloc<uint32_t>(ntiles * 32);
-        launch_mfma_patterns(m.W[c], m.S[c], (uint32_t)m.np[c], m.KS, m.frag[c], m.sc[c], s);
+        Scratch<uint64_t> rows(std::max<uint64_t>(m.np[c], 1) * KO, s);
+        launch_operand_rows(nullptr, 0, nullptr, m.W[c], m.KS, m.np[c], m.fv, false, rows.get(), s);
+        launch_mfma_patterns(rows.get(), m.S[c], (uint32_t)m.np[c], KO, m.frag[c], m.sc[c], s);
     }
+    m.score_factored = m.fv.KF > 0;
     IG_HIP(hipStreamSynchronize(s));
 }
 
@@ -514,9 +659,10 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         m.stats.pairs[c] = n * (n ? n - 1 : 0) / 2;
         m.stats.support_tests[c] = 0;
     }
-    // items per pair-space chunk: ~40 bytes of scratch per item
+    // items per pair-space chunk: ~80 bytes of scratch per item (sort pairs, flags,
+    // candidates and their matrix-core operand rows)
     uint64_t chunk_items = 1ull << 31;
-    if (opts && opts->mem_budget_bytes) chunk_items = std::max<uint64_t>(opts->mem_budget_bytes / 40, 4096);
+    if (opts && opts->mem_budget_bytes) chunk_items = std::max<uint64_t>(opts->mem_budget_bytes / 80, 4096);
     struct Piece {
         int c;
         uint64_t q0, cnt;
@@ -565,15 +711,27 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     }
     const uint32_t grid = coherence_grid(tu.grid_per_cu);
     const uint32_t mode = opts ? opts->coherence_mfma : 0u;
-    IG_REQUIRE(mode <= 2, IG_E_INVAL, "coherence_mfma must be 0, 1 or 2");
-    IG_REQUIRE(mode != 1 || KS <= 8, IG_E_UNSUPPORTED, "the matrix-core coherence path handles up to 8 words");
-    const bool use_mfma = mode == 1 || (mode == 0 && KS <= 8);
+    IG_REQUIRE(mode <= 3, IG_E_INVAL, "coherence_mfma must be 0, 1, 2 or 3");
+    // matrix-core operands: factored tokens when the fit has a factoring (mode 3: the
+    // one-hot words), at most 8 operand words
+    const FactorView mview = mode == 3 ? FactorView{} : m.fv;
+    const uint32_t KO = mview.KF ? mview.KF : KS;
+    IG_REQUIRE((mode != 1 && mode != 3) || KO <= 8, IG_E_UNSUPPORTED,
+               "the matrix-core subset tests handle up to 8 operand words");
+    const bool use_mfma = mode == 1 || mode == 3 || (mode == 0 && KO <= 8);
     Scratch<uint4> frag[2];   // per class c: the other class's records as the A operand
     uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
     if (use_mfma)
         for (int c = 0; c < 2; ++c) {
-            frag[c].reset(std::max<size_t>((size_t)mfma_record_tiles(cls[1 - c].n) * KS * 64, 1), s);
-            launch_mfma_records(cls[1 - c].NX.get(), cls[1 - c].n, KS, frag[c].get(), s);
+            const ClassRows &o = cls[1 - c];
+            frag[c].reset(std::max<size_t>((size_t)mfma_record_tiles(o.n) * KO * 64, 1), s);
+            if (mview.KF) {
+                Scratch<uint64_t> nrows(std::max<size_t>(o.n, 1) * KO, s);
+                launch_operand_rows(nullptr, 0, nullptr, o.X.get(), KS, o.n, mview, true, nrows.get(), s);
+                launch_mfma_records(nrows.get(), o.n, KO, frag[c].get(), s);
+            } else {
+                launch_mfma_records(o.NX.get(), o.n, KS, frag[c].get(), s);
+            }
         }
     float ms_pairs = 0, ms_sort = 0, ms_dedup = 0, ms_coh = 0;
     hipEvent_t e[5];
@@ -636,9 +794,10 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
             for (int c = 0; c < 2; ++c) {
                 if (!hc[c]) continue;
                 Scratch<uint32_t> keep(hc[c], s), kpos(hc[c], s), ktot(1, s);
+                Scratch<uint64_t> B((size_t)hc[c] * KO, s);
                 uint32_t *cc = cand.get() + (c == 0 ? 0 : hc[0]);
-                launch_coherence_mfma((int)KS, cc, hc[c], cls[c].X.get(), cls[c].n, frag[c].get(), cls[1 - c].n,
-                                      keep.get(), s);
+                launch_operand_rows(cls[c].X.get(), cls[c].n, cc, nullptr, KS, hc[c], mview, false, B.get(), s);
+                launch_contain_mfma((int)KO, false, B.get(), hc[c], frag[c].get(), cls[1 - c].n, keep.get(), s);
                 scan_exclusive_u32(keep.get(), kpos.get(), hc[c], ktot.get(), s);
                 launch_compact(keep.get(), kpos.get(), cc, hc[c], surv[c].get() + mfma_surv[c], s);
                 mfma_surv[c] += host_read_u32(ktot.get(), 1, s)[0];
@@ -729,7 +888,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     for (int c = 0; c < 2; ++c) {
         // frag[1 - c] holds class c's own records (it is class 1-c's coherence operand)
         order_and_weigh(m, c, cls[c], surv[c].get(), hn[c], chunked, tu, s, &tm, c == 0 ? 5 : 8,
-                        use_mfma ? frag[1 - c].get() : nullptr);
+                        use_mfma ? frag[1 - c].get() : nullptr, mview);
         m.stats.coherent[c] = m.np[c];
         m.stats.support_tests[c] = m.np[c] * (uint64_t)cls[c].n;
         if (c == 0) tm.mark(3);   // end of class 0's support
@@ -792,6 +951,7 @@ DevModel *fit_codes(const uint16_t *d_codes, const uint8_t *d_labels, uint32_t n
     IG_HIP(hipMemcpyAsync(m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
     IG_HIP(hipMemcpyAsync(m->nbins, h_nbins, d * 2, hipMemcpyHostToDevice, s));
     set_key_pieces(*m, h_nbins, d, s);
+    set_factor_table(*m, h_nbins, d, s);
     Scratch<uint32_t> err(1, s), pos(n ? n : 1, s), counts(2, s);
     launch_fill_u32(err.get(), 0u, 1, s);
     launch_fill_u32(counts.get(), 0u, 2, s);
@@ -853,6 +1013,7 @@ DevModel *import_patterns(const uint16_t *const h_codes[2], const uint32_t *cons
     m->nbins = dev_alloc<uint16_t>(d);
     IG_HIP(hipMemcpyAsync(m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
     IG_HIP(hipMemcpyAsync(m->nbins, h_nbins, d * 2, hipMemcpyHostToDevice, s));
+    set_factor_table(*m, h_nbins, d, s);
     for (int c = 0; c < 2; ++c) {
         const uint64_t cnt = count[c];
         IG_REQUIRE(cnt < (1ull << 31), IG_E_UNSUPPORTED, "more than 2^31 patterns in one class");
@@ -1094,6 +1255,7 @@ void fit_batch(const ig_problem *probs, uint32_t np, const ig_fit_opts *opts, hi
         IG_HIP(hipMemcpyAsync(b.m->nbins, b.nbins, b.d * 2, hipMemcpyHostToDevice, s));
         IG_HIP(hipStreamSynchronize(s));   // the host table must outlive its copy
         set_key_pieces(*b.m, b.nbins, b.d, s);
+        set_factor_table(*b.m, b.nbins, b.d, s);
         b.err.reset(1, s);
         b.pos.reset(b.n ? b.n : 1, s);
         b.counts.reset(2, s);
@@ -1258,6 +1420,22 @@ ig_status ig_model_digest(const ig_model *m, uint32_t cls, uint64_t *out) {
     });
 }
 
+static ig::ScoreModel score_model(const ig::DevModel &M) {
+    ig::ScoreModel sm{};
+    for (int c = 0; c < 2; ++c) {
+        sm.P[c] = M.W[c];
+        sm.S[c] = M.S[c];
+        sm.np[c] = M.np[c];
+        sm.maxS[c] = M.maxS[c];
+        sm.frag[c] = M.frag[c];
+        sm.sc[c] = M.sc[c];
+    }
+    sm.KS = M.KS;
+    sm.KO = M.score_factored ? M.fv.KF : M.KS;
+    if (M.score_factored) sm.fv = M.fv;
+    return sm;
+}
+
 ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out, void *stream) {
     return guarded([&] {
         check_model(m);
@@ -1265,8 +1443,7 @@ ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows,
         IG_REQUIRE(M.d > 0, IG_E_INVAL, "model was fitted from packed words: use ig_score_packed");
         IG_REQUIRE(n_flows < (1u << 31), IG_E_UNSUPPORTED, "n_flows must be below 2^31");
         IG_REQUIRE(n_flows == 0 || (d_codes && d_out), IG_E_INVAL, "codes or out is NULL");
-        ig::ScoreModel sm{{M.W[0], M.W[1]}, {M.S[0], M.S[1]}, {M.np[0], M.np[1]}, M.KS, {M.maxS[0], M.maxS[1]},
-                          {M.frag[0], M.frag[1]}, {M.sc[0], M.sc[1]}};
+        const ig::ScoreModel sm = score_model(M);
         if (M.frag[0] && M.frag[1])
             ig::launch_score_mfma(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, (hipStream_t)stream);
         else
@@ -1281,9 +1458,9 @@ ig_status ig_score_packed(const ig_model *m, const uint64_t *d_words, uint32_t n
         const DevModel &M = *m->m;
         IG_REQUIRE(n_flows < (1u << 31), IG_E_UNSUPPORTED, "n_flows must be below 2^31");
         IG_REQUIRE(n_flows == 0 || (d_words && d_out), IG_E_INVAL, "words or out is NULL");
-        ig::ScoreModel sm{{M.W[0], M.W[1]}, {M.S[0], M.S[1]}, {M.np[0], M.np[1]}, M.KS, {M.maxS[0], M.maxS[1]},
-                          {M.frag[0], M.frag[1]}, {M.sc[0], M.sc[1]}};
-        if (M.frag[0] && M.frag[1])
+        const ig::ScoreModel sm = score_model(M);
+        // words may hold several bins of a feature: factored operands cannot test them
+        if (M.frag[0] && M.frag[1] && !M.score_factored)
             ig::launch_score_mfma(sm, nullptr, d_words, M.K, n_flows, M.d, M.meta, M.nbins, d_out, (hipStream_t)stream);
         else
             ig::launch_score(sm, nullptr, d_words, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, (hipStream_t)stream);
@@ -1298,7 +1475,10 @@ ig_status ig_model_get_info(const ig_model *m, ig_model_info *info) {
         info->K = M.K;
         info->L = M.L;
         info->d = M.d;
-        info->flags = (M.frag[0] && M.frag[1]) ? IG_MODEL_SCORE_MFMA : 0u;
+        info->flags = ((M.frag[0] && M.frag[1]) ? IG_MODEL_SCORE_MFMA : 0u) |
+                      (M.score_factored ? IG_MODEL_FACTORED : 0u);
+        info->mfma_tokens = M.score_factored ? M.fac_tokens : M.L;
+        info->mfma_words = M.score_factored ? M.fv.KF : M.K;
         for (int c = 0; c < 2; ++c) {
             info->n_patterns[c] = M.np[c];
             info->max_weight[c] = M.maxS[c];

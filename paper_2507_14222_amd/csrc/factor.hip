@@ -1,0 +1,135 @@
+// Operand rows for the matrix-core subset tests: the one-hot words themselves, or
+// their factored form (mixed-radix digits, one-hot per digit; see FactorView).
+#include "common.h"
+#include "kernels.h"
+
+namespace ig {
+
+// Bin of feature ft in a one-hot row (word(w) returns word w), or -1 when the row
+// holds none of its tokens.  Rows of a fit from codes hold at most one.
+template <class Word>
+__device__ __forceinline__ int feature_code(const Word &word, const FacFeature ft) {
+    const uint32_t a = ft.off, b = ft.off + ft.nb;
+    for (uint32_t w = a / 64; w * 64 < b; ++w) {
+        const uint32_t lo = a > w * 64 ? a - w * 64 : 0;
+        const uint32_t hi = b < w * 64 + 64 ? b - w * 64 : 64;
+        uint64_t x = word(w) >> lo;
+        if (hi - lo < 64) x &= (1ull << (hi - lo)) - 1;
+        if (x) return (int)(w * 64 + lo + (uint32_t)__builtin_ctzll(x) - a);
+    }
+    return -1;
+}
+
+// The feature walk is uniform over the wave (every lane follows the same table);
+// each lane's row words are re-read from L1/L2 when a feature needs them, and the
+// digit tokens of its bin come from the mask table (L1/L2 resident).
+__global__ __launch_bounds__(256) void k_operand_rows(const uint64_t *__restrict__ X, uint32_t n,
+                                                     const uint32_t *__restrict__ ids,
+                                                     const uint64_t *__restrict__ W, uint32_t KS, size_t m,
+                                                     FactorView fv, uint32_t KO, uint64_t flip,
+                                                     uint64_t *__restrict__ out) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const uint64_t *ra, *rb;
+    if (ids) {
+        uint32_t i, j;
+        decode_pair(ids[e], n, i, j);
+        ra = X + (size_t)i * KS;
+        rb = X + (size_t)j * KS;
+    } else {
+        ra = rb = W + e * KS;
+    }
+    auto word = [&](uint32_t w) { return ra[w] & rb[w]; };
+    if (!fv.KF) {
+        for (uint32_t k = 0; k < KO; ++k) out[e * KO + k] = word(k) ^ flip;
+        return;
+    }
+    for (uint32_t ow = 0; ow < KO; ++ow) {
+        uint64_t acc = 0;
+        for (uint32_t f = fv.fbeg[ow]; f < fv.fend[ow]; ++f) {
+            const FacFeature ft = fv.feat[f];
+            if (ow - ft.w0 >= ft.nw) continue;   // a one-bin feature has no digits
+            const int code = feature_code(word, ft);
+            if (code >= 0) acc |= fv.mask[ft.mask + (uint32_t)code * ft.nw + (ow - ft.w0)];
+        }
+        out[e * KO + ow] = acc ^ flip;
+    }
+}
+
+// Factoring for rows of at most 8 one-hot words: each lane loads its row once
+// into registers and walks the pieces of each word (a uniform table); the masks of
+// every (feature, bin) are staged in LDS when they fit.  Output words are chosen
+// with uniform branches, so every register index is static.
+constexpr uint32_t kLdsMasks = 4096;   // u64 masks staged in LDS (32 KB)
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__restrict__ X, uint32_t n,
+                                                         const uint32_t *__restrict__ ids,
+                                                         const uint64_t *__restrict__ W, size_t m, FactorView fv,
+                                                         uint32_t KO, uint64_t flip, uint64_t *__restrict__ out) {
+    __shared__ uint64_t smask[kLdsMasks];
+    const bool in_lds = fv.nmask <= kLdsMasks;
+    if (in_lds)
+        for (uint32_t t = threadIdx.x; t < fv.nmask; t += blockDim.x) smask[t] = fv.mask[t];
+    __syncthreads();
+    const uint64_t *masks = in_lds ? smask : fv.mask;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    uint64_t w[KS];
+    if (ids) {
+        uint32_t i, j;
+        decode_pair(ids[e], n, i, j);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) w[k] = X[(size_t)i * KS + k] & X[(size_t)j * KS + k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) w[k] = W[e * KS + k];
+    }
+    uint64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        for (uint32_t p = fv.pbeg[k]; p < fv.pbeg[k + 1]; ++p) {
+            const FacPiece pc = fv.piece[p];
+            uint64_t x = w[k] >> pc.lo;
+            if (pc.width < 64) x &= (1ull << pc.width) - 1;
+            if (!x) continue;
+            const uint64_t *mk = masks + pc.mask + ((uint32_t)pc.base + (uint32_t)__builtin_ctzll(x)) * pc.nw;
+            const uint64_t m0 = mk[0], m1 = pc.nw > 1 ? mk[1] : 0ull;
+            switch (pc.w0) {   // uniform over the wave
+#define IG_OR(W0)                      \
+    case W0:                           \
+        acc[W0] |= m0;                 \
+        if (W0 + 1 < 8) acc[(W0 + 1) & 7] |= m1; \
+        break;
+                IG_OR(0) IG_OR(1) IG_OR(2) IG_OR(3) IG_OR(4) IG_OR(5) IG_OR(6) IG_OR(7)
+#undef IG_OR
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+        if ((uint32_t)o < KO) out[e * KO + o] = acc[o] ^ flip;
+}
+
+void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, const uint64_t *W, uint32_t KS, size_t m,
+                         const FactorView &fv, bool complement, uint64_t *out, hipStream_t s) {
+    if (!m) return;
+    const uint32_t KO = fv.KF ? fv.KF : KS;
+    const dim3 grid((unsigned)((m + 255) / 256));
+    const uint64_t flip = complement ? ~0ull : 0ull;
+    if (fv.KF && KS <= 8) {
+#define IG_OR_K(V)                                                                                                 \
+    case V:                                                                                                        \
+        hipLaunchKernelGGL((k_operand_rows_reg<V>), grid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, flip, out); \
+        break;
+        switch (KS) {
+            IG_OR_K(1) IG_OR_K(2) IG_OR_K(3) IG_OR_K(4) IG_OR_K(5) IG_OR_K(6) IG_OR_K(7) IG_OR_K(8)
+        }
+#undef IG_OR_K
+    } else {
+        hipLaunchKernelGGL(k_operand_rows, grid, dim3(256), 0, s, X, n, ids, W, KS, m, fv, KO, flip, out);
+    }
+    IG_HIP(hipGetLastError());
+}
+
+}  // namespace ig

@@ -70,6 +70,42 @@ void launch_adjacent_equal(const uint64_t *W, size_t m, uint32_t KS, uint32_t *d
 // S = f * popcount^2 (Eq. 2) for given rows and supports
 void launch_weights(const uint64_t *W, const uint32_t *f, size_t m, uint32_t KS, int64_t *S, hipStream_t s);
 
+// factor.hip -- factored tokens for the matrix-core operands.
+// A feature with nb bins is written as mixed-radix digits (radices q_0, q_1, ...
+// whose product is at least nb), each digit one-hot over its q tokens, instead of
+// one-hot over nb tokens.  Two codes are equal exactly when all their digits are,
+// so "b inside r" (every feature b holds has the same bin in r, Eq. 6 on the
+// one-hot packing of Eq. 5) is the same relation on the factored tokens.  Records
+// and flows hold one bin per feature and candidates and patterns at most one, so
+// every row of a fit from codes has a factored form; a bin of a feature is read
+// back from the one-hot row as the index of its one set bit.
+struct FacFeature {
+    uint16_t off, nb;            // one-hot token range [off, off + nb) of the feature
+    uint8_t w0, nw, pad[2];      // its digits lie in output words w0 .. w0 + nw - 1 (nw <= 2)
+    uint32_t mask;               // masks of bin c: mask + c * nw + (word - w0)
+};
+struct FacPiece {                // the part of a feature inside one one-hot word
+    uint8_t lo, width;           // bits [lo, lo + width) of that word
+    uint8_t w0, nw;              // output words of the feature (FacFeature)
+    uint16_t base, pad;          // bin of bit lo
+    uint32_t mask;               // FacFeature::mask of the feature
+};
+struct FactorView {
+    const FacFeature *feat = nullptr;   // [d]
+    const uint64_t *mask = nullptr;     // the digit tokens of every (feature, bin)
+    const uint32_t *fbeg = nullptr;     // [KF + 1]: features touching word w are
+    const uint32_t *fend = nullptr;     //   [fbeg[w], fend[w]) (features in token order)
+    const FacPiece *piece = nullptr;    // pieces grouped by one-hot word
+    const uint32_t *pbeg = nullptr;     // [K + 1]: pieces of one-hot word k are [pbeg[k], pbeg[k + 1])
+    uint32_t d = 0, KF = 0;             // KF = 0: no factoring (operands are the one-hot words)
+    uint32_t nmask = 0;                 // entries of mask
+};
+// Operand rows out[m][KO], KO = fv.KF when factoring, else KS: row e is the
+// pattern X[i] AND X[j] of pair id ids[e] (ids non-null, rows X [n][KS]) or the
+// row W[e] [m][KS]; complement writes NOT of every word.
+void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, const uint64_t *W, uint32_t KS, size_t m,
+                         const FactorView &fv, bool complement, uint64_t *out, hipStream_t s);
+
 // subset.hip -- the subset-test kernels (Eq. 6 inside Eq. 3, Eq. 2 and Eq. 4)
 struct CohSeg {                 // one (problem, class) for one coherence phase
     const uint64_t *X;          // class rows [n][KS]
@@ -93,18 +129,16 @@ uint32_t coherence_grid(uint32_t grid_per_cu);
 void launch_digest(const uint64_t *W, const uint32_t *f, const int64_t *S, size_t m, uint32_t KS, uint32_t K,
                    unsigned long long *out, hipStream_t s);
 
-// Coherence on the matrix cores (fp4 0/1 contraction, dense, KS <= 8): keep[i] =
-// 1 when candidate cand[i] lies in none of the n_o other-class records.  frag is
-// the records' operand layout from launch_mfma_records (mfma_record_tiles(n_o) *
-// KS * 64 uint4).
+// Subset tests on the matrix cores (fp4 0/1 contraction, dense, KO <= 8 operand
+// words): columns are m operand rows B [m][KO], the A side is n_rec records in
+// the tile layout of launch_mfma_records (mfma_record_tiles(n_rec) * KO * 64 uint4
+// built from complemented operand rows).  count = false: out[e] = 1 when no
+// record contains row e (coherence, Eq. 3); count = true: out[e] = the number of
+// records containing it (support f, Eq. 2).
 uint32_t mfma_record_tiles(uint32_t n);
 void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *frag, hipStream_t s);
-void launch_coherence_mfma(int KS, const uint32_t *cand, uint32_t ncand, const uint64_t *X, uint32_t n,
-                           const uint4 *frag, uint32_t n_o, uint32_t *keep, hipStream_t s);
-
-// Support on the matrix cores: frag = the class's own records (launch_mfma_records).
-void launch_support_mfma(int KS, const uint64_t *W, size_t m, const uint4 *frag, uint32_t n, uint32_t *f,
-                         int64_t *S, hipStream_t s);
+void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const uint4 *frag, uint32_t n_rec,
+                         uint32_t *out, hipStream_t s);
 
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented
 // rows NX [n][KS] of their class.
@@ -119,10 +153,13 @@ struct ScoreModel {
     int64_t maxS[2];            // largest weight of each class
     const uint4 *frag[2];       // matrix-core operands of the patterns (or null)
     const uint32_t *sc[2];      // their weights in accumulator order
+    uint32_t KO;                // operand words of frag (factored or one-hot)
+    FactorView fv;              // the factoring of frag (fv.KF = 0: one-hot)
 };
-// Scoring on the matrix cores (KS <= 8, every weight < 2^28): patterns pre-expanded
-// by launch_mfma_patterns into frag (ceil(m/32) * KS * 64 uint4) and sc
-// (ceil(m/32) * 32 u32).
+// Scoring on the matrix cores (KO <= 8, every weight < 2^28): patterns' operand
+// rows pre-expanded by launch_mfma_patterns into frag (ceil(m/32) * KO * 64 uint4)
+// and sc (ceil(m/32) * 32 u32).  Flows given as codes are factored like the
+// patterns; flows given as words need one-hot operands (fv.KF = 0).
 void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, uint4 *frag, uint32_t *sc,
                           hipStream_t s);
 void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K,

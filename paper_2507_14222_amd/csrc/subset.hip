@@ -327,37 +327,38 @@ constexpr int MF_WAVES_PER_SIMD = 4;
 template <int KS>
 constexpr int mf_group() { return 32 / KS > 0 ? 32 / KS : 1; }   // tiles per LDS buffer (32 KB)
 
-template <int KS>
-__global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_coherence_mfma(const uint32_t *__restrict__ cand, uint32_t ncand,
-                                                          const uint64_t *__restrict__ X, uint32_t n,
-                                                          const uint4 *__restrict__ frag, uint32_t ntiles,
-                                                          uint32_t *__restrict__ keep) {
+// Columns: operand rows B [m][KS], expanded bit -> nibble into the B operand in
+// registers (lane % 32 = column, lane / 32 = 32-token half of each word); the A
+// side streams the record tiles.  COUNT = false (coherence, Eq. 3): out[e] = 1
+// when no record contains row e; COUNT = true (support, Eq. 2): out[e] = the
+// number of records that contain it.
+template <int KS, bool COUNT>
+__global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const uint64_t *__restrict__ B, uint32_t m,
+                                                                         const uint4 *__restrict__ frag,
+                                                                         uint32_t ntiles, uint32_t *__restrict__ out) {
     constexpr int G = mf_group<KS>();
     __shared__ uint4 lds[2 * G * KS * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     v8i_t b[MF_FB][KS];
-    uint32_t cidx[MF_FB];
+    uint32_t e[MF_FB], hits[MF_FB];
 #pragma unroll
     for (int f = 0; f < MF_FB; ++f) {
-        cidx[f] = blockIdx.x * MF_COLS + wave * (MF_FB * 32) + f * 32 + col;
-        const bool act = cidx[f] < ncand;
-        // loads without branches (inactive columns read candidate 0), so that they overlap
-        uint32_t i, j;
-        decode_pair(cand[act ? cidx[f] : 0u], n, i, j);
-        const uint32_t *ra = reinterpret_cast<const uint32_t *>(X + (size_t)i * KS);
-        const uint32_t *rb = reinterpret_cast<const uint32_t *>(X + (size_t)j * KS);
+        e[f] = blockIdx.x * MF_COLS + wave * (MF_FB * 32) + f * 32 + col;
+        const bool act = e[f] < m;
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(B + (size_t)(act ? e[f] : 0) * KS);
+        hits[f] = 0;
 #pragma unroll
         for (int w = 0; w < KS; ++w) {
-            // inactive columns: all ones, so their result is ignored anyway
-            const uint32_t va = ra[2 * w + half], vb = rb[2 * w + half];
-            const uint32_t d = act ? (va & vb) : 0xffffffffu;
+            const uint32_t v = row[2 * w + half];   // unconditional: the loads overlap
+            // inactive columns: all tokens, so their result is ignored anyway
+            const uint32_t d = act ? v : 0xffffffffu;
             b[f][w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
                             0, 0, 0, 0};
         }
     }
-    bool covered[MF_FB] = {};
     if (ntiles)
-        stream_tiles<KS, G, MF_NT>(frag, nullptr, 0, ntiles, lds, nullptr, [&](const uint4 *tf, const uint32_t *) __attribute__((always_inline)) {
+        stream_tiles<KS, G, MF_NT>(frag, nullptr, 0, ntiles, lds, nullptr,
+                                   [&](const uint4 *tf, const uint32_t *) __attribute__((always_inline)) {
             v16f_t acc[MF_FB];
 #pragma unroll
             for (int f = 0; f < MF_FB; ++f) acc[f] = v16f_t{0};
@@ -371,93 +372,43 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_coherence_mfma(con
             }
 #pragma unroll
             for (int f = 0; f < MF_FB; ++f) {
-                bool z = false;
+                if (COUNT) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) z |= acc[f][r] == 0.0f;
-                covered[f] |= z;
+                    for (int r = 0; r < 16; ++r) hits[f] += acc[f][r] == 0.0f;
+                } else {
+                    bool z = false;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) z |= acc[f][r] == 0.0f;
+                    hits[f] |= z;
+                }
             }
         });
 #pragma unroll
     for (int f = 0; f < MF_FB; ++f) {
         // the two halves of the wave hold different record rows of the same column
-        const uint64_t m = __ballot(covered[f]);
-        const bool col_covered = ((m >> col) & 1ull) | ((m >> (col + 32)) & 1ull);
-        if (half == 0 && cidx[f] < ncand) keep[cidx[f]] = col_covered ? 0u : 1u;
+        const uint32_t h = hits[f] + __shfl_xor(hits[f], 32, 64);
+        if (half == 0 && e[f] < m) out[e[f]] = COUNT ? h : (h ? 0u : 1u);
     }
 }
 
-// Support (Eq. 2) as the same contraction: f(b) = number of same-class records
-// r with V[r][b] = 0.  Ordered pattern rows are the B operand; frag holds the
-// class's own complemented records (launch_mfma_records of that class).
-template <int KS>
-__global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_support_mfma(const uint64_t *__restrict__ Wrows, uint32_t m,
-                                                        const uint4 *__restrict__ frag, uint32_t ntiles,
-                                                        uint32_t *__restrict__ f_out, int64_t *__restrict__ S_out) {
-    constexpr int G = mf_group<KS>();
-    __shared__ uint4 lds[2 * G * KS * 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
-    v8i_t b[MF_FB][KS];
-    uint32_t e[MF_FB], len[MF_FB], cnt[MF_FB];
-#pragma unroll
-    for (int f = 0; f < MF_FB; ++f) {
-        e[f] = blockIdx.x * MF_COLS + wave * (MF_FB * 32) + f * 32 + col;
-        const bool act = e[f] < m;
-        const uint32_t *row = reinterpret_cast<const uint32_t *>(Wrows + (size_t)(act ? e[f] : 0) * KS);
-        len[f] = 0;
-        cnt[f] = 0;
-#pragma unroll
-        for (int w = 0; w < KS; ++w) {
-            const uint32_t v = row[2 * w + half];   // unconditional: the loads overlap
-            const uint32_t d = act ? v : 0xffffffffu;
-            len[f] += __popc(d);
-            b[f][w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
-                            0, 0, 0, 0};
-        }
-    }
-    if (ntiles)
-        stream_tiles<KS, G, MF_NT>(frag, nullptr, 0, ntiles, lds, nullptr, [&](const uint4 *tf, const uint32_t *) __attribute__((always_inline)) {
-            v16f_t acc[MF_FB];
-#pragma unroll
-            for (int f = 0; f < MF_FB; ++f) acc[f] = v16f_t{0};
-#pragma unroll
-            for (int w = 0; w < KS; ++w) {
-                const uint4 a4 = tf[w * 64 + lane];
-                const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
-#pragma unroll
-                for (int f = 0; f < MF_FB; ++f)
-                    acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
-            }
-#pragma unroll
-            for (int f = 0; f < MF_FB; ++f)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) cnt[f] += acc[f][r] == 0.0f;
-        });
-#pragma unroll
-    for (int f = 0; f < MF_FB; ++f) {
-        // the two halves hold different record rows (and token halves) of the same column
-        const uint32_t c = cnt[f] + __shfl_xor(cnt[f], 32, 64);
-        const uint32_t l = len[f] + __shfl_xor(len[f], 32, 64);
-        if (half == 0 && e[f] < m) {
-            f_out[e[f]] = c;
-            S_out[e[f]] = (int64_t)c * (int64_t)l * (int64_t)l;
-        }
-    }
-}
-
-void launch_support_mfma(int KS, const uint64_t *W, size_t m, const uint4 *frag, uint32_t n, uint32_t *f,
-                         int64_t *S, hipStream_t s) {
+void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const uint4 *frag, uint32_t n_rec,
+                         uint32_t *out, hipStream_t s) {
     if (!m) return;
+    IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 rows in one matrix-core launch");
     const dim3 grid((unsigned)((m + MF_COLS - 1) / MF_COLS));
-    const uint32_t ntiles = (n + 31) / 32;
-#define IG_SMF(V)                                                                                            \
-    case V:                                                                                                  \
-        hipLaunchKernelGGL((k_support_mfma<V>), grid, dim3(MF_NT), 0, s, W, (uint32_t)m, frag, ntiles, f, S); \
+    const uint32_t ntiles = (n_rec + 31) / 32;
+#define IG_CM(V)                                                                                               \
+    case V:                                                                                                    \
+        if (count)                                                                                             \
+            hipLaunchKernelGGL((k_contain_mfma<V, true>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, out); \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_contain_mfma<V, false>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, out); \
         break;
-    switch (KS) {
-        IG_SMF(1) IG_SMF(2) IG_SMF(3) IG_SMF(4) IG_SMF(5) IG_SMF(6) IG_SMF(7) IG_SMF(8)
-        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core support path handles up to 8 words");
+    switch (KO) {
+        IG_CM(1) IG_CM(2) IG_CM(3) IG_CM(4) IG_CM(5) IG_CM(6) IG_CM(7) IG_CM(8)
+        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 8 operand words");
     }
-#undef IG_SMF
+#undef IG_CM
     IG_HIP(hipGetLastError());
 }
 
@@ -501,6 +452,7 @@ struct ScoreMfmaArgs {
     const uint16_t *nbins;
     int64_t *out;
     uint32_t n_flows, d, K;
+    FactorView fv;              // fv.KF > 0: flows (codes) are factored like the patterns
 };
 
 // Workgroup (range, flow block): the fblocks workgroups that read the same range
@@ -529,7 +481,21 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_score_mfma(ScoreMf
         const bool act = t < a.n_flows;
         uint64_t wd[KS];
         bool ok = act;
-        if (act && a.codes) {
+        if (act && a.codes && a.fv.KF) {
+            const uint16_t *row = a.codes + (size_t)t * a.d;
+            for (uint32_t ft = 0; ft < a.d; ++ft) ok &= row[ft] < a.nbins[ft];
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                uint64_t v = 0;
+                for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
+                    const FacFeature ft = a.fv.feat[f];
+                    if ((uint32_t)k - ft.w0 >= ft.nw) continue;   // a one-bin feature has no digits
+                    const uint32_t c = row[f] < ft.nb ? row[f] : 0u;   // out of range: flow is dropped
+                    v |= a.fv.mask[ft.mask + c * ft.nw + (k - ft.w0)];
+                }
+                wd[k] = v;
+            }
+        } else if (act && a.codes) {
             const uint16_t *row = a.codes + (size_t)t * a.d;
             const uint32_t *off = a.meta, *flo = a.meta + a.d, *fhi = a.meta + a.d + KS;
 #pragma unroll
@@ -608,23 +574,6 @@ void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *fra
     if (!total) return;
     hipLaunchKernelGGL(k_mfma_records, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, NX, n, KS, ntiles,
                        frag);
-    IG_HIP(hipGetLastError());
-}
-
-void launch_coherence_mfma(int KS, const uint32_t *cand, uint32_t ncand, const uint64_t *X, uint32_t n,
-                           const uint4 *frag, uint32_t n_o, uint32_t *keep, hipStream_t s) {
-    if (!ncand) return;
-    const dim3 grid((ncand + MF_COLS - 1) / MF_COLS);
-    const uint32_t ntiles = mfma_record_tiles(n_o);
-#define IG_MF(V)                                                                                               \
-    case V:                                                                                                    \
-        hipLaunchKernelGGL((k_coherence_mfma<V>), grid, dim3(MF_NT), 0, s, cand, ncand, X, n, frag, ntiles, keep); \
-        break;
-    switch (KS) {
-        IG_MF(1) IG_MF(2) IG_MF(3) IG_MF(4) IG_MF(5) IG_MF(6) IG_MF(7) IG_MF(8)
-        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core coherence path handles up to 8 words");
-    }
-#undef IG_MF
     IG_HIP(hipGetLastError());
 }
 
@@ -1015,6 +964,8 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     a.n_flows = n_flows;
     a.d = d;
     a.K = K;
+    a.fv = m.fv;
+    IG_REQUIRE(!m.fv.KF || codes, IG_E_UNSUPPORTED, "factored matrix-core operands score flows given as codes");
     a.fblocks = (n_flows + MF_COLS - 1) / MF_COLS;
     const uint32_t tiles = a.ntiles[0] + a.ntiles[1];
     if (!tiles) return;
@@ -1031,7 +982,7 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     case V:                                                                          \
         hipLaunchKernelGGL((k_score_mfma<V>), grid, dim3(MF_NT), 0, s, a);          \
         break;
-    switch ((int)m.KS) {
+    switch ((int)m.KO) {
         IG_SCM(1) IG_SCM(2) IG_SCM(3) IG_SCM(4) IG_SCM(5) IG_SCM(6) IG_SCM(7) IG_SCM(8)
         default: throw Error(IG_E_UNSUPPORTED, "the matrix-core scoring path handles up to 8 words");
     }

@@ -21,6 +21,7 @@ _NAMES = {0: "IG_OK", -1: "IG_E_INVAL", -2: "IG_E_NOMEM", -3: "IG_E_DEVICE", -4:
           -5: "IG_E_UNSUPPORTED"}
 ABSENT = 0xFFFF
 IG_MODEL_SCORE_MFMA = 1   # ModelInfo.flags: scoring runs on the matrix cores
+IG_MODEL_FACTORED = 2     # ModelInfo.flags: matrix-core operands use factored tokens
 
 
 class IGError(RuntimeError):
@@ -48,6 +49,7 @@ class Stats(C.Structure):
 
 class ModelInfo(C.Structure):
     _fields_ = [("K", C.c_uint32), ("L", C.c_uint32), ("d", C.c_uint32), ("flags", C.c_uint32),
+                ("mfma_tokens", C.c_uint32), ("mfma_words", C.c_uint32),
                 ("n_patterns", C.c_uint64 * 2), ("max_weight", C.c_int64 * 2)]
 
 
@@ -139,9 +141,10 @@ def _np_u16(a) -> np.ndarray:
 def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tune=None,
           kernels: str = "auto") -> FitOpts:
     """Fit options; `tune` is a list of dicts with the fields of ig_tune_entry;
-    kernels = "auto" | "mfma" | "valu" selects the coherence/support kernels."""
+    kernels = "auto" | "mfma" | "valu" | "mfma_onehot" selects the coherence/support
+    kernels ("mfma_onehot": matrix cores on the one-hot words, no factored tokens)."""
     o = FitOpts()
-    o.coherence_mfma = {"auto": 0, "mfma": 1, "valu": 2}[kernels]
+    o.coherence_mfma = {"auto": 0, "mfma": 1, "valu": 2, "mfma_onehot": 3}[kernels]
     o.mem_budget_bytes = int(mem_budget_bytes)
     o.filter_cpl = int(filter_cpl)
     o.score_fpl = int(score_fpl)

@@ -127,7 +127,9 @@ def test_random_problem_parity(case):
     m = ig.fit(p.codes, p.labels, p.nbins)   # default kernels (matrix cores when K <= 8)
     assert_same_model(m, om, om.K)
     info = m.info()
-    assert m.score_on_matrix_cores == (om.K <= 8 and max(info.max_weight) < 2 ** 28)
+    # matrix cores whenever the operands (factored, else one-hot) fit 8 words
+    assert info.mfma_words == (om.K if not info.flags & ig.IG_MODEL_FACTORED else info.mfma_words)
+    assert m.score_on_matrix_cores == (info.mfma_words <= 8 and max(info.max_weight) < 2 ** 28)
     flows = synth.make_random_problem(seed + 1000, 97, d, bins_lo=blo, bins_hi=bhi).codes
     flows = np.minimum(flows, p.nbins[None, :] - 1).astype(np.uint16)
     flows = np.concatenate([flows, p.codes[: min(40, p.n)]])
@@ -173,6 +175,16 @@ def test_fit_packed_matches_codes_path():
     out = ig.score_packed(b, fl).cpu().numpy()
     A, N = gpu_scores(a, p.codes[:50])
     assert np.array_equal(out[:, 0], A) and np.array_equal(out[:, 1], N)
+    # a model fitted from codes scores packed flows too (on the VALU kernel when its
+    # matrix-core operands are factored), including flows holding two bins of a feature
+    out = ig.score_packed(a, fl).cpu().numpy()
+    assert np.array_equal(out[:, 0], A) and np.array_equal(out[:, 1], N)
+    wide = fl | oracle.pack(p.codes[50:100], p.nbins)
+    om = oracle.fit(p.codes, p.labels, p.nbins)
+    out = ig.score_packed(a, wide).cpu().numpy()
+    for c, col in ((1, 0), (0, 1)):   # Eq. 4 by its definition on the words
+        inside = np.all((om.patterns[c][None, :, :] & ~wide[:, None, :]) == 0, axis=2)
+        assert np.array_equal(out[:, col], inside.astype(np.int64) @ om.S[c].astype(np.int64))
 
 
 # ---------------------------------------------------------- imported sets
@@ -342,17 +354,31 @@ MFMA_CASES = [c for c in CASES if c[0] in (1, 2, 4, 6, 7, 8, 9, 10, 11, 18, 19)]
 
 
 @pytest.mark.parametrize("case", MFMA_CASES, ids=[f"s{c[0]}" for c in MFMA_CASES])
-def test_matrix_core_coherence_matches_oracle(case):
+@pytest.mark.parametrize("kernels", ["mfma", "mfma_onehot"])
+def test_matrix_core_coherence_matches_oracle(case, kernels):
     seed, n, d, blo, bhi, af = case
     p = synth.make_random_problem(seed, n, d, bins_lo=blo, bins_hi=bhi, attack_frac=af)
-    say("mfma coherence", case)
+    say("mfma coherence", case, kernels)
     om = oracle.fit(p.codes, p.labels, p.nbins)
-    m = ig.fit(p.codes, p.labels, p.nbins, kernels="mfma")
+    m = ig.fit(p.codes, p.labels, p.nbins, kernels=kernels)
     assert_same_model(m, om, om.K)
     st = m.stats()
     assert list(st.coherent) == om.stats["coherent"] and list(st.distinct) == om.stats["distinct"]
     for c in (0, 1):   # dense: every candidate against every other-class record
         assert st.tests[c] == om.stats["distinct"][c] * om.stats["n_class"][1 - c]
+    info = m.info()
+    assert info.mfma_words <= 8 and info.mfma_tokens <= 64 * info.mfma_words
+    if info.flags & ig.IG_MODEL_FACTORED:
+        assert info.mfma_words < om.K and info.mfma_tokens < p.L
+    flows = synth.make_random_problem(seed + 2000, 61, d, bins_lo=blo, bins_hi=bhi).codes
+    flows = np.minimum(flows, p.nbins[None, :] - 1).astype(np.uint16)
+    bad = np.zeros(len(flows), bool)
+    bad[::7] = True
+    flows[bad, 0] = p.nbins[0]   # a code out of range: (-1, -1)
+    A, N = gpu_scores(m, flows)
+    assert np.all(A[bad] == -1) and np.all(N[bad] == -1)
+    oA, oN = oracle.score(om, flows[~bad], p.nbins)
+    assert np.array_equal(A[~bad], oA) and np.array_equal(N[~bad], oN)
 
 
 def test_matrix_core_coherence_15k_digest():
