@@ -118,6 +118,8 @@ typedef struct {
                                 3 dedup, 4 coherence, 5 order, 6 support, 7 total
                                 (batched fits: a group's shared stages are split
                                 over its problems by their share of the pairs)       */
+    float kernel_ms[2];      /* device time of the subset-test kernels alone:
+                                0 coherence, 1 support (0 when not measured)         */
 } ig_stats;
 
 typedef struct {

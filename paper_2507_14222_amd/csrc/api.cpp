@@ -163,13 +163,12 @@ struct DevModel {
     uint32_t *meta = nullptr;    // off[d] | flo[KS] | fhi[KS]
     uint16_t *nbins = nullptr;
     uint4 *frag[2] = {nullptr, nullptr};   // matrix-core scoring operands (KS <= 8)
-    uint32_t *sc[2] = {nullptr, nullptr};
     KeyPiece *pieces = nullptr;            // compressed sort keys (fits from codes), or null
     uint32_t npieces = 0, nkeys = 0;
     void *fac = nullptr;                   // factored-token table (features | digits | word starts)
     FactorView fv;                         // fv.KF = 0: matrix-core operands stay one-hot
     uint32_t fac_tokens = 0;               // tokens of the factored form
-    bool score_factored = false;           // frag/sc hold factored operand rows
+    bool score_factored = false;           // frag holds factored operand rows
     ig_stats stats{};
 
     uint32_t KO() const { return fv.KF ? fv.KF : KS; }
@@ -182,7 +181,6 @@ struct DevModel {
         }
         for (int c = 0; c < 2; ++c) {
             if (frag[c]) (void)hipFree(frag[c]);
-            if (sc[c]) (void)hipFree(sc[c]);
         }
         if (meta) (void)hipFree(meta);
         if (nbins) (void)hipFree(nbins);
@@ -594,8 +592,20 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         const uint32_t KO = mfma_view.KF ? mfma_view.KF : KS;
         Scratch<uint64_t> B(final_count * KO, s);
         launch_operand_rows(nullptr, 0, nullptr, m.W[c], KS, final_count, mfma_view, false, B.get(), s);
+        hipEvent_t ke[2];
+        IG_HIP(hipEventCreate(&ke[0]));
+        IG_HIP(hipEventCreate(&ke[1]));
+        IG_HIP(hipEventRecord(ke[0], s));
         launch_contain_mfma((int)KO, true, B.get(), final_count, own_frag, cls.n, m.f[c], s);
+        IG_HIP(hipEventRecord(ke[1], s));
         launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
+        float tk = 0;
+        const hipError_t er = hipEventSynchronize(ke[1]);
+        if (er == hipSuccess) (void)hipEventElapsedTime(&tk, ke[0], ke[1]);
+        (void)hipEventDestroy(ke[0]);
+        (void)hipEventDestroy(ke[1]);
+        IG_HIP(er);
+        m.stats.kernel_ms[1] += tk;
     } else
         launch_support((int)KS, tu.support_cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
 }
@@ -608,11 +618,10 @@ static void build_score_operands(DevModel &m, hipStream_t s) {
     if (KO > 8 || m.maxS[0] >= (1ll << 28) || m.maxS[1] >= (1ll << 28)) return;
     for (int c = 0; c < 2; ++c) {
         const uint64_t ntiles = (m.np[c] + 31) / 32;
-        m.frag[c] = dev_alloc<uint4>(ntiles * KO * 64);
-        m.sc[c] = dev_alloc<uint32_t>(ntiles * 32);
+        m.frag[c] = dev_alloc<uint4>(std::max<uint64_t>(ntiles, 1) * (KO + 1) * 64);
         Scratch<uint64_t> rows(std::max<uint64_t>(m.np[c], 1) * KO, s);
         launch_operand_rows(nullptr, 0, nullptr, m.W[c], m.KS, m.np[c], m.fv, false, rows.get(), s);
-        launch_mfma_patterns(rows.get(), m.S[c], (uint32_t)m.np[c], KO, m.frag[c], m.sc[c], s);
+        launch_mfma_patterns(rows.get(), m.S[c], (uint32_t)m.np[c], KO, m.frag[c], s);
     }
     m.score_factored = m.fv.KF > 0;
     IG_HIP(hipStreamSynchronize(s));
@@ -797,10 +806,15 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
                 Scratch<uint64_t> B((size_t)hc[c] * KO, s);
                 uint32_t *cc = cand.get() + (c == 0 ? 0 : hc[0]);
                 launch_operand_rows(cls[c].X.get(), cls[c].n, cc, nullptr, KS, hc[c], mview, false, B.get(), s);
+                IG_HIP(hipEventRecord(e[0], s));
                 launch_contain_mfma((int)KO, false, B.get(), hc[c], frag[c].get(), cls[1 - c].n, keep.get(), s);
+                IG_HIP(hipEventRecord(e[1], s));
                 scan_exclusive_u32(keep.get(), kpos.get(), hc[c], ktot.get(), s);
                 launch_compact(keep.get(), kpos.get(), cc, hc[c], surv[c].get() + mfma_surv[c], s);
                 mfma_surv[c] += host_read_u32(ktot.get(), 1, s)[0];
+                float tk;
+                IG_HIP(hipEventElapsedTime(&tk, e[0], e[1]));
+                m.stats.kernel_ms[0] += tk;
                 mfma_tests[c] += (uint64_t)hc[c] * cls[1 - c].n;
             }
             IG_HIP(hipEventRecord(e[4], s));
@@ -1428,7 +1442,6 @@ static ig::ScoreModel score_model(const ig::DevModel &M) {
         sm.np[c] = M.np[c];
         sm.maxS[c] = M.maxS[c];
         sm.frag[c] = M.frag[c];
-        sm.sc[c] = M.sc[c];
     }
     sm.KS = M.KS;
     sm.KO = M.score_factored ? M.fv.KF : M.KS;

@@ -151,17 +151,16 @@ struct ScoreModel {
     uint64_t np[2];
     uint32_t KS;
     int64_t maxS[2];            // largest weight of each class
-    const uint4 *frag[2];       // matrix-core operands of the patterns (or null)
-    const uint32_t *sc[2];      // their weights in accumulator order
+    const uint4 *frag[2];       // matrix-core operands of the patterns and weights (or null)
     uint32_t KO;                // operand words of frag (factored or one-hot)
     FactorView fv;              // the factoring of frag (fv.KF = 0: one-hot)
 };
-// Scoring on the matrix cores (KO <= 8, every weight < 2^28): patterns' operand
-// rows pre-expanded by launch_mfma_patterns into frag (ceil(m/32) * KO * 64 uint4)
-// and sc (ceil(m/32) * 32 u32).  Flows given as codes are factored like the
+// Scoring on the matrix cores (KO <= 8, every weight < 2^28): each 32-pattern tile
+// of frag holds the patterns' operand rows (KO * 64 uint4, tokens as -1.0) and the
+// int8 operand of their 7-bit weight chunks (64 uint4): ceil(m/32) * (KO + 1) * 64
+// uint4 from launch_mfma_patterns.  Flows given as codes are factored like the
 // patterns; flows given as words need one-hot operands (fv.KF = 0).
-void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, uint4 *frag, uint32_t *sc,
-                          hipStream_t s);
+void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, uint4 *frag, hipStream_t s);
 void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K,
                        uint32_t n_flows, uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out,
                        hipStream_t s);

@@ -210,7 +210,9 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
 // the fp32 accumulators.  One v_mfma_scale_f32_32x32x64_f8f6f4 covers 64 tokens
 // (one 64-bit word): lanes l and l+32 of a row / column supply its two 32-bit
 // halves.  Records are the A operand (rows), candidates the B operand (columns).
+typedef int v4i_t __attribute__((ext_vector_type(4)));
 typedef int v8i_t __attribute__((ext_vector_type(8)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
 typedef float v16f_t __attribute__((ext_vector_type(16)));
 
 // 8 bits -> 8 nibbles, bit i -> nibble i = (bit ? 1.0 : 0) in e2m1
@@ -223,13 +225,14 @@ __device__ __forceinline__ uint32_t spread8(uint32_t b) {
 }
 
 // Streaming A-operand tiles through LDS.  The tiles [t0, t1) of a fragment array
-// (KS * 64 uint4 per 32-row tile, optionally 32 u32 of per-row data) pass through
-// two LDS buffers of G tiles each: while the waves multiply the tiles of one
-// buffer, the next G tiles are already on their way from memory into the other
-// buffer (global_load_lds_dwordx4: memory to LDS without registers, lane l of a
-// wave writing bytes [16 l, 16 l + 16) of the wave's 1 KB slice); one barrier per
-// G tiles.  Loads past t1 are clamped to the last element of the range (no
-// branches; the copies are never read).
+// (TW uint4 per 32-row tile) pass through a ring of NB LDS buffers of G tiles
+// each.  Loads go from memory straight to LDS (global_load_lds_dwordx4: lane l of
+// a wave writes bytes [16 l, 16 l + 16) of the wave's 1 KB slice) and are issued
+// NB - 1 groups ahead, so that several groups of multiplications cover their
+// latency; one barrier per group.  Every wave issues the same number of loads per
+// group (slices past the group go to a 1 KB scratch slot), which lets vmcnt tell
+// exactly when a group has landed.  Loads past t1 are clamped to the last element
+// of the range (the copies are never read).
 typedef uint32_t v4u_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void load_to_lds16(const v4u_t *src, v4u_t *wave_slice) {
@@ -237,68 +240,55 @@ __device__ __forceinline__ void load_to_lds16(const v4u_t *src, v4u_t *wave_slic
                                      (__attribute__((address_space(3))) void *)wave_slice, 16, 0, 0);
 }
 
-template <int KS, int G, int NT, class Body>
-__device__ __forceinline__ void stream_tiles(const uint4 *__restrict__ frag_in, const uint32_t *__restrict__ side,
-                                             uint32_t t0, uint32_t t1, uint4 *lds_in, uint32_t *lds_side, Body body) {
-    constexpr int N = G * KS * 64;            // uint4 per group, a multiple of 64: whole waves
-    constexpr int PER = (N + NT - 1) / NT;    // per thread
-    constexpr int NS = G * 32;                // side words per group
-    constexpr int SPER = (NS + NT - 1) / NT;
+template <int N>
+__device__ __forceinline__ void wait_loads() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// LDS (uint4) of a ring: NB buffers of G tiles of TW uint4, plus the scratch slot
+template <int TW, int G, int NB>
+constexpr int ring_lds() { return NB * G * TW + 64; }
+
+template <int TW, int G, int NB, int NT, class Body>
+__device__ __forceinline__ void stream_tiles(const uint4 *__restrict__ frag_in, uint32_t t0, uint32_t t1,
+                                             uint4 *lds_in, Body body) {
+    constexpr int N = G * TW;                 // uint4 per group
+    constexpr int PER = (N + NT - 1) / NT;    // loads per thread per group
+    static_assert(NB >= 2 && NB <= 4 && (NB - 2) * PER <= 63, "ring depth");
     const v4u_t *frag = reinterpret_cast<const v4u_t *>(frag_in);
     v4u_t *lds = reinterpret_cast<v4u_t *>(lds_in);
+    v4u_t *dummy = lds + NB * N;
     const uint32_t lane = threadIdx.x & 63, wave_base = threadIdx.x & ~63u;
-    uint32_t rs[SPER];
-    auto fetch = [&](uint32_t t, int buf) __attribute__((always_inline)) {
-        const uint32_t avail = (t1 - t) * (KS * 64);
+    const uint32_t ng = (t1 - t0 + G - 1) / G;
+    auto issue = [&](uint32_t gi) __attribute__((always_inline)) {
+        const uint32_t t = t0 + gi * G;
+        const uint32_t avail = (t1 - t) * TW;
         const uint32_t last = (avail < (uint32_t)N ? avail : (uint32_t)N) - 1;
-        const v4u_t *src = frag + (size_t)t * (KS * 64);
+        const v4u_t *src = frag + (size_t)t * TW;
+        v4u_t *buf = lds + (gi % NB) * N;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const uint32_t q0 = wave_base + i * NT;   // first slot of this wave's slice
-            if (q0 < (uint32_t)N) {
-                const uint32_t q = q0 + lane;
-                load_to_lds16(src + (q < last ? q : last), lds + buf * N + q0);
-            }
-        }
-        if (side) {
-            const uint32_t savail = (t1 - t) * 32u;
-            const uint32_t slast = (savail < (uint32_t)NS ? savail : (uint32_t)NS) - 1;
-#pragma unroll
-            for (int i = 0; i < SPER; ++i) {
-                const uint32_t q = threadIdx.x + i * NT;
-                rs[i] = side[(size_t)t * 32 + (q < slast ? q : slast)];
-            }
+            const uint32_t q = q0 + lane;
+            load_to_lds16(src + (q < last ? q : last), q0 < (uint32_t)N ? buf + q0 : dummy);
         }
     };
-    auto store_side = [&](int buf) __attribute__((always_inline)) {
-        if (side) {
-            uint32_t *sdst = lds_side + buf * NS;
 #pragma unroll
-            for (int i = 0; i < SPER; ++i) {
-                const uint32_t q = threadIdx.x + i * NT;
-                if (q < (uint32_t)NS) sdst[q] = rs[i];
-            }
-        }
-    };
-    auto landed = []() __attribute__((always_inline)) { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); };
-    fetch(t0, 0);
-    store_side(0);
-    landed();
-    __syncthreads();
-    int buf = 0;
-    for (uint32_t t = t0; t < t1; t += G) {
-        const bool more = t + G < t1;
-        // the other buffer was last read before the previous barrier
-        if (more) fetch(t + G, buf ^ 1);
-        const uint32_t ng = t1 - t < (uint32_t)G ? t1 - t : (uint32_t)G;
-        for (uint32_t g = 0; g < ng; ++g)
-            body(lds_in + buf * N + g * (KS * 64), side ? lds_side + buf * NS + g * 32 : nullptr);
-        if (more) {
-            store_side(buf ^ 1);
-            landed();
-        }
+    for (int p = 0; p < NB - 1; ++p)
+        if ((uint32_t)p < ng) issue(p);
+    for (uint32_t g = 0; g < ng; ++g) {
+        // groups issued after g: min(NB - 2, ng - 1 - g); wait until only those are in flight
+        const uint32_t ahead = ng - 1 - g < (uint32_t)(NB - 2) ? ng - 1 - g : (uint32_t)(NB - 2);
+        if (NB >= 4 && ahead >= 2) wait_loads<(NB >= 4 ? 2 : 0) * PER>();
+        else if (NB >= 3 && ahead >= 1) wait_loads<PER>();
+        else wait_loads<0>();
+        // all of group g is in LDS, and every wave is done with group g - 1's buffer
         __syncthreads();
-        buf ^= 1;
+        if (g + NB - 1 < ng) issue(g + NB - 1);
+        const uint32_t t = t0 + g * G;
+        const uint32_t nt = t1 - t < (uint32_t)G ? t1 - t : (uint32_t)G;
+        const uint4 *cur = lds_in + (g % NB) * N;
+        for (uint32_t j = 0; j < nt; ++j) body(cur + j * TW);
     }
 }
 
@@ -324,8 +314,15 @@ constexpr int MF_COLS = MF_NT / 64 * MF_FB * 32;
 // two workgroups per CU (4 waves per SIMD: at most 128 VGPRs each, 2 x 64 KB of LDS),
 // so that one workgroup's waves multiply while the other's wait at a barrier
 constexpr int MF_WAVES_PER_SIMD = 4;
+#ifndef IG_MF_GTOK
+#define IG_MF_GTOK 16
+#endif
+#ifndef IG_MF_NB
+#define IG_MF_NB 3
+#endif
+constexpr int MF_NB = IG_MF_NB;   // LDS ring depth
 template <int KS>
-constexpr int mf_group() { return 32 / KS > 0 ? 32 / KS : 1; }   // tiles per LDS buffer (32 KB)
+constexpr int mf_group() { return IG_MF_GTOK / KS > 0 ? IG_MF_GTOK / KS : 1; }   // tiles per LDS buffer
 
 // Columns: operand rows B [m][KS], expanded bit -> nibble into the B operand in
 // registers (lane % 32 = column, lane / 32 = 32-token half of each word); the A
@@ -337,7 +334,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
                                                                          const uint4 *__restrict__ frag,
                                                                          uint32_t ntiles, uint32_t *__restrict__ out) {
     constexpr int G = mf_group<KS>();
-    __shared__ uint4 lds[2 * G * KS * 64];
+    __shared__ uint4 lds[ring_lds<KS * 64, G, MF_NB>()];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     v8i_t b[MF_FB][KS];
     uint32_t e[MF_FB], hits[MF_FB];
@@ -357,8 +354,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
         }
     }
     if (ntiles)
-        stream_tiles<KS, G, MF_NT>(frag, nullptr, 0, ntiles, lds, nullptr,
-                                   [&](const uint4 *tf, const uint32_t *) __attribute__((always_inline)) {
+        stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, 0, ntiles, lds, [&](const uint4 *tf) __attribute__((always_inline)) {
             v16f_t acc[MF_FB];
 #pragma unroll
             for (int f = 0; f < MF_FB; ++f) acc[f] = v16f_t{0};
@@ -420,28 +416,60 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
 // holds row (r / 4) * 8 + 4 h + r % 4 of the 32-row tile.
 __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return (r >> 2) * 8 + half * 4 + (r & 3); }
 
-// frag[(tile * KS + w) * 64 + lane] = nibbles of half (lane/32) of word w of row
-// tile*32 + lane%32 (empty past m); sc[(tile * 2 + half) * 16 + r] = weight of the
-// row held in accumulator r of lane half `half` (0 past m).
+// Scoring operands of a pattern set: (KS + 1) * 64 uint4 per 32-row tile.
+//  words w < KS, frag[(tile * (KS + 1) + w) * 64 + lane]: the nibbles of half
+//    (lane/32) of word w of row tile*32 + lane%32, as -1.0 (e2m1 0xA) per token
+//    (empty past m), so that an accumulator started at 1.0 ends at 1 - (tokens of
+//    the pattern missing from the flow): 1 exactly when the pattern lies inside;
+//  slice KS, frag[(tile * (KS + 1) + KS) * 64 + lane]: the A operand of the
+//    weighting product (v_mfma_i32_32x32x32_i8): for lane%32 = c < 4 and half h,
+//    byte j holds 7-bit chunk c of the weight of the row in accumulator j of half h
+//    (0 past m); other lanes zero.
 __global__ void k_mfma_patterns(const uint64_t *__restrict__ W, const int64_t *__restrict__ S, uint32_t m,
-                                uint32_t KS, uint32_t ntiles, uint4 *__restrict__ frag, uint32_t *__restrict__ sc) {
+                                uint32_t KS, uint32_t ntiles, uint4 *__restrict__ frag) {
     const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < (size_t)ntiles * KS * 64) {
-        const uint32_t lane = (uint32_t)(g % 64), w = (uint32_t)((g / 64) % KS), tile = (uint32_t)(g / (64 * KS));
+    if (g >= (size_t)ntiles * (KS + 1) * 64) return;
+    const uint32_t lane = (uint32_t)(g % 64), w = (uint32_t)((g / 64) % (KS + 1)), tile = (uint32_t)(g / (64 * (KS + 1)));
+    if (w < KS) {
         const uint32_t row = tile * 32 + lane % 32;
         const uint32_t d = row < m ? (uint32_t)(W[(size_t)row * KS + w] >> (32 * (lane / 32))) : 0u;
-        frag[g] = make_uint4(spread8(d), spread8(d >> 8), spread8(d >> 16), spread8(d >> 24));
+        frag[g] = make_uint4(spread8(d) * 5u, spread8(d >> 8) * 5u, spread8(d >> 16) * 5u, spread8(d >> 24) * 5u);
+        return;
     }
-    if (g < (size_t)ntiles * 32) {
-        const uint32_t tile = (uint32_t)(g / 32), half = (uint32_t)((g / 16) % 2), r = (uint32_t)(g % 16);
-        const uint32_t row = tile * 32 + acc_row(half, r);
-        sc[g] = row < m ? (uint32_t)S[row] : 0u;
-    }
+    const uint32_t c = lane % 32, half = lane / 32;
+    uint32_t q[4] = {0, 0, 0, 0};
+    if (c < 4)
+        for (uint32_t j = 0; j < 16; ++j) {
+            const uint32_t row = tile * 32 + acc_row(half, j);
+            const uint32_t chunk = row < m ? (uint32_t)(S[row] >> (7 * c)) & 127u : 0u;
+            q[j / 4] |= chunk << (8 * (j % 4));
+        }
+    frag[g] = make_uint4(q[0], q[1], q[2], q[3]);
 }
+
+// Scoring workgroups: SC_NT threads, at most SC_WPS waves per SIMD (the weighting
+// product's int32 accumulators need more registers than the fit's kernels).
+#ifndef IG_SCORE_NT
+#define IG_SCORE_NT 256
+#endif
+#ifndef IG_SCORE_WPS
+#define IG_SCORE_WPS 3
+#endif
+#ifndef IG_SCORE_GTOK
+#define IG_SCORE_GTOK 16
+#endif
+#ifndef IG_SCORE_NB
+#define IG_SCORE_NB 3
+#endif
+constexpr int SC_NB = IG_SCORE_NB;
+constexpr int SC_NT = IG_SCORE_NT;
+constexpr int SC_WPS = IG_SCORE_WPS;
+constexpr int SC_COLS = SC_NT / 64 * MF_FB * 32;
+template <int KS>
+constexpr int sc_group() { return IG_SCORE_GTOK / (KS + 1) > 0 ? IG_SCORE_GTOK / (KS + 1) : 1; }
 
 struct ScoreMfmaArgs {
     const uint4 *frag[2];
-    const uint32_t *sc[2];
     uint32_t ntiles[2];
     uint32_t chunk;             // pattern tiles per workgroup
     uint32_t groups[2];         // tile ranges of each class
@@ -459,10 +487,10 @@ struct ScoreMfmaArgs {
 // of pattern tiles get ids that differ by multiples of 8, so they are dispatched
 // to one XCD and share its L2.
 template <int KS>
-__global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_score_mfma(ScoreMfmaArgs a) {
-    constexpr int G = mf_group<KS>();
-    __shared__ uint4 lds[2 * G * KS * 64];
-    __shared__ uint32_t lds_s[2 * G * 32];
+__global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
+    constexpr int G = sc_group<KS>();
+    constexpr int TW = (KS + 1) * 64;
+    __shared__ uint4 lds[ring_lds<TW, G, SC_NB>()];
     const uint32_t id = blockIdx.x, xcd = id % 8, seq = id / 8;
     const uint32_t range = (seq / a.fblocks) * 8 + xcd, fb = seq % a.fblocks;
     if (range >= a.groups[0] + a.groups[1]) return;   // uniform over the workgroup
@@ -472,11 +500,10 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_score_mfma(ScoreMf
     if (t0 >= t1) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     v8i_t b[MF_FB][KS];
-    uint64_t sum[MF_FB];
     uint32_t tf[MF_FB];
 #pragma unroll
     for (int f = 0; f < MF_FB; ++f) {
-        const uint32_t t = fb * MF_COLS + wave * (MF_FB * 32) + f * 32 + col;
+        const uint32_t t = fb * SC_COLS + wave * (MF_FB * 32) + f * 32 + col;
         tf[f] = t;
         const bool act = t < a.n_flows;
         uint64_t wd[KS];
@@ -521,12 +548,18 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_score_mfma(ScoreMf
             b[f][k] = v8i_t{(int)spread8(dwd), (int)spread8(dwd >> 8), (int)spread8(dwd >> 16),
                             (int)spread8(dwd >> 24), 0, 0, 0, 0};
         }
-        sum[f] = 0;
     }
-    stream_tiles<KS, G, MF_NT>(a.frag[cls], a.sc[cls], t0, t1, lds, lds_s, [&](const uint4 *tile, const uint32_t *ws) __attribute__((always_inline)) {
+    // C[f]: running weighting products; row c < 4 of column `col` (lane half 0,
+    // accumulators 0..3) sums chunk c of the weights of the patterns inside the flow
+    v16i_t C[MF_FB];
+#pragma unroll
+    for (int f = 0; f < MF_FB; ++f) C[f] = v16i_t{0};
+    stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], t0, t1, lds, [&](const uint4 *tile) __attribute__((always_inline)) {
         v16f_t acc[MF_FB];
 #pragma unroll
-        for (int f = 0; f < MF_FB; ++f) acc[f] = v16f_t{0};
+        for (int f = 0; f < MF_FB; ++f)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[f][r] = 1.0f;
 #pragma unroll
         for (int w = 0; w < KS; ++w) {
             const uint4 a4 = tile[w * 64 + lane];
@@ -535,34 +568,42 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_score_mfma(ScoreMf
             for (int f = 0; f < MF_FB; ++f)
                 acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
         }
-        uint32_t s16[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) s16[r] = ws[half * 16 + r];
+        // weight chunks of this tile as the A operand (rows c < 4; other rows zero)
+        const uint4 q = tile[KS * 64 + lane];
+        const v4i_t wa = {(int)q.x, (int)q.y, (int)q.z, (int)q.w};
 #pragma unroll
         for (int f = 0; f < MF_FB; ++f) {
-            uint32_t lo = 0;   // 16 weights below 2^28 each: no wrap
+            // inside = max(acc, 0) as a byte (1 or 0), accumulator r -> byte r
+            v4i_t z;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) lo += acc[f][r] == 0.0f ? s16[r] : 0u;
-            sum[f] += lo;
+            for (int q = 0; q < 4; ++q) {
+                uint32_t d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q], 0, 0u);
+                d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 1], 1, d);
+                d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 2], 2, d);
+                d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 3], 3, d);
+                z[q] = (int)d;
+            }
+            C[f] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wa, z, C[f], 0, 0, 0);
         }
     });
     const int colsel = cls == 1 ? 0 : 1;   // A from class 1, N from class 0
 #pragma unroll
     for (int f = 0; f < MF_FB; ++f) {
-        const uint64_t v = sum[f] + __shfl_xor(sum[f], 32, 64);   // the two halves hold different rows
+        uint64_t v = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v += (uint64_t)(uint32_t)C[f][c] << (7 * c);
         if (half == 0 && tf[f] < a.n_flows && v)
             atomicAdd(reinterpret_cast<unsigned long long *>(a.out + 2 * (size_t)tf[f] + colsel),
                       (unsigned long long)v);
     }
 }
 
-void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, uint4 *frag, uint32_t *sc,
-                          hipStream_t s) {
+void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, uint4 *frag, hipStream_t s) {
     const uint32_t ntiles = (m + 31) / 32;
-    const size_t total = (size_t)ntiles * KS * 64;
+    const size_t total = (size_t)ntiles * (KS + 1) * 64;
     if (!total) return;
     hipLaunchKernelGGL(k_mfma_patterns, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, W, S, m, KS, ntiles,
-                       frag, sc);
+                       frag);
     IG_HIP(hipGetLastError());
 }
 
@@ -953,7 +994,6 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     ScoreMfmaArgs a{};
     for (int c = 0; c < 2; ++c) {
         a.frag[c] = m.frag[c];
-        a.sc[c] = m.sc[c];
         a.ntiles[c] = (uint32_t)((m.np[c] + 31) / 32);
     }
     a.codes = codes;
@@ -966,13 +1006,15 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     a.K = K;
     a.fv = m.fv;
     IG_REQUIRE(!m.fv.KF || codes, IG_E_UNSUPPORTED, "factored matrix-core operands score flows given as codes");
-    a.fblocks = (n_flows + MF_COLS - 1) / MF_COLS;
+    a.fblocks = (n_flows + SC_COLS - 1) / SC_COLS;
     const uint32_t tiles = a.ntiles[0] + a.ntiles[1];
     if (!tiles) return;
     // about 2048 workgroups in all: several per CU, short tail
     uint32_t ranges = (2048 + a.fblocks - 1) / a.fblocks;
     if (ranges > tiles) ranges = tiles;
     a.chunk = (tiles + ranges - 1) / ranges;
+    // the int32 weighting sums stay exact: at most 32 rows x 127 per tile
+    if (a.chunk > (1u << 18)) a.chunk = 1u << 18;
     a.groups[0] = (a.ntiles[0] + a.chunk - 1) / a.chunk;
     a.groups[1] = (a.ntiles[1] + a.chunk - 1) / a.chunk;
     const uint64_t nr = ((uint64_t)a.groups[0] + a.groups[1] + 7) / 8 * 8;
@@ -980,7 +1022,7 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     const dim3 grid((unsigned)(nr * a.fblocks));
 #define IG_SCM(V)                                                                    \
     case V:                                                                          \
-        hipLaunchKernelGGL((k_score_mfma<V>), grid, dim3(MF_NT), 0, s, a);          \
+        hipLaunchKernelGGL((k_score_mfma<V>), grid, dim3(SC_NT), 0, s, a);          \
         break;
     switch ((int)m.KO) {
         IG_SCM(1) IG_SCM(2) IG_SCM(3) IG_SCM(4) IG_SCM(5) IG_SCM(6) IG_SCM(7) IG_SCM(8)

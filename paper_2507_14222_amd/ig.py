@@ -44,7 +44,7 @@ class FitOpts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n_class", C.c_uint64 * 2), ("pairs", C.c_uint64 * 2), ("distinct", C.c_uint64 * 2),
                 ("coherent", C.c_uint64 * 2), ("tests", C.c_uint64 * 2), ("support_tests", C.c_uint64 * 2),
-                ("chunks", C.c_uint32 * 2), ("ms", C.c_float * 8)]
+                ("chunks", C.c_uint32 * 2), ("ms", C.c_float * 8), ("kernel_ms", C.c_float * 2)]
 
 
 class ModelInfo(C.Structure):
@@ -169,6 +169,7 @@ class FitStats:
     support_tests: Tuple[int, int]
     chunks: Tuple[int, int]
     ms: Tuple[float, ...]
+    kernel_ms: Tuple[float, float] = (0.0, 0.0)   # subset-test kernels alone: coherence, support
 
 
 class Model:
@@ -205,7 +206,7 @@ class Model:
         _check(lib().ig_fit_stats(self.handle, C.byref(s)))
         t = lambda a: (int(a[0]), int(a[1]))
         return FitStats(t(s.n_class), t(s.pairs), t(s.distinct), t(s.coherent), t(s.tests), t(s.support_tests),
-                        t(s.chunks), tuple(float(x) for x in s.ms))
+                        t(s.chunks), tuple(float(x) for x in s.ms), tuple(float(x) for x in s.kernel_ms))
 
     def export(self, cls: int):
         """(words uint64 [n, K], f uint32 [n], S int64 [n]) of class ``cls``, ascending."""
