@@ -19,8 +19,10 @@
  *   of word j/64 (least significant bit first).  Unused high bits are zero.
  * Readings.  f_c(b) counts the class-c training records (repeats included)
  *   that contain b; |b| is the number of tokens of b; the empty intersection is
- *   never a pattern; patterns are reported in ascending order of
- *   (w_0, ..., w_{K-1}) compared as unsigned 64-bit words, w_0 most significant.
+ *   never a pattern.  A pattern set is a set: a model holds its rows in an
+ *   unspecified order (whatever the fit produced them in); ig_model_export
+ *   reports them in ascending order of (w_0, ..., w_{K-1}) compared as unsigned
+ *   64-bit words, w_0 most significant.
  * Memory.  Pointers named d_* are device (HBM) pointers on the current HIP
  *   device; h_* are host pointers.  Inputs are borrowed for the duration of the
  *   call (until the stream reaches the call's last kernel for the asynchronous
@@ -156,8 +158,7 @@ typedef struct {
  *   d_codes  device [n][d] uint16, row-major; d_codes[i*d+f] < h_nbins[f]
  *   d_labels device [n] uint8 in {0,1}
  *   h_nbins  host [d], each >= 1; L = sum <= 4096
- * Builds *out, a device-resident model holding P^0 and P^1 in canonical order
- * with f and S.  Synchronises `stream` before returning (pattern counts are
+ * Builds *out, a device-resident model holding P^0 and P^1 with f and S.  Synchronises `stream` before returning (pattern counts are
  * data-dependent).  IG_E_INVAL if any code or label is out of range (checked on
  * the device before anything is fitted).  On error *out is left untouched.
  * ------------------------------------------------------------------------- */
@@ -203,8 +204,9 @@ ig_status ig_score_packed(const ig_model *m, const uint64_t *d_words, uint32_t n
 ig_status ig_model_get_info(const ig_model *m, ig_model_info *info);
 
 /* Copy class `cls` of a model to the host: h_words [n][K] (may be NULL),
- * h_f [n] (may be NULL), h_S [n] (may be NULL), with n = info.n_patterns[cls].
- * Synchronous. */
+ * h_f [n] (may be NULL), h_S [n] (may be NULL), with n = info.n_patterns[cls],
+ * rows in ascending order of (w_0, ..., w_{K-1}) (sorted on the device, with
+ * scratch of about 24 bytes per pattern).  Synchronous. */
 ig_status ig_model_export(const ig_model *m, uint32_t cls, uint64_t *h_words, uint32_t *h_f,
                           int64_t *h_S);
 
@@ -212,16 +214,15 @@ ig_status ig_model_export(const ig_model *m, uint32_t cls, uint64_t *h_words, ui
  *   h_codes[c]  host [count[c]][d] uint16 pattern code rows; IG_ABSENT marks a
  *               feature the pattern does not contain; at least one feature set
  *   h_f[c]      host [count[c]] supports f
- * Each pattern is packed, weighted with S = f * |b|^2 (Eq. 2) and the set is put
- * in canonical order on the device.  Patterns of a class must be distinct
+ * Each pattern is packed and weighted with S = f * |b|^2 (Eq. 2) on the device.  Patterns of a class must be distinct
  * (IG_E_INVAL otherwise).  Synchronous. */
 ig_status ig_model_import(const uint16_t *const h_codes[2], const uint32_t *const h_f[2],
                           const uint64_t count[2], uint32_t d, const uint16_t *h_nbins,
                           void *stream, ig_model **out);
 
-/* Order-dependent 64-bit digest of class `cls` (rows, f and S in canonical
- * order), computed on the device: compares models that are too large to copy
- * out.  Equal models give equal digests.  Synchronous. */
+/* 64-bit digest of the set of (row, f, S) of class `cls`, independent of the order
+ * the rows are held in, computed on the device: compares models that are too
+ * large to copy out.  Equal pattern sets give equal digests.  Synchronous. */
 ig_status ig_model_digest(const ig_model *m, uint32_t cls, uint64_t *out);
 
 /* Counters and stage timings of the fit that built the model (zeros for an

@@ -483,21 +483,16 @@ struct ClassRows {
     uint32_t n = 0;
 };
 
-// Canonical order (ascending w_0..w_{K-1}) of the pair ids `ids` of one class;
-// then rows, merge of equal rows (they arise when the pair space was chunked),
-// support and weights.  Fills model class c.
-static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *ids, size_t count,
-                            bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
-                            int support_mark = -1, const uint4 *own_frag = nullptr,
-                            const FactorView &mfma_view = FactorView{}) {
+// Canonical order (ascending w_0 .. w_{K-1}, unsigned, w_0 most significant) of
+// `count` patterns: the pair ids `ids` into the class rows X [n][KS], or, with ids
+// null, the rows X [count][KS] themselves.  Writes the sorting permutation to perm
+// (perm[e] = index of the e-th pattern in order).  LSD radix sort of a permutation,
+// on compressed keys when the model has them (fits from codes), else on the words.
+static void canonical_permutation(const DevModel &m, const uint64_t *X, uint32_t n, const uint32_t *ids,
+                                  size_t count, uint32_t *perm, hipStream_t s) {
     const uint32_t KS = m.KS, K = m.K;
-    if (count == 0) {
-        m.np[c] = 0;
-        m.W[c] = dev_alloc<uint64_t>(KS);
-        m.f[c] = dev_alloc<uint32_t>(1);
-        m.S[c] = dev_alloc<int64_t>(1);
-        return;
-    }
+    launch_iota(perm, count, s);
+    if (count <= 1) return;
     auto byte_mask = [](unsigned long long orv, unsigned long long andv) {
         const uint64_t vary = orv ^ andv;   // bits that differ somewhere
         uint32_t mask = 0;
@@ -505,62 +500,69 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
             if ((vary >> (8 * b)) & 0xffull) mask |= 1u << b;
         return mask;
     };
-    Scratch<uint64_t> k0, k1;
-    Scratch<uint32_t> v1, sorted_ids;
-    uint32_t *vcur = ids, *valt = nullptr;
+    // key words (nk arrays of `count`), least significant first in the sort
+    const uint32_t nk = m.pieces ? m.nkeys : K;
+    Scratch<uint64_t> keys((size_t)nk * count, s);
     if (m.pieces) {
-        // compressed keys: LSD radix sort of a permutation over the key words
-        const uint32_t nk = m.nkeys;
-        Scratch<uint64_t> keys((size_t)nk * count, s);
-        launch_compress_keys(cls.X.get(), cls.n, KS, ids, count, m.pieces, m.npieces, keys.get(), s);
-        Scratch<unsigned long long> rng(2 * nk, s);
-        launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get()), 0ull, nk, s);
-        launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get() + nk), ~0ull, nk, s);
-        launch_key_range(keys.get(), nk, count, rng.get(), rng.get() + nk, s);
-        std::vector<unsigned long long> hr(2 * nk);
-        IG_HIP(hipMemcpyAsync(hr.data(), rng.get(), 2 * nk * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        IG_HIP(hipStreamSynchronize(s));
-        Scratch<uint32_t> perm(count, s), palt(count, s);
-        k1.reset(count, s);
-        k0.reset(count, s);
-        launch_iota(perm.get(), count, s);
-        uint32_t *pcur = perm.get(), *pnext = palt.get();
-        bool identity = true;   // pcur is still the identity permutation
-        for (int k = (int)nk - 1; k >= 0; --k) {
-            const uint32_t mask = byte_mask(hr[k], hr[nk + k]);
-            if (!mask) continue;
-            uint64_t *kin = keys.get() + (size_t)k * count;   // consumed: the sort may overwrite it
-            if (!identity) {
-                launch_permute_u64(kin, pcur, count, k0.get(), s);
-                kin = k0.get();
-            }
-            const int where = radix_sort_pairs(kin, pcur, k1.get(), pnext, count, mask, s);
-            if (where) std::swap(pcur, pnext);
-            identity = false;
-        }
-        sorted_ids.reset(count, s);
-        launch_permute_u32(ids, pcur, count, sorted_ids.get(), s);
-        vcur = sorted_ids.get();
+        launch_compress_keys(X, n, KS, ids, count, m.pieces, m.npieces, keys.get(), s);
     } else {
-        // which bytes of which words vary at all
-        Scratch<unsigned long long> rng(2 * K, s);
-        launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get()), 0ull, K, s);
-        launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get() + K), ~0ull, K, s);
-        launch_word_range(cls.X.get(), cls.n, KS, K, ids, count, rng.get(), rng.get() + K, s);
-        std::vector<unsigned long long> hr(2 * K);
-        IG_HIP(hipMemcpyAsync(hr.data(), rng.get(), 2 * K * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        IG_HIP(hipStreamSynchronize(s));
-        k0.reset(count, s);
-        k1.reset(count, s);
-        v1.reset(count, s);
-        valt = v1.get();
-        for (int k = (int)K - 1; k >= 0; --k) {
-            const uint32_t mask = byte_mask(hr[k], hr[K + k]);
-            if (!mask) continue;
-            launch_gather_word(cls.X.get(), cls.n, KS, (uint32_t)k, vcur, count, k0.get(), s);
-            int where = radix_sort_pairs(k0.get(), vcur, k1.get(), valt, count, mask, s);
-            if (where) std::swap(vcur, valt);
+        Scratch<uint32_t> iota(count, s);
+        launch_iota(iota.get(), count, s);
+        for (uint32_t k = 0; k < K; ++k) {
+            if (ids) launch_gather_word(X, n, KS, k, ids, count, keys.get() + (size_t)k * count, s);
+            else launch_row_word(X, iota.get(), count, KS, k, keys.get() + (size_t)k * count, s);
         }
+    }
+    Scratch<unsigned long long> rng(2 * nk, s);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get()), 0ull, nk, s);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(rng.get() + nk), ~0ull, nk, s);
+    launch_key_range(keys.get(), nk, count, rng.get(), rng.get() + nk, s);
+    std::vector<unsigned long long> hr(2 * nk);
+    IG_HIP(hipMemcpyAsync(hr.data(), rng.get(), 2 * nk * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    IG_HIP(hipStreamSynchronize(s));
+    Scratch<uint32_t> palt(count, s);
+    Scratch<uint64_t> k0(count, s), k1(count, s);
+    uint32_t *pcur = perm, *pnext = palt.get();
+    bool identity = true;   // pcur is still the identity permutation
+    for (int k = (int)nk - 1; k >= 0; --k) {
+        const uint32_t mask = byte_mask(hr[k], hr[nk + k]);
+        if (!mask) continue;
+        uint64_t *kin = keys.get() + (size_t)k * count;   // consumed: the sort may overwrite it
+        if (!identity) {
+            launch_permute_u64(kin, pcur, count, k0.get(), s);
+            kin = k0.get();
+        }
+        const int where = radix_sort_pairs(kin, pcur, k1.get(), pnext, count, mask, s);
+        if (where) std::swap(pcur, pnext);
+        identity = false;
+    }
+    if (pcur != perm) IG_HIP(hipMemcpyAsync(perm, pcur, count * 4, hipMemcpyDeviceToDevice, s));
+}
+
+// Rows of the coherent pair ids `ids` of one class (in the order given; in
+// canonical order first when the pair space was chunked, which merges the repeats
+// across chunks), then support and weights.  Fills model class c.
+static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *ids, size_t count,
+                            bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
+                            int support_mark = -1, const uint4 *own_frag = nullptr,
+                            const FactorView &mfma_view = FactorView{}) {
+    const uint32_t KS = m.KS;
+    if (count == 0) {
+        m.np[c] = 0;
+        m.W[c] = dev_alloc<uint64_t>(KS);
+        m.f[c] = dev_alloc<uint32_t>(1);
+        m.S[c] = dev_alloc<int64_t>(1);
+        return;
+    }
+    Scratch<uint32_t> sorted_ids;
+    uint32_t *vcur = ids;
+    if (may_repeat) {
+        // the chunks' survivors may repeat a pattern: canonical order puts repeats side by side
+        Scratch<uint32_t> perm(count, s);
+        canonical_permutation(m, cls.X.get(), cls.n, ids, count, perm.get(), s);
+        sorted_ids.reset(count, s);
+        launch_permute_u32(ids, perm.get(), count, sorted_ids.get(), s);
+        vcur = sorted_ids.get();
     }
     Scratch<uint64_t> Wtmp;
     Scratch<uint32_t> flag;
@@ -1505,15 +1507,25 @@ ig_status ig_model_export(const ig_model *m, uint32_t cls, uint64_t *h_words, ui
         IG_REQUIRE(cls <= 1, IG_E_INVAL, "class must be 0 or 1");
         const DevModel &M = *m->m;
         const uint64_t n = M.np[cls];
-        if (h_words && n) {
+        if (!n || !(h_words || h_f || h_S)) return;
+        IG_REQUIRE(n < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 patterns in one class");
+        // rows in canonical order, sorted on the device
+        hipStream_t s = nullptr;
+        ig::Scratch<uint32_t> perm(n, s), fo(n, s);
+        ig::Scratch<uint64_t> rows(n * M.KS, s), So(n, s);
+        ig::canonical_permutation(M, M.W[cls], 0, nullptr, n, perm.get(), s);
+        ig::launch_gather_rows(M.W[cls], perm.get(), n, M.KS, rows.get(), M.f[cls], fo.get(), s);
+        ig::launch_permute_u64(reinterpret_cast<const uint64_t *>(M.S[cls]), perm.get(), n, So.get(), s);
+        IG_HIP(hipStreamSynchronize(s));
+        if (h_words) {
             if (M.KS == M.K) {
-                IG_HIP(hipMemcpy(h_words, M.W[cls], n * M.K * 8, hipMemcpyDeviceToHost));
+                IG_HIP(hipMemcpy(h_words, rows.get(), n * M.K * 8, hipMemcpyDeviceToHost));
             } else {
-                IG_HIP(hipMemcpy2D(h_words, M.K * 8, M.W[cls], M.KS * 8, M.K * 8, n, hipMemcpyDeviceToHost));
+                IG_HIP(hipMemcpy2D(h_words, M.K * 8, rows.get(), M.KS * 8, M.K * 8, n, hipMemcpyDeviceToHost));
             }
         }
-        if (h_f && n) IG_HIP(hipMemcpy(h_f, M.f[cls], n * 4, hipMemcpyDeviceToHost));
-        if (h_S && n) IG_HIP(hipMemcpy(h_S, M.S[cls], n * 8, hipMemcpyDeviceToHost));
+        if (h_f) IG_HIP(hipMemcpy(h_f, fo.get(), n * 4, hipMemcpyDeviceToHost));
+        if (h_S) IG_HIP(hipMemcpy(h_S, So.get(), n * 8, hipMemcpyDeviceToHost));
     });
 }
 

@@ -56,7 +56,8 @@ void launch_iota(uint32_t *v, size_t m, hipStream_t s);
 struct KeyPiece {
     uint8_t word, lo, width, kw, shift, pad[3];   // bits [lo, lo+width) of word -> kw << shift
 };
-// keys[k * m + e] = key word k of pattern ids[e]
+// keys[k * m + e] = key word k of pattern ids[e] (rows X [n][KS]), or of row X[e]
+// when ids is null
 void launch_compress_keys(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m,
                           const KeyPiece *pieces, uint32_t npieces, uint64_t *keys, hipStream_t s);
 // OR and AND of each of nk key arrays of length m (orv/andv preset to 0 / ~0)
@@ -125,7 +126,7 @@ void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, ui
                       uint32_t *queue, uint32_t grid, hipStream_t s);
 // persistent grid of the coherence kernel: grid_per_cu workgroups per compute unit
 uint32_t coherence_grid(uint32_t grid_per_cu);
-// order-dependent digest of rows [m][KS] (first K words), f and S
+// digest of the set of (row [first K words], f, S) over rows [m][KS], order-free
 void launch_digest(const uint64_t *W, const uint32_t *f, const int64_t *S, size_t m, uint32_t KS, uint32_t K,
                    unsigned long long *out, hipStream_t s);
 

@@ -355,9 +355,15 @@ __global__ __launch_bounds__(256) void k_compress_keys(const uint64_t *__restric
                                                       uint64_t *__restrict__ keys) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
-    uint32_t i, j;
-    decode_pair(ids[e], n, i, j);
-    const uint64_t *ra = X + (size_t)i * KS, *rb = X + (size_t)j * KS;
+    const uint64_t *ra, *rb;
+    if (ids) {
+        uint32_t i, j;
+        decode_pair(ids[e], n, i, j);
+        ra = X + (size_t)i * KS;
+        rb = X + (size_t)j * KS;
+    } else {
+        ra = rb = X + e * KS;   // X holds the rows themselves
+    }
     uint32_t cur_word = 0xffffffffu, cur_kw = 0;
     uint64_t word = 0, acc = 0;
     for (uint32_t p = 0; p < npieces; ++p) {

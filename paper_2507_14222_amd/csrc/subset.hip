@@ -945,7 +945,7 @@ __global__ __launch_bounds__(256) void k_digest(const uint64_t *__restrict__ W, 
     __shared__ unsigned long long part[4];
     unsigned long long acc = 0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
-        uint64_t h = dmix(e + 0x9e3779b97f4a7c15ull);
+        uint64_t h = 0x9e3779b97f4a7c15ull;   // no position: a digest of the set
         for (uint32_t k = 0; k < K; ++k) h = dmix(h ^ W[e * KS + k]);
         h = dmix(h ^ f[e]);
         h = dmix(h ^ (uint64_t)S[e]);
