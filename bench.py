@@ -110,6 +110,8 @@ def measure_batch():
         st = m.stats()
         dig_s[i] = (m.digest(0), m.digest(1), tuple(st.coherent))
         m.free()
+        if i % 8 == 7:
+            log("sequential fits done:", i + 1)
     same = all(dig_b[i] == dig_s[i] for i in range(len(probs)))
     pats = sum(sum(dig_b[i][2]) for i in dig_b)
     return {"workload": "64 problems (seed 3)", "problems": len(probs), "slices": len(slices),

@@ -657,6 +657,73 @@ static std::vector<uint32_t> coherence_phases(uint32_t max_other) {
 // full comparison; at 2^24 distinct per class about 2^8 pairs of them do.
 constexpr int kPairKeyBytes = 5;
 
+// Matrix-core operands of one fit: the token view (factored, or the one-hot words
+// in mode 3) and, per class c, the records of class 1 - c as A tiles (class c's
+// coherence operand, and class 1 - c's support operand).
+struct MfmaFit {
+    bool on = false;
+    FactorView view;
+    uint32_t KO = 0;
+    Scratch<uint4> frag[2];
+};
+
+// Decide the subset-test path of a fit from the coherence_mfma option (0 auto:
+// matrix cores when the operands fit 8 words; 1 matrix cores; 2 VALU; 3 matrix
+// cores on the one-hot words) and build the record tiles when it is the matrix
+// cores.
+static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode, MfmaFit &mf, hipStream_t s) {
+    IG_REQUIRE(mode <= 3, IG_E_INVAL, "coherence_mfma must be 0, 1, 2 or 3");
+    const uint32_t KS = m.KS;
+    mf.view = mode == 3 ? FactorView{} : m.fv;
+    mf.KO = mf.view.KF ? mf.view.KF : KS;
+    IG_REQUIRE((mode != 1 && mode != 3) || mf.KO <= 8, IG_E_UNSUPPORTED,
+               "the matrix-core subset tests handle up to 8 operand words");
+    mf.on = mode == 1 || mode == 3 || (mode == 0 && mf.KO <= 8);
+    if (!mf.on) return;
+    for (int c = 0; c < 2; ++c) {
+        const ClassRows &o = cls[1 - c];
+        mf.frag[c].reset(std::max<size_t>((size_t)mfma_record_tiles(o.n) * mf.KO * 64, 1), s);
+        if (mf.view.KF) {
+            Scratch<uint64_t> nrows(std::max<size_t>(o.n, 1) * mf.KO, s);
+            launch_operand_rows(nullptr, 0, nullptr, o.X.get(), KS, o.n, mf.view, true, nrows.get(), s);
+            launch_mfma_records(nrows.get(), o.n, mf.KO, mf.frag[c].get(), s);
+        } else {
+            launch_mfma_records(o.NX.get(), o.n, KS, mf.frag[c].get(), s);
+        }
+    }
+}
+
+// Coherence of class c's ncand candidate pair ids `cand` on the matrix cores
+// (Eq. 3, dense): appends the coherent ids to `out` and returns how many
+// (synchronises the stream); adds the contraction's device time to *kernel_ms.
+static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c, uint32_t KS, const uint32_t *cand,
+                               uint32_t ncand, uint32_t *out, float *kernel_ms, hipStream_t s) {
+    if (!ncand) return 0;
+    Scratch<uint32_t> keep(ncand, s), kpos(ncand, s), ktot(1, s);
+    Scratch<uint64_t> B((size_t)ncand * mf.KO, s);
+    launch_operand_rows(cls[c].X.get(), cls[c].n, cand, nullptr, KS, ncand, mf.view, false, B.get(), s);
+    hipEvent_t ke[2];
+    IG_HIP(hipEventCreate(&ke[0]));
+    IG_HIP(hipEventCreate(&ke[1]));
+    struct Ev {
+        hipEvent_t *e;
+        ~Ev() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } evg{ke};
+    IG_HIP(hipEventRecord(ke[0], s));
+    launch_contain_mfma((int)mf.KO, false, B.get(), ncand, mf.frag[c].get(), cls[1 - c].n, keep.get(), s);
+    IG_HIP(hipEventRecord(ke[1], s));
+    scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
+    launch_compact(keep.get(), kpos.get(), cand, ncand, out, s);
+    const uint32_t kept = host_read_u32(ktot.get(), 1, s)[0];
+    float tk = 0;
+    IG_HIP(hipEventElapsedTime(&tk, ke[0], ke[1]));
+    if (kernel_ms) *kernel_ms += tk;
+    return kept;
+}
+
 static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts, hipStream_t s, Timer &tm) {
     const uint32_t KS = m.KS, K = m.K;
     const Tuning tu = tuning_for(opts, KS, (uint64_t)cls[0].n * (cls[0].n ? cls[0].n - 1 : 0) / 2 +
@@ -721,29 +788,10 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         IG_HIP(hipStreamSynchronize(s));
     }
     const uint32_t grid = coherence_grid(tu.grid_per_cu);
-    const uint32_t mode = opts ? opts->coherence_mfma : 0u;
-    IG_REQUIRE(mode <= 3, IG_E_INVAL, "coherence_mfma must be 0, 1, 2 or 3");
-    // matrix-core operands: factored tokens when the fit has a factoring (mode 3: the
-    // one-hot words), at most 8 operand words
-    const FactorView mview = mode == 3 ? FactorView{} : m.fv;
-    const uint32_t KO = mview.KF ? mview.KF : KS;
-    IG_REQUIRE((mode != 1 && mode != 3) || KO <= 8, IG_E_UNSUPPORTED,
-               "the matrix-core subset tests handle up to 8 operand words");
-    const bool use_mfma = mode == 1 || mode == 3 || (mode == 0 && KO <= 8);
-    Scratch<uint4> frag[2];   // per class c: the other class's records as the A operand
+    MfmaFit mf;
+    mfma_setup(m, cls, opts ? opts->coherence_mfma : 0u, mf, s);
+    const bool use_mfma = mf.on;
     uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
-    if (use_mfma)
-        for (int c = 0; c < 2; ++c) {
-            const ClassRows &o = cls[1 - c];
-            frag[c].reset(std::max<size_t>((size_t)mfma_record_tiles(o.n) * KO * 64, 1), s);
-            if (mview.KF) {
-                Scratch<uint64_t> nrows(std::max<size_t>(o.n, 1) * KO, s);
-                launch_operand_rows(nullptr, 0, nullptr, o.X.get(), KS, o.n, mview, true, nrows.get(), s);
-                launch_mfma_records(nrows.get(), o.n, KO, frag[c].get(), s);
-            } else {
-                launch_mfma_records(o.NX.get(), o.n, KS, frag[c].get(), s);
-            }
-        }
     float ms_pairs = 0, ms_sort = 0, ms_dedup = 0, ms_coh = 0;
     hipEvent_t e[5];
     for (auto &x : e) IG_HIP(hipEventCreate(&x));
@@ -803,20 +851,9 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         if (use_mfma) {
             IG_HIP(hipEventRecord(e[3], s));
             for (int c = 0; c < 2; ++c) {
-                if (!hc[c]) continue;
-                Scratch<uint32_t> keep(hc[c], s), kpos(hc[c], s), ktot(1, s);
-                Scratch<uint64_t> B((size_t)hc[c] * KO, s);
-                uint32_t *cc = cand.get() + (c == 0 ? 0 : hc[0]);
-                launch_operand_rows(cls[c].X.get(), cls[c].n, cc, nullptr, KS, hc[c], mview, false, B.get(), s);
-                IG_HIP(hipEventRecord(e[0], s));
-                launch_contain_mfma((int)KO, false, B.get(), hc[c], frag[c].get(), cls[1 - c].n, keep.get(), s);
-                IG_HIP(hipEventRecord(e[1], s));
-                scan_exclusive_u32(keep.get(), kpos.get(), hc[c], ktot.get(), s);
-                launch_compact(keep.get(), kpos.get(), cc, hc[c], surv[c].get() + mfma_surv[c], s);
-                mfma_surv[c] += host_read_u32(ktot.get(), 1, s)[0];
-                float tk;
-                IG_HIP(hipEventElapsedTime(&tk, e[0], e[1]));
-                m.stats.kernel_ms[0] += tk;
+                const uint32_t *cc = cand.get() + (c == 0 ? 0 : hc[0]);
+                mfma_surv[c] += mfma_coherence(mf, cls, c, KS, cc, hc[c], surv[c].get() + mfma_surv[c],
+                                               &m.stats.kernel_ms[0], s);
                 mfma_tests[c] += (uint64_t)hc[c] * cls[1 - c].n;
             }
             IG_HIP(hipEventRecord(e[4], s));
@@ -904,7 +941,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     for (int c = 0; c < 2; ++c) {
         // frag[1 - c] holds class c's own records (it is class 1-c's coherence operand)
         order_and_weigh(m, c, cls[c], surv[c].get(), hn[c], chunked, tu, s, &tm, c == 0 ? 5 : 8,
-                        use_mfma ? frag[1 - c].get() : nullptr, mview);
+                        use_mfma ? mf.frag[1 - c].get() : nullptr, mf.view);
         m.stats.coherent[c] = m.np[c];
         m.stats.support_tests[c] = m.np[c] * (uint64_t)cls[c].n;
         if (c == 0) tm.mark(3);   // end of class 0's support
@@ -1137,6 +1174,12 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
     Scratch<uint32_t> rws(radix_ws_size(cap), s), sws(scan_ws_size(cap), s);
     Scratch<unsigned char> rowsegs(nseg * rows_of_seg_size(), s);
     Scratch<CohSeg> cohsegs(nseg, s);
+    // per problem: matrix-core operands when its subset tests run there; their
+    // segments then give the captured VALU coherence no candidates (a zero count)
+    const uint32_t mode = opts ? opts->coherence_mfma : 0u;
+    std::vector<MfmaFit> mf(G.size());
+    for (uint32_t g = 0; g < G.size(); ++g) mfma_setup(*G[g]->m, G[g]->cls, mode, mf[g], s);
+    Scratch<uint32_t> zero(1, s);
     {
         std::vector<unsigned char> hr(nseg * rows_of_seg_size());
         std::vector<CohSeg> hc(nseg);
@@ -1151,7 +1194,7 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
                 h.NXo = G[g]->cls[1 - c].NX.get();
                 h.cand = cand.get();
                 h.cand_off = segoff.get() + sg;
-                h.ncand = segc.get() + sg;
+                h.ncand = mf[g].on ? zero.get() : segc.get() + sg;
                 h.out = surv.get() + off[sg];
                 h.nout = cnt.get() + sg;
                 h.tests = tests.get() + sg;
@@ -1167,6 +1210,7 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
     IG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
         launch_fill_u32(cnt.get(), 0u, nseg + 1, s);
+        launch_fill_u32(zero.get(), 0u, 1, s);
         launch_fill_u64(reinterpret_cast<uint64_t *>(tests.get()), 0ull, nseg, s);
         for (uint32_t g = 0; g < G.size(); ++g)
             for (int c = 0; c < 2; ++c) {
@@ -1203,9 +1247,23 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
     (void)hipEventDestroy(e1);
     std::vector<uint32_t> hdist = host_read_u32(segc.get(), nseg, s);
     std::vector<uint32_t> hsurv = host_read_u32(cnt.get(), nseg, s);
+    std::vector<uint32_t> hoff = host_read_u32(segoff.get(), nseg, s);
     std::vector<unsigned long long> htests(nseg);
     IG_HIP(hipMemcpyAsync(htests.data(), tests.get(), nseg * 8, hipMemcpyDeviceToHost, s));
     IG_HIP(hipStreamSynchronize(s));
+    // coherence on the matrix cores for the problems that use them (dense counts)
+    std::vector<float> mfma_ms(G.size(), 0.0f), mfma_kernel(G.size(), 0.0f);
+    for (uint32_t g = 0; g < G.size(); ++g) {
+        if (!mf[g].on) continue;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t sg = 2 * g + c;
+            hsurv[sg] = mfma_coherence(mf[g], G[g]->cls, c, KS, cand.get() + hoff[sg], hdist[sg],
+                                       surv.get() + off[sg], &mfma_kernel[g], s);
+            htests[sg] = (unsigned long long)hdist[sg] * G[g]->cls[1 - c].n;
+        }
+        mfma_ms[g] = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
     for (uint32_t g = 0; g < G.size(); ++g) {
         DevModel &m = *G[g]->m;
         const Tuning tp = tuning_for(opts, KS, G[g]->pairs());
@@ -1219,7 +1277,7 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
             m.stats.tests[c] = htests[sg];
             m.stats.chunks[c] = G[g]->M[c] ? 1 : 0;
             order_and_weigh(m, c, G[g]->cls[c], surv.get() + off[sg], hsurv[sg], false, tp, s, &tm,
-                            c == 0 ? 5 : 8);
+                            c == 0 ? 5 : 8, mf[g].on ? mf[g].frag[1 - c].get() : nullptr, mf[g].view);
             m.stats.coherent[c] = m.np[c];
             m.stats.support_tests[c] = m.np[c] * (uint64_t)G[g]->cls[c].n;
             if (c == 0) tm.mark(3);
@@ -1231,8 +1289,9 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
         record_times(m, tm);
         // the group's captured stages, split by this problem's share of the pairs
         const double share = group_pairs ? (double)G[g]->pairs() / (double)group_pairs : 0.0;
-        m.stats.ms[4] = (float)(graph_ms * share);
+        m.stats.ms[4] = (float)(graph_ms * share) + mfma_ms[g];
         m.stats.ms[1] = m.stats.ms[2] = m.stats.ms[3] = 0.0f;
+        m.stats.kernel_ms[0] = mfma_kernel[g];
     }
 }
 

@@ -95,3 +95,25 @@ def ig_storage_words(K: int) -> int:
         if K <= v:
             return v
     raise ValueError("K beyond 64")
+
+
+def main(argv=None) -> None:
+    """Tune the VALU-path widths of the batched-fit workload and write the table:
+    python -m paper_2507_14222_amd.tune --out paper_2507_14222_amd/tuning_gfx950.json"""
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--sizes", type=int, nargs="+", default=[1200, 5000])
+    ap.add_argument("--reps", type=int, default=2)
+    a = ap.parse_args(argv)
+    # widths beyond the matrix-core kernels' 8 one-hot words may fall to the VALU path
+    widths = [w for w in widths_of(synth.make_batch()) if w > 8]
+    table = autotune(widths, sizes=tuple(a.sizes), reps=a.reps)
+    save(table, a.out)
+    print(json.dumps({"widths": widths, "entries": table["entries"]}), flush=True)
+    sys.stdout.flush()
+
+
+if __name__ == "__main__":
+    main()

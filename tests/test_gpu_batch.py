@@ -45,15 +45,17 @@ def _same(a, b, tests=True):
 def test_batch_equals_plain_and_oracle():
     P = _problems()
     say("batch of", len(P))
-    B = ig.fit_batch(P)
-    for p, mb in zip(P, B):
-        _same(mb, ig.fit(p.codes, p.labels, p.nbins, kernels="valu"))   # same kernels, same counters
-        _same(mb, ig.fit(p.codes, p.labels, p.nbins), tests=False)
+    B = ig.fit_batch(P)                    # matrix cores where the operands fit 8 words
+    BV = ig.fit_batch(P, kernels="valu")   # early-exit VALU path everywhere
+    for p, mb, mv in zip(P, B, BV):
+        _same(mb, ig.fit(p.codes, p.labels, p.nbins))                   # same kernels, same counters
+        _same(mv, ig.fit(p.codes, p.labels, p.nbins, kernels="valu"))
+        _same(mb, mv, tests=False)
         om = oracle.fit(p.codes, p.labels, p.nbins)
         for c in (0, 1):
             w, f, S = mb.export(c)
             assert np.array_equal(w, om.patterns[c]) and np.array_equal(f, om.f[c]) and np.array_equal(S, om.S[c])
-        assert list(mb.stats().tests) == om.stats["tests"]
+        assert list(mv.stats().tests) == om.stats["tests"]
 
 
 def test_groups_split_by_memory_and_tuning_give_same_models():
