@@ -295,7 +295,7 @@ static std::vector<uint32_t> digit_radices(uint32_t nb) {
 }
 
 // Factored-token table of a fit from codes (see FactorView), used when it needs at
-// most 8 words and fewer words than the one-hot packing.  Digits never straddle a
+// most 16 words and fewer words than the one-hot packing.  Digits never straddle a
 // 64-bit word, so a feature's digits touch at most two words.
 static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, hipStream_t s) {
     std::vector<FacFeature> feat(d);
@@ -312,7 +312,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
             used += q;
             tokens += q;
         }
-        if (word >= 8) return;   // more than 8 words: not worth a factored form
+        if (word >= 16) return;   // more than 16 words: beyond the matrix-core kernels
         FacFeature ft{};
         ft.off = (uint16_t)off;
         ft.nb = (uint16_t)nb;
@@ -352,13 +352,15 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
             t = hi;
         }
     }
+    // one range per storage word (KS >= K): the kernels walk every word they hold,
+    // and the padding words K .. KS - 1 have no pieces
     std::vector<FacPiece> piece;
-    std::vector<uint32_t> pbeg(m.K + 1, 0);
-    for (uint32_t w = 0; w < m.K; ++w) {
+    std::vector<uint32_t> pbeg(m.KS + 1, 0);
+    for (uint32_t w = 0; w < m.KS; ++w) {
         pbeg[w] = (uint32_t)piece.size();
-        piece.insert(piece.end(), by_word[w].begin(), by_word[w].end());
+        if (w < m.K) piece.insert(piece.end(), by_word[w].begin(), by_word[w].end());
     }
-    pbeg[m.K] = (uint32_t)piece.size();
+    pbeg[m.KS] = (uint32_t)piece.size();
     std::vector<uint32_t> fbeg(KF + 1, d), fend(KF + 1, 0);
     for (uint32_t f = 0; f < d; ++f)
         for (uint32_t w = feat[f].w0; w < (uint32_t)feat[f].w0 + feat[f].nw; ++w) {
@@ -370,7 +372,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     // one device block: masks | features | pieces | fbeg | fend | pbeg (8-byte aligned parts)
     auto al8 = [](size_t b) { return (b + 7) / 8 * 8; };
     const size_t mb = mask.size() * 8, fb = al8(feat.size() * sizeof(FacFeature)),
-                 pb = al8(piece.size() * sizeof(FacPiece)), ib = al8((KF + 1) * 4), kb = al8((m.K + 1) * 4);
+                 pb = al8(piece.size() * sizeof(FacPiece)), ib = al8((KF + 1) * 4), kb = al8((m.KS + 1) * 4);
     std::vector<char> host(mb + fb + pb + 2 * ib + kb, 0);
     size_t at = 0;
     auto put = [&](const void *src, size_t bytes, size_t span) {
@@ -384,7 +386,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     const size_t o_piece = put(piece.data(), piece.size() * sizeof(FacPiece), pb);
     const size_t o_fbeg = put(fbeg.data(), (KF + 1) * 4, ib);
     const size_t o_fend = put(fend.data(), (KF + 1) * 4, ib);
-    const size_t o_pbeg = put(pbeg.data(), (m.K + 1) * 4, kb);
+    const size_t o_pbeg = put(pbeg.data(), (m.KS + 1) * 4, kb);
     char *dev = dev_alloc<char>(host.size());
     m.fac = dev;
     IG_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, s));
@@ -398,6 +400,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     m.fv.d = d;
     m.fv.KF = KF;
     m.fv.nmask = (uint32_t)mask.size();
+    m.fv.nwords = m.KS;
     m.fac_tokens = tokens;
 }
 
@@ -657,6 +660,8 @@ static std::vector<uint32_t> coherence_phases(uint32_t max_other) {
 // full comparison; at 2^24 distinct per class about 2^8 pairs of them do.
 constexpr int kPairKeyBytes = 5;
 
+constexpr uint32_t kMfmaWords = 16;   // widest operands of the subset-test contraction
+
 // Matrix-core operands of one fit: the token view (factored, or the one-hot words
 // in mode 3) and, per class c, the records of class 1 - c as A tiles (class c's
 // coherence operand, and class 1 - c's support operand).
@@ -668,7 +673,7 @@ struct MfmaFit {
 };
 
 // Decide the subset-test path of a fit from the coherence_mfma option (0 auto:
-// matrix cores when the operands fit 8 words; 1 matrix cores; 2 VALU; 3 matrix
+// matrix cores when the operands fit 16 words; 1 matrix cores; 2 VALU; 3 matrix
 // cores on the one-hot words) and build the record tiles when it is the matrix
 // cores.
 static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode, MfmaFit &mf, hipStream_t s) {
@@ -676,9 +681,9 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
     const uint32_t KS = m.KS;
     mf.view = mode == 3 ? FactorView{} : m.fv;
     mf.KO = mf.view.KF ? mf.view.KF : KS;
-    IG_REQUIRE((mode != 1 && mode != 3) || mf.KO <= 8, IG_E_UNSUPPORTED,
-               "the matrix-core subset tests handle up to 8 operand words");
-    mf.on = mode == 1 || mode == 3 || (mode == 0 && mf.KO <= 8);
+    IG_REQUIRE((mode != 1 && mode != 3) || mf.KO <= kMfmaWords, IG_E_UNSUPPORTED,
+               "the matrix-core subset tests handle up to 16 operand words");
+    mf.on = mode == 1 || mode == 3 || (mode == 0 && mf.KO <= kMfmaWords);
     if (!mf.on) return;
     for (int c = 0; c < 2; ++c) {
         const ClassRows &o = cls[1 - c];

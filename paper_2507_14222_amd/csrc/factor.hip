@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_operand_rows(const uint64_t *__restrict
     }
 }
 
-// Factoring for rows of at most 8 one-hot words: each lane loads its row once
+// Factoring for rows of at most 16 one-hot words: each lane loads its row once
 // into registers and walks the pieces of each word (a uniform table); the masks of
 // every (feature, bin) are staged in LDS when they fit.  Output words are chosen
 // with uniform branches, so every register index is static.
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
 #pragma unroll
         for (int k = 0; k < KS; ++k) w[k] = W[e * KS + k];
     }
-    uint64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t acc[16] = {};
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         for (uint32_t p = fv.pbeg[k]; p < fv.pbeg[k + 1]; ++p) {
@@ -96,18 +96,19 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
             const uint64_t *mk = masks + pc.mask + ((uint32_t)pc.base + (uint32_t)__builtin_ctzll(x)) * pc.nw;
             const uint64_t m0 = mk[0], m1 = pc.nw > 1 ? mk[1] : 0ull;
             switch (pc.w0) {   // uniform over the wave
-#define IG_OR(W0)                      \
-    case W0:                           \
-        acc[W0] |= m0;                 \
-        if (W0 + 1 < 8) acc[(W0 + 1) & 7] |= m1; \
+#define IG_OR(W0)                                 \
+    case W0:                                      \
+        acc[W0] |= m0;                            \
+        if (W0 + 1 < 16) acc[(W0 + 1) & 15] |= m1; \
         break;
                 IG_OR(0) IG_OR(1) IG_OR(2) IG_OR(3) IG_OR(4) IG_OR(5) IG_OR(6) IG_OR(7)
+                IG_OR(8) IG_OR(9) IG_OR(10) IG_OR(11) IG_OR(12) IG_OR(13) IG_OR(14) IG_OR(15)
 #undef IG_OR
             }
         }
     }
 #pragma unroll
-    for (int o = 0; o < 8; ++o)
+    for (int o = 0; o < 16; ++o)
         if ((uint32_t)o < KO) out[e * KO + o] = acc[o] ^ flip;
 }
 
@@ -115,15 +116,19 @@ void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, con
                          const FactorView &fv, bool complement, uint64_t *out, hipStream_t s) {
     if (!m) return;
     const uint32_t KO = fv.KF ? fv.KF : KS;
+    // the register kernel walks the pieces of every one of the KS words
+    IG_REQUIRE(!fv.KF || fv.nwords == KS, IG_E_DEVICE, "factoring table built for another storage width");
     const dim3 grid((unsigned)((m + 255) / 256));
     const uint64_t flip = complement ? ~0ull : 0ull;
-    if (fv.KF && KS <= 8) {
+    if (fv.KF && KS <= 16 && KO <= 16) {
 #define IG_OR_K(V)                                                                                                 \
     case V:                                                                                                        \
         hipLaunchKernelGGL((k_operand_rows_reg<V>), grid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, flip, out); \
         break;
-        switch (KS) {
+        switch (KS) {   // the compiled storage widths up to 16 words
             IG_OR_K(1) IG_OR_K(2) IG_OR_K(3) IG_OR_K(4) IG_OR_K(5) IG_OR_K(6) IG_OR_K(7) IG_OR_K(8)
+            IG_OR_K(10) IG_OR_K(12) IG_OR_K(14) IG_OR_K(16)
+            default: throw Error(IG_E_UNSUPPORTED, "storage width without a factoring kernel");
         }
 #undef IG_OR_K
     } else {

@@ -97,9 +97,10 @@ struct FactorView {
     const uint32_t *fbeg = nullptr;     // [KF + 1]: features touching word w are
     const uint32_t *fend = nullptr;     //   [fbeg[w], fend[w]) (features in token order)
     const FacPiece *piece = nullptr;    // pieces grouped by one-hot word
-    const uint32_t *pbeg = nullptr;     // [K + 1]: pieces of one-hot word k are [pbeg[k], pbeg[k + 1])
+    const uint32_t *pbeg = nullptr;     // [nwords + 1]: pieces of one-hot word k are [pbeg[k], pbeg[k + 1])
     uint32_t d = 0, KF = 0;             // KF = 0: no factoring (operands are the one-hot words)
     uint32_t nmask = 0;                 // entries of mask
+    uint32_t nwords = 0;                // one-hot storage words pbeg covers (the fit's KS)
 };
 // Operand rows out[m][KO], KO = fv.KF when factoring, else KS: row e is the
 // pattern X[i] AND X[j] of pair id ids[e] (ids non-null, rows X [n][KS]) or the

@@ -309,8 +309,13 @@ __global__ void k_mfma_records(const uint64_t *__restrict__ NX, uint32_t n, uint
 // One workgroup: 8 waves x 2 column sets x 32 candidates = 512 candidates; each
 // wave keeps its candidates' B operands in registers for the whole scan.
 constexpr int MF_NT = 512;                  // threads per matrix-core workgroup
-constexpr int MF_FB = 2;                    // 32-column sets per wave
-constexpr int MF_COLS = MF_NT / 64 * MF_FB * 32;
+constexpr int MF_FB = 2;                    // 32-column sets per wave (scoring)
+// 32-column sets per wave of the subset-test contraction: two up to 8 operand
+// words, one beyond (the B operands of a set take 4 VGPRs per word)
+template <int KS>
+constexpr int mf_sets() { return KS <= 8 ? 2 : 1; }
+template <int KS>
+constexpr int mf_cols() { return MF_NT / 64 * mf_sets<KS>() * 32; }
 // two workgroups per CU (4 waves per SIMD: at most 128 VGPRs each, 2 x 64 KB of LDS),
 // so that one workgroup's waves multiply while the other's wait at a barrier
 constexpr int MF_WAVES_PER_SIMD = 4;
@@ -334,13 +339,14 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
                                                                          const uint4 *__restrict__ frag,
                                                                          uint32_t ntiles, uint32_t *__restrict__ out) {
     constexpr int G = mf_group<KS>();
+    constexpr int FB = mf_sets<KS>();
     __shared__ uint4 lds[ring_lds<KS * 64, G, MF_NB>()];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
-    v8i_t b[MF_FB][KS];
-    uint32_t e[MF_FB], hits[MF_FB];
+    v8i_t b[FB][KS];
+    uint32_t e[FB], hits[FB];
 #pragma unroll
-    for (int f = 0; f < MF_FB; ++f) {
-        e[f] = blockIdx.x * MF_COLS + wave * (MF_FB * 32) + f * 32 + col;
+    for (int f = 0; f < FB; ++f) {
+        e[f] = blockIdx.x * mf_cols<KS>() + wave * (FB * 32) + f * 32 + col;
         const bool act = e[f] < m;
         const uint32_t *row = reinterpret_cast<const uint32_t *>(B + (size_t)(act ? e[f] : 0) * KS);
         hits[f] = 0;
@@ -355,19 +361,19 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
     }
     if (ntiles)
         stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, 0, ntiles, lds, [&](const uint4 *tf) __attribute__((always_inline)) {
-            v16f_t acc[MF_FB];
+            v16f_t acc[FB];
 #pragma unroll
-            for (int f = 0; f < MF_FB; ++f) acc[f] = v16f_t{0};
+            for (int f = 0; f < FB; ++f) acc[f] = v16f_t{0};
 #pragma unroll
             for (int w = 0; w < KS; ++w) {
                 const uint4 a4 = tf[w * 64 + lane];
                 const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
 #pragma unroll
-                for (int f = 0; f < MF_FB; ++f)
+                for (int f = 0; f < FB; ++f)
                     acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
             }
 #pragma unroll
-            for (int f = 0; f < MF_FB; ++f) {
+            for (int f = 0; f < FB; ++f) {
                 if (COUNT) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r) hits[f] += acc[f][r] == 0.0f;
@@ -380,7 +386,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
             }
         });
 #pragma unroll
-    for (int f = 0; f < MF_FB; ++f) {
+    for (int f = 0; f < FB; ++f) {
         // the two halves of the wave hold different record rows of the same column
         const uint32_t h = hits[f] + __shfl_xor(hits[f], 32, 64);
         if (half == 0 && e[f] < m) out[e[f]] = COUNT ? h : (h ? 0u : 1u);
@@ -391,18 +397,20 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
                          uint32_t *out, hipStream_t s) {
     if (!m) return;
     IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 rows in one matrix-core launch");
-    const dim3 grid((unsigned)((m + MF_COLS - 1) / MF_COLS));
     const uint32_t ntiles = (n_rec + 31) / 32;
-#define IG_CM(V)                                                                                               \
-    case V:                                                                                                    \
-        if (count)                                                                                             \
+#define IG_CM(V)                                                                                                 \
+    case V: {                                                                                                    \
+        const dim3 grid((unsigned)((m + mf_cols<V>() - 1) / mf_cols<V>()));                                      \
+        if (count)                                                                                               \
             hipLaunchKernelGGL((k_contain_mfma<V, true>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, out); \
-        else                                                                                                   \
+        else                                                                                                     \
             hipLaunchKernelGGL((k_contain_mfma<V, false>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, out); \
-        break;
+        break;                                                                                                   \
+    }
     switch (KO) {
         IG_CM(1) IG_CM(2) IG_CM(3) IG_CM(4) IG_CM(5) IG_CM(6) IG_CM(7) IG_CM(8)
-        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 8 operand words");
+        IG_CM(9) IG_CM(10) IG_CM(11) IG_CM(12) IG_CM(13) IG_CM(14) IG_CM(15) IG_CM(16)
+        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
     }
 #undef IG_CM
     IG_HIP(hipGetLastError());
