@@ -486,6 +486,14 @@ struct ClassRows {
     uint32_t n = 0;
 };
 
+// Operand rows of a model's patterns (in the model's own token view), kept from the
+// support step so that the scoring operands need not build them again.
+struct PatternRows {
+    Scratch<uint64_t> rows[2];
+    bool valid[2] = {false, false};
+};
+
+
 // Canonical order (ascending w_0 .. w_{K-1}, unsigned, w_0 most significant) of
 // `count` patterns: the pair ids `ids` into the class rows X [n][KS], or, with ids
 // null, the rows X [count][KS] themselves.  Writes the sorting permutation to perm
@@ -548,7 +556,7 @@ static void canonical_permutation(const DevModel &m, const uint64_t *X, uint32_t
 static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *ids, size_t count,
                             bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
                             int support_mark = -1, const uint4 *own_frag = nullptr,
-                            const FactorView &mfma_view = FactorView{}) {
+                            const FactorView &mfma_view = FactorView{}, PatternRows *keep = nullptr) {
     const uint32_t KS = m.KS;
     if (count == 0) {
         m.np[c] = 0;
@@ -611,6 +619,11 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         (void)hipEventDestroy(ke[1]);
         IG_HIP(er);
         m.stats.kernel_ms[1] += tk;
+        // the scoring operands use the model's own view: keep the rows when it is this one
+        if (keep && mfma_view.KF == m.fv.KF && mfma_view.KF) {
+            keep->rows[c] = std::move(B);
+            keep->valid[c] = true;
+        }
     } else
         launch_support((int)KS, tu.support_cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
 }
@@ -618,21 +631,28 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
 // Matrix-core scoring operands of a finished model: when its rows fit the
 // 8-word kernels and every weight is below 2^28 (sixteen of them sum without
 // wrapping in 32 bits).  Otherwise scoring stays on the VALU kernel.
-static void build_score_operands(DevModel &m, hipStream_t s) {
+static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr) {
     const uint32_t KO = m.KO();
     if (KO > 8 || m.maxS[0] >= (1ll << 28) || m.maxS[1] >= (1ll << 28)) return;
     for (int c = 0; c < 2; ++c) {
         const uint64_t ntiles = (m.np[c] + 31) / 32;
         m.frag[c] = dev_alloc<uint4>(std::max<uint64_t>(ntiles, 1) * (KO + 1) * 64);
-        Scratch<uint64_t> rows(std::max<uint64_t>(m.np[c], 1) * KO, s);
-        launch_operand_rows(nullptr, 0, nullptr, m.W[c], m.KS, m.np[c], m.fv, false, rows.get(), s);
-        launch_mfma_patterns(rows.get(), m.S[c], (uint32_t)m.np[c], KO, m.frag[c], s);
+        Scratch<uint64_t> own;
+        const uint64_t *rows;
+        if (pr && pr->valid[c]) {
+            rows = pr->rows[c].get();
+        } else {
+            own.reset(std::max<uint64_t>(m.np[c], 1) * KO, s);
+            launch_operand_rows(nullptr, 0, nullptr, m.W[c], m.KS, m.np[c], m.fv, false, own.get(), s);
+            rows = own.get();
+        }
+        launch_mfma_patterns(rows, m.S[c], (uint32_t)m.np[c], KO, m.frag[c], s);
     }
     m.score_factored = m.fv.KF > 0;
     IG_HIP(hipStreamSynchronize(s));
 }
 
-static void finish_weights(DevModel &m, hipStream_t s) {
+static void finish_weights(DevModel &m, hipStream_t s, PatternRows *pr = nullptr) {
     Scratch<unsigned long long> ms(4, s);
     for (int c = 0; c < 2; ++c) launch_reduce_maxsum(m.S[c], m.np[c], ms.get() + 2 * c, s);
     unsigned long long h[4];
@@ -644,7 +664,7 @@ static void finish_weights(DevModel &m, hipStream_t s) {
         IG_REQUIRE(h[2 * c + 1] <= (unsigned long long)INT64_MAX, IG_E_OVERFLOW,
                    "sum of pattern weights exceeds int64");
     }
-    build_score_operands(m, s);
+    build_score_operands(m, s, pr);
 }
 
 // Ends of the coherence phases over the other class's records.  One phase (the
@@ -943,16 +963,17 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         m.stats.tests[c] = ht[c];
     }
     const bool chunked = chunks.size() > 1;
+    PatternRows prow;
     for (int c = 0; c < 2; ++c) {
         // frag[1 - c] holds class c's own records (it is class 1-c's coherence operand)
         order_and_weigh(m, c, cls[c], surv[c].get(), hn[c], chunked, tu, s, &tm, c == 0 ? 5 : 8,
-                        use_mfma ? mf.frag[1 - c].get() : nullptr, mf.view);
+                        use_mfma ? mf.frag[1 - c].get() : nullptr, mf.view, &prow);
         m.stats.coherent[c] = m.np[c];
         m.stats.support_tests[c] = m.np[c] * (uint64_t)cls[c].n;
         if (c == 0) tm.mark(3);   // end of class 0's support
     }
     tm.mark(6);
-    finish_weights(m, s);
+    finish_weights(m, s, &prow);
     tm.mark(7);
     IG_HIP(hipStreamSynchronize(s));
     m.stats.ms[1] = ms_pairs;
@@ -1274,6 +1295,7 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
         const Tuning tp = tuning_for(opts, KS, G[g]->pairs());
         Timer tm(s);
         tm.mark(4);
+        PatternRows prow;
         for (int c = 0; c < 2; ++c) {
             const uint32_t sg = 2 * g + c;
             m.stats.n_class[c] = G[g]->cls[c].n;
@@ -1282,13 +1304,13 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
             m.stats.tests[c] = htests[sg];
             m.stats.chunks[c] = G[g]->M[c] ? 1 : 0;
             order_and_weigh(m, c, G[g]->cls[c], surv.get() + off[sg], hsurv[sg], false, tp, s, &tm,
-                            c == 0 ? 5 : 8, mf[g].on ? mf[g].frag[1 - c].get() : nullptr, mf[g].view);
+                            c == 0 ? 5 : 8, mf[g].on ? mf[g].frag[1 - c].get() : nullptr, mf[g].view, &prow);
             m.stats.coherent[c] = m.np[c];
             m.stats.support_tests[c] = m.np[c] * (uint64_t)G[g]->cls[c].n;
             if (c == 0) tm.mark(3);
         }
         tm.mark(6);
-        finish_weights(m, s);
+        finish_weights(m, s, &prow);
         tm.mark(7);
         IG_HIP(hipStreamSynchronize(s));
         record_times(m, tm);
