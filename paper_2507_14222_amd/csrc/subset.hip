@@ -320,10 +320,10 @@ constexpr int mf_cols() { return MF_NT / 64 * mf_sets<KS>() * 32; }
 // so that one workgroup's waves multiply while the other's wait at a barrier
 constexpr int MF_WAVES_PER_SIMD = 4;
 #ifndef IG_MF_GTOK
-#define IG_MF_GTOK 24
+#define IG_MF_GTOK 32
 #endif
 #ifndef IG_MF_NB
-#define IG_MF_NB 3
+#define IG_MF_NB 2
 #endif
 constexpr int MF_NB = IG_MF_NB;   // LDS ring depth
 template <int KS>
