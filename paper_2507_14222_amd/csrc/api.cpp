@@ -168,7 +168,9 @@ struct DevModel {
     void *fac = nullptr;                   // factored-token table (features | digits | word starts)
     FactorView fv;                         // fv.KF = 0: matrix-core operands stay one-hot
     uint32_t fac_tokens = 0;               // tokens of the factored form
+    uint32_t fac_tokens_last = 0;          // of them, in its last word
     bool score_factored = false;           // frag holds factored operand rows
+    bool score_spare = false;              // frag carries the +1 at the spare last token
     ig_stats stats{};
 
     uint32_t KO() const { return fv.KF ? fv.KF : KS; }
@@ -401,6 +403,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     m.fv.KF = KF;
     m.fv.nmask = (uint32_t)mask.size();
     m.fv.nwords = m.KS;
+    m.fac_tokens_last = used;
     m.fac_tokens = tokens;
 }
 
@@ -556,7 +559,8 @@ static void canonical_permutation(const DevModel &m, const uint64_t *X, uint32_t
 static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *ids, size_t count,
                             bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
                             int support_mark = -1, const uint4 *own_frag = nullptr,
-                            const FactorView &mfma_view = FactorView{}, PatternRows *keep = nullptr) {
+                            const FactorView &mfma_view = FactorView{}, PatternRows *keep = nullptr,
+                            Scratch<uint64_t> *pre_rows = nullptr) {
     const uint32_t KS = m.KS;
     if (count == 0) {
         m.np[c] = 0;
@@ -603,8 +607,13 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
     if (own_frag) {
         // f on the matrix cores against the class's own records, then S = f |b|^2
         const uint32_t KO = mfma_view.KF ? mfma_view.KF : KS;
-        Scratch<uint64_t> B(final_count * KO, s);
-        launch_operand_rows(nullptr, 0, nullptr, m.W[c], KS, final_count, mfma_view, false, B.get(), s);
+        Scratch<uint64_t> B;
+        if (pre_rows && !may_repeat) {
+            B = std::move(*pre_rows);   // the coherence step's rows of these patterns, same order
+        } else {
+            B.reset(final_count * KO, s);
+            launch_operand_rows(nullptr, 0, nullptr, m.W[c], KS, final_count, mfma_view, false, B.get(), s);
+        }
         hipEvent_t ke[2];
         IG_HIP(hipEventCreate(&ke[0]));
         IG_HIP(hipEventCreate(&ke[1]));
@@ -631,6 +640,13 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
 // Matrix-core scoring operands of a finished model: when its rows fit the
 // 8-word kernels and every weight is below 2^28 (sixteen of them sum without
 // wrapping in 32 bits).  Otherwise scoring stays on the VALU kernel.
+// Whether the last token of the scoring operands' last word is used by no pattern
+// (factored tokens, or one-hot tokens, fewer than 64 per word on the last word).
+static bool score_spare(const DevModel &m) {
+    const uint32_t used = m.fv.KF ? m.fac_tokens_last : (m.L % 64 ? m.L % 64 : (m.KS > m.K ? 0u : 64u));
+    return used < 64;
+}
+
 static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr) {
     const uint32_t KO = m.KO();
     if (KO > 8 || m.maxS[0] >= (1ll << 28) || m.maxS[1] >= (1ll << 28)) return;
@@ -646,9 +662,10 @@ static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr) {
             launch_operand_rows(nullptr, 0, nullptr, m.W[c], m.KS, m.np[c], m.fv, false, own.get(), s);
             rows = own.get();
         }
-        launch_mfma_patterns(rows, m.S[c], (uint32_t)m.np[c], KO, m.frag[c], s);
+        launch_mfma_patterns(rows, m.S[c], (uint32_t)m.np[c], KO, score_spare(m), m.frag[c], s);
     }
     m.score_factored = m.fv.KF > 0;
+    m.score_spare = score_spare(m);
     IG_HIP(hipStreamSynchronize(s));
 }
 
@@ -722,7 +739,8 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
 // (Eq. 3, dense): appends the coherent ids to `out` and returns how many
 // (synchronises the stream); adds the contraction's device time to *kernel_ms.
 static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c, uint32_t KS, const uint32_t *cand,
-                               uint32_t ncand, uint32_t *out, float *kernel_ms, hipStream_t s) {
+                               uint32_t ncand, uint32_t *out, float *kernel_ms, hipStream_t s,
+                               uint64_t *rows_out = nullptr) {
     if (!ncand) return 0;
     Scratch<uint32_t> keep(ncand, s), kpos(ncand, s), ktot(1, s);
     Scratch<uint64_t> B((size_t)ncand * mf.KO, s);
@@ -742,6 +760,8 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
     IG_HIP(hipEventRecord(ke[1], s));
     scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
     launch_compact(keep.get(), kpos.get(), cand, ncand, out, s);
+    // the coherent candidates' operand rows, in the same order (support and scoring use them)
+    if (rows_out) launch_compact_rows(B.get(), keep.get(), kpos.get(), ncand, mf.KO, rows_out, s);
     const uint32_t kept = host_read_u32(ktot.get(), 1, s)[0];
     float tk = 0;
     IG_HIP(hipEventElapsedTime(&tk, ke[0], ke[1]));
@@ -816,6 +836,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     MfmaFit mf;
     mfma_setup(m, cls, opts ? opts->coherence_mfma : 0u, mf, s);
     const bool use_mfma = mf.on;
+    Scratch<uint64_t> surv_rows[2];   // operand rows of the coherent candidates (one-chunk fits)
     uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
     float ms_pairs = 0, ms_sort = 0, ms_dedup = 0, ms_coh = 0;
     hipEvent_t e[5];
@@ -877,8 +898,14 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
             IG_HIP(hipEventRecord(e[3], s));
             for (int c = 0; c < 2; ++c) {
                 const uint32_t *cc = cand.get() + (c == 0 ? 0 : hc[0]);
+                // one chunk: keep the survivors' operand rows for support and scoring
+                uint64_t *ro = nullptr;
+                if (chunks.size() == 1) {
+                    surv_rows[c].reset(std::max<size_t>(hc[c], 1) * mf.KO, s);
+                    ro = surv_rows[c].get();
+                }
                 mfma_surv[c] += mfma_coherence(mf, cls, c, KS, cc, hc[c], surv[c].get() + mfma_surv[c],
-                                               &m.stats.kernel_ms[0], s);
+                                               &m.stats.kernel_ms[0], s, ro);
                 mfma_tests[c] += (uint64_t)hc[c] * cls[1 - c].n;
             }
             IG_HIP(hipEventRecord(e[4], s));
@@ -967,7 +994,8 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     for (int c = 0; c < 2; ++c) {
         // frag[1 - c] holds class c's own records (it is class 1-c's coherence operand)
         order_and_weigh(m, c, cls[c], surv[c].get(), hn[c], chunked, tu, s, &tm, c == 0 ? 5 : 8,
-                        use_mfma ? mf.frag[1 - c].get() : nullptr, mf.view, &prow);
+                        use_mfma ? mf.frag[1 - c].get() : nullptr, mf.view, &prow,
+                        surv_rows[c].get() ? &surv_rows[c] : nullptr);
         m.stats.coherent[c] = m.np[c];
         m.stats.support_tests[c] = m.np[c] * (uint64_t)cls[c].n;
         if (c == 0) tm.mark(3);   // end of class 0's support
@@ -1534,6 +1562,7 @@ static ig::ScoreModel score_model(const ig::DevModel &M) {
     sm.KS = M.KS;
     sm.KO = M.score_factored ? M.fv.KF : M.KS;
     if (M.score_factored) sm.fv = M.fv;
+    sm.spare = M.score_spare;
     return sm;
 }
 

@@ -156,13 +156,18 @@ struct ScoreModel {
     const uint4 *frag[2];       // matrix-core operands of the patterns and weights (or null)
     uint32_t KO;                // operand words of frag (factored or one-hot)
     FactorView fv;              // the factoring of frag (fv.KF = 0: one-hot)
+    bool spare;                 // frag holds +1.0 at the unused last token (see k_mfma_patterns)
 };
 // Scoring on the matrix cores (KO <= 8, every weight < 2^28): each 32-pattern tile
 // of frag holds the patterns' operand rows (KO * 64 uint4, tokens as -1.0) and the
 // int8 operand of their 7-bit weight chunks (64 uint4): ceil(m/32) * (KO + 1) * 64
 // uint4 from launch_mfma_patterns.  Flows given as codes are factored like the
 // patterns; flows given as words need one-hot operands (fv.KF = 0).
-void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, uint4 *frag, hipStream_t s);
+// spare: the last token of the last word is used by no row; it then carries the
+// +1 that starts each containment count (flows hold 1 there), so the accumulators
+// can start at 0.
+void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, bool spare, uint4 *frag,
+                          hipStream_t s);
 void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K,
                        uint32_t n_flows, uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out,
                        hipStream_t s);

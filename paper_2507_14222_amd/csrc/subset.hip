@@ -434,14 +434,17 @@ __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return 
 //    byte j holds 7-bit chunk c of the weight of the row in accumulator j of half h
 //    (0 past m); other lanes zero.
 __global__ void k_mfma_patterns(const uint64_t *__restrict__ W, const int64_t *__restrict__ S, uint32_t m,
-                                uint32_t KS, uint32_t ntiles, uint4 *__restrict__ frag) {
+                                uint32_t KS, uint32_t ntiles, bool spare, uint4 *__restrict__ frag) {
     const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (size_t)ntiles * (KS + 1) * 64) return;
     const uint32_t lane = (uint32_t)(g % 64), w = (uint32_t)((g / 64) % (KS + 1)), tile = (uint32_t)(g / (64 * (KS + 1)));
     if (w < KS) {
         const uint32_t row = tile * 32 + lane % 32;
         const uint32_t d = row < m ? (uint32_t)(W[(size_t)row * KS + w] >> (32 * (lane / 32))) : 0u;
-        frag[g] = make_uint4(spread8(d) * 5u, spread8(d >> 8) * 5u, spread8(d >> 16) * 5u, spread8(d >> 24) * 5u);
+        uint4 v = make_uint4(spread8(d) * 5u, spread8(d >> 8) * 5u, spread8(d >> 16) * 5u, spread8(d >> 24) * 5u);
+        // +1.0 (0x2) at the spare token: bit 63 of the last word = top nibble of the upper half
+        if (spare && w == KS - 1 && lane >= 32) v.w = (v.w & 0x0fffffffu) | 0x20000000u;
+        frag[g] = v;
         return;
     }
     const uint32_t c = lane % 32, half = lane / 32;
@@ -494,7 +497,7 @@ struct ScoreMfmaArgs {
 // Workgroup (range, flow block): the fblocks workgroups that read the same range
 // of pattern tiles get ids that differ by multiples of 8, so they are dispatched
 // to one XCD and share its L2.
-template <int KS>
+template <int KS, bool SPARE>
 __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     constexpr int G = sc_group<KS>();
     constexpr int TW = (KS + 1) * 64;
@@ -550,8 +553,10 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
         }
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-            // NOT t; an inactive or invalid flow is the empty set, which contains no pattern
-            const uint64_t nt = ok ? ~wd[k] : ~0ull;
+            // NOT t; an inactive or invalid flow is the empty set, which contains no pattern.
+            // The spare token is 1 in every flow (it carries the count's starting +1).
+            uint64_t nt = ok ? ~wd[k] : ~0ull;
+            if (SPARE && k == KS - 1) nt |= 1ull << 63;
             const uint32_t dwd = (uint32_t)(nt >> (32 * half));
             b[f][k] = v8i_t{(int)spread8(dwd), (int)spread8(dwd >> 8), (int)spread8(dwd >> 16),
                             (int)spread8(dwd >> 24), 0, 0, 0, 0};
@@ -563,11 +568,12 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
 #pragma unroll
     for (int f = 0; f < MF_FB; ++f) C[f] = v16i_t{0};
     stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], t0, t1, lds, [&](const uint4 *tile) __attribute__((always_inline)) {
+        // the count starts at +1: from the spare token, or here
         v16f_t acc[MF_FB];
 #pragma unroll
         for (int f = 0; f < MF_FB; ++f)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[f][r] = 1.0f;
+            for (int r = 0; r < 16; ++r) acc[f][r] = SPARE ? 0.0f : 1.0f;
 #pragma unroll
         for (int w = 0; w < KS; ++w) {
             const uint4 a4 = tile[w * 64 + lane];
@@ -606,12 +612,13 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     }
 }
 
-void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, uint4 *frag, hipStream_t s) {
+void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, bool spare, uint4 *frag,
+                          hipStream_t s) {
     const uint32_t ntiles = (m + 31) / 32;
     const size_t total = (size_t)ntiles * (KS + 1) * 64;
     if (!total) return;
     hipLaunchKernelGGL(k_mfma_patterns, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, W, S, m, KS, ntiles,
-                       frag);
+                       spare, frag);
     IG_HIP(hipGetLastError());
 }
 
@@ -1030,7 +1037,10 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     const dim3 grid((unsigned)(nr * a.fblocks));
 #define IG_SCM(V)                                                                    \
     case V:                                                                          \
-        hipLaunchKernelGGL((k_score_mfma<V>), grid, dim3(SC_NT), 0, s, a);          \
+        if (m.spare)                                                                 \
+            hipLaunchKernelGGL((k_score_mfma<V, true>), grid, dim3(SC_NT), 0, s, a); \
+        else                                                                         \
+            hipLaunchKernelGGL((k_score_mfma<V, false>), grid, dim3(SC_NT), 0, s, a); \
         break;
     switch ((int)m.KO) {
         IG_SCM(1) IG_SCM(2) IG_SCM(3) IG_SCM(4) IG_SCM(5) IG_SCM(6) IG_SCM(7) IG_SCM(8)
