@@ -312,8 +312,11 @@ constexpr int MF_NT = 512;                  // threads per matrix-core workgroup
 constexpr int MF_FB = 2;                    // 32-column sets per wave (scoring)
 // 32-column sets per wave of the subset-test contraction: two up to 8 operand
 // words, one beyond (the B operands of a set take 4 VGPRs per word)
+#ifndef IG_MF_SETS_NARROW
+#define IG_MF_SETS_NARROW 2
+#endif
 template <int KS>
-constexpr int mf_sets() { return KS <= 8 ? 2 : 1; }
+constexpr int mf_sets() { return KS <= 5 ? IG_MF_SETS_NARROW : KS <= 8 ? 2 : 1; }
 template <int KS>
 constexpr int mf_cols() { return MF_NT / 64 * mf_sets<KS>() * 32; }
 // two workgroups per CU (4 waves per SIMD: at most 128 VGPRs each, 2 x 64 KB of LDS),
