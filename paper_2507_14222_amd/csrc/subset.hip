@@ -14,6 +14,8 @@
 //                the same class; counts the rows containing each pattern.
 //   k_score      Eq. 4: lanes = flows (packed from their codes in registers and
 //                complemented), uniform = patterns with their weights.
+#include <atomic>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -485,8 +487,7 @@ constexpr int sc_group() { return IG_SCORE_GTOK / (KS + 1) > 0 ? IG_SCORE_GTOK /
 struct ScoreMfmaArgs {
     const uint4 *frag[2];
     uint32_t ntiles[2];
-    uint32_t chunk;             // pattern tiles per workgroup
-    uint32_t groups[2];         // tile ranges of each class
+    uint32_t ranges;            // ranges over the tiles of class 0 then class 1 (a multiple of 8)
     uint32_t fblocks;           // workgroups over the flows
     const uint16_t *codes;      // [n][d] or null
     const uint64_t *words;      // [n][K] or null
@@ -499,7 +500,9 @@ struct ScoreMfmaArgs {
 
 // Workgroup (range, flow block): the fblocks workgroups that read the same range
 // of pattern tiles get ids that differ by multiples of 8, so they are dispatched
-// to one XCD and share its L2.
+// to one XCD and share its L2.  The ranges split the tiles of both classes, taken
+// one after the other, into equal parts; a range that holds tiles of both classes
+// scans them as two segments and adds each class's sums to its own column.
 template <int KS, bool SPARE>
 __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     constexpr int G = sc_group<KS>();
@@ -507,11 +510,10 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     __shared__ uint4 lds[ring_lds<TW, G, SC_NB>()];
     const uint32_t id = blockIdx.x, xcd = id % 8, seq = id / 8;
     const uint32_t range = (seq / a.fblocks) * 8 + xcd, fb = seq % a.fblocks;
-    if (range >= a.groups[0] + a.groups[1]) return;   // uniform over the workgroup
-    const int cls = range < a.groups[0] ? 0 : 1;
-    const uint32_t t0 = (cls ? range - a.groups[0] : range) * a.chunk;
-    const uint32_t t1 = t0 + a.chunk < a.ntiles[cls] ? t0 + a.chunk : a.ntiles[cls];
-    if (t0 >= t1) return;
+    if (range >= a.ranges) return;   // uniform over the workgroup
+    const uint64_t T = (uint64_t)a.ntiles[0] + a.ntiles[1];
+    const uint32_t u0 = (uint32_t)(T * range / a.ranges), u1 = (uint32_t)(T * (range + 1) / a.ranges);
+    if (u0 >= u1) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     v8i_t b[MF_FB][KS];
     uint32_t tf[MF_FB];
@@ -568,50 +570,58 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     // C[f]: running weighting products; row c < 4 of column `col` (lane half 0,
     // accumulators 0..3) sums chunk c of the weights of the patterns inside the flow
     v16i_t C[MF_FB];
+#pragma nounroll
+    for (int cls = 0; cls < 2; ++cls) {
+        const uint32_t lo = cls ? a.ntiles[0] : 0u, hi = lo + a.ntiles[cls];
+        const uint32_t s0 = u0 > lo ? u0 : lo, s1 = u1 < hi ? u1 : hi;
+        if (s0 >= s1) continue;
+        // the class-0 segment's last group may still be read from the ring
+        if (cls == 1 && u0 < lo) __syncthreads();
 #pragma unroll
-    for (int f = 0; f < MF_FB; ++f) C[f] = v16i_t{0};
-    stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], t0, t1, lds, [&](const uint4 *tile) __attribute__((always_inline)) {
-        // the count starts at +1: from the spare token, or here
-        v16f_t acc[MF_FB];
-#pragma unroll
-        for (int f = 0; f < MF_FB; ++f)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[f][r] = SPARE ? 0.0f : 1.0f;
-#pragma unroll
-        for (int w = 0; w < KS; ++w) {
-            const uint4 a4 = tile[w * 64 + lane];
-            const v8i_t av = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+        for (int f = 0; f < MF_FB; ++f) C[f] = v16i_t{0};
+        stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], s0 - lo, s1 - lo, lds, [&](const uint4 *tile) __attribute__((always_inline)) {
+            // the count starts at +1: from the spare token, or here
+            v16f_t acc[MF_FB];
 #pragma unroll
             for (int f = 0; f < MF_FB; ++f)
-                acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
-        }
-        // weight chunks of this tile as the A operand (rows c < 4; other rows zero)
-        const uint4 q = tile[KS * 64 + lane];
-        const v4i_t wa = {(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[f][r] = SPARE ? 0.0f : 1.0f;
+#pragma unroll
+            for (int w = 0; w < KS; ++w) {
+                const uint4 a4 = tile[w * 64 + lane];
+                const v8i_t av = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+#pragma unroll
+                for (int f = 0; f < MF_FB; ++f)
+                    acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
+            }
+            // weight chunks of this tile as the A operand (rows c < 4; other rows zero)
+            const uint4 q = tile[KS * 64 + lane];
+            const v4i_t wa = {(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+#pragma unroll
+            for (int f = 0; f < MF_FB; ++f) {
+                // inside = max(acc, 0) as a byte (1 or 0), accumulator r -> byte r
+                v4i_t z;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q], 0, 0u);
+                    d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 1], 1, d);
+                    d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 2], 2, d);
+                    d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 3], 3, d);
+                    z[q] = (int)d;
+                }
+                C[f] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wa, z, C[f], 0, 0, 0);
+            }
+        });
+        const int colsel = cls == 1 ? 0 : 1;   // A from class 1, N from class 0
 #pragma unroll
         for (int f = 0; f < MF_FB; ++f) {
-            // inside = max(acc, 0) as a byte (1 or 0), accumulator r -> byte r
-            v4i_t z;
+            uint64_t v = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint32_t d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q], 0, 0u);
-                d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 1], 1, d);
-                d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 2], 2, d);
-                d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 3], 3, d);
-                z[q] = (int)d;
-            }
-            C[f] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wa, z, C[f], 0, 0, 0);
+            for (int c = 0; c < 4; ++c) v += (uint64_t)(uint32_t)C[f][c] << (7 * c);
+            if (half == 0 && tf[f] < a.n_flows && v)
+                atomicAdd(reinterpret_cast<unsigned long long *>(a.out + 2 * (size_t)tf[f] + colsel),
+                          (unsigned long long)v);
         }
-    });
-    const int colsel = cls == 1 ? 0 : 1;   // A from class 1, N from class 0
-#pragma unroll
-    for (int f = 0; f < MF_FB; ++f) {
-        uint64_t v = 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v += (uint64_t)(uint32_t)C[f][c] << (7 * c);
-        if (half == 0 && tf[f] < a.n_flows && v)
-            atomicAdd(reinterpret_cast<unsigned long long *>(a.out + 2 * (size_t)tf[f] + colsel),
-                      (unsigned long long)v);
     }
 }
 
@@ -829,19 +839,33 @@ int storage_words(int K) {
     return -1;
 }
 
-uint32_t coherence_grid(uint32_t grid_per_cu) {
+// Compute units of the current device (256 when it cannot be read)
+static uint32_t device_cus() {
     static int cached[64] = {0};
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
-        if (!cached[dev]) {
-            int v = 0;
-            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-                cached[dev] = v;
-            else
-                cached[dev] = 256;
-        }
-        cus = cached[dev];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cached[dev] = v;
+        else
+            cached[dev] = 256;
     }
+    return (uint32_t)cached[dev];
+}
+
+// Workgroups of `kernel` (threads each, static LDS only) that one XCD runs at once:
+// its eighth of the compute units times the workgroups per compute unit.
+static uint32_t xcd_slots(const void *kernel, int threads) {
+    int per_cu = 0;
+    IG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+    const uint32_t cus = device_cus();
+    const uint32_t s = (cus >= 8 ? cus / 8 : 1) * (uint32_t)(per_cu > 0 ? per_cu : 1);
+    return s ? s : 1;
+}
+
+uint32_t coherence_grid(uint32_t grid_per_cu) {
+    const uint32_t cus = device_cus();
     if (grid_per_cu < 1) grid_per_cu = 1;
     if (grid_per_cu > 32) grid_per_cu = 32;
     return (uint32_t)cus * grid_per_cu;   // persistent workgroups of 4 waves
@@ -1025,32 +1049,57 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     a.fv = m.fv;
     IG_REQUIRE(!m.fv.KF || codes, IG_E_UNSUPPORTED, "factored matrix-core operands score flows given as codes");
     a.fblocks = (n_flows + SC_COLS - 1) / SC_COLS;
-    const uint32_t tiles = a.ntiles[0] + a.ntiles[1];
+    const uint64_t tiles = (uint64_t)a.ntiles[0] + a.ntiles[1];
     if (!tiles) return;
-    // about 2048 workgroups in all: several per CU, short tail
-    uint32_t ranges = (2048 + a.fblocks - 1) / a.fblocks;
-    if (ranges > tiles) ranges = tiles;
-    a.chunk = (tiles + ranges - 1) / ranges;
-    // the int32 weighting sums stay exact: at most 32 rows x 127 per tile
-    if (a.chunk > (1u << 18)) a.chunk = 1u << 18;
-    a.groups[0] = (a.ntiles[0] + a.chunk - 1) / a.chunk;
-    a.groups[1] = (a.ntiles[1] + a.chunk - 1) / a.chunk;
-    const uint64_t nr = ((uint64_t)a.groups[0] + a.groups[1] + 7) / 8 * 8;
-    IG_REQUIRE(nr * a.fblocks < (1ull << 31), IG_E_UNSUPPORTED, "too many flows for one scoring launch");
-    const dim3 grid((unsigned)(nr * a.fblocks));
-#define IG_SCM(V)                                                                    \
-    case V:                                                                          \
-        if (m.spare)                                                                 \
-            hipLaunchKernelGGL((k_score_mfma<V, true>), grid, dim3(SC_NT), 0, s, a); \
-        else                                                                         \
-            hipLaunchKernelGGL((k_score_mfma<V, false>), grid, dim3(SC_NT), 0, s, a); \
-        break;
-    switch ((int)m.KO) {
-        IG_SCM(1) IG_SCM(2) IG_SCM(3) IG_SCM(4) IG_SCM(5) IG_SCM(6) IG_SCM(7) IG_SCM(8)
-        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core scoring path handles up to 8 words");
+    IG_REQUIRE(m.KO >= 1 && m.KO <= 8, IG_E_UNSUPPORTED, "the matrix-core scoring path handles up to 8 words");
+    const void *kernels[8][2] = {
+#define IG_SCK(V) {(const void *)k_score_mfma<V, false>, (const void *)k_score_mfma<V, true>},
+        IG_SCK(1) IG_SCK(2) IG_SCK(3) IG_SCK(4) IG_SCK(5) IG_SCK(6) IG_SCK(7) IG_SCK(8)
+#undef IG_SCK
+    };
+    const void *kern = kernels[m.KO - 1][m.spare ? 1 : 0];
+    // Equal ranges, 8 r of them (r per XCD): the r * fblocks workgroups of an XCD
+    // run in ceil(r * fblocks / slots) rounds of (tiles / 8 r) tiles each, plus a
+    // set-up per workgroup (the flows' operands and the ring's first loads, taken
+    // as kSetupTiles tiles).  r is chosen to minimise that time: workgroup counts
+    // that fill the last round, without making ranges shorter than needed.
+    constexpr double kSetupTiles = 32.0;
+    static std::atomic<uint32_t> slot_cache[8][2] = {};
+    uint32_t slots = slot_cache[m.KO - 1][m.spare ? 1 : 0].load(std::memory_order_relaxed);
+    if (!slots) {
+        slots = xcd_slots(kern, SC_NT);
+        slot_cache[m.KO - 1][m.spare ? 1 : 0].store(slots, std::memory_order_relaxed);
     }
-#undef IG_SCM
-    IG_HIP(hipGetLastError());
+    // the last choice is kept: serving launches repeat the same shapes
+    thread_local uint64_t memo_key[3] = {0, 0, 0}, memo_r = 0;
+    // the int32 weighting sums stay exact: at most 2^18 tiles x 32 rows x 127 per range
+    const uint64_t rmin = (tiles + 8 * (1ull << 18) - 1) / (8 * (1ull << 18));
+    uint64_t rmax = (tiles + 7) / 8;
+    if (rmax > 4096) rmax = 4096;
+    if (rmax < rmin) rmax = rmin;
+    uint64_t best_r = rmin;
+    if (memo_r && memo_key[0] == tiles && memo_key[1] == a.fblocks && memo_key[2] == slots) {
+        best_r = memo_r;
+    } else {
+        double best = -1.0;
+        for (uint64_t r = rmin; r <= rmax; ++r) {
+            const uint64_t rounds = (r * a.fblocks + slots - 1) / slots;
+            const double t = (double)rounds * ((double)tiles / (8.0 * (double)r) + kSetupTiles);
+            if (best < 0.0 || t < best * (1.0 - 1e-9)) {
+                best = t;
+                best_r = r;
+            }
+        }
+        memo_key[0] = tiles;
+        memo_key[1] = a.fblocks;
+        memo_key[2] = slots;
+        memo_r = best_r;
+    }
+    IG_REQUIRE(8 * best_r * a.fblocks < (1ull << 31), IG_E_UNSUPPORTED, "too many flows for one scoring launch");
+    a.ranges = (uint32_t)(8 * best_r);
+    const dim3 grid((unsigned)(a.ranges * a.fblocks));
+    void *args[] = {&a};
+    IG_HIP(hipLaunchKernel(kern, grid, dim3(SC_NT), args, 0, s));
 }
 
 }  // namespace ig
