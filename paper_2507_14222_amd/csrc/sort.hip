@@ -176,44 +176,83 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
+// One tile per workgroup, in two phases.  Ranking: wave w takes elements
+// [1024 w, 1024 w + 1024) of the tile, 64 at a time; lanes with equal digits find
+// each other with eight ballots, and a per-wave running count per digit (LDS, only
+// that wave touches its row) gives each element its stable rank among the wave's
+// elements of its digit.  The tile's elements are then placed in LDS in digit order
+// (wave-major inside a digit, so input order is kept) and written out from there:
+// consecutive threads store consecutive positions of a digit's output run, so the
+// stores coalesce instead of landing one element per bucket.
 __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                     size_t n, int shift, const uint32_t *__restrict__ offs,
                                                     uint32_t tiles) {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[4][256];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    run[threadIdx.x] = offs[(size_t)threadIdx.x * tiles + blockIdx.x];
-    size_t base = (size_t)blockIdx.x * RS_TILE;
+    __shared__ uint64_t skey[RS_TILE];
+    __shared__ uint32_t sval[RS_TILE];
+    __shared__ uint32_t wcnt[4][256];   // per-wave counts, then per-wave starts in the tile
+    __shared__ uint32_t gmap[256];      // output position of tile slot 0 of each digit
+    __shared__ uint32_t wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+    for (int i = t; i < 4 * 256; i += RS_T) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * RS_TILE;
+    const uint32_t nt = n - base < (size_t)RS_TILE ? (uint32_t)(n - base) : (uint32_t)RS_TILE;
+    uint64_t key[RS_I];
+    uint32_t val[RS_I], dr[RS_I];   // dr: digit | rank in the wave << 8
+#pragma unroll
     for (int it = 0; it < RS_I; ++it) {
-        for (int t = threadIdx.x; t < 4 * 256; t += RS_T) (&wcnt[0][0])[t] = 0;
-        __syncthreads();
-        size_t e = base + (size_t)it * RS_T + threadIdx.x;
-        bool valid = e < n;
-        uint64_t key = valid ? kin[e] : 0ull;
-        uint32_t val = valid ? vin[e] : 0u;
-        uint32_t dg = (uint32_t)(key >> shift) & 255u;
+        const uint32_t li = (uint32_t)wave * (RS_I * 64) + it * 64 + lane;
+        const bool valid = li < nt;
+        key[it] = valid ? kin[base + li] : 0ull;
+        val[it] = valid ? vin[base + li] : 0u;
+        const uint32_t dg = (uint32_t)(key[it] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            bool bit = (dg >> b) & 1u;
-            uint64_t m = __ballot(bit);
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
-        if (valid && rank == 0) wcnt[wave][dg] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[dg] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][dg];
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-        const int t = threadIdx.x;
-        run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
-        // the next iteration's clearing is ordered after this update by its barrier
-        __syncthreads();
+        const uint32_t before = wcnt[wave][dg];
+        const uint32_t rank = before + (uint32_t)__popcll(peers & lanemask_lt());
+        // the wave reads its counts before the lowest lane of each digit moves them on
+        if (valid && (peers & lanemask_lt()) == 0) wcnt[wave][dg] = before + (uint32_t)__popcll(peers);
+        dr[it] = valid ? (dg | rank << 8) : 0xffffffffu;
+    }
+    __syncthreads();
+    // digit t: counts of the four waves, their prefix, and the digit's start in the tile
+    const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t start = incl - tot;
+    for (int w = 0; w < wave; ++w) start += wsum[w];
+    wcnt[0][t] = start;
+    wcnt[1][t] = start + c0;
+    wcnt[2][t] = start + c0 + c1;
+    wcnt[3][t] = start + c0 + c1 + c2;
+    gmap[t] = offs[(size_t)t * tiles + blockIdx.x] - start;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < RS_I; ++it) {
+        if (dr[it] == 0xffffffffu) continue;
+        const uint32_t slot = wcnt[wave][dr[it] & 255u] + (dr[it] >> 8);
+        skey[slot] = key[it];
+        sval[slot] = val[it];
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < nt; i += RS_T) {
+        const uint64_t k = skey[i];
+        const uint32_t pos = gmap[(uint32_t)(k >> shift) & 255u] + i;
+        kout[pos] = k;
+        vout[pos] = sval[i];
     }
 }
 
