@@ -1,5 +1,8 @@
 // Operand rows for the matrix-core subset tests: the one-hot words themselves, or
 // their factored form (mixed-radix digits, one-hot per digit; see FactorView).
+#include <algorithm>
+#include <cstddef>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -56,60 +59,61 @@ __global__ __launch_bounds__(256) void k_operand_rows(const uint64_t *__restrict
     }
 }
 
-// Factoring for rows of at most 16 one-hot words: each lane loads its row once
-// into registers and walks the pieces of each word (a uniform table); the masks of
-// every (feature, bin) are staged in LDS when they fit.  Output words are chosen
-// with uniform branches, so every register index is static.
-constexpr uint32_t kLdsMasks = 4096;   // u64 masks staged in LDS (32 KB)
+// Factoring for rows of at most 16 one-hot words, masks in LDS: each lane loads
+// its row once into registers and walks the pieces of each word.  The piece table
+// is read one 16-byte piece at a time at wave-uniform addresses (scalar loads), every step is
+// branch-free (a piece with no bit set ORs zeros), and the output word is a
+// wave-uniform register index.  Workgroups stride over the rows, so each stages
+// the masks once.
+// At most 2 masks per one-hot token, and the kernel takes at most 16 x 64 tokens.
+constexpr uint32_t kLdsMasks = 2048;   // u64 masks staged in LDS (16 KB)
+static_assert(sizeof(FacPiece) == 16 && offsetof(FacPiece, base) == 4 && offsetof(FacPiece, mask) == 8,
+              "the kernel reads a piece as four dwords");
 
 template <int KS>
 __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__restrict__ X, uint32_t n,
                                                          const uint32_t *__restrict__ ids,
                                                          const uint64_t *__restrict__ W, size_t m, FactorView fv,
                                                          uint32_t KO, uint64_t flip, uint64_t *__restrict__ out) {
-    __shared__ uint64_t smask[kLdsMasks];
-    const bool in_lds = fv.nmask <= kLdsMasks;
-    if (in_lds)
-        for (uint32_t t = threadIdx.x; t < fv.nmask; t += blockDim.x) smask[t] = fv.mask[t];
+    __shared__ uint64_t smask[kLdsMasks + 1];   // + 1: the second word read next to the last entry
+    for (uint32_t t = threadIdx.x; t <= fv.nmask; t += blockDim.x) smask[t] = t < fv.nmask ? fv.mask[t] : 0ull;
     __syncthreads();
-    const uint64_t *masks = in_lds ? smask : fv.mask;
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    uint64_t w[KS];
-    if (ids) {
-        uint32_t i, j;
-        decode_pair(ids[e], n, i, j);
+    const uint4 *pw = reinterpret_cast<const uint4 *>(fv.piece);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+        uint64_t w[KS];
+        if (ids) {
+            uint32_t i, j;
+            decode_pair(ids[e], n, i, j);
 #pragma unroll
-        for (int k = 0; k < KS; ++k) w[k] = X[(size_t)i * KS + k] & X[(size_t)j * KS + k];
-    } else {
+            for (int k = 0; k < KS; ++k) w[k] = X[(size_t)i * KS + k] & X[(size_t)j * KS + k];
+        } else {
 #pragma unroll
-        for (int k = 0; k < KS; ++k) w[k] = W[e * KS + k];
-    }
-    uint64_t acc[16] = {};
+            for (int k = 0; k < KS; ++k) w[k] = W[e * KS + k];
+        }
+        uint64_t acc[16] = {};
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-        for (uint32_t p = fv.pbeg[k]; p < fv.pbeg[k + 1]; ++p) {
-            const FacPiece pc = fv.piece[p];
-            uint64_t x = w[k] >> pc.lo;
-            if (pc.width < 64) x &= (1ull << pc.width) - 1;
-            if (!x) continue;
-            const uint64_t *mk = masks + pc.mask + ((uint32_t)pc.base + (uint32_t)__builtin_ctzll(x)) * pc.nw;
-            const uint64_t m0 = mk[0], m1 = pc.nw > 1 ? mk[1] : 0ull;
-            switch (pc.w0) {   // uniform over the wave
-#define IG_OR(W0)                                 \
-    case W0:                                      \
-        acc[W0] |= m0;                            \
-        if (W0 + 1 < 16) acc[(W0 + 1) & 15] |= m1; \
-        break;
-                IG_OR(0) IG_OR(1) IG_OR(2) IG_OR(3) IG_OR(4) IG_OR(5) IG_OR(6) IG_OR(7)
-                IG_OR(8) IG_OR(9) IG_OR(10) IG_OR(11) IG_OR(12) IG_OR(13) IG_OR(14) IG_OR(15)
-#undef IG_OR
+        for (int k = 0; k < KS; ++k) {
+            const uint32_t p1 = fv.pbeg[k + 1];
+            for (uint32_t p = fv.pbeg[k]; p < p1; ++p) {
+                const uint4 pc = pw[p];
+                const uint32_t shape = pc.x, base = pc.y & 0xffffu, mk = pc.z;
+                const uint32_t lo = shape & 255u, width = (shape >> 8) & 255u, w0 = (shape >> 16) & 15u;
+                const uint32_t nw = shape >> 24;
+                const uint64_t keep = width < 64 ? (1ull << width) - 1 : ~0ull;
+                const uint64_t x = (w[k] >> lo) & keep;
+                // bin base + (lowest set bit), or bin base when the row holds none
+                // of the piece's tokens (its masks are then dropped)
+                const uint32_t idx = mk + (base + (x ? (uint32_t)__builtin_ctzll(x) : 0u)) * nw;
+                const uint64_t m0 = x ? smask[idx] : 0ull;
+                const uint64_t m1 = x && nw > 1 ? smask[idx + 1] : 0ull;
+                acc[w0] |= m0;
+                acc[(w0 + 1) & 15] |= m1;
             }
         }
-    }
 #pragma unroll
-    for (int o = 0; o < 16; ++o)
-        if ((uint32_t)o < KO) out[e * KO + o] = acc[o] ^ flip;
+        for (int o = 0; o < 16; ++o)
+            if ((uint32_t)o < KO) out[e * KO + o] = acc[o] ^ flip;
+    }
 }
 
 void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, const uint64_t *W, uint32_t KS, size_t m,
@@ -120,10 +124,12 @@ void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, con
     IG_REQUIRE(!fv.KF || fv.nwords == KS, IG_E_DEVICE, "factoring table built for another storage width");
     const dim3 grid((unsigned)((m + 255) / 256));
     const uint64_t flip = complement ? ~0ull : 0ull;
-    if (fv.KF && KS <= 16 && KO <= 16) {
-#define IG_OR_K(V)                                                                                                 \
-    case V:                                                                                                        \
-        hipLaunchKernelGGL((k_operand_rows_reg<V>), grid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, flip, out); \
+    if (fv.KF && KS <= 16 && KO <= 16 && fv.nmask <= kLdsMasks) {
+        // strided over the rows: a few workgroups per CU, each staging the masks once
+        const dim3 sgrid((unsigned)std::min<size_t>((m + 255) / 256, (size_t)device_cus() * 8));
+#define IG_OR_K(V)                                                                                                  \
+    case V:                                                                                                         \
+        hipLaunchKernelGGL((k_operand_rows_reg<V>), sgrid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, flip, out); \
         break;
         switch (KS) {   // the compiled storage widths up to 16 words
             IG_OR_K(1) IG_OR_K(2) IG_OR_K(3) IG_OR_K(4) IG_OR_K(5) IG_OR_K(6) IG_OR_K(7) IG_OR_K(8)

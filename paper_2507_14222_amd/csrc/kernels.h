@@ -90,6 +90,7 @@ struct FacPiece {                // the part of a feature inside one one-hot wor
     uint8_t w0, nw;              // output words of the feature (FacFeature)
     uint16_t base, pad;          // bin of bit lo
     uint32_t mask;               // FacFeature::mask of the feature
+    uint32_t pad2;               // 16 bytes: one scalar load per piece
 };
 struct FactorView {
     const FacFeature *feat = nullptr;   // [d]
@@ -126,6 +127,8 @@ struct CohSeg {                 // one (problem, class) for one coherence phase
 void launch_coherence(int KS, int cpl, const CohSeg *segs_dev, uint32_t nseg, uint32_t r_begin, uint32_t r_end,
                       uint32_t *queue, uint32_t grid, hipStream_t s);
 // persistent grid of the coherence kernel: grid_per_cu workgroups per compute unit
+// Compute units of the current device (256 when it cannot be read)
+uint32_t device_cus();
 uint32_t coherence_grid(uint32_t grid_per_cu);
 // digest of the set of (row [first K words], f, S) over rows [m][KS], order-free
 void launch_digest(const uint64_t *W, const uint32_t *f, const int64_t *S, size_t m, uint32_t KS, uint32_t K,

@@ -839,8 +839,7 @@ int storage_words(int K) {
     return -1;
 }
 
-// Compute units of the current device (256 when it cannot be read)
-static uint32_t device_cus() {
+uint32_t device_cus() {
     static int cached[64] = {0};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
