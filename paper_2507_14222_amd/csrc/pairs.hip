@@ -189,6 +189,20 @@ __global__ void k_materialize(const uint64_t *__restrict__ X, uint32_t n, uint32
     if (newflag) newflag[e] = differs ? 1u : 0u;
 }
 
+// The same rows without the repeat flags, one thread per word: the KS threads of a
+// row read and write its words side by side, so loads and stores coalesce.  A
+// workgroup takes 256 / KS rows.
+__global__ __launch_bounds__(256) void k_materialize_words(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS,
+                                                          const uint32_t *__restrict__ ids, size_t m,
+                                                          uint64_t *__restrict__ W) {
+    const uint32_t per = 256u / KS, lr = threadIdx.x / KS, k = threadIdx.x - lr * KS;
+    const size_t e = (size_t)blockIdx.x * per + lr;
+    if (lr >= per || e >= m) return;
+    uint32_t i, j;
+    decode_pair(ids[e], n, i, j);
+    W[e * KS + k] = X[(size_t)i * KS + k] & X[(size_t)j * KS + k];
+}
+
 // out[pos[e]] = W[e] for flagged e (row copy)
 __global__ void k_compact_rows(const uint64_t *__restrict__ W, const uint32_t *__restrict__ flags,
                                const uint32_t *__restrict__ pos, size_t m, uint32_t KS, uint64_t *__restrict__ out) {
@@ -302,7 +316,13 @@ void launch_word_range(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, c
 void launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m, uint64_t *W,
                         uint32_t *newflag, hipStream_t s) {
     if (!m) return;
-    hipLaunchKernelGGL(k_materialize, blocks_for(m), dim3(256), 0, s, X, n, KS, ids, m, W, newflag);
+    if (!newflag && KS <= 256) {
+        const size_t per = 256 / KS;
+        hipLaunchKernelGGL(k_materialize_words, dim3((unsigned)((m + per - 1) / per)), dim3(256), 0, s, X, n, KS, ids,
+                           m, W);
+    } else {
+        hipLaunchKernelGGL(k_materialize, blocks_for(m), dim3(256), 0, s, X, n, KS, ids, m, W, newflag);
+    }
     IG_HIP(hipGetLastError());
 }
 

@@ -438,29 +438,42 @@ __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return 
 //    weighting product (v_mfma_i32_32x32x32_i8): for lane%32 = c < 4 and half h,
 //    byte j holds 7-bit chunk c of the weight of the row in accumulator j of half h
 //    (0 past m); other lanes zero.
-__global__ void k_mfma_patterns(const uint64_t *__restrict__ W, const int64_t *__restrict__ S, uint32_t m,
-                                uint32_t KS, uint32_t ntiles, bool spare, uint4 *__restrict__ frag) {
-    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (size_t)ntiles * (KS + 1) * 64) return;
-    const uint32_t lane = (uint32_t)(g % 64), w = (uint32_t)((g / 64) % (KS + 1)), tile = (uint32_t)(g / (64 * (KS + 1)));
-    if (w < KS) {
-        const uint32_t row = tile * 32 + lane % 32;
-        const uint32_t d = row < m ? (uint32_t)(W[(size_t)row * KS + w] >> (32 * (lane / 32))) : 0u;
+// One wave per 32-row tile (four per workgroup): lane l takes row l % 32 and half
+// l / 32 of every word, and each slice is one contiguous 1 KB store.  The weight
+// slice gathers the 16 rows of a lane's accumulators with lane shuffles.
+__global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restrict__ W, const int64_t *__restrict__ S,
+                                                      uint32_t m, uint32_t KS, uint32_t ntiles, bool spare,
+                                                      uint4 *__restrict__ frag) {
+    const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;   // uniform over the wave
+    const uint32_t lane = threadIdx.x & 63, half = lane >> 5, r = lane & 31;
+    const uint32_t row = tile * 32 + r;
+    const bool in = row < m;
+    uint4 *dst = frag + (size_t)tile * (KS + 1) * 64;
+    uint64_t wv[8];
+#pragma unroll
+    for (uint32_t w = 0; w < 8; ++w) wv[w] = in && w < KS ? W[(size_t)row * KS + w] : 0ull;
+#pragma unroll
+    for (uint32_t w = 0; w < 8; ++w) {
+        if (w >= KS) break;
+        const uint32_t d = (uint32_t)(wv[w] >> (32 * half));
         uint4 v = make_uint4(spread8(d) * 5u, spread8(d >> 8) * 5u, spread8(d >> 16) * 5u, spread8(d >> 24) * 5u);
         // +1.0 (0x2) at the spare token: bit 63 of the last word = top nibble of the upper half
-        if (spare && w == KS - 1 && lane >= 32) v.w = (v.w & 0x0fffffffu) | 0x20000000u;
-        frag[g] = v;
-        return;
+        if (spare && w == KS - 1 && half) v.w = (v.w & 0x0fffffffu) | 0x20000000u;
+        dst[w * 64 + lane] = v;
     }
-    const uint32_t c = lane % 32, half = lane / 32;
+    const int64_t sv = in ? S[row] : 0;
+    const uint32_t s_lo = (uint32_t)sv, s_hi = (uint32_t)((uint64_t)sv >> 32);
     uint32_t q[4] = {0, 0, 0, 0};
-    if (c < 4)
-        for (uint32_t j = 0; j < 16; ++j) {
-            const uint32_t row = tile * 32 + acc_row(half, j);
-            const uint32_t chunk = row < m ? (uint32_t)(S[row] >> (7 * c)) & 127u : 0u;
-            q[j / 4] |= chunk << (8 * (j % 4));
-        }
-    frag[g] = make_uint4(q[0], q[1], q[2], q[3]);
+#pragma unroll
+    for (uint32_t j = 0; j < 16; ++j) {
+        const int src = (int)acc_row(half, j);   // lane src (half 0) holds that row's weight
+        const uint64_t v = (uint64_t)(uint32_t)__shfl((int)s_lo, src, 64) |
+                           (uint64_t)(uint32_t)__shfl((int)s_hi, src, 64) << 32;
+        const uint32_t chunk = r < 4 ? (uint32_t)(v >> (7 * r)) & 127u : 0u;
+        q[j / 4] |= chunk << (8 * (j % 4));
+    }
+    dst[KS * 64 + lane] = make_uint4(q[0], q[1], q[2], q[3]);
 }
 
 // Scoring workgroups: SC_NT threads, at most SC_WPS waves per SIMD (the weighting
@@ -628,10 +641,9 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
 void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, bool spare, uint4 *frag,
                           hipStream_t s) {
     const uint32_t ntiles = (m + 31) / 32;
-    const size_t total = (size_t)ntiles * (KS + 1) * 64;
-    if (!total) return;
-    hipLaunchKernelGGL(k_mfma_patterns, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, W, S, m, KS, ntiles,
-                       spare, frag);
+    if (!ntiles) return;
+    IG_REQUIRE(KS >= 1 && KS <= 8, IG_E_UNSUPPORTED, "matrix-core scoring operands of more than 8 words");
+    hipLaunchKernelGGL(k_mfma_patterns, dim3((ntiles + 3) / 4), dim3(256), 0, s, W, S, m, KS, ntiles, spare, frag);
     IG_HIP(hipGetLastError());
 }
 
