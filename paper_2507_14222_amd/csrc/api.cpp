@@ -371,11 +371,36 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
         }
     for (uint32_t w = 0; w <= KF; ++w)
         if (fbeg[w] >= fend[w]) fbeg[w] = fend[w] = 0;
-    // one device block: masks | features | pieces | fbeg | fend | pbeg (8-byte aligned parts)
-    auto al8 = [](size_t b) { return (b + 7) / 8 * 8; };
-    const size_t mb = mask.size() * 8, fb = al8(feat.size() * sizeof(FacFeature)),
-                 pb = al8(piece.size() * sizeof(FacPiece)), ib = al8((KF + 1) * 4), kb = al8((m.KS + 1) * 4);
-    std::vector<char> host(mb + fb + pb + 2 * ib + kb, 0);
+    // digit ranges per output word (rows of record pairs): every bin's digit tokens
+    // of a feature, one entry per word it touches; a feature on two words gets the
+    // next bit of the spanning mask
+    std::vector<std::vector<uint32_t>> wq(KF);   // 4 dwords per entry
+    uint32_t nspan = 0;
+    for (uint32_t f = 0; f < d; ++f) {
+        const FacFeature &ft = feat[f];
+        if (!ft.nw) continue;
+        const uint32_t bit = ft.nw > 1 ? nspan++ : 0u;
+        for (uint32_t k = 0; k < ft.nw; ++k) {
+            uint64_t rg = 0;
+            for (uint32_t c = 0; c < ft.nb; ++c) rg |= mask[ft.mask + c * ft.nw + k];
+            wq[ft.w0 + k].insert(wq[ft.w0 + k].end(),
+                                 {bit, ft.nw > 1 ? 1u : 0u, (uint32_t)rg, (uint32_t)(rg >> 32)});
+        }
+    }
+    if (nspan > 32) return;   // cannot happen: a spanning feature per word boundary, KF <= 16
+    std::vector<uint32_t> wfe, wbeg(KF + 1, 0);
+    for (uint32_t w = 0; w < KF; ++w) {
+        wbeg[w] = (uint32_t)(wfe.size() / 4);
+        wfe.insert(wfe.end(), wq[w].begin(), wq[w].end());
+    }
+    wbeg[KF] = (uint32_t)(wfe.size() / 4);
+    // one device block: range entries | masks | features | pieces | fbeg | fend | pbeg | wbeg
+    // (16-byte aligned parts; the entries and pieces are read as 16-byte scalar loads)
+    auto al16 = [](size_t b) { return (b + 15) / 16 * 16; };
+    const size_t eb = al16(wfe.size() * 4), mb = al16(mask.size() * 8),
+                 fb = al16(feat.size() * sizeof(FacFeature)), pb = al16(piece.size() * sizeof(FacPiece)),
+                 ib = al16((KF + 1) * 4), kb = al16((m.KS + 1) * 4);
+    std::vector<char> host(eb + mb + fb + pb + 3 * ib + kb, 0);
     size_t at = 0;
     auto put = [&](const void *src, size_t bytes, size_t span) {
         std::memcpy(host.data() + at, src, bytes);
@@ -383,12 +408,14 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
         at += span;
         return here;
     };
-    const size_t o_mask = put(mask.data(), mb, mb);
+    const size_t o_wfe = put(wfe.data(), wfe.size() * 4, eb);
+    const size_t o_mask = put(mask.data(), mask.size() * 8, mb);
     const size_t o_feat = put(feat.data(), feat.size() * sizeof(FacFeature), fb);
     const size_t o_piece = put(piece.data(), piece.size() * sizeof(FacPiece), pb);
     const size_t o_fbeg = put(fbeg.data(), (KF + 1) * 4, ib);
     const size_t o_fend = put(fend.data(), (KF + 1) * 4, ib);
     const size_t o_pbeg = put(pbeg.data(), (m.KS + 1) * 4, kb);
+    const size_t o_wbeg = put(wbeg.data(), (KF + 1) * 4, ib);
     char *dev = dev_alloc<char>(host.size());
     m.fac = dev;
     IG_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, s));
@@ -399,6 +426,8 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     m.fv.fbeg = reinterpret_cast<const uint32_t *>(dev + o_fbeg);
     m.fv.fend = reinterpret_cast<const uint32_t *>(dev + o_fend);
     m.fv.pbeg = reinterpret_cast<const uint32_t *>(dev + o_pbeg);
+    m.fv.wfe = reinterpret_cast<const uint4 *>(dev + o_wfe);
+    m.fv.wbeg = reinterpret_cast<const uint32_t *>(dev + o_wbeg);
     m.fv.d = d;
     m.fv.KF = KF;
     m.fv.nmask = (uint32_t)mask.size();
@@ -707,6 +736,7 @@ struct MfmaFit {
     FactorView view;
     uint32_t KO = 0;
     Scratch<uint4> frag[2];
+    Scratch<uint64_t> fr[2];   // factored rows of each class's records (factored view only)
 };
 
 // Decide the subset-test path of a fit from the coherence_mfma option (0 auto:
@@ -729,6 +759,12 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
             Scratch<uint64_t> nrows(std::max<size_t>(o.n, 1) * mf.KO, s);
             launch_operand_rows(nullptr, 0, nullptr, o.X.get(), KS, o.n, mf.view, true, nrows.get(), s);
             launch_mfma_records(nrows.get(), o.n, mf.KO, mf.frag[c].get(), s);
+            // class c's own records, factored: the candidates' rows are built from them
+            if (mf.view.wfe && cls[c].n) {
+                mf.fr[c].reset((size_t)cls[c].n * mf.KO, s);
+                launch_operand_rows(nullptr, 0, nullptr, cls[c].X.get(), KS, cls[c].n, mf.view, false,
+                                    mf.fr[c].get(), s);
+            }
         } else {
             launch_mfma_records(o.NX.get(), o.n, KS, mf.frag[c].get(), s);
         }
@@ -744,7 +780,10 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
     if (!ncand) return 0;
     Scratch<uint32_t> keep(ncand, s), kpos(ncand, s), ktot(1, s);
     Scratch<uint64_t> B((size_t)ncand * mf.KO, s);
-    launch_operand_rows(cls[c].X.get(), cls[c].n, cand, nullptr, KS, ncand, mf.view, false, B.get(), s);
+    if (mf.fr[c].get())
+        launch_pair_rows_factored(mf.fr[c].get(), cls[c].n, cand, ncand, mf.view, B.get(), s);
+    else
+        launch_operand_rows(cls[c].X.get(), cls[c].n, cand, nullptr, KS, ncand, mf.view, false, B.get(), s);
     hipEvent_t ke[2];
     IG_HIP(hipEventCreate(&ke[0]));
     IG_HIP(hipEventCreate(&ke[1]));

@@ -116,6 +116,87 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
     }
 }
 
+// Rows of record pairs in factored form (see launch_pair_rows_factored).  Two
+// records hold the same bin of a feature exactly when their digit tokens of that
+// feature agree, so the pair's row keeps FR[i] AND FR[j] on the features where
+// (FR[i] XOR FR[j]) has no bit in the feature's digit range and clears the rest.
+// A feature whose digits span two words is tested on both (first pass, one bit
+// per such feature).  Each thread takes R rows at once, so one wave-uniform table
+// entry (a scalar load) serves R rows.
+template <int KO, int R>
+__global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__restrict__ FR, uint32_t n,
+                                                           const uint32_t *__restrict__ ids, size_t m,
+                                                           const uint4 *__restrict__ wfe,
+                                                           const uint32_t *__restrict__ wbeg,
+                                                           uint64_t *__restrict__ out) {
+    const size_t T = (size_t)gridDim.x * blockDim.x;
+    for (size_t e0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < m; e0 += T * R) {
+        uint64_t x[R][KO], keep[R][KO];
+        uint32_t D[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const size_t e = e0 + r * T;
+            uint32_t i = 0, j = 0;
+            if (e < m) decode_pair(ids[e], n, i, j);
+#pragma unroll
+            for (int o = 0; o < KO; ++o) {
+                const uint64_t a = FR[(size_t)i * KO + o], b = FR[(size_t)j * KO + o];
+                x[r][o] = a ^ b;
+                keep[r][o] = a & b;
+            }
+            D[r] = 0;
+        }
+#pragma unroll
+        for (int o = 0; o < KO; ++o)
+            for (uint32_t q = wbeg[o]; q < wbeg[o + 1]; ++q) {
+                const uint4 t = wfe[q];
+                if (!t.y) continue;
+                const uint64_t rg = (uint64_t)t.w << 32 | t.z;
+#pragma unroll
+                for (int r = 0; r < R; ++r) D[r] |= (x[r][o] & rg) ? 1u << t.x : 0u;
+            }
+#pragma unroll
+        for (int o = 0; o < KO; ++o)
+            for (uint32_t q = wbeg[o]; q < wbeg[o + 1]; ++q) {
+                const uint4 t = wfe[q];
+                const uint64_t rg = (uint64_t)t.w << 32 | t.z;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool differ = t.y ? ((D[r] >> t.x) & 1u) != 0 : (x[r][o] & rg) != 0;
+                    keep[r][o] &= differ ? ~rg : ~0ull;
+                }
+            }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const size_t e = e0 + r * T;
+            if (e < m)
+#pragma unroll
+                for (int o = 0; o < KO; ++o) out[e * KO + o] = keep[r][o];
+        }
+    }
+}
+
+void launch_pair_rows_factored(const uint64_t *FR, uint32_t n, const uint32_t *ids, size_t m, const FactorView &fv,
+                               uint64_t *out, hipStream_t s) {
+    if (!m) return;
+    IG_REQUIRE(fv.KF >= 1 && fv.KF <= 16 && fv.wfe && fv.wbeg && n > 0, IG_E_DEVICE,
+               "factored pair rows without a digit-range table");
+    const size_t cap = (size_t)device_cus() * 8;
+#define IG_PR(V, RR)                                                                                               \
+    case V: {                                                                                                      \
+        const dim3 grid((unsigned)std::min<size_t>((m + 256 * RR - 1) / (256 * RR), cap));                       \
+        hipLaunchKernelGGL((k_pair_rows_factored<V, RR>), grid, dim3(256), 0, s, FR, n, ids, m, fv.wfe, fv.wbeg, out); \
+        break;                                                                                                     \
+    }
+    switch (fv.KF) {
+        IG_PR(1, 4) IG_PR(2, 4) IG_PR(3, 4) IG_PR(4, 4) IG_PR(5, 4) IG_PR(6, 2) IG_PR(7, 2) IG_PR(8, 2)
+        IG_PR(9, 1) IG_PR(10, 1) IG_PR(11, 1) IG_PR(12, 1) IG_PR(13, 1) IG_PR(14, 1) IG_PR(15, 1) IG_PR(16, 1)
+        default: throw Error(IG_E_UNSUPPORTED, "factored pair rows of more than 16 words");
+    }
+#undef IG_PR
+    IG_HIP(hipGetLastError());
+}
+
 void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, const uint64_t *W, uint32_t KS, size_t m,
                          const FactorView &fv, bool complement, uint64_t *out, hipStream_t s) {
     if (!m) return;

@@ -99,6 +99,11 @@ struct FactorView {
     const uint32_t *fend = nullptr;     //   [fbeg[w], fend[w]) (features in token order)
     const FacPiece *piece = nullptr;    // pieces grouped by one-hot word
     const uint32_t *pbeg = nullptr;     // [nwords + 1]: pieces of one-hot word k are [pbeg[k], pbeg[k + 1])
+    // Digit ranges for rows of record pairs: entries of output word o are
+    // [wbeg[o], wbeg[o + 1]) of wfe, each {x: bit in the spanning mask, y: 1 when the
+    // feature's digits span two words, z | w << 32: its digit bits in word o}
+    const uint4 *wfe = nullptr;
+    const uint32_t *wbeg = nullptr;     // [KF + 1]
     uint32_t d = 0, KF = 0;             // KF = 0: no factoring (operands are the one-hot words)
     uint32_t nmask = 0;                 // entries of mask
     uint32_t nwords = 0;                // one-hot storage words pbeg covers (the fit's KS)
@@ -108,6 +113,11 @@ struct FactorView {
 // row W[e] [m][KS]; complement writes NOT of every word.
 void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, const uint64_t *W, uint32_t KS, size_t m,
                          const FactorView &fv, bool complement, uint64_t *out, hipStream_t s);
+// Factored operand rows of record pairs from the records' own factored rows FR
+// [n][fv.KF]: row e (pair id ids[e]) is FR[i] AND FR[j] with the digits of every
+// feature on which the two records differ cleared (a one-bin-per-feature fit).
+void launch_pair_rows_factored(const uint64_t *FR, uint32_t n, const uint32_t *ids, size_t m, const FactorView &fv,
+                               uint64_t *out, hipStream_t s);
 
 // subset.hip -- the subset-test kernels (Eq. 6 inside Eq. 3, Eq. 2 and Eq. 4)
 struct CohSeg {                 // one (problem, class) for one coherence phase
