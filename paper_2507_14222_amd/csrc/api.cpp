@@ -723,8 +723,11 @@ static std::vector<uint32_t> coherence_phases(uint32_t max_other) {
 
 // Bytes of the (class, hash) keys that the de-duplication sorts on: 1 class bit and
 // 39 hash bits.  Distinct intersections that share a key are told apart by the
-// full comparison; at 2^24 distinct per class about 2^8 pairs of them do.
+// full comparison; at 2^24 distinct per class about 2^8 pairs of them do.  Fewer
+// bits save a radix pass but cost more: the occurrences of two intersections that
+// share a key interleave, and each one scans back over the other's to find its own.
 constexpr int kPairKeyBytes = 5;
+constexpr int kSortHashBits = 8 * kPairKeyBytes - 1;
 
 constexpr uint32_t kMfmaWords = 16;   // widest operands of the subset-test contraction
 
@@ -1299,6 +1302,8 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
         IG_HIP(hipStreamSynchronize(s));   // nothing may be in flight on s when capture begins
     }
     const uint32_t grid = coherence_grid(tu.grid_per_cu);
+    // the segment bits and as many hash bits as a single fit's keys, whole bytes
+    const int batch_key_bytes = std::min(8, (segbits + kSortHashBits + 7) / 8);
     GraphGuard gg;
     IG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
@@ -1309,9 +1314,10 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
             for (int c = 0; c < 2; ++c) {
                 const uint32_t sg = 2 * g + c;
                 launch_pair_hash(G[g]->cls[c].X.get(), G[g]->cls[c].n, KS, G[g]->K, 0, G[g]->M[c], sg, segbits,
-                                 k0.get() + off[sg], v0.get() + off[sg], s);
+                                 k0.get() + off[sg], v0.get() + off[sg], s, batch_key_bytes);
             }
-        const int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items, 0xffu, s, rws.get());
+        const int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items,
+                                           0xffu & ~((1u << (8 - batch_key_bytes)) - 1), s, rws.get());
         uint64_t *ks = where ? k1.get() : k0.get();
         uint32_t *vs = where ? v1.get() : v0.get();
         launch_dedup_flags(ks, vs, items, rowsegs.get(), segbits, flags.get(), nullptr, s);

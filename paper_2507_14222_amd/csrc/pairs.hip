@@ -43,7 +43,9 @@ __global__ void k_pair_hash(const uint64_t *__restrict__ X, uint32_t n, uint32_t
         keys[e] = (seg_hi | (h >> segbits)) & keep;
         vals[e] = (uint32_t)q;
     } else {
-        keys[e] = ~0ull;
+        // the largest key the sort sees (masked like the others, so a run of equal
+        // keys that sentinels join is still one run; the run scan skips them)
+        keys[e] = keep;
         vals[e] = ~0u;
     }
 }

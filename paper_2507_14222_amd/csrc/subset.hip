@@ -364,8 +364,10 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
                             0, 0, 0, 0};
         }
     }
+    const uint32_t one = m != 0u;   // 1 (the kernel runs only with columns)
     if (ntiles)
         stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, 0, ntiles, lds, [&](const uint4 *tf) __attribute__((always_inline)) {
+            // an accumulator ends at the number of candidate tokens the record lacks
             v16f_t acc[FB];
 #pragma unroll
             for (int f = 0; f < FB; ++f) acc[f] = v16f_t{0};
@@ -379,14 +381,21 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
             }
 #pragma unroll
             for (int f = 0; f < FB; ++f) {
+                // exact non-negative integers: +0.0 (all bits zero) exactly when the
+                // record contains the candidate, so the bit patterns are compared as
+                // integers (no float compares, whose lane masks cost hazard waits)
                 if (COUNT) {
+                    // min(bits, one) with `one` not a literal: the compiler would turn
+                    // min(bits, 1) into a compare again
+                    uint32_t lacking = 0;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) hits[f] += acc[f][r] == 0.0f;
+                    for (int r = 0; r < 16; ++r) lacking += min(__float_as_uint(acc[f][r]), one);
+                    hits[f] += 16u - lacking;
                 } else {
-                    bool z = false;
+                    uint32_t lo = __float_as_uint(acc[f][0]);
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) z |= acc[f][r] == 0.0f;
-                    hits[f] |= z;
+                    for (int r = 1; r < 16; ++r) lo = min(lo, __float_as_uint(acc[f][r]));
+                    hits[f] |= (lo - 1u) >> 31;   // 1 when lo == 0
                 }
             }
         });
