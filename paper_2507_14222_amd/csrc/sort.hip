@@ -183,13 +183,14 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // elements of its digit.  The tile's elements are then placed in LDS in digit order
 // (wave-major inside a digit, so input order is kept) and written out from there:
 // consecutive threads store consecutive positions of a digit's output run, so the
-// stores coalesce instead of landing one element per bucket.
+// stores coalesce instead of landing one element per bucket.  Keys and values pass
+// through the same LDS buffer one after the other, which keeps a workgroup at
+// 37 KB of LDS (four per CU).
 __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                     size_t n, int shift, const uint32_t *__restrict__ offs,
                                                     uint32_t tiles) {
-    __shared__ uint64_t skey[RS_TILE];
-    __shared__ uint32_t sval[RS_TILE];
+    __shared__ uint64_t skey[RS_TILE];   // keys, then the values (as uint32)
     __shared__ uint32_t wcnt[4][256];   // per-wave counts, then per-wave starts in the tile
     __shared__ uint32_t gmap[256];      // output position of tile slot 0 of each digit
     __shared__ uint32_t wsum[4];
@@ -240,19 +241,35 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t *__restrict_
     wcnt[3][t] = start + c0 + c1 + c2;
     gmap[t] = offs[(size_t)t * tiles + blockIdx.x] - start;
     __syncthreads();
+    // keys through LDS, then the values through the same buffer
 #pragma unroll
     for (int it = 0; it < RS_I; ++it) {
         if (dr[it] == 0xffffffffu) continue;
-        const uint32_t slot = wcnt[wave][dr[it] & 255u] + (dr[it] >> 8);
-        skey[slot] = key[it];
-        sval[slot] = val[it];
+        skey[wcnt[wave][dr[it] & 255u] + (dr[it] >> 8)] = key[it];
     }
     __syncthreads();
-    for (uint32_t i = t; i < nt; i += RS_T) {
-        const uint64_t k = skey[i];
-        const uint32_t pos = gmap[(uint32_t)(k >> shift) & 255u] + i;
-        kout[pos] = k;
-        vout[pos] = sval[i];
+    uint32_t dst[RS_I];
+#pragma unroll
+    for (int j = 0; j < RS_I; ++j) {
+        const uint32_t i = t + j * RS_T;
+        if (i < nt) {
+            const uint64_t k = skey[i];
+            dst[j] = gmap[(uint32_t)(k >> shift) & 255u] + i;
+            kout[dst[j]] = k;
+        }
+    }
+    __syncthreads();
+    uint32_t *sv = reinterpret_cast<uint32_t *>(skey);
+#pragma unroll
+    for (int it = 0; it < RS_I; ++it) {
+        if (dr[it] == 0xffffffffu) continue;
+        sv[wcnt[wave][dr[it] & 255u] + (dr[it] >> 8)] = val[it];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_I; ++j) {
+        const uint32_t i = t + j * RS_T;
+        if (i < nt) vout[dst[j]] = sv[i];
     }
 }
 

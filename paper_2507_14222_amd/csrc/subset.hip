@@ -493,11 +493,13 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
 #ifndef IG_SCORE_WPS
 #define IG_SCORE_WPS 3
 #endif
+// ring: groups of IG_SCORE_GTOK / (KS + 1) tiles (4 at five operand words), two
+// buffers; three workgroups of 256 threads then fit a CU's LDS
 #ifndef IG_SCORE_GTOK
-#define IG_SCORE_GTOK 16
+#define IG_SCORE_GTOK 24
 #endif
 #ifndef IG_SCORE_NB
-#define IG_SCORE_NB 3
+#define IG_SCORE_NB 2
 #endif
 constexpr int SC_NB = IG_SCORE_NB;
 constexpr int SC_NT = IG_SCORE_NT;
