@@ -34,10 +34,17 @@ __global__ void k_pair_hash(const uint64_t *__restrict__ X, uint32_t n, uint32_t
     const uint64_t *xi = X + (size_t)i * KS, *xj = X + (size_t)j * KS;
     uint64_t h = 0x9e3779b97f4a7c15ull ^ K;
     uint64_t any = 0;
-    for (uint32_t k = 0; k < K; ++k) {
-        uint64_t b = xi[k] & xj[k];
-        any |= b;
-        h = mix64(h ^ b) + 0x632be59bd9b4e019ull;
+    for (uint32_t k0 = 0; k0 < K; k0 += 8) {
+        // eight words' loads in flight at once, then the hash chain in word order
+        uint64_t b[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) b[u] = k0 + u < K ? xi[k0 + u] & xj[k0 + u] : 0ull;
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u)
+            if (k0 + u < K) {
+                any |= b[u];
+                h = mix64(h ^ b[u]) + 0x632be59bd9b4e019ull;
+            }
     }
     if (any) {
         keys[e] = (seg_hi | (h >> segbits)) & keep;
@@ -61,8 +68,13 @@ __device__ __forceinline__ bool same_candidate(const RowsOfSeg &r, uint32_t qa, 
     decode_pair(qb, r.n, ib, jb);
     const uint64_t *a0 = r.X + (size_t)ia * r.KS, *a1 = r.X + (size_t)ja * r.KS;
     const uint64_t *b0 = r.X + (size_t)ib * r.KS, *b1 = r.X + (size_t)jb * r.KS;
-    for (uint32_t k = 0; k < r.K; ++k)
-        if ((a0[k] & a1[k]) != (b0[k] & b1[k])) return false;
+    for (uint32_t k0 = 0; k0 < r.K; k0 += 8) {
+        uint64_t diff = 0;   // eight words of the four rows loaded together
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u)
+            if (k0 + u < r.K) diff |= (a0[k0 + u] & a1[k0 + u]) ^ (b0[k0 + u] & b1[k0 + u]);
+        if (diff) return false;
+    }
     return true;
 }
 
