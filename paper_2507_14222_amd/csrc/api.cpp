@@ -165,7 +165,7 @@ struct DevModel {
     uint4 *frag[2] = {nullptr, nullptr};   // matrix-core scoring operands (KS <= 8)
     KeyPiece *pieces = nullptr;            // compressed sort keys (fits from codes), or null
     uint32_t npieces = 0, nkeys = 0;
-    void *fac = nullptr;                   // factored-token table (features | digits | word starts)
+    void *fac = nullptr;                   // factored-token table (one device block)
     FactorView fv;                         // fv.KF = 0: matrix-core operands stay one-hot
     uint32_t fac_tokens = 0;               // tokens of the factored form
     uint32_t fac_tokens_last = 0;          // of them, in its last word
@@ -275,61 +275,69 @@ static void set_key_pieces(DevModel &m, const uint16_t *h_nbins, uint32_t d, hip
     m.nkeys = nk;
 }
 
-// Radices of the digits of a feature with nb bins: the smallest sum of radices
-// (each >= 2) whose product is at least nb; a feature with one bin needs none (every
-// row of a fit holds it).
-static std::vector<uint32_t> digit_radices(uint32_t nb) {
-    static std::mutex mu;
-    static std::vector<uint32_t> cost{0, 0}, first{0, 0};   // per bin count: min sum, first radix
-    std::lock_guard<std::mutex> lock(mu);
-    for (uint32_t v = (uint32_t)cost.size(); v <= nb; ++v) {
-        uint32_t bc = v, bq = v;
-        for (uint32_t q = 2; q < v; ++q) {
-            const uint32_t c = q + cost[(v + q - 1) / q];
-            if (c < bc) { bc = c; bq = q; }
-        }
-        cost.push_back(bc);
-        first.push_back(bq);
-    }
-    std::vector<uint32_t> r;
-    for (uint32_t v = nb; v > 1; v = (v + first[v] - 1) / first[v]) r.push_back(first[v]);
-    return r;
+// Signed-bit tokens of a feature with nb bins (nb >= 2): m = ceil(log2 nb) tokens
+// for the bits of the bin index and p presence tokens, p = 1 when m <= 4 and 2 when
+// 5 <= m <= 10.  The record side carries the popcount of its bin index on them, in
+// parts that e2m1 holds exactly: the first min(popcount, 4), or 6 when the popcount
+// is 6 or more, the second what is left (at most 4).  Returns m + p with *bits = m;
+// 0 for one bin; ~0 beyond 1024 bins.
+static uint32_t feature_tokens(uint32_t nb, uint32_t *bits) {
+    uint32_t mb = 0;
+    while ((1u << mb) < nb) ++mb;
+    *bits = mb;
+    if (mb == 0) return 0;
+    if (mb > 10) return ~0u;
+    return mb + (mb <= 4 ? 1u : 2u);
 }
 
 // Factored-token table of a fit from codes (see FactorView), used when it needs at
-// most 16 words and fewer words than the one-hot packing.  Digits never straddle a
-// 64-bit word, so a feature's digits touch at most two words.
+// most 16 words and fewer words than the one-hot packing.  A pattern (or candidate)
+// sets, for each feature it holds, the bits of the bin index and the presence
+// tokens; the other side (a record, or a flow in scoring) holds every feature and
+// carries +1 on a bit token whose bit is 0, -1 where it is 1, and the popcount of
+// its bin index on the presence tokens.  Their product summed over a feature's
+// tokens is the number of bits in which the two bin indices differ (0 when the
+// pattern lacks the feature), so the contraction is zero exactly when the pattern
+// lies inside (Eq. 6).  Tokens are laid out feature after feature; a feature may
+// cross a word boundary, so its tokens touch at most two words.
 static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, hipStream_t s) {
     std::vector<FacFeature> feat(d);
     std::vector<uint64_t> mask;
-    uint32_t off = 0, word = 0, used = 0, tokens = 0;
+    std::vector<uint64_t> fbit(2 * (size_t)d, 0);   // bit tokens of each feature, words w0 and w0 + 1
+    std::vector<uint32_t> tokdesc;                  // per token: kind | (bit index or cap) << 8 | feature << 16
+    uint32_t off = 0, tokens = 0, used = 0, word = 0;
     for (uint32_t f = 0; f < d; ++f) {
         const uint32_t nb = h_nbins[f];
-        const std::vector<uint32_t> qs = digit_radices(nb);
-        // place the digits: (word, first bit) of each
-        std::vector<std::pair<uint32_t, uint32_t>> at;
-        for (uint32_t q : qs) {
-            if (used + q > 64) { ++word; used = 0; }
-            at.push_back({word, used});
-            used += q;
-            tokens += q;
-        }
-        if (word >= 16) return;   // more than 16 words: beyond the matrix-core kernels
+        uint32_t mb = 0;
+        const uint32_t nt = feature_tokens(nb, &mb);
+        if (nt == ~0u) return;   // a feature beyond 1024 bins: stay one-hot
+        if (f >= (1u << 16)) return;
         FacFeature ft{};
         ft.off = (uint16_t)off;
         ft.nb = (uint16_t)nb;
-        ft.w0 = (uint8_t)(at.empty() ? 0 : at.front().first);
-        ft.nw = (uint8_t)(at.empty() ? 0 : at.back().first - at.front().first + 1);
         ft.mask = (uint32_t)mask.size();
-        for (uint32_t c = 0; c < nb && ft.nw; ++c) {
-            uint64_t part[2] = {0, 0};
-            uint32_t rest = c;   // digits from the least significant (last) one
-            for (size_t i = qs.size(); i-- > 0;) {
-                const uint32_t dg = rest % qs[i];
-                rest /= qs[i];
-                part[at[i].first - ft.w0] |= 1ull << (at[i].second + dg);
+        if (nt) {
+            const uint32_t t0 = tokens, t1 = tokens + nt;   // tokens [t0, t1)
+            if ((t1 - 1) / 64 >= 16) return;                 // more than 16 words
+            ft.w0 = (uint8_t)(t0 / 64);
+            ft.nw = (uint8_t)((t1 - 1) / 64 - t0 / 64 + 1);
+            for (uint32_t t = t0; t < t1; ++t) {
+                const uint32_t k = t - t0;
+                const uint32_t desc = k < mb ? (1u | k << 8) : (k == mb ? 2u : 3u);
+                tokdesc.push_back(desc | f << 16);
+                if (k < mb) fbit[2 * f + (t / 64 - ft.w0)] |= 1ull << (t % 64);
             }
-            for (uint32_t w = 0; w < ft.nw; ++w) mask.push_back(part[w]);
+            for (uint32_t c = 0; c < nb; ++c) {
+                uint64_t part[2] = {0, 0};
+                for (uint32_t t = t0; t < t1; ++t) {
+                    const uint32_t k = t - t0;
+                    if (k >= mb || ((c >> k) & 1u)) part[t / 64 - ft.w0] |= 1ull << (t % 64);
+                }
+                for (uint32_t w = 0; w < ft.nw; ++w) mask.push_back(part[w]);
+            }
+            tokens = t1;
+            word = (t1 - 1) / 64;
+            used = t1 - 64 * word;
         }
         feat[f] = ft;
         off += nb;
@@ -371,7 +379,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
         }
     for (uint32_t w = 0; w <= KF; ++w)
         if (fbeg[w] >= fend[w]) fbeg[w] = fend[w] = 0;
-    // digit ranges per output word (rows of record pairs): every bin's digit tokens
+    // token ranges per output word (rows of record pairs): every bin's tokens
     // of a feature, one entry per word it touches; a feature on two words gets the
     // next bit of the spanning mask
     std::vector<std::vector<uint32_t>> wq(KF);   // 4 dwords per entry
@@ -396,11 +404,13 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     wbeg[KF] = (uint32_t)(wfe.size() / 4);
     // one device block: range entries | masks | features | pieces | fbeg | fend | pbeg | wbeg
     // (16-byte aligned parts; the entries and pieces are read as 16-byte scalar loads)
+    tokdesc.resize((size_t)KF * 64, 0u);   // tokens past the last feature: kind 0
     auto al16 = [](size_t b) { return (b + 15) / 16 * 16; };
     const size_t eb = al16(wfe.size() * 4), mb = al16(mask.size() * 8),
                  fb = al16(feat.size() * sizeof(FacFeature)), pb = al16(piece.size() * sizeof(FacPiece)),
-                 ib = al16((KF + 1) * 4), kb = al16((m.KS + 1) * 4);
-    std::vector<char> host(eb + mb + fb + pb + 3 * ib + kb, 0);
+                 ib = al16((KF + 1) * 4), kb = al16((m.KS + 1) * 4), tb = al16(tokdesc.size() * 4),
+                 bb = al16(fbit.size() * 8);
+    std::vector<char> host(eb + mb + fb + pb + 3 * ib + kb + tb + bb, 0);
     size_t at = 0;
     auto put = [&](const void *src, size_t bytes, size_t span) {
         std::memcpy(host.data() + at, src, bytes);
@@ -416,6 +426,8 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     const size_t o_fend = put(fend.data(), (KF + 1) * 4, ib);
     const size_t o_pbeg = put(pbeg.data(), (m.KS + 1) * 4, kb);
     const size_t o_wbeg = put(wbeg.data(), (KF + 1) * 4, ib);
+    const size_t o_tok = put(tokdesc.data(), tokdesc.size() * 4, tb);
+    const size_t o_fbit = put(fbit.data(), fbit.size() * 8, bb);
     char *dev = dev_alloc<char>(host.size());
     m.fac = dev;
     IG_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, s));
@@ -428,6 +440,8 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     m.fv.pbeg = reinterpret_cast<const uint32_t *>(dev + o_pbeg);
     m.fv.wfe = reinterpret_cast<const uint4 *>(dev + o_wfe);
     m.fv.wbeg = reinterpret_cast<const uint32_t *>(dev + o_wbeg);
+    m.fv.tok = reinterpret_cast<const uint32_t *>(dev + o_tok);
+    m.fv.fbit = reinterpret_cast<const uint64_t *>(dev + o_fbit);
     m.fv.d = d;
     m.fv.KF = KF;
     m.fv.nmask = (uint32_t)mask.size();
@@ -755,22 +769,20 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
                "the matrix-core subset tests handle up to 16 operand words");
     mf.on = mode == 1 || mode == 3 || (mode == 0 && mf.KO <= kMfmaWords);
     if (!mf.on) return;
+    if (mf.view.KF) {
+        // each class's records, factored: its candidates' rows are built from them,
+        // and the other class's record tiles hold them on the signed side
+        for (int c = 0; c < 2; ++c) {
+            mf.fr[c].reset(std::max<size_t>(cls[c].n, 1) * mf.KO, s);
+            launch_operand_rows(nullptr, 0, nullptr, cls[c].X.get(), KS, cls[c].n, mf.view, false, mf.fr[c].get(),
+                                s);
+        }
+    }
     for (int c = 0; c < 2; ++c) {
         const ClassRows &o = cls[1 - c];
         mf.frag[c].reset(std::max<size_t>((size_t)mfma_record_tiles(o.n) * mf.KO * 64, 1), s);
-        if (mf.view.KF) {
-            Scratch<uint64_t> nrows(std::max<size_t>(o.n, 1) * mf.KO, s);
-            launch_operand_rows(nullptr, 0, nullptr, o.X.get(), KS, o.n, mf.view, true, nrows.get(), s);
-            launch_mfma_records(nrows.get(), o.n, mf.KO, mf.frag[c].get(), s);
-            // class c's own records, factored: the candidates' rows are built from them
-            if (mf.view.wfe && cls[c].n) {
-                mf.fr[c].reset((size_t)cls[c].n * mf.KO, s);
-                launch_operand_rows(nullptr, 0, nullptr, cls[c].X.get(), KS, cls[c].n, mf.view, false,
-                                    mf.fr[c].get(), s);
-            }
-        } else {
-            launch_mfma_records(o.NX.get(), o.n, KS, mf.frag[c].get(), s);
-        }
+        if (mf.view.KF) launch_mfma_records_signed(mf.fr[1 - c].get(), o.n, mf.view, mf.frag[c].get(), s);
+        else launch_mfma_records(o.NX.get(), o.n, KS, mf.frag[c].get(), s);
     }
 }
 
@@ -783,7 +795,7 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
     if (!ncand) return 0;
     Scratch<uint32_t> keep(ncand, s), kpos(ncand, s), ktot(1, s);
     Scratch<uint64_t> B((size_t)ncand * mf.KO, s);
-    if (mf.fr[c].get())
+    if (mf.view.KF)
         launch_pair_rows_factored(mf.fr[c].get(), cls[c].n, cand, ncand, mf.view, B.get(), s);
     else
         launch_operand_rows(cls[c].X.get(), cls[c].n, cand, nullptr, KS, ncand, mf.view, false, B.get(), s);

@@ -1,5 +1,5 @@
 // Operand rows for the matrix-core subset tests: the one-hot words themselves, or
-// their factored form (mixed-radix digits, one-hot per digit; see FactorView).
+// their factored form (bit and presence tokens per feature; see FactorView).
 #include <algorithm>
 #include <cstddef>
 
@@ -25,7 +25,7 @@ __device__ __forceinline__ int feature_code(const Word &word, const FacFeature f
 
 // The feature walk is uniform over the wave (every lane follows the same table);
 // each lane's row words are re-read from L1/L2 when a feature needs them, and the
-// digit tokens of its bin come from the mask table (L1/L2 resident).
+// tokens of its bin come from the mask table (L1/L2 resident).
 __global__ __launch_bounds__(256) void k_operand_rows(const uint64_t *__restrict__ X, uint32_t n,
                                                      const uint32_t *__restrict__ ids,
                                                      const uint64_t *__restrict__ W, uint32_t KS, size_t m,
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_operand_rows(const uint64_t *__restrict
         uint64_t acc = 0;
         for (uint32_t f = fv.fbeg[ow]; f < fv.fend[ow]; ++f) {
             const FacFeature ft = fv.feat[f];
-            if (ow - ft.w0 >= ft.nw) continue;   // a one-bin feature has no digits
+            if (ow - ft.w0 >= ft.nw) continue;   // a one-bin feature has no tokens
             const int code = feature_code(word, ft);
             if (code >= 0) acc |= fv.mask[ft.mask + (uint32_t)code * ft.nw + (ow - ft.w0)];
         }
@@ -117,10 +117,10 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
 }
 
 // Rows of record pairs in factored form (see launch_pair_rows_factored).  Two
-// records hold the same bin of a feature exactly when their digit tokens of that
+// records hold the same bin of a feature exactly when their tokens of that
 // feature agree, so the pair's row keeps FR[i] AND FR[j] on the features where
-// (FR[i] XOR FR[j]) has no bit in the feature's digit range and clears the rest.
-// A feature whose digits span two words is tested on both (first pass, one bit
+// (FR[i] XOR FR[j]) has no bit in the feature's token range and clears the rest.
+// A feature whose tokens span two words is tested on both (first pass, one bit
 // per such feature).  Each thread takes R rows at once, so one wave-uniform table
 // entry (a scalar load) serves R rows.
 template <int KO, int R>
@@ -180,7 +180,7 @@ void launch_pair_rows_factored(const uint64_t *FR, uint32_t n, const uint32_t *i
                                uint64_t *out, hipStream_t s) {
     if (!m) return;
     IG_REQUIRE(fv.KF >= 1 && fv.KF <= 16 && fv.wfe && fv.wbeg && n > 0, IG_E_DEVICE,
-               "factored pair rows without a digit-range table");
+               "factored pair rows without a token-range table");
     const size_t cap = (size_t)device_cus() * 8;
 #define IG_PR(V, RR)                                                                                               \
     case V: {                                                                                                      \

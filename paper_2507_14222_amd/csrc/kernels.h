@@ -72,17 +72,19 @@ void launch_adjacent_equal(const uint64_t *W, size_t m, uint32_t KS, uint32_t *d
 void launch_weights(const uint64_t *W, const uint32_t *f, size_t m, uint32_t KS, int64_t *S, hipStream_t s);
 
 // factor.hip -- factored tokens for the matrix-core operands.
-// A feature with nb bins is written as mixed-radix digits (radices q_0, q_1, ...
-// whose product is at least nb), each digit one-hot over its q tokens, instead of
-// one-hot over nb tokens.  Two codes are equal exactly when all their digits are,
-// so "b inside r" (every feature b holds has the same bin in r, Eq. 6 on the
-// one-hot packing of Eq. 5) is the same relation on the factored tokens.  Records
-// and flows hold one bin per feature and candidates and patterns at most one, so
-// every row of a fit from codes has a factored form; a bin of a feature is read
-// back from the one-hot row as the index of its one set bit.
+// A feature with nb bins takes m = ceil(log2 nb) bit tokens and one or two presence
+// tokens instead of nb one-hot tokens.  A pattern's (candidate's) factored row, a
+// bitset, sets for every feature it holds the bits of the bin index and the
+// presence tokens; the side that holds every feature (records; flows in scoring)
+// is written with signed values instead (see FactorView::tok), so that the
+// contraction counts the bits in which the bin indices differ over the features the
+// pattern holds: zero exactly when "b inside r" (Eq. 6 on the one-hot packing of
+// Eq. 5).  Records and flows hold one bin per feature and candidates and patterns
+// at most one, so every row of a fit from codes has a factored form; a bin of a
+// feature is read back from the one-hot row as the index of its one set bit.
 struct FacFeature {
     uint16_t off, nb;            // one-hot token range [off, off + nb) of the feature
-    uint8_t w0, nw, pad[2];      // its digits lie in output words w0 .. w0 + nw - 1 (nw <= 2)
+    uint8_t w0, nw, pad[2];      // its tokens lie in output words w0 .. w0 + nw - 1 (nw <= 2)
     uint32_t mask;               // masks of bin c: mask + c * nw + (word - w0)
 };
 struct FacPiece {                // the part of a feature inside one one-hot word
@@ -94,16 +96,23 @@ struct FacPiece {                // the part of a feature inside one one-hot wor
 };
 struct FactorView {
     const FacFeature *feat = nullptr;   // [d]
-    const uint64_t *mask = nullptr;     // the digit tokens of every (feature, bin)
+    const uint64_t *mask = nullptr;     // the pattern-side tokens of every (feature, bin)
     const uint32_t *fbeg = nullptr;     // [KF + 1]: features touching word w are
     const uint32_t *fend = nullptr;     //   [fbeg[w], fend[w]) (features in token order)
     const FacPiece *piece = nullptr;    // pieces grouped by one-hot word
     const uint32_t *pbeg = nullptr;     // [nwords + 1]: pieces of one-hot word k are [pbeg[k], pbeg[k + 1])
     // Digit ranges for rows of record pairs: entries of output word o are
     // [wbeg[o], wbeg[o + 1]) of wfe, each {x: bit in the spanning mask, y: 1 when the
-    // feature's digits span two words, z | w << 32: its digit bits in word o}
+    // feature's tokens span two words, z | w << 32: its tokens in word o}
     const uint4 *wfe = nullptr;
     const uint32_t *wbeg = nullptr;     // [KF + 1]
+    // Signed operands of the side that holds every feature (records; flows in
+    // scoring): tok[t], t < KF * 64, = kind | bit << 8 | feature << 16, kind 0 no
+    // token, 1 bit `bit` of the bin index (+1.0 when 0, -1.0 when 1), 2 and 3 the
+    // two parts of the popcount of the bin index (presence_parts); fbit[2 f + i] =
+    // the bit tokens of feature f in word feat[f].w0 + i
+    const uint32_t *tok = nullptr;
+    const uint64_t *fbit = nullptr;
     uint32_t d = 0, KF = 0;             // KF = 0: no factoring (operands are the one-hot words)
     uint32_t nmask = 0;                 // entries of mask
     uint32_t nwords = 0;                // one-hot storage words pbeg covers (the fit's KS)
@@ -114,7 +123,7 @@ struct FactorView {
 void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, const uint64_t *W, uint32_t KS, size_t m,
                          const FactorView &fv, bool complement, uint64_t *out, hipStream_t s);
 // Factored operand rows of record pairs from the records' own factored rows FR
-// [n][fv.KF]: row e (pair id ids[e]) is FR[i] AND FR[j] with the digits of every
+// [n][fv.KF]: row e (pair id ids[e]) is FR[i] AND FR[j] with the tokens of every
 // feature on which the two records differ cleared (a one-bin-per-feature fit).
 void launch_pair_rows_factored(const uint64_t *FR, uint32_t n, const uint32_t *ids, size_t m, const FactorView &fv,
                                uint64_t *out, hipStream_t s);
@@ -152,6 +161,9 @@ void launch_digest(const uint64_t *W, const uint32_t *f, const int64_t *S, size_
 // records containing it (support f, Eq. 2).
 uint32_t mfma_record_tiles(uint32_t n);
 void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *frag, hipStream_t s);
+// The same tiles for factored tokens: records on the signed side (FactorView::tok)
+// from their factored rows FR [n][fv.KF]; KO = fv.KF.
+void launch_mfma_records_signed(const uint64_t *FR, uint32_t n, const FactorView &fv, uint4 *frag, hipStream_t s);
 void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const uint4 *frag, uint32_t n_rec,
                          uint32_t *out, hipStream_t s);
 

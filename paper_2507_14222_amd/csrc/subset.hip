@@ -308,6 +308,51 @@ __global__ void k_mfma_records(const uint64_t *__restrict__ NX, uint32_t n, uint
     frag[g] = make_uint4(spread8(d), spread8(d >> 8), spread8(d >> 16), spread8(d >> 24));
 }
 
+// The signed side of the factored tokens (FactorView::tok): the e2m1 nibble of
+// token `desc` for a row whose bin index of the token's feature has the given bit
+// (bit tokens) and popcount pc (presence tokens: two parts e2m1 holds exactly).
+__device__ __forceinline__ uint32_t signed_nibble(uint32_t desc, uint32_t bit, uint32_t pc) {
+    const uint32_t kind = desc & 3u;
+    if (kind == 1u) return bit ? 0xAu : 0x2u;   // -1.0 / +1.0
+    if (kind == 0u) return 0u;
+    const uint32_t first = pc >= 6u ? 6u : min(pc, 4u);
+    const uint32_t v = kind == 2u ? first : pc - first;
+    return (0x7065420u >> (4u * v)) & 0xFu;   // e2m1 of 0, 1, 2, 3, 4, -, 6
+}
+
+// Records in the A-operand layout of k_mfma_records, on the signed side of the
+// factored tokens, from their factored rows FR [n][KO] (every feature present).
+// Rows past n are +1.0 on every token: a candidate sets a presence token for each
+// feature it holds, so it never lies inside them.
+__global__ void k_mfma_records_signed(const uint64_t *__restrict__ FR, uint32_t n, uint32_t KO, uint32_t ntiles,
+                                      FactorView fv, uint4 *__restrict__ frag) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (size_t)ntiles * KO * 64) return;
+    const uint32_t lane = (uint32_t)(g % 64), word = (uint32_t)((g / 64) % KO), tile = (uint32_t)(g / (64 * KO));
+    const uint32_t r = tile * 32 + lane % 32, h = lane / 32;
+    if (r >= n) {
+        frag[g] = make_uint4(0x22222222u, 0x22222222u, 0x22222222u, 0x22222222u);
+        return;
+    }
+    const uint64_t *R = FR + (size_t)r * KO;
+    const uint32_t mine = (uint32_t)(R[word] >> (32 * h));
+    uint64_t lo = 0, hi = 0;
+    for (uint32_t j = 0; j < 32; ++j) {
+        const uint32_t desc = fv.tok[word * 64 + 32 * h + j];
+        uint32_t pc = 0;
+        if ((desc & 3u) >= 2u) {
+            const uint32_t f = desc >> 16;
+            const FacFeature ft = fv.feat[f];
+            pc = (uint32_t)__popcll(R[ft.w0] & fv.fbit[2 * f]);
+            if (ft.nw > 1) pc += (uint32_t)__popcll(R[ft.w0 + 1] & fv.fbit[2 * f + 1]);
+        }
+        const uint32_t nib = signed_nibble(desc, (mine >> j) & 1u, pc);
+        if (j < 16) lo |= (uint64_t)nib << (4 * j);
+        else hi |= (uint64_t)nib << (4 * (j - 16));
+    }
+    frag[g] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+}
+
 // One workgroup: 8 waves x 2 column sets x 32 candidates = 512 candidates; each
 // wave keeps its candidates' B operands in registers for the whole scan.
 constexpr int MF_NT = 512;                  // threads per matrix-core workgroup
@@ -548,21 +593,36 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
         const bool act = t < a.n_flows;
         uint64_t wd[KS];
         bool ok = act;
-        if (act && a.codes && a.fv.KF) {
-            const uint16_t *row = a.codes + (size_t)t * a.d;
-            for (uint32_t ft = 0; ft < a.d; ++ft) ok &= row[ft] < a.nbins[ft];
+        if (a.fv.KF) {
+            // factored tokens: the flow is the signed side (FactorView::tok), built
+            // token by token from its codes; an inactive or invalid flow is +1.0 on
+            // every token (the empty set: no pattern lies inside it)
+            const uint16_t *row = a.codes + (size_t)(act ? t : 0u) * a.d;
+            if (act)
+                for (uint32_t ft = 0; ft < a.d; ++ft) ok &= row[ft] < a.nbins[ft];
 #pragma unroll
             for (int k = 0; k < KS; ++k) {
-                uint64_t v = 0;
-                for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
-                    const FacFeature ft = a.fv.feat[f];
-                    if ((uint32_t)k - ft.w0 >= ft.nw) continue;   // a one-bin feature has no digits
-                    const uint32_t c = row[f] < ft.nb ? row[f] : 0u;   // out of range: flow is dropped
-                    v |= a.fv.mask[ft.mask + c * ft.nw + (k - ft.w0)];
+                uint64_t lo = 0, hi = 0;
+                for (uint32_t j = 0; j < 32; ++j) {
+                    const uint32_t desc = a.fv.tok[k * 64 + 32 * half + j];
+                    uint32_t nib = 0x2u;
+                    if (ok && (desc & 3u)) {
+                        const uint32_t c = row[desc >> 16];
+                        nib = signed_nibble(desc, (c >> ((desc >> 8) & 0xffu)) & 1u, __popc(c));
+                    } else if (ok) {
+                        nib = 0u;
+                    }
+                    // the spare token is +1.0 in every flow (it carries the count's starting +1)
+                    if (SPARE && k == KS - 1 && half && j == 31) nib = 0x2u;
+                    if (j < 16) lo |= (uint64_t)nib << (4 * j);
+                    else hi |= (uint64_t)nib << (4 * (j - 16));
                 }
-                wd[k] = v;
+                b[f][k] = v8i_t{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
+                                (int)(uint32_t)(hi >> 32), 0, 0, 0, 0};
             }
-        } else if (act && a.codes) {
+            continue;
+        }
+        if (act && a.codes) {
             const uint16_t *row = a.codes + (size_t)t * a.d;
             const uint32_t *off = a.meta, *flo = a.meta + a.d, *fhi = a.meta + a.d + KS;
 #pragma unroll
@@ -659,6 +719,16 @@ void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint3
 }
 
 uint32_t mfma_record_tiles(uint32_t n) { return (n + 31) / 32; }
+
+void launch_mfma_records_signed(const uint64_t *FR, uint32_t n, const FactorView &fv, uint4 *frag, hipStream_t s) {
+    const uint32_t KO = fv.KF, ntiles = mfma_record_tiles(n);
+    const size_t total = (size_t)ntiles * KO * 64;
+    if (!total) return;
+    IG_REQUIRE(fv.tok && fv.fbit, IG_E_DEVICE, "signed record operands without a token table");
+    hipLaunchKernelGGL(k_mfma_records_signed, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, FR, n, KO,
+                       ntiles, fv, frag);
+    IG_HIP(hipGetLastError());
+}
 
 void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *frag, hipStream_t s) {
     const uint32_t ntiles = mfma_record_tiles(n);
