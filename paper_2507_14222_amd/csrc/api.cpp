@@ -304,7 +304,9 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     std::vector<FacFeature> feat(d);
     std::vector<uint64_t> mask;
     std::vector<uint64_t> fbit(2 * (size_t)d, 0);   // bit tokens of each feature, words w0 and w0 + 1
-    std::vector<uint32_t> tokdesc;                  // per token: kind | (bit index or cap) << 8 | feature << 16
+    std::vector<uint32_t> tokdesc;                  // per token: kind | bit index << 8 | feature << 16
+    std::vector<uint64_t> bitw(16, 0);              // bit tokens per word
+    std::vector<uint32_t> ptok(d, ~0u);             // first presence token | count << 24
     uint32_t off = 0, tokens = 0, used = 0, word = 0;
     for (uint32_t f = 0; f < d; ++f) {
         const uint32_t nb = h_nbins[f];
@@ -325,8 +327,12 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
                 const uint32_t k = t - t0;
                 const uint32_t desc = k < mb ? (1u | k << 8) : (k == mb ? 2u : 3u);
                 tokdesc.push_back(desc | f << 16);
-                if (k < mb) fbit[2 * f + (t / 64 - ft.w0)] |= 1ull << (t % 64);
+                if (k < mb) {
+                    fbit[2 * f + (t / 64 - ft.w0)] |= 1ull << (t % 64);
+                    bitw[t / 64] |= 1ull << (t % 64);
+                }
             }
+            ptok[f] = (t0 + mb) | (nt - mb) << 24;
             for (uint32_t c = 0; c < nb; ++c) {
                 uint64_t part[2] = {0, 0};
                 for (uint32_t t = t0; t < t1; ++t) {
@@ -405,12 +411,13 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     // one device block: range entries | masks | features | pieces | fbeg | fend | pbeg | wbeg
     // (16-byte aligned parts; the entries and pieces are read as 16-byte scalar loads)
     tokdesc.resize((size_t)KF * 64, 0u);   // tokens past the last feature: kind 0
+    bitw.resize(KF);
     auto al16 = [](size_t b) { return (b + 15) / 16 * 16; };
     const size_t eb = al16(wfe.size() * 4), mb = al16(mask.size() * 8),
                  fb = al16(feat.size() * sizeof(FacFeature)), pb = al16(piece.size() * sizeof(FacPiece)),
                  ib = al16((KF + 1) * 4), kb = al16((m.KS + 1) * 4), tb = al16(tokdesc.size() * 4),
-                 bb = al16(fbit.size() * 8);
-    std::vector<char> host(eb + mb + fb + pb + 3 * ib + kb + tb + bb, 0);
+                 bb = al16(fbit.size() * 8), wb = al16(bitw.size() * 8), qb = al16(ptok.size() * 4);
+    std::vector<char> host(eb + mb + fb + pb + 3 * ib + kb + tb + bb + wb + qb, 0);
     size_t at = 0;
     auto put = [&](const void *src, size_t bytes, size_t span) {
         std::memcpy(host.data() + at, src, bytes);
@@ -428,6 +435,8 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     const size_t o_wbeg = put(wbeg.data(), (KF + 1) * 4, ib);
     const size_t o_tok = put(tokdesc.data(), tokdesc.size() * 4, tb);
     const size_t o_fbit = put(fbit.data(), fbit.size() * 8, bb);
+    const size_t o_bitw = put(bitw.data(), bitw.size() * 8, wb);
+    const size_t o_ptok = put(ptok.data(), ptok.size() * 4, qb);
     char *dev = dev_alloc<char>(host.size());
     m.fac = dev;
     IG_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, s));
@@ -442,6 +451,8 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     m.fv.wbeg = reinterpret_cast<const uint32_t *>(dev + o_wbeg);
     m.fv.tok = reinterpret_cast<const uint32_t *>(dev + o_tok);
     m.fv.fbit = reinterpret_cast<const uint64_t *>(dev + o_fbit);
+    m.fv.bitw = reinterpret_cast<const uint64_t *>(dev + o_bitw);
+    m.fv.ptok = reinterpret_cast<const uint32_t *>(dev + o_ptok);
     m.fv.d = d;
     m.fv.KF = KF;
     m.fv.nmask = (uint32_t)mask.size();

@@ -113,6 +113,8 @@ struct FactorView {
     // the bit tokens of feature f in word feat[f].w0 + i
     const uint32_t *tok = nullptr;
     const uint64_t *fbit = nullptr;
+    const uint64_t *bitw = nullptr;     // [KF]: the bit tokens of every feature, per word
+    const uint32_t *ptok = nullptr;     // [d]: first presence token | count << 24 (~0: none)
     uint32_t d = 0, KF = 0;             // KF = 0: no factoring (operands are the one-hot words)
     uint32_t nmask = 0;                 // entries of mask
     uint32_t nwords = 0;                // one-hot storage words pbeg covers (the fit's KS)

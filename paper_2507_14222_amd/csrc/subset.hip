@@ -357,10 +357,11 @@ __global__ void k_mfma_records_signed(const uint64_t *__restrict__ FR, uint32_t 
 // wave keeps its candidates' B operands in registers for the whole scan.
 constexpr int MF_NT = 512;                  // threads per matrix-core workgroup
 constexpr int MF_FB = 2;                    // 32-column sets per wave (scoring)
-// 32-column sets per wave of the subset-test contraction: two up to 8 operand
-// words, one beyond (the B operands of a set take 4 VGPRs per word)
+// 32-column sets per wave of the subset-test contraction: three up to 5 operand
+// words, two up to 8, one beyond (the B operands of a set take 4 VGPRs per word;
+// more sets share each A tile read from LDS among more multiplications)
 #ifndef IG_MF_SETS_NARROW
-#define IG_MF_SETS_NARROW 2
+#define IG_MF_SETS_NARROW 3
 #endif
 template <int KS>
 constexpr int mf_sets() { return KS <= 5 ? IG_MF_SETS_NARROW : KS <= 8 ? 2 : 1; }
@@ -594,34 +595,49 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
         uint64_t wd[KS];
         bool ok = act;
         if (a.fv.KF) {
-            // factored tokens: the flow is the signed side (FactorView::tok), built
-            // token by token from its codes; an inactive or invalid flow is +1.0 on
-            // every token (the empty set: no pattern lies inside it)
+            // factored tokens: the flow is the signed side (FactorView::tok).  Its
+            // bit tokens come from its factored row (bin bit 0: +1.0, 1: -1.0), its
+            // presence tokens from the popcounts of its bin indices; an inactive or
+            // invalid flow is +1.0 on every token (the empty set: no pattern lies inside)
             const uint16_t *row = a.codes + (size_t)(act ? t : 0u) * a.d;
             if (act)
                 for (uint32_t ft = 0; ft < a.d; ++ft) ok &= row[ft] < a.nbins[ft];
 #pragma unroll
             for (int k = 0; k < KS; ++k) {
-                uint64_t lo = 0, hi = 0;
-                for (uint32_t j = 0; j < 32; ++j) {
-                    const uint32_t desc = a.fv.tok[k * 64 + 32 * half + j];
-                    uint32_t nib = 0x2u;
-                    if (ok && (desc & 3u)) {
-                        const uint32_t c = row[desc >> 16];
-                        nib = signed_nibble(desc, (c >> ((desc >> 8) & 0xffu)) & 1u, __popc(c));
-                    } else if (ok) {
-                        nib = 0u;
+                uint64_t v = 0;   // the flow's factored word k (pattern side: bits and presence)
+                uint64_t lo = 0x2222222222222222ull, hi = 0x2222222222222222ull;
+                if (ok) {
+                    for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
+                        const FacFeature ft = a.fv.feat[f];
+                        if ((uint32_t)k - ft.w0 >= ft.nw) continue;
+                        v |= a.fv.mask[ft.mask + (uint32_t)row[f] * ft.nw + (k - ft.w0)];
                     }
-                    // the spare token is +1.0 in every flow (it carries the count's starting +1)
-                    if (SPARE && k == KS - 1 && half && j == 31) nib = 0x2u;
-                    if (j < 16) lo |= (uint64_t)nib << (4 * j);
-                    else hi |= (uint64_t)nib << (4 * (j - 16));
+                    const uint64_t bw = a.fv.bitw[k];
+                    const uint32_t ones = (uint32_t)((v & bw) >> (32 * half)), zeros = (uint32_t)((~v & bw) >> (32 * half));
+                    lo = (uint64_t)(spread8(zeros) | spread8(ones) * 5u) |
+                         (uint64_t)(spread8(zeros >> 8) | spread8(ones >> 8) * 5u) << 32;
+                    hi = (uint64_t)(spread8(zeros >> 16) | spread8(ones >> 16) * 5u) |
+                         (uint64_t)(spread8(zeros >> 24) | spread8(ones >> 24) * 5u) << 32;
+                    for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
+                        const uint32_t pt = a.fv.ptok[f];
+                        if (pt == ~0u) continue;
+                        const uint32_t pc = __popc(row[f]);
+                        for (uint32_t part = 0; part < (pt >> 24); ++part) {
+                            const uint32_t tk = (pt & 0xffffffu) + part;
+                            if (tk / 64 != (uint32_t)k || (tk % 64) / 32 != half) continue;
+                            const uint32_t j = tk % 32;
+                            const uint64_t nib = signed_nibble(2u + part, 0u, pc);
+                            if (j < 16) lo |= nib << (4 * j);
+                            else hi |= nib << (4 * (j - 16));
+                        }
+                    }
                 }
+                // the spare token is +1.0 in every flow (it carries the count's starting +1)
+                if (SPARE && k == KS - 1 && half) hi = (hi & 0x0fffffffffffffffull) | 0x2000000000000000ull;
                 b[f][k] = v8i_t{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
                                 (int)(uint32_t)(hi >> 32), 0, 0, 0, 0};
             }
-            continue;
-        }
+        } else {
         if (act && a.codes) {
             const uint16_t *row = a.codes + (size_t)t * a.d;
             const uint32_t *off = a.meta, *flo = a.meta + a.d, *fhi = a.meta + a.d + KS;
@@ -649,6 +665,7 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
             const uint32_t dwd = (uint32_t)(nt >> (32 * half));
             b[f][k] = v8i_t{(int)spread8(dwd), (int)spread8(dwd >> 8), (int)spread8(dwd >> 16),
                             (int)spread8(dwd >> 24), 0, 0, 0, 0};
+        }
         }
     }
     // C[f]: running weighting products; row c < 4 of column `col` (lane half 0,
