@@ -87,18 +87,18 @@ typedef struct {
     const ig_tune_entry *tune;  /* host tuning table (may be NULL)                    */
     uint32_t coherence_mfma;    /* coherence (Eq. 3) and support (Eq. 2) kernels:
                                    0 = automatic: matrix cores when the operands fit
-                                       8 words, else the VALU path;
-                                   1 = matrix cores: a dense 0/1 contraction with fp4
+                                       16 words, else the VALU path;
+                                   1 = matrix cores: a dense contraction with fp4
                                        operands and fp32 accumulation, exact; no early
                                        exit, so ig_stats.tests counts every (candidate,
                                        other-class record) pair.  Fits from codes use
-                                       factored tokens (each feature as mixed-radix
-                                       digits, one-hot per digit: 288 instead of 464
-                                       tokens for 41 features of ~11 bins), else the
-                                       K one-hot words; at most 8 words;
+                                       factored tokens (per feature the bits of its
+                                       bin index plus presence tokens: 207 instead of
+                                       464 tokens for 41 features of ~11 bins), else
+                                       the K one-hot words; at most 16 words;
                                    2 = VALU path: AND-NOT chains with early exit in
                                        input order (ig_stats.tests = sum of t(b));
-                                   3 = matrix cores on the one-hot words (K <= 8).
+                                   3 = matrix cores on the one-hot words (K <= 16).
                                    All give the same patterns, f and S.             */
     uint32_t reserved;
 } ig_fit_opts;
