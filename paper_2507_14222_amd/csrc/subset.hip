@@ -205,13 +205,16 @@ __global__ __launch_bounds__(256) void k_coherence(const CohSeg *__restrict__ se
 }
 
 // ------------------------------------------------ coherence as a contraction ----
-// The coherence test as a dense matrix product on the matrix cores:
-// V[r][b] = sum over tokens of (NOT r)[token] * b[token] counts the tokens of
-// candidate b missing from record r; b is covered when some V is 0 (Eq. 6).  The
-// 0/1 operands are exact in fp4 (e2m1: 1.0 = 0x2) and every V <= 512 is exact in
-// the fp32 accumulators.  One v_mfma_scale_f32_32x32x64_f8f6f4 covers 64 tokens
-// (one 64-bit word): lanes l and l+32 of a row / column supply its two 32-bit
-// halves.  Records are the A operand (rows), candidates the B operand (columns).
+// The coherence test as a dense matrix product on the matrix cores: V[r][b] =
+// sum over tokens of r'[token] * b[token], with b the candidate's 0/1 tokens and
+// r' the record's side, is 0 exactly when record r contains candidate b (Eq. 6)
+// and positive otherwise.  On one-hot tokens r' = NOT r and V counts b's tokens
+// missing from r; on factored tokens r' is the signed side (FactorView::tok) and
+// V counts the bits in which the bin indices differ.  Every operand is exact in
+// fp4 (e2m1: 1.0 = 0x2, -1.0 = 0xA) and every V is a small integer, exact in the
+// fp32 accumulators.  One v_mfma_scale_f32_32x32x64_f8f6f4 covers 64 tokens (one
+// 64-bit word): lanes l and l+32 of a row / column supply its two 32-bit halves.
+// Records are the A operand (rows), candidates the B operand (columns).
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 typedef int v8i_t __attribute__((ext_vector_type(8)));
 typedef int v16i_t __attribute__((ext_vector_type(16)));
@@ -294,10 +297,10 @@ __device__ __forceinline__ void stream_tiles(const uint4 *__restrict__ frag_in, 
     }
 }
 
-// Other-class records, complemented, in the A-operand layout of each 32-record
-// tile: frag[(tile * KS + word) * 64 + lane] = the 32 nibbles of half (lane/32) of
-// word `word` of record tile*32 + lane%32.  Rows past n are all ones (the empty
-// record), which never contain a candidate.
+// Other-class records, complemented (one-hot tokens), in the A-operand layout of
+// each 32-record tile: frag[(tile * KS + word) * 64 + lane] = the 32 nibbles of
+// half (lane/32) of word `word` of record tile*32 + lane%32.  Rows past n are all
+// ones (the empty record), which never contain a candidate.
 __global__ void k_mfma_records(const uint64_t *__restrict__ NX, uint32_t n, uint32_t KS, uint32_t ntiles,
                                uint4 *__restrict__ frag) {
     const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -477,18 +480,19 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
 }
 
 // Scoring (Eq. 4) as the same contraction: V[b][t] = sum over tokens of
-// b[token] * (NOT t)[token] is 0 exactly when pattern b lies inside flow t.
-// Patterns are the A operand (rows), pre-expanded per model with their weights in
-// accumulator order; flows are the B operand (columns), packed from their codes,
-// complemented and expanded in registers.  Accumulator register r of lane half h
-// holds row (r / 4) * 8 + 4 h + r % 4 of the 32-row tile.
+// b[token] * t'[token] is 0 exactly when pattern b lies inside flow t, with t' the
+// complement of the flow's one-hot words or the signed side of its factored
+// tokens.  Patterns are the A operand (rows), pre-expanded per model with their
+// weights in accumulator order; flows are the B operand (columns), built from
+// their codes in registers.  Accumulator register r of lane half h holds row
+// (r / 4) * 8 + 4 h + r % 4 of the 32-row tile.
 __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return (r >> 2) * 8 + half * 4 + (r & 3); }
 
 // Scoring operands of a pattern set: (KS + 1) * 64 uint4 per 32-row tile.
 //  words w < KS, frag[(tile * (KS + 1) + w) * 64 + lane]: the nibbles of half
 //    (lane/32) of word w of row tile*32 + lane%32, as -1.0 (e2m1 0xA) per token
-//    (empty past m), so that an accumulator started at 1.0 ends at 1 - (tokens of
-//    the pattern missing from the flow): 1 exactly when the pattern lies inside;
+//    (empty past m), so that an accumulator started at 1.0 ends at 1 - V: 1
+//    exactly when the pattern lies inside, at most 0 otherwise;
 //  slice KS, frag[(tile * (KS + 1) + KS) * 64 + lane]: the A operand of the
 //    weighting product (v_mfma_i32_32x32x32_i8): for lane%32 = c < 4 and half h,
 //    byte j holds 7-bit chunk c of the weight of the row in accumulator j of half h
@@ -539,8 +543,8 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
 #ifndef IG_SCORE_WPS
 #define IG_SCORE_WPS 3
 #endif
-// ring: groups of IG_SCORE_GTOK / (KS + 1) tiles (4 at five operand words), two
-// buffers; three workgroups of 256 threads then fit a CU's LDS
+// ring: groups of IG_SCORE_GTOK / (KS + 1) tiles (4 at four or five operand
+// words), two buffers; three workgroups of 256 threads then fit a CU's LDS
 #ifndef IG_SCORE_GTOK
 #define IG_SCORE_GTOK 24
 #endif
