@@ -391,7 +391,8 @@ constexpr int mf_group() { return IG_MF_GTOK / KS > 0 ? IG_MF_GTOK / KS : 1; }  
 template <int KS, bool COUNT>
 __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const uint64_t *__restrict__ B, uint32_t m,
                                                                          const uint4 *__restrict__ frag,
-                                                                         uint32_t ntiles, uint32_t *__restrict__ out) {
+                                                                         uint32_t ntiles, uint32_t pad,
+                                                                         uint32_t *__restrict__ out) {
     constexpr int G = mf_group<KS>();
     constexpr int FB = mf_sets<KS>();
     __shared__ uint4 lds[ring_lds<KS * 64, G, MF_NB>()];
@@ -451,7 +452,16 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
         // the two halves of the wave hold different record rows of the same column
-        const uint32_t h = hits[f] + __shfl_xor(hits[f], 32, 64);
+        uint32_t h = hits[f] + __shfl_xor(hits[f], 32, 64);
+        // A row with no tokens (a pattern of one-bin features only, in factored
+        // form) gives 0 against every A row, the padding rows of the last tile too:
+        // they are not records, so they come off its count.  (Coherence needs no
+        // such care: a real record of the tile contains that row as well.)
+        if (COUNT && pad && half == 0 && e[f] < m) {
+            uint64_t any = 0;
+            for (int w = 0; w < KS; ++w) any |= B[(size_t)e[f] * KS + w];
+            if (!any) h -= pad;
+        }
         if (half == 0 && e[f] < m) out[e[f]] = COUNT ? h : (h ? 0u : 1u);
     }
 }
@@ -460,14 +470,16 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
                          uint32_t *out, hipStream_t s) {
     if (!m) return;
     IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 rows in one matrix-core launch");
-    const uint32_t ntiles = (n_rec + 31) / 32;
+    const uint32_t ntiles = (n_rec + 31) / 32, pad = 32 * ntiles - n_rec;
 #define IG_CM(V)                                                                                                 \
     case V: {                                                                                                    \
         const dim3 grid((unsigned)((m + mf_cols<V>() - 1) / mf_cols<V>()));                                      \
         if (count)                                                                                               \
-            hipLaunchKernelGGL((k_contain_mfma<V, true>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, out); \
+            hipLaunchKernelGGL((k_contain_mfma<V, true>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, pad, \
+                               out);                                                                             \
         else                                                                                                     \
-            hipLaunchKernelGGL((k_contain_mfma<V, false>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, out); \
+            hipLaunchKernelGGL((k_contain_mfma<V, false>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, \
+                               pad, out);                                                                        \
         break;                                                                                                   \
     }
     switch (KO) {
@@ -591,6 +603,7 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     v8i_t b[MF_FB][KS];
     uint32_t tf[MF_FB];
+    bool valid[MF_FB];   // active, with every code in range (the others keep their -1)
 #pragma unroll
     for (int f = 0; f < MF_FB; ++f) {
         const uint32_t t = fb * SC_COLS + wave * (MF_FB * 32) + f * 32 + col;
@@ -671,6 +684,7 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
                             (int)spread8(dwd >> 24), 0, 0, 0, 0};
         }
         }
+        valid[f] = ok;
     }
     // C[f]: running weighting products; row c < 4 of column `col` (lane half 0,
     // accumulators 0..3) sums chunk c of the weights of the patterns inside the flow
@@ -723,7 +737,7 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
             uint64_t v = 0;
 #pragma unroll
             for (int c = 0; c < 4; ++c) v += (uint64_t)(uint32_t)C[f][c] << (7 * c);
-            if (half == 0 && tf[f] < a.n_flows && v)
+            if (half == 0 && valid[f] && v)
                 atomicAdd(reinterpret_cast<unsigned long long *>(a.out + 2 * (size_t)tf[f] + colsel),
                           (unsigned long long)v);
         }

@@ -391,6 +391,29 @@ def test_matrix_core_coherence_matches_oracle(case, kernels):
     assert np.array_equal(A[~bad], oA) and np.array_equal(N[~bad], oN)
 
 
+def test_factored_patterns_without_tokens():
+    """A pattern of one-bin features only has no factored tokens: its support must
+    not count the padding rows of the last record tile, and an invalid flow must
+    keep its (-1, -1) although such a pattern meets every operand with zero."""
+    say("token-free factored patterns")
+    rng = np.random.default_rng(11)
+    nb = np.array([1, 70, 2], np.uint16)   # 73 one-hot tokens in 2 words; factored, 1 word
+    n = 40                                  # the last record tile holds 8 of 32 rows
+    codes = np.stack([np.zeros(n, np.int64), rng.integers(0, 70, n), rng.integers(0, 2, n)], 1).astype(np.uint16)
+    labels = np.zeros(n, np.uint8)          # one class: every candidate is coherent
+    om = oracle.fit(codes, labels, nb)
+    m = ig.fit(codes, labels, nb, kernels="mfma")
+    info = m.info()
+    assert info.flags & ig.IG_MODEL_FACTORED and m.score_on_matrix_cores
+    assert_same_model(m, om, om.K)
+    flows = np.array([[0, 5, 1], [0, 69, 0], [0, 70, 0], [0, 3, 2], [0, 12, 1]], np.uint16)
+    bad = np.array([False, False, True, True, False])
+    A, N = gpu_scores(m, flows)
+    assert np.all(A[bad] == -1) and np.all(N[bad] == -1)
+    oA, oN = oracle.score(om, flows[~bad], nb)
+    assert np.array_equal(A[~bad], oA) and np.array_equal(N[~bad], oN)
+
+
 def test_matrix_core_coherence_15k_digest():
     g = json.load(open(os.path.join(GOLD, "mixture41_15k.json")))
     w = synth.make_15k()
