@@ -456,6 +456,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     m.fv.d = d;
     m.fv.KF = KF;
     m.fv.nmask = (uint32_t)mask.size();
+    m.fv.npiece = (uint32_t)piece.size();
     m.fv.nwords = m.KS;
     m.fac_tokens_last = used;
     m.fac_tokens = tokens;

@@ -70,15 +70,23 @@ constexpr uint32_t kLdsMasks = 2048;   // u64 masks staged in LDS (16 KB)
 static_assert(sizeof(FacPiece) == 16 && offsetof(FacPiece, base) == 4 && offsetof(FacPiece, mask) == 8,
               "the kernel reads a piece as four dwords");
 
-template <int KS>
+// LPIECES: the piece table is staged in LDS too (a launch of few rows would
+// otherwise wait on one scalar-cache miss per piece on every CU it touches) and
+// read back to scalar registers with readfirstlane.
+constexpr uint32_t kLdsPieces = 512;
+
+template <int KS, bool LPIECES>
 __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__restrict__ X, uint32_t n,
                                                          const uint32_t *__restrict__ ids,
                                                          const uint64_t *__restrict__ W, size_t m, FactorView fv,
                                                          uint32_t KO, uint64_t flip, uint64_t *__restrict__ out) {
     __shared__ uint64_t smask[kLdsMasks + 1];   // + 1: the second word read next to the last entry
+    __shared__ uint4 spiece[LPIECES ? kLdsPieces : 1];
     for (uint32_t t = threadIdx.x; t <= fv.nmask; t += blockDim.x) smask[t] = t < fv.nmask ? fv.mask[t] : 0ull;
-    __syncthreads();
     const uint4 *pw = reinterpret_cast<const uint4 *>(fv.piece);
+    if (LPIECES)
+        for (uint32_t t = threadIdx.x; t < fv.npiece; t += blockDim.x) spiece[t] = pw[t];
+    __syncthreads();
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
         uint64_t w[KS];
         if (ids) {
@@ -95,7 +103,14 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
         for (int k = 0; k < KS; ++k) {
             const uint32_t p1 = fv.pbeg[k + 1];
             for (uint32_t p = fv.pbeg[k]; p < p1; ++p) {
-                const uint4 pc = pw[p];
+                uint4 pc;
+                if (LPIECES) {
+                    const uint4 v = spiece[p];   // same address in every lane
+                    pc = make_uint4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
+                                    __builtin_amdgcn_readfirstlane(v.z), 0u);
+                } else {
+                    pc = pw[p];
+                }
                 const uint32_t shape = pc.x, base = pc.y & 0xffffu, mk = pc.z;
                 const uint32_t lo = shape & 255u, width = (shape >> 8) & 255u, w0 = (shape >> 16) & 15u;
                 const uint32_t nw = shape >> 24;
@@ -208,9 +223,14 @@ void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, con
     if (fv.KF && KS <= 16 && KO <= 16 && fv.nmask <= kLdsMasks) {
         // strided over the rows: a few workgroups per CU, each staging the masks once
         const dim3 sgrid((unsigned)std::min<size_t>((m + 255) / 256, (size_t)device_cus() * 8));
-#define IG_OR_K(V)                                                                                                  \
-    case V:                                                                                                         \
-        hipLaunchKernelGGL((k_operand_rows_reg<V>), sgrid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, flip, out); \
+#define IG_OR_K(V)                                                                                             \
+    case V:                                                                                                    \
+        if (fv.npiece <= kLdsPieces)                                                                           \
+            hipLaunchKernelGGL((k_operand_rows_reg<V, true>), sgrid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, \
+                               flip, out);                                                                     \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_operand_rows_reg<V, false>), sgrid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, \
+                               flip, out);                                                                     \
         break;
         switch (KS) {   // the compiled storage widths up to 16 words
             IG_OR_K(1) IG_OR_K(2) IG_OR_K(3) IG_OR_K(4) IG_OR_K(5) IG_OR_K(6) IG_OR_K(7) IG_OR_K(8)

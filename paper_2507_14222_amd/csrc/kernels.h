@@ -117,6 +117,7 @@ struct FactorView {
     const uint32_t *ptok = nullptr;     // [d]: first presence token | count << 24 (~0: none)
     uint32_t d = 0, KF = 0;             // KF = 0: no factoring (operands are the one-hot words)
     uint32_t nmask = 0;                 // entries of mask
+    uint32_t npiece = 0;                // entries of piece
     uint32_t nwords = 0;                // one-hot storage words pbeg covers (the fit's KS)
 };
 // Operand rows out[m][KO], KO = fv.KF when factoring, else KS: row e is the
