@@ -57,7 +57,7 @@ class GpuExecutor:
 
     def new_slot(self):
         import torch
-        return {
+        h = {
             "stream": torch.cuda.Stream(),
             "done": torch.cuda.Event(),
             "h_codes": torch.empty((self.cap, self.d), dtype=torch.int16, pin_memory=True),
@@ -65,6 +65,12 @@ class GpuExecutor:
             "d_codes": torch.empty((self.cap, self.d), dtype=torch.int16, device="cuda"),
             "d_out": torch.empty((self.cap, 2), dtype=torch.int64, device="cuda"),
         }
+        # one copy on the new stream now: its first launch sets the stream up (a
+        # few ms), which would otherwise fall on the first request it serves
+        with torch.cuda.stream(h["stream"]):
+            h["d_out"][:1].copy_(h["h_out"][:1], non_blocking=True)
+        h["stream"].synchronize()
+        return h
 
     def staging(self, h) -> np.ndarray:
         return h["h_codes"].numpy().view(np.uint16)
@@ -90,11 +96,19 @@ class Server:
     n_slots          concurrent micro-batches (one HIP stream each)
     max_batch_flows  flows per micro-batch (a larger request is rejected)
     mem_budget_bytes bytes of flows in flight (codes + results); 0 = what the slots hold
+    freeze_gc        move every object that exists when the server starts out of the
+                     cyclic collector's scans (gc.freeze, process-wide): a full
+                     collection otherwise walks the whole process -- torch included --
+                     and stalls the dispatcher for tens of ms at a time
     """
 
     def __init__(self, model: Optional[ig.Model], n_slots: int = 4, max_batch_flows: int = 16384,
-                 mem_budget_bytes: int = 0, d: Optional[int] = None, executor=None):
+                 mem_budget_bytes: int = 0, d: Optional[int] = None, executor=None, freeze_gc: bool = True):
+        import gc
         import sys
+        if freeze_gc:
+            gc.collect()
+            gc.freeze()
         # the dispatcher shares the interpreter with the callers: hand the lock over often
         if sys.getswitchinterval() > 0.0005:
             sys.setswitchinterval(0.0005)
