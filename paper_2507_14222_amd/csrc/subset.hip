@@ -1197,17 +1197,24 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
         slots = xcd_slots(kern, SC_NT);
         slot_cache[m.KO - 1][m.spare ? 1 : 0].store(slots, std::memory_order_relaxed);
     }
-    // the last choice is kept: serving launches repeat the same shapes
-    thread_local uint64_t memo_key[3] = {0, 0, 0}, memo_r = 0;
+    // a few recent choices are kept per thread: serving batches cycle through a small set of
+    // flow-block counts over one pattern set, and the search below is up to 4,096 steps
+    constexpr int kMemo = 16;
+    thread_local uint64_t memo_key[kMemo][3] = {}, memo_r[kMemo] = {};
+    thread_local int memo_next = 0;
     // the int32 weighting sums stay exact: at most 2^18 tiles x 32 rows x 127 per range
     const uint64_t rmin = (tiles + 8 * (1ull << 18) - 1) / (8 * (1ull << 18));
     uint64_t rmax = (tiles + 7) / 8;
     if (rmax > 4096) rmax = 4096;
     if (rmax < rmin) rmax = rmin;
-    uint64_t best_r = rmin;
-    if (memo_r && memo_key[0] == tiles && memo_key[1] == a.fblocks && memo_key[2] == slots) {
-        best_r = memo_r;
-    } else {
+    uint64_t best_r = 0;
+    for (int i = 0; i < kMemo; ++i)
+        if (memo_r[i] && memo_key[i][0] == tiles && memo_key[i][1] == a.fblocks && memo_key[i][2] == slots) {
+            best_r = memo_r[i];
+            break;
+        }
+    if (!best_r) {
+        best_r = rmin;
         double best = -1.0;
         for (uint64_t r = rmin; r <= rmax; ++r) {
             const uint64_t rounds = (r * a.fblocks + slots - 1) / slots;
@@ -1217,10 +1224,11 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
                 best_r = r;
             }
         }
-        memo_key[0] = tiles;
-        memo_key[1] = a.fblocks;
-        memo_key[2] = slots;
-        memo_r = best_r;
+        memo_key[memo_next][0] = tiles;
+        memo_key[memo_next][1] = a.fblocks;
+        memo_key[memo_next][2] = slots;
+        memo_r[memo_next] = best_r;
+        memo_next = (memo_next + 1) % kMemo;
     }
     IG_REQUIRE(8 * best_r * a.fblocks < (1ull << 31), IG_E_UNSUPPORTED, "too many flows for one scoring launch");
     a.ranges = (uint32_t)(8 * best_r);
