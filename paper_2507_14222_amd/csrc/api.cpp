@@ -53,7 +53,10 @@ ScratchCache &cache() {
     static ScratchCache *c = new ScratchCache();   // never destroyed: frees may run at exit
     return *c;
 }
-constexpr size_t kCacheCap = 32ull << 30;   // cached free bytes per device
+#ifndef IG_SCRATCH_CACHE_GB
+#define IG_SCRATCH_CACHE_GB 32
+#endif
+constexpr size_t kCacheCap = (size_t)IG_SCRATCH_CACHE_GB << 30;   // cached free bytes per device
 
 size_t round_bytes(size_t b) {
     if (b <= 4096) return 4096;
@@ -75,6 +78,17 @@ void release_cached(ScratchCache &c, int dev, size_t keep) {
         c.cached_bytes[dev] -= b.bytes;
         c.free_blocks.erase(c.free_blocks.begin() + (ptrdiff_t)i);
     }
+}
+// empty the current device's cache (after a failed allocation outside it)
+void release_all_cached() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return;
+    }
+    ScratchCache &c = cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    release_cached(c, dev, 0);
 }
 }  // namespace
 
@@ -196,6 +210,12 @@ static T *dev_alloc(size_t count) {
     void *p = nullptr;
     if (count == 0) count = 1;
     hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess || !p) {
+        // the scratch cache may hold the memory: hand it back and try once more
+        (void)hipGetLastError();
+        release_all_cached();
+        e = hipMalloc(&p, count * sizeof(T));
+    }
     if (e != hipSuccess || !p) {
         (void)hipGetLastError();
         throw Error(IG_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
