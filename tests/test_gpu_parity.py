@@ -414,6 +414,58 @@ def test_factored_patterns_without_tokens():
     assert np.array_equal(A[~bad], oA) and np.array_equal(N[~bad], oN)
 
 
+def _boundary_codes(rng, nb, n):
+    """Codes that reach each feature's extreme bin indices: 0, nb - 1, every
+    all-ones index 2^k - 1 below nb and its neighbours, plus a few random bins,
+    so the bin popcounts span 0 up to ceil(log2 nb)."""
+    cols = []
+    for b in nb:
+        b = int(b)
+        vals = {0, b - 1}
+        k = 1
+        while (1 << k) - 1 < b:
+            vals.update(v for v in ((1 << k) - 1, (1 << k) - 2, 1 << k) if 0 <= v < b)
+            k += 1
+        vals.update(int(v) for v in rng.integers(0, b, 3))
+        vals = np.array(sorted(vals))
+        cols.append(vals[rng.integers(0, len(vals), n)])
+    return np.stack(cols, 1).astype(np.uint16)
+
+
+@pytest.mark.parametrize("nb,n", [
+    ([2, 3, 9, 16, 17, 33, 65, 513], 90),   # 1 to 4 bit tokens with one presence token, 5 to 10 with two
+    ([1024], 120),                           # bin 1023: 10 bits set, presence parts 6 + 4
+])
+def test_factored_bin_boundaries(nb, n):
+    """Features whose bin counts sit at the factored encoding's boundaries, with
+    bins of every popcount up to the feature's bit count: model and scores on the
+    matrix cores against the oracle, including flows one bit away from a pattern."""
+    nb = np.array(nb, np.uint16)
+    say("factored bin boundaries", list(nb))
+    rng = np.random.default_rng(int(nb.sum()))
+    codes = _boundary_codes(rng, nb, n)
+    labels = (rng.random(n) < 0.5).astype(np.uint8)
+    om = oracle.fit(codes, labels, nb)
+    m = ig.fit(codes, labels, nb, kernels="mfma")
+    info = m.info()
+    assert info.flags & ig.IG_MODEL_FACTORED and m.score_on_matrix_cores
+    assert_same_model(m, om, om.K)
+    st = m.stats()
+    for key in ("pairs", "distinct", "coherent", "n_class"):
+        assert list(getattr(st, key)) == om.stats[key], key
+    # the matrix cores test every distinct candidate against every other-class record
+    assert list(st.tests) == [om.stats["distinct"][c] * om.stats["n_class"][1 - c] for c in (0, 1)]
+    flows = _boundary_codes(rng, nb, 300)
+    near = flows.copy()   # one bin bit flipped where the result stays a valid bin
+    for j, b in enumerate(nb):
+        flip = near[:, j] ^ (1 << rng.integers(0, max(int(b - 1).bit_length(), 1), len(near)))
+        near[:, j] = np.where(flip < b, flip, near[:, j])
+    flows = np.concatenate([flows, near, codes])
+    A, N = gpu_scores(m, flows)
+    oA, oN = oracle.score(om, flows, nb)
+    assert np.array_equal(A, oA) and np.array_equal(N, oN)
+
+
 def test_matrix_core_coherence_15k_digest():
     g = json.load(open(os.path.join(GOLD, "mixture41_15k.json")))
     w = synth.make_15k()
