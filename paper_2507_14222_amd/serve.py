@@ -90,6 +90,40 @@ class GpuExecutor:
         return h["h_out"][:n].numpy()
 
 
+# Interpreter settings held while any server runs, restored when the last one closes.
+_settings_lock = threading.Lock()
+_settings = {"servers": 0, "freezers": 0, "switch": None}
+
+
+def _hold_settings(freeze: bool) -> None:
+    import gc
+    import sys
+    with _settings_lock:
+        if freeze:
+            gc.collect()
+            gc.freeze()
+            _settings["freezers"] += 1
+        if _settings["servers"] == 0:
+            # the dispatcher shares the interpreter with the callers: hand the lock over often
+            _settings["switch"] = sys.getswitchinterval()
+            if _settings["switch"] > 0.0005:
+                sys.setswitchinterval(0.0005)
+        _settings["servers"] += 1
+
+
+def _release_settings(freeze: bool) -> None:
+    import gc
+    import sys
+    with _settings_lock:
+        if freeze:
+            _settings["freezers"] -= 1
+            if _settings["freezers"] == 0:
+                gc.unfreeze()
+        _settings["servers"] -= 1
+        if _settings["servers"] == 0:
+            sys.setswitchinterval(_settings["switch"])
+
+
 class Server:
     """Serve scoring requests against ``model`` with continuous batching.
 
@@ -99,19 +133,23 @@ class Server:
     freeze_gc        move every object that exists when the server starts out of the
                      cyclic collector's scans (gc.freeze, process-wide): a full
                      collection otherwise walks the whole process -- torch included --
-                     and stalls the dispatcher for tens of ms at a time
+                     and stalls the dispatcher for tens of ms at a time; undone
+                     (gc.unfreeze) when the last server that froze closes
     """
 
     def __init__(self, model: Optional[ig.Model], n_slots: int = 4, max_batch_flows: int = 16384,
                  mem_budget_bytes: int = 0, d: Optional[int] = None, executor=None, freeze_gc: bool = True):
-        import gc
-        import sys
-        if freeze_gc:
-            gc.collect()
-            gc.freeze()
-        # the dispatcher shares the interpreter with the callers: hand the lock over often
-        if sys.getswitchinterval() > 0.0005:
-            sys.setswitchinterval(0.0005)
+        _hold_settings(freeze_gc)
+        self._freeze = freeze_gc
+        self._held = True
+        try:
+            self._setup(model, n_slots, max_batch_flows, mem_budget_bytes, d, executor)
+        except BaseException:
+            self._held = False
+            _release_settings(freeze_gc)
+            raise
+
+    def _setup(self, model, n_slots, max_batch_flows, mem_budget_bytes, d, executor) -> None:
         if model is not None:
             info = model.info()
             if info.d == 0:
@@ -162,6 +200,9 @@ class Server:
             self._stop = True
             self._cv.notify()
         self._thread.join()
+        if self._held:
+            self._held = False
+            _release_settings(self._freeze)
         if self.error is not None:
             raise RuntimeError(f"server failed: {self.error}")
 

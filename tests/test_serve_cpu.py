@@ -129,3 +129,26 @@ def test_concurrent_submitters():
     for k in range(4):
         for r, o in zip(per_thread[k], results[k]):
             assert np.array_equal(o, _expected(r))
+
+
+def test_process_settings_are_restored_by_the_last_server():
+    """The collector freeze and the switch interval are held while any server runs
+    and restored when the last one closes, also when a constructor fails."""
+    import gc
+    import sys
+    if gc.get_freeze_count():
+        pytest.skip("objects were frozen before this test")
+    switch = sys.getswitchinterval()
+    a = Server(None, n_slots=1, max_batch_flows=8, d=2, executor=FakeExecutor(8, 2))
+    b = Server(None, n_slots=1, max_batch_flows=8, d=2, executor=FakeExecutor(8, 2), freeze_gc=False)
+    c = Server(None, n_slots=1, max_batch_flows=8, d=2, executor=FakeExecutor(8, 2))
+    assert gc.get_freeze_count() > 0 and sys.getswitchinterval() <= 0.0005
+    with pytest.raises(ValueError):
+        Server(None, n_slots=1, max_batch_flows=8, executor=FakeExecutor(8, 2))   # no d
+    a.close()
+    c.close()
+    assert gc.get_freeze_count() == 0          # the last freezing server is gone
+    assert sys.getswitchinterval() <= 0.0005   # b still runs
+    assert np.array_equal(b.submit(np.ones((2, 2), np.uint16)).result(timeout=10), _expected(np.ones((2, 2))))
+    b.close()
+    assert sys.getswitchinterval() == switch
