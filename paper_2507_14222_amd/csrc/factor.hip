@@ -59,6 +59,28 @@ __global__ __launch_bounds__(256) void k_operand_rows(const uint64_t *__restrict
     }
 }
 
+// One-hot operand rows (no factoring table): one lane per output word, so the
+// loads of a row's words and the stores are contiguous across the wave.
+__global__ __launch_bounds__(256) void k_operand_rows_onehot(const uint64_t *__restrict__ X, uint32_t n,
+                                                            const uint32_t *__restrict__ ids,
+                                                            const uint64_t *__restrict__ W, uint32_t KS, size_t m,
+                                                            uint64_t flip, uint64_t *__restrict__ out) {
+    const size_t total = m * KS;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        uint64_t v;
+        if (ids) {
+            const size_t e = t / KS;
+            const uint32_t k = (uint32_t)(t - e * KS);
+            uint32_t i, j;
+            decode_pair(ids[e], n, i, j);
+            v = X[(size_t)i * KS + k] & X[(size_t)j * KS + k];
+        } else {
+            v = W[t];
+        }
+        out[t] = v ^ flip;
+    }
+}
+
 // Factoring for rows of at most 16 one-hot words, masks in LDS: each lane loads
 // its row once into registers and walks the pieces of each word.  The piece table
 // is read one 16-byte piece at a time at wave-uniform addresses (scalar loads), every step is
@@ -238,6 +260,9 @@ void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, con
             default: throw Error(IG_E_UNSUPPORTED, "storage width without a factoring kernel");
         }
 #undef IG_OR_K
+    } else if (!fv.KF) {
+        const dim3 ogrid((unsigned)std::min<size_t>((m * KS + 255) / 256, (size_t)device_cus() * 16));
+        hipLaunchKernelGGL(k_operand_rows_onehot, ogrid, dim3(256), 0, s, X, n, ids, W, KS, m, flip, out);
     } else {
         hipLaunchKernelGGL(k_operand_rows, grid, dim3(256), 0, s, X, n, ids, W, KS, m, fv, KO, flip, out);
     }
