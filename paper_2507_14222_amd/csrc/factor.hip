@@ -81,14 +81,16 @@ __global__ __launch_bounds__(256) void k_operand_rows_onehot(const uint64_t *__r
     }
 }
 
-// Factoring for rows of at most 16 one-hot words, masks in LDS: each lane loads
+// Factoring for rows of at most 40 one-hot words, masks in LDS: each lane loads
 // its row once into registers and walks the pieces of each word.  The piece table
 // is read one 16-byte piece at a time at wave-uniform addresses (scalar loads), every step is
 // branch-free (a piece with no bit set ORs zeros), and the output word is a
 // wave-uniform register index.  Workgroups stride over the rows, so each stages
 // the masks once.
-// At most 2 masks per one-hot token, and the kernel takes at most 16 x 64 tokens.
+// At most 2 masks per one-hot token: 16 x 64 tokens fill the narrow widths' table.
 constexpr uint32_t kLdsMasks = 2048;   // u64 masks staged in LDS (16 KB)
+// wider storage (20 to 40 words) stages its whole mask table: 2 masks per token at most
+__host__ __device__ constexpr uint32_t lds_masks(int KS) { return KS <= 16 ? kLdsMasks : 2u * 64u * (uint32_t)KS; }
 static_assert(sizeof(FacPiece) == 16 && offsetof(FacPiece, base) == 4 && offsetof(FacPiece, mask) == 8,
               "the kernel reads a piece as four dwords");
 
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
                                                          const uint32_t *__restrict__ ids,
                                                          const uint64_t *__restrict__ W, size_t m, FactorView fv,
                                                          uint32_t KO, uint64_t flip, uint64_t *__restrict__ out) {
-    __shared__ uint64_t smask[kLdsMasks + 1];   // + 1: the second word read next to the last entry
+    __shared__ uint64_t smask[lds_masks(KS) + 1];   // + 1: the second word read next to the last entry
     __shared__ uint4 spiece[LPIECES ? kLdsPieces : 1];
     for (uint32_t t = threadIdx.x; t <= fv.nmask; t += blockDim.x) smask[t] = t < fv.nmask ? fv.mask[t] : 0ull;
     const uint4 *pw = reinterpret_cast<const uint4 *>(fv.piece);
@@ -242,7 +244,8 @@ void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, con
     IG_REQUIRE(!fv.KF || fv.nwords == KS, IG_E_DEVICE, "factoring table built for another storage width");
     const dim3 grid((unsigned)((m + 255) / 256));
     const uint64_t flip = complement ? ~0ull : 0ull;
-    if (fv.KF && KS <= 16 && KO <= 16 && fv.nmask <= kLdsMasks) {
+    const bool reg_width = KS <= 16 || KS == 20 || KS == 24 || KS == 28 || KS == 32 || KS == 40;
+    if (fv.KF && reg_width && KO <= 16 && fv.nmask <= lds_masks((int)KS)) {
         // strided over the rows: a few workgroups per CU, each staging the masks once
         const dim3 sgrid((unsigned)std::min<size_t>((m + 255) / 256, (size_t)device_cus() * 8));
 #define IG_OR_K(V)                                                                                             \
@@ -254,9 +257,10 @@ void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, con
             hipLaunchKernelGGL((k_operand_rows_reg<V, false>), sgrid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, \
                                flip, out);                                                                     \
         break;
-        switch (KS) {   // the compiled storage widths up to 16 words
+        switch (KS) {   // the compiled storage widths up to 40 words
             IG_OR_K(1) IG_OR_K(2) IG_OR_K(3) IG_OR_K(4) IG_OR_K(5) IG_OR_K(6) IG_OR_K(7) IG_OR_K(8)
-            IG_OR_K(10) IG_OR_K(12) IG_OR_K(14) IG_OR_K(16)
+            IG_OR_K(10) IG_OR_K(12) IG_OR_K(14) IG_OR_K(16) IG_OR_K(20) IG_OR_K(24) IG_OR_K(28) IG_OR_K(32)
+            IG_OR_K(40)
             default: throw Error(IG_E_UNSUPPORTED, "storage width without a factoring kernel");
         }
 #undef IG_OR_K
