@@ -256,13 +256,25 @@ __global__ void k_adjacent_equal(const uint64_t *__restrict__ W, size_t m, uint3
     if (eq) atomicAdd(cnt, 1u);
 }
 
-__global__ void k_weights(const uint64_t *__restrict__ W, const uint32_t *__restrict__ f, size_t m, uint32_t KS,
-                          int64_t *__restrict__ S) {
-    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    uint32_t len = 0;
-    for (uint32_t k = 0; k < KS; ++k) len += (uint32_t)__popcll(W[e * KS + k]);
-    S[e] = (int64_t)f[e] * (int64_t)len * (int64_t)len;
+// S = f |b|^2 for 256 rows per workgroup: the rows' words are read contiguously
+// across the workgroup (a row is KS words, so one lane per row would stride),
+// their popcounts kept in LDS, then each lane sums its own row.
+constexpr uint32_t kWeightRows = 256;
+__global__ __launch_bounds__(256) void k_weights(const uint64_t *__restrict__ W, const uint32_t *__restrict__ f,
+                                                 size_t m, uint32_t KS, int64_t *__restrict__ S) {
+    __shared__ uint8_t pc[kWeightRows * 64];   // KS <= 64
+    const size_t row0 = (size_t)blockIdx.x * kWeightRows;
+    const uint32_t rows = (uint32_t)min((size_t)kWeightRows, m - row0);
+    const uint32_t words = rows * KS;
+    const uint64_t *base = W + row0 * KS;
+    for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) pc[t] = (uint8_t)__popcll(base[t]);
+    __syncthreads();
+    if (threadIdx.x < rows) {
+        uint32_t len = 0;
+        for (uint32_t k = 0; k < KS; ++k) len += pc[threadIdx.x * KS + k];
+        const size_t e = row0 + threadIdx.x;
+        S[e] = (int64_t)f[e] * (int64_t)len * (int64_t)len;
+    }
 }
 
 static dim3 blocks_for(size_t n, unsigned bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
@@ -369,7 +381,8 @@ void launch_adjacent_equal(const uint64_t *W, size_t m, uint32_t KS, uint32_t *d
 
 void launch_weights(const uint64_t *W, const uint32_t *f, size_t m, uint32_t KS, int64_t *S, hipStream_t s) {
     if (!m) return;
-    hipLaunchKernelGGL(k_weights, blocks_for(m), dim3(256), 0, s, W, f, m, KS, S);
+    IG_REQUIRE(KS >= 1 && KS <= 64, IG_E_UNSUPPORTED, "pattern rows wider than 64 words");
+    hipLaunchKernelGGL(k_weights, blocks_for(m, kWeightRows), dim3(256), 0, s, W, f, m, KS, S);
     IG_HIP(hipGetLastError());
 }
 
