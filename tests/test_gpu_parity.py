@@ -362,6 +362,9 @@ MFMA_RUNS = ([(c, k) for c in MFMA_CASES for k in ("mfma", "mfma_onehot")] +
 PADDED_CASES = [(32, 60, 32, 14, 18, 0.5), (30, 60, 41, 14, 18, 0.5), (30, 60, 50, 14, 18, 0.5),
                 (32, 60, 56, 14, 18, 0.5)]
 MFMA_RUNS += [(c, k) for c in PADDED_CASES for k in ("mfma", "mfma_onehot")]
+# one-hot storage of 20 (K = 17, padded), 24 and 28 words, factored into 6 to 9 words
+WIDE_STORAGE_CASES = [(35, 80, 70, 14, 16, 0.5), (33, 80, 80, 16, 19, 0.5), (34, 80, 80, 20, 23, 0.5)]
+MFMA_RUNS += [(c, "mfma") for c in WIDE_STORAGE_CASES]
 
 
 @pytest.mark.parametrize("case,kernels", MFMA_RUNS, ids=[f"s{c[0]}-d{c[2]}-{k}" for c, k in MFMA_RUNS])
