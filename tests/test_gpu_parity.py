@@ -264,6 +264,30 @@ def test_scores_do_not_depend_on_batching():
         at += k
 
 
+def test_scoring_shapes_beyond_the_launch_cache():
+    """Scoring launches of 20 flow-block counts, then the same in reverse: the
+    launcher keeps its last 16 range choices, so the sequence both evicts and
+    reuses them.  Every slice equals the matching rows of one launch over all
+    flows, and a sample of those equals the oracle."""
+    p = synth.make_random_problem(11, 170, 41, bins_lo=10, bins_hi=14, attack_frac=0.55)
+    say("scoring shapes", p.codes.shape)
+    m = ig.fit(p.codes, p.labels, p.nbins, kernels="mfma")
+    assert m.score_on_matrix_cores
+    rng = np.random.default_rng(5)
+    sizes = [256 * k - 7 * k for k in range(1, 21)]   # k flow blocks of 256 flows
+    flows = np.stack([rng.integers(0, b, sum(sizes)) for b in p.nbins], 1).astype(np.uint16)
+    flows[: p.codes.shape[0]] = p.codes             # records score non-zero
+    A, N = gpu_scores(m, flows)
+    pick = np.concatenate([np.arange(p.codes.shape[0]), rng.choice(flows.shape[0], 400, replace=False)])
+    om = oracle.fit(p.codes, p.labels, p.nbins)
+    oA, oN = oracle.score(om, flows[pick], p.nbins)
+    assert np.array_equal(A[pick], oA) and np.array_equal(N[pick], oN)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    for k in list(range(20)) + list(range(19, -1, -1)):
+        a, n = gpu_scores(m, flows[starts[k]:starts[k + 1]])
+        assert np.array_equal(a, A[starts[k]:starts[k + 1]]) and np.array_equal(n, N[starts[k]:starts[k + 1]]), k
+
+
 # ----------------------------------------------------- full-size workloads
 def _model_digest(m):
     h = hashlib.sha256()
