@@ -17,6 +17,7 @@ import numpy as np
 from . import build_oracle
 
 _lib = None
+_lib_path = None   # another build of ig_oracle.c to load instead of build_oracle.LIB
 
 
 class _Model(C.Structure):
@@ -34,9 +35,7 @@ class _Model(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        path = build_oracle.LIB
-        if not os.path.exists(path):
-            build_oracle.build()
+        path = _lib_path or build_oracle.build(force=False)   # rebuilt when the source is newer
         L = C.CDLL(path)
         p = C.c_void_p
         L.igo_pack.argtypes = [p, C.c_uint64, C.c_uint32, p, C.c_uint32, p]
@@ -55,6 +54,14 @@ def lib():
         L.igo_set_threads.restype = None
         _lib = L
     return _lib
+
+
+def use_library(path: Optional[str]) -> None:
+    """Load the oracle from another build of the same source (the benchmark's
+    host-tuned copy); None returns to the default build."""
+    global _lib, _lib_path
+    _lib = None
+    _lib_path = path
 
 
 def _ptr(a: np.ndarray):
@@ -142,6 +149,8 @@ def fit(codes, labels, nbins) -> OracleModel:
 
 
 def model_from_patterns(codes0, f0, codes1, f1, nbins) -> OracleModel:
+    """A model from given pattern code rows (0xFFFF = feature absent) and supports:
+    Eq. 5 packing and Eq. 2 weights, rows in the order given."""
     codes0 = _c(codes0, np.uint16); codes1 = _c(codes1, np.uint16)
     f0 = _c(f0, np.uint32); f1 = _c(f1, np.uint32)
     nbins = _c(nbins, np.uint16)

@@ -329,8 +329,9 @@ int igo_score(const igo_model *m, const uint16_t *codes, uint64_t n_flows, uint3
 }
 
 /* Model built from given pattern code rows and supports (for scoring a given
- * pattern set): pack, sort, and weight each pattern by Eq. 2 with the given f.
- * Patterns must be distinct and non-empty. */
+ * pattern set): pack each pattern (Eq. 5) and weight it by Eq. 2 with the given
+ * f.  Rows stay in the order given (scores do not depend on it).  Patterns must
+ * be distinct and non-empty. */
 int igo_model_from_patterns(const uint16_t *codes0, const uint32_t *f0, uint64_t m0,
                             const uint16_t *codes1, const uint32_t *f1, uint64_t m1,
                             uint32_t d, const uint16_t *nbins, igo_model *m)
@@ -459,7 +460,8 @@ int igo_pair_facts(const uint16_t *codes, uint64_t n, uint32_t d, const uint8_t 
             for (int64_t q = 0; q < (int64_t)n_pairs; ++q) {
                 uint64_t *b = out_words + (uint64_t)q * K;
                 for (uint32_t k = 0; k < K; ++k) b[k] = Xc[pi[q] * K + k] & Xc[pj[q] * K + k];
-                uint64_t t = is_empty(b, K) ? 1 : first_cover(b, Xo, ns[1 - cls], K);
+                /* the empty set lies inside the first other-class record, if any */
+                uint64_t t = is_empty(b, K) ? (ns[1 - cls] ? 1 : 0) : first_cover(b, Xo, ns[1 - cls], K);
                 out_coherent[q] = (uint8_t)(t == 0 && !is_empty(b, K));
                 out_t[q] = t ? t : ns[1 - cls];
                 out_f[q] = support(b, Xc, ns[cls], K);

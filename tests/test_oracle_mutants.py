@@ -1,8 +1,8 @@
 """Plant plausible mistakes in copies of the C oracle and check the pins catch each.
 
 Every mutant is a one-place edit of oracle/ig_oracle.c compiled into a temporary
-library; the pins of test_oracle_pins (worked example, exhaustive enumeration)
-must fail on it.  This runs on the CPU only.
+library; the pins of test_oracle_pins (worked example, exhaustive enumeration,
+patterns given as code rows, t(b) by scanning) must fail on it.  This runs on the CPU only.
 """
 import os
 import subprocess
@@ -44,6 +44,16 @@ MUTANTS = {
                               "for (uint64_t j = i + 1; j < n && j < i + 2; ++j) {\n            uint64_t *b = rows + m * K;"),
     # first-cover position counted from zero
     "t_off_by_one": ("if (subset(b, Xo + t * K, K)) return t + 1;", "if (subset(b, Xo + t * K, K)) return t + 2;"),
+    # Eq. 2 with |b| instead of |b|^2 for patterns given as code rows
+    "from_patterns_not_squared": ("m->S[c][p] = (int64_t)fs[c][p] * (int64_t)len * (int64_t)len;",
+                                  "m->S[c][p] = (int64_t)fs[c][p] * (int64_t)len;"),
+    # |b| of given patterns without their last word
+    "from_patterns_last_word_dropped": ("uint32_t len = popcount_row(m->words[c] + p * K, K);",
+                                        "uint32_t len = popcount_row(m->words[c] + p * K, K - 1);"),
+    # the supports of given patterns taken from the other class's list
+    "from_patterns_f_swapped": ("m->f[c][p] = fs[c][p];", "m->f[c][p] = fs[1 - c][p < ms[1 - c] ? p : 0];"),
+    # t(b) of a coherent pair counted as zero instead of every other-class record
+    "pair_facts_t_coherent_zero": ("out_t[q] = t ? t : ns[1 - cls];", "out_t[q] = t;"),
 }
 
 
@@ -55,6 +65,12 @@ def _run_pins():
             pins.test_exhaustive_enumeration(s)
         pins.test_pack_bit_order()
         pins.test_one_and_two_records()
+        pins.test_model_from_patterns_worked_example()
+        pins.test_model_from_patterns_weights_by_hand()
+        for s in range(4):
+            pins.test_model_from_patterns_reproduces_a_fit(s)
+        for s in range(6):
+            pins.test_pair_facts_t_by_scanning(s)
     except (AssertionError, oracle.OracleError):
         return False
     return True
@@ -79,14 +95,10 @@ def test_pins_catch_mutant(name, src_text, tmp_path):
     c_path.write_text(mut)
     subprocess.run(["gcc", "-O1", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", str(so_path),
                     str(c_path)], check=True)
-    saved = oracle._lib
     try:
-        oracle._lib = None
-        path_saved = oracle.build_oracle.LIB
-        oracle.build_oracle.LIB = str(so_path)
+        oracle.use_library(str(so_path))
         oracle.lib()
         caught = not _run_pins()
     finally:
-        oracle.build_oracle.LIB = path_saved
-        oracle._lib = saved
+        oracle.use_library(None)
     assert caught, f"mutant {name} passed every pin"

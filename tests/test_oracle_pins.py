@@ -262,3 +262,117 @@ def test_pair_facts_and_direct_score():
     A, N = oracle.score(m, flows, p.nbins)
     A2, N2 = oracle.score_direct(p.codes, p.labels, p.nbins, flows)
     assert A.tolist() == A2.tolist() and N.tolist() == N2.tolist()
+
+
+# --------------------------------------------- patterns given as code rows
+def _words_to_codes(W, nbins):
+    """Code rows of one-token-per-feature bitsets (the inverse of Eq. 5, written
+    here): the set bit of a feature's block gives its bin, no bit gives 0xFFFF."""
+    nbins = np.asarray(nbins, np.int64)
+    off = np.concatenate([[0], np.cumsum(nbins)])
+    out = np.full((W.shape[0], nbins.size), 0xFFFF, np.uint16)
+    for r in range(W.shape[0]):
+        x = 0
+        for k in range(W.shape[1]):
+            x |= int(W[r, k]) << (64 * k)
+        for f in range(nbins.size):
+            block = (x >> int(off[f])) & ((1 << int(nbins[f])) - 1)
+            if block:
+                assert block & (block - 1) == 0, "more than one bin of a feature"
+                out[r, f] = block.bit_length() - 1
+    return out
+
+
+def test_model_from_patterns_worked_example():
+    # Eq. 2 on the hand-worked patterns: the given supports, S = f |b|^2 by hand
+    g = json.load(open(GOLD))
+    nbins = np.array(g["nbins"], np.uint16)
+    rows = {c: np.array([[int(h, 16)] for h, _, _ in g["patterns"][str(c)]], np.uint64) for c in (0, 1)}
+    f = {c: np.array([ff for _, ff, _ in g["patterns"][str(c)]], np.uint32) for c in (0, 1)}
+    S = {c: [SS for _, _, SS in g["patterns"][str(c)]] for c in (0, 1)}
+    codes = {c: _words_to_codes(rows[c], nbins) for c in (0, 1)}
+    m = oracle.model_from_patterns(codes[0], f[0], codes[1], f[1], nbins)
+    for c in (0, 1):
+        assert m.patterns[c].tolist() == rows[c].tolist()
+        assert m.f[c].tolist() == f[c].tolist()
+        assert m.S[c].tolist() == S[c]
+    A, N = oracle.score(m, np.array(g["flows"], np.uint16), nbins)
+    assert A.tolist() == g["A"] and N.tolist() == g["N"]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_model_from_patterns_reproduces_a_fit(seed):
+    # the patterns of a fit, given back as code rows with their supports, make the
+    # same words, f and S (in the order given, here shuffled) and the same scores
+    p = synth.make_random_problem(300 + seed, 45, 6 + 3 * seed, bins_lo=3, bins_hi=9 + 8 * seed)
+    om = oracle.fit(p.codes, p.labels, p.nbins)
+    rng = np.random.default_rng(seed)
+    perm = [rng.permutation(om.patterns[c].shape[0]) for c in (0, 1)]
+    codes = [_words_to_codes(om.patterns[c][perm[c]], p.nbins) for c in (0, 1)]
+    m = oracle.model_from_patterns(codes[0], om.f[0][perm[0]], codes[1], om.f[1][perm[1]], p.nbins)
+    for c in (0, 1):
+        assert np.array_equal(m.patterns[c], om.patterns[c][perm[c]])
+        assert np.array_equal(m.f[c], om.f[c][perm[c]])
+        assert np.array_equal(m.S[c], om.S[c][perm[c]])
+    flows = np.stack([rng.integers(0, nb, size=40) for nb in p.nbins], axis=1).astype(np.uint16)
+    A, N = oracle.score(m, flows, p.nbins)
+    A2, N2 = oracle.score(om, flows, p.nbins)
+    assert A.tolist() == A2.tolist() and N.tolist() == N2.tolist()
+
+
+def test_model_from_patterns_weights_by_hand():
+    # one pattern of 3 tokens over two words (L = 70 + 30): S = f * 9 for any f
+    nbins = np.array([70, 30], np.uint16)
+    codes = np.array([[0xFFFF, 5], [69, 0xFFFF], [3, 29]], np.uint16)
+    f = np.array([7, 1, 3], np.uint32)
+    m = oracle.model_from_patterns(codes, f, codes[:0], f[:0], nbins)
+    assert m.patterns[0].tolist() == [[0, 1 << 11], [0, 1 << 5], [1 << 3, 1 << 35]]
+    assert m.S[0].tolist() == [7 * 1, 1 * 1, 3 * 4]
+    assert m.patterns[1].shape == (0, 2)
+
+
+# ----------------------------------------------------- t(b) by scanning
+def _bits(codes, nbins):
+    off = np.concatenate([[0], np.cumsum(np.asarray(nbins, np.int64))[:-1]])
+    out = []
+    for row in codes:
+        x = 0
+        for f, c in enumerate(row):
+            x |= 1 << int(off[f] + c)
+        out.append(x)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pair_facts_t_by_scanning(seed):
+    # t(b): other-class records examined in input order up to and including the
+    # first that contains b, all of them when none does (Eq. 3's scan); checked on
+    # every pair i <= j of both classes, and summed over the distinct candidates it
+    # is the fit's test count
+    rng = np.random.default_rng(500 + seed)
+    d = int(rng.integers(2, 6))
+    nbins = rng.integers(2, 5, size=d).astype(np.uint16)
+    n = int(rng.integers(3, 30))
+    codes = np.stack([rng.integers(0, nb, size=n) for nb in nbins], axis=1).astype(np.uint16)
+    labels = (rng.random(n) < 0.5).astype(np.uint8)
+    if seed == 5:
+        labels[:] = 0          # no other class: t = 0 and every candidate is coherent
+    x = _bits(codes, nbins)
+    om = oracle.fit(codes, labels, nbins)
+    for c in (0, 1):
+        Xc = [v for v, lab in zip(x, labels) if lab == c]
+        Xo = [v for v, lab in zip(x, labels) if lab != c]
+        if not Xc:
+            continue
+        pi, pj = zip(*[(i, j) for i in range(len(Xc)) for j in range(i, len(Xc))])
+        words, coh, f, t = oracle.pair_facts(codes, labels, nbins, c, np.array(pi), np.array(pj))
+        seen = {}
+        for q, (i, j) in enumerate(zip(pi, pj)):
+            b = Xc[i] & Xc[j]
+            exp_t = next((r + 1 for r, o in enumerate(Xo) if b & o == b), len(Xo))
+            assert int(t[q]) == exp_t, (c, i, j)
+            assert bool(coh[q]) == (b != 0 and all(b & o != b for o in Xo))
+            assert int(f[q]) == sum(1 for v in Xc if b & v == b)
+            if b:
+                seen[b] = exp_t
+        assert sum(seen.values()) == om.stats["tests"][c]
