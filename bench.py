@@ -1,19 +1,31 @@
 """Benchmark of the IG hot path on one MI355X.
 
-One step = ig_fit of the 15k workload (41 features, L = 464, K = 8; ~10.5k
-training records) followed by ig_score of its ~4.5k held-out flows, with every
+One step = ig_fit of the 15k workload (41 features, L = 464, K = 8; 10,500
+training records) followed by ig_score of its 4,500 held-out flows, with every
 input already resident in HBM.  The reported throughput is subset tests per
 second: the tests the method has to make in one step --
 
   coherence  sum over distinct candidates of t(b) (records of the other class
-             examined up to and including the first that contains b)   Eq. 3
+             examined in input order up to and including the first that
+             contains b)                                               Eq. 3
   support    |P^c| * n_c for both classes                              Eq. 2
   scoring    (|P^0| + |P^1|) * n_flows                                 Eq. 4
 
-Also printed: the fit wall time at 15k and 148k, the roofline of the coherence
-kernel (integer VALU bound) and the CPU oracle timed on a bounded sample.
+The subset tests run as dense fp4 contractions on the matrix cores (exact:
+small integers accumulated in fp32; scoring also weights in int8 -> int32).
+Each contraction kernel's roofline is reported per launch: achieved = the
+method's operations of the launch (2 * tokens per test, tests counted as above)
+/ the launch's duration from HIP events on its stream, against the vendor's
+dense fp4 peak and the peak measured in the same run (ig_probe_mfma_fp4); the
+fraction of executed matrix-core operations (every (row, column) pair of the
+padded tiles) is given beside it.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu] [--no-148k]
+Also printed: the fit wall time at 15k and 148k (from device inputs, and from
+host arrays including the export of both sorted pattern sets), scoring wall
+time, served scoring, the 64-problem batched fit against 64 plain fits, and the
+CPU oracle built for this host and timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu] [--no-148k] [--no-serve] [--no-batch]
 """
 import argparse
 import json
@@ -72,21 +84,7 @@ def measure_batch():
         def __init__(self, c, l, nb):
             self.codes, self.labels, self.nbins = c, l, nb
 
-    def est_bytes(p):
-        n1 = int(p.labels.sum())
-        n0 = p.n - n1
-        K = tune.ig_storage_words((p.L + 63) // 64)
-        return (n0 * (n0 + 1) // 2 + n1 * (n1 + 1) // 2) * (K * 8 + 12)
-
-    slices, cur, acc = [], [], 0
-    for i, p in enumerate(probs):
-        b = est_bytes(p)
-        if cur and acc + b > 90e9:
-            slices.append(cur)
-            cur, acc = [], 0
-        cur.append(i)
-        acc += b
-    slices.append(cur)
+    slices = tune.slices_by_memory(probs)
     log("batch: %d problems in %d slices" % (len(probs), len(slices)))
     tests = 0
     dig_b, dig_s = {}, {}
@@ -193,6 +191,94 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def measured_peaks():
+    """fp4 matrix-core and HBM copy rates measured on this device (best of 3)."""
+    import torch
+
+    from paper_2507_14222_amd import ig
+
+    mf = max(ig.probe_mfma_fp4(20000)[0] for _ in range(3))
+    src = torch.empty(1 << 32, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    hbm = max(ig.probe_hbm_copy(src, dst)[0] for _ in range(3))
+    del src, dst
+    torch.cuda.synchronize()
+    return {"fp4_mfma_ops_per_s": mf, "hbm_copy_bytes_per_s": hbm,
+            "fp4_mfma_frac_of_vendor": mf / MFMA_FP4_PEAK_OPS, "hbm_frac_of_vendor": hbm / (HBM_PEAK_GBS * 1e9)}
+
+
+def fit_wall(codes, labels, nbins, d_codes, d_labels, reps=3):
+    """Median wall time of ig_fit alone (device inputs, returns with the model
+    complete) and of the whole fit from host arrays plus the export of both
+    sorted pattern sets to the host."""
+    import numpy as np
+    import torch
+
+    from paper_2507_14222_amd import ig
+
+    dev, host = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        m = ig.fit(d_codes, d_labels, nbins)
+        dev.append(time.perf_counter() - a)
+        del m
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        m = ig.fit(codes, labels, nbins)
+        m.export(0)
+        m.export(1)
+        host.append(time.perf_counter() - a)
+        del m
+    return float(np.median(dev)), float(np.median(host))
+
+
+def cpu_baseline(w, n_records, n_flows, n_records_1t):
+    """The oracle as it stands, compiled for this host (-O3 -march=native), timed
+    on a bounded sample of the 15k workload with all host threads, and on a
+    smaller sample with one thread; value in subset tests/s."""
+    import tempfile
+
+    import oracle
+    from oracle import build_oracle
+
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    tmp = tempfile.mkdtemp(prefix="igoracle")
+    oracle.use_library(build_oracle.build_native(tmp))
+
+    def run(ns, nf):
+        a = time.perf_counter()
+        om = oracle.fit(w.codes[:ns], w.labels[:ns], w.nbins)
+        oracle.score(om, w.test_codes[:nf], w.nbins)
+        dt = time.perf_counter() - a
+        tests = sum(om.stats["tests"]) + sum(p.shape[0] * n for p, n in zip(om.patterns, om.stats["n_class"])) \
+            + sum(p.shape[0] for p in om.patterns) * nf
+        return tests / dt, dt
+
+    threads = oracle.max_threads()
+    log("cpu oracle on", n_records, "records,", n_flows, "flows,", threads, "threads")
+    v, dt = run(n_records, n_flows)
+    oracle.set_threads(1)
+    log("cpu oracle on", n_records_1t, "records, 1 thread")
+    v1, dt1 = run(n_records_1t, n_flows // 3)
+    oracle.set_threads(threads)
+    oracle.use_library(None)
+    return {"value": v, "unit": "subset tests/s", "cores": threads, "kind": "oracle", "seconds": dt,
+            "sample": f"oracle fit of the first {n_records} training records of the 15k workload "
+                      f"+ scoring {n_flows} held-out flows",
+            "build": "gcc -O3 -march=native -fopenmp, built on this host", "cpu_model": model,
+            "one_thread": {"value": v1, "seconds": dt1,
+                           "sample": f"first {n_records_1t} training records + {n_flows // 3} flows"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,8 +287,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-148k", action="store_true", help="skip the 148k fit wall time")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-scoring measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched fit")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured-peak probes")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="offered load duration per rate")
-    ap.add_argument("--cpu-records", type=int, default=7000, help="training records in the oracle sample")
+    ap.add_argument("--cpu-records", type=int, default=8000, help="training records in the oracle sample")
     ap.add_argument("--batch", action="store_true",
                     help="only run the 64-problem workload: batched fit vs 64 plain fits")
     ap.add_argument("--copy-probe", action="store_true",
@@ -256,13 +344,10 @@ def main():
         torch.cuda.synchronize()
         log("warmup", i, "done")
     torch.cuda.synchronize()
-    fit_s, models = [], []
+    models = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        a = time.perf_counter()
-        m = step()
-        fit_s.append(time.perf_counter() - a)   # ig_fit returns once the model is complete
-        models.append(m)
+        models.append(step())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -271,7 +356,6 @@ def main():
     st = models[-1].stats()
     npat = models[-1].n_patterns()
     K = models[-1].K
-    L = int(w.L)
     n_flows = w.test_codes.shape[0]
     # the method's subset tests: sum of t(b) in input order (from one untimed fit on the
     # early-exit path), |P^c| * n_c support tests and |P| * n_flows scoring tests
@@ -282,61 +366,86 @@ def main():
     score_tests = (npat[0] + npat[1]) * n_flows
     tests_per_step = coh_tests + sup_tests + score_tests
     value = tests_per_step / (ms_per_step / 1e3)
-    on_mfma = sum(st.tests) != coh_tests            # dense count: the matrix-core kernels ran
-    coh_ms = sum(mm.stats().ms[4] for mm in models) / len(models)
-    sup_ms = sum(mm.stats().ms[6] for mm in models) / len(models)
-    # the subset-test kernels alone (event pairs around their launches), where timed
+    dense = sum(st.tests)                    # every (candidate, other-class record) pair
+    on_mfma = dense != coh_tests             # the matrix-core kernels ran (no early exit)
+    info = models[-1].info()
+    L_mfma = int(info.mfma_tokens)           # tokens per row of the matrix-core operands
+    W_mfma = int(info.mfma_words)            # 64-token words they occupy
+    # per-kernel device time: event pairs around each launch on its stream; two
+    # launches (one per class) of each contraction per fit, one scoring launch per step
     kcoh_ms = sum(mm.stats().kernel_ms[0] for mm in models) / len(models)
     ksup_ms = sum(mm.stats().kernel_ms[1] for mm in models) / len(models)
     score_ms = sum(a.elapsed_time(b) for a, b in score_ev[-len(models):]) / len(models)
-    n_cls = list(st.n_class)
+    peaks = None if args.no_peaks else measured_peaks()
+    if peaks:
+        log("measured peaks", peaks)
     kernels = {}
-    info = models[-1].info()
-    L_mfma = int(info.mfma_tokens)                      # tokens per row of the matrix-core operands
     if on_mfma:
-        dense = sum(st.tests)                           # every (candidate, other-class record) pair
-        kernels["k_contain_mfma[coherence]"] = {"bound": "mfma", "ms": kcoh_ms or coh_ms,
-                                                "ops": 2.0 * L_mfma * dense,
-                                                "peak": MFMA_FP4_PEAK_OPS, "unit": "TFLOP/s (fp4 dense)"}
-        kernels["k_contain_mfma[support]"] = {"bound": "mfma", "ms": ksup_ms or sup_ms,
-                                              "ops": 2.0 * L_mfma * sup_tests,
-                                              "peak": MFMA_FP4_PEAK_OPS, "unit": "TFLOP/s (fp4 dense)"}
-    else:
-        kernels["k_coherence"] = {"bound": "alu", "ms": coh_ms, "ops": 2.0 * K * coh_tests,
-                                  "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
-        kernels["k_support"] = {"bound": "alu", "ms": sup_ms, "ops": 2.0 * K * sup_tests,
-                                "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
+        # coherence: the method's tests are sum t(b); the launch executes every pair
+        kernels["k_contain_mfma[coherence]"] = dict(ms=kcoh_ms, launches=2, tests=coh_tests, exec_tests=dense)
+        kernels["k_contain_mfma[support]"] = dict(ms=ksup_ms, launches=2, tests=sup_tests, exec_tests=sup_tests)
     if models[-1].score_on_matrix_cores:
-        kernels["k_score_mfma"] = {"bound": "mfma", "ms": score_ms, "ops": 2.0 * L_mfma * score_tests,
-                                   "peak": MFMA_FP4_PEAK_OPS, "unit": "TFLOP/s (fp4 dense)"}
-    else:
-        kernels["k_score"] = {"bound": "alu", "ms": score_ms, "ops": 2.0 * K * score_tests,
-                              "peak": VALU_INT32_PEAK_OPS, "unit": "TOP/s (int32 VALU)"}
+        kernels["k_score_mfma"] = dict(ms=score_ms, launches=1, tests=score_tests, exec_tests=score_tests)
     for k, v in kernels.items():
-        v["achieved"] = v["ops"] / (v["ms"] / 1e3) / 1e12
-        v["frac"] = v["ops"] / (v["ms"] / 1e3) / v["peak"]
-    dom = max(kernels, key=lambda k: kernels[k]["ms"])
-    d = kernels[dom]
-    roofline = {"bound": d["bound"], "kernel": dom, "achieved": d["achieved"], "peak": d["peak"] / 1e12,
-                "unit": d["unit"], "frac": d["frac"], "traffic": counted_traffic(args.traffic, dom),
-                "avg_ms": d["ms"]}
+        v["bound"] = "mfma"
+        v["unit"] = "TFLOP/s (fp4 dense)"
+        v["ops"] = 2.0 * L_mfma * v["tests"]                       # the method's operations
+        v["exec_ops"] = 2.0 * 64 * W_mfma * v["exec_tests"]         # what the padded tiles execute
+        sec = v["ms"] / 1e3
+        v["avg_ms"] = v["ms"] / v["launches"]
+        v["achieved"] = v["ops"] / sec / 1e12
+        v["frac"] = v["ops"] / sec / MFMA_FP4_PEAK_OPS
+        v["frac_dense"] = 2.0 * L_mfma * v["exec_tests"] / sec / MFMA_FP4_PEAK_OPS
+        v["frac_executed"] = v["exec_ops"] / sec / MFMA_FP4_PEAK_OPS
+        if peaks:
+            v["frac_of_measured_peak"] = v["ops"] / sec / peaks["fp4_mfma_ops_per_s"]
     res = {
         "metric": METRIC, "value": value, "unit": "subset tests/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp4(e2m1)->fp32 and int8->int32, exact integers",
         "data": "synthetic",
         "config": {"workload": w.name, "n_train": int(w.n), "n_flows": int(n_flows), "d": int(w.d),
-                   "L": int(w.L), "K": int(K), "mfma_tokens": L_mfma, "mfma_words": int(info.mfma_words)},
-        "fit_wall_s_15k": float(np.median(fit_s)),
-        "tests_per_step": {"coherence": coh_tests, "support": sup_tests, "scoring": score_tests},
+                   "L": int(w.L), "K": int(K), "mfma_tokens": L_mfma, "mfma_words": W_mfma},
+        "tests_per_step": {"coherence": coh_tests, "coherence_dense": dense, "support": sup_tests,
+                           "scoring": score_tests},
         "patterns": list(npat), "distinct": list(st.distinct),
         "stage_ms": {k: round(v, 3) for k, v in zip(
             ["pack", "pairs", "sort", "dedup", "coherence", "order", "support", "fit_total"], st.ms)},
-        "roofline": roofline,
-        "kernels": {k: {"ms": round(v["ms"], 3), "achieved": round(v["achieved"], 2), "frac": round(v["frac"], 4),
-                        "bound": v["bound"]} for k, v in kernels.items()},
     }
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["ms"])
+        d = kernels[dom]
+        res["roofline"] = {"bound": d["bound"], "kernel": dom, "achieved": d["achieved"],
+                           "peak": MFMA_FP4_PEAK_OPS / 1e12, "unit": d["unit"], "frac": d["frac"],
+                           "traffic": counted_traffic(args.traffic, dom), "avg_ms": d["avg_ms"],
+                           "launches_per_step": d["launches"],
+                           "tokens_per_test": L_mfma, "tests_per_launch": d["tests"] / d["launches"],
+                           "frac_dense": d["frac_dense"], "frac_executed": d["frac_executed"],
+                           "frac_of_measured_peak": d.get("frac_of_measured_peak")}
+        res["kernels"] = {k: {x: (round(v[x], 4) if isinstance(v[x], float) else v[x])
+                              for x in ("avg_ms", "launches", "achieved", "frac", "frac_dense", "frac_executed",
+                                        "frac_of_measured_peak") if x in v}
+                          for k, v in kernels.items()}
+    if peaks:
+        res["measured_peaks"] = peaks
     del models
+    torch.cuda.synchronize()
+    # fit alone, and from host arrays with the export; scoring alone
+    res["fit_wall_s_15k"], res["fit_wall_s_15k_host_export"] = fit_wall(
+        w.codes, w.labels, w.nbins, d_codes, d_labels)
+    m = ig.fit(d_codes, d_labels, w.nbins)
+    sw = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        ig.score(m, d_flows, out=out)
+        torch.cuda.synchronize()
+        sw.append(time.perf_counter() - a)
+    res["score_wall_s_15k"] = float(np.median(sw))
+    del m
+    log("15k fit %.1f ms (device inputs), %.1f ms (host arrays + export), score %.1f ms" % (
+        res["fit_wall_s_15k"] * 1e3, res["fit_wall_s_15k_host_export"] * 1e3, res["score_wall_s_15k"] * 1e3))
     if not args.no_148k:
         w2 = synth.make_148k()
         log("148k workload", w2.codes.shape)
@@ -344,31 +453,32 @@ def main():
         dl2 = torch.from_numpy(w2.labels).cuda()
         m2 = ig.fit(dc2, dl2, w2.nbins)   # warm (allocations, code load)
         del m2
+        res["fit_wall_s_148k"], res["fit_wall_s_148k_host_export"] = fit_wall(
+            w2.codes, w2.labels, w2.nbins, dc2, dl2)
+        m2 = ig.fit(dc2, dl2, w2.nbins)
+        st2 = m2.stats()
+        res["fit_148k"] = {"n_train": int(w2.n), "patterns": list(m2.n_patterns()), "tests_dense": list(st2.tests),
+                           "coherence_kernel_ms": st2.kernel_ms[0], "support_kernel_ms": st2.kernel_ms[1]}
+        d_f2 = torch.from_numpy(w2.test_codes.view(np.int16)).cuda()
+        out2 = torch.empty((w2.test_codes.shape[0], 2), dtype=torch.int64, device="cuda")
+        ig.score(m2, d_f2, out=out2)
         torch.cuda.synchronize()
         a = time.perf_counter()
-        m2 = ig.fit(dc2, dl2, w2.nbins)
-        res["fit_wall_s_148k"] = time.perf_counter() - a
-        st2 = m2.stats()
-        res["fit_148k"] = {"n_train": int(w2.n), "patterns": list(m2.n_patterns()), "tests": list(st2.tests),
-                           "coherence_ms": st2.ms[4]}
-        del m2
+        ig.score(m2, d_f2, out=out2)
+        torch.cuda.synchronize()
+        res["score_wall_s_148k"] = time.perf_counter() - a
+        res["fit_148k"]["score_tests"] = sum(m2.n_patterns()) * int(w2.test_codes.shape[0])
+        del m2, d_f2, out2
+        log("148k fit %.1f ms, score of %d flows %.1f ms" % (res["fit_wall_s_148k"] * 1e3, w2.test_codes.shape[0],
+                                                             res["score_wall_s_148k"] * 1e3))
     if not args.no_serve:
         res["serve"] = measure_serving(args.serve_seconds)
     if not args.no_cpu:
-        import oracle
-        ns = min(args.cpu_records, w.n)
-        nf = 300
-        log("cpu oracle on", ns, "records,", nf, "flows")
-        a = time.perf_counter()
-        om = oracle.fit(w.codes[:ns], w.labels[:ns], w.nbins)
-        oracle.score(om, w.test_codes[:nf], w.nbins)
-        dt = time.perf_counter() - a
-        t_or = sum(om.stats["tests"]) + sum(p.shape[0] * n for p, n in zip(om.patterns, om.stats["n_class"])) \
-            + sum(p.shape[0] for p in om.patterns) * nf
-        res["cpu_baseline"] = {"value": t_or / dt, "unit": "subset tests/s", "cores": oracle.max_threads(),
-                               "kind": "oracle", "seconds": dt,
-                               "sample": f"oracle fit of the first {ns} training records of the 15k workload "
-                                         f"+ scoring {nf} held-out flows"}
+        res["cpu_baseline"] = cpu_baseline(w, min(args.cpu_records, w.n), 300, 2500)
+    if not args.no_batch:
+        torch.cuda.synchronize()
+        res["batch"] = measure_batch()
+        log("batch", res["batch"])
     print(json.dumps(res), flush=True)
 
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libig.so")
 ARCH = "gfx950"
-SOURCES = ["api.cpp", "factor.hip", "pack.hip", "pairs.hip", "sort.hip", "subset.hip"]
+SOURCES = ["api.cpp", "factor.hip", "pack.hip", "pairs.hip", "probe.hip", "sort.hip", "subset.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-Wno-unused-result", "-ffp-contract=off",
@@ -34,7 +34,8 @@ def build(force: bool = True, jobs: int = 8) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     hdrs = [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
-    hdrs.append(os.path.join(HERE, "..", "include", "ig.h"))
+    inc = os.path.join(HERE, "..", "include")
+    hdrs += [os.path.join(inc, h) for h in os.listdir(inc) if h.endswith(".h")]
     if not force and os.path.exists(LIB):
         newest = max(os.path.getmtime(p) for p in srcs + hdrs)
         if os.path.getmtime(LIB) >= newest:

@@ -20,6 +20,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "../../include/ig_probe.h"
 
 namespace ig {
 
@@ -1757,6 +1758,23 @@ void ig_model_free(ig_model *m) {
 
 const char *ig_last_error(void) { return ig::g_last_error.c_str(); }
 
-const char *ig_version(void) { return "libig 0.1 (gfx950)"; }
+const char *ig_version(void) { return "libig 0.2 (gfx950)"; }
+
+ig_status ig_probe_mfma_fp4(uint32_t iters, void *stream, double *ops_per_s, float *ms) {
+    return guarded([&] {
+        IG_REQUIRE(ops_per_s != nullptr, IG_E_INVAL, "ops_per_s is NULL");
+        *ops_per_s = ig::probe_mfma_fp4(iters, (hipStream_t)stream, ms);
+    });
+}
+
+ig_status ig_probe_hbm_copy(const void *d_src, void *d_dst, size_t bytes, void *stream, double *bytes_per_s,
+                            float *ms) {
+    return guarded([&] {
+        IG_REQUIRE(bytes_per_s != nullptr, IG_E_INVAL, "bytes_per_s is NULL");
+        const uintptr_t a = (uintptr_t)d_src, b = (uintptr_t)d_dst;
+        IG_REQUIRE(a + bytes <= b || b + bytes <= a, IG_E_INVAL, "source and destination overlap");
+        *bytes_per_s = ig::probe_copy(d_src, d_dst, bytes, (hipStream_t)stream, ms);
+    });
+}
 
 }  // extern "C"

@@ -206,4 +206,8 @@ void launch_score(const ScoreModel &m, const uint16_t *codes, const uint64_t *wo
 
 void launch_reduce_maxsum(const int64_t *S, size_t m, unsigned long long *d_max_sum /*[2]*/, hipStream_t s);
 
+// probe.hip -- attainable peaks (include/ig_probe.h); both wait for the stream
+double probe_mfma_fp4(uint32_t iters, hipStream_t s, float *ms);                          // operations/s
+double probe_copy(const void *src, void *dst, size_t bytes, hipStream_t s, float *ms);   // bytes/s
+
 }  // namespace ig

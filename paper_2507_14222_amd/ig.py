@@ -60,10 +60,10 @@ class Problem(C.Structure):
 
 _lib = None
 
-# every symbol include/ig.h declares
+# every symbol the headers under include/ declare
 EXPORTS = ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_packed", "ig_model_get_info",
            "ig_model_export", "ig_model_import", "ig_model_digest", "ig_fit_stats", "ig_model_free",
-           "ig_last_error", "ig_version")
+           "ig_last_error", "ig_version", "ig_probe_mfma_fp4", "ig_probe_hbm_copy")
 
 
 def lib():
@@ -89,8 +89,11 @@ def lib():
     L.ig_model_free.restype = None
     L.ig_last_error.restype = C.c_char_p
     L.ig_version.restype = C.c_char_p
+    L.ig_probe_mfma_fp4.argtypes = [u32, vp, C.POINTER(C.c_double), C.POINTER(C.c_float)]
+    L.ig_probe_hbm_copy.argtypes = [vp, vp, C.c_size_t, vp, C.POINTER(C.c_double), C.POINTER(C.c_float)]
     for name in ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_packed", "ig_model_get_info",
-                 "ig_model_export", "ig_model_import", "ig_model_digest", "ig_fit_stats"):
+                 "ig_model_export", "ig_model_import", "ig_model_digest", "ig_fit_stats", "ig_probe_mfma_fp4",
+                 "ig_probe_hbm_copy"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -110,6 +113,43 @@ def _stream_handle(stream) -> C.c_void_p:
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+class _OnStream:
+    """Context for one library call on `stream` (None = torch's current stream).
+
+    Inside it torch's current stream is the call's stream, so the temporaries the
+    binding makes (host-to-device copies, dtype conversions, default outputs) are
+    enqueued and allocated on the stream the library then launches on.  That
+    stream first waits for work already queued on the caller's current stream
+    (which may have produced the inputs), and every device tensor handed to the
+    library is marked as used on it, so that torch's caching allocator does not
+    reuse its memory while the call is still in flight."""
+
+    def __init__(self, stream):
+        torch = _torch()
+        self.caller = torch.cuda.current_stream()
+        self.s = stream if stream is not None else self.caller
+        self._ctx = torch.cuda.stream(self.s)
+
+    def __enter__(self):
+        if self.s != self.caller:
+            self.s.wait_stream(self.caller)
+        self._ctx.__enter__()
+        return self
+
+    def __exit__(self, *exc):
+        return self._ctx.__exit__(*exc)
+
+    def use(self, t):
+        """Mark a device tensor as read or written by the call."""
+        if self.s != self.caller:
+            t.record_stream(self.s)
+        return t
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return C.c_void_p(self.s.cuda_stream)
 
 
 def _dev(a, dtype):
@@ -241,28 +281,30 @@ def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tu
         kernels: str = "auto", stream=None) -> Model:
     """ig_fit: codes [n, d] bin codes, labels [n] (0 normal / 1 attack), nbins [d]."""
     torch = _torch()
-    dc = _dev(codes, torch.int16)
-    dl = _dev(labels, torch.uint8)
-    n, d = (int(dc.shape[0]), int(dc.shape[1])) if dc.dim() == 2 else (0, 0)
-    nb = _np_u16(nbins)
-    h = C.c_void_p()
-    o = _opts(mem_budget_bytes, filter_cpl, tune=tune, kernels=kernels)
-    _check(lib().ig_fit(C.c_void_p(dc.data_ptr()), C.c_void_p(dl.data_ptr()), n, d or nb.size,
-                        C.c_void_p(nb.ctypes.data), C.byref(o), _stream_handle(stream), C.byref(h)))
+    with _OnStream(stream) as on:
+        dc = on.use(_dev(codes, torch.int16))
+        dl = on.use(_dev(labels, torch.uint8))
+        n, d = (int(dc.shape[0]), int(dc.shape[1])) if dc.dim() == 2 else (0, 0)
+        nb = _np_u16(nbins)
+        h = C.c_void_p()
+        o = _opts(mem_budget_bytes, filter_cpl, tune=tune, kernels=kernels)
+        _check(lib().ig_fit(C.c_void_p(dc.data_ptr()), C.c_void_p(dl.data_ptr()), n, d or nb.size,
+                            C.c_void_p(nb.ctypes.data), C.byref(o), on.handle, C.byref(h)))
     return Model(h)
 
 
 def fit_packed(words, labels, mem_budget_bytes: int = 0, stream=None) -> Model:
     """ig_fit_packed: words [n, K] uint64 bitsets (Eq. 5 layout), labels [n]."""
     torch = _torch()
-    dw = _dev(np.ascontiguousarray(words).view(np.int64) if isinstance(words, np.ndarray) else words,
-              torch.int64)
-    dl = _dev(labels, torch.uint8)
-    n, K = int(dw.shape[0]), int(dw.shape[1])
-    h = C.c_void_p()
-    o = _opts(mem_budget_bytes)
-    _check(lib().ig_fit_packed(C.c_void_p(dw.data_ptr()), C.c_void_p(dl.data_ptr()), n, K, C.byref(o),
-                               _stream_handle(stream), C.byref(h)))
+    with _OnStream(stream) as on:
+        dw = on.use(_dev(np.ascontiguousarray(words).view(np.int64) if isinstance(words, np.ndarray) else words,
+                         torch.int64))
+        dl = on.use(_dev(labels, torch.uint8))
+        n, K = int(dw.shape[0]), int(dw.shape[1])
+        h = C.c_void_p()
+        o = _opts(mem_budget_bytes)
+        _check(lib().ig_fit_packed(C.c_void_p(dw.data_ptr()), C.c_void_p(dl.data_ptr()), n, K, C.byref(o),
+                                   on.handle, C.byref(h)))
     return Model(h)
 
 
@@ -272,43 +314,51 @@ def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, tune=None, kernels:
     torch = _torch()
     keep = []
     arr = (Problem * len(problems))()
-    for p, pr in enumerate(problems):
-        dc = _dev(pr.codes, torch.int16)
-        dl = _dev(pr.labels, torch.uint8)
-        nb = _np_u16(pr.nbins)
-        keep += [dc, dl, nb]
-        arr[p].d_codes = dc.data_ptr()
-        arr[p].d_labels = dl.data_ptr()
-        arr[p].n = int(dc.shape[0])
-        arr[p].d = int(nb.size)
-        arr[p].h_nbins = nb.ctypes.data
-    outs = (C.c_void_p * len(problems))()
-    o = _opts(mem_budget_bytes, tune=tune, kernels=kernels)
-    _check(lib().ig_fit_batch(arr, len(problems), C.byref(o), _stream_handle(stream), outs))
+    with _OnStream(stream) as on:
+        for p, pr in enumerate(problems):
+            dc = on.use(_dev(pr.codes, torch.int16))
+            dl = on.use(_dev(pr.labels, torch.uint8))
+            nb = _np_u16(pr.nbins)
+            keep += [dc, dl, nb]
+            arr[p].d_codes = dc.data_ptr()
+            arr[p].d_labels = dl.data_ptr()
+            arr[p].n = int(dc.shape[0])
+            arr[p].d = int(nb.size)
+            arr[p].h_nbins = nb.ctypes.data
+        outs = (C.c_void_p * len(problems))()
+        o = _opts(mem_budget_bytes, tune=tune, kernels=kernels)
+        _check(lib().ig_fit_batch(arr, len(problems), C.byref(o), on.handle, outs))
     return [Model(C.c_void_p(outs[p])) for p in range(len(problems))]
 
 
 def score(model: Model, flows, out=None, stream=None):
-    """ig_score: (A, N) per flow as an int64 device tensor [n, 2] (asynchronous)."""
+    """ig_score: (A, N) per flow as an int64 device tensor [n, 2], asynchronous on
+    `stream` (torch's current stream when None): the result is ready once that
+    stream reaches the call."""
     torch = _torch()
-    dc = _dev(flows, torch.int16)
-    n = int(dc.shape[0])
-    if out is None:
-        out = torch.empty((n, 2), dtype=torch.int64, device=dc.device)
-    _check(lib().ig_score(model.handle, C.c_void_p(dc.data_ptr()), n, C.c_void_p(out.data_ptr()),
-                          _stream_handle(stream)))
+    with _OnStream(stream) as on:
+        dc = on.use(_dev(flows, torch.int16))
+        n = int(dc.shape[0])
+        if out is None:
+            out = torch.empty((n, 2), dtype=torch.int64, device=dc.device)
+        on.use(out)
+        _check(lib().ig_score(model.handle, C.c_void_p(dc.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                              on.handle))
     return out
 
 
 def score_packed(model: Model, words, out=None, stream=None):
+    """ig_score_packed: as score() for flows given as packed words [n, K]."""
     torch = _torch()
-    dw = _dev(np.ascontiguousarray(words).view(np.int64) if isinstance(words, np.ndarray) else words,
-              torch.int64)
-    n = int(dw.shape[0])
-    if out is None:
-        out = torch.empty((n, 2), dtype=torch.int64, device=dw.device)
-    _check(lib().ig_score_packed(model.handle, C.c_void_p(dw.data_ptr()), n, C.c_void_p(out.data_ptr()),
-                                 _stream_handle(stream)))
+    with _OnStream(stream) as on:
+        dw = on.use(_dev(np.ascontiguousarray(words).view(np.int64) if isinstance(words, np.ndarray) else words,
+                         torch.int64))
+        n = int(dw.shape[0])
+        if out is None:
+            out = torch.empty((n, 2), dtype=torch.int64, device=dw.device)
+        on.use(out)
+        _check(lib().ig_score_packed(model.handle, C.c_void_p(dw.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                     on.handle))
     return out
 
 
@@ -328,3 +378,25 @@ def import_patterns(codes0, f0, codes1, f1, nbins, stream=None) -> Model:
 
 def version() -> str:
     return lib().ig_version().decode()
+
+
+def probe_mfma_fp4(iters: int = 20000, stream=None) -> Tuple[float, float]:
+    """Measured fp4 matrix-core rate of the device: (operations/s, launch ms)."""
+    r, ms = C.c_double(), C.c_float()
+    with _OnStream(stream) as on:
+        _check(lib().ig_probe_mfma_fp4(int(iters), on.handle, C.byref(r), C.byref(ms)))
+    return float(r.value), float(ms.value)
+
+
+def probe_hbm_copy(src, dst, stream=None) -> Tuple[float, float]:
+    """Measured HBM copy rate between two equal device tensors: (bytes/s read +
+    written, launch ms)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    r, ms = C.c_double(), C.c_float()
+    with _OnStream(stream) as on:
+        on.use(src)
+        on.use(dst)
+        _check(lib().ig_probe_hbm_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, on.handle,
+                                       C.byref(r), C.byref(ms)))
+    return float(r.value), float(ms.value)

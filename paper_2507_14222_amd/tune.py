@@ -85,6 +85,34 @@ def load(path: str) -> Optional[List[Dict]]:
     return t.get("entries")
 
 
+def model_bytes_estimate(p) -> int:
+    """Upper estimate of the device bytes a fit of problem p holds at once: every
+    pair intersection and record of both classes as a candidate row plus its
+    12-byte sort entry."""
+    n1 = int(np.asarray(p.labels).sum())
+    n0 = int(p.n) - n1
+    K = ig_storage_words((int(p.L) + 63) // 64)
+    return (n0 * (n0 + 1) // 2 + n1 * (n1 + 1) // 2) * (K * 8 + 12)
+
+
+def slices_by_memory(problems, budget_bytes: float = 90e9) -> List[List[int]]:
+    """Consecutive slices of the problem list whose estimated bytes stay within
+    the budget (a slice holds at least one problem): the 64 models of the batch
+    workload together are larger than device memory, so a caller fits and
+    releases them slice by slice."""
+    slices, cur, acc = [], [], 0
+    for i, p in enumerate(problems):
+        b = model_bytes_estimate(p)
+        if cur and acc + b > budget_bytes:
+            slices.append(cur)
+            cur, acc = [], 0
+        cur.append(i)
+        acc += b
+    if cur:
+        slices.append(cur)
+    return slices
+
+
 def widths_of(problems) -> List[int]:
     return sorted(set(ig_storage_words((p.L + 63) // 64) for p in problems))
 

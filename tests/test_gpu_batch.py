@@ -1,6 +1,9 @@
 """Batched fitting (ig_fit_batch): every model equals the one ig_fit builds for
 the same problem -- patterns, supports, weights and counters -- whatever the
 grouping, widths, sizes and tuning; small problems also equal the oracle."""
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -88,3 +91,78 @@ def test_autotuner_small():
     a = ig.fit(p.codes, p.labels, p.nbins, kernels="valu")
     b = ig.fit(p.codes, p.labels, p.nbins, tune=t["entries"], kernels="valu")
     _same(a, b)
+
+
+# ------------------------------------------------ the 64-problem workload
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch64_small.json")
+
+
+def _export_digest(m):
+    h = hashlib.sha256()
+    for c in (0, 1):
+        w, f, S = m.export(c)
+        h.update(np.ascontiguousarray(w, dtype="<u8").tobytes())
+        h.update(np.ascontiguousarray(f, dtype="<u4").tobytes())
+        h.update(np.ascontiguousarray(S, dtype="<i8").tobytes())
+    return h.hexdigest()
+
+
+def _check_golden(m, e):
+    st = m.stats()
+    for k in ("n_class", "pairs", "distinct", "coherent"):
+        assert list(getattr(st, k)) == e["stats"][k], k
+    assert _export_digest(m) == e["model_sha256"]
+
+
+@pytest.mark.timeout(600)
+def test_small_problems_of_the_64_problem_workload_match_the_oracle():
+    """Every problem of the 64-problem workload (seed 3) with at most 5,000 records,
+    fitted batched and one by one, against the oracle's stored digests."""
+    g = json.load(open(GOLD))
+    probs = synth.make_batch()
+    idx = sorted(int(k) for k in g["problems"])
+    say("seed-3 problems with n <= %d:" % g["max_n"], idx)
+    ms = ig.fit_batch([probs[i] for i in idx])
+    for i, m in zip(idx, ms):
+        _check_golden(m, g["problems"][str(i)])
+        m.free()
+    for i in idx:
+        p = probs[i]
+        m = ig.fit(p.codes, p.labels, p.nbins)
+        _check_golden(m, g["problems"][str(i)])
+        m.free()
+        say("problem", i, "ok")
+
+
+@pytest.mark.timeout(900)
+def test_64_problem_workload_batched_equals_plain():
+    """All 64 problems (seed 3): ig_fit_batch over memory-sized slices against 64
+    plain ig_fit calls, model by model (device digests of the set of rows, f and S,
+    plus every counter but the timings)."""
+    import torch
+    probs = synth.make_batch()
+    dev = [(torch.from_numpy(p.codes.view(np.int16)).cuda(), torch.from_numpy(p.labels).cuda(), p.nbins)
+           for p in probs]
+
+    class P:
+        def __init__(self, c, l, nb):
+            self.codes, self.labels, self.nbins = c, l, nb
+
+    def key(m):
+        st = m.stats()
+        return (m.digest(0), m.digest(1), st.n_class, st.pairs, st.distinct, st.coherent, st.tests,
+                st.support_tests)
+
+    batched = {}
+    for sl in tune.slices_by_memory(probs):
+        ms = ig.fit_batch([P(*dev[i]) for i in sl])
+        for i, m in zip(sl, ms):
+            batched[i] = key(m)
+            m.free()
+        say("batched slice", sl[0], "..", sl[-1])
+    for i in range(len(probs)):
+        m = ig.fit(*dev[i])
+        assert key(m) == batched[i], f"problem {i}"
+        m.free()
+        if i % 8 == 7:
+            say("plain fits equal up to", i)

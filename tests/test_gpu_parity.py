@@ -264,6 +264,38 @@ def test_scores_do_not_depend_on_batching():
         at += k
 
 
+def test_binding_calls_on_a_non_current_stream():
+    """Calls on a stream other than torch's current one, with host inputs and with
+    device inputs that the binding converts: the conversions run on the call's
+    stream after it waits for the caller's stream (here kept busy, so that an
+    unordered read would see an unfinished copy), and the temporaries are not
+    reused while the call runs.  Results equal those of the default path."""
+    import torch
+    w = synth.make_tiny(0)
+    say("non-current stream")
+    m = ig.fit(w.codes, w.labels, w.nbins)
+    A, N = gpu_scores(m, w.test_codes)
+    s = torch.cuda.Stream()
+    outs = []
+    for rep in range(3):
+        torch.cuda._sleep(20_000_000)                            # the caller's stream is busy
+        d64 = torch.from_numpy(w.test_codes.astype(np.int64)).cuda()   # queued behind it
+        outs.append(ig.score(m, d64, stream=s))                 # converted to int16 on s
+        del d64
+        outs.append(ig.score(m, w.test_codes, stream=s))        # host flows
+        junk = torch.full((1 << 22,), -1, dtype=torch.int64, device="cuda")   # reuse pressure
+        del junk
+    s.synchronize()
+    for o in outs:
+        o = o.cpu().numpy()
+        assert np.array_equal(o[:, 0], A) and np.array_equal(o[:, 1], N)
+    torch.cuda._sleep(20_000_000)
+    dcodes = torch.from_numpy(w.codes.astype(np.int64)).cuda()
+    m2 = ig.fit(dcodes, w.labels, w.nbins, stream=s)
+    om = oracle.fit(w.codes, w.labels, w.nbins)
+    assert_same_model(m2, om, om.K)
+
+
 def test_scoring_shapes_beyond_the_launch_cache():
     """Scoring launches of 20 flow-block counts, then the same in reverse: the
     launcher keeps its last 16 range choices, so the sequence both evicts and
@@ -313,6 +345,33 @@ def test_15k_workload_matches_oracle_digest():
     assert list(st.distinct) == g["stats"]["distinct"]
     assert list(st.coherent) == g["stats"]["coherent"]
     assert _model_digest(m) == g["model_sha256"]
+    A, N = gpu_scores(m, w.test_codes)
+    assert A[:16].tolist() == g["scores_head"]["A"] and N[:16].tolist() == g["scores_head"]["N"]
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(A, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(N, dtype="<i8").tobytes())
+    assert h.hexdigest() == g["scores_sha256"]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("kernels", ["auto", "mfma_onehot", "valu"])
+def test_148k_workload_matches_oracle_digest(kernels):
+    """The 148k workload (14.8k training records, 133,200 flows) at full output:
+    both pattern sets with f and S, and the scores of every held-out flow, against
+    the oracle's stored digests."""
+    g = json.load(open(os.path.join(GOLD, "mixture41_148k.json")))
+    w = synth.make_148k()
+    say("148k workload", kernels, w.codes.shape, w.test_codes.shape)
+    m = ig.fit(w.codes, w.labels, w.nbins, kernels=kernels)
+    st = m.stats()
+    assert list(st.pairs) == g["stats"]["pairs"]
+    assert list(st.distinct) == g["stats"]["distinct"]
+    assert list(st.coherent) == g["stats"]["coherent"]
+    if kernels == "valu":
+        assert list(st.tests) == g["stats"]["tests"]
+    assert _model_digest(m) == g["model_sha256"]
+    if kernels != "auto":
+        return
     A, N = gpu_scores(m, w.test_codes)
     assert A[:16].tolist() == g["scores_head"]["A"] and N[:16].tolist() == g["scores_head"]["N"]
     h = hashlib.sha256()
