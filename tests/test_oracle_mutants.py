@@ -102,3 +102,73 @@ def test_pins_catch_mutant(name, src_text, tmp_path):
     finally:
         oracle.use_library(None)
     assert caught, f"mutant {name} passed every pin"
+
+
+# ---------------------------------------------- regulations and metrics
+REG_SRC = os.path.join(os.path.dirname(SRC), "regulations.py")
+REG_MUTANTS = {
+    # Regulation 1 with ties going to normal
+    "r1_strict": ("lab, rule = (1 if a >= n else 0), R1", "lab, rule = (1 if a > n else 0), R1"),
+    # Regulation 2 dropped
+    "r2_missing": ("if use_r2 and a == 0 and n == 0:", "if False:"),
+    # Regulation 3 applied to flows already labelled attack
+    "r3_on_attack_too": ("if use_r3 and lab == 0 and regulation3_fires(n, st, r):",
+                         "if use_r3 and regulation3_fires(n, st, r):"),
+    # Regulation 3's gap reversed
+    "r3_gap_reversed": ("gap = st.mu - n_x", "gap = n_x - st.mu"),
+    # sample instead of population variance
+    "sample_variance": ("return Fraction(self.count * self.total_sq - self.total * self.total, self.count * self.count)",
+                        "return Fraction(self.count * self.total_sq - self.total * self.total, "
+                        "self.count * (self.count - 1))"),
+    # ties counted as wins in the AUC
+    "auc_ties_full": ("num += 2 * below + (upto - below)", "num += 2 * upto"),
+    # recall over predicted positives
+    "recall_is_precision": ("return self.tp / (self.tp + self.fn) if self.tp + self.fn else 0.0",
+                            "return self.tp / (self.tp + self.fp) if self.tp + self.fp else 0.0"),
+}
+
+
+def _run_regulation_pins(mod):
+    from tests import test_oracle_regulations as rp
+    saved = rp.reg
+    rp.reg = mod
+    try:
+        rp.test_worked_example_labels()
+        rp.test_textbook_moments()
+        for r, f in [(1.0, 3), (0.5, 4), (0.0, 5), (2.0, 1), (2.5, 0)]:
+            rp.test_regulation3_threshold_is_exact(r, f)
+        rp.test_regulation3_only_turns_normal_into_attack()
+        rp.test_regulation3_with_a_non_dyadic_r()
+        for s in range(8):
+            rp.test_metrics_against_sklearn_and_brute_force(s)
+        rp.test_auc_closed_forms()
+    except AssertionError:
+        return False
+    finally:
+        rp.reg = saved
+    return True
+
+
+def _module_from(text, name):
+    import sys
+    import types
+    mod = types.ModuleType(name)
+    sys.modules[name] = mod          # dataclasses look their module up there
+    try:
+        exec(compile(text, name, "exec"), mod.__dict__)
+    finally:
+        del sys.modules[name]
+    return mod
+
+
+def test_regulation_pins_pass_on_unmodified_oracle():
+    assert _run_regulation_pins(_module_from(open(REG_SRC).read(), "reg_ok"))
+
+
+@pytest.mark.parametrize("name", sorted(REG_MUTANTS))
+def test_regulation_pins_catch_mutant(name):
+    text = open(REG_SRC).read()
+    old, new = REG_MUTANTS[name]
+    assert text.count(old) == 1, f"mutation site of {name} not found exactly once"
+    assert not _run_regulation_pins(_module_from(text.replace(old, new), "reg_" + name)), \
+        f"mutant {name} passed every pin"
