@@ -1234,7 +1234,7 @@ DevModel *import_patterns(const uint16_t *const h_codes[2], const uint32_t *cons
             int where = radix_sort_pairs(k0.get(), vcur, k1.get(), valt, cnt, 0xffu, s);
             if (where) std::swap(vcur, valt);
         }
-        launch_gather_rows(Wraw.get(), vcur, cnt, (uint32_t)KS, m->W[c], df.get(), m->f[c], s);
+        launch_gather_rows(Wraw.get(), vcur, cnt, (uint32_t)KS, (uint32_t)KS, m->W[c], df.get(), m->f[c], s);
         // distinctness: ordered rows must all differ from their predecessor
         launch_fill_u32(tot.get(), 0u, 1, s);
         launch_adjacent_equal(m->W[c], cnt, (uint32_t)KS, tot.get(), s);
@@ -1717,18 +1717,13 @@ ig_status ig_model_export(const ig_model *m, uint32_t cls, uint64_t *h_words, ui
         // rows in canonical order, sorted on the device
         hipStream_t s = nullptr;
         ig::Scratch<uint32_t> perm(n, s), fo(n, s);
-        ig::Scratch<uint64_t> rows(n * M.KS, s), So(n, s);
+        // rows gathered in order and cut to K words on the device: one contiguous copy
+        ig::Scratch<uint64_t> rows(n * M.K, s), So(n, s);
         ig::canonical_permutation(M, M.W[cls], 0, nullptr, n, perm.get(), s);
-        ig::launch_gather_rows(M.W[cls], perm.get(), n, M.KS, rows.get(), M.f[cls], fo.get(), s);
+        ig::launch_gather_rows(M.W[cls], perm.get(), n, M.KS, M.K, rows.get(), M.f[cls], fo.get(), s);
         ig::launch_permute_u64(reinterpret_cast<const uint64_t *>(M.S[cls]), perm.get(), n, So.get(), s);
         IG_HIP(hipStreamSynchronize(s));
-        if (h_words) {
-            if (M.KS == M.K) {
-                IG_HIP(hipMemcpy(h_words, rows.get(), n * M.K * 8, hipMemcpyDeviceToHost));
-            } else {
-                IG_HIP(hipMemcpy2D(h_words, M.K * 8, rows.get(), M.KS * 8, M.K * 8, n, hipMemcpyDeviceToHost));
-            }
-        }
+        if (h_words) IG_HIP(hipMemcpy(h_words, rows.get(), n * M.K * 8, hipMemcpyDeviceToHost));
         if (h_f) IG_HIP(hipMemcpy(h_f, fo.get(), n * 4, hipMemcpyDeviceToHost));
         if (h_S) IG_HIP(hipMemcpy(h_S, So.get(), n * 8, hipMemcpyDeviceToHost));
     });

@@ -40,7 +40,7 @@ void launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32
                         uint32_t *newflag, hipStream_t s);
 void launch_compact_rows(const uint64_t *W, const uint32_t *flags, const uint32_t *pos, size_t m, uint32_t KS,
                          uint64_t *out, hipStream_t s);
-void launch_gather_rows(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint64_t *out,
+void launch_gather_rows(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint32_t KD, uint64_t *out,
                         const uint32_t *fin, uint32_t *fout, hipStream_t s);
 void launch_row_word(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint32_t k, uint64_t *keys,
                      hipStream_t s);

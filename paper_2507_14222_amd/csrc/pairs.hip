@@ -227,12 +227,13 @@ __global__ void k_compact_rows(const uint64_t *__restrict__ W, const uint32_t *_
 }
 
 // rows W[ids[e]] in the order of ids (ordering of given pattern sets)
+// out [m][KD] = the first KD <= KS words of rows ids[e] of W [.][KS]
 __global__ void k_gather_rows(const uint64_t *__restrict__ W, const uint32_t *__restrict__ ids, size_t m,
-                              uint32_t KS, uint64_t *__restrict__ out, const uint32_t *__restrict__ fin,
+                              uint32_t KS, uint32_t KD, uint64_t *__restrict__ out, const uint32_t *__restrict__ fin,
                               uint32_t *__restrict__ fout) {
     size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= m * KS) return;
-    size_t e = g / KS, k = g % KS;
+    if (g >= m * KD) return;
+    size_t e = g / KD, k = g % KD;
     out[g] = W[(size_t)ids[e] * KS + k];
     if (fin && k == 0) fout[e] = fin[ids[e]];
 }
@@ -359,10 +360,11 @@ void launch_compact_rows(const uint64_t *W, const uint32_t *flags, const uint32_
     IG_HIP(hipGetLastError());
 }
 
-void launch_gather_rows(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint64_t *out,
+void launch_gather_rows(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint32_t KD, uint64_t *out,
                         const uint32_t *fin, uint32_t *fout, hipStream_t s) {
     if (!m) return;
-    hipLaunchKernelGGL(k_gather_rows, blocks_for(m * KS), dim3(256), 0, s, W, ids, m, KS, out, fin, fout);
+    IG_REQUIRE(KD >= 1 && KD <= KS, IG_E_INVAL, "gathered rows wider than the stored rows");
+    hipLaunchKernelGGL(k_gather_rows, blocks_for(m * KD), dim3(256), 0, s, W, ids, m, KS, KD, out, fin, fout);
     IG_HIP(hipGetLastError());
 }
 

@@ -123,9 +123,11 @@ def test_small_problems_of_the_64_problem_workload_match_the_oracle():
     idx = sorted(int(k) for k in g["problems"])
     say("seed-3 problems with n <= %d:" % g["max_n"], idx)
     ms = ig.fit_batch([probs[i] for i in idx])
+    say("batched fit done")
     for i, m in zip(idx, ms):
         _check_golden(m, g["problems"][str(i)])
         m.free()
+        say("batched problem", i, "ok")
     for i in idx:
         p = probs[i]
         m = ig.fit(p.codes, p.labels, p.nbins)
