@@ -187,6 +187,78 @@ def measure_serving(seconds):
     return out
 
 
+def pruned_work(model, flows, nbins):
+    """Pattern-flow tests of pruned scoring, from the model's bucket sizes and the
+    flows' tokens: the tests it makes and those its padded tiles execute."""
+    import numpy as np
+    off = np.concatenate([[0], np.cumsum(nbins.astype(np.int64))])
+    F = np.zeros(int(off[-1]), np.int64)
+    for f in range(flows.shape[1]):
+        np.add.at(F, off[f] + flows[:, f].astype(np.int64), 1)
+    tests = ex = 0
+    for c in (0, 1):
+        P = model.bucket_sizes(c).astype(np.int64)
+        tests += int((P * F).sum())
+        ex += int((((P + 31) // 32) * 32 * ((F + 255) // 256) * 256).sum())
+    return {"tests": tests, "exec_tests": ex}
+
+
+def scoring_modes(model, d_flows, out, reps=5):
+    """Device time of one scoring launch, pruned and dense (HIP events on the stream)."""
+    import numpy as np
+    import torch
+
+    from paper_2507_14222_amd import ig
+    res = {}
+    for mode in ("pruned", "dense"):
+        ts = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ig.score(model, d_flows, out=out, mode=mode)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        res[mode + "_ms"] = float(np.median(ts[1:]))
+    res["speedup"] = res["dense_ms"] / res["pruned_ms"]
+    return res
+
+
+def detection(model, d_train, d_train_labels, d_flows, truth, r=0.568):
+    """Regulations 1-3 (Regulation 3 with mu_N, sigma_N of the normal training
+    records and r = 0.568) on the held-out flows, and the metrics of Table 2."""
+    import time as _t
+
+    import torch
+
+    from paper_2507_14222_amd import ig
+    torch.cuda.synchronize()
+    a = _t.perf_counter()
+    tr = ig.score(model, d_train)
+    mo = ig.normal_moments(tr, d_train_labels)
+    T = ig.r3_threshold(mo, r)
+    te = ig.score(model, d_flows)
+    lab, _ = ig.classify(te, T)
+    mt = ig.detection_metrics(te, lab, truth)
+    torch.cuda.synchronize()
+    out = mt.as_dict()
+    out.update({"r": r, "r3_threshold": T, "wall_s": _t.perf_counter() - a})
+    return out
+
+
+def evidence_time(model, d_flows, k):
+    import torch
+
+    from paper_2507_14222_amd import ig
+    ig.evidence(model, d_flows[:8], k)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ig.evidence(model, d_flows, k)
+    e1.record()
+    torch.cuda.synchronize()
+    return {"flows": int(d_flows.shape[0]), "k": k, "ms": e0.elapsed_time(e1)}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -384,7 +456,16 @@ def main():
         # coherence: the method's tests are sum t(b); the launch executes every pair
         kernels["k_contain_mfma[coherence]"] = dict(ms=kcoh_ms, launches=2, tests=coh_tests, exec_tests=dense)
         kernels["k_contain_mfma[support]"] = dict(ms=ksup_ms, launches=2, tests=sup_tests, exec_tests=sup_tests)
-    if models[-1].score_on_matrix_cores:
+    pruned = None
+    if models[-1].score_on_matrix_cores and models[-1].bucketed:
+        # pruned scoring (the default): each flow meets the buckets of its tokens only.
+        # Its work is sum over (class, bucket u) of |P^c_u| * F_u pattern-flow tests
+        # (F_u = test flows holding token u); the tiles execute ceil(|P^c_u| / 32) * 32
+        # rows against ceil(F_u / 256) * 256 columns.
+        pruned = pruned_work(models[-1], w.test_codes, w.nbins)
+        kernels["k_score_mfma_pruned"] = dict(ms=score_ms, launches=1, tests=pruned["tests"],
+                                              exec_tests=pruned["exec_tests"])
+    elif models[-1].score_on_matrix_cores:
         kernels["k_score_mfma"] = dict(ms=score_ms, launches=1, tests=score_tests, exec_tests=score_tests)
     for k, v in kernels.items():
         v["bound"] = "mfma"
@@ -408,7 +489,8 @@ def main():
         "config": {"workload": w.name, "n_train": int(w.n), "n_flows": int(n_flows), "d": int(w.d),
                    "L": int(w.L), "K": int(K), "mfma_tokens": L_mfma, "mfma_words": W_mfma},
         "tests_per_step": {"coherence": coh_tests, "coherence_dense": dense, "support": sup_tests,
-                           "scoring": score_tests},
+                           "scoring": score_tests,
+                           "scoring_executed": pruned["tests"] if pruned else score_tests},
         "patterns": list(npat), "distinct": list(st.distinct),
         "stage_ms": {k: round(v, 3) for k, v in zip(
             ["pack", "pairs", "sort", "dedup", "coherence", "order", "support", "fit_total"], st.ms)},
@@ -443,6 +525,10 @@ def main():
         torch.cuda.synchronize()
         sw.append(time.perf_counter() - a)
     res["score_wall_s_15k"] = float(np.median(sw))
+    res["scoring_15k"] = scoring_modes(m, d_flows, out)
+    res["detection_15k"] = detection(m, d_codes, d_labels, d_flows, w.test_labels)
+    res["evidence_15k"] = evidence_time(m, d_flows[:512], 16)
+    log("15k scoring", res["scoring_15k"], "detection", res["detection_15k"], "evidence", res["evidence_15k"])
     del m
     log("15k fit %.1f ms (device inputs), %.1f ms (host arrays + export), score %.1f ms" % (
         res["fit_wall_s_15k"] * 1e3, res["fit_wall_s_15k_host_export"] * 1e3, res["score_wall_s_15k"] * 1e3))
@@ -468,6 +554,9 @@ def main():
         torch.cuda.synchronize()
         res["score_wall_s_148k"] = time.perf_counter() - a
         res["fit_148k"]["score_tests"] = sum(m2.n_patterns()) * int(w2.test_codes.shape[0])
+        res["scoring_148k"] = scoring_modes(m2, d_f2, out2, reps=2)
+        res["detection_148k"] = detection(m2, dc2, dl2, d_f2, w2.test_labels)
+        log("148k scoring", res["scoring_148k"], "detection", res["detection_148k"])
         del m2, d_f2, out2
         log("148k fit %.1f ms, score of %d flows %.1f ms" % (res["fit_wall_s_148k"] * 1e3, w2.test_codes.shape[0],
                                                              res["score_wall_s_148k"] * 1e3))

@@ -74,6 +74,20 @@ typedef struct {
     uint32_t reserved[3];
 } ig_tune_entry;
 
+/* A caller's device allocator (e.g. a framework's caching allocator).  alloc
+ * returns `bytes` of device memory on the current device, usable by work queued on
+ * `stream` (NULL for a model buffer, which every stream may use), or NULL when it
+ * cannot; free takes back a block alloc returned, with the stream the library last
+ * used it on (NULL for model buffers: by then no queued work uses them).  Both may
+ * be called from any host thread that calls the library.  A model built with an
+ * allocator returns its buffers to it in ig_model_free: the allocator (and ctx)
+ * must stay valid until every such model is freed. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} ig_allocator;
+
 /* Optional knobs of a fit.  Zero-initialise and set what is needed. */
 typedef struct {
     uint64_t mem_budget_bytes;  /* 0: no limit.  Otherwise the pair space of a class
@@ -101,6 +115,12 @@ typedef struct {
                                    3 = matrix cores on the one-hot words (K <= 16).
                                    All give the same patterns, f and S.             */
     uint32_t reserved;
+    const ig_allocator *alloc;  /* NULL: the library's device arena (chunks taken from
+                                   the runtime once and sub-allocated, see
+                                   ig_release_memory); else every model buffer and
+                                   every scratch block of the call comes from it.
+                                   When it fails, the call returns IG_E_NOMEM, frees
+                                   what it took and builds no model.                 */
 } ig_fit_opts;
 
 /* Counters and timings of a fit (Section 3.3 stages). */
@@ -143,6 +163,9 @@ typedef struct {
  * bins of a feature) then runs on the vector ALUs. */
 #define IG_MODEL_SCORE_MFMA 1u
 #define IG_MODEL_FACTORED 2u
+/* IG_MODEL_BUCKETED: the matrix-core scoring tiles are grouped by token bucket
+ * (fits from codes and imported models), so ig_score can prune (ig_score_ex). */
+#define IG_MODEL_BUCKETED 4u
 
 /* One problem of a batched fit. */
 typedef struct {
@@ -191,14 +214,126 @@ ig_status ig_fit_batch(const ig_problem *probs, uint32_t n_probs, const ig_fit_o
  *   d_codes device [n_flows][d] uint16
  *   d_out   device [n_flows][2] int64, written as (A, N) per flow.
  *           A flow with a code >= its feature's bin count gets (-1, -1).
- * Needs no scratch memory; safe to call concurrently on several streams.
+ * Pruned by token buckets when the model has them (see ig_score_ex), with
+ * stream-ordered scratch from the library; safe to call concurrently on several
+ * streams.
  * ------------------------------------------------------------------------- */
 ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out,
                    void *stream);
 
-/* ig_score for flows already packed: d_words device [n_flows][K] uint64. */
+/* ---------------------------------------------------------------------------
+ * ig_score_ex -- ig_score with a choice of kernels; all give identical scores.
+ *   IG_SCORE_DENSE   every flow is tested against every pattern.
+ *   IG_SCORE_PRUNED  exact pruning of Eq. 4: a pattern lies inside a flow only if
+ *                    the flow holds every token of the pattern (Eq. 6).  The model
+ *                    files each pattern under one of its tokens (its bucket: the
+ *                    token the fewest training records hold, or for an imported
+ *                    model the token of the feature with the most bins), and each
+ *                    flow is tested only against the buckets of the d tokens it
+ *                    holds.  Needs IG_MODEL_BUCKETED (IG_E_UNSUPPORTED otherwise)
+ *                    and device scratch of about 4 * (n_flows * d + 5 L) bytes,
+ *                    which the library takes from its stream-ordered cache.
+ *   IG_SCORE_AUTO    pruned when the model is bucketed, else dense (= ig_score).
+ * ------------------------------------------------------------------------- */
+#define IG_SCORE_AUTO 0u
+#define IG_SCORE_DENSE 1u
+#define IG_SCORE_PRUNED 2u
+ig_status ig_score_ex(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out, uint32_t mode,
+                      void *stream);
+
+/* ig_score for flows already packed: d_words device [n_flows][K] uint64 (always
+ * dense: such words may hold several bins of a feature). */
 ig_status ig_score_packed(const ig_model *m, const uint64_t *d_words, uint32_t n_flows,
                           int64_t *d_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * ig_evidence -- the evidence of each flow's scores: the coherent patterns of
+ * each class inside the flow, the terms Eq. 4 sums into A (class 1) and N
+ * (class 0); Sections 2 and 5 present the matched patterns as the readable
+ * account of a detection.  The k reported per (flow, class) are the heaviest:
+ * weight S descending, then the words ascending in the canonical order (w_0 most
+ * significant, unsigned) -- a unique list.  Asynchronous on `stream`.
+ *   d_codes  device [n_flows][d] uint16 (same d and nbins as the model)
+ *   k        1..256 (IG_E_INVAL otherwise)
+ *   d_count  device [n_flows][2] uint32: how many patterns of class 0 / 1 lie
+ *            inside the flow (all of them, not only the k); 0xFFFFFFFF for a flow
+ *            with a code out of range (its slots are zero)
+ *   d_words  device [n_flows][2][k][K] uint64: the patterns, best first
+ *   d_f, d_S device [n_flows][2][k] uint32 / int64: their supports and weights
+ *   Slots past min(k, count) are zero.  Models with token buckets
+ *   (IG_MODEL_BUCKETED) test each flow only against the buckets of its tokens;
+ *   others against every pattern.  One workgroup per (flow, class): meant for
+ *   the flows a caller wants explained, not for whole test sets.
+ * ------------------------------------------------------------------------- */
+ig_status ig_evidence(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, uint32_t k, uint32_t *d_count,
+                      uint64_t *d_words, uint32_t *d_f, int64_t *d_S, void *stream);
+
+/* ===========================================================================
+ * The classifier of Section 3.1 and the detection metrics of Table 2, on the
+ * scores (A, N) that ig_score wrote (device [n][2] int64; (-1, -1) marks a flow
+ * with a code out of range).
+ *   Regulation 1  attack when A >= N
+ *   Regulation 2  attack when A = N = 0 (covered by Regulation 1; reported as the
+ *                 deciding rule)
+ *   Regulation 3  attack when N < mu_N - r sigma_N
+ * Readings: mu_N and sigma_N are the mean and the population standard deviation
+ * of N over the normal (label 0) training records, scored by the model like any
+ * flow; r is a given constant (Table 2 names 0.568).  Regulation 3 is decided
+ * exactly: the real values mu_N - r sigma_N, with r the exact value of the double,
+ * are never rounded.
+ * ======================================================================== */
+
+/* Exact moments of N over the normal records: mu_N = sum / count,
+ * sigma_N^2 = (count * sumsq - sum^2) / count^2. */
+typedef struct {
+    uint64_t count;      /* records labelled 0 with valid scores                  */
+    uint64_t sum[2];     /* sum of N, 128-bit unsigned, least significant word first */
+    uint64_t sumsq[3];   /* sum of N^2, 192-bit unsigned                          */
+} ig_moments;
+
+/* Confusion counts of predicted labels against the truth (attack = positive) and
+ * the AUC of the margin A - N as an exact fraction: over every (attack, normal)
+ * pair of flows, auc_num counts 2 when the attack flow's margin is larger and 1
+ * when they are equal; auc_den = 2 * attacks * normals. */
+typedef struct {
+    uint64_t tp, fp, tn, fn;
+    uint64_t auc_num, auc_den;
+    uint64_t invalid;    /* flows skipped: predicted label 255 (no valid scores)   */
+} ig_metrics;
+
+/* ig_classify flags */
+#define IG_CLASSIFY_R3 1u      /* apply Regulation 3 with the given threshold      */
+#define IG_CLASSIFY_NO_R2 2u   /* report A = N = 0 as decided by Regulation 1      */
+
+/* Moments of N over the records with d_labels[i] == 0 (device [n] uint8, each 0
+ * or 1, IG_E_INVAL otherwise), skipping flows without valid scores.  d_scores
+ * device [n][2].  Synchronous. */
+ig_status ig_normal_moments(const int64_t *d_scores, const uint8_t *d_labels, uint32_t n, ig_moments *out,
+                            void *stream);
+
+/* Regulation 3 as an integer cut: *out = T such that, for every integer N >= 0,
+ * N < mu_N - r sigma_N exactly when N < T.  Host only (exact big-integer
+ * arithmetic).  IG_E_INVAL when r is negative or not finite, or m->count = 0. */
+ig_status ig_r3_threshold(const ig_moments *m, double r, int64_t *out);
+
+/* Labels of n flows: d_label device [n] uint8 (1 attack, 0 normal, 255 for a flow
+ * without valid scores); d_rule device [n] uint8 (may be NULL): the regulation
+ * that decided (1, 2 or 3; 0 when invalid).  Regulation 3 fires when flags has
+ * IG_CLASSIFY_R3 and N < r3_threshold (ig_r3_threshold).  Asynchronous. */
+ig_status ig_classify(const int64_t *d_scores, uint32_t n, int64_t r3_threshold, uint32_t flags, uint8_t *d_label,
+                      uint8_t *d_rule, void *stream);
+
+/* Detection metrics of predicted labels d_pred (device [n], from ig_classify)
+ * against d_truth (device [n] uint8, each 0 or 1, IG_E_INVAL otherwise), with
+ * the AUC ranked by A - N of d_scores.  Synchronous; uses library scratch of
+ * about 40 bytes per flow. */
+ig_status ig_detection_metrics(const int64_t *d_scores, const uint8_t *d_pred, const uint8_t *d_truth, uint32_t n,
+                               ig_metrics *out, void *stream);
+
+/* Patterns of class `cls` filed under each token bucket (diagnostics of pruned
+ * scoring): h_counts host [L] uint32.  IG_E_UNSUPPORTED when the model has no
+ * buckets (IG_MODEL_BUCKETED clear).  Synchronous. */
+ig_status ig_model_bucket_sizes(const ig_model *m, uint32_t cls, uint32_t *h_counts);
 
 /* Sizes of a model. */
 ig_status ig_model_get_info(const ig_model *m, ig_model_info *info);
@@ -232,6 +367,15 @@ ig_status ig_fit_stats(const ig_model *m, ig_stats *out);
 /* Release a model (NULL-safe).  The caller must not free a model while a
  * scoring call that uses it is still queued on a stream. */
 void ig_model_free(ig_model *m);
+
+/* The library's own device memory on the current device (used when no caller
+ * allocator is given): hands cached scratch blocks and wholly free arena chunks
+ * back to the runtime.  Models stay valid.  Waits for the scratch's last users. */
+ig_status ig_release_memory(void);
+
+/* Bytes of the current device's arena: reserved from the runtime, held by models
+ * and live scratch, and cached (freed scratch kept for reuse). */
+ig_status ig_memory_stats(uint64_t *reserved, uint64_t *in_use, uint64_t *cached);
 
 /* Thread-local text of the last error ("" when none). */
 const char *ig_last_error(void);

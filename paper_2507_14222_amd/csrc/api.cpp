@@ -28,147 +28,11 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string &m) { g_last_error = m; }
 
-// ----------------------------------------------------------- scratch cache ----
-// Scratch comes from a per-device cache of device blocks: allocating and freeing
-// multi-hundred-MB buffers through the runtime cost milliseconds of host time per
-// call, during which the GPU idles between the stages of a fit.  A freed block
-// keeps an event recorded on the freeing stream; whoever takes the block next
-// makes its own stream wait for that event first (free when it is the same
-// stream).  Blocks go back to the runtime only when an allocation fails (the
-// cache is emptied and the allocation retried) or the cached bytes pass a cap.
-namespace {
-struct CachedBlock {
-    void *p;
-    size_t bytes;
-    int dev;
-    hipEvent_t ev;
-};
-struct ScratchCache {
-    std::mutex mu;
-    std::vector<CachedBlock> free_blocks;
-    std::unordered_map<void *, std::pair<size_t, int>> live;   // block -> (bytes, device)
-    std::vector<hipEvent_t> spare_events[64];
-    size_t cached_bytes[64] = {};
-};
-ScratchCache &cache() {
-    static ScratchCache *c = new ScratchCache();   // never destroyed: frees may run at exit
-    return *c;
-}
-#ifndef IG_SCRATCH_CACHE_GB
-#define IG_SCRATCH_CACHE_GB 32
-#endif
-constexpr size_t kCacheCap = (size_t)IG_SCRATCH_CACHE_GB << 30;   // cached free bytes per device
-
-size_t round_bytes(size_t b) {
-    if (b <= 4096) return 4096;
-    const int lg = 63 - __builtin_clzll((unsigned long long)(b - 1));
-    const size_t step = (size_t)1 << (lg - 3);   // eight sizes per power of two
-    return (b + step - 1) / step * step;
-}
-
-// release cached blocks of `dev` (caller holds the lock) until at most `keep` bytes remain
-void release_cached(ScratchCache &c, int dev, size_t keep) {
-    std::sort(c.free_blocks.begin(), c.free_blocks.end(),
-              [](const CachedBlock &x, const CachedBlock &y) { return x.bytes < y.bytes; });
-    for (size_t i = c.free_blocks.size(); i-- > 0 && c.cached_bytes[dev] > keep;) {
-        CachedBlock b = c.free_blocks[i];
-        if (b.dev != dev) continue;
-        (void)hipEventSynchronize(b.ev);
-        (void)hipFree(b.p);
-        c.spare_events[dev].push_back(b.ev);
-        c.cached_bytes[dev] -= b.bytes;
-        c.free_blocks.erase(c.free_blocks.begin() + (ptrdiff_t)i);
-    }
-}
-// empty the current device's cache (after a failed allocation outside it)
-void release_all_cached() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
-        (void)hipGetLastError();
-        return;
-    }
-    ScratchCache &c = cache();
-    std::lock_guard<std::mutex> lock(c.mu);
-    release_cached(c, dev, 0);
-}
-}  // namespace
-
-void *scratch_alloc(size_t bytes, hipStream_t s) {
-    int dev = 0;
-    IG_HIP(hipGetDevice(&dev));
-    IG_REQUIRE(dev >= 0 && dev < 64, IG_E_UNSUPPORTED, "device index above 63");
-    const size_t want = round_bytes(bytes ? bytes : 1);
-    ScratchCache &c = cache();
-    std::lock_guard<std::mutex> lock(c.mu);
-    size_t best = SIZE_MAX, bi = 0;
-    for (size_t i = 0; i < c.free_blocks.size(); ++i) {
-        const CachedBlock &b = c.free_blocks[i];
-        if (b.dev == dev && b.bytes >= want && b.bytes <= 2 * want && b.bytes < best) {
-            best = b.bytes;
-            bi = i;
-        }
-    }
-    if (best != SIZE_MAX) {
-        CachedBlock b = c.free_blocks[bi];
-        IG_HIP(hipStreamWaitEvent(s, b.ev, 0));
-        c.free_blocks.erase(c.free_blocks.begin() + (ptrdiff_t)bi);
-        c.spare_events[dev].push_back(b.ev);
-        c.cached_bytes[dev] -= b.bytes;
-        c.live[b.p] = {b.bytes, dev};
-        return b.p;
-    }
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess || !p) {
-        (void)hipGetLastError();
-        release_cached(c, dev, 0);
-        e = hipMalloc(&p, want);
-        if (e != hipSuccess || !p) {
-            (void)hipGetLastError();
-            throw Error(IG_E_NOMEM, "device scratch allocation of " + std::to_string(bytes) + " bytes failed");
-        }
-    }
-    c.live[p] = {want, dev};
-    return p;
-}
-
-void scratch_free(void *p, hipStream_t s) noexcept {
-    if (!p) return;
-    ScratchCache &c = cache();
-    std::lock_guard<std::mutex> lock(c.mu);
-    auto it = c.live.find(p);
-    if (it == c.live.end()) return;
-    const size_t bytes = it->second.first;
-    const int dev = it->second.second;
-    c.live.erase(it);
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    (void)hipStreamIsCapturing(s, &cap);
-    hipEvent_t ev = nullptr;
-    if (cap == hipStreamCaptureStatusNone) {
-        if (!c.spare_events[dev].empty()) {
-            ev = c.spare_events[dev].back();
-            c.spare_events[dev].pop_back();
-        } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-            (void)hipGetLastError();
-            ev = nullptr;
-        }
-    }
-    if (!ev || hipEventRecord(ev, s) != hipSuccess) {
-        // no event to order a later user after this stream's work: wait here instead
-        (void)hipGetLastError();
-        if (ev) c.spare_events[dev].push_back(ev);
-        if (cap == hipStreamCaptureStatusNone) (void)hipStreamSynchronize(s);
-        (void)hipFree(p);
-        return;
-    }
-    c.free_blocks.push_back({p, bytes, dev, ev});
-    c.cached_bytes[dev] += bytes;
-    if (c.cached_bytes[dev] > kCacheCap) release_cached(c, dev, kCacheCap / 2);
-}
-
 // --------------------------------------------------------------- the model ----
 struct DevModel {
     int device = 0;
+    ig_allocator user{};                   // the caller allocator the buffers came from
+    bool has_user = false;                 //   (else the library's arena)
     uint32_t K = 0, KS = 0, L = 0, d = 0;
     uint64_t np[2] = {0, 0};
     uint64_t *W[2] = {nullptr, nullptr};
@@ -178,6 +42,10 @@ struct DevModel {
     uint32_t *meta = nullptr;    // off[d] | flo[KS] | fhi[KS]
     uint16_t *nbins = nullptr;
     uint4 *frag[2] = {nullptr, nullptr};   // matrix-core scoring operands (KS <= 8)
+    uint32_t ftiles[2] = {0, 0};           // 32-row tiles of frag
+    uint32_t *btile[2] = {nullptr, nullptr};   // [L + 1] first tile of each token bucket (fits from codes)
+    uint32_t *brow[2] = {nullptr, nullptr};    // [L + 1] first position of each bucket in bperm
+    uint32_t *bperm[2] = {nullptr, nullptr};   // [np] rows of the class grouped by bucket
     KeyPiece *pieces = nullptr;            // compressed sort keys (fits from codes), or null
     uint32_t npieces = 0, nkeys = 0;
     void *fac = nullptr;                   // factored-token table (one device block)
@@ -190,38 +58,30 @@ struct DevModel {
 
     uint32_t KO() const { return fv.KF ? fv.KF : KS; }
 
+    void release(void *p) const noexcept { device_free(p, device, has_user ? &user : nullptr); }
+
     ~DevModel() {
         for (int c = 0; c < 2; ++c) {
-            if (W[c]) (void)hipFree(W[c]);
-            if (f[c]) (void)hipFree(f[c]);
-            if (S[c]) (void)hipFree(S[c]);
+            release(W[c]);
+            release(f[c]);
+            release(S[c]);
+            release(frag[c]);
+            release(btile[c]);
+            release(brow[c]);
+            release(bperm[c]);
         }
-        for (int c = 0; c < 2; ++c) {
-            if (frag[c]) (void)hipFree(frag[c]);
-        }
-        if (meta) (void)hipFree(meta);
-        if (nbins) (void)hipFree(nbins);
-        if (pieces) (void)hipFree(pieces);
-        if (fac) (void)hipFree(fac);
+        release(meta);
+        release(nbins);
+        release(pieces);
+        release(fac);
     }
 };
 
+// A model buffer of `count` T, from the allocator of the running call (the caller's,
+// or the library's arena); DevModel::release hands it back.
 template <class T>
 static T *dev_alloc(size_t count) {
-    void *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess || !p) {
-        // the scratch cache may hold the memory: hand it back and try once more
-        (void)hipGetLastError();
-        release_all_cached();
-        e = hipMalloc(&p, count * sizeof(T));
-    }
-    if (e != hipSuccess || !p) {
-        (void)hipGetLastError();
-        throw Error(IG_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
-    }
-    return static_cast<T *>(p);
+    return static_cast<T *>(device_alloc((count ? count : 1) * sizeof(T), nullptr, current_user_allocator()));
 }
 
 // Token layout tables for codes with the given bins: off[f], and per storage
@@ -676,7 +536,7 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         m.f[c] = dev_alloc<uint32_t>(final_count);
         m.S[c] = dev_alloc<int64_t>(final_count);
     } catch (...) {
-        if (Wd && m.W[c] != Wd) (void)hipFree(Wd);
+        if (Wd && m.W[c] != Wd) m.release(Wd);
         throw;
     }
     if (tm && support_mark >= 0) tm->mark(support_mark);
@@ -723,12 +583,85 @@ static bool score_spare(const DevModel &m) {
     return used < 64;
 }
 
-static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr) {
+// Costs of the tokens for the choice of each pattern's bucket token (the lowest
+// cost wins): the training records of both classes that hold the token, so that a
+// pattern is filed under the token the fewest flows are expected to hold; for a
+// model without records (imported) the tokens of features with more bins first.
+static Scratch<uint32_t> token_costs(const DevModel &m, const ClassRows *cls, hipStream_t s) {
+    Scratch<uint32_t> cost(m.L, s);
+    if (cls) {
+        launch_fill_u32(cost.get(), 0u, m.L, s);
+        for (int c = 0; c < 2; ++c) launch_token_counts(cls[c].X.get(), cls[c].n, m.KS, m.L, cost.get(), s);
+    } else {
+        std::vector<uint16_t> nb(m.d);
+        IG_HIP(hipMemcpyAsync(nb.data(), m.nbins, m.d * 2, hipMemcpyDeviceToHost, s));
+        IG_HIP(hipStreamSynchronize(s));
+        std::vector<uint32_t> h(m.L, 0);
+        uint32_t t = 0;
+        for (uint32_t f = 0; f < m.d; ++f)
+            for (uint32_t c = 0; c < nb[f]; ++c) h[t++] = 65536u - nb[f];
+        IG_HIP(hipMemcpyAsync(cost.get(), h.data(), m.L * 4, hipMemcpyHostToDevice, s));
+        IG_HIP(hipStreamSynchronize(s));
+    }
+    return cost;
+}
+
+// Scoring operands of class c with its tiles grouped by bucket token (every tile
+// holds patterns of one bucket; a bucket's last tile is padded with empty rows of
+// weight 0): m.frag[c], m.ftiles[c] and m.btile[c].
+static void bucketed_operands(DevModel &m, int c, const uint64_t *rows, uint32_t KO, const uint32_t *cost,
+                              hipStream_t s) {
+    const size_t np = m.np[c];
+    const uint32_t L = m.L;
+    Scratch<uint64_t> key(np, s), key2(np, s);
+    Scratch<uint32_t> perm(np, s), perm2(np, s), err(1, s), first(L, s);
+    launch_fill_u32(err.get(), 0u, 1, s);
+    launch_bucket_keys(m.W[c], np, m.KS, L, cost, key.get(), err.get(), s);
+    launch_iota(perm.get(), np, s);
+    const uint32_t digits = L <= 256 ? 0x1u : 0x3u;
+    const int where = radix_sort_pairs(key.get(), perm.get(), key2.get(), perm2.get(), np, digits, s);
+    const uint64_t *sk = where ? key2.get() : key.get();
+    const uint32_t *P = where ? perm2.get() : perm.get();
+    launch_fill_u32(first.get(), ~0u, L, s);
+    launch_bucket_first(sk, np, first.get(), s);
+    std::vector<uint32_t> hf = host_read_u32(first.get(), L, s);
+    IG_REQUIRE(host_read_u32(err.get(), 1, s)[0] == 0, IG_E_DEVICE, "a pattern without a token");
+    // bucket sizes from the first positions; first tile and first position of each bucket
+    std::vector<uint32_t> bt(L + 1, 0), cnt(L, 0);
+    uint32_t next = (uint32_t)np;
+    for (int u = (int)L - 1; u >= 0; --u) {
+        if (hf[u] == ~0u) continue;
+        cnt[u] = next - hf[u];
+        next = hf[u];
+    }
+    std::vector<uint32_t> br(L + 1, 0);
+    for (uint32_t u = 0; u < L; ++u) {
+        bt[u + 1] = bt[u] + (cnt[u] + 31) / 32;
+        br[u + 1] = br[u] + cnt[u];
+    }
+    const uint32_t ntiles = bt[L];
+    m.btile[c] = dev_alloc<uint32_t>(L + 1);
+    IG_HIP(hipMemcpyAsync(m.btile[c], bt.data(), (L + 1) * 4, hipMemcpyHostToDevice, s));
+    // the rows of each bucket: for the tiles below and the evidence of a flow (ig_evidence)
+    m.brow[c] = dev_alloc<uint32_t>(L + 1);
+    IG_HIP(hipMemcpyAsync(m.brow[c], br.data(), (L + 1) * 4, hipMemcpyHostToDevice, s));
+    m.bperm[c] = dev_alloc<uint32_t>(np);
+    IG_HIP(hipMemcpyAsync(m.bperm[c], P, np * 4, hipMemcpyDeviceToDevice, s));
+    m.ftiles[c] = ntiles;
+    m.frag[c] = dev_alloc<uint4>((size_t)std::max<uint32_t>(ntiles, 1) * (KO + 1) * 64);
+    launch_mfma_patterns(rows, m.S[c], (uint32_t)np, KO, score_spare(m), m.frag[c], s, P, m.btile[c], m.brow[c], L,
+                         ntiles);
+    IG_HIP(hipStreamSynchronize(s));   // the host tables above are freed on return
+}
+
+static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr, const ClassRows *cls) {
     const uint32_t KO = m.KO();
     if (KO > 8 || m.maxS[0] >= (1ll << 28) || m.maxS[1] >= (1ll << 28)) return;
+    // fits from codes and imported models group their tiles by token for pruned scoring
+    const bool bucketed = m.d > 0 && m.L <= 4096;
+    Scratch<uint32_t> cost;
+    if (bucketed) cost = token_costs(m, cls, s);
     for (int c = 0; c < 2; ++c) {
-        const uint64_t ntiles = (m.np[c] + 31) / 32;
-        m.frag[c] = dev_alloc<uint4>(std::max<uint64_t>(ntiles, 1) * (KO + 1) * 64);
         Scratch<uint64_t> own;
         const uint64_t *rows;
         if (pr && pr->valid[c]) {
@@ -738,6 +671,20 @@ static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr) {
             launch_operand_rows(nullptr, 0, nullptr, m.W[c], m.KS, m.np[c], m.fv, false, own.get(), s);
             rows = own.get();
         }
+        if (bucketed && m.np[c]) {
+            bucketed_operands(m, c, rows, KO, cost.get(), s);
+            continue;
+        }
+        if (bucketed) {   // an empty class: no tiles or rows in any bucket
+            m.btile[c] = dev_alloc<uint32_t>(m.L + 1);
+            launch_fill_u32(m.btile[c], 0u, m.L + 1, s);
+            m.brow[c] = dev_alloc<uint32_t>(m.L + 1);
+            launch_fill_u32(m.brow[c], 0u, m.L + 1, s);
+            m.bperm[c] = dev_alloc<uint32_t>(1);
+        }
+        const uint64_t ntiles = (m.np[c] + 31) / 32;
+        m.ftiles[c] = (uint32_t)ntiles;
+        m.frag[c] = dev_alloc<uint4>(std::max<uint64_t>(ntiles, 1) * (KO + 1) * 64);
         launch_mfma_patterns(rows, m.S[c], (uint32_t)m.np[c], KO, score_spare(m), m.frag[c], s);
     }
     m.score_factored = m.fv.KF > 0;
@@ -745,7 +692,7 @@ static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr) {
     IG_HIP(hipStreamSynchronize(s));
 }
 
-static void finish_weights(DevModel &m, hipStream_t s, PatternRows *pr = nullptr) {
+static void finish_weights(DevModel &m, hipStream_t s, PatternRows *pr = nullptr, const ClassRows *cls = nullptr) {
     Scratch<unsigned long long> ms(4, s);
     for (int c = 0; c < 2; ++c) launch_reduce_maxsum(m.S[c], m.np[c], ms.get() + 2 * c, s);
     unsigned long long h[4];
@@ -757,7 +704,7 @@ static void finish_weights(DevModel &m, hipStream_t s, PatternRows *pr = nullptr
         IG_REQUIRE(h[2 * c + 1] <= (unsigned long long)INT64_MAX, IG_E_OVERFLOW,
                    "sum of pattern weights exceeds int64");
     }
-    build_score_operands(m, s, pr);
+    build_score_operands(m, s, pr, cls);
 }
 
 // Ends of the coherence phases over the other class's records.  One phase (the
@@ -1088,7 +1035,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         if (c == 0) tm.mark(3);   // end of class 0's support
     }
     tm.mark(6);
-    finish_weights(m, s, &prow);
+    finish_weights(m, s, &prow, cls);
     tm.mark(7);
     IG_HIP(hipStreamSynchronize(s));
     m.stats.ms[1] = ms_pairs;
@@ -1109,6 +1056,10 @@ static void alloc_class_rows(ClassRows cls[2], const uint32_t *counts, uint32_t 
 static DevModel *new_model() {
     DevModel *m = new DevModel();
     IG_HIP(hipGetDevice(&m->device));
+    if (const ig_allocator *u = current_user_allocator()) {
+        m->user = *u;
+        m->has_user = true;
+    }
     return m;
 }
 
@@ -1428,7 +1379,7 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
             if (c == 0) tm.mark(3);
         }
         tm.mark(6);
-        finish_weights(m, s, &prow);
+        finish_weights(m, s, &prow, G[g]->cls);
         tm.mark(7);
         IG_HIP(hipStreamSynchronize(s));
         record_times(m, tm);
@@ -1586,6 +1537,7 @@ ig_status ig_fit(const uint16_t *d_codes, const uint8_t *d_labels, uint32_t n, u
                  const ig_fit_opts *opts, void *stream, ig_model **out) {
     return guarded([&] {
         IG_REQUIRE(out != nullptr, IG_E_INVAL, "out is NULL");
+        ig::UserAllocScope scope(opts ? opts->alloc : nullptr);
         DevModel *m = ig::fit_codes(d_codes, d_labels, n, d, h_nbins, opts, (hipStream_t)stream);
         *out = wrap(m);
     });
@@ -1595,6 +1547,7 @@ ig_status ig_fit_packed(const uint64_t *d_words, const uint8_t *d_labels, uint32
                         const ig_fit_opts *opts, void *stream, ig_model **out) {
     return guarded([&] {
         IG_REQUIRE(out != nullptr, IG_E_INVAL, "out is NULL");
+        ig::UserAllocScope scope(opts ? opts->alloc : nullptr);
         DevModel *m = ig::fit_packed(d_words, d_labels, n, K, opts, (hipStream_t)stream);
         *out = wrap(m);
     });
@@ -1604,6 +1557,7 @@ ig_status ig_fit_batch(const ig_problem *probs, uint32_t n_probs, const ig_fit_o
                        ig_model **outs) {
     return guarded([&] {
         IG_REQUIRE(outs != nullptr && (n_probs == 0 || probs != nullptr), IG_E_INVAL, "NULL argument");
+        ig::UserAllocScope scope(opts ? opts->alloc : nullptr);
         std::vector<DevModel *> made;
         try {
             ig::fit_batch(probs, n_probs, opts, (hipStream_t)stream, made);
@@ -1648,7 +1602,10 @@ static ig::ScoreModel score_model(const ig::DevModel &M) {
         sm.np[c] = M.np[c];
         sm.maxS[c] = M.maxS[c];
         sm.frag[c] = M.frag[c];
+        sm.ftiles[c] = M.ftiles[c];
+        sm.btile[c] = M.btile[c];
     }
+    sm.nbucket = (M.btile[0] && M.btile[1]) ? M.L : 0u;
     sm.KS = M.KS;
     sm.KO = M.score_factored ? M.fv.KF : M.KS;
     if (M.score_factored) sm.fv = M.fv;
@@ -1656,19 +1613,34 @@ static ig::ScoreModel score_model(const ig::DevModel &M) {
     return sm;
 }
 
-ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out, void *stream) {
+ig_status ig_score_ex(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out, uint32_t mode,
+                      void *stream) {
     return guarded([&] {
         check_model(m);
         const DevModel &M = *m->m;
         IG_REQUIRE(M.d > 0, IG_E_INVAL, "model was fitted from packed words: use ig_score_packed");
         IG_REQUIRE(n_flows < (1u << 31), IG_E_UNSUPPORTED, "n_flows must be below 2^31");
         IG_REQUIRE(n_flows == 0 || (d_codes && d_out), IG_E_INVAL, "codes or out is NULL");
+        IG_REQUIRE(mode <= IG_SCORE_PRUNED, IG_E_INVAL, "unknown scoring mode");
         const ig::ScoreModel sm = score_model(M);
-        if (M.frag[0] && M.frag[1])
-            ig::launch_score_mfma(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, (hipStream_t)stream);
+        hipStream_t s = (hipStream_t)stream;
+        const bool mfma = M.frag[0] && M.frag[1];
+        IG_REQUIRE(mode != IG_SCORE_PRUNED || (mfma && sm.nbucket), IG_E_UNSUPPORTED,
+                   "the model's scoring tiles are not grouped by token");
+        if (mfma && sm.nbucket && mode != IG_SCORE_DENSE) {
+            ig::Scratch<uint32_t> ws(ig::prune_scratch_words(sm.nbucket, n_flows, M.d), s);
+            if (ig::launch_score_mfma_pruned(sm, d_codes, n_flows, M.d, M.meta, M.nbins, d_out, ws.get(), s)) return;
+            IG_REQUIRE(mode != IG_SCORE_PRUNED, IG_E_UNSUPPORTED, "too many flows for one pruned scoring launch");
+        }
+        if (mfma)
+            ig::launch_score_mfma(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, s);
         else
-            ig::launch_score(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, (hipStream_t)stream);
+            ig::launch_score(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, s);
     });
+}
+
+ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out, void *stream) {
+    return ig_score_ex(m, d_codes, n_flows, d_out, IG_SCORE_AUTO, stream);
 }
 
 ig_status ig_score_packed(const ig_model *m, const uint64_t *d_words, uint32_t n_flows, int64_t *d_out,
@@ -1687,6 +1659,84 @@ ig_status ig_score_packed(const ig_model *m, const uint64_t *d_words, uint32_t n
     });
 }
 
+ig_status ig_evidence(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, uint32_t k, uint32_t *d_count,
+                      uint64_t *d_words, uint32_t *d_f, int64_t *d_S, void *stream) {
+    return guarded([&] {
+        check_model(m);
+        const DevModel &M = *m->m;
+        IG_REQUIRE(M.d > 0, IG_E_INVAL, "model was fitted from packed words: flows are given as codes");
+        IG_REQUIRE(k >= 1 && k <= ig::evidence_max_k(), IG_E_INVAL, "k must be in 1..256");
+        IG_REQUIRE(n_flows < (1u << 31), IG_E_UNSUPPORTED, "n_flows must be below 2^31");
+        IG_REQUIRE(n_flows == 0 || (d_codes && d_count && d_words && d_f && d_S), IG_E_INVAL, "NULL argument");
+        IG_REQUIRE(M.np[0] < (1ull << 32) && M.np[1] < (1ull << 32), IG_E_UNSUPPORTED,
+                   "more than 2^32 patterns in one class");
+        ig::EvidenceModel em{};
+        for (int c = 0; c < 2; ++c) {
+            em.W[c] = M.W[c];
+            em.f[c] = M.f[c];
+            em.S[c] = M.S[c];
+            em.np[c] = M.np[c];
+            em.bperm[c] = (M.bperm[0] && M.bperm[1]) ? M.bperm[c] : nullptr;
+            em.brow[c] = (M.bperm[0] && M.bperm[1]) ? M.brow[c] : nullptr;
+        }
+        em.KS = M.KS;
+        em.K = M.K;
+        em.d = M.d;
+        em.off = M.meta;
+        em.nbins = M.nbins;
+        ig::launch_evidence(em, d_codes, n_flows, k, d_count, d_words, d_f, d_S, (hipStream_t)stream);
+    });
+}
+
+ig_status ig_normal_moments(const int64_t *d_scores, const uint8_t *d_labels, uint32_t n, ig_moments *out,
+                            void *stream) {
+    return guarded([&] {
+        IG_REQUIRE(out && (n == 0 || (d_scores && d_labels)), IG_E_INVAL, "NULL argument");
+        ig_moments mo{};
+        if (n) ig::normal_moments(d_scores, d_labels, n, &mo, (hipStream_t)stream);
+        *out = mo;
+    });
+}
+
+ig_status ig_r3_threshold(const ig_moments *m, double r, int64_t *out) {
+    return guarded([&] {
+        IG_REQUIRE(m && out, IG_E_INVAL, "NULL argument");
+        *out = ig::r3_threshold(*m, r);
+    });
+}
+
+ig_status ig_classify(const int64_t *d_scores, uint32_t n, int64_t r3_threshold, uint32_t flags, uint8_t *d_label,
+                      uint8_t *d_rule, void *stream) {
+    return guarded([&] {
+        IG_REQUIRE(n == 0 || (d_scores && d_label), IG_E_INVAL, "scores or labels is NULL");
+        IG_REQUIRE(!(flags & ~(IG_CLASSIFY_R3 | IG_CLASSIFY_NO_R2)), IG_E_INVAL, "unknown classify flags");
+        ig::classify(d_scores, n, r3_threshold, flags, d_label, d_rule, (hipStream_t)stream);
+    });
+}
+
+ig_status ig_detection_metrics(const int64_t *d_scores, const uint8_t *d_pred, const uint8_t *d_truth, uint32_t n,
+                               ig_metrics *out, void *stream) {
+    return guarded([&] {
+        IG_REQUIRE(out && (n == 0 || (d_scores && d_pred && d_truth)), IG_E_INVAL, "NULL argument");
+        IG_REQUIRE(n < (1u << 31), IG_E_UNSUPPORTED, "n must be below 2^31");
+        ig_metrics mt{};
+        ig::detection_metrics(d_scores, d_pred, d_truth, n, &mt, (hipStream_t)stream);
+        *out = mt;
+    });
+}
+
+ig_status ig_model_bucket_sizes(const ig_model *m, uint32_t cls, uint32_t *h_counts) {
+    return guarded([&] {
+        check_model(m);
+        IG_REQUIRE(cls <= 1 && h_counts, IG_E_INVAL, "class must be 0 or 1 and h_counts non-NULL");
+        const DevModel &M = *m->m;
+        IG_REQUIRE(M.brow[0] && M.brow[1], IG_E_UNSUPPORTED, "the model has no token buckets");
+        std::vector<uint32_t> br(M.L + 1);
+        IG_HIP(hipMemcpy(br.data(), M.brow[cls], (M.L + 1) * 4, hipMemcpyDeviceToHost));
+        for (uint32_t u = 0; u < M.L; ++u) h_counts[u] = br[u + 1] - br[u];
+    });
+}
+
 ig_status ig_model_get_info(const ig_model *m, ig_model_info *info) {
     return guarded([&] {
         IG_REQUIRE(m && m->m && info, IG_E_INVAL, "model or info is NULL");
@@ -1696,7 +1746,8 @@ ig_status ig_model_get_info(const ig_model *m, ig_model_info *info) {
         info->L = M.L;
         info->d = M.d;
         info->flags = ((M.frag[0] && M.frag[1]) ? IG_MODEL_SCORE_MFMA : 0u) |
-                      (M.score_factored ? IG_MODEL_FACTORED : 0u);
+                      (M.score_factored ? IG_MODEL_FACTORED : 0u) |
+                      ((M.frag[0] && M.frag[1] && M.btile[0] && M.btile[1]) ? IG_MODEL_BUCKETED : 0u);
         info->mfma_tokens = M.score_factored ? M.fac_tokens : M.L;
         info->mfma_words = M.score_factored ? M.fv.KF : M.K;
         for (int c = 0; c < 2; ++c) {
@@ -1749,6 +1800,17 @@ void ig_model_free(ig_model *m) {
     if (!m) return;
     delete m->m;
     delete m;
+}
+
+ig_status ig_release_memory(void) {
+    return guarded([&] { ig::release_memory(); });
+}
+
+ig_status ig_memory_stats(uint64_t *reserved, uint64_t *in_use, uint64_t *cached) {
+    return guarded([&] {
+        IG_REQUIRE(reserved && in_use && cached, IG_E_INVAL, "NULL argument");
+        ig::memory_stats(reserved, in_use, cached);
+    });
 }
 
 const char *ig_last_error(void) { return ig::g_last_error.c_str(); }

@@ -31,11 +31,30 @@ struct Error : std::runtime_error {
     } while (0)
 
 // ------------------------------------------------------------ device memory ----
-// Stream-ordered scratch from a per-device block cache: a block freed on one
-// stream is handed to a later allocation only after that allocation's stream
-// has been made to wait for the freeing stream's work.
+// (memory.cpp) Stream-ordered scratch from a per-device block cache over the
+// library's arena: a block freed on one stream is handed to a later allocation
+// only after that allocation's stream has been made to wait for the freeing
+// stream's work.  While a UserAllocScope with a caller allocator is alive on the
+// thread, scratch comes from that allocator instead.
 void *scratch_alloc(size_t bytes, hipStream_t s);
 void scratch_free(void *p, hipStream_t s) noexcept;
+// Long-lived buffers (models): from `user` when non-null, else the arena of the
+// current device; device_free takes the device the buffer was allocated on.
+void *device_alloc(size_t bytes, hipStream_t s, const ig_allocator *user);
+void device_free(void *p, int dev, const ig_allocator *user) noexcept;
+// The caller allocator of the running call (null: the library's arena).
+struct UserAllocScope {
+    const ig_allocator *prev;
+    explicit UserAllocScope(const ig_allocator *a);
+    ~UserAllocScope();
+    UserAllocScope(const UserAllocScope &) = delete;
+    UserAllocScope &operator=(const UserAllocScope &) = delete;
+};
+const ig_allocator *current_user_allocator();
+// Cached scratch and wholly free arena chunks of the current device back to the
+// runtime; the arena's sizes on the current device.
+void release_memory();
+void memory_stats(uint64_t *reserved, uint64_t *in_use, uint64_t *cached);
 
 template <class T>
 struct Scratch {

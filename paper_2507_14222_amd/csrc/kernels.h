@@ -182,10 +182,34 @@ struct ScoreModel {
     uint32_t KS;
     int64_t maxS[2];            // largest weight of each class
     const uint4 *frag[2];       // matrix-core operands of the patterns and weights (or null)
+    uint32_t ftiles[2];         // 32-row tiles of frag
     uint32_t KO;                // operand words of frag (factored or one-hot)
     FactorView fv;              // the factoring of frag (fv.KF = 0: one-hot)
     bool spare;                 // frag holds +1.0 at the unused last token (see k_mfma_patterns)
+    const uint32_t *btile[2];   // [nbucket + 1]: first tile of each token bucket (null: not bucketed)
+    uint32_t nbucket;           // buckets = tokens L
 };
+
+// prune.hip -- token buckets (see prune.hip).
+// cnt[u] += records of X [n][KS] holding token u < L (cnt preset by the caller)
+void launch_token_counts(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, uint32_t *cnt, hipStream_t s);
+// key[e] = the token of row e with the smallest cost[token] (lowest token on ties)
+void launch_bucket_keys(const uint64_t *W, size_t m, uint32_t KS, uint32_t L, const uint32_t *cost, uint64_t *key,
+                        uint32_t *err, hipStream_t s);
+// first[key[e]] = e where ascending keys change (first preset by the caller)
+void launch_bucket_first(const uint64_t *key, size_t m, uint32_t *first, hipStream_t s);
+// Per-call work of pruned scoring, carved from prune_scratch_words(L, n, d) u32.
+struct PruneWork {
+    uint32_t *cnt, *cursor, *foff, *uoff, *queue, *list;
+};
+size_t prune_scratch_words(uint32_t L, uint32_t n_flows, uint32_t d);
+PruneWork prune_work(uint32_t *ws, uint32_t L);
+// Lists of the valid flows holding each token, work units of SC_COLS-flow blocks
+// and rt-tile ranges per (class, bucket), and out initialised ((0,0) valid,
+// (-1,-1) invalid flows).
+void launch_prune_lists(const uint16_t *codes, uint32_t n, uint32_t d, const uint32_t *off, const uint16_t *nbins,
+                        uint32_t L, const uint32_t *bt0, const uint32_t *bt1, uint32_t rt, uint32_t cols,
+                        int64_t *out, PruneWork &w, hipStream_t s);
 // Scoring on the matrix cores (KO <= 8, every weight < 2^28): each 32-pattern tile
 // of frag holds the patterns' operand rows (KO * 64 uint4, tokens as -1.0) and the
 // int8 operand of their 7-bit weight chunks (64 uint4): ceil(m/32) * (KO + 1) * 64
@@ -194,17 +218,53 @@ struct ScoreModel {
 // spare: the last token of the last word is used by no row; it then carries the
 // +1 that starts each containment count (flows hold 1 there), so the accumulators
 // can start at 0.
+// With buckets (bt, brow: [L + 1] each, ntiles = bt[L]), the tiles [bt[u], bt[u + 1])
+// hold positions [brow[u], brow[u + 1]) of the order perm, row perm[e] at position
+// e (perm may be null: the identity); without, ntiles is ceil(m / 32) and tile t
+// holds rows 32 t ...
 void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, bool spare, uint4 *frag,
-                          hipStream_t s);
+                          hipStream_t s, const uint32_t *perm = nullptr, const uint32_t *bt = nullptr,
+                          const uint32_t *brow = nullptr, uint32_t L = 0, uint32_t ntiles = 0);
 void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K,
                        uint32_t n_flows, uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out,
                        hipStream_t s);
+// Eq. 4 on the matrix cores for flows given as codes, each flow tested only against
+// the token buckets of its own tokens (m.btile non-null).  ws: prune_scratch_words(
+// m.nbucket, n_flows, d) u32 of device scratch, used until the stream reaches the
+// end of the call.  false (nothing launched) when the work units of the call could
+// overflow 32-bit counts; the caller then scores densely.
+bool launch_score_mfma_pruned(const ScoreModel &m, const uint16_t *codes, uint32_t n_flows, uint32_t d,
+                              const uint32_t *meta, const uint16_t *nbins, int64_t *out, uint32_t *ws, hipStream_t s);
 // Eq. 4 for n_flows flows: codes [n][d] (meta = off|flo|fhi, nbins) or packed
 // words [n][K].  out [n][2] = (A, N) is initialised by the launcher.
 void launch_score(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K, uint32_t n_flows,
                   uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out, int fpl, hipStream_t s);
 
 void launch_reduce_maxsum(const int64_t *S, size_t m, unsigned long long *d_max_sum /*[2]*/, hipStream_t s);
+
+// evidence.hip -- the heaviest patterns inside each flow (see ig_evidence)
+struct EvidenceModel {
+    const uint64_t *W[2];
+    const uint32_t *f[2];
+    const int64_t *S[2];
+    uint64_t np[2];
+    const uint32_t *bperm[2];   // rows grouped by token bucket, or null (scan every row)
+    const uint32_t *brow[2];    // [L + 1] bucket starts in bperm
+    uint32_t KS, K, d;
+    const uint32_t *off;        // token offset of each feature
+    const uint16_t *nbins;
+};
+uint32_t evidence_max_k();
+void launch_evidence(const EvidenceModel &m, const uint16_t *codes, uint32_t n, uint32_t k, uint32_t *count,
+                     uint64_t *words, uint32_t *f, int64_t *S, hipStream_t s);
+
+// regulate.hip -- Regulations 1-3 and the detection metrics (Section 3.1, Table 2)
+void normal_moments(const int64_t *scores, const uint8_t *labels, uint32_t n, ig_moments *h, hipStream_t s);
+int64_t r3_threshold(const ig_moments &mo, double r);
+void classify(const int64_t *scores, uint32_t n, int64_t r3_cut, uint32_t flags, uint8_t *label, uint8_t *rule,
+              hipStream_t s);
+void detection_metrics(const int64_t *scores, const uint8_t *pred, const uint8_t *truth, uint32_t n, ig_metrics *h,
+                       hipStream_t s);
 
 // probe.hip -- attainable peaks (include/ig_probe.h); both wait for the stream
 double probe_mfma_fp4(uint32_t iters, hipStream_t s, float *ms);                          // operations/s

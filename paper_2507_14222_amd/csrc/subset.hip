@@ -512,14 +512,32 @@ __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return 
 // One wave per 32-row tile (four per workgroup): lane l takes row l % 32 and half
 // l / 32 of every word, and each slice is one contiguous 1 KB store.  The weight
 // slice gathers the 16 rows of a lane's accumulators with lane shuffles.
+// With buckets, the tiles of bucket u are [bt[u], bt[u + 1]) and hold positions
+// [brow[u], brow[u + 1]) of the order perm (position e is row perm[e]), 32 per
+// tile, the last tile of a bucket padded with empty rows: every tile holds the
+// patterns of one bucket only.  Without, tile t holds rows [32 t, 32 t + 32).
 __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restrict__ W, const int64_t *__restrict__ S,
                                                       uint32_t m, uint32_t KS, uint32_t ntiles, bool spare,
+                                                      const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bt,
+                                                      const uint32_t *__restrict__ brow, uint32_t L,
                                                       uint4 *__restrict__ frag) {
     const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;   // uniform over the wave
     const uint32_t lane = threadIdx.x & 63, half = lane >> 5, r = lane & 31;
-    const uint32_t row = tile * 32 + r;
-    const bool in = row < m;
+    uint32_t pos = tile * 32 + r;
+    bool in = pos < m;
+    if (bt) {
+        // the bucket u of the tile: bt[u] <= tile < bt[u + 1] (bt[0] = 0, bt[L] = ntiles)
+        uint32_t lo = 0, hi = L;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (bt[mid] <= tile) lo = mid;
+            else hi = mid;
+        }
+        pos = brow[lo] + (tile - bt[lo]) * 32 + r;
+        in = pos < brow[lo + 1];
+    }
+    const uint32_t row = in ? (perm ? perm[pos] : pos) : 0u;
     uint4 *dst = frag + (size_t)tile * (KS + 1) * 64;
     uint64_t wv[8];
 #pragma unroll
@@ -584,6 +602,146 @@ struct ScoreMfmaArgs {
     FactorView fv;              // fv.KF > 0: flows (codes) are factored like the patterns
 };
 
+// B operand of flow t for one 32-column set of a wave (lane half `half` supplies
+// the 32-token halves): the complement of its one-hot words, or the signed side
+// of its factored tokens.  Returns whether the flow is active with every code in
+// range; otherwise its operand is the empty set, inside which no pattern lies.
+template <int KS, bool SPARE>
+__device__ __forceinline__ bool flow_operand(const ScoreMfmaArgs &a, uint32_t t, bool act, int half,
+                                             v8i_t (&b)[KS]) {
+    uint64_t wd[KS];
+    bool ok = act;
+    if (a.fv.KF) {
+        // factored tokens: the flow is the signed side (FactorView::tok).  Its
+        // bit tokens come from its factored row (bin bit 0: +1.0, 1: -1.0), its
+        // presence tokens from the popcounts of its bin indices; an inactive or
+        // invalid flow is +1.0 on every token (the empty set: no pattern lies inside)
+        const uint16_t *row = a.codes + (size_t)(act ? t : 0u) * a.d;
+        if (act)
+            for (uint32_t ft = 0; ft < a.d; ++ft) ok &= row[ft] < a.nbins[ft];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            uint64_t v = 0;   // the flow's factored word k (pattern side: bits and presence)
+            uint64_t lo = 0x2222222222222222ull, hi = 0x2222222222222222ull;
+            if (ok) {
+                for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
+                    const FacFeature ft = a.fv.feat[f];
+                    if ((uint32_t)k - ft.w0 >= ft.nw) continue;
+                    v |= a.fv.mask[ft.mask + (uint32_t)row[f] * ft.nw + (k - ft.w0)];
+                }
+                const uint64_t bw = a.fv.bitw[k];
+                const uint32_t ones = (uint32_t)((v & bw) >> (32 * half)), zeros = (uint32_t)((~v & bw) >> (32 * half));
+                lo = (uint64_t)(spread8(zeros) | spread8(ones) * 5u) |
+                     (uint64_t)(spread8(zeros >> 8) | spread8(ones >> 8) * 5u) << 32;
+                hi = (uint64_t)(spread8(zeros >> 16) | spread8(ones >> 16) * 5u) |
+                     (uint64_t)(spread8(zeros >> 24) | spread8(ones >> 24) * 5u) << 32;
+                for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
+                    const uint32_t pt = a.fv.ptok[f];
+                    if (pt == ~0u) continue;
+                    const uint32_t pc = __popc(row[f]);
+                    for (uint32_t part = 0; part < (pt >> 24); ++part) {
+                        const uint32_t tk = (pt & 0xffffffu) + part;
+                        if (tk / 64 != (uint32_t)k || (tk % 64) / 32 != (uint32_t)half) continue;
+                        const uint32_t j = tk % 32;
+                        const uint64_t nib = signed_nibble(2u + part, 0u, pc);
+                        if (j < 16) lo |= nib << (4 * j);
+                        else hi |= nib << (4 * (j - 16));
+                    }
+                }
+            }
+            // the spare token is +1.0 in every flow (it carries the count's starting +1)
+            if (SPARE && k == KS - 1 && half) hi = (hi & 0x0fffffffffffffffull) | 0x2000000000000000ull;
+            b[k] = v8i_t{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
+                         (int)(uint32_t)(hi >> 32), 0, 0, 0, 0};
+        }
+        return ok;
+    }
+    if (act && a.codes) {
+        const uint16_t *row = a.codes + (size_t)t * a.d;
+        const uint32_t *off = a.meta, *flo = a.meta + a.d, *fhi = a.meta + a.d + KS;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            uint64_t v = 0;
+            for (uint32_t ft = flo[k]; ft < fhi[k]; ++ft) {
+                const uint32_t c = row[ft];
+                ok &= c < a.nbins[ft];
+                const uint32_t bit = off[ft] + c;
+                if ((bit >> 6) == (uint32_t)k) v |= 1ull << (bit & 63);
+            }
+            wd[k] = v;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) wd[k] = (act && k < (int)a.K) ? a.words[(size_t)t * a.K + k] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        // NOT t; an inactive or invalid flow is the empty set, which contains no pattern.
+        // The spare token is 1 in every flow (it carries the count's starting +1).
+        uint64_t nt = ok ? ~wd[k] : ~0ull;
+        if (SPARE && k == KS - 1) nt |= 1ull << 63;
+        const uint32_t dwd = (uint32_t)(nt >> (32 * half));
+        b[k] = v8i_t{(int)spread8(dwd), (int)spread8(dwd >> 8), (int)spread8(dwd >> 16), (int)spread8(dwd >> 24),
+                     0, 0, 0, 0};
+    }
+    return ok;
+}
+
+// One 32-pattern tile against the wave's column sets: the containment counts on
+// the fp4 matrix cores, then the weighting product adds the weight chunks of the
+// patterns inside each flow to C.
+template <int KS, bool SPARE>
+__device__ __forceinline__ void score_tile(const uint4 *tile, int lane, const v8i_t (&b)[MF_FB][KS],
+                                           v16i_t (&C)[MF_FB]) {
+    // the count starts at +1: from the spare token, or here
+    v16f_t acc[MF_FB];
+#pragma unroll
+    for (int f = 0; f < MF_FB; ++f)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[f][r] = SPARE ? 0.0f : 1.0f;
+#pragma unroll
+    for (int w = 0; w < KS; ++w) {
+        const uint4 a4 = tile[w * 64 + lane];
+        const v8i_t av = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+#pragma unroll
+        for (int f = 0; f < MF_FB; ++f)
+            acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
+    }
+    // weight chunks of this tile as the A operand (rows c < 4; other rows zero)
+    const uint4 q = tile[KS * 64 + lane];
+    const v4i_t wa = {(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+#pragma unroll
+    for (int f = 0; f < MF_FB; ++f) {
+        // inside = max(acc, 0) as a byte (1 or 0), accumulator r -> byte r
+        v4i_t z;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            uint32_t d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * qq], 0, 0u);
+            d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * qq + 1], 1, d);
+            d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * qq + 2], 2, d);
+            d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * qq + 3], 3, d);
+            z[qq] = (int)d;
+        }
+        C[f] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wa, z, C[f], 0, 0, 0);
+    }
+}
+
+// Adds the weighting sums of the wave's valid flows to their column of out (A from
+// class 1, N from class 0).
+__device__ __forceinline__ void score_flush(int64_t *out, int cls, int half, const v16i_t (&C)[MF_FB],
+                                            const uint32_t (&tf)[MF_FB], const bool (&valid)[MF_FB]) {
+    const int colsel = cls == 1 ? 0 : 1;
+#pragma unroll
+    for (int f = 0; f < MF_FB; ++f) {
+        uint64_t v = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v += (uint64_t)(uint32_t)C[f][c] << (7 * c);
+        if (half == 0 && valid[f] && v)
+            atomicAdd(reinterpret_cast<unsigned long long *>(out + 2 * (size_t)tf[f] + colsel),
+                      (unsigned long long)v);
+    }
+}
+
 // Workgroup (range, flow block): the fblocks workgroups that read the same range
 // of pattern tiles get ids that differ by multiples of 8, so they are dispatched
 // to one XCD and share its L2.  The ranges split the tiles of both classes, taken
@@ -608,83 +766,7 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     for (int f = 0; f < MF_FB; ++f) {
         const uint32_t t = fb * SC_COLS + wave * (MF_FB * 32) + f * 32 + col;
         tf[f] = t;
-        const bool act = t < a.n_flows;
-        uint64_t wd[KS];
-        bool ok = act;
-        if (a.fv.KF) {
-            // factored tokens: the flow is the signed side (FactorView::tok).  Its
-            // bit tokens come from its factored row (bin bit 0: +1.0, 1: -1.0), its
-            // presence tokens from the popcounts of its bin indices; an inactive or
-            // invalid flow is +1.0 on every token (the empty set: no pattern lies inside)
-            const uint16_t *row = a.codes + (size_t)(act ? t : 0u) * a.d;
-            if (act)
-                for (uint32_t ft = 0; ft < a.d; ++ft) ok &= row[ft] < a.nbins[ft];
-#pragma unroll
-            for (int k = 0; k < KS; ++k) {
-                uint64_t v = 0;   // the flow's factored word k (pattern side: bits and presence)
-                uint64_t lo = 0x2222222222222222ull, hi = 0x2222222222222222ull;
-                if (ok) {
-                    for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
-                        const FacFeature ft = a.fv.feat[f];
-                        if ((uint32_t)k - ft.w0 >= ft.nw) continue;
-                        v |= a.fv.mask[ft.mask + (uint32_t)row[f] * ft.nw + (k - ft.w0)];
-                    }
-                    const uint64_t bw = a.fv.bitw[k];
-                    const uint32_t ones = (uint32_t)((v & bw) >> (32 * half)), zeros = (uint32_t)((~v & bw) >> (32 * half));
-                    lo = (uint64_t)(spread8(zeros) | spread8(ones) * 5u) |
-                         (uint64_t)(spread8(zeros >> 8) | spread8(ones >> 8) * 5u) << 32;
-                    hi = (uint64_t)(spread8(zeros >> 16) | spread8(ones >> 16) * 5u) |
-                         (uint64_t)(spread8(zeros >> 24) | spread8(ones >> 24) * 5u) << 32;
-                    for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
-                        const uint32_t pt = a.fv.ptok[f];
-                        if (pt == ~0u) continue;
-                        const uint32_t pc = __popc(row[f]);
-                        for (uint32_t part = 0; part < (pt >> 24); ++part) {
-                            const uint32_t tk = (pt & 0xffffffu) + part;
-                            if (tk / 64 != (uint32_t)k || (tk % 64) / 32 != half) continue;
-                            const uint32_t j = tk % 32;
-                            const uint64_t nib = signed_nibble(2u + part, 0u, pc);
-                            if (j < 16) lo |= nib << (4 * j);
-                            else hi |= nib << (4 * (j - 16));
-                        }
-                    }
-                }
-                // the spare token is +1.0 in every flow (it carries the count's starting +1)
-                if (SPARE && k == KS - 1 && half) hi = (hi & 0x0fffffffffffffffull) | 0x2000000000000000ull;
-                b[f][k] = v8i_t{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
-                                (int)(uint32_t)(hi >> 32), 0, 0, 0, 0};
-            }
-        } else {
-        if (act && a.codes) {
-            const uint16_t *row = a.codes + (size_t)t * a.d;
-            const uint32_t *off = a.meta, *flo = a.meta + a.d, *fhi = a.meta + a.d + KS;
-#pragma unroll
-            for (int k = 0; k < KS; ++k) {
-                uint64_t v = 0;
-                for (uint32_t ft = flo[k]; ft < fhi[k]; ++ft) {
-                    const uint32_t c = row[ft];
-                    ok &= c < a.nbins[ft];
-                    const uint32_t bit = off[ft] + c;
-                    if ((bit >> 6) == (uint32_t)k) v |= 1ull << (bit & 63);
-                }
-                wd[k] = v;
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < KS; ++k) wd[k] = (act && k < (int)a.K) ? a.words[(size_t)t * a.K + k] : 0ull;
-        }
-#pragma unroll
-        for (int k = 0; k < KS; ++k) {
-            // NOT t; an inactive or invalid flow is the empty set, which contains no pattern.
-            // The spare token is 1 in every flow (it carries the count's starting +1).
-            uint64_t nt = ok ? ~wd[k] : ~0ull;
-            if (SPARE && k == KS - 1) nt |= 1ull << 63;
-            const uint32_t dwd = (uint32_t)(nt >> (32 * half));
-            b[f][k] = v8i_t{(int)spread8(dwd), (int)spread8(dwd >> 8), (int)spread8(dwd >> 16),
-                            (int)spread8(dwd >> 24), 0, 0, 0, 0};
-        }
-        }
-        valid[f] = ok;
+        valid[f] = flow_operand<KS, SPARE>(a, t, t < a.n_flows, half, b[f]);
     }
     // C[f]: running weighting products; row c < 4 of column `col` (lane half 0,
     // accumulators 0..3) sums chunk c of the weights of the patterns inside the flow
@@ -699,57 +781,93 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
 #pragma unroll
         for (int f = 0; f < MF_FB; ++f) C[f] = v16i_t{0};
         stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], s0 - lo, s1 - lo, lds, [&](const uint4 *tile) __attribute__((always_inline)) {
-            // the count starts at +1: from the spare token, or here
-            v16f_t acc[MF_FB];
-#pragma unroll
-            for (int f = 0; f < MF_FB; ++f)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[f][r] = SPARE ? 0.0f : 1.0f;
-#pragma unroll
-            for (int w = 0; w < KS; ++w) {
-                const uint4 a4 = tile[w * 64 + lane];
-                const v8i_t av = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
-#pragma unroll
-                for (int f = 0; f < MF_FB; ++f)
-                    acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
-            }
-            // weight chunks of this tile as the A operand (rows c < 4; other rows zero)
-            const uint4 q = tile[KS * 64 + lane];
-            const v4i_t wa = {(int)q.x, (int)q.y, (int)q.z, (int)q.w};
-#pragma unroll
-            for (int f = 0; f < MF_FB; ++f) {
-                // inside = max(acc, 0) as a byte (1 or 0), accumulator r -> byte r
-                v4i_t z;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    uint32_t d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q], 0, 0u);
-                    d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 1], 1, d);
-                    d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 2], 2, d);
-                    d = __builtin_amdgcn_cvt_pk_u8_f32(acc[f][4 * q + 3], 3, d);
-                    z[q] = (int)d;
-                }
-                C[f] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wa, z, C[f], 0, 0, 0);
-            }
+            score_tile<KS, SPARE>(tile, lane, b, C);
         });
-        const int colsel = cls == 1 ? 0 : 1;   // A from class 1, N from class 0
+        score_flush(a.out, cls, half, C, tf, valid);
+    }
+}
+
+// Pruned scoring: a pattern can lie inside a flow only when the flow holds every
+// token of it, in particular the pattern's bucket token (one token of each pattern,
+// chosen when the model was built; the tiles of each class are grouped by it).
+// A work unit is (class, bucket u, a range of at most p.rt of the bucket's tiles,
+// a block of SC_COLS of the flows holding token u); its flows are tested against
+// those tiles only.  Workgroups take units from a queue until it runs dry.  Every
+// flow in the lists is valid; the launcher initialised out.
+struct PruneArgs {
+    const uint32_t *btile[2];   // [L + 1]: first tile of each bucket, per class
+    const uint32_t *fcnt;       // [L]: flows holding token u
+    const uint32_t *foff;       // [L + 1]: start of the list of flows holding token u
+    const uint32_t *flist;      // flow ids grouped by token
+    const uint32_t *uoff;       // [2L + 1]: first unit of (class, bucket) c * L + u
+    uint32_t *queue;            // next unit to take (zero at launch)
+    uint32_t L, rt;
+};
+
+template <int KS, bool SPARE>
+__global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma_pruned(ScoreMfmaArgs a, PruneArgs p) {
+    constexpr int G = sc_group<KS>();
+    constexpr int TW = (KS + 1) * 64;
+    __shared__ uint4 lds[ring_lds<TW, G, SC_NB>()];
+    __shared__ uint32_t next_unit;
+    const uint32_t total = p.uoff[2 * p.L];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
+    for (;;) {
+        if (threadIdx.x == 0) next_unit = atomicAdd(p.queue, 1u);
+        __syncthreads();   // also: every wave is done with the previous unit's ring
+        const uint32_t unit = next_unit;
+        __syncthreads();   // every thread has read next_unit before thread 0 rewrites it
+        if (unit >= total) break;   // uniform over the workgroup
+        // (class, bucket) of the unit: the last i with uoff[i] <= unit (its range is not empty)
+        uint32_t lo = 0, hi = 2 * p.L;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (p.uoff[mid] <= unit) lo = mid;
+            else hi = mid;
+        }
+        const int cls = lo >= p.L ? 1 : 0;
+        const uint32_t u = lo - (uint32_t)cls * p.L;
+        const uint32_t nf = p.fcnt[u], nb = (nf + SC_COLS - 1) / SC_COLS;
+        const uint32_t local = unit - p.uoff[lo], r = local / nb, fb = local % nb;
+        const uint32_t t0 = p.btile[cls][u] + r * p.rt, tend = p.btile[cls][u + 1];
+        const uint32_t t1 = t0 + p.rt < tend ? t0 + p.rt : tend;
+        v8i_t b[MF_FB][KS];
+        uint32_t tf[MF_FB];
+        bool valid[MF_FB];
+        const uint32_t wave0 = fb * SC_COLS + wave * (MF_FB * 32);   // first slot of the wave
 #pragma unroll
         for (int f = 0; f < MF_FB; ++f) {
-            uint64_t v = 0;
+            const uint32_t slot = wave0 + f * 32 + col;
+            const bool act = slot < nf;
+            tf[f] = act ? p.flist[p.foff[u] + slot] : 0u;
+            valid[f] = flow_operand<KS, SPARE>(a, tf[f], act, half, b[f]);
+        }
+        v16i_t C[MF_FB];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) v += (uint64_t)(uint32_t)C[f][c] << (7 * c);
-            if (half == 0 && valid[f] && v)
-                atomicAdd(reinterpret_cast<unsigned long long *>(a.out + 2 * (size_t)tf[f] + colsel),
-                          (unsigned long long)v);
+        for (int f = 0; f < MF_FB; ++f) C[f] = v16i_t{0};
+        // a wave without flows in this block only helps to stream the tiles (it takes
+        // the same loads and barriers, and skips the products)
+        if (__builtin_amdgcn_readfirstlane(wave0 < nf ? 1 : 0)) {
+            stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], t0, t1, lds, [&](const uint4 *tile) __attribute__((always_inline)) {
+                score_tile<KS, SPARE>(tile, lane, b, C);
+            });
+            score_flush(a.out, cls, half, C, tf, valid);
+        } else {
+            stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], t0, t1, lds,
+                                               [&](const uint4 *) __attribute__((always_inline)) {});
         }
     }
 }
 
 void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, bool spare, uint4 *frag,
-                          hipStream_t s) {
-    const uint32_t ntiles = (m + 31) / 32;
+                          hipStream_t s, const uint32_t *perm, const uint32_t *bt, const uint32_t *brow, uint32_t L,
+                          uint32_t ntiles) {
+    if (!bt) ntiles = (m + 31) / 32;
     if (!ntiles) return;
     IG_REQUIRE(KS >= 1 && KS <= 8, IG_E_UNSUPPORTED, "matrix-core scoring operands of more than 8 words");
-    hipLaunchKernelGGL(k_mfma_patterns, dim3((ntiles + 3) / 4), dim3(256), 0, s, W, S, m, KS, ntiles, spare, frag);
+    IG_REQUIRE(!bt || (brow && L >= 1), IG_E_INVAL, "bucket tiles without bucket rows");
+    hipLaunchKernelGGL(k_mfma_patterns, dim3((ntiles + 3) / 4), dim3(256), 0, s, W, S, m, KS, ntiles, spare, perm,
+                       bt, brow, L, frag);
     IG_HIP(hipGetLastError());
 }
 
@@ -1163,7 +1281,7 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     ScoreMfmaArgs a{};
     for (int c = 0; c < 2; ++c) {
         a.frag[c] = m.frag[c];
-        a.ntiles[c] = (uint32_t)((m.np[c] + 31) / 32);
+        a.ntiles[c] = m.ftiles[c];
     }
     a.codes = codes;
     a.words = words;
@@ -1235,6 +1353,69 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     const dim3 grid((unsigned)(a.ranges * a.fblocks));
     void *args[] = {&a};
     IG_HIP(hipLaunchKernel(kern, grid, dim3(SC_NT), args, 0, s));
+}
+
+// Tiles per work unit of pruned scoring: long enough to cover a unit's set-up (the
+// flows' operands and the ring's first loads), short enough that the units of a
+// large bucket spread over many workgroups.
+#ifndef IG_PRUNE_RT
+#define IG_PRUNE_RT 128
+#endif
+
+bool launch_score_mfma_pruned(const ScoreModel &m, const uint16_t *codes, uint32_t n_flows, uint32_t d,
+                              const uint32_t *meta, const uint16_t *nbins, int64_t *out, uint32_t *ws, hipStream_t s) {
+    IG_REQUIRE(m.btile[0] && m.btile[1] && m.nbucket, IG_E_INVAL, "model tiles are not grouped by token");
+    IG_REQUIRE(m.KO >= 1 && m.KO <= 8, IG_E_UNSUPPORTED, "the matrix-core scoring path handles up to 8 words");
+    if (!n_flows) return true;
+    const uint32_t L = m.nbucket, rt = IG_PRUNE_RT;
+    // every unit count and the queue stay below 2^32
+    const uint64_t tiles = (uint64_t)m.ftiles[0] + m.ftiles[1];
+    const uint64_t bound = (tiles / rt + 2ull * L) * ((uint64_t)n_flows / SC_COLS + 1);
+    if (bound >= (1ull << 31)) return false;
+    PruneWork w = prune_work(ws, L);
+    launch_prune_lists(codes, n_flows, d, meta, nbins, L, m.btile[0], m.btile[1], rt, SC_COLS, out, w, s);
+    if (!tiles) return true;
+    ScoreMfmaArgs a{};
+    for (int c = 0; c < 2; ++c) {
+        a.frag[c] = m.frag[c];
+        a.ntiles[c] = m.ftiles[c];
+    }
+    a.codes = codes;
+    a.meta = meta;
+    a.nbins = nbins;
+    a.out = out;
+    a.n_flows = n_flows;
+    a.d = d;
+    a.fv = m.fv;
+    PruneArgs p{};
+    p.btile[0] = m.btile[0];
+    p.btile[1] = m.btile[1];
+    p.fcnt = w.cnt;
+    p.foff = w.foff;
+    p.flist = w.list;
+    p.uoff = w.uoff;
+    p.queue = w.queue;
+    p.L = L;
+    p.rt = rt;
+    const void *kernels[8][2] = {
+#define IG_SCP(V) {(const void *)k_score_mfma_pruned<V, false>, (const void *)k_score_mfma_pruned<V, true>},
+        IG_SCP(1) IG_SCP(2) IG_SCP(3) IG_SCP(4) IG_SCP(5) IG_SCP(6) IG_SCP(7) IG_SCP(8)
+#undef IG_SCP
+    };
+    const void *kern = kernels[m.KO - 1][m.spare ? 1 : 0];
+    static std::atomic<uint32_t> slot_cache[8][2] = {};
+    uint32_t slots = slot_cache[m.KO - 1][m.spare ? 1 : 0].load(std::memory_order_relaxed);
+    if (!slots) {
+        slots = xcd_slots(kern, SC_NT);
+        slot_cache[m.KO - 1][m.spare ? 1 : 0].store(slots, std::memory_order_relaxed);
+    }
+    // a persistent grid: every resident workgroup drains the queue; no more
+    // workgroups than units can exist
+    uint64_t grid = 8ull * slots;
+    if (grid > bound) grid = bound ? bound : 1;
+    void *args[] = {&a, &p};
+    IG_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(SC_NT), args, 0, s));
+    return true;
 }
 
 }  // namespace ig

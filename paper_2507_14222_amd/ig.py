@@ -22,6 +22,8 @@ _NAMES = {0: "IG_OK", -1: "IG_E_INVAL", -2: "IG_E_NOMEM", -3: "IG_E_DEVICE", -4:
 ABSENT = 0xFFFF
 IG_MODEL_SCORE_MFMA = 1   # ModelInfo.flags: scoring runs on the matrix cores
 IG_MODEL_FACTORED = 2     # ModelInfo.flags: matrix-core operands use factored tokens
+IG_MODEL_BUCKETED = 4     # ModelInfo.flags: scoring tiles grouped by token (pruned scoring)
+SCORE_MODES = {"auto": 0, "dense": 1, "pruned": 2}
 
 
 class IGError(RuntimeError):
@@ -35,10 +37,49 @@ class TuneEntry(C.Structure):
                 ("grid_per_cu", C.c_uint32), ("support_cpl", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """ig_allocator: a caller's device allocator (see torch_allocator())."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
 class FitOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_uint64), ("filter_cpl", C.c_uint32), ("score_fpl", C.c_uint32),
                 ("block", C.c_uint32), ("n_tune", C.c_uint32), ("tune", C.POINTER(TuneEntry)),
-                ("coherence_mfma", C.c_uint32), ("reserved", C.c_uint32)]
+                ("coherence_mfma", C.c_uint32), ("reserved", C.c_uint32), ("alloc", C.POINTER(Allocator))]
+
+
+def torch_allocator(fail_after: Optional[int] = None) -> Allocator:
+    """An ig_allocator over torch's caching allocator: the library's model buffers
+    and fit scratch then come from torch's pool, stream-ordered on the stream the
+    library passes.  fail_after = n makes every allocation after the first n fail
+    (for tests of the failure path).  The returned object keeps its callbacks alive;
+    keep it (the models built with it keep a reference)."""
+    torch = _torch()
+    state = {"n": 0, "live": {}}
+
+    def _alloc(nbytes, stream, ctx):
+        if fail_after is not None and state["n"] >= fail_after:
+            return None
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), int(stream or 0))
+        except Exception:
+            return None
+        state["n"] += 1
+        state["live"][p] = int(nbytes)
+        return p
+
+    def _free(ptr, stream, ctx):
+        if ptr:
+            state["live"].pop(ptr, None)
+            torch.cuda.caching_allocator_delete(ptr)
+
+    a = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    a._state = state          # allocations made and blocks still held (tests)
+    return a
 
 
 class Stats(C.Structure):
@@ -53,6 +94,34 @@ class ModelInfo(C.Structure):
                 ("n_patterns", C.c_uint64 * 2), ("max_weight", C.c_int64 * 2)]
 
 
+class Moments(C.Structure):
+    """Exact moments of N over the normal records (ig_moments)."""
+    _fields_ = [("count", C.c_uint64), ("sum", C.c_uint64 * 2), ("sumsq", C.c_uint64 * 3)]
+
+    @property
+    def total(self) -> int:
+        return int(self.sum[0]) | int(self.sum[1]) << 64
+
+    @property
+    def total_sq(self) -> int:
+        return int(self.sumsq[0]) | int(self.sumsq[1]) << 64 | int(self.sumsq[2]) << 128
+
+
+class Metrics(C.Structure):
+    """Confusion counts and the exact AUC fraction (ig_metrics)."""
+    _fields_ = [("tp", C.c_uint64), ("fp", C.c_uint64), ("tn", C.c_uint64), ("fn", C.c_uint64),
+                ("auc_num", C.c_uint64), ("auc_den", C.c_uint64), ("invalid", C.c_uint64)]
+
+    def as_dict(self) -> dict:
+        tp, fp, tn, fn = int(self.tp), int(self.fp), int(self.tn), int(self.fn)
+        n = tp + fp + tn + fn
+        return {"tp": tp, "fp": fp, "tn": tn, "fn": fn, "invalid": int(self.invalid),
+                "accuracy": (tp + tn) / n if n else 0.0,
+                "recall": tp / (tp + fn) if tp + fn else 0.0,
+                "precision": tp / (tp + fp) if tp + fp else 0.0,
+                "auc": int(self.auc_num) / int(self.auc_den) if self.auc_den else 0.0}
+
+
 class Problem(C.Structure):
     _fields_ = [("d_codes", C.c_void_p), ("d_labels", C.c_void_p), ("n", C.c_uint32), ("d", C.c_uint32),
                 ("h_nbins", C.c_void_p)]
@@ -61,9 +130,11 @@ class Problem(C.Structure):
 _lib = None
 
 # every symbol the headers under include/ declare
-EXPORTS = ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_packed", "ig_model_get_info",
+EXPORTS = ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_ex", "ig_score_packed", "ig_model_get_info",
            "ig_model_export", "ig_model_import", "ig_model_digest", "ig_fit_stats", "ig_model_free",
-           "ig_last_error", "ig_version", "ig_probe_mfma_fp4", "ig_probe_hbm_copy")
+           "ig_last_error", "ig_version", "ig_probe_mfma_fp4", "ig_probe_hbm_copy", "ig_normal_moments",
+           "ig_r3_threshold", "ig_classify", "ig_detection_metrics", "ig_evidence", "ig_model_bucket_sizes", "ig_release_memory", "ig_memory_stats")
+IG_CLASSIFY_R3, IG_CLASSIFY_NO_R2 = 1, 2
 
 
 def lib():
@@ -79,6 +150,7 @@ def lib():
     L.ig_fit_packed.argtypes = [vp, vp, u32, u32, C.POINTER(FitOpts), vp, C.POINTER(vp)]
     L.ig_fit_batch.argtypes = [C.POINTER(Problem), u32, C.POINTER(FitOpts), vp, C.POINTER(vp)]
     L.ig_score.argtypes = [vp, vp, u32, vp, vp]
+    L.ig_score_ex.argtypes = [vp, vp, u32, vp, u32, vp]
     L.ig_score_packed.argtypes = [vp, vp, u32, vp, vp]
     L.ig_model_get_info.argtypes = [vp, C.POINTER(ModelInfo)]
     L.ig_model_export.argtypes = [vp, u32, vp, vp, vp]
@@ -91,9 +163,18 @@ def lib():
     L.ig_version.restype = C.c_char_p
     L.ig_probe_mfma_fp4.argtypes = [u32, vp, C.POINTER(C.c_double), C.POINTER(C.c_float)]
     L.ig_probe_hbm_copy.argtypes = [vp, vp, C.c_size_t, vp, C.POINTER(C.c_double), C.POINTER(C.c_float)]
-    for name in ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_packed", "ig_model_get_info",
+    L.ig_normal_moments.argtypes = [vp, vp, u32, C.POINTER(Moments), vp]
+    L.ig_evidence.argtypes = [vp, vp, u32, u32, vp, vp, vp, vp, vp]
+    L.ig_model_bucket_sizes.argtypes = [vp, u32, vp]
+    L.ig_release_memory.argtypes = []
+    L.ig_memory_stats.argtypes = [C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]
+    L.ig_r3_threshold.argtypes = [C.POINTER(Moments), C.c_double, C.POINTER(C.c_int64)]
+    L.ig_classify.argtypes = [vp, u32, C.c_int64, u32, vp, vp, vp]
+    L.ig_detection_metrics.argtypes = [vp, vp, vp, u32, C.POINTER(Metrics), vp]
+    for name in ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_ex", "ig_score_packed", "ig_model_get_info",
                  "ig_model_export", "ig_model_import", "ig_model_digest", "ig_fit_stats", "ig_probe_mfma_fp4",
-                 "ig_probe_hbm_copy"):
+                 "ig_probe_hbm_copy", "ig_normal_moments", "ig_r3_threshold", "ig_classify",
+                 "ig_detection_metrics", "ig_evidence", "ig_model_bucket_sizes", "ig_release_memory", "ig_memory_stats"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -179,11 +260,17 @@ def _np_u16(a) -> np.ndarray:
 
 
 def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tune=None,
-          kernels: str = "auto") -> FitOpts:
+          kernels: str = "auto", allocator=None) -> FitOpts:
     """Fit options; `tune` is a list of dicts with the fields of ig_tune_entry;
     kernels = "auto" | "mfma" | "valu" | "mfma_onehot" selects the coherence/support
-    kernels ("mfma_onehot": matrix cores on the one-hot words, no factored tokens)."""
+    kernels ("mfma_onehot": matrix cores on the one-hot words, no factored tokens);
+    allocator = None (the library's arena), "torch" (torch's caching allocator) or an
+    Allocator."""
     o = FitOpts()
+    if allocator is not None:
+        a = torch_allocator() if allocator == "torch" else allocator
+        o.alloc = C.pointer(a)
+        o._alloc = a
     o.coherence_mfma = {"auto": 0, "mfma": 1, "valu": 2, "mfma_onehot": 3}[kernels]
     o.mem_budget_bytes = int(mem_budget_bytes)
     o.filter_cpl = int(filter_cpl)
@@ -215,8 +302,9 @@ class FitStats:
 class Model:
     """A device-resident pair of coherent pattern sets (P^0 normal, P^1 attack)."""
 
-    def __init__(self, handle: C.c_void_p):
+    def __init__(self, handle: C.c_void_p, keep=None):
         self._h = handle
+        self._keep = keep   # a caller allocator the model's buffers came from
 
     @property
     def handle(self) -> C.c_void_p:
@@ -236,6 +324,10 @@ class Model:
     @property
     def score_on_matrix_cores(self) -> bool:
         return bool(self.info().flags & IG_MODEL_SCORE_MFMA)
+
+    @property
+    def bucketed(self) -> bool:
+        return bool(self.info().flags & IG_MODEL_BUCKETED)
 
     def n_patterns(self) -> Tuple[int, int]:
         i = self.info()
@@ -259,6 +351,12 @@ class Model:
         _check(lib().ig_model_export(self.handle, cls, ptr(w), ptr(f), ptr(S)))
         return w, f, S
 
+    def bucket_sizes(self, cls: int) -> np.ndarray:
+        """Patterns of class ``cls`` per token bucket (uint32 [L])."""
+        out = np.zeros(int(self.info().L), np.uint32)
+        _check(lib().ig_model_bucket_sizes(self.handle, cls, C.c_void_p(out.ctypes.data)))
+        return out
+
     def digest(self, cls: int) -> int:
         """Device-computed digest of class ``cls`` (rows, f, S in canonical order)."""
         h = C.c_uint64()
@@ -278,7 +376,7 @@ class Model:
 
 
 def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tune=None,
-        kernels: str = "auto", stream=None) -> Model:
+        kernels: str = "auto", stream=None, allocator=None) -> Model:
     """ig_fit: codes [n, d] bin codes, labels [n] (0 normal / 1 attack), nbins [d]."""
     torch = _torch()
     with _OnStream(stream) as on:
@@ -287,10 +385,10 @@ def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tu
         n, d = (int(dc.shape[0]), int(dc.shape[1])) if dc.dim() == 2 else (0, 0)
         nb = _np_u16(nbins)
         h = C.c_void_p()
-        o = _opts(mem_budget_bytes, filter_cpl, tune=tune, kernels=kernels)
+        o = _opts(mem_budget_bytes, filter_cpl, tune=tune, kernels=kernels, allocator=allocator)
         _check(lib().ig_fit(C.c_void_p(dc.data_ptr()), C.c_void_p(dl.data_ptr()), n, d or nb.size,
                             C.c_void_p(nb.ctypes.data), C.byref(o), on.handle, C.byref(h)))
-    return Model(h)
+    return Model(h, getattr(o, "_alloc", None))
 
 
 def fit_packed(words, labels, mem_budget_bytes: int = 0, stream=None) -> Model:
@@ -309,7 +407,7 @@ def fit_packed(words, labels, mem_budget_bytes: int = 0, stream=None) -> Model:
 
 
 def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, tune=None, kernels: str = "auto",
-              stream=None) -> List[Model]:
+              stream=None, allocator=None) -> List[Model]:
     """ig_fit_batch over problems with attributes codes, labels, nbins."""
     torch = _torch()
     keep = []
@@ -326,15 +424,16 @@ def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, tune=None, kernels:
             arr[p].d = int(nb.size)
             arr[p].h_nbins = nb.ctypes.data
         outs = (C.c_void_p * len(problems))()
-        o = _opts(mem_budget_bytes, tune=tune, kernels=kernels)
+        o = _opts(mem_budget_bytes, tune=tune, kernels=kernels, allocator=allocator)
         _check(lib().ig_fit_batch(arr, len(problems), C.byref(o), on.handle, outs))
-    return [Model(C.c_void_p(outs[p])) for p in range(len(problems))]
+    keep = getattr(o, "_alloc", None)
+    return [Model(C.c_void_p(outs[p]), keep) for p in range(len(problems))]
 
 
-def score(model: Model, flows, out=None, stream=None):
-    """ig_score: (A, N) per flow as an int64 device tensor [n, 2], asynchronous on
-    `stream` (torch's current stream when None): the result is ready once that
-    stream reaches the call."""
+def score(model: Model, flows, out=None, stream=None, mode: str = "auto"):
+    """ig_score / ig_score_ex: (A, N) per flow as an int64 device tensor [n, 2],
+    asynchronous on `stream` (torch's current stream when None): the result is
+    ready once that stream reaches the call.  mode = "auto" | "dense" | "pruned"."""
     torch = _torch()
     with _OnStream(stream) as on:
         dc = on.use(_dev(flows, torch.int16))
@@ -342,8 +441,12 @@ def score(model: Model, flows, out=None, stream=None):
         if out is None:
             out = torch.empty((n, 2), dtype=torch.int64, device=dc.device)
         on.use(out)
-        _check(lib().ig_score(model.handle, C.c_void_p(dc.data_ptr()), n, C.c_void_p(out.data_ptr()),
-                              on.handle))
+        if mode == "auto":
+            _check(lib().ig_score(model.handle, C.c_void_p(dc.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                  on.handle))
+        else:
+            _check(lib().ig_score_ex(model.handle, C.c_void_p(dc.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                     SCORE_MODES[mode], on.handle))
     return out
 
 
@@ -374,6 +477,88 @@ def import_patterns(codes0, f0, codes1, f1, nbins, stream=None) -> Model:
     _check(lib().ig_model_import(pc, pf, cnt, int(nb.size), C.c_void_p(nb.ctypes.data),
                                  _stream_handle(stream), C.byref(h)))
     return Model(h)
+
+
+def evidence(model: Model, flows, k: int, stream=None):
+    """ig_evidence: for each flow and class the number of patterns inside the flow
+    and the k heaviest of them (weight descending, then words ascending).
+    Returns device tensors count [n, 2] (int32 view of uint32; -1 marks a flow with
+    a code out of range), words [n, 2, k, K] (int64 view of uint64), f [n, 2, k]
+    (int32 view of uint32) and S [n, 2, k]; slots past the count are zero."""
+    torch = _torch()
+    K = model.K
+    with _OnStream(stream) as on:
+        dc = on.use(_dev(flows, torch.int16))
+        n = int(dc.shape[0])
+        cnt = on.use(torch.empty((n, 2), dtype=torch.int32, device=dc.device))
+        words = on.use(torch.empty((n, 2, k, K), dtype=torch.int64, device=dc.device))
+        f = on.use(torch.empty((n, 2, k), dtype=torch.int32, device=dc.device))
+        S = on.use(torch.empty((n, 2, k), dtype=torch.int64, device=dc.device))
+        _check(lib().ig_evidence(model.handle, C.c_void_p(dc.data_ptr()), n, int(k), C.c_void_p(cnt.data_ptr()),
+                                 C.c_void_p(words.data_ptr()), C.c_void_p(f.data_ptr()), C.c_void_p(S.data_ptr()),
+                                 on.handle))
+    return cnt, words, f, S
+
+
+def normal_moments(scores, labels, stream=None) -> Moments:
+    """ig_normal_moments: exact count, sum and sum of squares of N over the records
+    labelled 0 (scores: the [n, 2] (A, N) of those records)."""
+    torch = _torch()
+    mo = Moments()
+    with _OnStream(stream) as on:
+        ds = on.use(_dev(scores, torch.int64))
+        dl = on.use(_dev(labels, torch.uint8))
+        _check(lib().ig_normal_moments(C.c_void_p(ds.data_ptr()), C.c_void_p(dl.data_ptr()), int(ds.shape[0]),
+                                       C.byref(mo), on.handle))
+    return mo
+
+
+def r3_threshold(moments: Moments, r: float) -> int:
+    """ig_r3_threshold: T with N < mu_N - r sigma_N exactly when N < T (N >= 0)."""
+    t = C.c_int64()
+    _check(lib().ig_r3_threshold(C.byref(moments), float(r), C.byref(t)))
+    return int(t.value)
+
+
+def classify(scores, r3_threshold: Optional[int] = None, use_r2: bool = True, stream=None):
+    """ig_classify: (label, rule) uint8 device tensors [n]; Regulation 3 applies
+    when a threshold is given."""
+    torch = _torch()
+    with _OnStream(stream) as on:
+        ds = on.use(_dev(scores, torch.int64))
+        n = int(ds.shape[0])
+        lab = on.use(torch.empty(n, dtype=torch.uint8, device=ds.device))
+        rule = on.use(torch.empty(n, dtype=torch.uint8, device=ds.device))
+        flags = (IG_CLASSIFY_R3 if r3_threshold is not None else 0) | (0 if use_r2 else IG_CLASSIFY_NO_R2)
+        _check(lib().ig_classify(C.c_void_p(ds.data_ptr()), n, int(r3_threshold or 0), flags,
+                                 C.c_void_p(lab.data_ptr()), C.c_void_p(rule.data_ptr()), on.handle))
+    return lab, rule
+
+
+def detection_metrics(scores, pred, truth, stream=None) -> Metrics:
+    """ig_detection_metrics: confusion counts of pred against truth and the exact
+    AUC of the margins A - N."""
+    torch = _torch()
+    mt = Metrics()
+    with _OnStream(stream) as on:
+        ds = on.use(_dev(scores, torch.int64))
+        dp = on.use(_dev(pred, torch.uint8))
+        dt = on.use(_dev(truth, torch.uint8))
+        _check(lib().ig_detection_metrics(C.c_void_p(ds.data_ptr()), C.c_void_p(dp.data_ptr()),
+                                          C.c_void_p(dt.data_ptr()), int(ds.shape[0]), C.byref(mt), on.handle))
+    return mt
+
+
+def release_memory() -> None:
+    """ig_release_memory: the library's cached scratch and free arena chunks back."""
+    _check(lib().ig_release_memory())
+
+
+def memory_stats() -> dict:
+    """ig_memory_stats of the current device: reserved, in use, cached bytes."""
+    r, u, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    _check(lib().ig_memory_stats(C.byref(r), C.byref(u), C.byref(c)))
+    return {"reserved": int(r.value), "in_use": int(u.value), "cached": int(c.value)}
 
 
 def version() -> str:
