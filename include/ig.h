@@ -241,6 +241,25 @@ ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows,
 ig_status ig_score_ex(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out, uint32_t mode,
                       void *stream);
 
+/* ---------------------------------------------------------------------------
+ * ig_score_noalloc -- ig_score for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same results as ig_score; calls no allocating routine.  Pruned
+ * scoring's per-call work goes to a fixed array of IG_NOALLOC_SCRATCH_BYTES in
+ * the library's device memory (each GPU the library runs on holds its own copy
+ * until the process ends) instead of library-allocated scratch, so a call needs
+ *   4 * (n_flows * d + 5 L + 3) <= IG_NOALLOC_SCRATCH_BYTES
+ * (IG_E_UNSUPPORTED beyond; e.g. about 51,000 flows of 41 features and 464
+ * tokens).  Models without token buckets score with the dense kernels, which
+ * need no scratch.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on a GPU (on different streams, or from different host threads) race
+ * and can return wrong scores; order them (one stream, or events).  Each call
+ * clears what it uses before using it.  Asynchronous on `stream`.
+ * ------------------------------------------------------------------------- */
+#define IG_NOALLOC_SCRATCH_BYTES (8u << 20)
+ig_status ig_score_noalloc(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out,
+                           void *stream);
+
 /* ig_score for flows already packed: d_words device [n_flows][K] uint64 (always
  * dense: such words may hold several bins of a feature). */
 ig_status ig_score_packed(const ig_model *m, const uint64_t *d_words, uint32_t n_flows,

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libig.so")
 ARCH = "gfx950"
-SOURCES = ["api.cpp", "evidence.hip", "factor.hip", "memory.cpp", "pack.hip", "pairs.hip", "probe.hip", "prune.hip", "regulate.hip", "sort.hip", "subset.hip"]
+SOURCES = ["api.cpp", "evidence.hip", "factor.hip", "memory.cpp", "noalloc.hip", "pack.hip", "pairs.hip", "probe.hip", "prune.hip", "regulate.hip", "sort.hip", "subset.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-Wno-unused-result", "-ffp-contract=off",

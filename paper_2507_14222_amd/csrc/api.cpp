@@ -1643,6 +1643,34 @@ ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows,
     return ig_score_ex(m, d_codes, n_flows, d_out, IG_SCORE_AUTO, stream);
 }
 
+ig_status ig_score_noalloc(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows, int64_t *d_out,
+                           void *stream) {
+    return guarded([&] {
+        check_model(m);
+        const DevModel &M = *m->m;
+        IG_REQUIRE(M.d > 0, IG_E_INVAL, "model was fitted from packed words: use ig_score_packed");
+        IG_REQUIRE(n_flows < (1u << 31), IG_E_UNSUPPORTED, "n_flows must be below 2^31");
+        IG_REQUIRE(n_flows == 0 || (d_codes && d_out), IG_E_INVAL, "codes or out is NULL");
+        const ig::ScoreModel sm = score_model(M);
+        hipStream_t s = (hipStream_t)stream;
+        const bool mfma = M.frag[0] && M.frag[1];
+        if (mfma && sm.nbucket) {
+            const size_t need = ig::prune_scratch_words(sm.nbucket, n_flows, M.d);
+            const size_t have = ig::noalloc_scratch_words();
+            IG_REQUIRE(need <= have, IG_E_UNSUPPORTED,
+                       "n_flows * d + 5 L + 3 = " + std::to_string(need) + " words exceed the fixed scratch of " +
+                           std::to_string(have) + " words (IG_NOALLOC_SCRATCH_BYTES)");
+            if (ig::launch_score_mfma_pruned(sm, d_codes, n_flows, M.d, M.meta, M.nbins, d_out,
+                                             ig::noalloc_scratch(), s))
+                return;
+        }
+        if (mfma)
+            ig::launch_score_mfma(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, s);
+        else
+            ig::launch_score(sm, d_codes, nullptr, M.K, n_flows, M.d, M.meta, M.nbins, d_out, 2, s);
+    });
+}
+
 ig_status ig_score_packed(const ig_model *m, const uint64_t *d_words, uint32_t n_flows, int64_t *d_out,
                           void *stream) {
     return guarded([&] {

@@ -258,6 +258,11 @@ uint32_t evidence_max_k();
 void launch_evidence(const EvidenceModel &m, const uint16_t *codes, uint32_t n, uint32_t k, uint32_t *count,
                      uint64_t *words, uint32_t *f, int64_t *S, hipStream_t s);
 
+// noalloc.hip -- the fixed scratch array of ig_score_noalloc: its size in u32, and
+// the current device's copy (looked up once per device)
+size_t noalloc_scratch_words();
+uint32_t *noalloc_scratch();
+
 // regulate.hip -- Regulations 1-3 and the detection metrics (Section 3.1, Table 2)
 void normal_moments(const int64_t *scores, const uint8_t *labels, uint32_t n, ig_moments *h, hipStream_t s);
 int64_t r3_threshold(const ig_moments &mo, double r);

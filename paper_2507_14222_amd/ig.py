@@ -130,7 +130,7 @@ class Problem(C.Structure):
 _lib = None
 
 # every symbol the headers under include/ declare
-EXPORTS = ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_ex", "ig_score_packed", "ig_model_get_info",
+EXPORTS = ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_ex", "ig_score_noalloc", "ig_score_packed", "ig_model_get_info",
            "ig_model_export", "ig_model_import", "ig_model_digest", "ig_fit_stats", "ig_model_free",
            "ig_last_error", "ig_version", "ig_probe_mfma_fp4", "ig_probe_hbm_copy", "ig_normal_moments",
            "ig_r3_threshold", "ig_classify", "ig_detection_metrics", "ig_evidence", "ig_model_bucket_sizes", "ig_release_memory", "ig_memory_stats")
@@ -151,6 +151,7 @@ def lib():
     L.ig_fit_batch.argtypes = [C.POINTER(Problem), u32, C.POINTER(FitOpts), vp, C.POINTER(vp)]
     L.ig_score.argtypes = [vp, vp, u32, vp, vp]
     L.ig_score_ex.argtypes = [vp, vp, u32, vp, u32, vp]
+    L.ig_score_noalloc.argtypes = [vp, vp, u32, vp, vp]
     L.ig_score_packed.argtypes = [vp, vp, u32, vp, vp]
     L.ig_model_get_info.argtypes = [vp, C.POINTER(ModelInfo)]
     L.ig_model_export.argtypes = [vp, u32, vp, vp, vp]
@@ -171,7 +172,7 @@ def lib():
     L.ig_r3_threshold.argtypes = [C.POINTER(Moments), C.c_double, C.POINTER(C.c_int64)]
     L.ig_classify.argtypes = [vp, u32, C.c_int64, u32, vp, vp, vp]
     L.ig_detection_metrics.argtypes = [vp, vp, vp, u32, C.POINTER(Metrics), vp]
-    for name in ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_ex", "ig_score_packed", "ig_model_get_info",
+    for name in ("ig_fit", "ig_fit_packed", "ig_fit_batch", "ig_score", "ig_score_ex", "ig_score_noalloc", "ig_score_packed", "ig_model_get_info",
                  "ig_model_export", "ig_model_import", "ig_model_digest", "ig_fit_stats", "ig_probe_mfma_fp4",
                  "ig_probe_hbm_copy", "ig_normal_moments", "ig_r3_threshold", "ig_classify",
                  "ig_detection_metrics", "ig_evidence", "ig_model_bucket_sizes", "ig_release_memory", "ig_memory_stats"):
@@ -447,6 +448,23 @@ def score(model: Model, flows, out=None, stream=None, mode: str = "auto"):
         else:
             _check(lib().ig_score_ex(model.handle, C.c_void_p(dc.data_ptr()), n, C.c_void_p(out.data_ptr()),
                                      SCORE_MODES[mode], on.handle))
+    return out
+
+
+def score_noalloc(model: Model, flows, out, stream=None):
+    """ig_score_noalloc: as score(), through the entry point that allocates no device
+    memory (its scratch is a fixed array in the library); `flows` must already be a
+    contiguous int16/uint16-bit device tensor and `out` an int64 device tensor
+    [n, 2], so that the binding allocates nothing either."""
+    torch = _torch()
+    assert flows.is_cuda and flows.dtype == torch.int16 and flows.is_contiguous()
+    assert out.is_cuda and out.dtype == torch.int64 and out.is_contiguous()
+    n = int(flows.shape[0])
+    with _OnStream(stream) as on:
+        on.use(flows)
+        on.use(out)
+        _check(lib().ig_score_noalloc(model.handle, C.c_void_p(flows.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                      on.handle))
     return out
 
 
