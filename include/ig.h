@@ -61,17 +61,22 @@ typedef enum {
 
 typedef struct ig_model ig_model;   /* opaque; owns the device-resident pattern sets */
 
-/* One row of a tuning table (written by the project's autotuner): the launch
- * shape to use for problems stored with `ks` words and at least `min_pairs`
- * same-class pairs.  The matching row with the largest min_pairs wins; a row with
- * ks = 0 matches any width.  Tuning never changes results. */
+/* One row of a tuning table (written by the project's autotuner).  A row with
+ * mfma_words = 0 gives the VALU kernels' launch shape for problems stored with
+ * `ks` words (0 = any width); a row with mfma_words = W gives the matrix-core
+ * contractions' shape for problems whose operands take W words.  Of the rows that
+ * match, the one with the largest min_pairs not above the problem's pairs wins
+ * (an exact ks beats ks = 0).  Tuning never changes results. */
 typedef struct {
-    uint32_t ks;             /* storage words (0 = any)                               */
+    uint32_t ks;             /* storage words (0 = any; VALU rows)                   */
     uint32_t min_pairs;      /* smallest problem (pairs of both classes) it covers   */
     uint32_t filter_cpl;     /* coherence kernel: candidates per lane, 1 or 2        */
     uint32_t grid_per_cu;    /* coherence kernel: workgroups per compute unit, 1..32 */
     uint32_t support_cpl;    /* support kernel: patterns per lane, 1 or 2            */
-    uint32_t reserved[3];
+    uint32_t mfma_words;     /* 0: a VALU row; else the operand words it is for      */
+    uint32_t coherence_sets; /* matrix-core coherence: 32-column sets per wave, 1..3
+                                (capped by the registers at that width; 0 default)  */
+    uint32_t support_sets;   /* matrix-core support: the same                        */
 } ig_tune_entry;
 
 /* A caller's device allocator (e.g. a framework's caching allocator).  alloc

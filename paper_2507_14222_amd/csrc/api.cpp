@@ -394,6 +394,8 @@ struct Tuning {
     int cpl = 1;               // coherence: candidates per lane (one measured fastest at 15k)
     uint32_t grid_per_cu = 8;  // coherence: persistent workgroups per CU
     int support_cpl = 2;       // support: patterns per lane
+    int coh_sets = 0;          // matrix-core coherence: column sets per wave (0: default)
+    int sup_sets = 0;          // matrix-core support: the same
 };
 
 // Launch shape for a problem stored with KS words and `pairs` same-class pairs:
@@ -405,7 +407,7 @@ static Tuning tuning_for(const ig_fit_opts *o, uint32_t KS, uint64_t pairs) {
         const ig_tune_entry *best = nullptr;
         for (uint32_t i = 0; i < o->n_tune; ++i) {
             const ig_tune_entry &e = o->tune[i];
-            if ((e.ks != 0 && e.ks != KS) || e.min_pairs > pairs) continue;
+            if (e.mfma_words || (e.ks != 0 && e.ks != KS) || e.min_pairs > pairs) continue;
             if (!best || (best->ks == 0 && e.ks != 0) ||
                 ((best->ks != 0) == (e.ks != 0) && e.min_pairs > best->min_pairs))
                 best = &e;
@@ -418,6 +420,21 @@ static Tuning tuning_for(const ig_fit_opts *o, uint32_t KS, uint64_t pairs) {
     }
     if (o && (o->filter_cpl == 1 || o->filter_cpl == 2)) t.cpl = (int)o->filter_cpl;
     return t;
+}
+
+// The matrix-core contractions' shape for operands of KO words: the matching
+// mfma_words row with the largest min_pairs not above `pairs`.
+static void mfma_tuning(const ig_fit_opts *o, uint32_t KO, uint64_t pairs, Tuning &t) {
+    if (!o || !o->tune || !o->n_tune) return;
+    const ig_tune_entry *best = nullptr;
+    for (uint32_t i = 0; i < o->n_tune; ++i) {
+        const ig_tune_entry &e = o->tune[i];
+        if (e.mfma_words != KO || e.min_pairs > pairs) continue;
+        if (!best || e.min_pairs > best->min_pairs) best = &e;
+    }
+    if (!best) return;
+    if (best->coherence_sets >= 1 && best->coherence_sets <= 3) t.coh_sets = (int)best->coherence_sets;
+    if (best->support_sets >= 1 && best->support_sets <= 3) t.sup_sets = (int)best->support_sets;
 }
 
 struct ClassRows {
@@ -554,7 +571,7 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         IG_HIP(hipEventCreate(&ke[0]));
         IG_HIP(hipEventCreate(&ke[1]));
         IG_HIP(hipEventRecord(ke[0], s));
-        launch_contain_mfma((int)KO, true, B.get(), final_count, own_frag, cls.n, m.f[c], s);
+        launch_contain_mfma((int)KO, true, B.get(), final_count, own_frag, cls.n, m.f[c], s, tu.sup_sets);
         IG_HIP(hipEventRecord(ke[1], s));
         launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
         float tk = 0;
@@ -771,7 +788,7 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
 // (synchronises the stream); adds the contraction's device time to *kernel_ms.
 static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c, uint32_t KS, const uint32_t *cand,
                                uint32_t ncand, uint32_t *out, float *kernel_ms, hipStream_t s,
-                               uint64_t *rows_out = nullptr) {
+                               uint64_t *rows_out = nullptr, int sets = 0) {
     if (!ncand) return 0;
     Scratch<uint32_t> keep(ncand, s), kpos(ncand, s), ktot(1, s);
     Scratch<uint64_t> B((size_t)ncand * mf.KO, s);
@@ -790,7 +807,7 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
         }
     } evg{ke};
     IG_HIP(hipEventRecord(ke[0], s));
-    launch_contain_mfma((int)mf.KO, false, B.get(), ncand, mf.frag[c].get(), cls[1 - c].n, keep.get(), s);
+    launch_contain_mfma((int)mf.KO, false, B.get(), ncand, mf.frag[c].get(), cls[1 - c].n, keep.get(), s, sets);
     IG_HIP(hipEventRecord(ke[1], s));
     scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
     launch_compact(keep.get(), kpos.get(), cand, ncand, out, s);
@@ -805,8 +822,9 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
 
 static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts, hipStream_t s, Timer &tm) {
     const uint32_t KS = m.KS, K = m.K;
-    const Tuning tu = tuning_for(opts, KS, (uint64_t)cls[0].n * (cls[0].n ? cls[0].n - 1 : 0) / 2 +
-                                               (uint64_t)cls[1].n * (cls[1].n ? cls[1].n - 1 : 0) / 2);
+    const uint64_t fit_pairs = (uint64_t)cls[0].n * (cls[0].n ? cls[0].n - 1 : 0) / 2 +
+                               (uint64_t)cls[1].n * (cls[1].n ? cls[1].n - 1 : 0) / 2;
+    Tuning tu = tuning_for(opts, KS, fit_pairs);
     uint64_t M[2];
     for (int c = 0; c < 2; ++c) {
         uint64_t n = cls[c].n;
@@ -870,6 +888,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     MfmaFit mf;
     mfma_setup(m, cls, opts ? opts->coherence_mfma : 0u, mf, s);
     const bool use_mfma = mf.on;
+    if (use_mfma) mfma_tuning(opts, mf.KO, fit_pairs, tu);
     Scratch<uint64_t> surv_rows[2];   // operand rows of the coherent candidates (one-chunk fits)
     uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
     float ms_pairs = 0, ms_sort = 0, ms_dedup = 0, ms_coh = 0;
@@ -939,7 +958,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
                     ro = surv_rows[c].get();
                 }
                 mfma_surv[c] += mfma_coherence(mf, cls, c, KS, cc, hc[c], surv[c].get() + mfma_surv[c],
-                                               &m.stats.kernel_ms[0], s, ro);
+                                               &m.stats.kernel_ms[0], s, ro, tu.coh_sets);
                 mfma_tests[c] += (uint64_t)hc[c] * cls[1 - c].n;
             }
             IG_HIP(hipEventRecord(e[4], s));
@@ -1351,17 +1370,20 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
     for (uint32_t g = 0; g < G.size(); ++g) {
         if (!mf[g].on) continue;
         const auto t0 = std::chrono::steady_clock::now();
+        Tuning tg = tuning_for(opts, KS, G[g]->pairs());
+        mfma_tuning(opts, mf[g].KO, G[g]->pairs(), tg);
         for (int c = 0; c < 2; ++c) {
             const uint32_t sg = 2 * g + c;
             hsurv[sg] = mfma_coherence(mf[g], G[g]->cls, c, KS, cand.get() + hoff[sg], hdist[sg],
-                                       surv.get() + off[sg], &mfma_kernel[g], s);
+                                       surv.get() + off[sg], &mfma_kernel[g], s, nullptr, tg.coh_sets);
             htests[sg] = (unsigned long long)hdist[sg] * G[g]->cls[1 - c].n;
         }
         mfma_ms[g] = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     for (uint32_t g = 0; g < G.size(); ++g) {
         DevModel &m = *G[g]->m;
-        const Tuning tp = tuning_for(opts, KS, G[g]->pairs());
+        Tuning tp = tuning_for(opts, KS, G[g]->pairs());
+        if (mf[g].on) mfma_tuning(opts, mf[g].KO, G[g]->pairs(), tp);
         Timer tm(s);
         tm.mark(4);
         PatternRows prow;

@@ -167,8 +167,10 @@ void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *fra
 // The same tiles for factored tokens: records on the signed side (FactorView::tok)
 // from their factored rows FR [n][fv.KF]; KO = fv.KF.
 void launch_mfma_records_signed(const uint64_t *FR, uint32_t n, const FactorView &fv, uint4 *frag, hipStream_t s);
+// sets: 32-column sets per wave (1..3, capped by what fits the registers at KO
+// words; 0 = the default for KO)
 void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const uint4 *frag, uint32_t n_rec,
-                         uint32_t *out, hipStream_t s);
+                         uint32_t *out, hipStream_t s, int sets = 0);
 
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented
 // rows NX [n][KS] of their class.

@@ -368,8 +368,10 @@ constexpr int MF_FB = 2;                    // 32-column sets per wave (scoring)
 #endif
 template <int KS>
 constexpr int mf_sets() { return KS <= 5 ? IG_MF_SETS_NARROW : KS <= 8 ? 2 : 1; }
-template <int KS>
-constexpr int mf_cols() { return MF_NT / 64 * mf_sets<KS>() * 32; }
+// the most sets whose B operands and accumulators fit 128 VGPRs (4 waves per SIMD)
+__host__ __device__ constexpr int mf_max_sets(int KS) { return KS <= 5 ? 3 : KS <= 8 ? 2 : 1; }
+template <int FB>
+constexpr int mf_cols() { return MF_NT / 64 * FB * 32; }
 // two workgroups per CU (4 waves per SIMD: at most 128 VGPRs each, 2 x 64 KB of LDS),
 // so that one workgroup's waves multiply while the other's wait at a barrier
 constexpr int MF_WAVES_PER_SIMD = 4;
@@ -387,21 +389,20 @@ constexpr int mf_group() { return IG_MF_GTOK / KS > 0 ? IG_MF_GTOK / KS : 1; }  
 // registers (lane % 32 = column, lane / 32 = 32-token half of each word); the A
 // side streams the record tiles.  COUNT = false (coherence, Eq. 3): out[e] = 1
 // when no record contains row e; COUNT = true (support, Eq. 2): out[e] = the
-// number of records that contain it.
-template <int KS, bool COUNT>
+// number of records that contain it.  FB 32-column sets per wave.
+template <int KS, bool COUNT, int FB>
 __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const uint64_t *__restrict__ B, uint32_t m,
                                                                          const uint4 *__restrict__ frag,
                                                                          uint32_t ntiles, uint32_t pad,
                                                                          uint32_t *__restrict__ out) {
     constexpr int G = mf_group<KS>();
-    constexpr int FB = mf_sets<KS>();
     __shared__ uint4 lds[ring_lds<KS * 64, G, MF_NB>()];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     v8i_t b[FB][KS];
     uint32_t e[FB], hits[FB];
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
-        e[f] = blockIdx.x * mf_cols<KS>() + wave * (FB * 32) + f * 32 + col;
+        e[f] = blockIdx.x * mf_cols<FB>() + wave * (FB * 32) + f * 32 + col;
         const bool act = e[f] < m;
         const uint32_t *row = reinterpret_cast<const uint32_t *>(B + (size_t)(act ? e[f] : 0) * KS);
         hits[f] = 0;
@@ -467,27 +468,36 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
 }
 
 void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const uint4 *frag, uint32_t n_rec,
-                         uint32_t *out, hipStream_t s) {
+                         uint32_t *out, hipStream_t s, int sets) {
     if (!m) return;
     IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 rows in one matrix-core launch");
+    IG_REQUIRE(KO >= 1 && KO <= 16, IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
+    IG_REQUIRE(sets >= 0 && sets <= 3, IG_E_INVAL, "column sets per wave must be 0 (default) to 3");
+    const int fb = sets ? std::min(sets, mf_max_sets(KO)) : 0;
     const uint32_t ntiles = (n_rec + 31) / 32, pad = 32 * ntiles - n_rec;
-#define IG_CM(V)                                                                                                 \
-    case V: {                                                                                                    \
-        const dim3 grid((unsigned)((m + mf_cols<V>() - 1) / mf_cols<V>()));                                      \
+#define IG_CMF(V, F)                                                                                             \
+    {                                                                                                            \
+        const dim3 grid((unsigned)((m + mf_cols<F>() - 1) / mf_cols<F>()));                                      \
         if (count)                                                                                               \
-            hipLaunchKernelGGL((k_contain_mfma<V, true>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, pad, \
-                               out);                                                                             \
-        else                                                                                                     \
-            hipLaunchKernelGGL((k_contain_mfma<V, false>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, \
+            hipLaunchKernelGGL((k_contain_mfma<V, true, F>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, \
                                pad, out);                                                                        \
-        break;                                                                                                   \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_contain_mfma<V, false, F>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag,     \
+                               ntiles, pad, out);                                                                \
     }
+#define IG_CM(V)                                                                                                 \
+    case V:                                                                                                      \
+        if (fb == 1 || (fb == 0 && mf_sets<V>() == 1)) IG_CMF(V, 1)                                              \
+        else if (fb == 2 || (fb == 0 && mf_sets<V>() == 2)) IG_CMF(V, (mf_max_sets(V) >= 2 ? 2 : 1))             \
+        else IG_CMF(V, (mf_max_sets(V) >= 3 ? 3 : 1))                                                            \
+        break;
     switch (KO) {
         IG_CM(1) IG_CM(2) IG_CM(3) IG_CM(4) IG_CM(5) IG_CM(6) IG_CM(7) IG_CM(8)
         IG_CM(9) IG_CM(10) IG_CM(11) IG_CM(12) IG_CM(13) IG_CM(14) IG_CM(15) IG_CM(16)
-        default: throw Error(IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
+        default: break;
     }
 #undef IG_CM
+#undef IG_CMF
     IG_HIP(hipGetLastError());
 }
 

@@ -34,7 +34,8 @@ class IGError(RuntimeError):
 
 class TuneEntry(C.Structure):
     _fields_ = [("ks", C.c_uint32), ("min_pairs", C.c_uint32), ("filter_cpl", C.c_uint32),
-                ("grid_per_cu", C.c_uint32), ("support_cpl", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("grid_per_cu", C.c_uint32), ("support_cpl", C.c_uint32), ("mfma_words", C.c_uint32),
+                ("coherence_sets", C.c_uint32), ("support_sets", C.c_uint32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -279,7 +280,8 @@ def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tu
     if tune:
         arr = (TuneEntry * len(tune))()
         for i, e in enumerate(tune):
-            for k in ("ks", "min_pairs", "filter_cpl", "grid_per_cu", "support_cpl"):
+            for k in ("ks", "min_pairs", "filter_cpl", "grid_per_cu", "support_cpl", "mfma_words",
+                      "coherence_sets", "support_sets"):
                 setattr(arr[i], k, int(e.get(k, 0)))
         o.n_tune = len(tune)
         o.tune = C.cast(arr, C.POINTER(TuneEntry))

@@ -1,13 +1,15 @@
 """Autotuner for the launch shapes of libig's fit kernels.
 
-The shapes tuned are those of the VALU coherence and support kernels (the path
-for widths beyond the matrix-core kernels' 8 words, and the batched graph).
-For each storage width KS and problem-size bucket it fits a seeded synthetic
-problem of that width and size with every candidate shape and keeps the fastest
-(coherence: candidates per lane x workgroups per CU, timed by the library's own
-event pair around the coherence launch; support: patterns per lane, timed by its
-event pair).  The result is a table of ig_tune_entry rows, cached as JSON and
-passed to ig_fit / ig_fit_batch.  Tuning never changes results.
+Two families of shapes are tuned.  The VALU coherence and support kernels (the
+path for operands wider than the matrix-core kernels take): for each storage
+width KS and problem-size bucket a seeded synthetic problem of that width and
+size is fitted with every candidate shape (coherence: candidates per lane x
+workgroups per CU; support: patterns per lane), timed by the library's own event
+pairs.  The matrix-core contractions: for each operand width (factored words)
+and size bucket, the 32-column sets per wave of the coherence and the support
+contraction, timed by the library's event pairs around those launches
+(ig_stats.kernel_ms).  The result is a table of ig_tune_entry rows, cached as
+JSON and passed to ig_fit / ig_fit_batch.  Tuning never changes results.
 """
 from __future__ import annotations
 
@@ -69,6 +71,55 @@ def autotune(widths: Iterable[int], sizes=(1200, 5000), reps: int = 2, seed: int
                              "shapes": [dict(zip(("filter_cpl", "grid_per_cu", "support_cpl", "coherence_ms",
                                                   "support_ms"), r)) for r in rows]})
     return {"arch": "gfx950", "entries": entries, "measured": measured}
+
+
+MFMA_SETS = (1, 2, 3)
+
+
+def _problem_for_words(ko: int, n: int, seed: int) -> synth.Problem:
+    """A Dirichlet(0.5) problem whose factored operands take `ko` words: features
+    of 8 bins take 3 bit tokens and 1 presence token, so 16 ko - 4 of them fill
+    ko words but the last few tokens."""
+    rng = np.random.default_rng(seed)
+    d = max(2, 16 * ko - 4)
+    return synth.make_problem(rng, n, d, np.full(d, 8, np.int64), 0.5)
+
+
+def _time_mfma(p, tune, reps: int):
+    best_c = best_s = float("inf")
+    for _ in range(reps):
+        m = ig.fit(p.codes, p.labels, p.nbins, tune=tune)
+        st = m.stats()
+        best_c = min(best_c, st.kernel_ms[0])
+        best_s = min(best_s, st.kernel_ms[1])
+        m.free()
+    return best_c, best_s
+
+
+def autotune_mfma(words: Iterable[int], sizes=(1500, 6000), reps: int = 2, seed: int = 11) -> Dict:
+    """Column sets per wave of the matrix-core coherence and support contractions,
+    per operand width and size bucket."""
+    entries: List[Dict] = []
+    measured = []
+    for ko in sorted(set(int(w) for w in words)):
+        for n in sizes:
+            p = _problem_for_words(ko, n, seed + ko * 1000 + n)
+            n1 = int(p.labels.sum())
+            n0 = p.n - n1
+            pairs = n0 * (n0 - 1) // 2 + n1 * (n1 - 1) // 2
+            rows = []
+            for sets in MFMA_SETS:
+                t = [{"mfma_words": ko, "min_pairs": 0, "coherence_sets": sets, "support_sets": sets}]
+                c_ms, s_ms = _time_mfma(p, t, reps)
+                rows.append((sets, c_ms, s_ms))
+            best_c = min(rows, key=lambda r: r[1])
+            best_s = min(rows, key=lambda r: r[2])
+            lo = 0 if n == min(sizes) else pairs
+            entries.append({"ks": 0, "min_pairs": int(lo), "mfma_words": ko,
+                            "coherence_sets": best_c[0], "support_sets": best_s[0]})
+            measured.append({"mfma_words": ko, "n": n, "pairs": int(pairs),
+                             "shapes": [dict(zip(("sets", "coherence_ms", "support_ms"), r)) for r in rows]})
+    return {"entries": entries, "measured": measured}
 
 
 def save(table: Dict, path: str) -> None:
@@ -134,10 +185,17 @@ def main(argv=None) -> None:
     ap.add_argument("--out", required=True)
     ap.add_argument("--sizes", type=int, nargs="+", default=[1200, 5000])
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--mfma-words", type=int, nargs="+", default=list(range(3, 11)),
+                    help="operand widths of the matrix-core contractions to tune (the 64-problem "
+                         "workload factors into 3 to 10 words)")
     a = ap.parse_args(argv)
     # widths beyond the matrix-core kernels' 8 one-hot words may fall to the VALU path
     widths = [w for w in widths_of(synth.make_batch()) if w > 8]
     table = autotune(widths, sizes=tuple(a.sizes), reps=a.reps)
+    print("[tune] VALU rows:", len(table["entries"]), flush=True)
+    mf = autotune_mfma(a.mfma_words, reps=a.reps)
+    table["entries"] += mf["entries"]
+    table["measured_mfma"] = mf["measured"]
     save(table, a.out)
     print(json.dumps({"widths": widths, "entries": table["entries"]}), flush=True)
     sys.stdout.flush()
