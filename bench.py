@@ -441,8 +441,10 @@ def main():
     dense = sum(st.tests)                    # every (candidate, other-class record) pair
     on_mfma = dense != coh_tests             # the matrix-core kernels ran (no early exit)
     info = models[-1].info()
-    L_mfma = int(info.mfma_tokens)           # tokens per row of the matrix-core operands
-    W_mfma = int(info.mfma_words)            # 64-token words they occupy
+    L_mfma = int(info.fit_tokens)            # tokens per operand row of the fit's contractions
+    W_mfma = int(info.fit_words)             # 64-token words they occupy
+    L_score = int(info.mfma_tokens)          # tokens per row of the scoring operands
+    W_score = int(info.mfma_words)
     # per-kernel device time: event pairs around each launch on its stream; two
     # launches (one per class) of each contraction per fit, one scoring launch per step
     kcoh_ms = sum(mm.stats().kernel_ms[0] for mm in models) / len(models)
@@ -454,8 +456,10 @@ def main():
     kernels = {}
     if on_mfma:
         # coherence: the method's tests are sum t(b); the launch executes every pair
-        kernels["k_contain_mfma[coherence]"] = dict(ms=kcoh_ms, launches=2, tests=coh_tests, exec_tests=dense)
-        kernels["k_contain_mfma[support]"] = dict(ms=ksup_ms, launches=2, tests=sup_tests, exec_tests=sup_tests)
+        kernels["k_contain_mfma[coherence]"] = dict(ms=kcoh_ms, launches=2, tests=coh_tests, exec_tests=dense,
+                                                    tok=L_mfma, words=W_mfma)
+        kernels["k_contain_mfma[support]"] = dict(ms=ksup_ms, launches=2, tests=sup_tests, exec_tests=sup_tests,
+                                                  tok=L_mfma, words=W_mfma)
     pruned = None
     if models[-1].score_on_matrix_cores and models[-1].bucketed:
         # pruned scoring (the default): each flow meets the buckets of its tokens only.
@@ -464,19 +468,20 @@ def main():
         # rows against ceil(F_u / 256) * 256 columns.
         pruned = pruned_work(models[-1], w.test_codes, w.nbins)
         kernels["k_score_mfma_pruned"] = dict(ms=score_ms, launches=1, tests=pruned["tests"],
-                                              exec_tests=pruned["exec_tests"])
+                                              exec_tests=pruned["exec_tests"], tok=L_score, words=W_score)
     elif models[-1].score_on_matrix_cores:
-        kernels["k_score_mfma"] = dict(ms=score_ms, launches=1, tests=score_tests, exec_tests=score_tests)
+        kernels["k_score_mfma"] = dict(ms=score_ms, launches=1, tests=score_tests, exec_tests=score_tests,
+                                       tok=L_score, words=W_score)
     for k, v in kernels.items():
         v["bound"] = "mfma"
         v["unit"] = "TFLOP/s (fp4 dense)"
-        v["ops"] = 2.0 * L_mfma * v["tests"]                       # the method's operations
-        v["exec_ops"] = 2.0 * 64 * W_mfma * v["exec_tests"]         # what the padded tiles execute
+        v["ops"] = 2.0 * v["tok"] * v["tests"]                     # the method's operations
+        v["exec_ops"] = 2.0 * 64 * v["words"] * v["exec_tests"]     # what the padded tiles execute
         sec = v["ms"] / 1e3
         v["avg_ms"] = v["ms"] / v["launches"]
         v["achieved"] = v["ops"] / sec / 1e12
         v["frac"] = v["ops"] / sec / MFMA_FP4_PEAK_OPS
-        v["frac_dense"] = 2.0 * L_mfma * v["exec_tests"] / sec / MFMA_FP4_PEAK_OPS
+        v["frac_dense"] = 2.0 * v["tok"] * v["exec_tests"] / sec / MFMA_FP4_PEAK_OPS
         v["frac_executed"] = v["exec_ops"] / sec / MFMA_FP4_PEAK_OPS
         if peaks:
             v["frac_of_measured_peak"] = v["ops"] / sec / peaks["fp4_mfma_ops_per_s"]
@@ -487,7 +492,8 @@ def main():
         "dtype": "fp4(e2m1)->fp32 and int8->int32, exact integers",
         "data": "synthetic",
         "config": {"workload": w.name, "n_train": int(w.n), "n_flows": int(n_flows), "d": int(w.d),
-                   "L": int(w.L), "K": int(K), "mfma_tokens": L_mfma, "mfma_words": W_mfma},
+                   "L": int(w.L), "K": int(K), "fit_tokens": L_mfma, "fit_words": W_mfma,
+                   "score_tokens": L_score, "score_words": W_score},
         "tests_per_step": {"coherence": coh_tests, "coherence_dense": dense, "support": sup_tests,
                            "scoring": score_tests,
                            "scoring_executed": pruned["tests"] if pruned else score_tests},
@@ -502,7 +508,7 @@ def main():
                            "peak": MFMA_FP4_PEAK_OPS / 1e12, "unit": d["unit"], "frac": d["frac"],
                            "traffic": counted_traffic(args.traffic, dom), "avg_ms": d["avg_ms"],
                            "launches_per_step": d["launches"],
-                           "tokens_per_test": L_mfma, "tests_per_launch": d["tests"] / d["launches"],
+                           "tokens_per_test": d["tok"], "tests_per_launch": d["tests"] / d["launches"],
                            "frac_dense": d["frac_dense"], "frac_executed": d["frac_executed"],
                            "frac_of_measured_peak": d.get("frac_of_measured_peak")}
         res["kernels"] = {k: {x: (round(v[x], 4) if isinstance(v[x], float) else v[x])

@@ -111,13 +111,24 @@ typedef struct {
                                        operands and fp32 accumulation, exact; no early
                                        exit, so ig_stats.tests counts every (candidate,
                                        other-class record) pair.  Fits from codes use
-                                       factored tokens (per feature the bits of its
-                                       bin index plus presence tokens: 207 instead of
-                                       464 tokens for 41 features of ~11 bins), else
-                                       the K one-hot words; at most 16 words;
+                                       factored tokens: those of mode 5 when they
+                                       take fewer words than those of mode 4, else
+                                       those of mode 4; other fits the K one-hot
+                                       words; at most 16 words;
                                    2 = VALU path: AND-NOT chains with early exit in
                                        input order (ig_stats.tests = sum of t(b));
-                                   3 = matrix cores on the one-hot words (K <= 16).
+                                   3 = matrix cores on the one-hot words (K <= 16);
+                                   4 = matrix cores on factored tokens with presence
+                                       tokens (bits of the bin index plus one or two
+                                       presence tokens per feature: 207 tokens, 4
+                                       words, for 41 features of ~11 bins);
+                                   5 = matrix cores on ternary bit tokens whenever
+                                       the fit has them (else as 1): the bits of each
+                                       feature's bin index alone, +1 / -1 on both
+                                       sides for a bit of a feature the row holds, 0
+                                       for one it lacks, plus a few bias tokens: 165
+                                       + 7 tokens, 3 words, for 41 features of ~11
+                                       bins.
                                    All give the same patterns, f and S.             */
     uint32_t reserved;
     const ig_allocator *alloc;  /* NULL: the library's device arena (chunks taken from
@@ -159,6 +170,11 @@ typedef struct {
     uint32_t mfma_words;     /* 64-token words per row of those operands             */
     uint64_t n_patterns[2];  /* |P^0|, |P^1|                                         */
     int64_t max_weight[2];   /* largest S of each class                              */
+    uint32_t fit_tokens;     /* tokens per operand row of the fit's matrix-core
+                                contractions (coherence, support): the ternary bit
+                                tokens, the factored count or L; 0 when the fit ran
+                                on the vector ALUs or the model was imported         */
+    uint32_t fit_words;      /* 64-token words per operand row of those              */
 } ig_model_info;
 
 /* ig_model_info.flags.  IG_MODEL_SCORE_MFMA: ig_score evaluates Eq. 4 on the

@@ -50,8 +50,12 @@ struct DevModel {
     uint32_t npieces = 0, nkeys = 0;
     void *fac = nullptr;                   // factored-token table (one device block)
     FactorView fv;                         // fv.KF = 0: matrix-core operands stay one-hot
+    void *tfac = nullptr;                  // the ternary (bit tokens only) table
+    FactorView tv;                         // of the coherence and support contractions
     uint32_t fac_tokens = 0;               // tokens of the factored form
     uint32_t fac_tokens_last = 0;          // of them, in its last word
+    uint32_t tern_tokens = 0;              // tokens of the ternary form
+    uint32_t fit_tokens = 0, fit_words = 0;    // operand rows of the fit's contractions
     bool score_factored = false;           // frag holds factored operand rows
     bool score_spare = false;              // frag carries the +1 at the spare last token
     ig_stats stats{};
@@ -74,6 +78,7 @@ struct DevModel {
         release(nbins);
         release(pieces);
         release(fac);
+        release(tfac);
     }
 };
 
@@ -181,7 +186,10 @@ static uint32_t feature_tokens(uint32_t nb, uint32_t *bits) {
 // pattern lacks the feature), so the contraction is zero exactly when the pattern
 // lies inside (Eq. 6).  Tokens are laid out feature after feature; a feature may
 // cross a word boundary, so its tokens touch at most two words.
-static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, hipStream_t s) {
+//
+// ternary: the table of the bit tokens alone (no presence tokens), for the
+// contractions of the fit (see FactorView::ternary); stored in m.tv / m.tfac.
+static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, hipStream_t s, bool ternary = false) {
     std::vector<FacFeature> feat(d);
     std::vector<uint64_t> mask;
     std::vector<uint64_t> fbit(2 * (size_t)d, 0);   // bit tokens of each feature, words w0 and w0 + 1
@@ -192,8 +200,9 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     for (uint32_t f = 0; f < d; ++f) {
         const uint32_t nb = h_nbins[f];
         uint32_t mb = 0;
-        const uint32_t nt = feature_tokens(nb, &mb);
+        uint32_t nt = feature_tokens(nb, &mb);
         if (nt == ~0u) return;   // a feature beyond 1024 bins: stay one-hot
+        if (ternary) nt = mb;
         if (f >= (1u << 16)) return;
         FacFeature ft{};
         ft.off = (uint16_t)off;
@@ -213,7 +222,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
                     bitw[t / 64] |= 1ull << (t % 64);
                 }
             }
-            ptok[f] = (t0 + mb) | (nt - mb) << 24;
+            if (!ternary) ptok[f] = (t0 + mb) | (nt - mb) << 24;
             for (uint32_t c = 0; c < nb; ++c) {
                 uint64_t part[2] = {0, 0};
                 for (uint32_t t = t0; t < t1; ++t) {
@@ -229,8 +238,9 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
         feat[f] = ft;
         off += nb;
     }
-    const uint32_t KF = tokens ? word + 1 : 0;
-    if (KF == 0 || KF >= m.K) return;
+    // a ternary view keeps the top tokens of its last word for the bias slots
+    const uint32_t KF = !tokens ? 0 : ternary ? (tokens + tern_bias_slots(tokens) + 63) / 64 : word + 1;
+    if (KF == 0 || KF >= m.K || KF > 16) return;
     // pieces: each feature cut at one-hot word boundaries
     std::vector<std::vector<FacPiece>> by_word(m.K);
     for (uint32_t f = 0; f < d; ++f) {
@@ -245,6 +255,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
             p.nw = ft.nw;
             p.base = (uint16_t)(t - ft.off);
             p.mask = ft.mask;
+            p.pad2 = f;   // the feature (ternary views read its tokens, fbit, as P)
             by_word[w].push_back(p);
             t = hi;
         }
@@ -319,28 +330,34 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     const size_t o_bitw = put(bitw.data(), bitw.size() * 8, wb);
     const size_t o_ptok = put(ptok.data(), ptok.size() * 4, qb);
     char *dev = dev_alloc<char>(host.size());
-    m.fac = dev;
+    (ternary ? m.tfac : m.fac) = dev;
     IG_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, s));
     IG_HIP(hipStreamSynchronize(s));   // host must outlive its copy
-    m.fv.mask = reinterpret_cast<const uint64_t *>(dev + o_mask);
-    m.fv.feat = reinterpret_cast<const FacFeature *>(dev + o_feat);
-    m.fv.piece = reinterpret_cast<const FacPiece *>(dev + o_piece);
-    m.fv.fbeg = reinterpret_cast<const uint32_t *>(dev + o_fbeg);
-    m.fv.fend = reinterpret_cast<const uint32_t *>(dev + o_fend);
-    m.fv.pbeg = reinterpret_cast<const uint32_t *>(dev + o_pbeg);
-    m.fv.wfe = reinterpret_cast<const uint4 *>(dev + o_wfe);
-    m.fv.wbeg = reinterpret_cast<const uint32_t *>(dev + o_wbeg);
-    m.fv.tok = reinterpret_cast<const uint32_t *>(dev + o_tok);
-    m.fv.fbit = reinterpret_cast<const uint64_t *>(dev + o_fbit);
-    m.fv.bitw = reinterpret_cast<const uint64_t *>(dev + o_bitw);
-    m.fv.ptok = reinterpret_cast<const uint32_t *>(dev + o_ptok);
-    m.fv.d = d;
-    m.fv.KF = KF;
-    m.fv.nmask = (uint32_t)mask.size();
-    m.fv.npiece = (uint32_t)piece.size();
-    m.fv.nwords = m.KS;
-    m.fac_tokens_last = used;
-    m.fac_tokens = tokens;
+    FactorView &v = ternary ? m.tv : m.fv;
+    v.mask = reinterpret_cast<const uint64_t *>(dev + o_mask);
+    v.feat = reinterpret_cast<const FacFeature *>(dev + o_feat);
+    v.piece = reinterpret_cast<const FacPiece *>(dev + o_piece);
+    v.fbeg = reinterpret_cast<const uint32_t *>(dev + o_fbeg);
+    v.fend = reinterpret_cast<const uint32_t *>(dev + o_fend);
+    v.pbeg = reinterpret_cast<const uint32_t *>(dev + o_pbeg);
+    v.wfe = reinterpret_cast<const uint4 *>(dev + o_wfe);
+    v.wbeg = reinterpret_cast<const uint32_t *>(dev + o_wbeg);
+    v.tok = reinterpret_cast<const uint32_t *>(dev + o_tok);
+    v.fbit = reinterpret_cast<const uint64_t *>(dev + o_fbit);
+    v.bitw = reinterpret_cast<const uint64_t *>(dev + o_bitw);
+    v.ptok = reinterpret_cast<const uint32_t *>(dev + o_ptok);
+    v.d = d;
+    v.KF = KF;
+    v.nmask = (uint32_t)mask.size();
+    v.npiece = (uint32_t)piece.size();
+    v.nwords = m.KS;
+    v.ternary = ternary ? 1u : 0u;
+    if (!ternary) {
+        m.fac_tokens_last = used;
+        m.fac_tokens = tokens;
+    } else {
+        m.tern_tokens = tokens;
+    }
 }
 
 static void check_nbins(const uint16_t *h_nbins, uint32_t d, uint32_t &L, uint32_t &K) {
@@ -560,18 +577,20 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
     if (own_frag) {
         // f on the matrix cores against the class's own records, then S = f |b|^2
         const uint32_t KO = mfma_view.KF ? mfma_view.KF : KS;
+        const uint32_t RW = mfma_view.ternary ? 2 * KO : KO;
         Scratch<uint64_t> B;
         if (pre_rows && !may_repeat) {
             B = std::move(*pre_rows);   // the coherence step's rows of these patterns, same order
         } else {
-            B.reset(final_count * KO, s);
+            B.reset(final_count * RW, s);
             launch_operand_rows(nullptr, 0, nullptr, m.W[c], KS, final_count, mfma_view, false, B.get(), s);
         }
         hipEvent_t ke[2];
         IG_HIP(hipEventCreate(&ke[0]));
         IG_HIP(hipEventCreate(&ke[1]));
         IG_HIP(hipEventRecord(ke[0], s));
-        launch_contain_mfma((int)KO, true, B.get(), final_count, own_frag, cls.n, m.f[c], s, tu.sup_sets);
+        launch_contain_mfma((int)KO, true, B.get(), final_count, own_frag, cls.n, m.f[c], s, tu.sup_sets,
+                            mfma_view.ternary != 0);
         IG_HIP(hipEventRecord(ke[1], s));
         launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
         float tk = 0;
@@ -582,7 +601,7 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         IG_HIP(er);
         m.stats.kernel_ms[1] += tk;
         // the scoring operands use the model's own view: keep the rows when it is this one
-        if (keep && mfma_view.KF == m.fv.KF && mfma_view.KF) {
+        if (keep && !mfma_view.ternary && mfma_view.KF == m.fv.KF && mfma_view.KF) {
             keep->rows[c] = std::move(B);
             keep->valid[c] = true;
         }
@@ -749,28 +768,33 @@ struct MfmaFit {
     bool on = false;
     FactorView view;
     uint32_t KO = 0;
+    uint32_t RW = 0;           // words per operand row: 2 KO for a ternary view
     Scratch<uint4> frag[2];
     Scratch<uint64_t> fr[2];   // factored rows of each class's records (factored view only)
 };
 
 // Decide the subset-test path of a fit from the coherence_mfma option (0 auto:
 // matrix cores when the operands fit 16 words; 1 matrix cores; 2 VALU; 3 matrix
-// cores on the one-hot words) and build the record tiles when it is the matrix
-// cores.
+// cores on the one-hot words; 4 matrix cores on the factored tokens with presence
+// tokens; 5 matrix cores on the ternary bit tokens) and build the record tiles
+// when it is the matrix cores.  Modes 0 and 1 take the ternary view (bit tokens
+// only) of a fit from codes when it needs fewer words than the presence tokens.
 static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode, MfmaFit &mf, hipStream_t s) {
-    IG_REQUIRE(mode <= 3, IG_E_INVAL, "coherence_mfma must be 0, 1, 2 or 3");
+    IG_REQUIRE(mode <= 5, IG_E_INVAL, "coherence_mfma must be 0 to 5");
     const uint32_t KS = m.KS;
-    mf.view = mode == 3 ? FactorView{} : m.fv;
+    const bool tern = m.tv.KF && (mode == 5 || ((mode == 0 || mode == 1) && (!m.fv.KF || m.tv.KF < m.fv.KF)));
+    mf.view = mode == 3 ? FactorView{} : tern ? m.tv : m.fv;
     mf.KO = mf.view.KF ? mf.view.KF : KS;
-    IG_REQUIRE((mode != 1 && mode != 3) || mf.KO <= kMfmaWords, IG_E_UNSUPPORTED,
+    mf.RW = mf.view.ternary ? 2 * mf.KO : mf.KO;
+    IG_REQUIRE(mode == 0 || mode == 2 || mf.KO <= kMfmaWords, IG_E_UNSUPPORTED,
                "the matrix-core subset tests handle up to 16 operand words");
-    mf.on = mode == 1 || mode == 3 || (mode == 0 && mf.KO <= kMfmaWords);
+    mf.on = mode != 2 && (mode != 0 || mf.KO <= kMfmaWords);
     if (!mf.on) return;
     if (mf.view.KF) {
         // each class's records, factored: its candidates' rows are built from them,
-        // and the other class's record tiles hold them on the signed side
+        // and the other class's record tiles hold them on the signed (or ternary) side
         for (int c = 0; c < 2; ++c) {
-            mf.fr[c].reset(std::max<size_t>(cls[c].n, 1) * mf.KO, s);
+            mf.fr[c].reset(std::max<size_t>(cls[c].n, 1) * mf.RW, s);
             launch_operand_rows(nullptr, 0, nullptr, cls[c].X.get(), KS, cls[c].n, mf.view, false, mf.fr[c].get(),
                                 s);
         }
@@ -778,7 +802,9 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
     for (int c = 0; c < 2; ++c) {
         const ClassRows &o = cls[1 - c];
         mf.frag[c].reset(std::max<size_t>((size_t)mfma_record_tiles(o.n) * mf.KO * 64, 1), s);
-        if (mf.view.KF) launch_mfma_records_signed(mf.fr[1 - c].get(), o.n, mf.view, mf.frag[c].get(), s);
+        if (mf.view.ternary)
+            launch_mfma_records_ternary(mf.fr[1 - c].get(), o.n, mf.KO, m.tern_tokens, mf.frag[c].get(), s);
+        else if (mf.view.KF) launch_mfma_records_signed(mf.fr[1 - c].get(), o.n, mf.view, mf.frag[c].get(), s);
         else launch_mfma_records(o.NX.get(), o.n, KS, mf.frag[c].get(), s);
     }
 }
@@ -791,7 +817,7 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
                                uint64_t *rows_out = nullptr, int sets = 0) {
     if (!ncand) return 0;
     Scratch<uint32_t> keep(ncand, s), kpos(ncand, s), ktot(1, s);
-    Scratch<uint64_t> B((size_t)ncand * mf.KO, s);
+    Scratch<uint64_t> B((size_t)ncand * mf.RW, s);
     if (mf.view.KF)
         launch_pair_rows_factored(mf.fr[c].get(), cls[c].n, cand, ncand, mf.view, B.get(), s);
     else
@@ -807,17 +833,24 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
         }
     } evg{ke};
     IG_HIP(hipEventRecord(ke[0], s));
-    launch_contain_mfma((int)mf.KO, false, B.get(), ncand, mf.frag[c].get(), cls[1 - c].n, keep.get(), s, sets);
+    launch_contain_mfma((int)mf.KO, false, B.get(), ncand, mf.frag[c].get(), cls[1 - c].n, keep.get(), s, sets,
+                        mf.view.ternary != 0);
     IG_HIP(hipEventRecord(ke[1], s));
     scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
     launch_compact(keep.get(), kpos.get(), cand, ncand, out, s);
     // the coherent candidates' operand rows, in the same order (support and scoring use them)
-    if (rows_out) launch_compact_rows(B.get(), keep.get(), kpos.get(), ncand, mf.KO, rows_out, s);
+    if (rows_out) launch_compact_rows(B.get(), keep.get(), kpos.get(), ncand, mf.RW, rows_out, s);
     const uint32_t kept = host_read_u32(ktot.get(), 1, s)[0];
     float tk = 0;
     IG_HIP(hipEventElapsedTime(&tk, ke[0], ke[1]));
     if (kernel_ms) *kernel_ms += tk;
     return kept;
+}
+
+// The operand rows of the fit's contractions, for ig_model_info.
+static void note_fit_operands(DevModel &m, const MfmaFit &mf) {
+    m.fit_words = mf.KO;
+    m.fit_tokens = mf.view.ternary ? m.tern_tokens : mf.view.KF ? m.fac_tokens : m.L;
 }
 
 static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts, hipStream_t s, Timer &tm) {
@@ -888,7 +921,10 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     MfmaFit mf;
     mfma_setup(m, cls, opts ? opts->coherence_mfma : 0u, mf, s);
     const bool use_mfma = mf.on;
-    if (use_mfma) mfma_tuning(opts, mf.KO, fit_pairs, tu);
+    if (use_mfma) {
+        mfma_tuning(opts, mf.KO, fit_pairs, tu);
+        note_fit_operands(m, mf);
+    }
     Scratch<uint64_t> surv_rows[2];   // operand rows of the coherent candidates (one-chunk fits)
     uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
     float ms_pairs = 0, ms_sort = 0, ms_dedup = 0, ms_coh = 0;
@@ -954,7 +990,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
                 // one chunk: keep the survivors' operand rows for support and scoring
                 uint64_t *ro = nullptr;
                 if (chunks.size() == 1) {
-                    surv_rows[c].reset(std::max<size_t>(hc[c], 1) * mf.KO, s);
+                    surv_rows[c].reset(std::max<size_t>(hc[c], 1) * mf.RW, s);
                     ro = surv_rows[c].get();
                 }
                 mfma_surv[c] += mfma_coherence(mf, cls, c, KS, cc, hc[c], surv[c].get() + mfma_surv[c],
@@ -1116,6 +1152,7 @@ DevModel *fit_codes(const uint16_t *d_codes, const uint8_t *d_labels, uint32_t n
     IG_HIP(hipMemcpyAsync(m->nbins, h_nbins, d * 2, hipMemcpyHostToDevice, s));
     set_key_pieces(*m, h_nbins, d, s);
     set_factor_table(*m, h_nbins, d, s);
+    set_factor_table(*m, h_nbins, d, s, true);
     Scratch<uint32_t> err(1, s), pos(n ? n : 1, s), counts(2, s);
     launch_fill_u32(err.get(), 0u, 1, s);
     launch_fill_u32(counts.get(), 0u, 2, s);
@@ -1289,7 +1326,10 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
     // segments then give the captured VALU coherence no candidates (a zero count)
     const uint32_t mode = opts ? opts->coherence_mfma : 0u;
     std::vector<MfmaFit> mf(G.size());
-    for (uint32_t g = 0; g < G.size(); ++g) mfma_setup(*G[g]->m, G[g]->cls, mode, mf[g], s);
+    for (uint32_t g = 0; g < G.size(); ++g) {
+        mfma_setup(*G[g]->m, G[g]->cls, mode, mf[g], s);
+        if (mf[g].on) note_fit_operands(*G[g]->m, mf[g]);
+    }
     Scratch<uint32_t> zero(1, s);
     {
         std::vector<unsigned char> hr(nseg * rows_of_seg_size());
@@ -1449,6 +1489,7 @@ void fit_batch(const ig_problem *probs, uint32_t np, const ig_fit_opts *opts, hi
         IG_HIP(hipStreamSynchronize(s));   // the host table must outlive its copy
         set_key_pieces(*b.m, b.nbins, b.d, s);
         set_factor_table(*b.m, b.nbins, b.d, s);
+        set_factor_table(*b.m, b.nbins, b.d, s, true);
         b.err.reset(1, s);
         b.pos.reset(b.n ? b.n : 1, s);
         b.counts.reset(2, s);
@@ -1800,6 +1841,8 @@ ig_status ig_model_get_info(const ig_model *m, ig_model_info *info) {
                       ((M.frag[0] && M.frag[1] && M.btile[0] && M.btile[1]) ? IG_MODEL_BUCKETED : 0u);
         info->mfma_tokens = M.score_factored ? M.fac_tokens : M.L;
         info->mfma_words = M.score_factored ? M.fv.KF : M.K;
+        info->fit_tokens = M.fit_tokens;
+        info->fit_words = M.fit_words;
         for (int c = 0; c < 2; ++c) {
             info->n_patterns[c] = M.np[c];
             info->max_weight[c] = M.maxS[c];

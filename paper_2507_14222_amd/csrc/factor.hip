@@ -48,14 +48,22 @@ __global__ __launch_bounds__(256) void k_operand_rows(const uint64_t *__restrict
         return;
     }
     for (uint32_t ow = 0; ow < KO; ++ow) {
-        uint64_t acc = 0;
+        uint64_t acc = 0, pres = 0;
         for (uint32_t f = fv.fbeg[ow]; f < fv.fend[ow]; ++f) {
             const FacFeature ft = fv.feat[f];
             if (ow - ft.w0 >= ft.nw) continue;   // a one-bin feature has no tokens
             const int code = feature_code(word, ft);
-            if (code >= 0) acc |= fv.mask[ft.mask + (uint32_t)code * ft.nw + (ow - ft.w0)];
+            if (code >= 0) {
+                acc |= fv.mask[ft.mask + (uint32_t)code * ft.nw + (ow - ft.w0)];
+                pres |= fv.fbit[2 * f + (ow - ft.w0)];
+            }
         }
-        out[e * KO + ow] = acc ^ flip;
+        if (fv.ternary) {
+            out[e * 2 * KO + ow] = pres;
+            out[e * 2 * KO + KO + ow] = acc;
+        } else {
+            out[e * KO + ow] = acc ^ flip;
+        }
     }
 }
 
@@ -99,7 +107,9 @@ static_assert(sizeof(FacPiece) == 16 && offsetof(FacPiece, base) == 4 && offseto
 // read back to scalar registers with readfirstlane.
 constexpr uint32_t kLdsPieces = 512;
 
-template <int KS, bool LPIECES>
+// TERN: a ternary view (FactorView::ternary): rows of 2 KO words, P (the tokens
+// of each feature whose bin the row holds, fbit of the piece's feature) then V.
+template <int KS, bool LPIECES, bool TERN>
 __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__restrict__ X, uint32_t n,
                                                          const uint32_t *__restrict__ ids,
                                                          const uint64_t *__restrict__ W, size_t m, FactorView fv,
@@ -123,6 +133,7 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
             for (int k = 0; k < KS; ++k) w[k] = W[e * KS + k];
         }
         uint64_t acc[16] = {};
+        uint64_t pres[TERN ? 16 : 1] = {};
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const uint32_t p1 = fv.pbeg[k + 1];
@@ -131,7 +142,8 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
                 if (LPIECES) {
                     const uint4 v = spiece[p];   // same address in every lane
                     pc = make_uint4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
-                                    __builtin_amdgcn_readfirstlane(v.z), 0u);
+                                    __builtin_amdgcn_readfirstlane(v.z),
+                                    TERN ? __builtin_amdgcn_readfirstlane(v.w) : 0u);
                 } else {
                     pc = pw[p];
                 }
@@ -147,11 +159,26 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
                 const uint64_t m1 = x && nw > 1 ? smask[idx + 1] : 0ull;
                 acc[w0] |= m0;
                 acc[(w0 + 1) & 15] |= m1;
+                if (TERN) {
+                    // the feature's tokens when the row holds one of its bins
+                    const uint64_t f0 = fv.fbit[2 * pc.w], f1 = nw > 1 ? fv.fbit[2 * pc.w + 1] : 0ull;
+                    pres[w0] |= x ? f0 : 0ull;
+                    pres[(w0 + 1) & 15] |= x ? f1 : 0ull;
+                }
             }
         }
+        if (TERN) {
 #pragma unroll
-        for (int o = 0; o < 16; ++o)
-            if ((uint32_t)o < KO) out[e * KO + o] = acc[o] ^ flip;
+            for (int o = 0; o < 16; ++o)
+                if ((uint32_t)o < KO) {
+                    out[e * 2 * KO + o] = pres[o];
+                    out[e * 2 * KO + KO + o] = acc[o];
+                }
+        } else {
+#pragma unroll
+            for (int o = 0; o < 16; ++o)
+                if ((uint32_t)o < KO) out[e * KO + o] = acc[o] ^ flip;
+        }
     }
 }
 
@@ -162,15 +189,18 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
 // A feature whose tokens span two words is tested on both (first pass, one bit
 // per such feature).  Each thread takes R rows at once, so one wave-uniform table
 // entry (a scalar load) serves R rows.
-template <int KO, int R>
+// TERN: ternary rows (P then V, 2 KO words): the pair keeps P_i AND P_j on the
+// features where V_i and V_j agree, and V_i on those.
+template <int KO, int R, bool TERN>
 __global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__restrict__ FR, uint32_t n,
                                                            const uint32_t *__restrict__ ids, size_t m,
                                                            const uint4 *__restrict__ wfe,
                                                            const uint32_t *__restrict__ wbeg,
                                                            uint64_t *__restrict__ out) {
+    constexpr int RW = TERN ? 2 * KO : KO;   // words per row
     const size_t T = (size_t)gridDim.x * blockDim.x;
     for (size_t e0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < m; e0 += T * R) {
-        uint64_t x[R][KO], keep[R][KO];
+        uint64_t x[R][KO], keep[R][KO], val[R][TERN ? KO : 1];
         uint32_t D[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -179,9 +209,16 @@ __global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__re
             if (e < m) decode_pair(ids[e], n, i, j);
 #pragma unroll
             for (int o = 0; o < KO; ++o) {
-                const uint64_t a = FR[(size_t)i * KO + o], b = FR[(size_t)j * KO + o];
-                x[r][o] = a ^ b;
-                keep[r][o] = a & b;
+                if (TERN) {
+                    const uint64_t va = FR[(size_t)i * RW + KO + o], vb = FR[(size_t)j * RW + KO + o];
+                    x[r][o] = va ^ vb;
+                    keep[r][o] = FR[(size_t)i * RW + o] & FR[(size_t)j * RW + o];
+                    val[r][TERN ? o : 0] = va;
+                } else {
+                    const uint64_t a = FR[(size_t)i * KO + o], b = FR[(size_t)j * KO + o];
+                    x[r][o] = a ^ b;
+                    keep[r][o] = a & b;
+                }
             }
             D[r] = 0;
         }
@@ -210,7 +247,10 @@ __global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__re
             const size_t e = e0 + r * T;
             if (e < m)
 #pragma unroll
-                for (int o = 0; o < KO; ++o) out[e * KO + o] = keep[r][o];
+                for (int o = 0; o < KO; ++o) {
+                    out[e * RW + o] = keep[r][o];
+                    if (TERN) out[e * RW + KO + o] = val[r][TERN ? o : 0] & keep[r][o];
+                }
         }
     }
 }
@@ -224,7 +264,12 @@ void launch_pair_rows_factored(const uint64_t *FR, uint32_t n, const uint32_t *i
 #define IG_PR(V, RR)                                                                                               \
     case V: {                                                                                                      \
         const dim3 grid((unsigned)std::min<size_t>((m + 256 * RR - 1) / (256 * RR), cap));                       \
-        hipLaunchKernelGGL((k_pair_rows_factored<V, RR>), grid, dim3(256), 0, s, FR, n, ids, m, fv.wfe, fv.wbeg, out); \
+        if (fv.ternary)                                                                                            \
+            hipLaunchKernelGGL((k_pair_rows_factored<V, RR, true>), grid, dim3(256), 0, s, FR, n, ids, m, fv.wfe,  \
+                               fv.wbeg, out);                                                                      \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_pair_rows_factored<V, RR, false>), grid, dim3(256), 0, s, FR, n, ids, m, fv.wfe, \
+                               fv.wbeg, out);                                                                      \
         break;                                                                                                     \
     }
     switch (fv.KF) {
@@ -242,6 +287,7 @@ void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, con
     const uint32_t KO = fv.KF ? fv.KF : KS;
     // the register kernel walks the pieces of every one of the KS words
     IG_REQUIRE(!fv.KF || fv.nwords == KS, IG_E_DEVICE, "factoring table built for another storage width");
+    IG_REQUIRE(!fv.ternary || !complement, IG_E_DEVICE, "ternary rows are never complemented");
     const dim3 grid((unsigned)((m + 255) / 256));
     const uint64_t flip = complement ? ~0ull : 0ull;
     const bool reg_width = KS <= 16 || KS == 20 || KS == 24 || KS == 28 || KS == 32 || KS == 40;
@@ -250,12 +296,19 @@ void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, con
         const dim3 sgrid((unsigned)std::min<size_t>((m + 255) / 256, (size_t)device_cus() * 8));
 #define IG_OR_K(V)                                                                                             \
     case V:                                                                                                    \
-        if (fv.npiece <= kLdsPieces)                                                                           \
-            hipLaunchKernelGGL((k_operand_rows_reg<V, true>), sgrid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, \
-                               flip, out);                                                                     \
+        if (fv.ternary) {                                                                                      \
+            if (fv.npiece <= kLdsPieces)                                                                       \
+                hipLaunchKernelGGL((k_operand_rows_reg<V, true, true>), sgrid, dim3(256), 0, s, X, n, ids, W, m, \
+                                   fv, KO, flip, out);                                                         \
+            else                                                                                               \
+                hipLaunchKernelGGL((k_operand_rows_reg<V, false, true>), sgrid, dim3(256), 0, s, X, n, ids, W, m, \
+                                   fv, KO, flip, out);                                                         \
+        } else if (fv.npiece <= kLdsPieces)                                                                    \
+            hipLaunchKernelGGL((k_operand_rows_reg<V, true, false>), sgrid, dim3(256), 0, s, X, n, ids, W, m, fv, \
+                               KO, flip, out);                                                                 \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_operand_rows_reg<V, false>), sgrid, dim3(256), 0, s, X, n, ids, W, m, fv, KO, \
-                               flip, out);                                                                     \
+            hipLaunchKernelGGL((k_operand_rows_reg<V, false, false>), sgrid, dim3(256), 0, s, X, n, ids, W, m, fv, \
+                               KO, flip, out);                                                                 \
         break;
         switch (KS) {   // the compiled storage widths up to 40 words
             IG_OR_K(1) IG_OR_K(2) IG_OR_K(3) IG_OR_K(4) IG_OR_K(5) IG_OR_K(6) IG_OR_K(7) IG_OR_K(8)

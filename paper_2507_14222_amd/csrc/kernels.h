@@ -116,13 +116,22 @@ struct FactorView {
     const uint64_t *bitw = nullptr;     // [KF]: the bit tokens of every feature, per word
     const uint32_t *ptok = nullptr;     // [d]: first presence token | count << 24 (~0: none)
     uint32_t d = 0, KF = 0;             // KF = 0: no factoring (operands are the one-hot words)
+    // ternary = 1: bit tokens only, no presence tokens.  A row is two bitsets of KF
+    // words, P (every bit token of each feature the row holds) then V (the bits of
+    // its bin indices, V inside P); both sides of a contraction read P AND NOT V as
+    // +1, P AND V as -1, the rest as 0, so a (candidate, record) product sums to
+    // |P_b| - 2 (bits in which their bin indices differ): |P_b| exactly when b lies
+    // inside r.  mask holds only the bin bits; fbit the feature's tokens (P), and
+    // a piece's pad2 its feature.
+    uint32_t ternary = 0;
     uint32_t nmask = 0;                 // entries of mask
     uint32_t npiece = 0;                // entries of piece
     uint32_t nwords = 0;                // one-hot storage words pbeg covers (the fit's KS)
 };
-// Operand rows out[m][KO], KO = fv.KF when factoring, else KS: row e is the
-// pattern X[i] AND X[j] of pair id ids[e] (ids non-null, rows X [n][KS]) or the
-// row W[e] [m][KS]; complement writes NOT of every word.
+// Operand rows out[m][KO], KO = fv.KF when factoring, else KS (out[m][2 KO], P then
+// V, for a ternary view): row e is the pattern X[i] AND X[j] of pair id ids[e] (ids
+// non-null, rows X [n][KS]) or the row W[e] [m][KS]; complement writes NOT of every
+// word (not for a ternary view).
 void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, const uint64_t *W, uint32_t KS, size_t m,
                          const FactorView &fv, bool complement, uint64_t *out, hipStream_t s);
 // Factored operand rows of record pairs from the records' own factored rows FR
@@ -167,10 +176,24 @@ void launch_mfma_records(const uint64_t *NX, uint32_t n, uint32_t KS, uint4 *fra
 // The same tiles for factored tokens: records on the signed side (FactorView::tok)
 // from their factored rows FR [n][fv.KF]; KO = fv.KF.
 void launch_mfma_records_signed(const uint64_t *FR, uint32_t n, const FactorView &fv, uint4 *frag, hipStream_t s);
+// Bias slots of a ternary view with T bit tokens: the top tern_bias_slots(T) tokens
+// of its last word hold no bit token.  In the record tiles the top slot is +1.0 and
+// the others +6.0; each candidate row carries there the nibbles (weights 0, +-0.5
+// .. +-6) that add 1 - |P| to its product with every record, so that a product is
+// 1 when the record contains the candidate and at most -1 otherwise.  1 - |P| is
+// reached with one +1.0 slot (the remainder modulo 3), floor((|P| - 1) / 36) slots
+// of 36 and two of at most 24: 3 + floor((T - 1) / 36) slots.
+__host__ __device__ constexpr uint32_t tern_bias_slots(uint32_t T) { return 3u + (T ? (T - 1u) / 36u : 0u); }
+// The same tiles for a ternary view, from the records' ternary rows FR [n][2 KO]
+// with T bit tokens: the same nibbles as the candidate side (P AND NOT V +1.0, P
+// AND V -1.0, else 0) and the bias slots; rows past n are 0 on every token.
+void launch_mfma_records_ternary(const uint64_t *FR, uint32_t n, uint32_t KO, uint32_t T, uint4 *frag,
+                                 hipStream_t s);
 // sets: 32-column sets per wave (1..3, capped by what fits the registers at KO
-// words; 0 = the default for KO)
+// words; 0 = the default for KO).  ternary: B rows are [m][2 KO] ternary rows and
+// the tiles come from launch_mfma_records_ternary.
 void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const uint4 *frag, uint32_t n_rec,
-                         uint32_t *out, hipStream_t s, int sets = 0);
+                         uint32_t *out, hipStream_t s, int sets = 0, bool ternary = false);
 
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented
 // rows NX [n][KS] of their class.

@@ -356,6 +356,39 @@ __global__ void k_mfma_records_signed(const uint64_t *__restrict__ FR, uint32_t 
     frag[g] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
 }
 
+// Ternary rows (P then V, KO words each) as A-operand tiles: lane l of slice w
+// holds half l / 32 of word w of row tile * 32 + l % 32 as nibbles, P AND NOT V
+// +1.0 (0x2), P AND V -1.0 (0xA), else 0.  The top nslots tokens of the last word
+// (no bit token lies there) are the bias slots: +1.0 on the top one, +6.0 below it,
+// against which each candidate row carries the nibbles that add 1 - |P|.  Rows past
+// n are 0 everywhere, so every product with them is 0, never the 1 of a record that
+// contains the candidate.
+__global__ void k_mfma_records_ternary(const uint64_t *__restrict__ FR, uint32_t n, uint32_t KO, uint32_t ntiles,
+                                       uint32_t nslots, uint4 *__restrict__ frag) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (size_t)ntiles * KO * 64) return;
+    const uint32_t lane = (uint32_t)(g % 64), word = (uint32_t)((g / 64) % KO), tile = (uint32_t)(g / (64 * KO));
+    const uint32_t r = tile * 32 + lane % 32, h = lane / 32;
+    uint32_t P = 0, V = 0;
+    if (r < n) {
+        P = (uint32_t)(FR[(size_t)r * 2 * KO + word] >> (32 * h));
+        V = (uint32_t)(FR[(size_t)r * 2 * KO + KO + word] >> (32 * h));
+    }
+    uint32_t q[4] = {spread8(P) | spread8(V) * 4u, spread8(P >> 8) | spread8(V >> 8) * 4u,
+                     spread8(P >> 16) | spread8(V >> 16) * 4u, spread8(P >> 24) | spread8(V >> 24) * 4u};
+    if (r < n && word == KO - 1 && h == 1) {
+        // the bias slots, from the top token down: +1.0, then +6.0
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t slot = 31u - (uint32_t)(8 * j + i);
+                if (slot < nslots) q[j] |= (slot ? 0x7u : 0x2u) << (4 * i);
+            }
+    }
+    frag[g] = make_uint4(q[0], q[1], q[2], q[3]);
+}
+
 // One workgroup: 8 waves x 2 column sets x 32 candidates = 512 candidates; each
 // wave keeps its candidates' B operands in registers for the whole scan.
 constexpr int MF_NT = 512;                  // threads per matrix-core workgroup
@@ -385,40 +418,98 @@ constexpr int MF_NB = IG_MF_NB;   // LDS ring depth
 template <int KS>
 constexpr int mf_group() { return IG_MF_GTOK / KS > 0 ? IG_MF_GTOK / KS : 1; }   // tiles per LDS buffer
 
+// Bits [lo, hi) of a 128-bit string, as its 32-bit word j.
+__device__ __forceinline__ uint32_t bit_range_word(int lo, int hi, int j) {
+    const int a = max(lo - 32 * j, 0), b = min(hi - 32 * j, 32);
+    return b <= a ? 0u : (b - a == 32 ? ~0u : ((1u << (b - a)) - 1u)) << a;
+}
+
+// Word j (tokens 8 j .. 8 j + 7) of the candidate's nibbles in the bias slots of a
+// ternary view (the upper half of its last word; slot s is token 31 - s of that
+// half, see tern_bias_slots): they add 1 - np to its product with every record
+// tile row, whose slots hold +1.0 (slot 0) and +6.0 (the others).  np = 0: +1.0 on
+// slot 0.  Else, with v = np - 1 = 36 q + 3 k + i: -i on slot 0, -6.0 (36) on slots
+// 1 .. q, and 3 k as two slots of -k1 / 2 and -k2 / 2 (times 6), k1 the largest of
+// 0, 1, 2, 3, 4, 6, 8 not above k and k2 = k - k1 <= 3.
+__device__ __forceinline__ uint32_t tern_bias_word(uint32_t np, int j) {
+    if (np == 0) return j == 3 ? 0x2u << 28 : 0u;
+    const uint32_t v = np - 1, q = v / 36, r = v % 36, i = r % 3, k = r / 3;
+    const uint32_t k1 = k >= 8 ? 8u : k >= 6 ? 6u : k >= 4 ? 4u : k, k2 = k - k1;
+    // e2m1 codes of k / 2 for k = 0 .. 8 (0, 0.5, 1, 1.5, 2, -, 3, -, 4), negated
+    const uint32_t c1 = k1 ? (k1 <= 4 ? k1 : k1 == 6 ? 5u : 6u) | 8u : 0u, c2 = k2 ? k2 | 8u : 0u;
+    const uint32_t c0 = i == 0 ? 0u : i == 1 ? 0xAu : 0xCu;
+    const int top = 4 * 31;   // bit of slot 0
+    uint32_t w = bit_range_word(top - 4 * (int)q, top, j);   // slots 1 .. q: 0xF (-6.0)
+    const int p0 = top, p1 = top - 4 * ((int)q + 1), p2 = top - 4 * ((int)q + 2);
+    if ((p0 >> 5) == j) w |= c0 << (p0 & 31);
+    if ((p1 >> 5) == j) w |= c1 << (p1 & 31);
+    if ((p2 >> 5) == j) w |= c2 << (p2 & 31);
+    return w;
+}
+
 // Columns: operand rows B [m][KS], expanded bit -> nibble into the B operand in
 // registers (lane % 32 = column, lane / 32 = 32-token half of each word); the A
 // side streams the record tiles.  COUNT = false (coherence, Eq. 3): out[e] = 1
 // when no record contains row e; COUNT = true (support, Eq. 2): out[e] = the
 // number of records that contain it.  FB 32-column sets per wave.
-template <int KS, bool COUNT, int FB>
+// TERN: rows B [m][2 KS] are ternary (P then V; FactorView::ternary) and the tiles
+// hold the records' ternary nibbles and bias slots: with the column's bias nibbles
+// an accumulator ends at 1 - 2 (bits in which the bin indices differ), so at 1.0
+// exactly when the record contains the candidate, at most -1.0 otherwise and 0 on
+// the padding rows of the last tile.
+// The accumulators hold exact small integers, and their bit patterns are compared
+// as integers (no float compares, whose lane masks cost hazard waits).
+template <int KS, bool COUNT, int FB, bool TERN>
 __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const uint64_t *__restrict__ B, uint32_t m,
                                                                          const uint4 *__restrict__ frag,
                                                                          uint32_t ntiles, uint32_t pad,
                                                                          uint32_t *__restrict__ out) {
     constexpr int G = mf_group<KS>();
+    constexpr int RW = TERN ? 2 * KS : KS;             // words per operand row
     __shared__ uint4 lds[ring_lds<KS * 64, G, MF_NB>()];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     v8i_t b[FB][KS];
-    uint32_t e[FB], hits[FB];
+    uint32_t e[FB];
+    // coherence: the least accumulator (one-hot and factored: 0 when a record
+    // contains the column) or the greatest (ternary: 1.0 when one does) so far;
+    // support: the records that contain the column (ternary: that lack it)
+    uint32_t best[FB];
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
         e[f] = blockIdx.x * mf_cols<FB>() + wave * (FB * 32) + f * 32 + col;
         const bool act = e[f] < m;
-        const uint32_t *row = reinterpret_cast<const uint32_t *>(B + (size_t)(act ? e[f] : 0) * KS);
-        hits[f] = 0;
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(B + (size_t)(act ? e[f] : 0) * RW);
+        best[f] = COUNT || TERN ? 0u : ~0u;
+        uint32_t tokens = 0;
 #pragma unroll
         for (int w = 0; w < KS; ++w) {
-            const uint32_t v = row[2 * w + half];   // unconditional: the loads overlap
-            // inactive columns: all tokens, so their result is ignored anyway
-            const uint32_t d = act ? v : 0xffffffffu;
-            b[f][w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
-                            0, 0, 0, 0};
+            if (TERN) {
+                // inactive columns: no tokens, so their result is ignored anyway
+                const uint32_t P = act ? row[2 * w + half] : 0u, V = act ? row[2 * (KS + w) + half] : 0u;
+                tokens += __popc(P);
+                b[f][w] = v8i_t{(int)(spread8(P) | spread8(V) * 4u), (int)(spread8(P >> 8) | spread8(V >> 8) * 4u),
+                                (int)(spread8(P >> 16) | spread8(V >> 16) * 4u),
+                                (int)(spread8(P >> 24) | spread8(V >> 24) * 4u), 0, 0, 0, 0};
+            } else {
+                const uint32_t v = row[2 * w + half];   // unconditional: the loads overlap
+                // inactive columns: all tokens, so their result is ignored anyway
+                const uint32_t d = act ? v : 0xffffffffu;
+                b[f][w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
+                                0, 0, 0, 0};
+            }
+        }
+        if (TERN) {
+            // both halves of the wave hold the same column: |P| over both; the
+            // bias slots lie in the upper half of the last word
+            const uint32_t np = tokens + (uint32_t)__shfl_xor((int)tokens, 32, 64);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[f][KS - 1][j] |= half ? (int)tern_bias_word(np, j) : 0;
         }
     }
-    const uint32_t one = m != 0u;   // 1 (the kernel runs only with columns)
     if (ntiles)
         stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, 0, ntiles, lds, [&](const uint4 *tf) __attribute__((always_inline)) {
             // an accumulator ends at the number of candidate tokens the record lacks
+            // (ternary: at 1 - 2 (bits in which the bin indices differ), or 0 on padding)
             v16f_t acc[FB];
 #pragma unroll
             for (int f = 0; f < FB; ++f) acc[f] = v16f_t{0};
@@ -432,64 +523,101 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
             }
 #pragma unroll
             for (int f = 0; f < FB; ++f) {
-                // exact non-negative integers: +0.0 (all bits zero) exactly when the
-                // record contains the candidate, so the bit patterns are compared as
-                // integers (no float compares, whose lane masks cost hazard waits)
-                if (COUNT) {
-                    // min(bits, one) with `one` not a literal: the compiler would turn
-                    // min(bits, 1) into a compare again
+                if (COUNT && TERN) {
+                    // the records that lack the candidate: the negative values (sign
+                    // bit set); 1.0 and the 0 of a padding row have it clear
                     uint32_t lacking = 0;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) lacking += min(__float_as_uint(acc[f][r]), one);
-                    hits[f] += 16u - lacking;
-                } else {
-                    uint32_t lo = __float_as_uint(acc[f][0]);
+                    for (int r = 0; r < 16; ++r) lacking += __float_as_uint(acc[f][r]) >> 31;
+                    best[f] += lacking;
+                } else if (COUNT) {
+                    // +0.0 (all bits zero) exactly when the record contains the
+                    // candidate; min(bits, one) with `one` not a literal: the compiler
+                    // would turn min(bits, 1) into a compare again
+                    uint32_t lacking = 0;
 #pragma unroll
-                    for (int r = 1; r < 16; ++r) lo = min(lo, __float_as_uint(acc[f][r]));
-                    hits[f] |= (lo - 1u) >> 31;   // 1 when lo == 0
+                    for (int r = 0; r < 16; ++r) lacking += min(__float_as_uint(acc[f][r]), (uint32_t)(m != 0u));
+                    best[f] += 16u - lacking;
+                } else if (TERN) {
+                    // as integers the bits keep the order of 1.0 over 0 and the negatives
+                    int hi = (int)best[f];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) hi = max(hi, (int)__float_as_uint(acc[f][r]));
+                    best[f] = (uint32_t)hi;
+                } else {
+                    uint32_t lo = best[f];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) lo = min(lo, __float_as_uint(acc[f][r]));
+                    best[f] = lo;
                 }
             }
         });
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
         // the two halves of the wave hold different record rows of the same column
-        uint32_t h = hits[f] + __shfl_xor(hits[f], 32, 64);
-        // A row with no tokens (a pattern of one-bin features only, in factored
-        // form) gives 0 against every A row, the padding rows of the last tile too:
-        // they are not records, so they come off its count.  (Coherence needs no
-        // such care: a real record of the tile contains that row as well.)
-        if (COUNT && pad && half == 0 && e[f] < m) {
-            uint64_t any = 0;
-            for (int w = 0; w < KS; ++w) any |= B[(size_t)e[f] * KS + w];
-            if (!any) h -= pad;
+        const uint32_t o = (uint32_t)__shfl_xor((int)best[f], 32, 64);
+        uint32_t h;
+        if (COUNT && TERN) {
+            h = 32u * ntiles - pad - (best[f] + o);   // real records less those that lack it
+        } else if (COUNT) {
+            h = best[f] + o;
+            // One-hot and factored: a row with no tokens (a pattern of one-bin
+            // features only) gives 0 against every A row, the padding rows of the
+            // last tile too: they are not records, so they come off its count.
+            // (Coherence needs no such care: a real record of the tile contains
+            // that row as well.  Ternary padding rows give 0, not 1.0.)
+            if (!TERN && pad && half == 0 && e[f] < m) {
+                uint64_t any = 0;
+                for (int w = 0; w < KS; ++w) any |= B[(size_t)e[f] * RW + w];
+                if (!any) h -= pad;
+            }
+        } else if (TERN) {
+            h = max((int)best[f], (int)o) > 0 ? 1u : 0u;   // covered by a record
+        } else {
+            h = min(best[f], o) == 0u ? 1u : 0u;
         }
         if (half == 0 && e[f] < m) out[e[f]] = COUNT ? h : (h ? 0u : 1u);
     }
 }
 
+// One contraction launch of width V with F column sets per wave (ternary rows at 5
+// words take two sets: three spill).
+template <int V, int F>
+static void launch_cm(bool count, bool ternary, const uint64_t *B, size_t m, const uint4 *frag, uint32_t ntiles,
+                      uint32_t pad, uint32_t *out, hipStream_t s) {
+    constexpr int FT = (V == 5 && F == 3) ? 2 : F;
+    const dim3 grid((unsigned)((m + mf_cols<F>() - 1) / mf_cols<F>()));
+    const dim3 gridt((unsigned)((m + mf_cols<FT>() - 1) / mf_cols<FT>()));
+    if (count && ternary)
+        hipLaunchKernelGGL((k_contain_mfma<V, true, FT, true>), gridt, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles,
+                           pad, out);
+    else if (count)
+        hipLaunchKernelGGL((k_contain_mfma<V, true, F, false>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles,
+                           pad, out);
+    else if (ternary)
+        hipLaunchKernelGGL((k_contain_mfma<V, false, FT, true>), gridt, dim3(MF_NT), 0, s, B, (uint32_t)m, frag,
+                           ntiles, pad, out);
+    else
+        hipLaunchKernelGGL((k_contain_mfma<V, false, F, false>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles,
+                           pad, out);
+}
+
 void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const uint4 *frag, uint32_t n_rec,
-                         uint32_t *out, hipStream_t s, int sets) {
+                         uint32_t *out, hipStream_t s, int sets, bool ternary) {
     if (!m) return;
     IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 rows in one matrix-core launch");
     IG_REQUIRE(KO >= 1 && KO <= 16, IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
     IG_REQUIRE(sets >= 0 && sets <= 3, IG_E_INVAL, "column sets per wave must be 0 (default) to 3");
     const int fb = sets ? std::min(sets, mf_max_sets(KO)) : 0;
     const uint32_t ntiles = (n_rec + 31) / 32, pad = 32 * ntiles - n_rec;
-#define IG_CMF(V, F)                                                                                             \
-    {                                                                                                            \
-        const dim3 grid((unsigned)((m + mf_cols<F>() - 1) / mf_cols<F>()));                                      \
-        if (count)                                                                                               \
-            hipLaunchKernelGGL((k_contain_mfma<V, true, F>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag, ntiles, \
-                               pad, out);                                                                        \
-        else                                                                                                     \
-            hipLaunchKernelGGL((k_contain_mfma<V, false, F>), grid, dim3(MF_NT), 0, s, B, (uint32_t)m, frag,     \
-                               ntiles, pad, out);                                                                \
-    }
 #define IG_CM(V)                                                                                                 \
     case V:                                                                                                      \
-        if (fb == 1 || (fb == 0 && mf_sets<V>() == 1)) IG_CMF(V, 1)                                              \
-        else if (fb == 2 || (fb == 0 && mf_sets<V>() == 2)) IG_CMF(V, (mf_max_sets(V) >= 2 ? 2 : 1))             \
-        else IG_CMF(V, (mf_max_sets(V) >= 3 ? 3 : 1))                                                            \
+        if (fb == 1 || (fb == 0 && mf_sets<V>() == 1))                                                           \
+            launch_cm<V, 1>(count, ternary, B, m, frag, ntiles, pad, out, s);                                    \
+        else if (fb == 2 || (fb == 0 && mf_sets<V>() == 2))                                                      \
+            launch_cm<V, (mf_max_sets(V) >= 2 ? 2 : 1)>(count, ternary, B, m, frag, ntiles, pad, out, s);        \
+        else                                                                                                     \
+            launch_cm<V, (mf_max_sets(V) >= 3 ? 3 : 1)>(count, ternary, B, m, frag, ntiles, pad, out, s);        \
         break;
     switch (KO) {
         IG_CM(1) IG_CM(2) IG_CM(3) IG_CM(4) IG_CM(5) IG_CM(6) IG_CM(7) IG_CM(8)
@@ -497,7 +625,6 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
         default: break;
     }
 #undef IG_CM
-#undef IG_CMF
     IG_HIP(hipGetLastError());
 }
 
@@ -890,6 +1017,17 @@ void launch_mfma_records_signed(const uint64_t *FR, uint32_t n, const FactorView
     IG_REQUIRE(fv.tok && fv.fbit, IG_E_DEVICE, "signed record operands without a token table");
     hipLaunchKernelGGL(k_mfma_records_signed, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, FR, n, KO,
                        ntiles, fv, frag);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_mfma_records_ternary(const uint64_t *FR, uint32_t n, uint32_t KO, uint32_t T, uint4 *frag,
+                                 hipStream_t s) {
+    const uint32_t ntiles = mfma_record_tiles(n), nslots = tern_bias_slots(T);
+    IG_REQUIRE(KO >= 1 && T + nslots <= 64 * KO && nslots <= 32, IG_E_INVAL, "ternary tokens overlap the bias slots");
+    const size_t total = (size_t)ntiles * KO * 64;
+    if (!total) return;
+    hipLaunchKernelGGL(k_mfma_records_ternary, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, FR, n, KO,
+                       ntiles, nslots, frag);
     IG_HIP(hipGetLastError());
 }
 

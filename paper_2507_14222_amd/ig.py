@@ -92,7 +92,8 @@ class Stats(C.Structure):
 class ModelInfo(C.Structure):
     _fields_ = [("K", C.c_uint32), ("L", C.c_uint32), ("d", C.c_uint32), ("flags", C.c_uint32),
                 ("mfma_tokens", C.c_uint32), ("mfma_words", C.c_uint32),
-                ("n_patterns", C.c_uint64 * 2), ("max_weight", C.c_int64 * 2)]
+                ("n_patterns", C.c_uint64 * 2), ("max_weight", C.c_int64 * 2),
+                ("fit_tokens", C.c_uint32), ("fit_words", C.c_uint32)]
 
 
 class Moments(C.Structure):
@@ -264,8 +265,11 @@ def _np_u16(a) -> np.ndarray:
 def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tune=None,
           kernels: str = "auto", allocator=None) -> FitOpts:
     """Fit options; `tune` is a list of dicts with the fields of ig_tune_entry;
-    kernels = "auto" | "mfma" | "valu" | "mfma_onehot" selects the coherence/support
-    kernels ("mfma_onehot": matrix cores on the one-hot words, no factored tokens);
+    kernels = "auto" | "mfma" | "valu" | "mfma_onehot" | "mfma_presence" |
+    "mfma_ternary" selects the coherence/support kernels ("mfma_onehot": matrix cores
+    on the one-hot words, no factored tokens; "mfma_presence": factored tokens with
+    presence tokens; "mfma_ternary": the ternary bit tokens whenever the fit has
+    them; "mfma" and "auto" take whichever of the two needs fewer words);
     allocator = None (the library's arena), "torch" (torch's caching allocator) or an
     Allocator."""
     o = FitOpts()
@@ -273,7 +277,8 @@ def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tu
         a = torch_allocator() if allocator == "torch" else allocator
         o.alloc = C.pointer(a)
         o._alloc = a
-    o.coherence_mfma = {"auto": 0, "mfma": 1, "valu": 2, "mfma_onehot": 3}[kernels]
+    o.coherence_mfma = {"auto": 0, "mfma": 1, "valu": 2, "mfma_onehot": 3, "mfma_presence": 4,
+                        "mfma_ternary": 5}[kernels]
     o.mem_budget_bytes = int(mem_budget_bytes)
     o.filter_cpl = int(filter_cpl)
     o.score_fpl = int(score_fpl)

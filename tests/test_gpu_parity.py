@@ -448,6 +448,9 @@ MFMA_RUNS += [(c, k) for c in PADDED_CASES for k in ("mfma", "mfma_onehot")]
 # one-hot storage of 20 (K = 17, padded), 24 and 28 words, factored into 6 to 9 words
 WIDE_STORAGE_CASES = [(35, 80, 70, 14, 16, 0.5), (33, 80, 80, 16, 19, 0.5), (34, 80, 80, 20, 23, 0.5)]
 MFMA_RUNS += [(c, "mfma") for c in WIDE_STORAGE_CASES]
+# factored tokens with presence tokens, and the ternary bit tokens, each forced
+MFMA_RUNS += [(c, k) for c in MFMA_CASES + WIDE_CASES + PADDED_CASES + WIDE_STORAGE_CASES
+              for k in ("mfma_presence", "mfma_ternary")]
 
 
 @pytest.mark.parametrize("case,kernels", MFMA_RUNS, ids=[f"s{c[0]}-d{c[2]}-{k}" for c, k in MFMA_RUNS])
@@ -477,18 +480,19 @@ def test_matrix_core_coherence_matches_oracle(case, kernels):
     assert np.array_equal(A[~bad], oA) and np.array_equal(N[~bad], oN)
 
 
-def test_factored_patterns_without_tokens():
+@pytest.mark.parametrize("kernels", ["mfma", "mfma_presence", "mfma_ternary"])
+def test_factored_patterns_without_tokens(kernels):
     """A pattern of one-bin features only has no factored tokens: its support must
     not count the padding rows of the last record tile, and an invalid flow must
     keep its (-1, -1) although such a pattern meets every operand with zero."""
-    say("token-free factored patterns")
+    say("token-free factored patterns", kernels)
     rng = np.random.default_rng(11)
     nb = np.array([1, 70, 2], np.uint16)   # 73 one-hot tokens in 2 words; factored, 1 word
     n = 40                                  # the last record tile holds 8 of 32 rows
     codes = np.stack([np.zeros(n, np.int64), rng.integers(0, 70, n), rng.integers(0, 2, n)], 1).astype(np.uint16)
     labels = np.zeros(n, np.uint8)          # one class: every candidate is coherent
     om = oracle.fit(codes, labels, nb)
-    m = ig.fit(codes, labels, nb, kernels="mfma")
+    m = ig.fit(codes, labels, nb, kernels=kernels)
     info = m.info()
     assert info.flags & ig.IG_MODEL_FACTORED and m.score_on_matrix_cores
     assert_same_model(m, om, om.K)
@@ -498,6 +502,52 @@ def test_factored_patterns_without_tokens():
     assert np.all(A[bad] == -1) and np.all(N[bad] == -1)
     oA, oN = oracle.score(om, flows[~bad], nb)
     assert np.array_equal(A[~bad], oA) and np.array_equal(N[~bad], oN)
+
+
+def _bias_span_problem():
+    """Class 0 holds a zero row and, for every t = 0 .. T (T = 140 bit tokens), a row
+    that agrees with it on features worth exactly t bit tokens and differs on all
+    others, so the candidates of the ternary contraction take every size |P| from 0
+    to T (every quotient and remainder of the bias slots' 1 - |P|).  Class 1: random
+    rows and near copies of the zero row, which cover some of the candidates."""
+    rng = np.random.default_rng(5)
+    nb = np.array([2] * 10 + [4] * 10 + [16] * 10 + [128] * 10, np.uint16)
+    bits = np.array([1] * 10 + [2] * 10 + [4] * 10 + [7] * 10)
+    T, d = int(bits.sum()), len(nb)
+    order = np.argsort(-bits, kind="stable")
+    rows = [np.zeros(d, np.int64)]
+    for t in range(T + 1):
+        keep, left = np.zeros(d, bool), t
+        for f in order:
+            if bits[f] <= left:
+                keep[f], left = True, left - bits[f]
+        assert left == 0
+        r = rng.integers(1, nb.astype(np.int64))
+        r[keep] = 0
+        rows.append(r)
+    near = np.zeros((20, d), np.int64)
+    for i in range(20):
+        fl = rng.choice(d, size=1 + i % 3, replace=False)
+        near[i, fl] = rng.integers(1, nb[fl].astype(np.int64))
+    codes = np.concatenate([np.array(rows), rng.integers(0, nb.astype(np.int64), size=(20, d)), near])
+    labels = np.concatenate([np.zeros(len(rows)), np.ones(40)]).astype(np.uint8)
+    return codes.astype(np.uint16), labels, nb, T
+
+
+@pytest.mark.parametrize("kernels", ["mfma", "mfma_presence", "mfma_ternary"])
+def test_ternary_bias_spans_every_candidate_size(kernels):
+    codes, labels, nb, T = _bias_span_problem()
+    say("ternary bias span", kernels, T)
+    om = oracle.fit(codes, labels, nb)
+    m = ig.fit(codes, labels, nb, kernels=kernels)
+    info = m.info()
+    if kernels == "mfma_ternary":
+        slots = 3 + (T - 1) // 36
+        assert info.fit_tokens == T and info.fit_words == (T + slots + 63) // 64
+    assert_same_model(m, om, om.K)
+    st = m.stats()
+    assert list(st.coherent) == om.stats["coherent"] and list(st.distinct) == om.stats["distinct"]
+    assert 0 < om.stats["coherent"][0] < om.stats["distinct"][0]   # some candidates are covered
 
 
 def _boundary_codes(rng, nb, n):
@@ -518,11 +568,12 @@ def _boundary_codes(rng, nb, n):
     return np.stack(cols, 1).astype(np.uint16)
 
 
+@pytest.mark.parametrize("kernels", ["mfma", "mfma_presence", "mfma_ternary"])
 @pytest.mark.parametrize("nb,n", [
     ([2, 3, 9, 16, 17, 33, 65, 513], 90),   # 1 to 4 bit tokens with one presence token, 5 to 10 with two
     ([1024], 120),                           # bin 1023: 10 bits set, presence parts 6 + 4
 ])
-def test_factored_bin_boundaries(nb, n):
+def test_factored_bin_boundaries(nb, n, kernels):
     """Features whose bin counts sit at the factored encoding's boundaries, with
     bins of every popcount up to the feature's bit count: model and scores on the
     matrix cores against the oracle, including flows one bit away from a pattern."""
@@ -532,7 +583,7 @@ def test_factored_bin_boundaries(nb, n):
     codes = _boundary_codes(rng, nb, n)
     labels = (rng.random(n) < 0.5).astype(np.uint8)
     om = oracle.fit(codes, labels, nb)
-    m = ig.fit(codes, labels, nb, kernels="mfma")
+    m = ig.fit(codes, labels, nb, kernels=kernels)
     info = m.info()
     assert info.flags & ig.IG_MODEL_FACTORED and m.score_on_matrix_cores
     assert_same_model(m, om, om.K)
