@@ -57,10 +57,11 @@ struct DevModel {
     uint32_t tern_tokens = 0;              // tokens of the ternary form
     uint32_t fit_tokens = 0, fit_words = 0;    // operand rows of the fit's contractions
     bool score_factored = false;           // frag holds factored operand rows
+    bool score_ternary = false;            // ... of the ternary view (tv)
     bool score_spare = false;              // frag carries the +1 at the spare last token
+    int score_pref = -1;                   // scoring view: -1 automatic, 0 presence tokens, 1 ternary
     ig_stats stats{};
 
-    uint32_t KO() const { return fv.KF ? fv.KF : KS; }
 
     void release(void *p) const noexcept { device_free(p, device, has_user ? &user : nullptr); }
 
@@ -360,6 +361,16 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     }
 }
 
+// The view of the scoring operands: that of the fit's contractions when they used
+// factored tokens (ternary or with presence tokens), else the ternary bit tokens
+// when they take fewer words than the presence tokens, else the presence tokens
+// (fv.KF = 0: the one-hot words).  Ternary views of more than 8 words give way.
+static const FactorView &score_view(const DevModel &m) {
+    const bool tern = m.tv.KF && m.tv.KF <= 8 &&
+                      (m.score_pref == 1 || (m.score_pref < 0 && (!m.fv.KF || m.tv.KF < m.fv.KF)));
+    return tern ? m.tv : m.fv;
+}
+
 static void check_nbins(const uint16_t *h_nbins, uint32_t d, uint32_t &L, uint32_t &K) {
     IG_REQUIRE(d >= 1 && d <= 4096, IG_E_INVAL, "d must be in 1..4096");
     IG_REQUIRE(h_nbins != nullptr, IG_E_INVAL, "nbins is NULL");
@@ -601,7 +612,8 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         IG_HIP(er);
         m.stats.kernel_ms[1] += tk;
         // the scoring operands use the model's own view: keep the rows when it is this one
-        if (keep && !mfma_view.ternary && mfma_view.KF == m.fv.KF && mfma_view.KF) {
+        const FactorView &sv = score_view(m);
+        if (keep && mfma_view.KF && mfma_view.KF == sv.KF && mfma_view.ternary == sv.ternary) {
             keep->rows[c] = std::move(B);
             keep->valid[c] = true;
         }
@@ -645,8 +657,8 @@ static Scratch<uint32_t> token_costs(const DevModel &m, const ClassRows *cls, hi
 // Scoring operands of class c with its tiles grouped by bucket token (every tile
 // holds patterns of one bucket; a bucket's last tile is padded with empty rows of
 // weight 0): m.frag[c], m.ftiles[c] and m.btile[c].
-static void bucketed_operands(DevModel &m, int c, const uint64_t *rows, uint32_t KO, const uint32_t *cost,
-                              hipStream_t s) {
+static void bucketed_operands(DevModel &m, int c, const uint64_t *rows, uint32_t KO, bool spare, bool tern,
+                              const uint32_t *cost, hipStream_t s) {
     const size_t np = m.np[c];
     const uint32_t L = m.L;
     Scratch<uint64_t> key(np, s), key2(np, s);
@@ -685,14 +697,17 @@ static void bucketed_operands(DevModel &m, int c, const uint64_t *rows, uint32_t
     IG_HIP(hipMemcpyAsync(m.bperm[c], P, np * 4, hipMemcpyDeviceToDevice, s));
     m.ftiles[c] = ntiles;
     m.frag[c] = dev_alloc<uint4>((size_t)std::max<uint32_t>(ntiles, 1) * (KO + 1) * 64);
-    launch_mfma_patterns(rows, m.S[c], (uint32_t)np, KO, score_spare(m), m.frag[c], s, P, m.btile[c], m.brow[c], L,
+    launch_mfma_patterns(rows, m.S[c], (uint32_t)np, KO, spare, tern, m.frag[c], s, P, m.btile[c], m.brow[c], L,
                          ntiles);
     IG_HIP(hipStreamSynchronize(s));   // the host tables above are freed on return
 }
 
 static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr, const ClassRows *cls) {
-    const uint32_t KO = m.KO();
+    const FactorView &sv = score_view(m);
+    const bool tern = sv.ternary != 0;
+    const uint32_t KO = sv.KF ? sv.KF : m.KS, RW = tern ? 2 * KO : KO;
     if (KO > 8 || m.maxS[0] >= (1ll << 28) || m.maxS[1] >= (1ll << 28)) return;
+    const bool spare = !tern && score_spare(m);
     // fits from codes and imported models group their tiles by token for pruned scoring
     const bool bucketed = m.d > 0 && m.L <= 4096;
     Scratch<uint32_t> cost;
@@ -703,12 +718,12 @@ static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr, co
         if (pr && pr->valid[c]) {
             rows = pr->rows[c].get();
         } else {
-            own.reset(std::max<uint64_t>(m.np[c], 1) * KO, s);
-            launch_operand_rows(nullptr, 0, nullptr, m.W[c], m.KS, m.np[c], m.fv, false, own.get(), s);
+            own.reset(std::max<uint64_t>(m.np[c], 1) * RW, s);
+            launch_operand_rows(nullptr, 0, nullptr, m.W[c], m.KS, m.np[c], sv, false, own.get(), s);
             rows = own.get();
         }
         if (bucketed && m.np[c]) {
-            bucketed_operands(m, c, rows, KO, cost.get(), s);
+            bucketed_operands(m, c, rows, KO, spare, tern, cost.get(), s);
             continue;
         }
         if (bucketed) {   // an empty class: no tiles or rows in any bucket
@@ -721,10 +736,11 @@ static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr, co
         const uint64_t ntiles = (m.np[c] + 31) / 32;
         m.ftiles[c] = (uint32_t)ntiles;
         m.frag[c] = dev_alloc<uint4>(std::max<uint64_t>(ntiles, 1) * (KO + 1) * 64);
-        launch_mfma_patterns(rows, m.S[c], (uint32_t)m.np[c], KO, score_spare(m), m.frag[c], s);
+        launch_mfma_patterns(rows, m.S[c], (uint32_t)m.np[c], KO, spare, tern, m.frag[c], s);
     }
-    m.score_factored = m.fv.KF > 0;
-    m.score_spare = score_spare(m);
+    m.score_factored = sv.KF > 0;
+    m.score_ternary = tern;
+    m.score_spare = spare;
     IG_HIP(hipStreamSynchronize(s));
 }
 
@@ -924,6 +940,8 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     if (use_mfma) {
         mfma_tuning(opts, mf.KO, fit_pairs, tu);
         note_fit_operands(m, mf);
+        // scoring follows the fit's factored view
+        if (mf.view.KF) m.score_pref = mf.view.ternary ? 1 : 0;
     }
     Scratch<uint64_t> surv_rows[2];   // operand rows of the coherent candidates (one-chunk fits)
     uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
@@ -1215,6 +1233,7 @@ DevModel *import_patterns(const uint16_t *const h_codes[2], const uint32_t *cons
     IG_HIP(hipMemcpyAsync(m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
     IG_HIP(hipMemcpyAsync(m->nbins, h_nbins, d * 2, hipMemcpyHostToDevice, s));
     set_factor_table(*m, h_nbins, d, s);
+    set_factor_table(*m, h_nbins, d, s, true);
     for (int c = 0; c < 2; ++c) {
         const uint64_t cnt = count[c];
         IG_REQUIRE(cnt < (1ull << 31), IG_E_UNSUPPORTED, "more than 2^31 patterns in one class");
@@ -1670,9 +1689,11 @@ static ig::ScoreModel score_model(const ig::DevModel &M) {
     }
     sm.nbucket = (M.btile[0] && M.btile[1]) ? M.L : 0u;
     sm.KS = M.KS;
-    sm.KO = M.score_factored ? M.fv.KF : M.KS;
-    if (M.score_factored) sm.fv = M.fv;
+    const ig::FactorView &sv = M.score_ternary ? M.tv : M.fv;
+    sm.KO = M.score_factored ? sv.KF : M.KS;
+    if (M.score_factored) sm.fv = sv;
     sm.spare = M.score_spare;
+    sm.tslots = M.score_ternary ? ig::tern_bias_slots(M.tern_tokens) : 0u;
     return sm;
 }
 
@@ -1839,8 +1860,8 @@ ig_status ig_model_get_info(const ig_model *m, ig_model_info *info) {
         info->flags = ((M.frag[0] && M.frag[1]) ? IG_MODEL_SCORE_MFMA : 0u) |
                       (M.score_factored ? IG_MODEL_FACTORED : 0u) |
                       ((M.frag[0] && M.frag[1] && M.btile[0] && M.btile[1]) ? IG_MODEL_BUCKETED : 0u);
-        info->mfma_tokens = M.score_factored ? M.fac_tokens : M.L;
-        info->mfma_words = M.score_factored ? M.fv.KF : M.K;
+        info->mfma_tokens = M.score_ternary ? M.tern_tokens : M.score_factored ? M.fac_tokens : M.L;
+        info->mfma_words = M.score_ternary ? M.tv.KF : M.score_factored ? M.fv.KF : M.K;
         info->fit_tokens = M.fit_tokens;
         info->fit_words = M.fit_words;
         for (int c = 0; c < 2; ++c) {

@@ -211,6 +211,7 @@ struct ScoreModel {
     uint32_t KO;                // operand words of frag (factored or one-hot)
     FactorView fv;              // the factoring of frag (fv.KF = 0: one-hot)
     bool spare;                 // frag holds +1.0 at the unused last token (see k_mfma_patterns)
+    uint32_t tslots;            // fv.ternary: bias slots of the view (tern_bias_slots)
     const uint32_t *btile[2];   // [nbucket + 1]: first tile of each token bucket (null: not bucketed)
     uint32_t nbucket;           // buckets = tokens L
 };
@@ -242,13 +243,15 @@ void launch_prune_lists(const uint16_t *codes, uint32_t n, uint32_t d, const uin
 // patterns; flows given as words need one-hot operands (fv.KF = 0).
 // spare: the last token of the last word is used by no row; it then carries the
 // +1 that starts each containment count (flows hold 1 there), so the accumulators
-// can start at 0.
+// can start at 0.  tern: W holds ternary rows [m][2 KS] (P then V) of a ternary
+// view with bias slots (tern_bias_slots); the tiles take the candidate side of the
+// ternary contraction and the flows the record side (ScoreModel::tslots).
 // With buckets (bt, brow: [L + 1] each, ntiles = bt[L]), the tiles [bt[u], bt[u + 1])
 // hold positions [brow[u], brow[u + 1]) of the order perm, row perm[e] at position
 // e (perm may be null: the identity); without, ntiles is ceil(m / 32) and tile t
 // holds rows 32 t ...
-void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, bool spare, uint4 *frag,
-                          hipStream_t s, const uint32_t *perm = nullptr, const uint32_t *bt = nullptr,
+void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, bool spare, bool tern,
+                          uint4 *frag, hipStream_t s, const uint32_t *perm = nullptr, const uint32_t *bt = nullptr,
                           const uint32_t *brow = nullptr, uint32_t L = 0, uint32_t ntiles = 0);
 void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K,
                        uint32_t n_flows, uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out,

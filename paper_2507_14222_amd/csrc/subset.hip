@@ -472,7 +472,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
     uint32_t e[FB];
     // coherence: the least accumulator (one-hot and factored: 0 when a record
     // contains the column) or the greatest (ternary: 1.0 when one does) so far;
-    // support: the records that contain the column (ternary: that lack it)
+    // support: the records that contain the column (ternary: 8 x those that lack it)
     uint32_t best[FB];
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
@@ -525,11 +525,15 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
             for (int f = 0; f < FB; ++f) {
                 if (COUNT && TERN) {
                     // the records that lack the candidate: the negative values (sign
-                    // bit set); 1.0 and the 0 of a padding row have it clear
-                    uint32_t lacking = 0;
+                    // bit set); 1.0 and the 0 of a padding row have it clear.  A byte
+                    // permute copies the signs of two accumulators into two bytes
+                    // (selectors 9 and 11 repeat bit 31 of its second and first
+                    // source), and the population count adds 8 per sign.
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) lacking += __float_as_uint(acc[f][r]) >> 31;
-                    best[f] += lacking;
+                    for (int r = 0; r < 16; r += 2)
+                        best[f] += __builtin_popcount(__builtin_amdgcn_perm(__float_as_uint(acc[f][r]),
+                                                                            __float_as_uint(acc[f][r + 1]),
+                                                                            0x0c0c0b09u));
                 } else if (COUNT) {
                     // +0.0 (all bits zero) exactly when the record contains the
                     // candidate; min(bits, one) with `one` not a literal: the compiler
@@ -558,7 +562,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
         const uint32_t o = (uint32_t)__shfl_xor((int)best[f], 32, 64);
         uint32_t h;
         if (COUNT && TERN) {
-            h = 32u * ntiles - pad - (best[f] + o);   // real records less those that lack it
+            h = 32u * ntiles - pad - (best[f] + o) / 8u;   // real records less those that lack it
         } else if (COUNT) {
             h = best[f] + o;
             // One-hot and factored: a row with no tokens (a pattern of one-bin
@@ -606,6 +610,8 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
                          uint32_t *out, hipStream_t s, int sets, bool ternary) {
     if (!m) return;
     IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 rows in one matrix-core launch");
+    // the ternary support counts 8 per record lacking a candidate in 32 bits
+    IG_REQUIRE(n_rec < (1u << 28), IG_E_UNSUPPORTED, "more than 2^28 records in one matrix-core launch");
     IG_REQUIRE(KO >= 1 && KO <= 16, IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
     IG_REQUIRE(sets >= 0 && sets <= 3, IG_E_INVAL, "column sets per wave must be 0 (default) to 3");
     const int fb = sets ? std::min(sets, mf_max_sets(KO)) : 0;
@@ -641,7 +647,11 @@ __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return 
 //  words w < KS, frag[(tile * (KS + 1) + w) * 64 + lane]: the nibbles of half
 //    (lane/32) of word w of row tile*32 + lane%32, as -1.0 (e2m1 0xA) per token
 //    (empty past m), so that an accumulator started at 1.0 ends at 1 - V: 1
-//    exactly when the pattern lies inside, at most 0 otherwise;
+//    exactly when the pattern lies inside, at most 0 otherwise.  Ternary rows
+//    (tern; W is [m][2 KS], P then V) take the candidate side of the fit's
+//    ternary contraction instead, bias slots included, against flows on the
+//    record side: an accumulator started at 0 ends at 1 exactly when the pattern
+//    lies inside, at most -1 otherwise, and at 0 on the rows past m;
 //  slice KS, frag[(tile * (KS + 1) + KS) * 64 + lane]: the A operand of the
 //    weighting product (v_mfma_i32_32x32x32_i8): for lane%32 = c < 4 and half h,
 //    byte j holds 7-bit chunk c of the weight of the row in accumulator j of half h
@@ -655,7 +665,8 @@ __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return 
 // patterns of one bucket only.  Without, tile t holds rows [32 t, 32 t + 32).
 __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restrict__ W, const int64_t *__restrict__ S,
                                                       uint32_t m, uint32_t KS, uint32_t ntiles, bool spare,
-                                                      const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bt,
+                                                      bool tern, const uint32_t *__restrict__ perm,
+                                                      const uint32_t *__restrict__ bt,
                                                       const uint32_t *__restrict__ brow, uint32_t L,
                                                       uint4 *__restrict__ frag) {
     const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -676,17 +687,44 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
     }
     const uint32_t row = in ? (perm ? perm[pos] : pos) : 0u;
     uint4 *dst = frag + (size_t)tile * (KS + 1) * 64;
-    uint64_t wv[8];
+    const uint32_t RW = tern ? 2 * KS : KS;   // words per row
+    uint64_t wv[16];
 #pragma unroll
-    for (uint32_t w = 0; w < 8; ++w) wv[w] = in && w < KS ? W[(size_t)row * KS + w] : 0ull;
+    for (uint32_t w = 0; w < 16; ++w) wv[w] = in && w < RW ? W[(size_t)row * RW + w] : 0ull;
+    uint4 v[8];
+    uint32_t np = 0;   // ternary: |P| of the row
 #pragma unroll
     for (uint32_t w = 0; w < 8; ++w) {
         if (w >= KS) break;
         const uint32_t d = (uint32_t)(wv[w] >> (32 * half));
-        uint4 v = make_uint4(spread8(d) * 5u, spread8(d >> 8) * 5u, spread8(d >> 16) * 5u, spread8(d >> 24) * 5u);
-        // +1.0 (0x2) at the spare token: bit 63 of the last word = top nibble of the upper half
-        if (spare && w == KS - 1 && half) v.w = (v.w & 0x0fffffffu) | 0x20000000u;
-        dst[w * 64 + lane] = v;
+        if (tern) {
+            // the candidate side of the ternary contraction (k_contain_mfma): +1.0
+            // on P AND NOT V, -1.0 on P AND V
+            const uint32_t V = (uint32_t)(wv[(KS + w) & 15] >> (32 * half));
+            np += __popc(d);
+            v[w] = make_uint4(spread8(d) | spread8(V) * 4u, spread8(d >> 8) | spread8(V >> 8) * 4u,
+                              spread8(d >> 16) | spread8(V >> 16) * 4u, spread8(d >> 24) | spread8(V >> 24) * 4u);
+        } else {
+            v[w] = make_uint4(spread8(d) * 5u, spread8(d >> 8) * 5u, spread8(d >> 16) * 5u, spread8(d >> 24) * 5u);
+            // +1.0 (0x2) at the spare token: bit 63 of the last word = top nibble of the upper half
+            if (spare && w == KS - 1 && half) v[w].w = (v[w].w & 0x0fffffffu) | 0x20000000u;
+        }
+    }
+    if (tern) {
+        // the row's bias nibbles (1 - |P|; rows past m have none): both halves hold the row
+        np += (uint32_t)__shfl_xor((int)np, 32, 64);
+        if (in && half) {
+            uint4 &lw = v[(KS - 1) & 7];
+            lw.x |= tern_bias_word(np, 0);
+            lw.y |= tern_bias_word(np, 1);
+            lw.z |= tern_bias_word(np, 2);
+            lw.w |= tern_bias_word(np, 3);
+        }
+    }
+#pragma unroll
+    for (uint32_t w = 0; w < 8; ++w) {
+        if (w >= KS) break;
+        dst[w * 64 + lane] = v[w];
     }
     const int64_t sv = in ? S[row] : 0;
     const uint32_t s_lo = (uint32_t)sv, s_hi = (uint32_t)((uint64_t)sv >> 32);
@@ -737,13 +775,19 @@ struct ScoreMfmaArgs {
     int64_t *out;
     uint32_t n_flows, d, K;
     FactorView fv;              // fv.KF > 0: flows (codes) are factored like the patterns
+    uint64_t tbias[2];          // ternary: the bias slots' constants, upper half of the last word
 };
 
 // B operand of flow t for one 32-column set of a wave (lane half `half` supplies
 // the 32-token halves): the complement of its one-hot words, or the signed side
 // of its factored tokens.  Returns whether the flow is active with every code in
 // range; otherwise its operand is the empty set, inside which no pattern lies.
-template <int KS, bool SPARE>
+// Forms of the scoring contraction: one-hot or factored tokens with the count's
+// starting +1 in the accumulator (SF_PLAIN) or on the spare token (SF_SPARE), or
+// ternary bit tokens with bias slots (SF_TERN).
+enum { SF_PLAIN = 0, SF_SPARE = 1, SF_TERN = 2 };
+
+template <int KS, int SF>
 __device__ __forceinline__ bool flow_operand(const ScoreMfmaArgs &a, uint32_t t, bool act, int half,
                                              v8i_t (&b)[KS]) {
     uint64_t wd[KS];
@@ -752,14 +796,16 @@ __device__ __forceinline__ bool flow_operand(const ScoreMfmaArgs &a, uint32_t t,
         // factored tokens: the flow is the signed side (FactorView::tok).  Its
         // bit tokens come from its factored row (bin bit 0: +1.0, 1: -1.0), its
         // presence tokens from the popcounts of its bin indices; an inactive or
-        // invalid flow is +1.0 on every token (the empty set: no pattern lies inside)
+        // invalid flow is +1.0 on every token (the empty set: no pattern lies inside).
+        // Ternary: bit tokens only, the bias slots' constants of a record tile row,
+        // and an inactive or invalid flow 0 everywhere (every product 0)
         const uint16_t *row = a.codes + (size_t)(act ? t : 0u) * a.d;
         if (act)
             for (uint32_t ft = 0; ft < a.d; ++ft) ok &= row[ft] < a.nbins[ft];
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             uint64_t v = 0;   // the flow's factored word k (pattern side: bits and presence)
-            uint64_t lo = 0x2222222222222222ull, hi = 0x2222222222222222ull;
+            uint64_t lo = SF == SF_TERN ? 0ull : 0x2222222222222222ull, hi = lo;
             if (ok) {
                 for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
                     const FacFeature ft = a.fv.feat[f];
@@ -772,7 +818,7 @@ __device__ __forceinline__ bool flow_operand(const ScoreMfmaArgs &a, uint32_t t,
                      (uint64_t)(spread8(zeros >> 8) | spread8(ones >> 8) * 5u) << 32;
                 hi = (uint64_t)(spread8(zeros >> 16) | spread8(ones >> 16) * 5u) |
                      (uint64_t)(spread8(zeros >> 24) | spread8(ones >> 24) * 5u) << 32;
-                for (uint32_t f = a.fv.fbeg[k]; f < a.fv.fend[k]; ++f) {
+                for (uint32_t f = a.fv.fbeg[k]; SF != SF_TERN && f < a.fv.fend[k]; ++f) {
                     const uint32_t pt = a.fv.ptok[f];
                     if (pt == ~0u) continue;
                     const uint32_t pc = __popc(row[f]);
@@ -787,7 +833,11 @@ __device__ __forceinline__ bool flow_operand(const ScoreMfmaArgs &a, uint32_t t,
                 }
             }
             // the spare token is +1.0 in every flow (it carries the count's starting +1)
-            if (SPARE && k == KS - 1 && half) hi = (hi & 0x0fffffffffffffffull) | 0x2000000000000000ull;
+            if (SF == SF_SPARE && k == KS - 1 && half) hi = (hi & 0x0fffffffffffffffull) | 0x2000000000000000ull;
+            if (SF == SF_TERN && ok && k == KS - 1 && half) {
+                lo |= a.tbias[0];
+                hi |= a.tbias[1];
+            }
             b[k] = v8i_t{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
                          (int)(uint32_t)(hi >> 32), 0, 0, 0, 0};
         }
@@ -816,7 +866,7 @@ __device__ __forceinline__ bool flow_operand(const ScoreMfmaArgs &a, uint32_t t,
         // NOT t; an inactive or invalid flow is the empty set, which contains no pattern.
         // The spare token is 1 in every flow (it carries the count's starting +1).
         uint64_t nt = ok ? ~wd[k] : ~0ull;
-        if (SPARE && k == KS - 1) nt |= 1ull << 63;
+        if (SF == SF_SPARE && k == KS - 1) nt |= 1ull << 63;
         const uint32_t dwd = (uint32_t)(nt >> (32 * half));
         b[k] = v8i_t{(int)spread8(dwd), (int)spread8(dwd >> 8), (int)spread8(dwd >> 16), (int)spread8(dwd >> 24),
                      0, 0, 0, 0};
@@ -827,15 +877,15 @@ __device__ __forceinline__ bool flow_operand(const ScoreMfmaArgs &a, uint32_t t,
 // One 32-pattern tile against the wave's column sets: the containment counts on
 // the fp4 matrix cores, then the weighting product adds the weight chunks of the
 // patterns inside each flow to C.
-template <int KS, bool SPARE>
+template <int KS, int SF>
 __device__ __forceinline__ void score_tile(const uint4 *tile, int lane, const v8i_t (&b)[MF_FB][KS],
                                            v16i_t (&C)[MF_FB]) {
-    // the count starts at +1: from the spare token, or here
+    // the count starts at +1: from the spare token or the bias slots, or here
     v16f_t acc[MF_FB];
 #pragma unroll
     for (int f = 0; f < MF_FB; ++f)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[f][r] = SPARE ? 0.0f : 1.0f;
+        for (int r = 0; r < 16; ++r) acc[f][r] = SF == SF_PLAIN ? 1.0f : 0.0f;
 #pragma unroll
     for (int w = 0; w < KS; ++w) {
         const uint4 a4 = tile[w * 64 + lane];
@@ -884,7 +934,7 @@ __device__ __forceinline__ void score_flush(int64_t *out, int cls, int half, con
 // to one XCD and share its L2.  The ranges split the tiles of both classes, taken
 // one after the other, into equal parts; a range that holds tiles of both classes
 // scans them as two segments and adds each class's sums to its own column.
-template <int KS, bool SPARE>
+template <int KS, int SF>
 __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     constexpr int G = sc_group<KS>();
     constexpr int TW = (KS + 1) * 64;
@@ -903,7 +953,7 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     for (int f = 0; f < MF_FB; ++f) {
         const uint32_t t = fb * SC_COLS + wave * (MF_FB * 32) + f * 32 + col;
         tf[f] = t;
-        valid[f] = flow_operand<KS, SPARE>(a, t, t < a.n_flows, half, b[f]);
+        valid[f] = flow_operand<KS, SF>(a, t, t < a.n_flows, half, b[f]);
     }
     // C[f]: running weighting products; row c < 4 of column `col` (lane half 0,
     // accumulators 0..3) sums chunk c of the weights of the patterns inside the flow
@@ -918,7 +968,7 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
 #pragma unroll
         for (int f = 0; f < MF_FB; ++f) C[f] = v16i_t{0};
         stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], s0 - lo, s1 - lo, lds, [&](const uint4 *tile) __attribute__((always_inline)) {
-            score_tile<KS, SPARE>(tile, lane, b, C);
+            score_tile<KS, SF>(tile, lane, b, C);
         });
         score_flush(a.out, cls, half, C, tf, valid);
     }
@@ -941,7 +991,7 @@ struct PruneArgs {
     uint32_t L, rt;
 };
 
-template <int KS, bool SPARE>
+template <int KS, int SF>
 __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma_pruned(ScoreMfmaArgs a, PruneArgs p) {
     constexpr int G = sc_group<KS>();
     constexpr int TW = (KS + 1) * 64;
@@ -977,7 +1027,7 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma_pruned(ScoreMfmaAr
             const uint32_t slot = wave0 + f * 32 + col;
             const bool act = slot < nf;
             tf[f] = act ? p.flist[p.foff[u] + slot] : 0u;
-            valid[f] = flow_operand<KS, SPARE>(a, tf[f], act, half, b[f]);
+            valid[f] = flow_operand<KS, SF>(a, tf[f], act, half, b[f]);
         }
         v16i_t C[MF_FB];
 #pragma unroll
@@ -986,7 +1036,7 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma_pruned(ScoreMfmaAr
         // the same loads and barriers, and skips the products)
         if (__builtin_amdgcn_readfirstlane(wave0 < nf ? 1 : 0)) {
             stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], t0, t1, lds, [&](const uint4 *tile) __attribute__((always_inline)) {
-                score_tile<KS, SPARE>(tile, lane, b, C);
+                score_tile<KS, SF>(tile, lane, b, C);
             });
             score_flush(a.out, cls, half, C, tf, valid);
         } else {
@@ -996,15 +1046,16 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma_pruned(ScoreMfmaAr
     }
 }
 
-void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, bool spare, uint4 *frag,
-                          hipStream_t s, const uint32_t *perm, const uint32_t *bt, const uint32_t *brow, uint32_t L,
-                          uint32_t ntiles) {
+void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint32_t KS, bool spare, bool tern,
+                          uint4 *frag, hipStream_t s, const uint32_t *perm, const uint32_t *bt, const uint32_t *brow,
+                          uint32_t L, uint32_t ntiles) {
     if (!bt) ntiles = (m + 31) / 32;
     if (!ntiles) return;
     IG_REQUIRE(KS >= 1 && KS <= 8, IG_E_UNSUPPORTED, "matrix-core scoring operands of more than 8 words");
     IG_REQUIRE(!bt || (brow && L >= 1), IG_E_INVAL, "bucket tiles without bucket rows");
-    hipLaunchKernelGGL(k_mfma_patterns, dim3((ntiles + 3) / 4), dim3(256), 0, s, W, S, m, KS, ntiles, spare, perm,
-                       bt, brow, L, frag);
+    IG_REQUIRE(!(spare && tern), IG_E_INVAL, "ternary scoring operands take no spare token");
+    hipLaunchKernelGGL(k_mfma_patterns, dim3((ntiles + 3) / 4), dim3(256), 0, s, W, S, m, KS, ntiles, spare, tern,
+                       perm, bt, brow, L, frag);
     IG_HIP(hipGetLastError());
 }
 
@@ -1411,6 +1462,22 @@ void launch_reduce_maxsum(const int64_t *S, size_t m, unsigned long long *d_max_
     IG_HIP(hipGetLastError());
 }
 
+// The form of a model's scoring operands (SF_*).  Ternary operands: the flows carry
+// the constants of a record tile row in the bias slots (launch_mfma_records_ternary).
+static int score_form(const ScoreModel &m, ScoreMfmaArgs &a) {
+    if (!m.fv.ternary) return m.spare ? SF_SPARE : SF_PLAIN;
+    IG_REQUIRE(m.fv.KF == m.KO && m.tslots >= 1 && m.tslots <= 32, IG_E_DEVICE,
+               "ternary scoring operands without bias slots");
+    uint64_t q[2] = {0, 0};
+    for (uint32_t sl = 0; sl < m.tslots; ++sl) {
+        const uint32_t nib = 31 - sl;   // of the upper half of the last word
+        q[nib / 16] |= (uint64_t)(sl ? 0x7u : 0x2u) << (4 * (nib % 16));
+    }
+    a.tbias[0] = q[0];
+    a.tbias[1] = q[1];
+    return SF_TERN;
+}
+
 void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_t *words, uint32_t K,
                        uint32_t n_flows, uint32_t d, const uint32_t *meta, const uint16_t *nbins, int64_t *out,
                        hipStream_t s) {
@@ -1445,23 +1512,25 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
     const uint64_t tiles = (uint64_t)a.ntiles[0] + a.ntiles[1];
     if (!tiles) return;
     IG_REQUIRE(m.KO >= 1 && m.KO <= 8, IG_E_UNSUPPORTED, "the matrix-core scoring path handles up to 8 words");
-    const void *kernels[8][2] = {
-#define IG_SCK(V) {(const void *)k_score_mfma<V, false>, (const void *)k_score_mfma<V, true>},
+    const void *kernels[8][3] = {
+#define IG_SCK(V) {(const void *)k_score_mfma<V, SF_PLAIN>, (const void *)k_score_mfma<V, SF_SPARE>, \
+                   (const void *)k_score_mfma<V, SF_TERN>},
         IG_SCK(1) IG_SCK(2) IG_SCK(3) IG_SCK(4) IG_SCK(5) IG_SCK(6) IG_SCK(7) IG_SCK(8)
 #undef IG_SCK
     };
-    const void *kern = kernels[m.KO - 1][m.spare ? 1 : 0];
+    const int form = score_form(m, a);
+    const void *kern = kernels[m.KO - 1][form];
     // Equal ranges, 8 r of them (r per XCD): the r * fblocks workgroups of an XCD
     // run in ceil(r * fblocks / slots) rounds of (tiles / 8 r) tiles each, plus a
     // set-up per workgroup (the flows' operands and the ring's first loads, taken
     // as kSetupTiles tiles).  r is chosen to minimise that time: workgroup counts
     // that fill the last round, without making ranges shorter than needed.
     constexpr double kSetupTiles = 32.0;
-    static std::atomic<uint32_t> slot_cache[8][2] = {};
-    uint32_t slots = slot_cache[m.KO - 1][m.spare ? 1 : 0].load(std::memory_order_relaxed);
+    static std::atomic<uint32_t> slot_cache[8][3] = {};
+    uint32_t slots = slot_cache[m.KO - 1][form].load(std::memory_order_relaxed);
     if (!slots) {
         slots = xcd_slots(kern, SC_NT);
-        slot_cache[m.KO - 1][m.spare ? 1 : 0].store(slots, std::memory_order_relaxed);
+        slot_cache[m.KO - 1][form].store(slots, std::memory_order_relaxed);
     }
     // a few recent choices are kept per thread: serving batches cycle through a small set of
     // flow-block counts over one pattern set, and the search below is up to 4,096 steps
@@ -1545,17 +1614,19 @@ bool launch_score_mfma_pruned(const ScoreModel &m, const uint16_t *codes, uint32
     p.queue = w.queue;
     p.L = L;
     p.rt = rt;
-    const void *kernels[8][2] = {
-#define IG_SCP(V) {(const void *)k_score_mfma_pruned<V, false>, (const void *)k_score_mfma_pruned<V, true>},
+    const void *kernels[8][3] = {
+#define IG_SCP(V) {(const void *)k_score_mfma_pruned<V, SF_PLAIN>, (const void *)k_score_mfma_pruned<V, SF_SPARE>, \
+                   (const void *)k_score_mfma_pruned<V, SF_TERN>},
         IG_SCP(1) IG_SCP(2) IG_SCP(3) IG_SCP(4) IG_SCP(5) IG_SCP(6) IG_SCP(7) IG_SCP(8)
 #undef IG_SCP
     };
-    const void *kern = kernels[m.KO - 1][m.spare ? 1 : 0];
-    static std::atomic<uint32_t> slot_cache[8][2] = {};
-    uint32_t slots = slot_cache[m.KO - 1][m.spare ? 1 : 0].load(std::memory_order_relaxed);
+    const int form = score_form(m, a);
+    const void *kern = kernels[m.KO - 1][form];
+    static std::atomic<uint32_t> slot_cache[8][3] = {};
+    uint32_t slots = slot_cache[m.KO - 1][form].load(std::memory_order_relaxed);
     if (!slots) {
         slots = xcd_slots(kern, SC_NT);
-        slot_cache[m.KO - 1][m.spare ? 1 : 0].store(slots, std::memory_order_relaxed);
+        slot_cache[m.KO - 1][form].store(slots, std::memory_order_relaxed);
     }
     // a persistent grid: every resident workgroup drains the queue; no more
     // workgroups than units can exist
