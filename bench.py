@@ -434,13 +434,17 @@ def main():
     ref = ig.fit(d_codes, d_labels, w.nbins, kernels="valu", stream=stream)
     coh_tests = sum(ref.stats().tests)
     del ref
-    sup_tests = sum(st.support_tests)
+    n_class = list(st.n_class)
+    sup_tests = npat[0] * n_class[0] + npat[1] * n_class[1]   # Eq. 2: every pattern against its class
     score_tests = (npat[0] + npat[1]) * n_flows
     tests_per_step = coh_tests + sup_tests + score_tests
     value = tests_per_step / (ms_per_step / 1e3)
-    dense = sum(st.tests)                    # every (candidate, other-class record) pair
-    on_mfma = dense != coh_tests             # the matrix-core kernels ran (no early exit)
+    dense = st.distinct[0] * n_class[1] + st.distinct[1] * n_class[0]   # every (candidate, record) pair
     info = models[-1].info()
+    on_mfma = info.fit_words > 0             # the matrix-core kernels ran (no early exit)
+    buckets = bool(info.flags & ig.IG_MODEL_FIT_BUCKETS)
+    # pairs the contractions examined: all of them, or those of each candidate's bucket
+    exec_coh, exec_sup = sum(st.tests), sum(st.support_tests)
     L_mfma = int(info.fit_tokens)            # tokens per operand row of the fit's contractions
     W_mfma = int(info.fit_words)             # 64-token words they occupy
     L_score = int(info.mfma_tokens)          # tokens per row of the scoring operands
@@ -454,7 +458,14 @@ def main():
     if peaks:
         log("measured peaks", peaks)
     kernels = {}
-    if on_mfma:
+    if on_mfma and buckets:
+        # token buckets: a launch examines the pairs of each candidate with the records
+        # holding its bucket token (the padding of buckets to whole tiles not counted)
+        kernels["k_contain_mfma_pruned[coherence]"] = dict(ms=kcoh_ms, launches=2, tests=exec_coh,
+                                                           exec_tests=exec_coh, tok=L_mfma, words=W_mfma)
+        kernels["k_contain_mfma_pruned[support]"] = dict(ms=ksup_ms, launches=2, tests=exec_sup,
+                                                         exec_tests=exec_sup, tok=L_mfma, words=W_mfma)
+    elif on_mfma:
         # coherence: the method's tests are sum t(b); the launch executes every pair
         kernels["k_contain_mfma[coherence]"] = dict(ms=kcoh_ms, launches=2, tests=coh_tests, exec_tests=dense,
                                                     tok=L_mfma, words=W_mfma)
@@ -494,9 +505,10 @@ def main():
         "config": {"workload": w.name, "n_train": int(w.n), "n_flows": int(n_flows), "d": int(w.d),
                    "L": int(w.L), "K": int(K), "fit_tokens": L_mfma, "fit_words": W_mfma,
                    "score_tokens": L_score, "score_words": W_score},
-        "tests_per_step": {"coherence": coh_tests, "coherence_dense": dense, "support": sup_tests,
-                           "scoring": score_tests,
+        "tests_per_step": {"coherence": coh_tests, "coherence_dense": dense, "coherence_executed": exec_coh,
+                           "support": sup_tests, "support_executed": exec_sup, "scoring": score_tests,
                            "scoring_executed": pruned["tests"] if pruned else score_tests},
+        "fit_token_buckets": buckets,
         "patterns": list(npat), "distinct": list(st.distinct),
         "stage_ms": {k: round(v, 3) for k, v in zip(
             ["pack", "pairs", "sort", "dedup", "coherence", "order", "support", "fit_total"], st.ms)},
@@ -549,7 +561,7 @@ def main():
             w2.codes, w2.labels, w2.nbins, dc2, dl2)
         m2 = ig.fit(dc2, dl2, w2.nbins)
         st2 = m2.stats()
-        res["fit_148k"] = {"n_train": int(w2.n), "patterns": list(m2.n_patterns()), "tests_dense": list(st2.tests),
+        res["fit_148k"] = {"n_train": int(w2.n), "patterns": list(m2.n_patterns()), "tests_executed": list(st2.tests),
                            "coherence_kernel_ms": st2.kernel_ms[0], "support_kernel_ms": st2.kernel_ms[1]}
         d_f2 = torch.from_numpy(w2.test_codes.view(np.int16)).cuda()
         out2 = torch.empty((w2.test_codes.shape[0], 2), dtype=torch.int64, device="cuda")

@@ -130,7 +130,17 @@ typedef struct {
                                        + 7 tokens, 3 words, for 41 features of ~11
                                        bins.
                                    All give the same patterns, f and S.             */
-    uint32_t reserved;
+    uint32_t fit_dense;         /* matrix-core coherence and support on the ternary
+                                   bit tokens (mode 5, or 0 / 1 when they apply):
+                                   0 = token buckets: the records of the tested class
+                                       are listed under each token they hold, and a
+                                       candidate meets only the records holding its
+                                       token held by the fewest (a record without it
+                                       cannot contain the candidate, Eq. 6), so
+                                       ig_stats.tests and support_tests count the
+                                       (candidate, record) pairs of its bucket;
+                                   1 = every record (dense).
+                                   Both give the same patterns, f and S.             */
     const ig_allocator *alloc;  /* NULL: the library's device arena (chunks taken from
                                    the runtime once and sub-allocated, see
                                    ig_release_memory); else every model buffer and
@@ -149,8 +159,12 @@ typedef struct {
                                 path the sum over distinct candidates of t(b), the
                                 other-class records examined in input order up to and
                                 including the first that contains b (all of them when
-                                none does); on the matrix cores every pair           */
-    uint64_t support_tests[2]; /* |P^c| * n_c subset tests of Eq. 2                  */
+                                none does); on the matrix cores every pair, or with
+                                token buckets (fit_dense = 0) the pairs of each
+                                candidate and the records of its bucket             */
+    uint64_t support_tests[2]; /* subset tests of Eq. 2 made by the support kernel:
+                                |P^c| * n_c, or with token buckets the pairs of
+                                each pattern and the records of its bucket          */
     uint32_t chunks[2];      /* pair-space chunks used for the class                 */
     float ms[8];             /* device time per stage: 0 pack, 1 pairs+hash, 2 sort,
                                 3 dedup, 4 coherence, 5 order, 6 support, 7 total
@@ -187,6 +201,10 @@ typedef struct {
 /* IG_MODEL_BUCKETED: the matrix-core scoring tiles are grouped by token bucket
  * (fits from codes and imported models), so ig_score can prune (ig_score_ex). */
 #define IG_MODEL_BUCKETED 4u
+/* IG_MODEL_FIT_BUCKETS: the fit's coherence and support contractions tested each
+ * candidate only against the records holding its token held by the fewest of them
+ * (ig_fit_opts.fit_dense = 0). */
+#define IG_MODEL_FIT_BUCKETS 8u
 
 /* One problem of a batched fit. */
 typedef struct {

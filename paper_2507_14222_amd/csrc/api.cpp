@@ -56,6 +56,7 @@ struct DevModel {
     uint32_t fac_tokens_last = 0;          // of them, in its last word
     uint32_t tern_tokens = 0;              // tokens of the ternary form
     uint32_t fit_tokens = 0, fit_words = 0;    // operand rows of the fit's contractions
+    bool fit_buckets = false;              // the fit's contractions used token buckets
     bool score_factored = false;           // frag holds factored operand rows
     bool score_ternary = false;            // ... of the ternary view (tv)
     bool score_spare = false;              // frag carries the +1 at the spare last token
@@ -534,6 +535,110 @@ static void canonical_permutation(const DevModel &m, const uint64_t *X, uint32_t
     if (pcur != perm) IG_HIP(hipMemcpyAsync(perm, pcur, count * 4, hipMemcpyDeviceToDevice, s));
 }
 
+// The records of one class listed under each token they hold (bucket L: all of
+// them), as A tiles of the pruned contractions (k_contain_mfma_pruned).
+struct FitBuckets {
+    std::vector<uint32_t> cnt;     // [L + 1] records per bucket (host copy)
+    Scratch<uint32_t> dcnt;        // [L] the same on the device: the buckets' costs
+    Scratch<uint32_t> tab;         // [L + 2] tile starts bt, then [L + 1] records brec
+    Scratch<uint4> frag;
+};
+
+struct MfmaFit {
+    bool on = false;
+    FactorView view;
+    uint32_t KO = 0;
+    uint32_t RW = 0;           // words per operand row: 2 KO for a ternary view
+    Scratch<uint4> frag[2];
+    Scratch<uint64_t> fr[2];   // factored rows of each class's records (factored view only)
+    bool pruned = false;       // token buckets: bk[t] lists class t's records
+    uint32_t L = 0;
+    FitBuckets bk[2];
+};
+
+// Token buckets of class t's records for the pruned contractions (ternary view).
+static void build_fit_buckets(const DevModel &m, const ClassRows &R, const MfmaFit &mf, int t, FitBuckets &b,
+                              hipStream_t s) {
+    const uint32_t L = m.L;
+    b.dcnt.reset(L, s);
+    launch_fill_u32(b.dcnt.get(), 0u, L, s);
+    launch_token_counts(R.X.get(), R.n, m.KS, L, b.dcnt.get(), s);
+    b.cnt = host_read_u32(b.dcnt.get(), L, s);
+    b.cnt.push_back(R.n);
+    // list offsets ro, tile starts bt, records per bucket brec
+    std::vector<uint32_t> h(3 * (size_t)L + 5, 0);
+    uint32_t *ro = h.data(), *bt = ro + L + 2, *brec = bt + L + 2;
+    for (uint32_t u = 0; u <= L; ++u) {
+        ro[u + 1] = ro[u] + b.cnt[u];
+        bt[u + 1] = bt[u] + (b.cnt[u] + 31) / 32;
+        brec[u] = b.cnt[u];
+    }
+    const uint32_t ntiles = bt[L + 1];
+    Scratch<uint32_t> dro(L + 2, s), cursor(L + 1, s), list(std::max<uint32_t>(ro[L + 1], 1), s);
+    b.tab.reset(2 * (size_t)L + 3, s);
+    IG_HIP(hipMemcpyAsync(dro.get(), ro, (L + 2) * 4, hipMemcpyHostToDevice, s));
+    IG_HIP(hipMemcpyAsync(b.tab.get(), bt, (2 * (size_t)L + 3) * 4, hipMemcpyHostToDevice, s));
+    launch_bucket_records(R.X.get(), R.n, m.KS, L, dro.get(), cursor.get(), list.get(), s);
+    b.frag.reset(std::max<size_t>((size_t)ntiles * mf.KO * 64, 1), s);
+    launch_mfma_records_ternary_lists(mf.fr[t].get(), mf.KO, m.tern_tokens, list.get(), dro.get(), b.tab.get(),
+                                      b.tab.get() + L + 2, L + 1, ntiles, b.frag.get(), s);
+    IG_HIP(hipStreamSynchronize(s));   // the host tables above are freed on return
+}
+
+// Candidates (pair ids `ids` of the records X [n][KS], or rows W [m][KS] of
+// one-hot words when ids is null) whose operand rows are B, tested on the matrix
+// cores against the records of the buckets b only: out[e] as launch_contain_mfma's
+// (coherence flags, or support counts).  Returns the (candidate, record) pairs
+// tested; adds the contraction's device time to *kernel_ms.
+static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uint64_t *X, uint32_t n, uint32_t KS,
+                               const uint32_t *ids, const uint64_t *W, size_t m, const uint64_t *B, bool count,
+                               uint32_t *out, int sets, float *kernel_ms, hipStream_t s) {
+    if (!m) return 0;
+    IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 candidates in one contraction");
+    // the support count takes 8 per record lacking a candidate in 32 bits
+    IG_REQUIRE(b.cnt.back() < (1u << 28), IG_E_UNSUPPORTED, "more than 2^28 records in one class");
+    const uint32_t L = mf.L;
+    Scratch<uint32_t> key(m, s), hist(L + 1, s), perm(m, s), cursor(L + 1, s), tab(2 * (size_t)L + 4, s);
+    launch_cand_bucket_keys(X, n, KS, ids, W, m, L, b.dcnt.get(), key.get(), hist.get(), s);
+    const std::vector<uint32_t> h = host_read_u32(hist.get(), L + 1, s);
+    const uint32_t cols = contain_pruned_cols((int)mf.KO, sets);
+    std::vector<uint32_t> t(2 * (size_t)L + 4, 0);
+    uint32_t *cs = t.data(), *uoff = cs + L + 2;
+    uint64_t tests = 0;
+    for (uint32_t u = 0; u <= L; ++u) {
+        cs[u + 1] = cs[u] + h[u];
+        uoff[u + 1] = uoff[u] + (h[u] + cols - 1) / cols;
+        tests += (uint64_t)h[u] * b.cnt[u];
+    }
+    IG_HIP(hipMemcpyAsync(tab.get(), t.data(), t.size() * 4, hipMemcpyHostToDevice, s));
+    launch_bucket_place(key.get(), m, L, tab.get(), cursor.get(), perm.get(), s);
+    ContainBuckets k{};
+    k.perm = perm.get();
+    k.cs = tab.get();
+    k.uoff = tab.get() + L + 2;
+    k.bt = b.tab.get();
+    k.brec = b.tab.get() + L + 2;
+    k.nb = L + 1;
+    hipEvent_t ke[2];
+    IG_HIP(hipEventCreate(&ke[0]));
+    IG_HIP(hipEventCreate(&ke[1]));
+    struct Ev {
+        hipEvent_t *e;
+        ~Ev() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } evg{ke};
+    IG_HIP(hipEventRecord(ke[0], s));
+    launch_contain_mfma_pruned((int)mf.KO, count, B, b.frag.get(), k, uoff[L + 1], out, s, sets);
+    IG_HIP(hipEventRecord(ke[1], s));
+    IG_HIP(hipEventSynchronize(ke[1]));   // also: t outlives its copy
+    float tk = 0;
+    IG_HIP(hipEventElapsedTime(&tk, ke[0], ke[1]));
+    if (kernel_ms) *kernel_ms += tk;
+    return tests;
+}
+
 // Rows of the coherent pair ids `ids` of one class (in the order given; in
 // canonical order first when the pair space was chunked, which merges the repeats
 // across chunks), then support and weights.  Fills model class c.
@@ -541,7 +646,7 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
                             bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
                             int support_mark = -1, const uint4 *own_frag = nullptr,
                             const FactorView &mfma_view = FactorView{}, PatternRows *keep = nullptr,
-                            Scratch<uint64_t> *pre_rows = nullptr) {
+                            Scratch<uint64_t> *pre_rows = nullptr, const MfmaFit *pmf = nullptr) {
     const uint32_t KS = m.KS;
     if (count == 0) {
         m.np[c] = 0;
@@ -599,16 +704,27 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         hipEvent_t ke[2];
         IG_HIP(hipEventCreate(&ke[0]));
         IG_HIP(hipEventCreate(&ke[1]));
-        IG_HIP(hipEventRecord(ke[0], s));
-        launch_contain_mfma((int)KO, true, B.get(), final_count, own_frag, cls.n, m.f[c], s, tu.sup_sets,
-                            mfma_view.ternary != 0);
-        IG_HIP(hipEventRecord(ke[1], s));
-        launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
         float tk = 0;
-        const hipError_t er = hipEventSynchronize(ke[1]);
-        if (er == hipSuccess) (void)hipEventElapsedTime(&tk, ke[0], ke[1]);
-        (void)hipEventDestroy(ke[0]);
-        (void)hipEventDestroy(ke[1]);
+        hipError_t er = hipSuccess;
+        if (pmf && pmf->pruned) {
+            // the patterns against the class's records that hold their bucket token
+            (void)hipEventDestroy(ke[0]);
+            (void)hipEventDestroy(ke[1]);
+            m.stats.support_tests[c] = pruned_contain(*pmf, pmf->bk[c], nullptr, 0, KS, nullptr, m.W[c], final_count,
+                                                      B.get(), true, m.f[c], tu.sup_sets, &tk, s);
+            launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
+        } else {
+            m.stats.support_tests[c] = (uint64_t)final_count * cls.n;
+            IG_HIP(hipEventRecord(ke[0], s));
+            launch_contain_mfma((int)KO, true, B.get(), final_count, own_frag, cls.n, m.f[c], s, tu.sup_sets,
+                                mfma_view.ternary != 0);
+            IG_HIP(hipEventRecord(ke[1], s));
+            launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
+            er = hipEventSynchronize(ke[1]);
+            if (er == hipSuccess) (void)hipEventElapsedTime(&tk, ke[0], ke[1]);
+            (void)hipEventDestroy(ke[0]);
+            (void)hipEventDestroy(ke[1]);
+        }
         IG_HIP(er);
         m.stats.kernel_ms[1] += tk;
         // the scoring operands use the model's own view: keep the rows when it is this one
@@ -617,8 +733,10 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
             keep->rows[c] = std::move(B);
             keep->valid[c] = true;
         }
-    } else
+    } else {
+        m.stats.support_tests[c] = (uint64_t)final_count * cls.n;
         launch_support((int)KS, tu.support_cpl, m.W[c], final_count, cls.NX.get(), cls.n, m.f[c], m.S[c], s);
+    }
 }
 
 // Matrix-core scoring operands of a finished model: when its rows fit the
@@ -780,23 +898,16 @@ constexpr uint32_t kMfmaWords = 16;   // widest operands of the subset-test cont
 // Matrix-core operands of one fit: the token view (factored, or the one-hot words
 // in mode 3) and, per class c, the records of class 1 - c as A tiles (class c's
 // coherence operand, and class 1 - c's support operand).
-struct MfmaFit {
-    bool on = false;
-    FactorView view;
-    uint32_t KO = 0;
-    uint32_t RW = 0;           // words per operand row: 2 KO for a ternary view
-    Scratch<uint4> frag[2];
-    Scratch<uint64_t> fr[2];   // factored rows of each class's records (factored view only)
-};
-
 // Decide the subset-test path of a fit from the coherence_mfma option (0 auto:
 // matrix cores when the operands fit 16 words; 1 matrix cores; 2 VALU; 3 matrix
 // cores on the one-hot words; 4 matrix cores on the factored tokens with presence
 // tokens; 5 matrix cores on the ternary bit tokens) and build the record tiles
 // when it is the matrix cores.  Modes 0 and 1 take the ternary view (bit tokens
 // only) of a fit from codes when it needs fewer words than the presence tokens.
-static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode, MfmaFit &mf, hipStream_t s) {
+static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode, uint32_t dense, MfmaFit &mf,
+                       hipStream_t s) {
     IG_REQUIRE(mode <= 5, IG_E_INVAL, "coherence_mfma must be 0 to 5");
+    IG_REQUIRE(dense <= 1, IG_E_INVAL, "fit_dense must be 0 or 1");
     const uint32_t KS = m.KS;
     const bool tern = m.tv.KF && (mode == 5 || ((mode == 0 || mode == 1) && (!m.fv.KF || m.tv.KF < m.fv.KF)));
     mf.view = mode == 3 ? FactorView{} : tern ? m.tv : m.fv;
@@ -823,6 +934,13 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
         else if (mf.view.KF) launch_mfma_records_signed(mf.fr[1 - c].get(), o.n, mf.view, mf.frag[c].get(), s);
         else launch_mfma_records(o.NX.get(), o.n, KS, mf.frag[c].get(), s);
     }
+    // token buckets (ternary view): each candidate meets the records holding its
+    // rarest token only
+    mf.pruned = !dense && mf.view.ternary && m.L >= 1 && m.L <= 4096;
+    if (mf.pruned) {
+        mf.L = m.L;
+        for (int t = 0; t < 2; ++t) build_fit_buckets(m, cls[t], mf, t, mf.bk[t], s);
+    }
 }
 
 // Coherence of class c's ncand candidate pair ids `cand` on the matrix cores
@@ -830,7 +948,7 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
 // (synchronises the stream); adds the contraction's device time to *kernel_ms.
 static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c, uint32_t KS, const uint32_t *cand,
                                uint32_t ncand, uint32_t *out, float *kernel_ms, hipStream_t s,
-                               uint64_t *rows_out = nullptr, int sets = 0) {
+                               uint64_t *rows_out = nullptr, int sets = 0, uint64_t *tests = nullptr) {
     if (!ncand) return 0;
     Scratch<uint32_t> keep(ncand, s), kpos(ncand, s), ktot(1, s);
     Scratch<uint64_t> B((size_t)ncand * mf.RW, s);
@@ -838,6 +956,17 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
         launch_pair_rows_factored(mf.fr[c].get(), cls[c].n, cand, ncand, mf.view, B.get(), s);
     else
         launch_operand_rows(cls[c].X.get(), cls[c].n, cand, nullptr, KS, ncand, mf.view, false, B.get(), s);
+    if (mf.pruned) {
+        // the candidates against the other class's records that hold their bucket token
+        const uint64_t t = pruned_contain(mf, mf.bk[1 - c], cls[c].X.get(), cls[c].n, KS, cand, nullptr, ncand,
+                                          B.get(), false, keep.get(), sets, kernel_ms, s);
+        if (tests) *tests += t;
+        scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
+        launch_compact(keep.get(), kpos.get(), cand, ncand, out, s);
+        if (rows_out) launch_compact_rows(B.get(), keep.get(), kpos.get(), ncand, mf.RW, rows_out, s);
+        return host_read_u32(ktot.get(), 1, s)[0];
+    }
+    if (tests) *tests += (uint64_t)ncand * cls[1 - c].n;
     hipEvent_t ke[2];
     IG_HIP(hipEventCreate(&ke[0]));
     IG_HIP(hipEventCreate(&ke[1]));
@@ -935,13 +1064,14 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     }
     const uint32_t grid = coherence_grid(tu.grid_per_cu);
     MfmaFit mf;
-    mfma_setup(m, cls, opts ? opts->coherence_mfma : 0u, mf, s);
+    mfma_setup(m, cls, opts ? opts->coherence_mfma : 0u, opts ? opts->fit_dense : 0u, mf, s);
     const bool use_mfma = mf.on;
     if (use_mfma) {
         mfma_tuning(opts, mf.KO, fit_pairs, tu);
         note_fit_operands(m, mf);
         // scoring follows the fit's factored view
         if (mf.view.KF) m.score_pref = mf.view.ternary ? 1 : 0;
+        m.fit_buckets = mf.pruned;
     }
     Scratch<uint64_t> surv_rows[2];   // operand rows of the coherent candidates (one-chunk fits)
     uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
@@ -1012,8 +1142,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
                     ro = surv_rows[c].get();
                 }
                 mfma_surv[c] += mfma_coherence(mf, cls, c, KS, cc, hc[c], surv[c].get() + mfma_surv[c],
-                                               &m.stats.kernel_ms[0], s, ro, tu.coh_sets);
-                mfma_tests[c] += (uint64_t)hc[c] * cls[1 - c].n;
+                                               &m.stats.kernel_ms[0], s, ro, tu.coh_sets, &mfma_tests[c]);
             }
             IG_HIP(hipEventRecord(e[4], s));
             IG_HIP(hipStreamSynchronize(s));
@@ -1102,9 +1231,8 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         // frag[1 - c] holds class c's own records (it is class 1-c's coherence operand)
         order_and_weigh(m, c, cls[c], surv[c].get(), hn[c], chunked, tu, s, &tm, c == 0 ? 5 : 8,
                         use_mfma ? mf.frag[1 - c].get() : nullptr, mf.view, &prow,
-                        surv_rows[c].get() ? &surv_rows[c] : nullptr);
+                        surv_rows[c].get() ? &surv_rows[c] : nullptr, use_mfma ? &mf : nullptr);
         m.stats.coherent[c] = m.np[c];
-        m.stats.support_tests[c] = m.np[c] * (uint64_t)cls[c].n;
         if (c == 0) tm.mark(3);   // end of class 0's support
     }
     tm.mark(6);
@@ -1346,8 +1474,11 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
     const uint32_t mode = opts ? opts->coherence_mfma : 0u;
     std::vector<MfmaFit> mf(G.size());
     for (uint32_t g = 0; g < G.size(); ++g) {
-        mfma_setup(*G[g]->m, G[g]->cls, mode, mf[g], s);
-        if (mf[g].on) note_fit_operands(*G[g]->m, mf[g]);
+        mfma_setup(*G[g]->m, G[g]->cls, mode, opts ? opts->fit_dense : 0u, mf[g], s);
+        if (mf[g].on) {
+            note_fit_operands(*G[g]->m, mf[g]);
+            G[g]->m->fit_buckets = mf[g].pruned;
+        }
     }
     Scratch<uint32_t> zero(1, s);
     {
@@ -1433,9 +1564,10 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
         mfma_tuning(opts, mf[g].KO, G[g]->pairs(), tg);
         for (int c = 0; c < 2; ++c) {
             const uint32_t sg = 2 * g + c;
+            uint64_t t = 0;
             hsurv[sg] = mfma_coherence(mf[g], G[g]->cls, c, KS, cand.get() + hoff[sg], hdist[sg],
-                                       surv.get() + off[sg], &mfma_kernel[g], s, nullptr, tg.coh_sets);
-            htests[sg] = (unsigned long long)hdist[sg] * G[g]->cls[1 - c].n;
+                                       surv.get() + off[sg], &mfma_kernel[g], s, nullptr, tg.coh_sets, &t);
+            htests[sg] = (unsigned long long)t;
         }
         mfma_ms[g] = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -1454,9 +1586,9 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
             m.stats.tests[c] = htests[sg];
             m.stats.chunks[c] = G[g]->M[c] ? 1 : 0;
             order_and_weigh(m, c, G[g]->cls[c], surv.get() + off[sg], hsurv[sg], false, tp, s, &tm,
-                            c == 0 ? 5 : 8, mf[g].on ? mf[g].frag[1 - c].get() : nullptr, mf[g].view, &prow);
+                            c == 0 ? 5 : 8, mf[g].on ? mf[g].frag[1 - c].get() : nullptr, mf[g].view, &prow,
+                            nullptr, mf[g].on ? &mf[g] : nullptr);
             m.stats.coherent[c] = m.np[c];
-            m.stats.support_tests[c] = m.np[c] * (uint64_t)G[g]->cls[c].n;
             if (c == 0) tm.mark(3);
         }
         tm.mark(6);
@@ -1859,7 +1991,8 @@ ig_status ig_model_get_info(const ig_model *m, ig_model_info *info) {
         info->d = M.d;
         info->flags = ((M.frag[0] && M.frag[1]) ? IG_MODEL_SCORE_MFMA : 0u) |
                       (M.score_factored ? IG_MODEL_FACTORED : 0u) |
-                      ((M.frag[0] && M.frag[1] && M.btile[0] && M.btile[1]) ? IG_MODEL_BUCKETED : 0u);
+                      ((M.frag[0] && M.frag[1] && M.btile[0] && M.btile[1]) ? IG_MODEL_BUCKETED : 0u) |
+                      (M.fit_buckets ? IG_MODEL_FIT_BUCKETS : 0u);
         info->mfma_tokens = M.score_ternary ? M.tern_tokens : M.score_factored ? M.fac_tokens : M.L;
         info->mfma_words = M.score_ternary ? M.tv.KF : M.score_factored ? M.fv.KF : M.K;
         info->fit_tokens = M.fit_tokens;

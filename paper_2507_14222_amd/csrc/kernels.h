@@ -189,11 +189,30 @@ __host__ __device__ constexpr uint32_t tern_bias_slots(uint32_t T) { return 3u +
 // AND V -1.0, else 0) and the bias slots; rows past n are 0 on every token.
 void launch_mfma_records_ternary(const uint64_t *FR, uint32_t n, uint32_t KO, uint32_t T, uint4 *frag,
                                  hipStream_t s);
+// The same tiles of records listed per bucket (bucket u < nb: the brec[u] records
+// list[ro[u] ..] in tiles [bt[u], bt[u + 1]), the last one padded with empty rows).
+void launch_mfma_records_ternary_lists(const uint64_t *FR, uint32_t KO, uint32_t T, const uint32_t *list,
+                                       const uint32_t *ro, const uint32_t *bt, const uint32_t *brec, uint32_t nb,
+                                       uint32_t ntiles, uint4 *frag, hipStream_t s);
 // sets: 32-column sets per wave (1..3, capped by what fits the registers at KO
 // words; 0 = the default for KO).  ternary: B rows are [m][2 KO] ternary rows and
 // the tiles come from launch_mfma_records_ternary.
 void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const uint4 *frag, uint32_t n_rec,
                          uint32_t *out, hipStream_t s, int sets = 0, bool ternary = false);
+
+// The contraction pruned by token buckets (ternary rows only, see
+// k_contain_mfma_pruned): candidates of bucket u are positions [cs[u], cs[u + 1])
+// of perm (position -> row of B and of out); workgroups [uoff[u], uoff[u + 1])
+// take them contain_pruned_cols(KO, sets) at a time against the record tiles
+// [bt[u], bt[u + 1]) of bucket u (brec[u] real records), u < nb.  units =
+// uoff[nb].  out as launch_contain_mfma's.
+struct ContainBuckets {
+    const uint32_t *perm, *cs, *uoff, *bt, *brec;
+    uint32_t nb;                // buckets
+};
+uint32_t contain_pruned_cols(int KO, int sets);
+void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uint4 *frag, const ContainBuckets &k,
+                                uint32_t units, uint32_t *out, hipStream_t s, int sets = 0);
 
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented
 // rows NX [n][KS] of their class.
@@ -229,6 +248,19 @@ struct PruneWork {
     uint32_t *cnt, *cursor, *foff, *uoff, *queue, *list;
 };
 size_t prune_scratch_words(uint32_t L, uint32_t n_flows, uint32_t d);
+// Token buckets of the fit's contractions (see prune.hip).  key[e] (<= L) = the
+// bucket of candidate e (pair id ids[e] of X, or row e of W when ids is null):
+// its token held by the fewest records (cnt [L]), L when it has none; hist [L + 1]
+// = candidates per bucket.
+void launch_cand_bucket_keys(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, const uint64_t *W,
+                             size_t m, uint32_t L, const uint32_t *cnt, uint32_t *key, uint32_t *hist, hipStream_t s);
+// perm: positions grouped by bucket, bucket u from cs[u] (cursor: L + 1 scratch).
+void launch_bucket_place(const uint32_t *key, size_t m, uint32_t L, const uint32_t *cs, uint32_t *cursor,
+                         uint32_t *perm, hipStream_t s);
+// list[ro[u] ..]: the records of X [n][KS] holding token u < L; bucket L: all of
+// them in order (cursor: L + 1 scratch).
+void launch_bucket_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, const uint32_t *ro,
+                           uint32_t *cursor, uint32_t *list, hipStream_t s);
 PruneWork prune_work(uint32_t *ws, uint32_t L);
 // Lists of the valid flows holding each token, work units of SC_COLS-flow blocks
 // and rt-tile ranges per (class, bucket), and out initialised ((0,0) valid,

@@ -11,6 +11,15 @@
 // Model side (once per model): k_token_counts, k_bucket_keys, k_bucket_first.
 // Call side (per scoring call, in caller-provided or library scratch):
 // k_prune_count -> k_prune_plan -> k_prune_scatter -> k_score_mfma_pruned.
+//
+// The fit's contractions are pruned the same way (Eq. 3 and Eq. 2 test whether a
+// record contains a candidate, which needs every token of the candidate in the
+// record): the records of the tested class are listed under each token they hold
+// (k_bucket_records), a candidate goes to the bucket of its token held by the
+// fewest of those records (k_cand_bucket_keys, k_bucket_place), and
+// k_contain_mfma_pruned tests it against that bucket's records only.  Bucket L
+// lists every record: it takes the candidates without a token (the empty set,
+// which every record contains).
 #include "common.h"
 #include "kernels.h"
 
@@ -95,6 +104,125 @@ void launch_bucket_keys(const uint64_t *W, size_t m, uint32_t KS, uint32_t L, co
 void launch_bucket_first(const uint64_t *key, size_t m, uint32_t *first, hipStream_t s) {
     if (!m) return;
     hipLaunchKernelGGL(k_bucket_first, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, key, m, first);
+    IG_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------- fit contractions ----
+// key[e] = the bucket of candidate e: its token with the fewest records (cnt),
+// the lowest such token on ties, or L for a candidate without a token; hist[u] +=
+// the candidates of bucket u (u <= L).  Candidate e is the pair id ids[e] of the
+// records X [n][KS] (their intersection), or row e of W [m][KS] when ids is null.
+__global__ __launch_bounds__(256) void k_cand_bucket_keys(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS,
+                                                          const uint32_t *__restrict__ ids,
+                                                          const uint64_t *__restrict__ W, size_t m, uint32_t L,
+                                                          const uint32_t *__restrict__ cnt, uint32_t *__restrict__ key,
+                                                          uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[kMaxBuckets + 1];
+    for (uint32_t u = threadIdx.x; u <= L; u += blockDim.x) h[u] = 0;
+    __syncthreads();
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) {
+        uint32_t i = 0, j = 0;
+        if (ids) decode_pair(ids[e], n, i, j);
+        uint32_t best = L, bc = ~0u;
+        for (uint32_t k = 0; k < KS; ++k) {
+            uint64_t w = ids ? (X[(size_t)i * KS + k] & X[(size_t)j * KS + k]) : W[e * KS + k];
+            while (w) {
+                const uint32_t tok = 64 * k + (uint32_t)__builtin_ctzll(w);
+                w &= w - 1;
+                if (tok >= L) break;
+                const uint32_t c = cnt[tok];
+                if (c < bc) {   // tokens come in ascending order: ties keep the lowest
+                    bc = c;
+                    best = tok;
+                }
+            }
+        }
+        key[e] = best;
+        atomicAdd(&h[best], 1u);
+    }
+    __syncthreads();
+    for (uint32_t u = threadIdx.x; u <= L; u += blockDim.x)
+        if (h[u]) atomicAdd(&hist[u], h[u]);
+}
+
+// perm[cs[key[e]] + (place of e among its bucket's candidates)] = e.  Each
+// workgroup counts its elements per bucket, reserves a range of each bucket
+// (cursor, zero at launch), and places its elements there (the order inside a
+// bucket is not fixed; the results do not depend on it).
+constexpr uint32_t BP_T = 256, BP_I = 8;
+__global__ __launch_bounds__(BP_T) void k_bucket_place(const uint32_t *__restrict__ key, size_t m, uint32_t L,
+                                                       const uint32_t *__restrict__ cs, uint32_t *__restrict__ cursor,
+                                                       uint32_t *__restrict__ perm) {
+    __shared__ uint32_t h[kMaxBuckets + 1];
+    for (uint32_t u = threadIdx.x; u <= L; u += BP_T) h[u] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * (BP_T * BP_I);
+    uint32_t k[BP_I], r[BP_I];
+#pragma unroll
+    for (uint32_t it = 0; it < BP_I; ++it) {
+        const size_t e = base + (size_t)it * BP_T + threadIdx.x;
+        k[it] = e < m ? key[e] : ~0u;
+        r[it] = k[it] != ~0u ? atomicAdd(&h[k[it]], 1u) : 0u;
+    }
+    __syncthreads();
+    for (uint32_t u = threadIdx.x; u <= L; u += BP_T)
+        if (h[u]) h[u] = cs[u] + atomicAdd(&cursor[u], h[u]);   // the workgroup's first slot
+    __syncthreads();
+#pragma unroll
+    for (uint32_t it = 0; it < BP_I; ++it) {
+        const size_t e = base + (size_t)it * BP_T + threadIdx.x;
+        if (k[it] != ~0u) perm[h[k[it]] + r[it]] = (uint32_t)e;
+    }
+}
+
+// The records of X [n][KS] under each token u < L they hold: list[ro[u] + slot]
+// (slots taken from cursor, zero at launch); bucket L lists every record in order.
+__global__ void k_bucket_records(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS, uint32_t L,
+                                 const uint32_t *__restrict__ ro, uint32_t *__restrict__ cursor,
+                                 uint32_t *__restrict__ list) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    list[ro[L] + r] = r;
+    for (uint32_t k = 0; k < KS; ++k) {
+        uint64_t w = X[(size_t)r * KS + k];
+        while (w) {
+            const uint32_t tok = 64 * k + (uint32_t)__builtin_ctzll(w);
+            w &= w - 1;
+            if (tok >= L) break;
+            list[ro[tok] + atomicAdd(&cursor[tok], 1u)] = r;
+        }
+    }
+}
+
+void launch_cand_bucket_keys(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, const uint64_t *W,
+                             size_t m, uint32_t L, const uint32_t *cnt, uint32_t *key, uint32_t *hist, hipStream_t s) {
+    IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
+    IG_REQUIRE((ids && X) || (!ids && W), IG_E_INVAL, "candidates need pair ids and records, or rows");
+    launch_fill_u32(hist, 0u, L + 1, s);
+    if (!m) return;
+    hipLaunchKernelGGL(k_cand_bucket_keys, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, X, n, KS, ids, W, m,
+                       L, cnt, key, hist);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_bucket_place(const uint32_t *key, size_t m, uint32_t L, const uint32_t *cs, uint32_t *cursor,
+                         uint32_t *perm, hipStream_t s) {
+    IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
+    launch_fill_u32(cursor, 0u, L + 1, s);
+    if (!m) return;
+    const size_t per = (size_t)BP_T * BP_I;
+    hipLaunchKernelGGL(k_bucket_place, dim3((unsigned)((m + per - 1) / per)), dim3(BP_T), 0, s, key, m, L, cs, cursor,
+                       perm);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_bucket_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, const uint32_t *ro,
+                           uint32_t *cursor, uint32_t *list, hipStream_t s) {
+    IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
+    launch_fill_u32(cursor, 0u, L + 1, s);
+    if (!n) return;
+    hipLaunchKernelGGL(k_bucket_records, dim3((n + 255) / 256), dim3(256), 0, s, X, n, KS, L, ro, cursor, list);
     IG_HIP(hipGetLastError());
 }
 

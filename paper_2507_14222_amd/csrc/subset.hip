@@ -363,20 +363,17 @@ __global__ void k_mfma_records_signed(const uint64_t *__restrict__ FR, uint32_t 
 // against which each candidate row carries the nibbles that add 1 - |P|.  Rows past
 // n are 0 everywhere, so every product with them is 0, never the 1 of a record that
 // contains the candidate.
-__global__ void k_mfma_records_ternary(const uint64_t *__restrict__ FR, uint32_t n, uint32_t KO, uint32_t ntiles,
-                                       uint32_t nslots, uint4 *__restrict__ frag) {
-    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (size_t)ntiles * KO * 64) return;
-    const uint32_t lane = (uint32_t)(g % 64), word = (uint32_t)((g / 64) % KO), tile = (uint32_t)(g / (64 * KO));
-    const uint32_t r = tile * 32 + lane % 32, h = lane / 32;
+// Slice (word, half h) of a record tile row: record r of FR, or none (all zero).
+__device__ __forceinline__ uint4 ternary_record_slice(const uint64_t *__restrict__ FR, uint32_t KO, uint32_t nslots,
+                                                      bool has, uint32_t r, uint32_t word, uint32_t h) {
     uint32_t P = 0, V = 0;
-    if (r < n) {
+    if (has) {
         P = (uint32_t)(FR[(size_t)r * 2 * KO + word] >> (32 * h));
         V = (uint32_t)(FR[(size_t)r * 2 * KO + KO + word] >> (32 * h));
     }
     uint32_t q[4] = {spread8(P) | spread8(V) * 4u, spread8(P >> 8) | spread8(V >> 8) * 4u,
                      spread8(P >> 16) | spread8(V >> 16) * 4u, spread8(P >> 24) | spread8(V >> 24) * 4u};
-    if (r < n && word == KO - 1 && h == 1) {
+    if (has && word == KO - 1 && h == 1) {
         // the bias slots, from the top token down: +1.0, then +6.0
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -386,7 +383,38 @@ __global__ void k_mfma_records_ternary(const uint64_t *__restrict__ FR, uint32_t
                 if (slot < nslots) q[j] |= (slot ? 0x7u : 0x2u) << (4 * i);
             }
     }
-    frag[g] = make_uint4(q[0], q[1], q[2], q[3]);
+    return make_uint4(q[0], q[1], q[2], q[3]);
+}
+
+__global__ void k_mfma_records_ternary(const uint64_t *__restrict__ FR, uint32_t n, uint32_t KO, uint32_t ntiles,
+                                       uint32_t nslots, uint4 *__restrict__ frag) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (size_t)ntiles * KO * 64) return;
+    const uint32_t lane = (uint32_t)(g % 64), word = (uint32_t)((g / 64) % KO), tile = (uint32_t)(g / (64 * KO));
+    const uint32_t r = tile * 32 + lane % 32;
+    frag[g] = ternary_record_slice(FR, KO, nslots, r < n, r, word, lane / 32);
+}
+
+// The same tiles of the records listed per bucket: bucket u < nb holds the brec[u]
+// records list[ro[u] ..] in tiles [bt[u], bt[u + 1]), its last tile padded with
+// empty rows.
+__global__ void k_mfma_records_ternary_lists(const uint64_t *__restrict__ FR, uint32_t KO, uint32_t ntiles,
+                                             uint32_t nslots, const uint32_t *__restrict__ list,
+                                             const uint32_t *__restrict__ ro, const uint32_t *__restrict__ bt,
+                                             const uint32_t *__restrict__ brec, uint32_t nb,
+                                             uint4 *__restrict__ frag) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (size_t)ntiles * KO * 64) return;
+    const uint32_t lane = (uint32_t)(g % 64), word = (uint32_t)((g / 64) % KO), tile = (uint32_t)(g / (64 * KO));
+    uint32_t lo = 0, hi = nb;   // the bucket of the tile: bt[u] <= tile < bt[u + 1]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (bt[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    const uint32_t slot = (tile - bt[lo]) * 32 + lane % 32;
+    const bool has = slot < brec[lo];
+    frag[g] = ternary_record_slice(FR, KO, nslots, has, has ? list[ro[lo] + slot] : 0u, word, lane / 32);
 }
 
 // One workgroup: 8 waves x 2 column sets x 32 candidates = 512 candidates; each
@@ -447,6 +475,90 @@ __device__ __forceinline__ uint32_t tern_bias_word(uint32_t np, int j) {
     return w;
 }
 
+// B operand of one 32-column set: operand row `r` of B (inactive columns: none).
+template <int KS, bool TERN>
+__device__ __forceinline__ void contain_operand(const uint64_t *__restrict__ B, uint32_t r, bool act, int half,
+                                                v8i_t (&b)[KS]) {
+    constexpr int RW = TERN ? 2 * KS : KS;   // words per operand row
+    const uint32_t *row = reinterpret_cast<const uint32_t *>(B + (size_t)(act ? r : 0u) * RW);
+    uint32_t tokens = 0;
+#pragma unroll
+    for (int w = 0; w < KS; ++w) {
+        if (TERN) {
+            // inactive columns: no tokens, so their result is ignored anyway
+            const uint32_t P = act ? row[2 * w + half] : 0u, V = act ? row[2 * (KS + w) + half] : 0u;
+            tokens += __popc(P);
+            b[w] = v8i_t{(int)(spread8(P) | spread8(V) * 4u), (int)(spread8(P >> 8) | spread8(V >> 8) * 4u),
+                         (int)(spread8(P >> 16) | spread8(V >> 16) * 4u), (int)(spread8(P >> 24) | spread8(V >> 24) * 4u),
+                         0, 0, 0, 0};
+        } else {
+            const uint32_t v = row[2 * w + half];   // unconditional: the loads overlap
+            // inactive columns: all tokens, so their result is ignored anyway
+            const uint32_t d = act ? v : 0xffffffffu;
+            b[w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24), 0, 0, 0, 0};
+        }
+    }
+    if (TERN) {
+        // both halves of the wave hold the same column: |P| over both; the bias
+        // slots lie in the upper half of the last word
+        const uint32_t np = tokens + (uint32_t)__shfl_xor((int)tokens, 32, 64);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[KS - 1][j] |= half ? (int)tern_bias_word(np, j) : 0;
+    }
+}
+
+// One record tile against the wave's column sets.  An accumulator ends at the
+// number of candidate tokens the record lacks (ternary: at 1 - 2 (bits in which the
+// bin indices differ), or 0 on padding).  best (see k_contain_mfma) takes the tile.
+template <int KS, bool COUNT, int FB, bool TERN>
+__device__ __forceinline__ void contain_tile(const uint4 *tf, int lane, const v8i_t (&b)[FB][KS], uint32_t (&best)[FB],
+                                             uint32_t one) {
+    v16f_t acc[FB];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) acc[f] = v16f_t{0};
+#pragma unroll
+    for (int w = 0; w < KS; ++w) {
+        const uint4 a4 = tf[w * 64 + lane];
+        const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
+#pragma unroll
+        for (int f = 0; f < FB; ++f)
+            acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
+    }
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        if (COUNT && TERN) {
+            // the records that lack the candidate: the negative values (sign bit
+            // set); 1.0 and the 0 of a padding row have it clear.  A byte permute
+            // copies the signs of two accumulators into two bytes (selectors 9 and
+            // 11 repeat bit 31 of its second and first source), and the population
+            // count adds 8 per sign.
+#pragma unroll
+            for (int r = 0; r < 16; r += 2)
+                best[f] += __builtin_popcount(__builtin_amdgcn_perm(__float_as_uint(acc[f][r]),
+                                                                    __float_as_uint(acc[f][r + 1]), 0x0c0c0b09u));
+        } else if (COUNT) {
+            // +0.0 (all bits zero) exactly when the record contains the candidate;
+            // min(bits, one) with `one` not a literal: the compiler would turn
+            // min(bits, 1) into a compare again
+            uint32_t lacking = 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) lacking += min(__float_as_uint(acc[f][r]), one);
+            best[f] += 16u - lacking;
+        } else if (TERN) {
+            // as integers the bits keep the order of 1.0 over 0 and the negatives
+            int hi = (int)best[f];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) hi = max(hi, (int)__float_as_uint(acc[f][r]));
+            best[f] = (uint32_t)hi;
+        } else {
+            uint32_t lo = best[f];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) lo = min(lo, __float_as_uint(acc[f][r]));
+            best[f] = lo;
+        }
+    }
+}
+
 // Columns: operand rows B [m][KS], expanded bit -> nibble into the B operand in
 // registers (lane % 32 = column, lane / 32 = 32-token half of each word); the A
 // side streams the record tiles.  COUNT = false (coherence, Eq. 3): out[e] = 1
@@ -477,84 +589,13 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
         e[f] = blockIdx.x * mf_cols<FB>() + wave * (FB * 32) + f * 32 + col;
-        const bool act = e[f] < m;
-        const uint32_t *row = reinterpret_cast<const uint32_t *>(B + (size_t)(act ? e[f] : 0) * RW);
+        contain_operand<KS, TERN>(B, e[f], e[f] < m, half, b[f]);
         best[f] = COUNT || TERN ? 0u : ~0u;
-        uint32_t tokens = 0;
-#pragma unroll
-        for (int w = 0; w < KS; ++w) {
-            if (TERN) {
-                // inactive columns: no tokens, so their result is ignored anyway
-                const uint32_t P = act ? row[2 * w + half] : 0u, V = act ? row[2 * (KS + w) + half] : 0u;
-                tokens += __popc(P);
-                b[f][w] = v8i_t{(int)(spread8(P) | spread8(V) * 4u), (int)(spread8(P >> 8) | spread8(V >> 8) * 4u),
-                                (int)(spread8(P >> 16) | spread8(V >> 16) * 4u),
-                                (int)(spread8(P >> 24) | spread8(V >> 24) * 4u), 0, 0, 0, 0};
-            } else {
-                const uint32_t v = row[2 * w + half];   // unconditional: the loads overlap
-                // inactive columns: all tokens, so their result is ignored anyway
-                const uint32_t d = act ? v : 0xffffffffu;
-                b[f][w] = v8i_t{(int)spread8(d), (int)spread8(d >> 8), (int)spread8(d >> 16), (int)spread8(d >> 24),
-                                0, 0, 0, 0};
-            }
-        }
-        if (TERN) {
-            // both halves of the wave hold the same column: |P| over both; the
-            // bias slots lie in the upper half of the last word
-            const uint32_t np = tokens + (uint32_t)__shfl_xor((int)tokens, 32, 64);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[f][KS - 1][j] |= half ? (int)tern_bias_word(np, j) : 0;
-        }
     }
+    const uint32_t one = m != 0u;   // 1 (the kernel runs only with columns)
     if (ntiles)
         stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, 0, ntiles, lds, [&](const uint4 *tf) __attribute__((always_inline)) {
-            // an accumulator ends at the number of candidate tokens the record lacks
-            // (ternary: at 1 - 2 (bits in which the bin indices differ), or 0 on padding)
-            v16f_t acc[FB];
-#pragma unroll
-            for (int f = 0; f < FB; ++f) acc[f] = v16f_t{0};
-#pragma unroll
-            for (int w = 0; w < KS; ++w) {
-                const uint4 a4 = tf[w * 64 + lane];
-                const v8i_t a = {(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w, 0, 0, 0, 0};
-#pragma unroll
-                for (int f = 0; f < FB; ++f)
-                    acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
-            }
-#pragma unroll
-            for (int f = 0; f < FB; ++f) {
-                if (COUNT && TERN) {
-                    // the records that lack the candidate: the negative values (sign
-                    // bit set); 1.0 and the 0 of a padding row have it clear.  A byte
-                    // permute copies the signs of two accumulators into two bytes
-                    // (selectors 9 and 11 repeat bit 31 of its second and first
-                    // source), and the population count adds 8 per sign.
-#pragma unroll
-                    for (int r = 0; r < 16; r += 2)
-                        best[f] += __builtin_popcount(__builtin_amdgcn_perm(__float_as_uint(acc[f][r]),
-                                                                            __float_as_uint(acc[f][r + 1]),
-                                                                            0x0c0c0b09u));
-                } else if (COUNT) {
-                    // +0.0 (all bits zero) exactly when the record contains the
-                    // candidate; min(bits, one) with `one` not a literal: the compiler
-                    // would turn min(bits, 1) into a compare again
-                    uint32_t lacking = 0;
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) lacking += min(__float_as_uint(acc[f][r]), (uint32_t)(m != 0u));
-                    best[f] += 16u - lacking;
-                } else if (TERN) {
-                    // as integers the bits keep the order of 1.0 over 0 and the negatives
-                    int hi = (int)best[f];
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) hi = max(hi, (int)__float_as_uint(acc[f][r]));
-                    best[f] = (uint32_t)hi;
-                } else {
-                    uint32_t lo = best[f];
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) lo = min(lo, __float_as_uint(acc[f][r]));
-                    best[f] = lo;
-                }
-            }
+            contain_tile<KS, COUNT, FB, TERN>(tf, lane, b, best, one);
         });
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
@@ -570,7 +611,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
             // last tile too: they are not records, so they come off its count.
             // (Coherence needs no such care: a real record of the tile contains
             // that row as well.  Ternary padding rows give 0, not 1.0.)
-            if (!TERN && pad && half == 0 && e[f] < m) {
+            if (pad && half == 0 && e[f] < m) {
                 uint64_t any = 0;
                 for (int w = 0; w < KS; ++w) any |= B[(size_t)e[f] * RW + w];
                 if (!any) h -= pad;
@@ -581,6 +622,62 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
             h = min(best[f], o) == 0u ? 1u : 0u;
         }
         if (half == 0 && e[f] < m) out[e[f]] = COUNT ? h : (h ? 0u : 1u);
+    }
+}
+
+// The same contraction pruned by token buckets (ternary rows only).  A record can
+// contain a candidate only when it holds every token of it, in particular the
+// candidate's bucket token u (one of its tokens, chosen by the caller); the
+// records holding u form the tiles [bt[u], bt[u + 1]) (brec[u] real rows, see
+// launch_bucket_tiles), and the candidates of bucket u are positions
+// [cs[u], cs[u + 1]) of the order perm (position -> row of B and of out).
+// Workgroup `unit` takes the candidates of bucket u with uoff[u] <= unit <
+// uoff[u + 1], block unit - uoff[u] of mf_cols<FB>() of them, against the tiles of
+// bucket u only: the results are those of k_contain_mfma against all records.
+
+template <int KS, bool COUNT, int FB>
+__global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_pruned(const uint64_t *__restrict__ B,
+                                                                                const uint4 *__restrict__ frag,
+                                                                                ContainBuckets k,
+                                                                                uint32_t *__restrict__ out) {
+    constexpr int G = mf_group<KS>();
+    __shared__ uint4 lds[ring_lds<KS * 64, G, MF_NB>()];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
+    const uint32_t unit = blockIdx.x;
+    uint32_t lo = 0, hi = k.nb;   // the bucket: the last u with uoff[u] <= unit
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (k.uoff[mid] <= unit) lo = mid;
+        else hi = mid;
+    }
+    const uint32_t u = lo;
+    const uint32_t c0 = k.cs[u] + (unit - k.uoff[u]) * mf_cols<FB>(), c1 = k.cs[u + 1];
+    const uint32_t t0 = k.bt[u], t1 = k.bt[u + 1];
+    v8i_t b[FB][KS];
+    uint32_t r[FB], best[FB];
+    bool act[FB];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        const uint32_t e = c0 + wave * (FB * 32) + f * 32 + col;
+        act[f] = e < c1;
+        r[f] = act[f] ? k.perm[e] : 0u;
+        contain_operand<KS, true>(B, r[f], act[f], half, b[f]);
+        best[f] = 0u;
+    }
+    // a wave without candidates only helps to stream the tiles (same loads and barriers)
+    if (__builtin_amdgcn_readfirstlane(c0 + wave * (FB * 32) < c1 ? 1 : 0)) {
+        stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, t0, t1, lds, [&](const uint4 *tf) __attribute__((always_inline)) {
+            contain_tile<KS, COUNT, FB, true>(tf, lane, b, best, 1u);
+        });
+    } else {
+        stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, t0, t1, lds, [&](const uint4 *) __attribute__((always_inline)) {});
+    }
+    const uint32_t nrec = k.brec[u];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)best[f], 32, 64);
+        const uint32_t h = COUNT ? nrec - (best[f] + o) / 8u : (max((int)best[f], (int)o) > 0 ? 0u : 1u);
+        if (half == 0 && act[f]) out[r[f]] = h;
     }
 }
 
@@ -631,6 +728,47 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
         default: break;
     }
 #undef IG_CM
+    IG_HIP(hipGetLastError());
+}
+
+// Column sets per wave of the pruned contraction at KO words (ternary rows).
+static int pruned_sets(int KO, int sets) {
+    int fb = sets ? std::min(sets, mf_max_sets(KO)) : (KO <= 5 ? IG_MF_SETS_NARROW : KO <= 8 ? 2 : 1);
+    fb = std::min(fb, mf_max_sets(KO));
+    if (KO == 5 && fb == 3) fb = 2;   // three spill with ternary rows at 5 words
+    return fb;
+}
+
+uint32_t contain_pruned_cols(int KO, int sets) { return (uint32_t)(MF_NT / 64 * 32 * pruned_sets(KO, sets)); }
+
+template <int V, int F>
+static void launch_cmp(bool count, const uint64_t *B, const uint4 *frag, const ContainBuckets &k, uint32_t units,
+                       uint32_t *out, hipStream_t s) {
+    if (count)
+        hipLaunchKernelGGL((k_contain_mfma_pruned<V, true, F>), dim3(units), dim3(MF_NT), 0, s, B, frag, k, out);
+    else
+        hipLaunchKernelGGL((k_contain_mfma_pruned<V, false, F>), dim3(units), dim3(MF_NT), 0, s, B, frag, k, out);
+}
+
+void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uint4 *frag, const ContainBuckets &k,
+                                uint32_t units, uint32_t *out, hipStream_t s, int sets) {
+    if (!units) return;
+    IG_REQUIRE(KO >= 1 && KO <= 16, IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
+    IG_REQUIRE(sets >= 0 && sets <= 3, IG_E_INVAL, "column sets per wave must be 0 (default) to 3");
+    IG_REQUIRE(k.nb >= 1 && k.perm && k.cs && k.uoff && k.bt && k.brec, IG_E_INVAL, "incomplete bucket tables");
+    const int fb = pruned_sets(KO, sets);
+#define IG_CMP(V)                                                                             \
+    case V:                                                                                   \
+        if (fb == 1) launch_cmp<V, 1>(count, B, frag, k, units, out, s);                      \
+        else if (fb == 2) launch_cmp<V, (mf_max_sets(V) >= 2 ? 2 : 1)>(count, B, frag, k, units, out, s); \
+        else launch_cmp<V, (mf_max_sets(V) >= 3 && V != 5 ? 3 : 1)>(count, B, frag, k, units, out, s); \
+        break;
+    switch (KO) {
+        IG_CMP(1) IG_CMP(2) IG_CMP(3) IG_CMP(4) IG_CMP(5) IG_CMP(6) IG_CMP(7) IG_CMP(8)
+        IG_CMP(9) IG_CMP(10) IG_CMP(11) IG_CMP(12) IG_CMP(13) IG_CMP(14) IG_CMP(15) IG_CMP(16)
+        default: break;
+    }
+#undef IG_CMP
     IG_HIP(hipGetLastError());
 }
 
@@ -1079,6 +1217,18 @@ void launch_mfma_records_ternary(const uint64_t *FR, uint32_t n, uint32_t KO, ui
     if (!total) return;
     hipLaunchKernelGGL(k_mfma_records_ternary, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, FR, n, KO,
                        ntiles, nslots, frag);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_mfma_records_ternary_lists(const uint64_t *FR, uint32_t KO, uint32_t T, const uint32_t *list,
+                                       const uint32_t *ro, const uint32_t *bt, const uint32_t *brec, uint32_t nb,
+                                       uint32_t ntiles, uint4 *frag, hipStream_t s) {
+    const uint32_t nslots = tern_bias_slots(T);
+    IG_REQUIRE(KO >= 1 && T + nslots <= 64 * KO && nslots <= 32, IG_E_INVAL, "ternary tokens overlap the bias slots");
+    const size_t total = (size_t)ntiles * KO * 64;
+    if (!total) return;
+    hipLaunchKernelGGL(k_mfma_records_ternary_lists, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, FR, KO,
+                       ntiles, nslots, list, ro, bt, brec, nb, frag);
     IG_HIP(hipGetLastError());
 }
 

@@ -23,6 +23,7 @@ ABSENT = 0xFFFF
 IG_MODEL_SCORE_MFMA = 1   # ModelInfo.flags: scoring runs on the matrix cores
 IG_MODEL_FACTORED = 2     # ModelInfo.flags: matrix-core operands use factored tokens
 IG_MODEL_BUCKETED = 4     # ModelInfo.flags: scoring tiles grouped by token (pruned scoring)
+IG_MODEL_FIT_BUCKETS = 8  # ModelInfo.flags: the fit's contractions used token buckets
 SCORE_MODES = {"auto": 0, "dense": 1, "pruned": 2}
 
 
@@ -50,7 +51,7 @@ class Allocator(C.Structure):
 class FitOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_uint64), ("filter_cpl", C.c_uint32), ("score_fpl", C.c_uint32),
                 ("block", C.c_uint32), ("n_tune", C.c_uint32), ("tune", C.POINTER(TuneEntry)),
-                ("coherence_mfma", C.c_uint32), ("reserved", C.c_uint32), ("alloc", C.POINTER(Allocator))]
+                ("coherence_mfma", C.c_uint32), ("fit_dense", C.c_uint32), ("alloc", C.POINTER(Allocator))]
 
 
 def torch_allocator(fail_after: Optional[int] = None) -> Allocator:
@@ -263,13 +264,15 @@ def _np_u16(a) -> np.ndarray:
 
 
 def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tune=None,
-          kernels: str = "auto", allocator=None) -> FitOpts:
+          kernels: str = "auto", allocator=None, dense: bool = False) -> FitOpts:
     """Fit options; `tune` is a list of dicts with the fields of ig_tune_entry;
     kernels = "auto" | "mfma" | "valu" | "mfma_onehot" | "mfma_presence" |
     "mfma_ternary" selects the coherence/support kernels ("mfma_onehot": matrix cores
     on the one-hot words, no factored tokens; "mfma_presence": factored tokens with
     presence tokens; "mfma_ternary": the ternary bit tokens whenever the fit has
     them; "mfma" and "auto" take whichever of the two needs fewer words);
+    dense = True tests every candidate against every record on the ternary tokens
+    instead of the records of its token bucket (same results);
     allocator = None (the library's arena), "torch" (torch's caching allocator) or an
     Allocator."""
     o = FitOpts()
@@ -277,6 +280,7 @@ def _opts(mem_budget_bytes: int = 0, filter_cpl: int = 0, score_fpl: int = 0, tu
         a = torch_allocator() if allocator == "torch" else allocator
         o.alloc = C.pointer(a)
         o._alloc = a
+    o.fit_dense = 1 if dense else 0
     o.coherence_mfma = {"auto": 0, "mfma": 1, "valu": 2, "mfma_onehot": 3, "mfma_presence": 4,
                         "mfma_ternary": 5}[kernels]
     o.mem_budget_bytes = int(mem_budget_bytes)
@@ -384,7 +388,7 @@ class Model:
 
 
 def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tune=None,
-        kernels: str = "auto", stream=None, allocator=None) -> Model:
+        kernels: str = "auto", stream=None, allocator=None, dense: bool = False) -> Model:
     """ig_fit: codes [n, d] bin codes, labels [n] (0 normal / 1 attack), nbins [d]."""
     torch = _torch()
     with _OnStream(stream) as on:
@@ -393,7 +397,7 @@ def fit(codes, labels, nbins, mem_budget_bytes: int = 0, filter_cpl: int = 0, tu
         n, d = (int(dc.shape[0]), int(dc.shape[1])) if dc.dim() == 2 else (0, 0)
         nb = _np_u16(nbins)
         h = C.c_void_p()
-        o = _opts(mem_budget_bytes, filter_cpl, tune=tune, kernels=kernels, allocator=allocator)
+        o = _opts(mem_budget_bytes, filter_cpl, tune=tune, kernels=kernels, allocator=allocator, dense=dense)
         _check(lib().ig_fit(C.c_void_p(dc.data_ptr()), C.c_void_p(dl.data_ptr()), n, d or nb.size,
                             C.c_void_p(nb.ctypes.data), C.byref(o), on.handle, C.byref(h)))
     return Model(h, getattr(o, "_alloc", None))
@@ -415,7 +419,7 @@ def fit_packed(words, labels, mem_budget_bytes: int = 0, stream=None) -> Model:
 
 
 def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, tune=None, kernels: str = "auto",
-              stream=None, allocator=None) -> List[Model]:
+              stream=None, allocator=None, dense: bool = False) -> List[Model]:
     """ig_fit_batch over problems with attributes codes, labels, nbins."""
     torch = _torch()
     keep = []
@@ -432,7 +436,7 @@ def fit_batch(problems: Sequence, mem_budget_bytes: int = 0, tune=None, kernels:
             arr[p].d = int(nb.size)
             arr[p].h_nbins = nb.ctypes.data
         outs = (C.c_void_p * len(problems))()
-        o = _opts(mem_budget_bytes, tune=tune, kernels=kernels, allocator=allocator)
+        o = _opts(mem_budget_bytes, tune=tune, kernels=kernels, allocator=allocator, dense=dense)
         _check(lib().ig_fit_batch(arr, len(problems), C.byref(o), on.handle, outs))
     keep = getattr(o, "_alloc", None)
     return [Model(C.c_void_p(outs[p]), keep) for p in range(len(problems))]

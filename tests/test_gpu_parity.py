@@ -345,6 +345,10 @@ def test_15k_workload_matches_oracle_digest():
     assert list(st.distinct) == g["stats"]["distinct"]
     assert list(st.coherent) == g["stats"]["coherent"]
     assert _model_digest(m) == g["model_sha256"]
+    assert m.info().flags & ig.IG_MODEL_FIT_BUCKETS
+    md = ig.fit(w.codes, w.labels, w.nbins, dense=True)   # every candidate against every record
+    assert not md.info().flags & ig.IG_MODEL_FIT_BUCKETS and _model_digest(md) == g["model_sha256"]
+    del md
     A, N = gpu_scores(m, w.test_codes)
     assert A[:16].tolist() == g["scores_head"]["A"] and N[:16].tolist() == g["scores_head"]["N"]
     h = hashlib.sha256()
@@ -463,9 +467,13 @@ def test_matrix_core_coherence_matches_oracle(case, kernels):
     assert_same_model(m, om, om.K)
     st = m.stats()
     assert list(st.coherent) == om.stats["coherent"] and list(st.distinct) == om.stats["distinct"]
-    for c in (0, 1):   # dense: every candidate against every other-class record
-        assert st.tests[c] == om.stats["distinct"][c] * om.stats["n_class"][1 - c]
     info = m.info()
+    for c in (0, 1):   # dense: every candidate against every other-class record
+        dense = om.stats["distinct"][c] * om.stats["n_class"][1 - c]
+        if info.flags & ig.IG_MODEL_FIT_BUCKETS:
+            assert 0 < st.tests[c] <= dense or dense == 0
+        else:
+            assert st.tests[c] == dense
     assert info.mfma_tokens <= 64 * info.mfma_words
     if info.flags & ig.IG_MODEL_FACTORED:
         assert info.mfma_words < om.K and info.mfma_tokens < p.L
@@ -550,6 +558,62 @@ def test_ternary_bias_spans_every_candidate_size(kernels):
     assert 0 < om.stats["coherent"][0] < om.stats["distinct"][0]   # some candidates are covered
 
 
+def _bucket_tests(codes, labels, nbins, om):
+    """The subset tests of the token-bucketed contractions, from their definition:
+    each distinct candidate of class c (Eq. 1: the records and the non-empty pair
+    intersections) meets the other class's records that hold its token held by the
+    fewest of them (the lowest such token on ties); each pattern of class c meets
+    its own class's records that hold its token held by the fewest of those."""
+    nb = nbins.astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(nb)[:-1]])
+    L = int(nb.sum())
+    tok = codes.astype(np.int64) + off
+    coh, sup = [], []
+    for c in (0, 1):
+        Xc, Xo = tok[labels == c], tok[labels != c]
+        cnt_o = np.bincount(Xo.ravel(), minlength=L)
+        cnt_c = np.bincount(Xc.ravel(), minlength=L)
+        cands = {tuple(r) for r in Xc}
+        for i in range(len(Xc)):
+            eq = Xc[i + 1:] == Xc[i]
+            for j in np.nonzero(eq.any(1))[0]:
+                cands.add(tuple(Xc[i][eq[j]]))
+        coh.append(sum(int(min((cnt_o[t], t) for t in b)[0]) for b in cands))
+        words = om.patterns[c]
+        total = 0
+        for row in words:
+            toks = [64 * k + b for k in range(len(row)) for b in range(64) if (int(row[k]) >> b) & 1]
+            total += int(min((cnt_c[t], t) for t in toks)[0])
+        sup.append(total)
+    return coh, sup
+
+
+# widths where the ternary view takes fewer words than the one-hot words (K >= 3)
+BUCKET_CASES = [c for c in CASES if c[0] in (8, 9, 10, 11, 12, 13)]
+
+
+@pytest.mark.parametrize("case", BUCKET_CASES, ids=[f"s{c[0]}-n{c[1]}-d{c[2]}" for c in BUCKET_CASES])
+def test_fit_token_buckets_match_dense_and_oracle(case):
+    """The bucketed coherence and support contractions (ternary tokens) give the
+    dense ones' model, the oracle's, and test exactly the pairs of each candidate
+    with the records of its bucket."""
+    seed, n, d, blo, bhi, af = case
+    p = synth.make_random_problem(seed, n, d, bins_lo=blo, bins_hi=bhi, attack_frac=af)
+    say("fit buckets", case)
+    om = oracle.fit(p.codes, p.labels, p.nbins)
+    mb = ig.fit(p.codes, p.labels, p.nbins, kernels="mfma_ternary")
+    md = ig.fit(p.codes, p.labels, p.nbins, kernels="mfma_ternary", dense=True)
+    ib, idn = mb.info(), md.info()
+    assert ib.flags & ig.IG_MODEL_FIT_BUCKETS and not idn.flags & ig.IG_MODEL_FIT_BUCKETS
+    assert_same_model(mb, om, om.K)
+    assert_same_model(md, om, om.K)
+    coh, sup = _bucket_tests(p.codes, p.labels, p.nbins, om)
+    sb, sd = mb.stats(), md.stats()
+    assert list(sb.tests) == coh and list(sb.support_tests) == sup
+    assert list(sd.tests) == [om.stats["distinct"][c] * om.stats["n_class"][1 - c] for c in (0, 1)]
+    assert list(sd.support_tests) == [om.stats["coherent"][c] * om.stats["n_class"][c] for c in (0, 1)]
+
+
 def _boundary_codes(rng, nb, n):
     """Codes that reach each feature's extreme bin indices: 0, nb - 1, every
     all-ones index 2^k - 1 below nb and its neighbours, plus a few random bins,
@@ -590,8 +654,13 @@ def test_factored_bin_boundaries(nb, n, kernels):
     st = m.stats()
     for key in ("pairs", "distinct", "coherent", "n_class"):
         assert list(getattr(st, key)) == om.stats[key], key
-    # the matrix cores test every distinct candidate against every other-class record
-    assert list(st.tests) == [om.stats["distinct"][c] * om.stats["n_class"][1 - c] for c in (0, 1)]
+    if info.flags & ig.IG_MODEL_FIT_BUCKETS:
+        # each candidate against the other-class records of its token bucket
+        coh, sup = _bucket_tests(codes, labels, nb, om)
+        assert list(st.tests) == coh and list(st.support_tests) == sup
+    else:
+        # every distinct candidate against every other-class record
+        assert list(st.tests) == [om.stats["distinct"][c] * om.stats["n_class"][1 - c] for c in (0, 1)]
     flows = _boundary_codes(rng, nb, 300)
     near = flows.copy()   # one bin bit flipped where the result stays a valid bin
     for j, b in enumerate(nb):
