@@ -535,11 +535,12 @@ static void canonical_permutation(const DevModel &m, const uint64_t *X, uint32_t
     if (pcur != perm) IG_HIP(hipMemcpyAsync(perm, pcur, count * 4, hipMemcpyDeviceToDevice, s));
 }
 
-// The records of one class listed under each token they hold (bucket L: all of
-// them), as A tiles of the pruned contractions (k_contain_mfma_pruned).
+// The records of one class listed under each token they hold, the tokens taken in
+// rank order (ascending records holding them, then token), with bucket L holding
+// every record: the A tiles of the pruned contractions (k_contain_mfma_pruned).
 struct FitBuckets {
-    std::vector<uint32_t> cnt;     // [L + 1] records per bucket (host copy)
-    Scratch<uint32_t> dcnt;        // [L] the same on the device: the buckets' costs
+    std::vector<uint32_t> cnt;     // [L + 1] records per bucket, rank order (host copy)
+    Scratch<uint16_t> rank;        // [L] rank of each token
     Scratch<uint32_t> tab;         // [L + 2] tile starts bt, then [L + 1] records brec
     Scratch<uint4> frag;
 };
@@ -552,45 +553,65 @@ struct MfmaFit {
     Scratch<uint4> frag[2];
     Scratch<uint64_t> fr[2];   // factored rows of each class's records (factored view only)
     bool pruned = false;       // token buckets: bk[t] lists class t's records
-    uint32_t L = 0;
+    uint32_t L = 0, KSr = 0;
     FitBuckets bk[2];
+    // class c's records with their tokens renumbered by the ranks of the coherence
+    // (bk[1 - c]) and the support (bk[c]) buckets
+    Scratch<uint64_t> xr_coh[2], xr_sup[2];
 };
 
 // Token buckets of class t's records for the pruned contractions (ternary view).
 static void build_fit_buckets(const DevModel &m, const ClassRows &R, const MfmaFit &mf, int t, FitBuckets &b,
                               hipStream_t s) {
-    const uint32_t L = m.L;
-    b.dcnt.reset(L, s);
-    launch_fill_u32(b.dcnt.get(), 0u, L, s);
-    launch_token_counts(R.X.get(), R.n, m.KS, L, b.dcnt.get(), s);
-    b.cnt = host_read_u32(b.dcnt.get(), L, s);
-    b.cnt.push_back(R.n);
-    // list offsets ro, tile starts bt, records per bucket brec
+    const uint32_t L = m.L, d = m.d, n = R.n;
+    const size_t nd = (size_t)n * d;
+    Scratch<uint32_t> key(std::max<size_t>(nd, 1), s), list(nd + n + 1, s), first(L + 2, s);
+    Scratch<uint32_t> ws(bucket_ws_words(nd, L), s);
+    launch_group_records(R.X.get(), n, m.KS, L, d, key.get(), list.get(), first.get(), ws.get(), s);
+    if (n) launch_iota(list.get() + nd, n, s);   // bucket L: every record
+    const std::vector<uint32_t> hf = host_read_u32(first.get(), L + 2, s);
+    // ranks: tokens by ascending records holding them, then token
+    std::vector<uint32_t> order(L);
+    for (uint32_t u = 0; u < L; ++u) order[u] = u;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return hf[x + 1] - hf[x] < hf[y + 1] - hf[y]; });
+    std::vector<uint16_t> rank(L);
+    for (uint32_t r = 0; r < L; ++r) rank[order[r]] = (uint16_t)r;
+    // per bucket (rank order): records, list offsets ro, tile starts bt, records brec
+    b.cnt.assign(L + 1, 0);
     std::vector<uint32_t> h(3 * (size_t)L + 5, 0);
     uint32_t *ro = h.data(), *bt = ro + L + 2, *brec = bt + L + 2;
+    for (uint32_t r = 0; r < L; ++r) {
+        b.cnt[r] = hf[order[r] + 1] - hf[order[r]];
+        ro[r] = hf[order[r]];
+    }
+    b.cnt[L] = n;
+    ro[L] = (uint32_t)nd;
     for (uint32_t u = 0; u <= L; ++u) {
-        ro[u + 1] = ro[u] + b.cnt[u];
         bt[u + 1] = bt[u] + (b.cnt[u] + 31) / 32;
         brec[u] = b.cnt[u];
     }
     const uint32_t ntiles = bt[L + 1];
-    Scratch<uint32_t> dro(L + 2, s), cursor(L + 1, s), list(std::max<uint32_t>(ro[L + 1], 1), s);
+    Scratch<uint32_t> dro(L + 2, s);
+    b.rank.reset(L, s);
     b.tab.reset(2 * (size_t)L + 3, s);
     IG_HIP(hipMemcpyAsync(dro.get(), ro, (L + 2) * 4, hipMemcpyHostToDevice, s));
     IG_HIP(hipMemcpyAsync(b.tab.get(), bt, (2 * (size_t)L + 3) * 4, hipMemcpyHostToDevice, s));
-    launch_bucket_records(R.X.get(), R.n, m.KS, L, dro.get(), cursor.get(), list.get(), s);
+    IG_HIP(hipMemcpyAsync(b.rank.get(), rank.data(), L * 2, hipMemcpyHostToDevice, s));
     b.frag.reset(std::max<size_t>((size_t)ntiles * mf.KO * 64, 1), s);
     launch_mfma_records_ternary_lists(mf.fr[t].get(), mf.KO, m.tern_tokens, list.get(), dro.get(), b.tab.get(),
                                       b.tab.get() + L + 2, L + 1, ntiles, b.frag.get(), s);
     IG_HIP(hipStreamSynchronize(s));   // the host tables above are freed on return
 }
 
-// Candidates (pair ids `ids` of the records X [n][KS], or rows W [m][KS] of
-// one-hot words when ids is null) whose operand rows are B, tested on the matrix
-// cores against the records of the buckets b only: out[e] as launch_contain_mfma's
-// (coherence flags, or support counts).  Returns the (candidate, record) pairs
-// tested; adds the contraction's device time to *kernel_ms.
-static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uint64_t *X, uint32_t n, uint32_t KS,
+// Candidates (pair ids `ids` of the records Xr [n][KSr], renumbered by the ranks of
+// the buckets b, or rows W [m][KS] of one-hot words when ids is null) whose
+// operand rows are B,
+// tested on the matrix cores against the records of the buckets b only: out[e]
+// as launch_contain_mfma's (coherence flags, or support counts).  Returns the
+// (candidate, record) pairs tested; adds the contraction's device time to
+// *kernel_ms.
+static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uint64_t *Xr, uint32_t n, uint32_t KS,
                                const uint32_t *ids, const uint64_t *W, size_t m, const uint64_t *B, bool count,
                                uint32_t *out, int sets, float *kernel_ms, hipStream_t s) {
     if (!m) return 0;
@@ -598,24 +619,28 @@ static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uin
     // the support count takes 8 per record lacking a candidate in 32 bits
     IG_REQUIRE(b.cnt.back() < (1u << 28), IG_E_UNSUPPORTED, "more than 2^28 records in one class");
     const uint32_t L = mf.L;
-    Scratch<uint32_t> key(m, s), hist(L + 1, s), perm(m, s), cursor(L + 1, s), tab(2 * (size_t)L + 4, s);
-    launch_cand_bucket_keys(X, n, KS, ids, W, m, L, b.dcnt.get(), key.get(), hist.get(), s);
-    const std::vector<uint32_t> h = host_read_u32(hist.get(), L + 1, s);
+    Scratch<uint32_t> key(m, s), perm(m, s), first(L + 2, s), ws(bucket_ws_words(m, L), s);
+    launch_group_candidates(Xr, n, mf.KSr, ids, W, KS, m, L, b.rank.get(), key.get(), perm.get(), first.get(),
+                            ws.get(), s);
+    const std::vector<uint32_t> hf = host_read_u32(first.get(), L + 2, s);
     const uint32_t cols = contain_pruned_cols((int)mf.KO, sets);
-    std::vector<uint32_t> t(2 * (size_t)L + 4, 0);
-    uint32_t *cs = t.data(), *uoff = cs + L + 2;
+    std::vector<uint32_t> uoff(L + 2, 0);   // then the bucket of each unit
     uint64_t tests = 0;
     for (uint32_t u = 0; u <= L; ++u) {
-        cs[u + 1] = cs[u] + h[u];
-        uoff[u + 1] = uoff[u] + (h[u] + cols - 1) / cols;
-        tests += (uint64_t)h[u] * b.cnt[u];
+        const uint32_t h = hf[u + 1] - hf[u];
+        uoff[u + 1] = uoff[u] + (h + cols - 1) / cols;
+        tests += (uint64_t)h * b.cnt[u];
     }
-    IG_HIP(hipMemcpyAsync(tab.get(), t.data(), t.size() * 4, hipMemcpyHostToDevice, s));
-    launch_bucket_place(key.get(), m, L, tab.get(), cursor.get(), perm.get(), s);
+    const uint32_t units = uoff[L + 1];
+    for (uint32_t u = 0; u <= L; ++u)
+        for (uint32_t q = uoff[u]; q < uoff[u + 1]; ++q) uoff.push_back(u);
+    Scratch<uint32_t> uo(uoff.size(), s);
+    IG_HIP(hipMemcpyAsync(uo.get(), uoff.data(), uoff.size() * 4, hipMemcpyHostToDevice, s));
     ContainBuckets k{};
     k.perm = perm.get();
-    k.cs = tab.get();
-    k.uoff = tab.get() + L + 2;
+    k.cs = first.get();
+    k.uoff = uo.get();
+    k.ub = uo.get() + L + 2;
     k.bt = b.tab.get();
     k.brec = b.tab.get() + L + 2;
     k.nb = L + 1;
@@ -630,9 +655,9 @@ static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uin
         }
     } evg{ke};
     IG_HIP(hipEventRecord(ke[0], s));
-    launch_contain_mfma_pruned((int)mf.KO, count, B, b.frag.get(), k, uoff[L + 1], out, s, sets);
+    launch_contain_mfma_pruned((int)mf.KO, count, B, b.frag.get(), k, units, out, s, sets);
     IG_HIP(hipEventRecord(ke[1], s));
-    IG_HIP(hipEventSynchronize(ke[1]));   // also: t outlives its copy
+    IG_HIP(hipEventSynchronize(ke[1]));   // also: uoff outlives its copy
     float tk = 0;
     IG_HIP(hipEventElapsedTime(&tk, ke[0], ke[1]));
     if (kernel_ms) *kernel_ms += tk;
@@ -710,8 +735,11 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
             // the patterns against the class's records that hold their bucket token
             (void)hipEventDestroy(ke[0]);
             (void)hipEventDestroy(ke[1]);
-            m.stats.support_tests[c] = pruned_contain(*pmf, pmf->bk[c], nullptr, 0, KS, nullptr, m.W[c], final_count,
-                                                      B.get(), true, m.f[c], tu.sup_sets, &tk, s);
+            // by pair ids when the rows are the ids' intersections in order, else by the rows
+            const bool by_ids = !may_repeat;
+            m.stats.support_tests[c] =
+                pruned_contain(*pmf, pmf->bk[c], pmf->xr_sup[c].get(), cls.n, KS, by_ids ? vcur : nullptr,
+                               by_ids ? nullptr : m.W[c], final_count, B.get(), true, m.f[c], tu.sup_sets, &tk, s);
             launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
         } else {
             m.stats.support_tests[c] = (uint64_t)final_count * cls.n;
@@ -936,10 +964,18 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
     }
     // token buckets (ternary view): each candidate meets the records holding its
     // rarest token only
-    mf.pruned = !dense && mf.view.ternary && m.L >= 1 && m.L <= 4096;
+    mf.pruned = !dense && mf.view.ternary && m.L >= 1 && m.L <= 4096 && m.d >= 1;
     if (mf.pruned) {
         mf.L = m.L;
+        mf.KSr = (m.L + 63) / 64;
         for (int t = 0; t < 2; ++t) build_fit_buckets(m, cls[t], mf, t, mf.bk[t], s);
+        for (int c = 0; c < 2; ++c) {
+            const size_t rows = std::max<size_t>(cls[c].n, 1) * mf.KSr;
+            mf.xr_coh[c].reset(rows, s);
+            mf.xr_sup[c].reset(rows, s);
+            launch_rank_rows(cls[c].X.get(), cls[c].n, KS, m.L, mf.bk[1 - c].rank.get(), mf.KSr, mf.xr_coh[c].get(), s);
+            launch_rank_rows(cls[c].X.get(), cls[c].n, KS, m.L, mf.bk[c].rank.get(), mf.KSr, mf.xr_sup[c].get(), s);
+        }
     }
 }
 
@@ -958,7 +994,7 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
         launch_operand_rows(cls[c].X.get(), cls[c].n, cand, nullptr, KS, ncand, mf.view, false, B.get(), s);
     if (mf.pruned) {
         // the candidates against the other class's records that hold their bucket token
-        const uint64_t t = pruned_contain(mf, mf.bk[1 - c], cls[c].X.get(), cls[c].n, KS, cand, nullptr, ncand,
+        const uint64_t t = pruned_contain(mf, mf.bk[1 - c], mf.xr_coh[c].get(), cls[c].n, KS, cand, nullptr, ncand,
                                           B.get(), false, keep.get(), sets, kernel_ms, s);
         if (tests) *tests += t;
         scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);

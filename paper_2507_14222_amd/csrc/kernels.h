@@ -208,6 +208,7 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
 // uoff[nb].  out as launch_contain_mfma's.
 struct ContainBuckets {
     const uint32_t *perm, *cs, *uoff, *bt, *brec;
+    const uint32_t *ub;         // [units]: the bucket of each workgroup
     uint32_t nb;                // buckets
 };
 uint32_t contain_pruned_cols(int KO, int sets);
@@ -248,19 +249,25 @@ struct PruneWork {
     uint32_t *cnt, *cursor, *foff, *uoff, *queue, *list;
 };
 size_t prune_scratch_words(uint32_t L, uint32_t n_flows, uint32_t d);
-// Token buckets of the fit's contractions (see prune.hip).  key[e] (<= L) = the
-// bucket of candidate e (pair id ids[e] of X, or row e of W when ids is null):
-// its token held by the fewest records (cnt [L]), L when it has none; hist [L + 1]
-// = candidates per bucket.
-void launch_cand_bucket_keys(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, const uint64_t *W,
-                             size_t m, uint32_t L, const uint32_t *cnt, uint32_t *key, uint32_t *hist, hipStream_t s);
-// perm: positions grouped by bucket, bucket u from cs[u] (cursor: L + 1 scratch).
-void launch_bucket_place(const uint32_t *key, size_t m, uint32_t L, const uint32_t *cs, uint32_t *cursor,
-                         uint32_t *perm, hipStream_t s);
-// list[ro[u] ..]: the records of X [n][KS] holding token u < L; bucket L: all of
-// them in order (cursor: L + 1 scratch).
-void launch_bucket_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, const uint32_t *ro,
-                           uint32_t *cursor, uint32_t *list, hipStream_t s);
+// Token buckets of the fit's contractions (see prune.hip).  Elements are grouped
+// by a key <= L: out (perm or list) holds them key after key, first [L + 2] the
+// first position of each key (first[L + 1] = m); ws: bucket_ws_words(m, L) u32.
+size_t bucket_ws_words(size_t m, uint32_t L);
+// Xr [n][KSr]: the tokens of each record of X [n][KS] renumbered by rank [L] (a
+// permutation of 0 .. L - 1; KSr * 64 >= L).
+void launch_rank_rows(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, const uint16_t *rank, uint32_t KSr,
+                      uint64_t *Xr, hipStream_t s);
+// Candidates grouped by bucket, the lowest renumbered token they hold: candidate e
+// is the pair id ids[e] of the renumbered records Xr [n][KSr] (their intersection),
+// or row e of W [m][KS] (one-hot words, renumbered through rank); L for a
+// candidate without a token.  perm [m]: candidate indices.
+void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const uint32_t *ids, const uint64_t *W,
+                             uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, uint32_t *key, uint32_t *perm,
+                             uint32_t *first, uint32_t *ws, hipStream_t s);
+// The records of X [n][KS] (d tokens each) under each token they hold: list
+// [n d] of record indices, key [n d] scratch; ws: bucket_ws_words(n d, L) u32.
+void launch_group_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, uint32_t d, uint32_t *key,
+                          uint32_t *list, uint32_t *first, uint32_t *ws, hipStream_t s);
 PruneWork prune_work(uint32_t *ws, uint32_t L);
 // Lists of the valid flows holding each token, work units of SC_COLS-flow blocks
 // and rt-tile ranges per (class, bucket), and out initialised ((0,0) valid,

@@ -108,122 +108,253 @@ void launch_bucket_first(const uint64_t *key, size_t m, uint32_t *first, hipStre
 }
 
 // ---------------------------------------------------- fit contractions ----
-// key[e] = the bucket of candidate e: its token with the fewest records (cnt),
-// the lowest such token on ties, or L for a candidate without a token; hist[u] +=
-// the candidates of bucket u (u <= L).  Candidate e is the pair id ids[e] of the
-// records X [n][KS] (their intersection), or row e of W [m][KS] when ids is null.
-__global__ __launch_bounds__(256) void k_cand_bucket_keys(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS,
-                                                          const uint32_t *__restrict__ ids,
-                                                          const uint64_t *__restrict__ W, size_t m, uint32_t L,
-                                                          const uint32_t *__restrict__ cnt, uint32_t *__restrict__ key,
-                                                          uint32_t *__restrict__ hist) {
-    __shared__ uint32_t h[kMaxBuckets + 1];
-    for (uint32_t u = threadIdx.x; u <= L; u += blockDim.x) h[u] = 0;
+// Elements are grouped by key with one histogram per workgroup of BK_E elements
+// (whist, key-major: [key][workgroup]), whose exclusive scan gives each
+// (key, workgroup) its first output position; k_bucket_place then puts each
+// workgroup's elements there (their order inside a key is not fixed, and no
+// result depends on it).
+constexpr uint32_t BK_T = 256, BK_I = 8, BK_E = BK_T * BK_I;
+
+__device__ __forceinline__ void bucket_hist_out(uint32_t *h, uint32_t L, uint32_t *whist, uint32_t nwg) {
     __syncthreads();
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < m) {
-        uint32_t i = 0, j = 0;
-        if (ids) decode_pair(ids[e], n, i, j);
-        uint32_t best = L, bc = ~0u;
-        for (uint32_t k = 0; k < KS; ++k) {
-            uint64_t w = ids ? (X[(size_t)i * KS + k] & X[(size_t)j * KS + k]) : W[e * KS + k];
-            while (w) {
-                const uint32_t tok = 64 * k + (uint32_t)__builtin_ctzll(w);
-                w &= w - 1;
-                if (tok >= L) break;
-                const uint32_t c = cnt[tok];
-                if (c < bc) {   // tokens come in ascending order: ties keep the lowest
-                    bc = c;
-                    best = tok;
+    for (uint32_t u = threadIdx.x; u <= L; u += BK_T) whist[(size_t)u * nwg + blockIdx.x] = h[u];
+}
+
+// Lanes of the wave whose key (< 2^13) equals this lane's, among the active ones:
+// one ballot per key bit.
+__device__ __forceinline__ uint64_t key_peers(uint32_t k, bool active) {
+    uint64_t peers = __ballot(active);
+#pragma unroll
+    for (int b = 0; b < 13; ++b) {
+        const bool bit = (k >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+__device__ __forceinline__ uint64_t lanes_below() {
+    const int lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Adds this lane's element to h[k] with one LDS atomic per distinct key of the wave
+// (the lowest lane of each key adds for all); returns the element's place among
+// the workgroup's elements of key k.  Every lane of the wave calls it.
+__device__ __forceinline__ uint32_t group_add(uint32_t *h, uint32_t k, bool active) {
+    const uint64_t peers = key_peers(k, active);
+    const uint64_t below = peers & lanes_below();
+    const int leader = peers ? __builtin_ctzll(peers) : 0;
+    uint32_t base = 0;
+    if (active && !below) base = atomicAdd(&h[k], (uint32_t)__popcll(peers));
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    return base + (uint32_t)__popcll(below);
+}
+
+// Xr [n][KSr] (zero at launch): bit rank[t] for each token t < L of record r of
+// X [n][KS] -- the records' tokens renumbered so that a lower number is a token
+// held by fewer records of the tested class.  One thread per (record, word).
+__global__ void k_rank_rows(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS, uint32_t L,
+                            const uint16_t *__restrict__ rank, uint32_t KSr, unsigned long long *__restrict__ Xr) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (size_t)n * KS) return;
+    const uint32_t r = (uint32_t)(g / KS), w = (uint32_t)(g % KS);
+    uint64_t x = X[g];
+    while (x) {
+        const uint32_t t = 64 * w + (uint32_t)__builtin_ctzll(x);
+        x &= x - 1;
+        if (t >= L) break;
+        const uint32_t q = rank[t];
+        atomicOr(&Xr[(size_t)r * KSr + (q >> 6)], 1ull << (q & 63));
+    }
+}
+
+// key[e] = the bucket of candidate e, the pair id ids[e] of records i, j: the
+// lowest renumbered token both hold in Xr (L when none: the empty set);
+// per-workgroup histogram in whist.
+__global__ __launch_bounds__(BK_T) void k_cand_keys_rank(const uint64_t *__restrict__ Xr, uint32_t n, uint32_t KSr,
+                                                         const uint32_t *__restrict__ ids, size_t m, uint32_t L,
+                                                         uint32_t *__restrict__ key, uint32_t *__restrict__ whist,
+                                                         uint32_t nwg) {
+    __shared__ uint32_t h[kMaxBuckets + 1];
+    for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * BK_E;
+#pragma unroll 2
+    for (uint32_t it = 0; it < BK_I; ++it) {
+        const size_t e = base + (size_t)it * BK_T + threadIdx.x;
+        const bool act = e < m;
+        uint32_t best = L;
+        if (act) {
+            uint32_t i, j;
+            decode_pair(ids[e], n, i, j);
+            const uint64_t *xi = Xr + (size_t)i * KSr, *xj = Xr + (size_t)j * KSr;
+            for (uint32_t w = 0; w < KSr; ++w) {
+                const uint64_t x = xi[w] & xj[w];
+                if (x) {
+                    best = 64 * w + (uint32_t)__builtin_ctzll(x);
+                    break;
                 }
             }
+            key[e] = best;
         }
-        key[e] = best;
-        atomicAdd(&h[best], 1u);
+        group_add(h, best, act);
     }
-    __syncthreads();
-    for (uint32_t u = threadIdx.x; u <= L; u += blockDim.x)
-        if (h[u]) atomicAdd(&hist[u], h[u]);
+    bucket_hist_out(h, L, whist, nwg);
 }
 
-// perm[cs[key[e]] + (place of e among its bucket's candidates)] = e.  Each
-// workgroup counts its elements per bucket, reserves a range of each bucket
-// (cursor, zero at launch), and places its elements there (the order inside a
-// bucket is not fixed; the results do not depend on it).
-constexpr uint32_t BP_T = 256, BP_I = 8;
-__global__ __launch_bounds__(BP_T) void k_bucket_place(const uint32_t *__restrict__ key, size_t m, uint32_t L,
-                                                       const uint32_t *__restrict__ cs, uint32_t *__restrict__ cursor,
-                                                       uint32_t *__restrict__ perm) {
+// The same from one-hot rows W [m][KS]: the lowest rank of the row's tokens.
+__global__ __launch_bounds__(BK_T) void k_row_keys_rank(const uint64_t *__restrict__ W, size_t m, uint32_t KS,
+                                                        uint32_t L, const uint16_t *__restrict__ rank,
+                                                        uint32_t *__restrict__ key, uint32_t *__restrict__ whist,
+                                                        uint32_t nwg) {
     __shared__ uint32_t h[kMaxBuckets + 1];
-    for (uint32_t u = threadIdx.x; u <= L; u += BP_T) h[u] = 0;
+    __shared__ uint16_t rk[kMaxBuckets];
+    for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
+    for (uint32_t u = threadIdx.x; u < L; u += BK_T) rk[u] = rank[u];
     __syncthreads();
-    const size_t base = (size_t)blockIdx.x * (BP_T * BP_I);
-    uint32_t k[BP_I], r[BP_I];
-#pragma unroll
-    for (uint32_t it = 0; it < BP_I; ++it) {
-        const size_t e = base + (size_t)it * BP_T + threadIdx.x;
-        k[it] = e < m ? key[e] : ~0u;
-        r[it] = k[it] != ~0u ? atomicAdd(&h[k[it]], 1u) : 0u;
-    }
-    __syncthreads();
-    for (uint32_t u = threadIdx.x; u <= L; u += BP_T)
-        if (h[u]) h[u] = cs[u] + atomicAdd(&cursor[u], h[u]);   // the workgroup's first slot
-    __syncthreads();
-#pragma unroll
-    for (uint32_t it = 0; it < BP_I; ++it) {
-        const size_t e = base + (size_t)it * BP_T + threadIdx.x;
-        if (k[it] != ~0u) perm[h[k[it]] + r[it]] = (uint32_t)e;
-    }
-}
-
-// The records of X [n][KS] under each token u < L they hold: list[ro[u] + slot]
-// (slots taken from cursor, zero at launch); bucket L lists every record in order.
-__global__ void k_bucket_records(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS, uint32_t L,
-                                 const uint32_t *__restrict__ ro, uint32_t *__restrict__ cursor,
-                                 uint32_t *__restrict__ list) {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    list[ro[L] + r] = r;
-    for (uint32_t k = 0; k < KS; ++k) {
-        uint64_t w = X[(size_t)r * KS + k];
-        while (w) {
-            const uint32_t tok = 64 * k + (uint32_t)__builtin_ctzll(w);
-            w &= w - 1;
-            if (tok >= L) break;
-            list[ro[tok] + atomicAdd(&cursor[tok], 1u)] = r;
+    const size_t base = (size_t)blockIdx.x * BK_E;
+    for (uint32_t it = 0; it < BK_I; ++it) {
+        const size_t e = base + (size_t)it * BK_T + threadIdx.x;
+        const bool act = e < m;
+        uint32_t best = L;
+        if (act) {
+            for (uint32_t k = 0; k < KS; ++k) {
+                uint64_t w = W[e * KS + k];
+                while (w) {
+                    const uint32_t tok = 64 * k + (uint32_t)__builtin_ctzll(w);
+                    w &= w - 1;
+                    if (tok >= L) break;
+                    best = min(best, (uint32_t)rk[tok]);
+                }
+            }
+            key[e] = best;
         }
+        group_add(h, best, act);
+    }
+    bucket_hist_out(h, L, whist, nwg);
+}
+
+// key[r * d + k] = token k (ascending) of record r of X [n][KS], d per record;
+// per-workgroup histogram in whist.
+__global__ __launch_bounds__(BK_T) void k_record_keys(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS,
+                                                      uint32_t L, uint32_t d, uint32_t *__restrict__ key,
+                                                      uint32_t *__restrict__ whist, uint32_t nwg) {
+    __shared__ uint32_t h[kMaxBuckets + 1];
+    for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * BK_E, m = (size_t)n * d;
+    for (uint32_t it = 0; it < BK_I; ++it) {
+        const size_t e = base + (size_t)it * BK_T + threadIdx.x;
+        if (e >= m) break;
+        const uint32_t r = (uint32_t)(e / d), k = (uint32_t)(e % d);
+        // the k-th set bit of the row
+        uint32_t t = L, seen = 0;
+        for (uint32_t w = 0; w < KS; ++w) {
+            const uint64_t x = X[(size_t)r * KS + w];
+            const uint32_t c = (uint32_t)__popcll(x);
+            if (k < seen + c) {
+                uint64_t y = x;
+                for (uint32_t q = seen; q < k; ++q) y &= y - 1;
+                t = 64 * w + (uint32_t)__builtin_ctzll(y);
+                break;
+            }
+            seen += c;
+        }
+        if (t > L) t = L;
+        key[e] = t;
+        atomicAdd(&h[t], 1u);
+    }
+    bucket_hist_out(h, L, whist, nwg);
+}
+
+// out[pos[key][wg] + place] = e / div for the elements e of workgroup wg (pos:
+// the exclusive scan of whist).
+__global__ __launch_bounds__(BK_T) void k_bucket_place(const uint32_t *__restrict__ key, size_t m, uint32_t L,
+                                                       const uint32_t *__restrict__ pos, uint32_t nwg, uint32_t div,
+                                                       uint32_t *__restrict__ out) {
+    __shared__ uint32_t h[kMaxBuckets + 1];
+    for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * BK_E;
+    for (uint32_t it = 0; it < BK_I; ++it) {
+        const size_t e = base + (size_t)it * BK_T + threadIdx.x;
+        const bool act = e < m;
+        const uint32_t k = act ? key[e] : L;
+        const uint32_t r = group_add(h, k, act);
+        if (act) out[pos[(size_t)k * nwg + blockIdx.x] + r] = (uint32_t)(e / div);
     }
 }
 
-void launch_cand_bucket_keys(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, const uint64_t *W,
-                             size_t m, uint32_t L, const uint32_t *cnt, uint32_t *key, uint32_t *hist, hipStream_t s) {
-    IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
-    IG_REQUIRE((ids && X) || (!ids && W), IG_E_INVAL, "candidates need pair ids and records, or rows");
-    launch_fill_u32(hist, 0u, L + 1, s);
-    if (!m) return;
-    hipLaunchKernelGGL(k_cand_bucket_keys, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, X, n, KS, ids, W, m,
-                       L, cnt, key, hist);
+// first[u] = pos[u * nwg] for u <= L, first[L + 1] = m: each key's first position.
+__global__ void k_bucket_starts(const uint32_t *__restrict__ pos, uint32_t nwg, uint32_t L, uint32_t m,
+                                uint32_t *__restrict__ first) {
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u <= L) first[u] = pos[(size_t)u * nwg];
+    if (u == L + 1) first[u] = m;
+}
+
+uint32_t bucket_groups(size_t m) { return (uint32_t)((m + BK_E - 1) / BK_E); }
+
+size_t bucket_ws_words(size_t m, uint32_t L) {
+    const size_t cells = (size_t)(L + 1) * std::max<uint32_t>(bucket_groups(m), 1);
+    return 2 * cells + scan_ws_size(cells);
+}
+
+// Groups the m keyed elements (whist filled by a key kernel over bucket_groups(m)
+// workgroups): out[...] = e / div grouped by key, first [L + 2] = each key's first
+// position.  ws: bucket_ws_words(m, L) u32.
+static void bucket_group(const uint32_t *key, size_t m, uint32_t L, uint32_t *whist, uint32_t div, uint32_t *out,
+                         uint32_t *first, uint32_t *ws, hipStream_t s) {
+    const uint32_t nwg = std::max<uint32_t>(bucket_groups(m), 1);
+    const size_t cells = (size_t)(L + 1) * nwg;
+    uint32_t *pos = ws + cells;
+    scan_exclusive_u32(whist, pos, cells, nullptr, s, ws + 2 * cells);
+    hipLaunchKernelGGL(k_bucket_starts, dim3((L + 2 + 255) / 256), dim3(256), 0, s, pos, nwg, L, (uint32_t)m, first);
+    IG_HIP(hipGetLastError());
+    if (m) hipLaunchKernelGGL(k_bucket_place, dim3(nwg), dim3(BK_T), 0, s, key, m, L, pos, nwg, div, out);
     IG_HIP(hipGetLastError());
 }
 
-void launch_bucket_place(const uint32_t *key, size_t m, uint32_t L, const uint32_t *cs, uint32_t *cursor,
-                         uint32_t *perm, hipStream_t s) {
-    IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
-    launch_fill_u32(cursor, 0u, L + 1, s);
-    if (!m) return;
-    const size_t per = (size_t)BP_T * BP_I;
-    hipLaunchKernelGGL(k_bucket_place, dim3((unsigned)((m + per - 1) / per)), dim3(BP_T), 0, s, key, m, L, cs, cursor,
-                       perm);
+void launch_rank_rows(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, const uint16_t *rank, uint32_t KSr,
+                      uint64_t *Xr, hipStream_t s) {
+    IG_REQUIRE(L >= 1 && L <= kMaxBuckets && KSr * 64 >= L, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
+    launch_fill_u64(Xr, 0ull, std::max<size_t>((size_t)n * KSr, 1), s);
+    const size_t g = (size_t)n * KS;
+    if (!g) return;
+    hipLaunchKernelGGL(k_rank_rows, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, s, X, n, KS, L, rank, KSr,
+                       reinterpret_cast<unsigned long long *>(Xr));
     IG_HIP(hipGetLastError());
 }
 
-void launch_bucket_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, const uint32_t *ro,
-                           uint32_t *cursor, uint32_t *list, hipStream_t s) {
+void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const uint32_t *ids, const uint64_t *W,
+                             uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, uint32_t *key, uint32_t *perm,
+                             uint32_t *first, uint32_t *ws, hipStream_t s) {
     IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
-    launch_fill_u32(cursor, 0u, L + 1, s);
-    if (!n) return;
-    hipLaunchKernelGGL(k_bucket_records, dim3((n + 255) / 256), dim3(256), 0, s, X, n, KS, L, ro, cursor, list);
+    IG_REQUIRE((ids && Xr) || (!ids && W && rank), IG_E_INVAL, "candidates need pair ids and ranked records, or rows");
+    const uint32_t nwg = std::max<uint32_t>(bucket_groups(m), 1);
+    uint32_t *whist = ws;
+    if (!m) {
+        launch_fill_u32(whist, 0u, (size_t)(L + 1) * nwg, s);
+    } else if (ids) {
+        hipLaunchKernelGGL(k_cand_keys_rank, dim3(nwg), dim3(BK_T), 0, s, Xr, n, KSr, ids, m, L, key, whist, nwg);
+    } else {
+        hipLaunchKernelGGL(k_row_keys_rank, dim3(nwg), dim3(BK_T), 0, s, W, m, KS, L, rank, key, whist, nwg);
+    }
     IG_HIP(hipGetLastError());
+    bucket_group(key, m, L, whist, 1, perm, first, ws, s);
+}
+
+void launch_group_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, uint32_t d, uint32_t *key,
+                          uint32_t *list, uint32_t *first, uint32_t *ws, hipStream_t s) {
+    IG_REQUIRE(L >= 1 && L <= kMaxBuckets && d >= 1, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
+    const size_t m = (size_t)n * d;
+    const uint32_t nwg = std::max<uint32_t>(bucket_groups(m), 1);
+    uint32_t *whist = ws;
+    if (!m) launch_fill_u32(whist, 0u, (size_t)(L + 1) * nwg, s);
+    else hipLaunchKernelGGL(k_record_keys, dim3(nwg), dim3(BK_T), 0, s, X, n, KS, L, d, key, whist, nwg);
+    IG_HIP(hipGetLastError());
+    bucket_group(key, m, L, whist, d, list, first, ws, s);
 }
 
 // ------------------------------------------------------------ per call ----

@@ -644,13 +644,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
     __shared__ uint4 lds[ring_lds<KS * 64, G, MF_NB>()];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     const uint32_t unit = blockIdx.x;
-    uint32_t lo = 0, hi = k.nb;   // the bucket: the last u with uoff[u] <= unit
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (k.uoff[mid] <= unit) lo = mid;
-        else hi = mid;
-    }
-    const uint32_t u = lo;
+    const uint32_t u = k.ub[unit];   // uoff[u] <= unit < uoff[u + 1]
     const uint32_t c0 = k.cs[u] + (unit - k.uoff[u]) * mf_cols<FB>(), c1 = k.cs[u + 1];
     const uint32_t t0 = k.bt[u], t1 = k.bt[u + 1];
     v8i_t b[FB][KS];
@@ -755,7 +749,8 @@ void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uin
     if (!units) return;
     IG_REQUIRE(KO >= 1 && KO <= 16, IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
     IG_REQUIRE(sets >= 0 && sets <= 3, IG_E_INVAL, "column sets per wave must be 0 (default) to 3");
-    IG_REQUIRE(k.nb >= 1 && k.perm && k.cs && k.uoff && k.bt && k.brec, IG_E_INVAL, "incomplete bucket tables");
+    IG_REQUIRE(k.nb >= 1 && k.perm && k.cs && k.uoff && k.ub && k.bt && k.brec, IG_E_INVAL,
+               "incomplete bucket tables");
     const int fb = pruned_sets(KO, sets);
 #define IG_CMP(V)                                                                             \
     case V:                                                                                   \
@@ -805,8 +800,8 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
                                                       uint32_t m, uint32_t KS, uint32_t ntiles, bool spare,
                                                       bool tern, const uint32_t *__restrict__ perm,
                                                       const uint32_t *__restrict__ bt,
-                                                      const uint32_t *__restrict__ brow, uint32_t L,
-                                                      uint4 *__restrict__ frag) {
+                                                      const uint32_t *__restrict__ brow,
+                                                      const uint32_t *__restrict__ tb, uint4 *__restrict__ frag) {
     const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;   // uniform over the wave
     const uint32_t lane = threadIdx.x & 63, half = lane >> 5, r = lane & 31;
@@ -814,55 +809,47 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
     bool in = pos < m;
     if (bt) {
         // the bucket u of the tile: bt[u] <= tile < bt[u + 1] (bt[0] = 0, bt[L] = ntiles)
-        uint32_t lo = 0, hi = L;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (bt[mid] <= tile) lo = mid;
-            else hi = mid;
-        }
-        pos = brow[lo] + (tile - bt[lo]) * 32 + r;
-        in = pos < brow[lo + 1];
+        const uint32_t u = tb[tile];
+        pos = brow[u] + (tile - bt[u]) * 32 + r;
+        in = pos < brow[u + 1];
     }
     const uint32_t row = in ? (perm ? perm[pos] : pos) : 0u;
     uint4 *dst = frag + (size_t)tile * (KS + 1) * 64;
     const uint32_t RW = tern ? 2 * KS : KS;   // words per row
-    uint64_t wv[16];
+    const uint32_t *rw = reinterpret_cast<const uint32_t *>(W + (size_t)row * RW) + half;
+    uint32_t np = 0;   // ternary: |P| of the row (both halves of the wave hold it)
+    if (tern) {
 #pragma unroll
-    for (uint32_t w = 0; w < 16; ++w) wv[w] = in && w < RW ? W[(size_t)row * RW + w] : 0ull;
-    uint4 v[8];
-    uint32_t np = 0;   // ternary: |P| of the row
+        for (uint32_t w = 0; w < 8; ++w) {
+            if (w >= KS) break;
+            np += __popc(in ? rw[2 * w] : 0u);
+        }
+        np += (uint32_t)__shfl_xor((int)np, 32, 64);
+    }
 #pragma unroll
     for (uint32_t w = 0; w < 8; ++w) {
         if (w >= KS) break;
-        const uint32_t d = (uint32_t)(wv[w] >> (32 * half));
+        const uint32_t d = in ? rw[2 * w] : 0u;
+        uint4 v;
         if (tern) {
             // the candidate side of the ternary contraction (k_contain_mfma): +1.0
-            // on P AND NOT V, -1.0 on P AND V
-            const uint32_t V = (uint32_t)(wv[(KS + w) & 15] >> (32 * half));
-            np += __popc(d);
-            v[w] = make_uint4(spread8(d) | spread8(V) * 4u, spread8(d >> 8) | spread8(V >> 8) * 4u,
-                              spread8(d >> 16) | spread8(V >> 16) * 4u, spread8(d >> 24) | spread8(V >> 24) * 4u);
+            // on P AND NOT V, -1.0 on P AND V, and the row's bias nibbles (1 - |P|;
+            // rows past m have none) in the upper half of the last word
+            const uint32_t V = in ? rw[2 * (KS + w)] : 0u;
+            v = make_uint4(spread8(d) | spread8(V) * 4u, spread8(d >> 8) | spread8(V >> 8) * 4u,
+                           spread8(d >> 16) | spread8(V >> 16) * 4u, spread8(d >> 24) | spread8(V >> 24) * 4u);
+            if (in && half && w == KS - 1) {
+                v.x |= tern_bias_word(np, 0);
+                v.y |= tern_bias_word(np, 1);
+                v.z |= tern_bias_word(np, 2);
+                v.w |= tern_bias_word(np, 3);
+            }
         } else {
-            v[w] = make_uint4(spread8(d) * 5u, spread8(d >> 8) * 5u, spread8(d >> 16) * 5u, spread8(d >> 24) * 5u);
+            v = make_uint4(spread8(d) * 5u, spread8(d >> 8) * 5u, spread8(d >> 16) * 5u, spread8(d >> 24) * 5u);
             // +1.0 (0x2) at the spare token: bit 63 of the last word = top nibble of the upper half
-            if (spare && w == KS - 1 && half) v[w].w = (v[w].w & 0x0fffffffu) | 0x20000000u;
+            if (spare && w == KS - 1 && half) v.w = (v.w & 0x0fffffffu) | 0x20000000u;
         }
-    }
-    if (tern) {
-        // the row's bias nibbles (1 - |P|; rows past m have none): both halves hold the row
-        np += (uint32_t)__shfl_xor((int)np, 32, 64);
-        if (in && half) {
-            uint4 &lw = v[(KS - 1) & 7];
-            lw.x |= tern_bias_word(np, 0);
-            lw.y |= tern_bias_word(np, 1);
-            lw.z |= tern_bias_word(np, 2);
-            lw.w |= tern_bias_word(np, 3);
-        }
-    }
-#pragma unroll
-    for (uint32_t w = 0; w < 8; ++w) {
-        if (w >= KS) break;
-        dst[w * 64 + lane] = v[w];
+        dst[w * 64 + lane] = v;
     }
     const int64_t sv = in ? S[row] : 0;
     const uint32_t s_lo = (uint32_t)sv, s_hi = (uint32_t)((uint64_t)sv >> 32);
@@ -876,6 +863,19 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
         q[j / 4] |= chunk << (8 * (j % 4));
     }
     dst[KS * 64 + lane] = make_uint4(q[0], q[1], q[2], q[3]);
+}
+
+// tb[t] = the bucket u of tile t: bt[u] <= t < bt[u + 1] (the last such u).
+__global__ void k_tile_bucket(const uint32_t *__restrict__ bt, uint32_t L, uint32_t ntiles, uint32_t *__restrict__ tb) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    uint32_t lo = 0, hi = L;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (bt[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    tb[t] = lo;
 }
 
 // Scoring workgroups: SC_NT threads, at most SC_WPS waves per SIMD (the weighting
@@ -1192,8 +1192,14 @@ void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint3
     IG_REQUIRE(KS >= 1 && KS <= 8, IG_E_UNSUPPORTED, "matrix-core scoring operands of more than 8 words");
     IG_REQUIRE(!bt || (brow && L >= 1), IG_E_INVAL, "bucket tiles without bucket rows");
     IG_REQUIRE(!(spare && tern), IG_E_INVAL, "ternary scoring operands take no spare token");
+    Scratch<uint32_t> tb;
+    if (bt) {
+        tb.reset(ntiles, s);
+        hipLaunchKernelGGL(k_tile_bucket, dim3((ntiles + 255) / 256), dim3(256), 0, s, bt, L, ntiles, tb.get());
+        IG_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_mfma_patterns, dim3((ntiles + 3) / 4), dim3(256), 0, s, W, S, m, KS, ntiles, spare, tern,
-                       perm, bt, brow, L, frag);
+                       perm, bt, brow, tb.get(), frag);
     IG_HIP(hipGetLastError());
 }
 
