@@ -61,6 +61,9 @@ struct DevModel {
     bool score_ternary = false;            // ... of the ternary view (tv)
     bool score_spare = false;              // frag carries the +1 at the spare last token
     int score_pref = -1;                   // scoring view: -1 automatic, 0 presence tokens, 1 ternary
+    // [L + 2] first pattern of each bucket when the fit grouped class c's patterns
+    // by token bucket (empty otherwise)
+    std::vector<uint32_t> sgroup[2];
     ig_stats stats{};
 
 
@@ -535,14 +538,16 @@ static void canonical_permutation(const DevModel &m, const uint64_t *X, uint32_t
     if (pcur != perm) IG_HIP(hipMemcpyAsync(perm, pcur, count * 4, hipMemcpyDeviceToDevice, s));
 }
 
-// The records of one class listed under each token they hold, the tokens taken in
-// rank order (ascending records holding them, then token), with bucket L holding
-// every record: the A tiles of the pruned contractions (k_contain_mfma_pruned).
+// The records of one class listed under each token they hold, with bucket L
+// holding every record: the A tiles of the pruned contractions
+// (k_contain_mfma_pruned).  A candidate's bucket is its token held by the fewest
+// of these records (the lowest such token on ties): the token of lowest rank.
 struct FitBuckets {
-    std::vector<uint32_t> cnt;     // [L + 1] records per bucket, rank order (host copy)
-    Scratch<uint16_t> rank;        // [L] rank of each token
+    std::vector<uint32_t> cnt;     // [L + 1] records per bucket (host copy)
+    Scratch<uint16_t> rank;        // [L] rank of each token, then [L] the token of each rank
     Scratch<uint32_t> tab;         // [L + 2] tile starts bt, then [L + 1] records brec
     Scratch<uint4> frag;
+    const uint16_t *inv() const { return rank.get() + cnt.size() - 1; }
 };
 
 struct MfmaFit {
@@ -575,15 +580,18 @@ static void build_fit_buckets(const DevModel &m, const ClassRows &R, const MfmaF
     for (uint32_t u = 0; u < L; ++u) order[u] = u;
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t x, uint32_t y) { return hf[x + 1] - hf[x] < hf[y + 1] - hf[y]; });
-    std::vector<uint16_t> rank(L);
-    for (uint32_t r = 0; r < L; ++r) rank[order[r]] = (uint16_t)r;
-    // per bucket (rank order): records, list offsets ro, tile starts bt, records brec
+    std::vector<uint16_t> rank(2 * (size_t)L);   // rank of each token, then the token of each rank
+    for (uint32_t r = 0; r < L; ++r) {
+        rank[order[r]] = (uint16_t)r;
+        rank[L + r] = (uint16_t)order[r];
+    }
+    // per bucket: records, list offsets ro, tile starts bt, records brec
     b.cnt.assign(L + 1, 0);
     std::vector<uint32_t> h(3 * (size_t)L + 5, 0);
     uint32_t *ro = h.data(), *bt = ro + L + 2, *brec = bt + L + 2;
-    for (uint32_t r = 0; r < L; ++r) {
-        b.cnt[r] = hf[order[r] + 1] - hf[order[r]];
-        ro[r] = hf[order[r]];
+    for (uint32_t u = 0; u < L; ++u) {
+        b.cnt[u] = hf[u + 1] - hf[u];
+        ro[u] = hf[u];
     }
     b.cnt[L] = n;
     ro[L] = (uint32_t)nd;
@@ -593,36 +601,51 @@ static void build_fit_buckets(const DevModel &m, const ClassRows &R, const MfmaF
     }
     const uint32_t ntiles = bt[L + 1];
     Scratch<uint32_t> dro(L + 2, s);
-    b.rank.reset(L, s);
+    b.rank.reset(2 * (size_t)L, s);
     b.tab.reset(2 * (size_t)L + 3, s);
     IG_HIP(hipMemcpyAsync(dro.get(), ro, (L + 2) * 4, hipMemcpyHostToDevice, s));
     IG_HIP(hipMemcpyAsync(b.tab.get(), bt, (2 * (size_t)L + 3) * 4, hipMemcpyHostToDevice, s));
-    IG_HIP(hipMemcpyAsync(b.rank.get(), rank.data(), L * 2, hipMemcpyHostToDevice, s));
+    IG_HIP(hipMemcpyAsync(b.rank.get(), rank.data(), 2 * (size_t)L * 2, hipMemcpyHostToDevice, s));
     b.frag.reset(std::max<size_t>((size_t)ntiles * mf.KO * 64, 1), s);
     launch_mfma_records_ternary_lists(mf.fr[t].get(), mf.KO, m.tern_tokens, list.get(), dro.get(), b.tab.get(),
                                       b.tab.get() + L + 2, L + 1, ntiles, b.frag.get(), s);
     IG_HIP(hipStreamSynchronize(s));   // the host tables above are freed on return
 }
 
-// Candidates (pair ids `ids` of the records Xr [n][KSr], renumbered by the ranks of
-// the buckets b, or rows W [m][KS] of one-hot words when ids is null) whose
-// operand rows are B,
-// tested on the matrix cores against the records of the buckets b only: out[e]
-// as launch_contain_mfma's (coherence flags, or support counts).  Returns the
-// (candidate, record) pairs tested; adds the contraction's device time to
-// *kernel_ms.
-static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uint64_t *Xr, uint32_t n, uint32_t KS,
-                               const uint32_t *ids, const uint64_t *W, size_t m, const uint64_t *B, bool count,
-                               uint32_t *out, int sets, float *kernel_ms, hipStream_t s) {
-    if (!m) return 0;
+// Candidates grouped by bucket (see launch_group_candidates): perm, first on the
+// device and first on the host.
+struct CandGroups {
+    Scratch<uint32_t> perm, first;
+    std::vector<uint32_t> hf;
+};
+
+// Groups m candidates (pair ids `ids` of the records Xr [n][KSr], renumbered by the
+// ranks of the buckets b, or rows W [m][KS] of one-hot words when ids is null) by
+// bucket.
+static void group_candidates(const MfmaFit &mf, const FitBuckets &b, const uint64_t *Xr, uint32_t n, uint32_t KS,
+                             const uint32_t *ids, const uint64_t *W, size_t m, CandGroups &g, hipStream_t s) {
     IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 candidates in one contraction");
+    const uint32_t L = mf.L;
+    Scratch<uint32_t> key(std::max<size_t>(m, 1), s), ws(bucket_ws_words(m, L), s);
+    g.perm.reset(std::max<size_t>(m, 1), s);
+    g.first.reset(L + 2, s);
+    launch_group_candidates(Xr, n, mf.KSr, ids, W, KS, m, L, b.rank.get(), b.inv(), key.get(), g.perm.get(),
+                            g.first.get(), ws.get(), s);
+    g.hf = host_read_u32(g.first.get(), L + 2, s);
+}
+
+// The grouped candidates (perm: position -> row of B and of out, null for the
+// identity; first: bucket starts, on the device and the host) whose operand rows
+// are B, tested on the matrix cores against the records of their buckets in b
+// only: out[e] as launch_contain_mfma's (coherence flags, or support counts).
+// Returns the (candidate, record) pairs tested; adds the contraction's device time
+// to *kernel_ms.
+static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uint32_t *perm, const uint32_t *first,
+                               const std::vector<uint32_t> &hf, const uint64_t *B, bool count, uint32_t *out, int sets,
+                               float *kernel_ms, hipStream_t s) {
     // the support count takes 8 per record lacking a candidate in 32 bits
     IG_REQUIRE(b.cnt.back() < (1u << 28), IG_E_UNSUPPORTED, "more than 2^28 records in one class");
     const uint32_t L = mf.L;
-    Scratch<uint32_t> key(m, s), perm(m, s), first(L + 2, s), ws(bucket_ws_words(m, L), s);
-    launch_group_candidates(Xr, n, mf.KSr, ids, W, KS, m, L, b.rank.get(), key.get(), perm.get(), first.get(),
-                            ws.get(), s);
-    const std::vector<uint32_t> hf = host_read_u32(first.get(), L + 2, s);
     const uint32_t cols = contain_pruned_cols((int)mf.KO, sets);
     std::vector<uint32_t> uoff(L + 2, 0);   // then the bucket of each unit
     uint64_t tests = 0;
@@ -632,13 +655,14 @@ static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uin
         tests += (uint64_t)h * b.cnt[u];
     }
     const uint32_t units = uoff[L + 1];
+    if (!units) return tests;
     for (uint32_t u = 0; u <= L; ++u)
         for (uint32_t q = uoff[u]; q < uoff[u + 1]; ++q) uoff.push_back(u);
     Scratch<uint32_t> uo(uoff.size(), s);
     IG_HIP(hipMemcpyAsync(uo.get(), uoff.data(), uoff.size() * 4, hipMemcpyHostToDevice, s));
     ContainBuckets k{};
-    k.perm = perm.get();
-    k.cs = first.get();
+    k.perm = perm;
+    k.cs = first;
     k.uoff = uo.get();
     k.ub = uo.get() + L + 2;
     k.bt = b.tab.get();
@@ -682,6 +706,23 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
     }
     Scratch<uint32_t> sorted_ids;
     uint32_t *vcur = ids;
+    // token buckets: the patterns grouped by support bucket before they are
+    // materialised, so that support and the scoring tiles (which take the same
+    // buckets) read them in order
+    CandGroups sg;
+    const bool grouped = pmf && pmf->pruned && own_frag && !may_repeat;
+    if (grouped) {
+        group_candidates(*pmf, pmf->bk[c], pmf->xr_sup[c].get(), cls.n, KS, ids, nullptr, count, sg, s);
+        sorted_ids.reset(count, s);
+        launch_permute_u32(ids, sg.perm.get(), count, sorted_ids.get(), s);
+        vcur = sorted_ids.get();
+        if (pre_rows) {
+            const uint32_t RWp = mfma_view.ternary ? 2 * mfma_view.KF : (mfma_view.KF ? mfma_view.KF : KS);
+            Scratch<uint64_t> B2(count * RWp, s);
+            launch_gather_rows(pre_rows->get(), sg.perm.get(), count, RWp, RWp, B2.get(), nullptr, nullptr, s);
+            *pre_rows = std::move(B2);
+        }
+    }
     if (may_repeat) {
         // the chunks' survivors may repeat a pattern: canonical order puts repeats side by side
         Scratch<uint32_t> perm(count, s);
@@ -735,12 +776,14 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
             // the patterns against the class's records that hold their bucket token
             (void)hipEventDestroy(ke[0]);
             (void)hipEventDestroy(ke[1]);
-            // by pair ids when the rows are the ids' intersections in order, else by the rows
-            const bool by_ids = !may_repeat;
-            m.stats.support_tests[c] =
-                pruned_contain(*pmf, pmf->bk[c], pmf->xr_sup[c].get(), cls.n, KS, by_ids ? vcur : nullptr,
-                               by_ids ? nullptr : m.W[c], final_count, B.get(), true, m.f[c], tu.sup_sets, &tk, s);
+            if (!grouped)   // the rows of a chunked fit, grouped here
+                group_candidates(*pmf, pmf->bk[c], nullptr, cls.n, KS, nullptr, m.W[c], final_count, sg, s);
+            m.stats.support_tests[c] = pruned_contain(*pmf, pmf->bk[c], grouped ? nullptr : sg.perm.get(),
+                                                      sg.first.get(), sg.hf, B.get(), true, m.f[c], tu.sup_sets,
+                                                      &tk, s);
             launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
+            // the scoring tiles take these buckets when the patterns are in their order
+            if (grouped) m.sgroup[c] = sg.hf;
         } else {
             m.stats.support_tests[c] = (uint64_t)final_count * cls.n;
             IG_HIP(hipEventRecord(ke[0], s));
@@ -778,23 +821,27 @@ static bool score_spare(const DevModel &m) {
 }
 
 // Costs of the tokens for the choice of each pattern's bucket token (the lowest
-// cost wins): the training records of both classes that hold the token, so that a
-// pattern is filed under the token the fewest flows are expected to hold; for a
-// model without records (imported) the tokens of features with more bins first.
+// cost wins), [2][L], one row per class: the training records of the pattern's own
+// class that hold the token (the buckets of the fit's pruned support, so that the
+// patterns it grouped keep their order; such tokens are also held by few of the
+// flows a model scores); for a model without records (imported) the tokens of
+// features with more bins first.
 static Scratch<uint32_t> token_costs(const DevModel &m, const ClassRows *cls, hipStream_t s) {
-    Scratch<uint32_t> cost(m.L, s);
+    Scratch<uint32_t> cost(2 * (size_t)m.L, s);
     if (cls) {
-        launch_fill_u32(cost.get(), 0u, m.L, s);
-        for (int c = 0; c < 2; ++c) launch_token_counts(cls[c].X.get(), cls[c].n, m.KS, m.L, cost.get(), s);
+        launch_fill_u32(cost.get(), 0u, 2 * (size_t)m.L, s);
+        for (int c = 0; c < 2; ++c)
+            launch_token_counts(cls[c].X.get(), cls[c].n, m.KS, m.L, cost.get() + (size_t)c * m.L, s);
     } else {
         std::vector<uint16_t> nb(m.d);
         IG_HIP(hipMemcpyAsync(nb.data(), m.nbins, m.d * 2, hipMemcpyDeviceToHost, s));
         IG_HIP(hipStreamSynchronize(s));
-        std::vector<uint32_t> h(m.L, 0);
+        std::vector<uint32_t> h(2 * (size_t)m.L, 0);
         uint32_t t = 0;
         for (uint32_t f = 0; f < m.d; ++f)
             for (uint32_t c = 0; c < nb[f]; ++c) h[t++] = 65536u - nb[f];
-        IG_HIP(hipMemcpyAsync(cost.get(), h.data(), m.L * 4, hipMemcpyHostToDevice, s));
+        std::copy(h.begin(), h.begin() + m.L, h.begin() + m.L);
+        IG_HIP(hipMemcpyAsync(cost.get(), h.data(), 2 * (size_t)m.L * 4, hipMemcpyHostToDevice, s));
         IG_HIP(hipStreamSynchronize(s));
     }
     return cost;
@@ -807,26 +854,38 @@ static void bucketed_operands(DevModel &m, int c, const uint64_t *rows, uint32_t
                               const uint32_t *cost, hipStream_t s) {
     const size_t np = m.np[c];
     const uint32_t L = m.L;
-    Scratch<uint64_t> key(np, s), key2(np, s);
-    Scratch<uint32_t> perm(np, s), perm2(np, s), err(1, s), first(L, s);
-    launch_fill_u32(err.get(), 0u, 1, s);
-    launch_bucket_keys(m.W[c], np, m.KS, L, cost, key.get(), err.get(), s);
-    launch_iota(perm.get(), np, s);
-    const uint32_t digits = L <= 256 ? 0x1u : 0x3u;
-    const int where = radix_sort_pairs(key.get(), perm.get(), key2.get(), perm2.get(), np, digits, s);
-    const uint64_t *sk = where ? key2.get() : key.get();
-    const uint32_t *P = where ? perm2.get() : perm.get();
-    launch_fill_u32(first.get(), ~0u, L, s);
-    launch_bucket_first(sk, np, first.get(), s);
-    std::vector<uint32_t> hf = host_read_u32(first.get(), L, s);
-    IG_REQUIRE(host_read_u32(err.get(), 1, s)[0] == 0, IG_E_DEVICE, "a pattern without a token");
-    // bucket sizes from the first positions; first tile and first position of each bucket
     std::vector<uint32_t> bt(L + 1, 0), cnt(L, 0);
-    uint32_t next = (uint32_t)np;
-    for (int u = (int)L - 1; u >= 0; --u) {
-        if (hf[u] == ~0u) continue;
-        cnt[u] = next - hf[u];
-        next = hf[u];
+    const uint32_t *P = nullptr;   // position -> row (null: the rows are in bucket order)
+    Scratch<uint64_t> key, key2;
+    Scratch<uint32_t> perm, perm2;
+    const std::vector<uint32_t> &g = m.sgroup[c];
+    if (g.size() == L + 2 && g[L] == np && g[L + 1] == np) {
+        // the fit left the patterns grouped by these buckets (none without a token)
+        for (uint32_t u = 0; u < L; ++u) cnt[u] = g[u + 1] - g[u];
+    } else {
+        key.reset(np, s);
+        key2.reset(np, s);
+        perm.reset(np, s);
+        perm2.reset(np, s);
+        Scratch<uint32_t> err(1, s), first(L, s);
+        launch_fill_u32(err.get(), 0u, 1, s);
+        launch_bucket_keys(m.W[c], np, m.KS, L, cost, key.get(), err.get(), s);
+        launch_iota(perm.get(), np, s);
+        const uint32_t digits = L <= 256 ? 0x1u : 0x3u;
+        const int where = radix_sort_pairs(key.get(), perm.get(), key2.get(), perm2.get(), np, digits, s);
+        const uint64_t *sk = where ? key2.get() : key.get();
+        P = where ? perm2.get() : perm.get();
+        launch_fill_u32(first.get(), ~0u, L, s);
+        launch_bucket_first(sk, np, first.get(), s);
+        std::vector<uint32_t> hf = host_read_u32(first.get(), L, s);
+        IG_REQUIRE(host_read_u32(err.get(), 1, s)[0] == 0, IG_E_DEVICE, "a pattern without a token");
+        // bucket sizes from the first positions
+        uint32_t next = (uint32_t)np;
+        for (int u = (int)L - 1; u >= 0; --u) {
+            if (hf[u] == ~0u) continue;
+            cnt[u] = next - hf[u];
+            next = hf[u];
+        }
     }
     std::vector<uint32_t> br(L + 1, 0);
     for (uint32_t u = 0; u < L; ++u) {
@@ -840,7 +899,8 @@ static void bucketed_operands(DevModel &m, int c, const uint64_t *rows, uint32_t
     m.brow[c] = dev_alloc<uint32_t>(L + 1);
     IG_HIP(hipMemcpyAsync(m.brow[c], br.data(), (L + 1) * 4, hipMemcpyHostToDevice, s));
     m.bperm[c] = dev_alloc<uint32_t>(np);
-    IG_HIP(hipMemcpyAsync(m.bperm[c], P, np * 4, hipMemcpyDeviceToDevice, s));
+    if (P) IG_HIP(hipMemcpyAsync(m.bperm[c], P, np * 4, hipMemcpyDeviceToDevice, s));
+    else launch_iota(m.bperm[c], np, s);
     m.ftiles[c] = ntiles;
     m.frag[c] = dev_alloc<uint4>((size_t)std::max<uint32_t>(ntiles, 1) * (KO + 1) * 64);
     launch_mfma_patterns(rows, m.S[c], (uint32_t)np, KO, spare, tern, m.frag[c], s, P, m.btile[c], m.brow[c], L,
@@ -857,7 +917,8 @@ static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr, co
     // fits from codes and imported models group their tiles by token for pruned scoring
     const bool bucketed = m.d > 0 && m.L <= 4096;
     Scratch<uint32_t> cost;
-    if (bucketed) cost = token_costs(m, cls, s);
+    const auto grouped = [&](int c) { return m.sgroup[c].size() == m.L + 2 && m.sgroup[c][m.L + 1] == m.np[c]; };
+    if (bucketed && !(grouped(0) && grouped(1))) cost = token_costs(m, cls, s);
     for (int c = 0; c < 2; ++c) {
         Scratch<uint64_t> own;
         const uint64_t *rows;
@@ -869,7 +930,7 @@ static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr, co
             rows = own.get();
         }
         if (bucketed && m.np[c]) {
-            bucketed_operands(m, c, rows, KO, spare, tern, cost.get(), s);
+            bucketed_operands(m, c, rows, KO, spare, tern, cost.get() + (size_t)c * m.L, s);
             continue;
         }
         if (bucketed) {   // an empty class: no tiles or rows in any bucket
@@ -994,8 +1055,10 @@ static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c,
         launch_operand_rows(cls[c].X.get(), cls[c].n, cand, nullptr, KS, ncand, mf.view, false, B.get(), s);
     if (mf.pruned) {
         // the candidates against the other class's records that hold their bucket token
-        const uint64_t t = pruned_contain(mf, mf.bk[1 - c], mf.xr_coh[c].get(), cls[c].n, KS, cand, nullptr, ncand,
-                                          B.get(), false, keep.get(), sets, kernel_ms, s);
+        CandGroups g;
+        group_candidates(mf, mf.bk[1 - c], mf.xr_coh[c].get(), cls[c].n, KS, cand, nullptr, ncand, g, s);
+        const uint64_t t = pruned_contain(mf, mf.bk[1 - c], g.perm.get(), g.first.get(), g.hf, B.get(), false,
+                                          keep.get(), sets, kernel_ms, s);
         if (tests) *tests += t;
         scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
         launch_compact(keep.get(), kpos.get(), cand, ncand, out, s);

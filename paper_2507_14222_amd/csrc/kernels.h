@@ -202,7 +202,7 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
 
 // The contraction pruned by token buckets (ternary rows only, see
 // k_contain_mfma_pruned): candidates of bucket u are positions [cs[u], cs[u + 1])
-// of perm (position -> row of B and of out); workgroups [uoff[u], uoff[u + 1])
+// of perm (position -> row of B and of out; null: the identity); workgroups [uoff[u], uoff[u + 1])
 // take them contain_pruned_cols(KO, sets) at a time against the record tiles
 // [bt[u], bt[u + 1]) of bucket u (brec[u] real records), u < nb.  units =
 // uoff[nb].  out as launch_contain_mfma's.
@@ -257,13 +257,13 @@ size_t bucket_ws_words(size_t m, uint32_t L);
 // permutation of 0 .. L - 1; KSr * 64 >= L).
 void launch_rank_rows(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, const uint16_t *rank, uint32_t KSr,
                       uint64_t *Xr, hipStream_t s);
-// Candidates grouped by bucket, the lowest renumbered token they hold: candidate e
-// is the pair id ids[e] of the renumbered records Xr [n][KSr] (their intersection),
-// or row e of W [m][KS] (one-hot words, renumbered through rank); L for a
-// candidate without a token.  perm [m]: candidate indices.
+// Candidates grouped by bucket, the token inv[q] of the lowest renumbered token q
+// they hold: candidate e is the pair id ids[e] of the renumbered records Xr
+// [n][KSr] (their intersection), or row e of W [m][KS] (one-hot words, renumbered
+// through rank); L for a candidate without a token.  perm [m]: candidate indices.
 void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const uint32_t *ids, const uint64_t *W,
-                             uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, uint32_t *key, uint32_t *perm,
-                             uint32_t *first, uint32_t *ws, hipStream_t s);
+                             uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, const uint16_t *inv,
+                             uint32_t *key, uint32_t *perm, uint32_t *first, uint32_t *ws, hipStream_t s);
 // The records of X [n][KS] (d tokens each) under each token they hold: list
 // [n d] of record indices, key [n d] scratch; ws: bucket_ws_words(n d, L) u32.
 void launch_group_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, uint32_t d, uint32_t *key,

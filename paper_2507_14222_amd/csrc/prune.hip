@@ -170,12 +170,12 @@ __global__ void k_rank_rows(const uint64_t *__restrict__ X, uint32_t n, uint32_t
 }
 
 // key[e] = the bucket of candidate e, the pair id ids[e] of records i, j: the
-// lowest renumbered token both hold in Xr (L when none: the empty set);
-// per-workgroup histogram in whist.
+// token inv[q] of the lowest renumbered token q both hold in Xr (L when none: the
+// empty set); per-workgroup histogram in whist.
 __global__ __launch_bounds__(BK_T) void k_cand_keys_rank(const uint64_t *__restrict__ Xr, uint32_t n, uint32_t KSr,
                                                          const uint32_t *__restrict__ ids, size_t m, uint32_t L,
-                                                         uint32_t *__restrict__ key, uint32_t *__restrict__ whist,
-                                                         uint32_t nwg) {
+                                                         const uint16_t *__restrict__ inv, uint32_t *__restrict__ key,
+                                                         uint32_t *__restrict__ whist, uint32_t nwg) {
     __shared__ uint32_t h[kMaxBuckets + 1];
     for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
     __syncthreads();
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(BK_T) void k_cand_keys_rank(const uint64_t *__restr
             for (uint32_t w = 0; w < KSr; ++w) {
                 const uint64_t x = xi[w] & xj[w];
                 if (x) {
-                    best = 64 * w + (uint32_t)__builtin_ctzll(x);
+                    best = inv[64 * w + (uint32_t)__builtin_ctzll(x)];
                     break;
                 }
             }
@@ -203,11 +203,11 @@ __global__ __launch_bounds__(BK_T) void k_cand_keys_rank(const uint64_t *__restr
     bucket_hist_out(h, L, whist, nwg);
 }
 
-// The same from one-hot rows W [m][KS]: the lowest rank of the row's tokens.
+// The same from one-hot rows W [m][KS]: the row's token of the lowest rank.
 __global__ __launch_bounds__(BK_T) void k_row_keys_rank(const uint64_t *__restrict__ W, size_t m, uint32_t KS,
                                                         uint32_t L, const uint16_t *__restrict__ rank,
-                                                        uint32_t *__restrict__ key, uint32_t *__restrict__ whist,
-                                                        uint32_t nwg) {
+                                                        const uint16_t *__restrict__ inv, uint32_t *__restrict__ key,
+                                                        uint32_t *__restrict__ whist, uint32_t nwg) {
     __shared__ uint32_t h[kMaxBuckets + 1];
     __shared__ uint16_t rk[kMaxBuckets];
     for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
@@ -228,6 +228,7 @@ __global__ __launch_bounds__(BK_T) void k_row_keys_rank(const uint64_t *__restri
                     best = min(best, (uint32_t)rk[tok]);
                 }
             }
+            if (best < L) best = inv[best];
             key[e] = best;
         }
         group_add(h, best, act);
@@ -328,18 +329,20 @@ void launch_rank_rows(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, co
 }
 
 void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const uint32_t *ids, const uint64_t *W,
-                             uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, uint32_t *key, uint32_t *perm,
-                             uint32_t *first, uint32_t *ws, hipStream_t s) {
+                             uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, const uint16_t *inv,
+                             uint32_t *key, uint32_t *perm, uint32_t *first, uint32_t *ws, hipStream_t s) {
     IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
-    IG_REQUIRE((ids && Xr) || (!ids && W && rank), IG_E_INVAL, "candidates need pair ids and ranked records, or rows");
+    IG_REQUIRE(inv && ((ids && Xr) || (!ids && W && rank)), IG_E_INVAL,
+               "candidates need pair ids and ranked records, or rows");
     const uint32_t nwg = std::max<uint32_t>(bucket_groups(m), 1);
     uint32_t *whist = ws;
     if (!m) {
         launch_fill_u32(whist, 0u, (size_t)(L + 1) * nwg, s);
     } else if (ids) {
-        hipLaunchKernelGGL(k_cand_keys_rank, dim3(nwg), dim3(BK_T), 0, s, Xr, n, KSr, ids, m, L, key, whist, nwg);
+        hipLaunchKernelGGL(k_cand_keys_rank, dim3(nwg), dim3(BK_T), 0, s, Xr, n, KSr, ids, m, L, inv, key, whist,
+                           nwg);
     } else {
-        hipLaunchKernelGGL(k_row_keys_rank, dim3(nwg), dim3(BK_T), 0, s, W, m, KS, L, rank, key, whist, nwg);
+        hipLaunchKernelGGL(k_row_keys_rank, dim3(nwg), dim3(BK_T), 0, s, W, m, KS, L, rank, inv, key, whist, nwg);
     }
     IG_HIP(hipGetLastError());
     bucket_group(key, m, L, whist, 1, perm, first, ws, s);

@@ -654,7 +654,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
     for (int f = 0; f < FB; ++f) {
         const uint32_t e = c0 + wave * (FB * 32) + f * 32 + col;
         act[f] = e < c1;
-        r[f] = act[f] ? k.perm[e] : 0u;
+        r[f] = act[f] ? (k.perm ? k.perm[e] : e) : 0u;
         contain_operand<KS, true>(B, r[f], act[f], half, b[f]);
         best[f] = 0u;
     }
@@ -749,7 +749,7 @@ void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uin
     if (!units) return;
     IG_REQUIRE(KO >= 1 && KO <= 16, IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
     IG_REQUIRE(sets >= 0 && sets <= 3, IG_E_INVAL, "column sets per wave must be 0 (default) to 3");
-    IG_REQUIRE(k.nb >= 1 && k.perm && k.cs && k.uoff && k.ub && k.bt && k.brec, IG_E_INVAL,
+    IG_REQUIRE(k.nb >= 1 && k.cs && k.uoff && k.ub && k.bt && k.brec, IG_E_INVAL,
                "incomplete bucket tables");
     const int fb = pruned_sets(KO, sets);
 #define IG_CMP(V)                                                                             \

@@ -154,16 +154,17 @@ def _token_counts(codes, nbins):
     return cnt
 
 
-def test_bucket_of_each_pattern_is_its_rarest_token():
-    """Every pattern is filed under its token held by the fewest training records
-    (lowest token on ties): the bucket sizes equal a histogram of that rule over the
-    exported patterns."""
+@pytest.mark.parametrize("kernels,dense", [("auto", False), ("auto", True), ("valu", False)])
+def test_bucket_of_each_pattern_is_its_rarest_token(kernels, dense):
+    """Every pattern is filed under its token held by the fewest training records of
+    its own class (lowest token on ties), whichever path fitted it: the bucket sizes
+    equal a histogram of that rule over the exported patterns."""
     p = synth.make_random_problem(11, 170, 41, bins_lo=10, bins_hi=14, attack_frac=0.55)
-    m = ig.fit(p.codes, p.labels, p.nbins)
+    m = ig.fit(p.codes, p.labels, p.nbins, kernels=kernels, dense=dense)
     assert m.bucketed
-    cost = _token_counts(p.codes, p.nbins)
-    L = int(cost.size)
     for c in (0, 1):
+        cost = _token_counts(p.codes[p.labels == c], p.nbins)
+        L = int(cost.size)
         w, _, _ = m.export(c)
         bits = np.unpackbits(w.view(np.uint8), axis=1, bitorder="little")[:, :L].astype(bool)
         keyed = np.where(bits, cost[None, :], np.iinfo(np.int64).max)
