@@ -538,6 +538,46 @@ static void canonical_permutation(const DevModel &m, const uint64_t *X, uint32_t
     if (pcur != perm) IG_HIP(hipMemcpyAsync(perm, pcur, count * 4, hipMemcpyDeviceToDevice, s));
 }
 
+// Device times of launches, from event pairs read once the stream has passed
+// them (collect), instead of a synchronisation per launch; host tables whose
+// asynchronous copies precede those launches are kept until then.
+struct KernelClock {
+    struct Item {
+        hipEvent_t a = nullptr, b = nullptr;
+        float *to = nullptr;
+    };
+    std::vector<Item> items;
+    std::vector<std::vector<uint32_t>> keep;
+    Item &open(hipStream_t s, float *to) {
+        items.emplace_back();
+        Item &it = items.back();
+        it.to = to;
+        IG_HIP(hipEventCreate(&it.a));
+        IG_HIP(hipEventCreate(&it.b));
+        IG_HIP(hipEventRecord(it.a, s));
+        return it;
+    }
+    void close(Item &it, hipStream_t s) { IG_HIP(hipEventRecord(it.b, s)); }
+    void collect() {
+        for (Item &it : items) {
+            float ms = 0;
+            if (hipEventSynchronize(it.b) == hipSuccess && hipEventElapsedTime(&ms, it.a, it.b) == hipSuccess &&
+                it.to)
+                *it.to += ms;
+        }
+        release();
+    }
+    void release() {
+        for (Item &it : items) {
+            if (it.a) (void)hipEventDestroy(it.a);
+            if (it.b) (void)hipEventDestroy(it.b);
+        }
+        items.clear();
+        keep.clear();
+    }
+    ~KernelClock() { release(); }
+};
+
 // The records of one class listed under each token they hold, with bucket L
 // holding every record: the A tiles of the pruned contractions
 // (k_contain_mfma_pruned).  A candidate's bucket is its token held by the fewest
@@ -563,53 +603,73 @@ struct MfmaFit {
     // class c's records with their tokens renumbered by the ranks of the coherence
     // (bk[1 - c]) and the support (bk[c]) buckets
     Scratch<uint64_t> xr_coh[2], xr_sup[2];
+    KernelClock clock;         // device times of the pruned contractions
 };
 
-// Token buckets of class t's records for the pruned contractions (ternary view).
-static void build_fit_buckets(const DevModel &m, const ClassRows &R, const MfmaFit &mf, int t, FitBuckets &b,
-                              hipStream_t s) {
-    const uint32_t L = m.L, d = m.d, n = R.n;
-    const size_t nd = (size_t)n * d;
-    Scratch<uint32_t> key(std::max<size_t>(nd, 1), s), list(nd + n + 1, s), first(L + 2, s);
-    Scratch<uint32_t> ws(bucket_ws_words(nd, L), s);
-    launch_group_records(R.X.get(), n, m.KS, L, d, key.get(), list.get(), first.get(), ws.get(), s);
-    if (n) launch_iota(list.get() + nd, n, s);   // bucket L: every record
-    const std::vector<uint32_t> hf = host_read_u32(first.get(), L + 2, s);
-    // ranks: tokens by ascending records holding them, then token
-    std::vector<uint32_t> order(L);
-    for (uint32_t u = 0; u < L; ++u) order[u] = u;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t x, uint32_t y) { return hf[x + 1] - hf[x] < hf[y + 1] - hf[y]; });
-    std::vector<uint16_t> rank(2 * (size_t)L);   // rank of each token, then the token of each rank
-    for (uint32_t r = 0; r < L; ++r) {
-        rank[order[r]] = (uint16_t)r;
-        rank[L + r] = (uint16_t)order[r];
+// Token buckets of both classes' records for the pruned contractions (ternary
+// view), with one host round trip for both.
+static void build_fit_buckets(const DevModel &m, const ClassRows cls[2], MfmaFit &mf, hipStream_t s) {
+    const uint32_t L = m.L, d = m.d;
+    Scratch<uint32_t> key[2], list[2], first(2 * ((size_t)L + 2), s);
+    for (int t = 0; t < 2; ++t) {
+        const uint32_t n = cls[t].n;
+        const size_t nd = (size_t)n * d;
+        key[t].reset(std::max<size_t>(nd, 1), s);
+        list[t].reset(nd + n + 1, s);
+        Scratch<uint32_t> ws(bucket_ws_words(nd, L), s);
+        launch_group_records(cls[t].X.get(), n, m.KS, L, d, key[t].get(), list[t].get(), first.get() + t * (L + 2),
+                             ws.get(), s);
+        if (n) launch_iota(list[t].get() + nd, n, s);   // bucket L: every record
     }
-    // per bucket: records, list offsets ro, tile starts bt, records brec
-    b.cnt.assign(L + 1, 0);
-    std::vector<uint32_t> h(3 * (size_t)L + 5, 0);
-    uint32_t *ro = h.data(), *bt = ro + L + 2, *brec = bt + L + 2;
-    for (uint32_t u = 0; u < L; ++u) {
-        b.cnt[u] = hf[u + 1] - hf[u];
-        ro[u] = hf[u];
+    const std::vector<uint32_t> hf = host_read_u32(first.get(), 2 * ((size_t)L + 2), s);
+    // per class: ranks and their tokens (u16 pairs), then list offsets ro [L + 2],
+    // tile starts bt [L + 2] and records brec [L + 1]
+    const size_t per = (size_t)L + (3 * (size_t)L + 5);
+    std::vector<uint32_t> up(2 * per, 0);
+    uint32_t ntiles[2];
+    for (int t = 0; t < 2; ++t) {
+        FitBuckets &b = mf.bk[t];
+        const uint32_t *h = hf.data() + t * (L + 2);
+        const uint32_t n = cls[t].n;
+        const size_t nd = (size_t)n * d;
+        // ranks: tokens by ascending records holding them, then token
+        std::vector<uint32_t> order(L);
+        for (uint32_t u = 0; u < L; ++u) order[u] = u;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t x, uint32_t y) { return h[x + 1] - h[x] < h[y + 1] - h[y]; });
+        uint16_t *rank = reinterpret_cast<uint16_t *>(up.data() + t * per);
+        for (uint32_t r = 0; r < L; ++r) {
+            rank[order[r]] = (uint16_t)r;
+            rank[L + r] = (uint16_t)order[r];
+        }
+        uint32_t *ro = up.data() + t * per + L, *bt = ro + L + 2, *brec = bt + L + 2;
+        b.cnt.assign(L + 1, 0);
+        for (uint32_t u = 0; u < L; ++u) {
+            b.cnt[u] = h[u + 1] - h[u];
+            ro[u] = h[u];
+        }
+        b.cnt[L] = n;
+        ro[L] = (uint32_t)nd;
+        for (uint32_t u = 0; u <= L; ++u) {
+            bt[u + 1] = bt[u] + (b.cnt[u] + 31) / 32;
+            brec[u] = b.cnt[u];
+        }
+        ntiles[t] = bt[L + 1];
     }
-    b.cnt[L] = n;
-    ro[L] = (uint32_t)nd;
-    for (uint32_t u = 0; u <= L; ++u) {
-        bt[u + 1] = bt[u] + (b.cnt[u] + 31) / 32;
-        brec[u] = b.cnt[u];
+    Scratch<uint32_t> dup(up.size(), s);
+    IG_HIP(hipMemcpyAsync(dup.get(), up.data(), up.size() * 4, hipMemcpyHostToDevice, s));
+    for (int t = 0; t < 2; ++t) {
+        FitBuckets &b = mf.bk[t];
+        const uint32_t *base = dup.get() + t * per;
+        b.rank.reset(2 * (size_t)L, s);
+        b.tab.reset(2 * (size_t)L + 3, s);
+        IG_HIP(hipMemcpyAsync(b.rank.get(), base, 2 * (size_t)L * 2, hipMemcpyDeviceToDevice, s));
+        IG_HIP(hipMemcpyAsync(b.tab.get(), base + L + L + 2, (2 * (size_t)L + 3) * 4, hipMemcpyDeviceToDevice, s));
+        b.frag.reset(std::max<size_t>((size_t)ntiles[t] * mf.KO * 64, 1), s);
+        launch_mfma_records_ternary_lists(mf.fr[t].get(), mf.KO, m.tern_tokens, list[t].get(), base + L, b.tab.get(),
+                                          b.tab.get() + L + 2, L + 1, ntiles[t], b.frag.get(), s);
     }
-    const uint32_t ntiles = bt[L + 1];
-    Scratch<uint32_t> dro(L + 2, s);
-    b.rank.reset(2 * (size_t)L, s);
-    b.tab.reset(2 * (size_t)L + 3, s);
-    IG_HIP(hipMemcpyAsync(dro.get(), ro, (L + 2) * 4, hipMemcpyHostToDevice, s));
-    IG_HIP(hipMemcpyAsync(b.tab.get(), bt, (2 * (size_t)L + 3) * 4, hipMemcpyHostToDevice, s));
-    IG_HIP(hipMemcpyAsync(b.rank.get(), rank.data(), 2 * (size_t)L * 2, hipMemcpyHostToDevice, s));
-    b.frag.reset(std::max<size_t>((size_t)ntiles * mf.KO * 64, 1), s);
-    launch_mfma_records_ternary_lists(mf.fr[t].get(), mf.KO, m.tern_tokens, list.get(), dro.get(), b.tab.get(),
-                                      b.tab.get() + L + 2, L + 1, ntiles, b.frag.get(), s);
-    IG_HIP(hipStreamSynchronize(s));   // the host tables above are freed on return
+    mf.clock.keep.push_back(std::move(up));   // until its copy has run
 }
 
 // Candidates grouped by bucket (see launch_group_candidates): perm, first on the
@@ -623,14 +683,15 @@ struct CandGroups {
 // ranks of the buckets b, or rows W [m][KS] of one-hot words when ids is null) by
 // bucket.
 static void group_candidates(const MfmaFit &mf, const FitBuckets &b, const uint64_t *Xr, uint32_t n, uint32_t KS,
-                             const uint32_t *ids, const uint64_t *W, size_t m, CandGroups &g, hipStream_t s) {
+                             const uint32_t *ids, const uint64_t *W, size_t m, CandGroups &g, hipStream_t s,
+                             uint32_t *ids_out = nullptr) {
     IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 candidates in one contraction");
     const uint32_t L = mf.L;
     Scratch<uint32_t> key(std::max<size_t>(m, 1), s), ws(bucket_ws_words(m, L), s);
     g.perm.reset(std::max<size_t>(m, 1), s);
     g.first.reset(L + 2, s);
     launch_group_candidates(Xr, n, mf.KSr, ids, W, KS, m, L, b.rank.get(), b.inv(), key.get(), g.perm.get(),
-                            g.first.get(), ws.get(), s);
+                            g.first.get(), ws.get(), s, ids_out);
     g.hf = host_read_u32(g.first.get(), L + 2, s);
 }
 
@@ -640,7 +701,7 @@ static void group_candidates(const MfmaFit &mf, const FitBuckets &b, const uint6
 // only: out[e] as launch_contain_mfma's (coherence flags, or support counts).
 // Returns the (candidate, record) pairs tested; adds the contraction's device time
 // to *kernel_ms.
-static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uint32_t *perm, const uint32_t *first,
+static uint64_t pruned_contain(MfmaFit &mf, const FitBuckets &b, const uint32_t *perm, const uint32_t *first,
                                const std::vector<uint32_t> &hf, const uint64_t *B, bool count, uint32_t *out, int sets,
                                float *kernel_ms, hipStream_t s) {
     // the support count takes 8 per record lacking a candidate in 32 bits
@@ -668,23 +729,10 @@ static uint64_t pruned_contain(const MfmaFit &mf, const FitBuckets &b, const uin
     k.bt = b.tab.get();
     k.brec = b.tab.get() + L + 2;
     k.nb = L + 1;
-    hipEvent_t ke[2];
-    IG_HIP(hipEventCreate(&ke[0]));
-    IG_HIP(hipEventCreate(&ke[1]));
-    struct Ev {
-        hipEvent_t *e;
-        ~Ev() {
-            (void)hipEventDestroy(e[0]);
-            (void)hipEventDestroy(e[1]);
-        }
-    } evg{ke};
-    IG_HIP(hipEventRecord(ke[0], s));
+    KernelClock::Item &it = mf.clock.open(s, kernel_ms);
     launch_contain_mfma_pruned((int)mf.KO, count, B, b.frag.get(), k, units, out, s, sets);
-    IG_HIP(hipEventRecord(ke[1], s));
-    IG_HIP(hipEventSynchronize(ke[1]));   // also: uoff outlives its copy
-    float tk = 0;
-    IG_HIP(hipEventElapsedTime(&tk, ke[0], ke[1]));
-    if (kernel_ms) *kernel_ms += tk;
+    mf.clock.close(it, s);
+    mf.clock.keep.push_back(std::move(uoff));   // until its copy has run
     return tests;
 }
 
@@ -695,7 +743,7 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
                             bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
                             int support_mark = -1, const uint4 *own_frag = nullptr,
                             const FactorView &mfma_view = FactorView{}, PatternRows *keep = nullptr,
-                            Scratch<uint64_t> *pre_rows = nullptr, const MfmaFit *pmf = nullptr) {
+                            Scratch<uint64_t> *pre_rows = nullptr, MfmaFit *pmf = nullptr) {
     const uint32_t KS = m.KS;
     if (count == 0) {
         m.np[c] = 0;
@@ -712,9 +760,9 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
     CandGroups sg;
     const bool grouped = pmf && pmf->pruned && own_frag && !may_repeat;
     if (grouped) {
-        group_candidates(*pmf, pmf->bk[c], pmf->xr_sup[c].get(), cls.n, KS, ids, nullptr, count, sg, s);
         sorted_ids.reset(count, s);
-        launch_permute_u32(ids, sg.perm.get(), count, sorted_ids.get(), s);
+        group_candidates(*pmf, pmf->bk[c], pmf->xr_sup[c].get(), cls.n, KS, ids, nullptr, count, sg, s,
+                         sorted_ids.get());
         vcur = sorted_ids.get();
         if (pre_rows) {
             const uint32_t RWp = mfma_view.ternary ? 2 * mfma_view.KF : (mfma_view.KF ? mfma_view.KF : KS);
@@ -780,7 +828,7 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
                 group_candidates(*pmf, pmf->bk[c], nullptr, cls.n, KS, nullptr, m.W[c], final_count, sg, s);
             m.stats.support_tests[c] = pruned_contain(*pmf, pmf->bk[c], grouped ? nullptr : sg.perm.get(),
                                                       sg.first.get(), sg.hf, B.get(), true, m.f[c], tu.sup_sets,
-                                                      &tk, s);
+                                                      &m.stats.kernel_ms[1], s);
             launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
             // the scoring tiles take these buckets when the patterns are in their order
             if (grouped) m.sgroup[c] = sg.hf;
@@ -1029,7 +1077,7 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
     if (mf.pruned) {
         mf.L = m.L;
         mf.KSr = (m.L + 63) / 64;
-        for (int t = 0; t < 2; ++t) build_fit_buckets(m, cls[t], mf, t, mf.bk[t], s);
+        build_fit_buckets(m, cls, mf, s);
         for (int c = 0; c < 2; ++c) {
             const size_t rows = std::max<size_t>(cls[c].n, 1) * mf.KSr;
             mf.xr_coh[c].reset(rows, s);
@@ -1043,7 +1091,7 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
 // Coherence of class c's ncand candidate pair ids `cand` on the matrix cores
 // (Eq. 3, dense): appends the coherent ids to `out` and returns how many
 // (synchronises the stream); adds the contraction's device time to *kernel_ms.
-static uint32_t mfma_coherence(const MfmaFit &mf, const ClassRows cls[2], int c, uint32_t KS, const uint32_t *cand,
+static uint32_t mfma_coherence(MfmaFit &mf, const ClassRows cls[2], int c, uint32_t KS, const uint32_t *cand,
                                uint32_t ncand, uint32_t *out, float *kernel_ms, hipStream_t s,
                                uint64_t *rows_out = nullptr, int sets = 0, uint64_t *tests = nullptr) {
     if (!ncand) return 0;
@@ -1338,6 +1386,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     finish_weights(m, s, &prow, cls);
     tm.mark(7);
     IG_HIP(hipStreamSynchronize(s));
+    mf.clock.collect();
     m.stats.ms[1] = ms_pairs;
     m.stats.ms[2] = ms_sort;
     m.stats.ms[3] = ms_dedup;
@@ -1699,6 +1748,7 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
         const double share = group_pairs ? (double)G[g]->pairs() / (double)group_pairs : 0.0;
         m.stats.ms[4] = (float)(graph_ms * share) + mfma_ms[g];
         m.stats.ms[1] = m.stats.ms[2] = m.stats.ms[3] = 0.0f;
+        mf[g].clock.collect();
         m.stats.kernel_ms[0] = mfma_kernel[g];
     }
 }

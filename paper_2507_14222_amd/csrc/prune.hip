@@ -270,10 +270,11 @@ __global__ __launch_bounds__(BK_T) void k_record_keys(const uint64_t *__restrict
 }
 
 // out[pos[key][wg] + place] = e / div for the elements e of workgroup wg (pos:
-// the exclusive scan of whist).
+// the exclusive scan of whist), and out2 there = src[e] when src is given.
 __global__ __launch_bounds__(BK_T) void k_bucket_place(const uint32_t *__restrict__ key, size_t m, uint32_t L,
                                                        const uint32_t *__restrict__ pos, uint32_t nwg, uint32_t div,
-                                                       uint32_t *__restrict__ out) {
+                                                       uint32_t *__restrict__ out, const uint32_t *__restrict__ src,
+                                                       uint32_t *__restrict__ out2) {
     __shared__ uint32_t h[kMaxBuckets + 1];
     for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
     __syncthreads();
@@ -283,7 +284,11 @@ __global__ __launch_bounds__(BK_T) void k_bucket_place(const uint32_t *__restric
         const bool act = e < m;
         const uint32_t k = act ? key[e] : L;
         const uint32_t r = group_add(h, k, act);
-        if (act) out[pos[(size_t)k * nwg + blockIdx.x] + r] = (uint32_t)(e / div);
+        if (act) {
+            const size_t p = pos[(size_t)k * nwg + blockIdx.x] + r;
+            out[p] = (uint32_t)(e / div);
+            if (src) out2[p] = src[e];
+        }
     }
 }
 
@@ -306,14 +311,15 @@ size_t bucket_ws_words(size_t m, uint32_t L) {
 // workgroups): out[...] = e / div grouped by key, first [L + 2] = each key's first
 // position.  ws: bucket_ws_words(m, L) u32.
 static void bucket_group(const uint32_t *key, size_t m, uint32_t L, uint32_t *whist, uint32_t div, uint32_t *out,
-                         uint32_t *first, uint32_t *ws, hipStream_t s) {
+                         uint32_t *first, uint32_t *ws, hipStream_t s, const uint32_t *src = nullptr,
+                         uint32_t *out2 = nullptr) {
     const uint32_t nwg = std::max<uint32_t>(bucket_groups(m), 1);
     const size_t cells = (size_t)(L + 1) * nwg;
     uint32_t *pos = ws + cells;
     scan_exclusive_u32(whist, pos, cells, nullptr, s, ws + 2 * cells);
     hipLaunchKernelGGL(k_bucket_starts, dim3((L + 2 + 255) / 256), dim3(256), 0, s, pos, nwg, L, (uint32_t)m, first);
     IG_HIP(hipGetLastError());
-    if (m) hipLaunchKernelGGL(k_bucket_place, dim3(nwg), dim3(BK_T), 0, s, key, m, L, pos, nwg, div, out);
+    if (m) hipLaunchKernelGGL(k_bucket_place, dim3(nwg), dim3(BK_T), 0, s, key, m, L, pos, nwg, div, out, src, out2);
     IG_HIP(hipGetLastError());
 }
 
@@ -330,7 +336,8 @@ void launch_rank_rows(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, co
 
 void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const uint32_t *ids, const uint64_t *W,
                              uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, const uint16_t *inv,
-                             uint32_t *key, uint32_t *perm, uint32_t *first, uint32_t *ws, hipStream_t s) {
+                             uint32_t *key, uint32_t *perm, uint32_t *first, uint32_t *ws, hipStream_t s,
+                             uint32_t *ids_out) {
     IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
     IG_REQUIRE(inv && ((ids && Xr) || (!ids && W && rank)), IG_E_INVAL,
                "candidates need pair ids and ranked records, or rows");
@@ -345,7 +352,7 @@ void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const
         hipLaunchKernelGGL(k_row_keys_rank, dim3(nwg), dim3(BK_T), 0, s, W, m, KS, L, rank, inv, key, whist, nwg);
     }
     IG_HIP(hipGetLastError());
-    bucket_group(key, m, L, whist, 1, perm, first, ws, s);
+    bucket_group(key, m, L, whist, 1, perm, first, ws, s, ids_out ? ids : nullptr, ids_out);
 }
 
 void launch_group_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, uint32_t d, uint32_t *key,
