@@ -1235,26 +1235,49 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     for (auto &ch : chunks) {
         uint64_t items = 0;
         for (auto &p : ch) items += p.cnt;
-        Scratch<uint64_t> k0(items, s), k1(items, s);
-        Scratch<uint32_t> v0(items, s), v1(items, s);
-        IG_HIP(hipEventRecord(e[0], s));
-        uint64_t at = 0;
-        for (auto &p : ch) {
-            launch_pair_hash(cls[p.c].X.get(), cls[p.c].n, KS, K, p.q0, p.cnt, (uint32_t)p.c, 1, k0.get() + at,
-                             v0.get() + at, s, kPairKeyBytes);
-            at += p.cnt;
-        }
-        IG_HIP(hipEventRecord(e[1], s));
-        int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items,
-                                     0xffu & ~((1u << (8 - kPairKeyBytes)) - 1), s);
-        uint64_t *ks = where ? k1.get() : k0.get();
-        uint32_t *vs = where ? v1.get() : v0.get();
-        IG_HIP(hipEventRecord(e[2], s));
         Scratch<uint32_t> flags(items, s), pos(items, s), segc(2, s), cand(items, s), tot(1, s);
-        launch_dedup_flags(ks, vs, items, rowsegs.get(), 1, flags.get(), segc.get(), s);
-        scan_exclusive_u32(flags.get(), pos.get(), items, tot.get(), s);
-        launch_seg_counts(ks, items, pos.get(), tot.get(), 1, 2, segc.get(), s);
-        launch_compact(flags.get(), pos.get(), vs, items, cand.get(), s);
+        // one chunk holding both classes' whole pair spaces: de-duplication with a
+        // partial sort, candidates in pair order; the full sort below when it cannot
+        // separate two candidates
+        bool done = false;
+        if (chunks.size() == 1 && dedup_partitioned_fits(items)) {
+            uint64_t q0[2] = {0, 0}, cnt[2] = {0, 0};
+            for (auto &p : ch) {
+                q0[p.c] = p.q0;
+                cnt[p.c] = p.cnt;
+            }
+            Scratch<uint32_t> pids(items, s), err(1, s);
+            IG_HIP(hipEventRecord(e[0], s));   // pairs and sort stages: none (all in the de-duplication)
+            IG_HIP(hipEventRecord(e[1], s));
+            IG_HIP(hipEventRecord(e[2], s));
+            launch_dedup_partitioned(cls[0].X.get(), cls[0].n, q0[0], cnt[0], cls[1].X.get(), cls[1].n, q0[1], cnt[1],
+                                     KS, K, flags.get(), pids.get(), pos.get(), tot.get(), segc.get(), err.get(), s);
+            if (host_read_u32(err.get(), 1, s)[0] == 0) {
+                launch_compact(flags.get(), pos.get(), pids.get(), items, cand.get(), s);
+                done = true;
+            }
+        }
+        if (!done) {
+            Scratch<uint64_t> k0(items, s), k1(items, s);
+            Scratch<uint32_t> v0(items, s), v1(items, s);
+            IG_HIP(hipEventRecord(e[0], s));
+            uint64_t at = 0;
+            for (auto &p : ch) {
+                launch_pair_hash(cls[p.c].X.get(), cls[p.c].n, KS, K, p.q0, p.cnt, (uint32_t)p.c, 1, k0.get() + at,
+                                 v0.get() + at, s, kPairKeyBytes);
+                at += p.cnt;
+            }
+            IG_HIP(hipEventRecord(e[1], s));
+            int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items,
+                                         0xffu & ~((1u << (8 - kPairKeyBytes)) - 1), s);
+            uint64_t *ks = where ? k1.get() : k0.get();
+            uint32_t *vs = where ? v1.get() : v0.get();
+            IG_HIP(hipEventRecord(e[2], s));
+            launch_dedup_flags(ks, vs, items, rowsegs.get(), 1, flags.get(), segc.get(), s);
+            scan_exclusive_u32(flags.get(), pos.get(), items, tot.get(), s);
+            launch_seg_counts(ks, items, pos.get(), tot.get(), 1, 2, segc.get(), s);
+            launch_compact(flags.get(), pos.get(), vs, items, cand.get(), s);
+        }
         IG_HIP(hipEventRecord(e[3], s));
         std::vector<uint32_t> hc = host_read_u32(segc.get(), 2, s);
         std::vector<uint32_t> hn = host_read_u32(counters.get(), 2, s);

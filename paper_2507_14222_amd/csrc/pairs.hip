@@ -104,6 +104,154 @@ __global__ void k_dedup_flags(const uint64_t *__restrict__ keys, const uint32_t 
     }
 }
 
+// ------------------------------------------- partitioned de-duplication ----
+// The same de-duplication with two radix passes instead of five, for one pass over
+// the pair space of both classes (segments 0 and 1): item g of segment c is pair
+// id q0[c] + (g - gbase[c]).  Each item gets the full 64-bit hash of its
+// intersection (the class mixed in after the words); a stable sort on the top 16
+// bits splits the items into 65,536 partitions, in item order inside each; one
+// workgroup per partition then finds equal hashes with an LDS hash table whose
+// entries keep the lowest local index per hash (the first occurrence in item
+// order, as after the full sort), and every other item compares its intersection
+// with that first one in full: a difference (two candidates sharing a hash), or a
+// partition beyond the table's capacity, sets *err and the caller falls back to
+// the full sort.  The flags land at the items' own positions, so the candidates
+// come out in pair order.
+struct DedupArgs {
+    RowsOfSeg seg[2];
+    uint64_t q0[2], gbase[2];
+};
+
+__device__ __forceinline__ void dedup_item_of(const DedupArgs &a, uint64_t g, int &c, uint32_t &q) {
+    c = g >= a.gbase[1] ? 1 : 0;
+    q = (uint32_t)(a.q0[c] + (g - a.gbase[c]));
+}
+
+// keys[g] = the 64-bit hash of item g's intersection, vals[g] = g; pids[g] = its
+// pair id.  Empty intersections get vals[g] = ~0 and a key spread by g (so that no
+// partition collects them).
+__global__ __launch_bounds__(256) void k_pair_hash64(DedupArgs a, uint64_t items, uint64_t *__restrict__ keys,
+                                                     uint32_t *__restrict__ vals, uint32_t *__restrict__ pids) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= items) return;
+    int c;
+    uint32_t q;
+    dedup_item_of(a, g, c, q);
+    const RowsOfSeg &r = a.seg[c];
+    uint32_t i, j;
+    decode_pair(q, r.n, i, j);
+    const uint64_t *xi = r.X + (size_t)i * r.KS, *xj = r.X + (size_t)j * r.KS;
+    uint64_t hh = 0x9e3779b97f4a7c15ull ^ r.K;
+    uint64_t any = 0;
+    for (uint32_t k0 = 0; k0 < r.K; k0 += 8) {
+        uint64_t b[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) b[u] = k0 + u < r.K ? xi[k0 + u] & xj[k0 + u] : 0ull;
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u)
+            if (k0 + u < r.K) {
+                any |= b[u];
+                hh = mix64(hh ^ b[u]) + 0x632be59bd9b4e019ull;
+            }
+    }
+    // the class enters after the words: mixed into the starting state, a difference
+    // there could be cancelled by one in the first word (the same two tokens of a
+    // feature in either class would then hash alike)
+    keys[g] = any ? mix64(hh ^ ((uint64_t)(c + 1) * 0x9ddfea08eb382d69ull)) : mix64(g + 0x51afd7ed558ccdull);
+    vals[g] = any ? (uint32_t)g : ~0u;
+    pids[g] = q;
+}
+
+constexpr uint32_t kPartBits = 16;          // partitions: the top bits of the hash
+constexpr uint32_t kPartSlots = 2048;       // LDS hash table of a partition (distinct hashes)
+
+// starts[p] = the first sorted position of partition p (starts[2^16] = m).
+__global__ void k_part_starts(const uint64_t *__restrict__ keys, size_t m, uint32_t *__restrict__ starts) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e > m) return;
+    const uint32_t np = 1u << kPartBits;
+    const uint32_t p = e < m ? (uint32_t)(keys[e] >> (64 - kPartBits)) : np;
+    const uint32_t prev = e > 0 ? (uint32_t)(keys[e - 1] >> (64 - kPartBits)) : 0u;
+    // the partitions after the previous element's, up to this one, start here
+    for (uint32_t q = e > 0 ? prev + 1 : 0u; q <= p; ++q) starts[q] = (uint32_t)e;
+}
+
+__global__ __launch_bounds__(256) void k_part_dedup(DedupArgs a, const uint64_t *__restrict__ keys,
+                                                    const uint32_t *__restrict__ vals,
+                                                    const uint32_t *__restrict__ starts,
+                                                    uint32_t *__restrict__ flags, uint32_t *__restrict__ err) {
+    __shared__ unsigned long long tab[kPartSlots];
+    const uint32_t s0 = starts[blockIdx.x], s1 = starts[blockIdx.x + 1];
+    if (s1 - s0 >= (1u << 26)) {   // uniform: local indices beyond an entry's 26 bits
+        if (threadIdx.x == 0) atomicOr(err, 1u);
+        return;
+    }
+    for (uint32_t t = threadIdx.x; t < kPartSlots; t += 256) tab[t] = 0ull;
+    __syncthreads();
+    // entry: hash bits above the slot index (never zero) << 26 | local index (copies
+    // of one candidate share an entry, so a partition may hold many more items than
+    // slots); a table that fills up sets *err
+    const uint32_t mask = kPartSlots - 1;
+    for (uint32_t li = threadIdx.x; li < s1 - s0; li += 256) {
+        if (vals[s0 + li] == ~0u) continue;
+        const uint64_t h = keys[s0 + li];
+        const unsigned long long tag = ((h >> 11) & ((1ull << 37) - 1)) | (1ull << 37);
+        const unsigned long long v = tag << 26 | li;
+        uint32_t slot = (uint32_t)h & mask, probes = 0;
+        for (;; slot = (slot + 1) & mask) {
+            const unsigned long long cur = atomicCAS(&tab[slot], 0ull, v);
+            if (cur == 0ull) break;
+            if ((cur >> 26) == tag) {
+                if (v < cur) atomicMin(&tab[slot], v);
+                break;
+            }
+            if (++probes == kPartSlots) {
+                atomicOr(err, 1u);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t li = threadIdx.x; li < s1 - s0; li += 256) {
+        const uint32_t g = vals[s0 + li];
+        if (g == ~0u) continue;
+        const uint64_t h = keys[s0 + li];
+        const unsigned long long tag = ((h >> 11) & ((1ull << 37) - 1)) | (1ull << 37);
+        uint32_t own = 0, probes = 0;
+        for (uint32_t slot = (uint32_t)h & mask;; slot = (slot + 1) & mask) {
+            const unsigned long long cur = tab[slot];
+            if (cur == 0ull || ++probes > kPartSlots) {   // not inserted: the table filled up
+                atomicOr(err, 1u);
+                break;
+            }
+            if ((cur >> 26) != tag) continue;
+            const uint32_t lo = (uint32_t)(cur & ((1ull << 26) - 1));
+            if (lo == li) {
+                own = 1;
+            } else {
+                int c, oc;
+                uint32_t q, oq;
+                dedup_item_of(a, g, c, q);
+                dedup_item_of(a, vals[s0 + lo], oc, oq);
+                if (oc != c || keys[s0 + lo] != h || !same_candidate(a.seg[c], oq, q)) atomicOr(err, 1u);
+            }
+            break;
+        }
+        flags[g] = own;
+    }
+}
+
+// seg_counts[0] = flags set among the items of segment 0, [1] = the rest (pos: the
+// exclusive scan of the flags, total: their sum).
+__global__ void k_dedup_seg_counts(const uint32_t *__restrict__ pos, const uint32_t *__restrict__ total,
+                                   uint64_t items0, uint64_t items, uint32_t *__restrict__ seg_counts) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint32_t d0 = items0 < items ? pos[items0] : *total;
+        seg_counts[0] = d0;
+        seg_counts[1] = *total - d0;
+    }
+}
+
 // Distinct candidates per segment from the scan of the flags: the keys are
 // sorted with the segment id in their top bits, so segment s occupies one
 // contiguous range, found by binary search (no atomics).
@@ -308,6 +456,41 @@ void launch_seg_counts(const uint64_t *keys, size_t m, const uint32_t *pos, cons
     }
     hipLaunchKernelGGL(k_seg_counts, dim3((nseg + 63) / 64), dim3(64), 0, s, keys, m, pos, total, segbits, nseg,
                        seg_counts, seg_offsets);
+    IG_HIP(hipGetLastError());
+}
+
+bool dedup_partitioned_fits(uint64_t items) { return items > 0 && items < (1ull << 32) - 1; }
+
+void launch_dedup_partitioned(const uint64_t *X0, uint32_t n0, uint64_t q00, uint64_t cnt0, const uint64_t *X1,
+                              uint32_t n1, uint64_t q01, uint64_t cnt1, uint32_t KS, uint32_t K, uint32_t *flags,
+                              uint32_t *pids, uint32_t *pos, uint32_t *total, uint32_t *seg_counts, uint32_t *err,
+                              hipStream_t s) {
+    const uint64_t items = cnt0 + cnt1;
+    IG_REQUIRE(dedup_partitioned_fits(items), IG_E_INVAL, "partitioned de-duplication of that many items");
+    DedupArgs a{};
+    a.seg[0] = RowsOfSeg{X0, n0, KS, K};
+    a.seg[1] = RowsOfSeg{X1, n1, KS, K};
+    a.q0[0] = q00;
+    a.q0[1] = q01;
+    a.gbase[0] = 0;
+    a.gbase[1] = cnt0;
+    Scratch<uint64_t> k0(items, s), k1(items, s);
+    Scratch<uint32_t> v0(items, s), v1(items, s), starts((1u << kPartBits) + 1, s);
+    launch_fill_u32(err, 0u, 1, s);
+    launch_fill_u32(flags, 0u, items, s);
+    const unsigned blocks = (unsigned)((items + 255) / 256);
+    hipLaunchKernelGGL(k_pair_hash64, dim3(blocks), dim3(256), 0, s, a, items, k0.get(), v0.get(), pids);
+    IG_HIP(hipGetLastError());
+    const int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items, 0xc0u, s);   // the top 16 bits
+    const uint64_t *ks = where ? k1.get() : k0.get();
+    const uint32_t *vs = where ? v1.get() : v0.get();
+    hipLaunchKernelGGL(k_part_starts, dim3((unsigned)((items + 1 + 255) / 256)), dim3(256), 0, s, ks, (size_t)items,
+                       starts.get());
+    IG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_part_dedup, dim3(1u << kPartBits), dim3(256), 0, s, a, ks, vs, starts.get(), flags, err);
+    IG_HIP(hipGetLastError());
+    scan_exclusive_u32(flags, pos, items, total, s);
+    hipLaunchKernelGGL(k_dedup_seg_counts, dim3(1), dim3(64), 0, s, pos, total, cnt0, items, seg_counts);
     IG_HIP(hipGetLastError());
 }
 
