@@ -1235,7 +1235,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     for (auto &ch : chunks) {
         uint64_t items = 0;
         for (auto &p : ch) items += p.cnt;
-        Scratch<uint32_t> flags(items, s), pos(items, s), segc(2, s), cand(items, s), tot(1, s);
+        Scratch<uint32_t> segc(2, s), cand(items, s), tot(1, s);
         // one chunk holding both classes' whole pair spaces: de-duplication with a
         // partial sort, candidates in pair order; the full sort below when it cannot
         // separate two candidates
@@ -1246,20 +1246,17 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
                 q0[p.c] = p.q0;
                 cnt[p.c] = p.cnt;
             }
-            Scratch<uint32_t> pids(items, s), err(1, s);
+            Scratch<uint32_t> err(1, s);
             IG_HIP(hipEventRecord(e[0], s));   // pairs and sort stages: none (all in the de-duplication)
             IG_HIP(hipEventRecord(e[1], s));
             IG_HIP(hipEventRecord(e[2], s));
             launch_dedup_partitioned(cls[0].X.get(), cls[0].n, q0[0], cnt[0], cls[1].X.get(), cls[1].n, q0[1], cnt[1],
-                                     KS, K, flags.get(), pids.get(), pos.get(), tot.get(), segc.get(), err.get(), s);
-            if (host_read_u32(err.get(), 1, s)[0] == 0) {
-                launch_compact(flags.get(), pos.get(), pids.get(), items, cand.get(), s);
-                done = true;
-            }
+                                     KS, K, cand.get(), tot.get(), segc.get(), err.get(), s);
+            done = host_read_u32(err.get(), 1, s)[0] == 0;
         }
         if (!done) {
             Scratch<uint64_t> k0(items, s), k1(items, s);
-            Scratch<uint32_t> v0(items, s), v1(items, s);
+            Scratch<uint32_t> v0(items, s), v1(items, s), flags(items, s), pos(items, s);
             IG_HIP(hipEventRecord(e[0], s));
             uint64_t at = 0;
             for (auto &p : ch) {

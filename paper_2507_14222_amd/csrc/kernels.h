@@ -24,16 +24,15 @@ void launch_pack_patterns(const uint16_t *codes, uint32_t m, uint32_t d, uint32_
 void launch_pair_hash(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, uint64_t q0, uint64_t count,
                       uint32_t seg, int segbits, uint64_t *keys, uint32_t *vals, hipStream_t s, int key_bytes = 8);
 // De-duplication with a partial sort (see pairs.hip) over the pair ids [q0c, q0c +
-// cntc) of both classes' records Xc: flags [cnt0 + cnt1] = 1 for the first
-// occurrence of each candidate, in item order; pids [cnt0 + cnt1] the items' pair
-// ids; pos the flags' exclusive scan, total and seg_counts [2] the distinct
-// candidates; *err set when the hashes could not tell two candidates apart or a
-// partition was too large (then use the full sort).
+// cntc) of both classes' records Xc: cand [cnt0 + cnt1] = the distinct candidates'
+// pair ids (the first occurrence of each), class 0's then class 1's; total and
+// seg_counts [2] their numbers; *err set when the hashes could not tell two
+// candidates apart or a partition had too many distinct keys (then use the full
+// sort).
 bool dedup_partitioned_fits(uint64_t items);
 void launch_dedup_partitioned(const uint64_t *X0, uint32_t n0, uint64_t q00, uint64_t cnt0, const uint64_t *X1,
-                              uint32_t n1, uint64_t q01, uint64_t cnt1, uint32_t KS, uint32_t K, uint32_t *flags,
-                              uint32_t *pids, uint32_t *pos, uint32_t *total, uint32_t *seg_counts, uint32_t *err,
-                              hipStream_t s);
+                              uint32_t n1, uint64_t q01, uint64_t cnt1, uint32_t KS, uint32_t K, uint32_t *cand,
+                              uint32_t *total, uint32_t *seg_counts, uint32_t *err, hipStream_t s);
 size_t rows_of_seg_size();
 void fill_rows_of_seg(void *dst, const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K);
 void launch_dedup_flags(const uint64_t *keys, const uint32_t *vals, size_t m, const void *segs_dev, int segbits,

@@ -107,16 +107,16 @@ __global__ void k_dedup_flags(const uint64_t *__restrict__ keys, const uint32_t 
 // ------------------------------------------- partitioned de-duplication ----
 // The same de-duplication with two radix passes instead of five, for one pass over
 // the pair space of both classes (segments 0 and 1): item g of segment c is pair
-// id q0[c] + (g - gbase[c]).  Each item gets the full 64-bit hash of its
-// intersection (the class mixed in after the words); a stable sort on the top 16
-// bits splits the items into 65,536 partitions, in item order inside each; one
-// workgroup per partition then finds equal hashes with an LDS hash table whose
-// entries keep the lowest local index per hash (the first occurrence in item
-// order, as after the full sort), and every other item compares its intersection
-// with that first one in full: a difference (two candidates sharing a hash), or a
-// partition beyond the table's capacity, sets *err and the caller falls back to
-// the full sort.  The flags land at the items' own positions, so the candidates
-// come out in pair order.
+// id q0[c] + (g - gbase[c]).  Each item gets a key: its class in the top bit and 63
+// bits of a 64-bit hash of its intersection (the class mixed in after the words).
+// A stable sort on the top 16 bits splits the items into 2 x 32,768 partitions,
+// class 0's first, in item order inside each; one workgroup per partition finds
+// equal keys with an LDS hash table whose entries keep the lowest local index per
+// key (the first occurrence in item order, as after the full sort), and every
+// other copy is then compared with that first one in full (k_dedup_verify): a
+// difference (two candidates sharing a key) or a partition with too many distinct
+// keys sets *err, and the caller falls back to the full sort.  The candidates come
+// out class by class in the partitions' order.
 struct DedupArgs {
     RowsOfSeg seg[2];
     uint64_t q0[2], gbase[2];
@@ -127,11 +127,11 @@ __device__ __forceinline__ void dedup_item_of(const DedupArgs &a, uint64_t g, in
     q = (uint32_t)(a.q0[c] + (g - a.gbase[c]));
 }
 
-// keys[g] = the 64-bit hash of item g's intersection, vals[g] = g; pids[g] = its
-// pair id.  Empty intersections get vals[g] = ~0 and a key spread by g (so that no
+// keys[g] = item g's class << 63 | 63 bits of the hash of its intersection, vals[g]
+// = g.  Empty intersections get vals[g] = ~0 and a key spread by g (so that no
 // partition collects them).
 __global__ __launch_bounds__(256) void k_pair_hash64(DedupArgs a, uint64_t items, uint64_t *__restrict__ keys,
-                                                     uint32_t *__restrict__ vals, uint32_t *__restrict__ pids) {
+                                                     uint32_t *__restrict__ vals) {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= items) return;
     int c;
@@ -157,9 +157,9 @@ __global__ __launch_bounds__(256) void k_pair_hash64(DedupArgs a, uint64_t items
     // the class enters after the words: mixed into the starting state, a difference
     // there could be cancelled by one in the first word (the same two tokens of a
     // feature in either class would then hash alike)
-    keys[g] = any ? mix64(hh ^ ((uint64_t)(c + 1) * 0x9ddfea08eb382d69ull)) : mix64(g + 0x51afd7ed558ccdull);
+    const uint64_t h = any ? mix64(hh ^ ((uint64_t)(c + 1) * 0x9ddfea08eb382d69ull)) : mix64(g + 0x51afd7ed558ccdull);
+    keys[g] = (uint64_t)c << 63 | h >> 1;
     vals[g] = any ? (uint32_t)g : ~0u;
-    pids[g] = q;
 }
 
 constexpr uint32_t kPartBits = 16;          // partitions: the top bits of the hash
@@ -176,10 +176,11 @@ __global__ void k_part_starts(const uint64_t *__restrict__ keys, size_t m, uint3
     for (uint32_t q = e > 0 ? prev + 1 : 0u; q <= p; ++q) starts[q] = (uint32_t)e;
 }
 
-__global__ __launch_bounds__(256) void k_part_dedup(DedupArgs a, const uint64_t *__restrict__ keys,
-                                                    const uint32_t *__restrict__ vals,
-                                                    const uint32_t *__restrict__ starts,
-                                                    uint32_t *__restrict__ flags, uint32_t *__restrict__ err) {
+// flags[e] = 1 for the first copy (in item order) of each key among the sorted
+// items of a partition, own[e] = the sorted position of that first copy.
+__global__ __launch_bounds__(256) void k_part_dedup(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                                                    const uint32_t *__restrict__ starts, uint32_t *__restrict__ flags,
+                                                    uint32_t *__restrict__ own, uint32_t *__restrict__ err) {
     __shared__ unsigned long long tab[kPartSlots];
     const uint32_t s0 = starts[blockIdx.x], s1 = starts[blockIdx.x + 1];
     if (s1 - s0 >= (1u << 26)) {   // uniform: local indices beyond an entry's 26 bits
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void k_part_dedup(DedupArgs a, const uint64_t 
     }
     for (uint32_t t = threadIdx.x; t < kPartSlots; t += 256) tab[t] = 0ull;
     __syncthreads();
-    // entry: hash bits above the slot index (never zero) << 26 | local index (copies
+    // entry: key bits above the slot index (never zero) << 26 | local index (copies
     // of one candidate share an entry, so a partition may hold many more items than
     // slots); a table that fills up sets *err
     const uint32_t mask = kPartSlots - 1;
@@ -199,7 +200,9 @@ __global__ __launch_bounds__(256) void k_part_dedup(DedupArgs a, const uint64_t 
         const unsigned long long v = tag << 26 | li;
         uint32_t slot = (uint32_t)h & mask, probes = 0;
         for (;; slot = (slot + 1) & mask) {
-            const unsigned long long cur = atomicCAS(&tab[slot], 0ull, v);
+            const unsigned long long seen = tab[slot];
+            if ((seen >> 26) == tag && seen <= v) break;   // an earlier copy holds the entry
+            const unsigned long long cur = seen ? seen : atomicCAS(&tab[slot], 0ull, v);
             if (cur == 0ull) break;
             if ((cur >> 26) == tag) {
                 if (v < cur) atomicMin(&tab[slot], v);
@@ -213,39 +216,64 @@ __global__ __launch_bounds__(256) void k_part_dedup(DedupArgs a, const uint64_t 
     }
     __syncthreads();
     for (uint32_t li = threadIdx.x; li < s1 - s0; li += 256) {
-        const uint32_t g = vals[s0 + li];
-        if (g == ~0u) continue;
-        const uint64_t h = keys[s0 + li];
-        const unsigned long long tag = ((h >> 11) & ((1ull << 37) - 1)) | (1ull << 37);
-        uint32_t own = 0, probes = 0;
-        for (uint32_t slot = (uint32_t)h & mask;; slot = (slot + 1) & mask) {
-            const unsigned long long cur = tab[slot];
-            if (cur == 0ull || ++probes > kPartSlots) {   // not inserted: the table filled up
-                atomicOr(err, 1u);
+        uint32_t f = 0, o = s0 + li;
+        if (vals[s0 + li] != ~0u) {
+            const uint64_t h = keys[s0 + li];
+            const unsigned long long tag = ((h >> 11) & ((1ull << 37) - 1)) | (1ull << 37);
+            uint32_t probes = 0;
+            for (uint32_t slot = (uint32_t)h & mask;; slot = (slot + 1) & mask) {
+                const unsigned long long cur = tab[slot];
+                if (cur == 0ull || ++probes > kPartSlots) {   // not inserted: the table filled up
+                    atomicOr(err, 1u);
+                    break;
+                }
+                if ((cur >> 26) != tag) continue;
+                const uint32_t lo = (uint32_t)(cur & ((1ull << 26) - 1));
+                o = s0 + lo;
+                f = lo == li ? 1u : 0u;
+                if (keys[o] != h) atomicOr(err, 1u);   // two keys share a tag
                 break;
             }
-            if ((cur >> 26) != tag) continue;
-            const uint32_t lo = (uint32_t)(cur & ((1ull << 26) - 1));
-            if (lo == li) {
-                own = 1;
-            } else {
-                int c, oc;
-                uint32_t q, oq;
-                dedup_item_of(a, g, c, q);
-                dedup_item_of(a, vals[s0 + lo], oc, oq);
-                if (oc != c || keys[s0 + lo] != h || !same_candidate(a.seg[c], oq, q)) atomicOr(err, 1u);
-            }
-            break;
         }
-        flags[g] = own;
+        flags[s0 + li] = f;
+        own[s0 + li] = o;
     }
 }
 
-// seg_counts[0] = flags set among the items of segment 0, [1] = the rest (pos: the
-// exclusive scan of the flags, total: their sum).
+// Every copy is compared in full with the first one of its key: a difference sets
+// *err.
+__global__ __launch_bounds__(256) void k_dedup_verify(DedupArgs a, uint64_t items, const uint32_t *__restrict__ vals,
+                                                      const uint32_t *__restrict__ own, uint32_t *__restrict__ err) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= items) return;
+    const uint32_t g = vals[e], o = own[e];
+    if (g == ~0u || o == (uint32_t)e) return;
+    int c, oc;
+    uint32_t q, oq;
+    dedup_item_of(a, g, c, q);
+    dedup_item_of(a, vals[o], oc, oq);
+    if (oc != c || !same_candidate(a.seg[c], oq, q)) atomicOr(err, 1u);
+}
+
+// out[pos[e]] = the pair id of sorted item e, for the flagged ones.
+__global__ __launch_bounds__(256) void k_dedup_compact(DedupArgs a, uint64_t items, const uint32_t *__restrict__ flags,
+                                                       const uint32_t *__restrict__ pos,
+                                                       const uint32_t *__restrict__ vals, uint32_t *__restrict__ out) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= items || !flags[e]) return;
+    int c;
+    uint32_t q;
+    dedup_item_of(a, vals[e], c, q);
+    out[pos[e]] = q;
+}
+
+// seg_counts[0] = flags set among the sorted items of class 0 (those before
+// *boundary), [1] = the rest (pos: the exclusive scan of the flags, total: their sum).
 __global__ void k_dedup_seg_counts(const uint32_t *__restrict__ pos, const uint32_t *__restrict__ total,
-                                   uint64_t items0, uint64_t items, uint32_t *__restrict__ seg_counts) {
+                                   const uint32_t *__restrict__ boundary, uint64_t items,
+                                   uint32_t *__restrict__ seg_counts) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint64_t items0 = *boundary;
         const uint32_t d0 = items0 < items ? pos[items0] : *total;
         seg_counts[0] = d0;
         seg_counts[1] = *total - d0;
@@ -462,9 +490,8 @@ void launch_seg_counts(const uint64_t *keys, size_t m, const uint32_t *pos, cons
 bool dedup_partitioned_fits(uint64_t items) { return items > 0 && items < (1ull << 32) - 1; }
 
 void launch_dedup_partitioned(const uint64_t *X0, uint32_t n0, uint64_t q00, uint64_t cnt0, const uint64_t *X1,
-                              uint32_t n1, uint64_t q01, uint64_t cnt1, uint32_t KS, uint32_t K, uint32_t *flags,
-                              uint32_t *pids, uint32_t *pos, uint32_t *total, uint32_t *seg_counts, uint32_t *err,
-                              hipStream_t s) {
+                              uint32_t n1, uint64_t q01, uint64_t cnt1, uint32_t KS, uint32_t K, uint32_t *cand,
+                              uint32_t *total, uint32_t *seg_counts, uint32_t *err, hipStream_t s) {
     const uint64_t items = cnt0 + cnt1;
     IG_REQUIRE(dedup_partitioned_fits(items), IG_E_INVAL, "partitioned de-duplication of that many items");
     DedupArgs a{};
@@ -477,9 +504,8 @@ void launch_dedup_partitioned(const uint64_t *X0, uint32_t n0, uint64_t q00, uin
     Scratch<uint64_t> k0(items, s), k1(items, s);
     Scratch<uint32_t> v0(items, s), v1(items, s), starts((1u << kPartBits) + 1, s);
     launch_fill_u32(err, 0u, 1, s);
-    launch_fill_u32(flags, 0u, items, s);
     const unsigned blocks = (unsigned)((items + 255) / 256);
-    hipLaunchKernelGGL(k_pair_hash64, dim3(blocks), dim3(256), 0, s, a, items, k0.get(), v0.get(), pids);
+    hipLaunchKernelGGL(k_pair_hash64, dim3(blocks), dim3(256), 0, s, a, items, k0.get(), v0.get());
     IG_HIP(hipGetLastError());
     const int where = radix_sort_pairs(k0.get(), v0.get(), k1.get(), v1.get(), items, 0xc0u, s);   // the top 16 bits
     const uint64_t *ks = where ? k1.get() : k0.get();
@@ -487,10 +513,20 @@ void launch_dedup_partitioned(const uint64_t *X0, uint32_t n0, uint64_t q00, uin
     hipLaunchKernelGGL(k_part_starts, dim3((unsigned)((items + 1 + 255) / 256)), dim3(256), 0, s, ks, (size_t)items,
                        starts.get());
     IG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_part_dedup, dim3(1u << kPartBits), dim3(256), 0, s, a, ks, vs, starts.get(), flags, err);
+    // the other key array and value array are free now: flags and first copies
+    uint32_t *flags = where ? v0.get() : v1.get();
+    uint32_t *own = reinterpret_cast<uint32_t *>(where ? k0.get() : k1.get());
+    uint32_t *pos = own + items;
+    hipLaunchKernelGGL(k_part_dedup, dim3(1u << kPartBits), dim3(256), 0, s, ks, vs, starts.get(), flags, own, err);
+    IG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_dedup_verify, dim3(blocks), dim3(256), 0, s, a, items, vs, own, err);
     IG_HIP(hipGetLastError());
     scan_exclusive_u32(flags, pos, items, total, s);
-    hipLaunchKernelGGL(k_dedup_seg_counts, dim3(1), dim3(64), 0, s, pos, total, cnt0, items, seg_counts);
+    hipLaunchKernelGGL(k_dedup_compact, dim3(blocks), dim3(256), 0, s, a, items, flags, pos, vs, cand);
+    IG_HIP(hipGetLastError());
+    // class 1's partitions begin at 2^15
+    hipLaunchKernelGGL(k_dedup_seg_counts, dim3(1), dim3(64), 0, s, pos, total, starts.get() + (1u << (kPartBits - 1)),
+                       items, seg_counts);
     IG_HIP(hipGetLastError());
 }
 
