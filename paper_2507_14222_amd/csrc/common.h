@@ -110,7 +110,9 @@ struct Seg {
 __device__ __forceinline__ void decode_pair(uint64_t q, uint32_t n, uint32_t &i, uint32_t &j) {
     if (q < n) { i = j = (uint32_t)q; return; }
     uint64_t p = q - n;
-    uint64_t jj = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+    // a single-precision estimate (within one of the root for p < 2^40), then exact
+    // integer correction
+    uint64_t jj = (uint64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)p)) * 0.5f);
     while (jj * (jj - 1) / 2 > p) --jj;
     while ((jj + 1) * jj / 2 <= p) ++jj;
     i = (uint32_t)(p - jj * (jj - 1) / 2);
