@@ -266,8 +266,9 @@ ig_status ig_score(const ig_model *m, const uint16_t *d_codes, uint32_t n_flows,
  *   IG_SCORE_PRUNED  exact pruning of Eq. 4: a pattern lies inside a flow only if
  *                    the flow holds every token of the pattern (Eq. 6).  The model
  *                    files each pattern under one of its tokens (its bucket: the
- *                    token the fewest training records hold, or for an imported
- *                    model the token of the feature with the most bins), and each
+ *                    token the fewest training records of its class hold, or for
+ *                    an imported model the token of the feature with the most
+ *                    bins), and each
  *                    flow is tested only against the buckets of the d tokens it
  *                    holds.  Needs IG_MODEL_BUCKETED (IG_E_UNSUPPORTED otherwise)
  *                    and device scratch of about 4 * (n_flows * d + 5 L) bytes,
