@@ -288,9 +288,10 @@ ig_status ig_score_ex(const ig_model *m, const uint16_t *d_codes, uint32_t n_flo
  * scoring's per-call work goes to a fixed array of IG_NOALLOC_SCRATCH_BYTES in
  * the library's device memory (each GPU the library runs on holds its own copy
  * until the process ends) instead of library-allocated scratch, so a call needs
- *   4 * (n_flows * d + 5 L + 3) <= IG_NOALLOC_SCRATCH_BYTES
- * (IG_E_UNSUPPORTED beyond; e.g. about 51,000 flows of 41 features and 464
- * tokens).  Models without token buckets score with the dense kernels, which
+ *   4 * (ceil4(n_flows * d + 5 L + 3) + 8 W n_flows) <= IG_NOALLOC_SCRATCH_BYTES
+ * with W the model's scoring operand words (ig_model_info.mfma_words) and
+ * ceil4 rounding up to a multiple of 4 (IG_E_UNSUPPORTED beyond; e.g. about
+ * 32,000 flows of 41 features, 464 tokens and 3 words).  Models without token buckets score with the dense kernels, which
  * need no scratch.  Every call on one GPU shares that GPU's array: calls that
  * overlap on a GPU (on different streams, or from different host threads) race
  * and can return wrong scores; order them (one stream, or events).  Each call

@@ -2013,7 +2013,7 @@ ig_status ig_score_ex(const ig_model *m, const uint16_t *d_codes, uint32_t n_flo
         IG_REQUIRE(mode != IG_SCORE_PRUNED || (mfma && sm.nbucket), IG_E_UNSUPPORTED,
                    "the model's scoring tiles are not grouped by token");
         if (mfma && sm.nbucket && mode != IG_SCORE_DENSE) {
-            ig::Scratch<uint32_t> ws(ig::prune_scratch_words(sm.nbucket, n_flows, M.d), s);
+            ig::Scratch<uint32_t> ws(ig::prune_scratch_words(sm.nbucket, n_flows, M.d, sm.KO), s);
             if (ig::launch_score_mfma_pruned(sm, d_codes, n_flows, M.d, M.meta, M.nbins, d_out, ws.get(), s)) return;
             IG_REQUIRE(mode != IG_SCORE_PRUNED, IG_E_UNSUPPORTED, "too many flows for one pruned scoring launch");
         }
@@ -2040,10 +2040,10 @@ ig_status ig_score_noalloc(const ig_model *m, const uint16_t *d_codes, uint32_t 
         hipStream_t s = (hipStream_t)stream;
         const bool mfma = M.frag[0] && M.frag[1];
         if (mfma && sm.nbucket) {
-            const size_t need = ig::prune_scratch_words(sm.nbucket, n_flows, M.d);
+            const size_t need = ig::prune_scratch_words(sm.nbucket, n_flows, M.d, sm.KO);
             const size_t have = ig::noalloc_scratch_words();
             IG_REQUIRE(need <= have, IG_E_UNSUPPORTED,
-                       "n_flows * d + 5 L + 3 = " + std::to_string(need) + " words exceed the fixed scratch of " +
+                       "the call's " + std::to_string(need) + " words of scratch exceed the fixed array of " +
                            std::to_string(have) + " words (IG_NOALLOC_SCRATCH_BYTES)");
             if (ig::launch_score_mfma_pruned(sm, d_codes, n_flows, M.d, M.meta, M.nbins, d_out,
                                              ig::noalloc_scratch(), s))

@@ -254,11 +254,13 @@ void launch_bucket_keys(const uint64_t *W, size_t m, uint32_t KS, uint32_t L, co
                         uint32_t *err, hipStream_t s);
 // first[key[e]] = e where ascending keys change (first preset by the caller)
 void launch_bucket_first(const uint64_t *key, size_t m, uint32_t *first, hipStream_t s);
-// Per-call work of pruned scoring, carved from prune_scratch_words(L, n, d) u32.
+// Per-call work of pruned scoring, carved from prune_scratch_words(L, n, d, KO) u32
+// (16-byte aligned): flow lists, work units, and the flows' B operands.
 struct PruneWork {
     uint32_t *cnt, *cursor, *foff, *uoff, *queue, *list;
+    uint4 *ops;
 };
-size_t prune_scratch_words(uint32_t L, uint32_t n_flows, uint32_t d);
+size_t prune_scratch_words(uint32_t L, uint32_t n_flows, uint32_t d, uint32_t KO);
 // Token buckets of the fit's contractions (see prune.hip).  Elements are grouped
 // by a key <= L: out (perm or list) holds them key after key, first [L + 2] the
 // first position of each key (first[L + 1] = m); ws: bucket_ws_words(m, L) u32.
@@ -280,7 +282,7 @@ void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const
 // [n d] of record indices, key [n d] scratch; ws: bucket_ws_words(n d, L) u32.
 void launch_group_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, uint32_t d, uint32_t *key,
                           uint32_t *list, uint32_t *first, uint32_t *ws, hipStream_t s);
-PruneWork prune_work(uint32_t *ws, uint32_t L);
+PruneWork prune_work(uint32_t *ws, uint32_t L, uint32_t n_flows, uint32_t d);
 // Lists of the valid flows holding each token, work units of SC_COLS-flow blocks
 // and rt-tile ranges per (class, bucket), and out initialised ((0,0) valid,
 // (-1,-1) invalid flows).
@@ -309,7 +311,7 @@ void launch_score_mfma(const ScoreModel &m, const uint16_t *codes, const uint64_
                        hipStream_t s);
 // Eq. 4 on the matrix cores for flows given as codes, each flow tested only against
 // the token buckets of its own tokens (m.btile non-null).  ws: prune_scratch_words(
-// m.nbucket, n_flows, d) u32 of device scratch, used until the stream reaches the
+// m.nbucket, n_flows, d, m.KO) u32 of device scratch (16-byte aligned), used until the stream reaches the
 // end of the call.  false (nothing launched) when the work units of the call could
 // overflow 32-bit counts; the caller then scores densely.
 bool launch_score_mfma_pruned(const ScoreModel &m, const uint16_t *codes, uint32_t n_flows, uint32_t d,

@@ -489,8 +489,14 @@ __global__ __launch_bounds__(256) void k_prune_scatter(const uint16_t *__restric
         }
 }
 
-size_t prune_scratch_words(uint32_t L, uint32_t n_flows, uint32_t d) {
-    return 5ull * L + 3 + (size_t)n_flows * d;
+// the lists and units, then (at a multiple of 4 words) the flows' operands: 2 KO
+// uint4 per flow
+static size_t prune_list_words(uint32_t L, uint32_t n_flows, uint32_t d) {
+    return (5ull * L + 3 + (size_t)n_flows * d + 3) & ~(size_t)3;
+}
+
+size_t prune_scratch_words(uint32_t L, uint32_t n_flows, uint32_t d, uint32_t KO) {
+    return prune_list_words(L, n_flows, d) + 8ull * KO * n_flows;
 }
 
 void launch_prune_lists(const uint16_t *codes, uint32_t n, uint32_t d, const uint32_t *off, const uint16_t *nbins,
@@ -510,8 +516,9 @@ void launch_prune_lists(const uint16_t *codes, uint32_t n, uint32_t d, const uin
     IG_HIP(hipGetLastError());
 }
 
-PruneWork prune_work(uint32_t *ws, uint32_t L) {
+PruneWork prune_work(uint32_t *ws, uint32_t L, uint32_t n_flows, uint32_t d) {
     PruneWork w;
+    w.ops = reinterpret_cast<uint4 *>(ws + prune_list_words(L, n_flows, d));
     w.cnt = ws;
     w.cursor = ws + L;
     w.foff = ws + 2 * (size_t)L;

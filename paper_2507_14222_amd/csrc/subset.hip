@@ -254,9 +254,9 @@ __device__ __forceinline__ void wait_loads() {
 template <int TW, int G, int NB>
 constexpr int ring_lds() { return NB * G * TW + 64; }
 
-template <int TW, int G, int NB, int NT, class Body>
-__device__ __forceinline__ void stream_tiles(const uint4 *__restrict__ frag_in, uint32_t t0, uint32_t t1,
-                                             uint4 *lds_in, Body body) {
+template <int TW, int G, int NB, int NT, class Pre, class Body>
+__device__ __forceinline__ void stream_tiles_after(const uint4 *__restrict__ frag_in, uint32_t t0, uint32_t t1,
+                                                   uint4 *lds_in, Pre pre, Body body) {
     constexpr int N = G * TW;                 // uint4 per group
     constexpr int PER = (N + NT - 1) / NT;    // loads per thread per group
     static_assert(NB >= 2 && NB <= 4 && (NB - 2) * PER <= 63, "ring depth");
@@ -281,6 +281,9 @@ __device__ __forceinline__ void stream_tiles(const uint4 *__restrict__ frag_in, 
 #pragma unroll
     for (int p = 0; p < NB - 1; ++p)
         if ((uint32_t)p < ng) issue(p);
+    // work that overlaps the first groups' loads (its own loads are counted by vmcnt
+    // after the ring's, so the waits below only wait longer)
+    pre();
     for (uint32_t g = 0; g < ng; ++g) {
         // groups issued after g: min(NB - 2, ng - 1 - g); wait until only those are in flight
         const uint32_t ahead = ng - 1 - g < (uint32_t)(NB - 2) ? ng - 1 - g : (uint32_t)(NB - 2);
@@ -295,6 +298,12 @@ __device__ __forceinline__ void stream_tiles(const uint4 *__restrict__ frag_in, 
         const uint4 *cur = lds_in + (g % NB) * N;
         for (uint32_t j = 0; j < nt; ++j) body(cur + j * TW);
     }
+}
+
+template <int TW, int G, int NB, int NT, class Body>
+__device__ __forceinline__ void stream_tiles(const uint4 *__restrict__ frag_in, uint32_t t0, uint32_t t1,
+                                             uint4 *lds_in, Body body) {
+    stream_tiles_after<TW, G, NB, NT>(frag_in, t0, t1, lds_in, [] {}, body);
 }
 
 // Other-class records, complemented (one-hot tokens), in the A-operand layout of
@@ -900,6 +909,16 @@ constexpr int SC_WPS = IG_SCORE_WPS;
 constexpr int SC_COLS = SC_NT / 64 * MF_FB * 32;
 template <int KS>
 constexpr int sc_group() { return IG_SCORE_GTOK / (KS + 1) > 0 ? IG_SCORE_GTOK / (KS + 1) : 1; }
+// pruned scoring's ring (its work units stream a few tiles each)
+#ifndef IG_PRUNE_GTOK
+#define IG_PRUNE_GTOK IG_SCORE_GTOK
+#endif
+#ifndef IG_PRUNE_NB
+#define IG_PRUNE_NB IG_SCORE_NB
+#endif
+constexpr int SP_NB = IG_PRUNE_NB;
+template <int KS>
+constexpr int sp_group() { return IG_PRUNE_GTOK / (KS + 1) > 0 ? IG_PRUNE_GTOK / (KS + 1) : 1; }
 
 struct ScoreMfmaArgs {
     const uint4 *frag[2];
@@ -1118,68 +1137,117 @@ __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
 // A work unit is (class, bucket u, a range of at most p.rt of the bucket's tiles,
 // a block of SC_COLS of the flows holding token u); its flows are tested against
 // those tiles only.  Workgroups take units from a queue until it runs dry.  Every
-// flow in the lists is valid; the launcher initialised out.
+// flow in the lists is valid; the launcher initialised out.  The flows' operands
+// are built once per call (k_flow_operands) and loaded by each unit.
 struct PruneArgs {
     const uint32_t *btile[2];   // [L + 1]: first tile of each bucket, per class
     const uint32_t *fcnt;       // [L]: flows holding token u
     const uint32_t *foff;       // [L + 1]: start of the list of flows holding token u
     const uint32_t *flist;      // flow ids grouped by token
     const uint32_t *uoff;       // [2L + 1]: first unit of (class, bucket) c * L + u
+    const uint4 *ops;           // [n_flows][2][KS]: B operand of each flow and lane half
     uint32_t *queue;            // next unit to take (zero at launch)
     uint32_t L, rt;
 };
 
+// B operands of every flow, one thread per (flow, lane half): ops[(t * 2 + half) *
+// KS + k] = the four used dwords of word k's operand.
+template <int KS, int SF>
+__global__ __launch_bounds__(256) void k_flow_operands(ScoreMfmaArgs a, uint4 *__restrict__ ops) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 2 * a.n_flows) return;
+    v8i_t b[KS];
+    flow_operand<KS, SF>(a, g >> 1, true, (int)(g & 1), b);
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+        ops[(size_t)g * KS + k] = uint4{(uint32_t)b[k][0], (uint32_t)b[k][1], (uint32_t)b[k][2], (uint32_t)b[k][3]};
+}
+
+// The (class, bucket) entry that owns `unit`: the last i < n2 with uoff[i] <= unit
+// (uoff ascends from uoff[0] = 0, and that entry's range is not empty).  The 64
+// lanes of one wave (all active, unit uniform) probe every stride-th entry, then
+// the entries of the block found: two rounds of loads instead of a binary search.
+__device__ __forceinline__ uint32_t unit_owner(const uint32_t *__restrict__ uoff, uint32_t n2, uint32_t unit) {
+    const uint32_t lane = threadIdx.x & 63, stride = (n2 + 63) / 64;
+    const uint32_t p = lane * stride;
+    const uint32_t k = (uint32_t)__popcll(__ballot(p < n2 && uoff[p] <= unit)) - 1u;
+    uint32_t cnt = 0;
+    for (uint32_t c = 0; c < stride; c += 64) {
+        const uint32_t q = k * stride + c + lane;
+        cnt += (uint32_t)__popcll(__ballot(c + lane < stride && q < n2 && uoff[q] <= unit));
+    }
+    return k * stride + cnt - 1u;
+}
+
 template <int KS, int SF>
 __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma_pruned(ScoreMfmaArgs a, PruneArgs p) {
-    constexpr int G = sc_group<KS>();
+    constexpr int G = sp_group<KS>();
     constexpr int TW = (KS + 1) * 64;
-    __shared__ uint4 lds[ring_lds<TW, G, SC_NB>()];
-    __shared__ uint32_t next_unit;
+    __shared__ uint4 lds[ring_lds<TW, G, SP_NB>()];
+    __shared__ uint32_t s_unit[2], s_owner[2];
     const uint32_t total = p.uoff[2 * p.L];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
-    for (;;) {
-        if (threadIdx.x == 0) next_unit = atomicAdd(p.queue, 1u);
-        __syncthreads();   // also: every wave is done with the previous unit's ring
-        const uint32_t unit = next_unit;
-        __syncthreads();   // every thread has read next_unit before thread 0 rewrites it
-        if (unit >= total) break;   // uniform over the workgroup
-        // (class, bucket) of the unit: the last i with uoff[i] <= unit (its range is not empty)
-        uint32_t lo = 0, hi = 2 * p.L;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (p.uoff[mid] <= unit) lo = mid;
-            else hi = mid;
+    // the operand of an inactive column (no flow): no pattern lies inside it
+    v8i_t bz[KS];
+    flow_operand<KS, SF>(a, 0u, false, half, bz);
+    // thread 0 takes the next unit one unit ahead, so the queue's latency overlaps work
+    uint32_t next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(p.queue, 1u);
+    for (uint32_t it = 0;; ++it) {
+        if (wave == 0) {
+            const uint32_t unit = __builtin_amdgcn_readfirstlane(next);
+            const uint32_t owner = unit < total ? unit_owner(p.uoff, 2 * p.L, unit) : 0u;
+            if (threadIdx.x == 0) {
+                s_unit[it & 1] = unit;
+                s_owner[it & 1] = owner;
+                if (unit < total) next = atomicAdd(p.queue, 1u);
+            }
         }
+        // the unit is published; every wave is done with the previous unit's ring.
+        // (slot it & 1 is rewritten two units later, after the next barrier, by which
+        // time every thread has read it)
+        __syncthreads();
+        const uint32_t unit = s_unit[it & 1], lo = s_owner[it & 1];
+        if (unit >= total) break;   // uniform over the workgroup
         const int cls = lo >= p.L ? 1 : 0;
         const uint32_t u = lo - (uint32_t)cls * p.L;
         const uint32_t nf = p.fcnt[u], nb = (nf + SC_COLS - 1) / SC_COLS;
         const uint32_t local = unit - p.uoff[lo], r = local / nb, fb = local % nb;
         const uint32_t t0 = p.btile[cls][u] + r * p.rt, tend = p.btile[cls][u + 1];
         const uint32_t t1 = t0 + p.rt < tend ? t0 + p.rt : tend;
-        v8i_t b[MF_FB][KS];
-        uint32_t tf[MF_FB];
-        bool valid[MF_FB];
         const uint32_t wave0 = fb * SC_COLS + wave * (MF_FB * 32);   // first slot of the wave
-#pragma unroll
-        for (int f = 0; f < MF_FB; ++f) {
-            const uint32_t slot = wave0 + f * 32 + col;
-            const bool act = slot < nf;
-            tf[f] = act ? p.flist[p.foff[u] + slot] : 0u;
-            valid[f] = flow_operand<KS, SF>(a, tf[f], act, half, b[f]);
-        }
-        v16i_t C[MF_FB];
-#pragma unroll
-        for (int f = 0; f < MF_FB; ++f) C[f] = v16i_t{0};
         // a wave without flows in this block only helps to stream the tiles (it takes
         // the same loads and barriers, and skips the products)
         if (__builtin_amdgcn_readfirstlane(wave0 < nf ? 1 : 0)) {
-            stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], t0, t1, lds, [&](const uint4 *tile) __attribute__((always_inline)) {
-                score_tile<KS, SF>(tile, lane, b, C);
-            });
+            v8i_t b[MF_FB][KS];
+            uint32_t tf[MF_FB];
+            bool valid[MF_FB];
+            v16i_t C[MF_FB];
+            stream_tiles_after<TW, G, SP_NB, SC_NT>(
+                a.frag[cls], t0, t1, lds,
+                [&]() __attribute__((always_inline)) {
+                    const uint32_t *fl = p.flist + p.foff[u];
+#pragma unroll
+                    for (int f = 0; f < MF_FB; ++f) {
+                        const uint32_t slot = wave0 + f * 32 + col;
+                        valid[f] = slot < nf;
+                        tf[f] = valid[f] ? fl[slot] : 0u;
+                    }
+#pragma unroll
+                    for (int f = 0; f < MF_FB; ++f)
+#pragma unroll
+                        for (int k = 0; k < KS; ++k) {
+                            const uint4 q = p.ops[((size_t)tf[f] * 2 + half) * KS + k];
+                            b[f][k] = valid[f] ? v8i_t{(int)q.x, (int)q.y, (int)q.z, (int)q.w, 0, 0, 0, 0} : bz[k];
+                        }
+#pragma unroll
+                    for (int f = 0; f < MF_FB; ++f) C[f] = v16i_t{0};
+                },
+                [&](const uint4 *tile) __attribute__((always_inline)) { score_tile<KS, SF>(tile, lane, b, C); });
             score_flush(a.out, cls, half, C, tf, valid);
         } else {
-            stream_tiles<TW, G, SC_NB, SC_NT>(a.frag[cls], t0, t1, lds,
-                                               [&](const uint4 *) __attribute__((always_inline)) {});
+            stream_tiles<TW, G, SP_NB, SC_NT>(a.frag[cls], t0, t1, lds,
+                                              [&](const uint4 *) __attribute__((always_inline)) {});
         }
     }
 }
@@ -1745,7 +1813,8 @@ bool launch_score_mfma_pruned(const ScoreModel &m, const uint16_t *codes, uint32
     const uint64_t tiles = (uint64_t)m.ftiles[0] + m.ftiles[1];
     const uint64_t bound = (tiles / rt + 2ull * L) * ((uint64_t)n_flows / SC_COLS + 1);
     if (bound >= (1ull << 31)) return false;
-    PruneWork w = prune_work(ws, L);
+    PruneWork w = prune_work(ws, L, n_flows, d);
+    IG_REQUIRE(((uintptr_t)w.ops & 15u) == 0, IG_E_INVAL, "scoring scratch must be 16-byte aligned");
     launch_prune_lists(codes, n_flows, d, meta, nbins, L, m.btile[0], m.btile[1], rt, SC_COLS, out, w, s);
     if (!tiles) return true;
     ScoreMfmaArgs a{};
@@ -1778,6 +1847,19 @@ bool launch_score_mfma_pruned(const ScoreModel &m, const uint16_t *codes, uint32
     };
     const int form = score_form(m, a);
     const void *kern = kernels[m.KO - 1][form];
+    const void *opk[8][3] = {
+#define IG_FOP(V) {(const void *)k_flow_operands<V, SF_PLAIN>, (const void *)k_flow_operands<V, SF_SPARE>, \
+                   (const void *)k_flow_operands<V, SF_TERN>},
+        IG_FOP(1) IG_FOP(2) IG_FOP(3) IG_FOP(4) IG_FOP(5) IG_FOP(6) IG_FOP(7) IG_FOP(8)
+#undef IG_FOP
+    };
+    {
+        uint4 *ops = w.ops;
+        void *oargs[] = {&a, &ops};
+        IG_HIP(hipLaunchKernel(opk[m.KO - 1][form], dim3((unsigned)((2ull * n_flows + 255) / 256)), dim3(256), oargs,
+                               0, s));
+    }
+    p.ops = w.ops;
     static std::atomic<uint32_t> slot_cache[8][3] = {};
     uint32_t slots = slot_cache[m.KO - 1][form].load(std::memory_order_relaxed);
     if (!slots) {

@@ -64,7 +64,15 @@ def test_noalloc_rejects_sizes_beyond_the_array():
     m = ig.fit(w.codes, w.labels, w.nbins)
     assert m.bucketed
     words = (8 << 20) // 4
-    n = (words - 5 * int(w.L) - 3) // int(w.d) + 1     # one flow too many
+    W = int(m.info().mfma_words)
+
+    def need(n):   # the call's scratch words: lists and units, then 2 W uint4 per flow
+        return (n * int(w.d) + 5 * int(w.L) + 3 + 3) // 4 * 4 + 8 * W * n
+
+    n = words // (int(w.d) + 8 * W)
+    while need(n) > words:
+        n -= 1
+    n += 1                                              # one flow too many
     say("oversize", n, "flows of", w.d)
     dc = torch.zeros((n, int(w.d)), dtype=torch.int16, device="cuda")
     out = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
