@@ -416,18 +416,21 @@ def main():
         torch.cuda.synchronize()
         log("warmup", i, "done")
     torch.cuda.synchronize()
-    models = []
+    # each step's model replaces the previous one (freed once the next fit has
+    # synchronised the stream, so its scoring is done); the stats are kept
+    fit_stats = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        models.append(step())
+        m = step()
+        fit_stats.append(m.stats())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     log("timed steps done: %.2f ms/step" % ms_per_step)
 
-    st = models[-1].stats()
-    npat = models[-1].n_patterns()
-    K = models[-1].K
+    st = fit_stats[-1]
+    npat = m.n_patterns()
+    K = m.K
     n_flows = w.test_codes.shape[0]
     # the method's subset tests: sum of t(b) in input order (from one untimed fit on the
     # early-exit path), |P^c| * n_c support tests and |P| * n_flows scoring tests
@@ -440,7 +443,7 @@ def main():
     tests_per_step = coh_tests + sup_tests + score_tests
     value = tests_per_step / (ms_per_step / 1e3)
     dense = st.distinct[0] * n_class[1] + st.distinct[1] * n_class[0]   # every (candidate, record) pair
-    info = models[-1].info()
+    info = m.info()
     on_mfma = info.fit_words > 0             # the matrix-core kernels ran (no early exit)
     buckets = bool(info.flags & ig.IG_MODEL_FIT_BUCKETS)
     # pairs the contractions examined: all of them, or those of each candidate's bucket
@@ -451,9 +454,9 @@ def main():
     W_score = int(info.mfma_words)
     # per-kernel device time: event pairs around each launch on its stream; two
     # launches (one per class) of each contraction per fit, one scoring launch per step
-    kcoh_ms = sum(mm.stats().kernel_ms[0] for mm in models) / len(models)
-    ksup_ms = sum(mm.stats().kernel_ms[1] for mm in models) / len(models)
-    score_ms = sum(a.elapsed_time(b) for a, b in score_ev[-len(models):]) / len(models)
+    kcoh_ms = sum(fs.kernel_ms[0] for fs in fit_stats) / len(fit_stats)
+    ksup_ms = sum(fs.kernel_ms[1] for fs in fit_stats) / len(fit_stats)
+    score_ms = sum(a.elapsed_time(b) for a, b in score_ev[-len(fit_stats):]) / len(fit_stats)
     peaks = None if args.no_peaks else measured_peaks()
     if peaks:
         log("measured peaks", peaks)
@@ -472,15 +475,15 @@ def main():
         kernels["k_contain_mfma[support]"] = dict(ms=ksup_ms, launches=2, tests=sup_tests, exec_tests=sup_tests,
                                                   tok=L_mfma, words=W_mfma)
     pruned = None
-    if models[-1].score_on_matrix_cores and models[-1].bucketed:
+    if m.score_on_matrix_cores and m.bucketed:
         # pruned scoring (the default): each flow meets the buckets of its tokens only.
         # Its work is sum over (class, bucket u) of |P^c_u| * F_u pattern-flow tests
         # (F_u = test flows holding token u); the tiles execute ceil(|P^c_u| / 32) * 32
         # rows against ceil(F_u / 256) * 256 columns.
-        pruned = pruned_work(models[-1], w.test_codes, w.nbins)
+        pruned = pruned_work(m, w.test_codes, w.nbins)
         kernels["k_score_mfma_pruned"] = dict(ms=score_ms, launches=1, tests=pruned["tests"],
                                               exec_tests=pruned["exec_tests"], tok=L_score, words=W_score)
-    elif models[-1].score_on_matrix_cores:
+    elif m.score_on_matrix_cores:
         kernels["k_score_mfma"] = dict(ms=score_ms, launches=1, tests=score_tests, exec_tests=score_tests,
                                        tok=L_score, words=W_score)
     for k, v in kernels.items():
@@ -529,7 +532,7 @@ def main():
                           for k, v in kernels.items()}
     if peaks:
         res["measured_peaks"] = peaks
-    del models
+    del m
     torch.cuda.synchronize()
     # fit alone, and from host arrays with the export; scoring alone
     res["fit_wall_s_15k"], res["fit_wall_s_15k_host_export"] = fit_wall(

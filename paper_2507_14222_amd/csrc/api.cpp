@@ -160,8 +160,7 @@ static void set_key_pieces(DevModel &m, const uint16_t *h_nbins, uint32_t d, hip
     const uint32_t nk = key_pieces(h_nbins, d, m.K, pc);
     if (!nk) return;
     m.pieces = dev_alloc<KeyPiece>(pc.size());
-    IG_HIP(hipMemcpyAsync(m.pieces, pc.data(), pc.size() * sizeof(KeyPiece), hipMemcpyHostToDevice, s));
-    IG_HIP(hipStreamSynchronize(s));   // pc must outlive its copy
+    upload(m.pieces, pc.data(), pc.size() * sizeof(KeyPiece), s);
     m.npieces = (uint32_t)pc.size();
     m.nkeys = nk;
 }
@@ -336,8 +335,7 @@ static void set_factor_table(DevModel &m, const uint16_t *h_nbins, uint32_t d, h
     const size_t o_ptok = put(ptok.data(), ptok.size() * 4, qb);
     char *dev = dev_alloc<char>(host.size());
     (ternary ? m.tfac : m.fac) = dev;
-    IG_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, s));
-    IG_HIP(hipStreamSynchronize(s));   // host must outlive its copy
+    upload(dev, host.data(), host.size(), s);
     FactorView &v = ternary ? m.tv : m.fv;
     v.mask = reinterpret_cast<const uint64_t *>(dev + o_mask);
     v.feat = reinterpret_cast<const FacFeature *>(dev + o_feat);
@@ -604,6 +602,20 @@ struct MfmaFit {
     // (bk[1 - c]) and the support (bk[c]) buckets
     Scratch<uint64_t> xr_coh[2], xr_sup[2];
     KernelClock clock;         // device times of the pruned contractions
+    // pairs the pruned contractions examined: coherence of class 0, 1, support of 0, 1
+    Scratch<unsigned long long> dtests;
+    unsigned long long htests[4] = {};
+    // queues the copy of dtests to htests (read it after the stream has synchronised)
+    void queue_tests(hipStream_t s) {
+        if (pruned) IG_HIP(hipMemcpyAsync(htests, dtests.get(), sizeof(htests), hipMemcpyDeviceToHost, s));
+    }
+    void put_tests(DevModel &m) const {
+        if (!pruned) return;
+        for (int c = 0; c < 2; ++c) {
+            m.stats.tests[c] = htests[c];
+            m.stats.support_tests[c] = htests[2 + c];
+        }
+    }
 };
 
 // Token buckets of both classes' records for the pruned contractions (ternary
@@ -657,7 +669,7 @@ static void build_fit_buckets(const DevModel &m, const ClassRows cls[2], MfmaFit
         ntiles[t] = bt[L + 1];
     }
     Scratch<uint32_t> dup(up.size(), s);
-    IG_HIP(hipMemcpyAsync(dup.get(), up.data(), up.size() * 4, hipMemcpyHostToDevice, s));
+    upload(dup.get(), up.data(), up.size() * 4, s);
     for (int t = 0; t < 2; ++t) {
         FitBuckets &b = mf.bk[t];
         const uint32_t *base = dup.get() + t * per;
@@ -672,11 +684,10 @@ static void build_fit_buckets(const DevModel &m, const ClassRows cls[2], MfmaFit
     mf.clock.keep.push_back(std::move(up));   // until its copy has run
 }
 
-// Candidates grouped by bucket (see launch_group_candidates): perm, first on the
-// device and first on the host.
+// Candidates grouped by bucket (see launch_group_candidates): perm and first on
+// the device (first [L + 2]: bucket starts).
 struct CandGroups {
     Scratch<uint32_t> perm, first;
-    std::vector<uint32_t> hf;
 };
 
 // Groups m candidates (pair ids `ids` of the records Xr [n][KSr], renumbered by the
@@ -692,48 +703,37 @@ static void group_candidates(const MfmaFit &mf, const FitBuckets &b, const uint6
     g.first.reset(L + 2, s);
     launch_group_candidates(Xr, n, mf.KSr, ids, W, KS, m, L, b.rank.get(), b.inv(), key.get(), g.perm.get(),
                             g.first.get(), ws.get(), s, ids_out);
-    g.hf = host_read_u32(g.first.get(), L + 2, s);
 }
 
-// The grouped candidates (perm: position -> row of B and of out, null for the
-// identity; first: bucket starts, on the device and the host) whose operand rows
-// are B, tested on the matrix cores against the records of their buckets in b
-// only: out[e] as launch_contain_mfma's (coherence flags, or support counts).
-// Returns the (candidate, record) pairs tested; adds the contraction's device time
-// to *kernel_ms.
-static uint64_t pruned_contain(MfmaFit &mf, const FitBuckets &b, const uint32_t *perm, const uint32_t *first,
-                               const std::vector<uint32_t> &hf, const uint64_t *B, bool count, uint32_t *out, int sets,
-                               float *kernel_ms, hipStream_t s) {
+// The m grouped candidates (perm: position -> row of B and of out, null for the
+// identity; first: bucket starts on the device) whose operand rows are B, tested on
+// the matrix cores against the records of their buckets in b only: out[e] as
+// launch_contain_mfma's (coherence flags, or support counts).  The work units are
+// counted on the device (no host round trip); the (candidate, record) pairs tested
+// are added to *tests (device), the contraction's device time to *kernel_ms.
+static void pruned_contain(MfmaFit &mf, const FitBuckets &b, const uint32_t *perm, const uint32_t *first, size_t m,
+                           const uint64_t *B, bool count, uint32_t *out, int sets, unsigned long long *tests,
+                           float *kernel_ms, hipStream_t s) {
     // the support count takes 8 per record lacking a candidate in 32 bits
     IG_REQUIRE(b.cnt.back() < (1u << 28), IG_E_UNSUPPORTED, "more than 2^28 records in one class");
+    if (!m) return;
     const uint32_t L = mf.L;
     const uint32_t cols = contain_pruned_cols((int)mf.KO, sets);
-    std::vector<uint32_t> uoff(L + 2, 0);   // then the bucket of each unit
-    uint64_t tests = 0;
-    for (uint32_t u = 0; u <= L; ++u) {
-        const uint32_t h = hf[u + 1] - hf[u];
-        uoff[u + 1] = uoff[u] + (h + cols - 1) / cols;
-        tests += (uint64_t)h * b.cnt[u];
-    }
-    const uint32_t units = uoff[L + 1];
-    if (!units) return tests;
-    for (uint32_t u = 0; u <= L; ++u)
-        for (uint32_t q = uoff[u]; q < uoff[u + 1]; ++q) uoff.push_back(u);
-    Scratch<uint32_t> uo(uoff.size(), s);
-    IG_HIP(hipMemcpyAsync(uo.get(), uoff.data(), uoff.size() * 4, hipMemcpyHostToDevice, s));
+    // units: at most ceil(count_u / cols) <= count_u / cols + 1 per bucket
+    const uint64_t bound = (m + cols - 1) / cols + L + 1;
+    IG_REQUIRE(bound < (1ull << 31), IG_E_UNSUPPORTED, "too many work units in one contraction");
+    Scratch<uint32_t> uo(L + 2, s);
+    launch_contain_plan(first, b.tab.get() + L + 2, L + 1, cols, uo.get(), tests, s);
     ContainBuckets k{};
     k.perm = perm;
     k.cs = first;
     k.uoff = uo.get();
-    k.ub = uo.get() + L + 2;
     k.bt = b.tab.get();
     k.brec = b.tab.get() + L + 2;
     k.nb = L + 1;
     KernelClock::Item &it = mf.clock.open(s, kernel_ms);
-    launch_contain_mfma_pruned((int)mf.KO, count, B, b.frag.get(), k, units, out, s, sets);
+    launch_contain_mfma_pruned((int)mf.KO, count, B, b.frag.get(), k, (uint32_t)bound, out, s, sets);
     mf.clock.close(it, s);
-    mf.clock.keep.push_back(std::move(uoff));   // until its copy has run
-    return tests;
 }
 
 // Rows of the coherent pair ids `ids` of one class (in the order given; in
@@ -743,7 +743,8 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
                             bool may_repeat, const Tuning &tu, hipStream_t s, Timer *tm = nullptr,
                             int support_mark = -1, const uint4 *own_frag = nullptr,
                             const FactorView &mfma_view = FactorView{}, PatternRows *keep = nullptr,
-                            Scratch<uint64_t> *pre_rows = nullptr, MfmaFit *pmf = nullptr) {
+                            Scratch<uint64_t> *pre_rows = nullptr, MfmaFit *pmf = nullptr,
+                            const uint32_t *pre_idx = nullptr) {
     const uint32_t KS = m.KS;
     if (count == 0) {
         m.np[c] = 0;
@@ -765,10 +766,14 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
                          sorted_ids.get());
         vcur = sorted_ids.get();
         if (pre_rows) {
+            // row of position p: pre_rows[pre_idx[perm[p]]] (pre_idx: the coherent
+            // candidates' rows among all of the coherence step's), or pre_rows[perm[p]]
             const uint32_t RWp = mfma_view.ternary ? 2 * mfma_view.KF : (mfma_view.KF ? mfma_view.KF : KS);
             Scratch<uint64_t> B2(count * RWp, s);
-            launch_gather_rows(pre_rows->get(), sg.perm.get(), count, RWp, RWp, B2.get(), nullptr, nullptr, s);
+            launch_gather_rows(pre_rows->get(), sg.perm.get(), count, RWp, RWp, B2.get(), nullptr, nullptr, s,
+                               pre_idx);
             *pre_rows = std::move(B2);
+            pre_idx = nullptr;
         }
     }
     if (may_repeat) {
@@ -809,7 +814,11 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         const uint32_t KO = mfma_view.KF ? mfma_view.KF : KS;
         const uint32_t RW = mfma_view.ternary ? 2 * KO : KO;
         Scratch<uint64_t> B;
-        if (pre_rows && !may_repeat) {
+        if (pre_rows && !may_repeat && pre_idx) {
+            // the coherence step's rows of these patterns, picked out in their order
+            B.reset(final_count * RW, s);
+            launch_gather_rows(pre_rows->get(), pre_idx, final_count, RW, RW, B.get(), nullptr, nullptr, s);
+        } else if (pre_rows && !may_repeat) {
             B = std::move(*pre_rows);   // the coherence step's rows of these patterns, same order
         } else {
             B.reset(final_count * RW, s);
@@ -826,12 +835,11 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
             (void)hipEventDestroy(ke[1]);
             if (!grouped)   // the rows of a chunked fit, grouped here
                 group_candidates(*pmf, pmf->bk[c], nullptr, cls.n, KS, nullptr, m.W[c], final_count, sg, s);
-            m.stats.support_tests[c] = pruned_contain(*pmf, pmf->bk[c], grouped ? nullptr : sg.perm.get(),
-                                                      sg.first.get(), sg.hf, B.get(), true, m.f[c], tu.sup_sets,
-                                                      &m.stats.kernel_ms[1], s);
+            pruned_contain(*pmf, pmf->bk[c], grouped ? nullptr : sg.perm.get(), sg.first.get(), final_count,
+                           B.get(), true, m.f[c], tu.sup_sets, pmf->dtests.get() + 2 + c, &m.stats.kernel_ms[1], s);
             launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
             // the scoring tiles take these buckets when the patterns are in their order
-            if (grouped) m.sgroup[c] = sg.hf;
+            if (grouped) m.sgroup[c] = host_read_u32(sg.first.get(), pmf->L + 2, s);
         } else {
             m.stats.support_tests[c] = (uint64_t)final_count * cls.n;
             IG_HIP(hipEventRecord(ke[0], s));
@@ -889,7 +897,7 @@ static Scratch<uint32_t> token_costs(const DevModel &m, const ClassRows *cls, hi
         for (uint32_t f = 0; f < m.d; ++f)
             for (uint32_t c = 0; c < nb[f]; ++c) h[t++] = 65536u - nb[f];
         std::copy(h.begin(), h.begin() + m.L, h.begin() + m.L);
-        IG_HIP(hipMemcpyAsync(cost.get(), h.data(), 2 * (size_t)m.L * 4, hipMemcpyHostToDevice, s));
+        upload(cost.get(), h.data(), 2 * (size_t)m.L * 4, s);
         IG_HIP(hipStreamSynchronize(s));
     }
     return cost;
@@ -942,10 +950,10 @@ static void bucketed_operands(DevModel &m, int c, const uint64_t *rows, uint32_t
     }
     const uint32_t ntiles = bt[L];
     m.btile[c] = dev_alloc<uint32_t>(L + 1);
-    IG_HIP(hipMemcpyAsync(m.btile[c], bt.data(), (L + 1) * 4, hipMemcpyHostToDevice, s));
+    upload(m.btile[c], bt.data(), (L + 1) * 4, s);
     // the rows of each bucket: for the tiles below and the evidence of a flow (ig_evidence)
     m.brow[c] = dev_alloc<uint32_t>(L + 1);
-    IG_HIP(hipMemcpyAsync(m.brow[c], br.data(), (L + 1) * 4, hipMemcpyHostToDevice, s));
+    upload(m.brow[c], br.data(), (L + 1) * 4, s);
     m.bperm[c] = dev_alloc<uint32_t>(np);
     if (P) IG_HIP(hipMemcpyAsync(m.bperm[c], P, np * 4, hipMemcpyDeviceToDevice, s));
     else launch_iota(m.bperm[c], np, s);
@@ -953,7 +961,6 @@ static void bucketed_operands(DevModel &m, int c, const uint64_t *rows, uint32_t
     m.frag[c] = dev_alloc<uint4>((size_t)std::max<uint32_t>(ntiles, 1) * (KO + 1) * 64);
     launch_mfma_patterns(rows, m.S[c], (uint32_t)np, KO, spare, tern, m.frag[c], s, P, m.btile[c], m.brow[c], L,
                          ntiles);
-    IG_HIP(hipStreamSynchronize(s));   // the host tables above are freed on return
 }
 
 static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr, const ClassRows *cls) {
@@ -1077,6 +1084,8 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
     if (mf.pruned) {
         mf.L = m.L;
         mf.KSr = (m.L + 63) / 64;
+        mf.dtests.reset(4, s);
+        launch_fill_u64(reinterpret_cast<uint64_t *>(mf.dtests.get()), 0ull, 4, s);
         build_fit_buckets(m, cls, mf, s);
         for (int c = 0; c < 2; ++c) {
             const size_t rows = std::max<size_t>(cls[c].n, 1) * mf.KSr;
@@ -1089,11 +1098,15 @@ static void mfma_setup(const DevModel &m, const ClassRows cls[2], uint32_t mode,
 }
 
 // Coherence of class c's ncand candidate pair ids `cand` on the matrix cores
-// (Eq. 3, dense): appends the coherent ids to `out` and returns how many
-// (synchronises the stream); adds the contraction's device time to *kernel_ms.
+// (Eq. 3): appends the coherent ids to `out` and returns how many (synchronises
+// the stream); adds the contraction's device time to *kernel_ms.  With rows_out,
+// the coherent candidates' operand rows are kept for support and scoring: on token
+// buckets every candidate's rows, with idx_out [kept] their positions in order;
+// otherwise only the coherent ones' rows, in order (idx_out left empty).
 static uint32_t mfma_coherence(MfmaFit &mf, const ClassRows cls[2], int c, uint32_t KS, const uint32_t *cand,
                                uint32_t ncand, uint32_t *out, float *kernel_ms, hipStream_t s,
-                               uint64_t *rows_out = nullptr, int sets = 0, uint64_t *tests = nullptr) {
+                               Scratch<uint64_t> *rows_out = nullptr, Scratch<uint32_t> *idx_out = nullptr,
+                               int sets = 0, uint64_t *tests = nullptr) {
     if (!ncand) return 0;
     Scratch<uint32_t> keep(ncand, s), kpos(ncand, s), ktot(1, s);
     Scratch<uint64_t> B((size_t)ncand * mf.RW, s);
@@ -1105,13 +1118,14 @@ static uint32_t mfma_coherence(MfmaFit &mf, const ClassRows cls[2], int c, uint3
         // the candidates against the other class's records that hold their bucket token
         CandGroups g;
         group_candidates(mf, mf.bk[1 - c], mf.xr_coh[c].get(), cls[c].n, KS, cand, nullptr, ncand, g, s);
-        const uint64_t t = pruned_contain(mf, mf.bk[1 - c], g.perm.get(), g.first.get(), g.hf, B.get(), false,
-                                          keep.get(), sets, kernel_ms, s);
-        if (tests) *tests += t;
+        pruned_contain(mf, mf.bk[1 - c], g.perm.get(), g.first.get(), ncand, B.get(), false, keep.get(), sets,
+                       mf.dtests.get() + c, kernel_ms, s);
         scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
-        launch_compact(keep.get(), kpos.get(), cand, ncand, out, s);
-        if (rows_out) launch_compact_rows(B.get(), keep.get(), kpos.get(), ncand, mf.RW, rows_out, s);
-        return host_read_u32(ktot.get(), 1, s)[0];
+        if (rows_out) idx_out->reset(ncand, s);
+        launch_compact(keep.get(), kpos.get(), cand, ncand, out, s, rows_out ? idx_out->get() : nullptr);
+        const uint32_t kept = host_read_u32(ktot.get(), 1, s)[0];
+        if (rows_out) *rows_out = std::move(B);
+        return kept;
     }
     if (tests) *tests += (uint64_t)ncand * cls[1 - c].n;
     hipEvent_t ke[2];
@@ -1131,7 +1145,10 @@ static uint32_t mfma_coherence(MfmaFit &mf, const ClassRows cls[2], int c, uint3
     scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
     launch_compact(keep.get(), kpos.get(), cand, ncand, out, s);
     // the coherent candidates' operand rows, in the same order (support and scoring use them)
-    if (rows_out) launch_compact_rows(B.get(), keep.get(), kpos.get(), ncand, mf.RW, rows_out, s);
+    if (rows_out) {
+        rows_out->reset((size_t)ncand * mf.RW, s);
+        launch_compact_rows(B.get(), keep.get(), kpos.get(), ncand, mf.RW, rows_out->get(), s);
+    }
     const uint32_t kept = host_read_u32(ktot.get(), 1, s)[0];
     float tk = 0;
     IG_HIP(hipEventElapsedTime(&tk, ke[0], ke[1]));
@@ -1206,8 +1223,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     {
         std::vector<unsigned char> h(2 * rows_of_seg_size());
         for (int c = 0; c < 2; ++c) fill_rows_of_seg(h.data() + c * rows_of_seg_size(), cls[c].X.get(), cls[c].n, KS, K);
-        IG_HIP(hipMemcpyAsync(rowsegs.get(), h.data(), h.size(), hipMemcpyHostToDevice, s));
-        IG_HIP(hipStreamSynchronize(s));
+        upload(rowsegs.get(), h.data(), h.size(), s);
     }
     const uint32_t grid = coherence_grid(tu.grid_per_cu);
     MfmaFit mf;
@@ -1221,6 +1237,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         m.fit_buckets = mf.pruned;
     }
     Scratch<uint64_t> surv_rows[2];   // operand rows of the coherent candidates (one-chunk fits)
+    Scratch<uint32_t> surv_idx[2];    // on token buckets: their positions among surv_rows
     uint64_t mfma_surv[2] = {0, 0}, mfma_tests[2] = {0, 0};
     float ms_pairs = 0, ms_sort = 0, ms_dedup = 0, ms_coh = 0;
     hipEvent_t e[5];
@@ -1303,13 +1320,10 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
             for (int c = 0; c < 2; ++c) {
                 const uint32_t *cc = cand.get() + (c == 0 ? 0 : hc[0]);
                 // one chunk: keep the survivors' operand rows for support and scoring
-                uint64_t *ro = nullptr;
-                if (chunks.size() == 1) {
-                    surv_rows[c].reset(std::max<size_t>(hc[c], 1) * mf.RW, s);
-                    ro = surv_rows[c].get();
-                }
+                const bool keep_rows = chunks.size() == 1;
                 mfma_surv[c] += mfma_coherence(mf, cls, c, KS, cc, hc[c], surv[c].get() + mfma_surv[c],
-                                               &m.stats.kernel_ms[0], s, ro, tu.coh_sets, &mfma_tests[c]);
+                                               &m.stats.kernel_ms[0], s, keep_rows ? &surv_rows[c] : nullptr,
+                                               keep_rows ? &surv_idx[c] : nullptr, tu.coh_sets, &mfma_tests[c]);
             }
             IG_HIP(hipEventRecord(e[4], s));
             IG_HIP(hipStreamSynchronize(s));
@@ -1361,7 +1375,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         }
         Scratch<CohSeg> dsegs(std::max<size_t>(hs.size(), 1), s);
         if (!hs.empty())
-            IG_HIP(hipMemcpyAsync(dsegs.get(), hs.data(), hs.size() * sizeof(CohSeg), hipMemcpyHostToDevice, s));
+            upload(dsegs.get(), hs.data(), hs.size() * sizeof(CohSeg), s);
         IG_HIP(hipEventRecord(e[3], s));   // brackets the coherence phases
         {
             uint32_t r_begin = 0;
@@ -1398,15 +1412,18 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
         // frag[1 - c] holds class c's own records (it is class 1-c's coherence operand)
         order_and_weigh(m, c, cls[c], surv[c].get(), hn[c], chunked, tu, s, &tm, c == 0 ? 5 : 8,
                         use_mfma ? mf.frag[1 - c].get() : nullptr, mf.view, &prow,
-                        surv_rows[c].get() ? &surv_rows[c] : nullptr, use_mfma ? &mf : nullptr);
+                        surv_rows[c].get() ? &surv_rows[c] : nullptr, use_mfma ? &mf : nullptr,
+                        surv_idx[c].get());
         m.stats.coherent[c] = m.np[c];
         if (c == 0) tm.mark(3);   // end of class 0's support
     }
     tm.mark(6);
     finish_weights(m, s, &prow, cls);
     tm.mark(7);
+    mf.queue_tests(s);
     IG_HIP(hipStreamSynchronize(s));
     mf.clock.collect();
+    mf.put_tests(m);
     m.stats.ms[1] = ms_pairs;
     m.stats.ms[2] = ms_sort;
     m.stats.ms[3] = ms_dedup;
@@ -1462,8 +1479,8 @@ DevModel *fit_codes(const uint16_t *d_codes, const uint8_t *d_labels, uint32_t n
     std::vector<uint32_t> tab = token_tables(h_nbins, d, (uint32_t)KS);
     m->meta = dev_alloc<uint32_t>(tab.size());
     m->nbins = dev_alloc<uint16_t>(d);
-    IG_HIP(hipMemcpyAsync(m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
-    IG_HIP(hipMemcpyAsync(m->nbins, h_nbins, d * 2, hipMemcpyHostToDevice, s));
+    upload(m->meta, tab.data(), tab.size() * 4, s);
+    upload(m->nbins, h_nbins, d * 2, s);
     set_key_pieces(*m, h_nbins, d, s);
     set_factor_table(*m, h_nbins, d, s);
     set_factor_table(*m, h_nbins, d, s, true);
@@ -1526,8 +1543,8 @@ DevModel *import_patterns(const uint16_t *const h_codes[2], const uint32_t *cons
     std::vector<uint32_t> tab = token_tables(h_nbins, d, (uint32_t)KS);
     m->meta = dev_alloc<uint32_t>(tab.size());
     m->nbins = dev_alloc<uint16_t>(d);
-    IG_HIP(hipMemcpyAsync(m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
-    IG_HIP(hipMemcpyAsync(m->nbins, h_nbins, d * 2, hipMemcpyHostToDevice, s));
+    upload(m->meta, tab.data(), tab.size() * 4, s);
+    upload(m->nbins, h_nbins, d * 2, s);
     set_factor_table(*m, h_nbins, d, s);
     set_factor_table(*m, h_nbins, d, s, true);
     for (int c = 0; c < 2; ++c) {
@@ -1542,8 +1559,8 @@ DevModel *import_patterns(const uint16_t *const h_codes[2], const uint32_t *cons
         Scratch<uint16_t> dc(cnt * d, s);
         Scratch<uint32_t> df(cnt, s), err(1, s), ids(cnt, s), v1(cnt, s), tot(1, s);
         Scratch<uint64_t> Wraw(cnt * KS, s), k0(cnt, s), k1(cnt, s);
-        IG_HIP(hipMemcpyAsync(dc.get(), h_codes[c], cnt * d * 2, hipMemcpyHostToDevice, s));
-        IG_HIP(hipMemcpyAsync(df.get(), h_f[c], cnt * 4, hipMemcpyHostToDevice, s));
+        upload(dc.get(), h_codes[c], cnt * d * 2, s);
+        upload(df.get(), h_f[c], cnt * 4, s);
         launch_fill_u32(err.get(), 0u, 1, s);
         launch_pack_patterns(dc.get(), (uint32_t)cnt, d, (uint32_t)KS, m->meta, m->nbins, Wraw.get(), err.get(), s);
         std::vector<uint32_t> he = host_read_u32(err.get(), 1, s);
@@ -1670,8 +1687,8 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
                 h.n = G[g]->cls[c].n;
                 h.n_o = G[g]->cls[1 - c].n;
             }
-        IG_HIP(hipMemcpyAsync(rowsegs.get(), hr.data(), hr.size(), hipMemcpyHostToDevice, s));
-        IG_HIP(hipMemcpyAsync(cohsegs.get(), hc.data(), hc.size() * sizeof(CohSeg), hipMemcpyHostToDevice, s));
+        upload(rowsegs.get(), hr.data(), hr.size(), s);
+        upload(cohsegs.get(), hc.data(), hc.size() * sizeof(CohSeg), s);
         IG_HIP(hipStreamSynchronize(s));   // nothing may be in flight on s when capture begins
     }
     const uint32_t grid = coherence_grid(tu.grid_per_cu);
@@ -1734,7 +1751,8 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
             const uint32_t sg = 2 * g + c;
             uint64_t t = 0;
             hsurv[sg] = mfma_coherence(mf[g], G[g]->cls, c, KS, cand.get() + hoff[sg], hdist[sg],
-                                       surv.get() + off[sg], &mfma_kernel[g], s, nullptr, tg.coh_sets, &t);
+                                       surv.get() + off[sg], &mfma_kernel[g], s, nullptr, nullptr, tg.coh_sets,
+                                       &t);
             htests[sg] = (unsigned long long)t;
         }
         mfma_ms[g] = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1762,7 +1780,9 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
         tm.mark(6);
         finish_weights(m, s, &prow, G[g]->cls);
         tm.mark(7);
+        mf[g].queue_tests(s);
         IG_HIP(hipStreamSynchronize(s));
+        mf[g].put_tests(m);
         record_times(m, tm);
         // the group's captured stages, split by this problem's share of the pairs
         const double share = group_pairs ? (double)G[g]->pairs() / (double)group_pairs : 0.0;
@@ -1804,9 +1824,8 @@ void fit_batch(const ig_problem *probs, uint32_t np, const ig_fit_opts *opts, hi
         std::vector<uint32_t> tab = token_tables(b.nbins, b.d, b.KS);
         b.m->meta = dev_alloc<uint32_t>(tab.size());
         b.m->nbins = dev_alloc<uint16_t>(b.d);
-        IG_HIP(hipMemcpyAsync(b.m->meta, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
-        IG_HIP(hipMemcpyAsync(b.m->nbins, b.nbins, b.d * 2, hipMemcpyHostToDevice, s));
-        IG_HIP(hipStreamSynchronize(s));   // the host table must outlive its copy
+        upload(b.m->meta, tab.data(), tab.size() * 4, s);
+        upload(b.m->nbins, b.nbins, b.d * 2, s);
         set_key_pieces(*b.m, b.nbins, b.d, s);
         set_factor_table(*b.m, b.nbins, b.d, s);
         set_factor_table(*b.m, b.nbins, b.d, s, true);

@@ -55,6 +55,9 @@ const ig_allocator *current_user_allocator();
 // runtime; the arena's sizes on the current device.
 void release_memory();
 void memory_stats(uint64_t *reserved, uint64_t *in_use, uint64_t *cached);
+// bytes from host memory to device memory, queued on s (the host memory may be
+// reused as soon as the call returns: small copies go through pinned staging)
+void upload(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 template <class T>
 struct Scratch {

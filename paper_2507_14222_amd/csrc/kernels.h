@@ -40,8 +40,9 @@ void launch_dedup_flags(const uint64_t *keys, const uint32_t *vals, size_t m, co
 // distinct candidates per segment from the exclusive scan `pos` (and its total)
 void launch_seg_counts(const uint64_t *keys, size_t m, const uint32_t *pos, const uint32_t *total, int segbits,
                        uint32_t nseg, uint32_t *seg_counts, hipStream_t s, uint32_t *seg_offsets = nullptr);
+// out[pos[e]] = vals[e] for the flagged e (and idx[pos[e]] = e when idx is given)
 void launch_compact(const uint32_t *flags, const uint32_t *pos, const uint32_t *vals, size_t m, uint32_t *out,
-                    hipStream_t s);
+                    hipStream_t s, uint32_t *idx = nullptr);
 void launch_gather_word(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t k, const uint32_t *ids, size_t m,
                         uint64_t *keys, hipStream_t s);
 void launch_word_range(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, const uint32_t *ids, size_t m,
@@ -50,8 +51,10 @@ void launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32
                         uint32_t *newflag, hipStream_t s);
 void launch_compact_rows(const uint64_t *W, const uint32_t *flags, const uint32_t *pos, size_t m, uint32_t KS,
                          uint64_t *out, hipStream_t s);
+// out row e = the first KD words of row r of W [.][KS], r = ids[e] (or ids2[ids[e]]);
+// fout[e] = fin[r] when fin is given
 void launch_gather_rows(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint32_t KD, uint64_t *out,
-                        const uint32_t *fin, uint32_t *fout, hipStream_t s);
+                        const uint32_t *fin, uint32_t *fout, hipStream_t s, const uint32_t *ids2 = nullptr);
 void launch_row_word(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint32_t k, uint64_t *keys,
                      hipStream_t s);
 void launch_iota(uint32_t *v, size_t m, hipStream_t s);
@@ -218,12 +221,17 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
 // uoff[nb].  out as launch_contain_mfma's.
 struct ContainBuckets {
     const uint32_t *perm, *cs, *uoff, *bt, *brec;
-    const uint32_t *ub;         // [units]: the bucket of each workgroup
     uint32_t nb;                // buckets
 };
 uint32_t contain_pruned_cols(int KO, int sets);
+// units: the grid, at least uoff[nb] (workgroups past it end at once)
 void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uint4 *frag, const ContainBuckets &k,
                                 uint32_t units, uint32_t *out, hipStream_t s, int sets = 0);
+// uoff [nb + 1] of the pruned contraction's work units from the bucket starts first
+// [nb + 1] and cols candidates per unit; *tests += the pairs it examines (nrec [nb]:
+// records per bucket)
+void launch_contain_plan(const uint32_t *first, const uint32_t *nrec, uint32_t nb, uint32_t cols, uint32_t *uoff,
+                         unsigned long long *tests, hipStream_t s);
 
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented
 // rows NX [n][KS] of their class.

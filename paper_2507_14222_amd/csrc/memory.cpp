@@ -15,6 +15,7 @@
 // scratch block of the call comes from it instead; a model remembers the
 // allocator and hands its buffers back to it when it is freed.
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -307,6 +308,82 @@ void scratch_free(void *p, hipStream_t s) noexcept {
     dm.cached.push_back({p, bytes, ev});
     dm.cached_bytes += bytes;
     if (dm.cached_bytes > kCacheCap) drop_cached(dm, kCacheCap / 2);
+}
+
+// ------------------------------------------------------------- uploads ----
+// Host tables go to the device through a pinned staging ring per device, so that
+// the copy is queued on the stream and the host goes on at once (a copy from
+// pageable memory returns only when the copy is done, which waits for the work
+// queued before it).  Each upload records an event; a range of the ring is taken
+// again only after the events of the uploads that used it have completed.
+namespace {
+constexpr size_t kRing = (size_t)8 << 20;   // bytes per device
+constexpr size_t kRingMax = kRing / 4;      // larger uploads are copied directly
+
+struct Pending {
+    size_t lo, hi;
+    hipEvent_t ev;
+};
+
+struct Ring {
+    std::mutex mu;
+    char *base = nullptr;
+    bool failed = false;
+    size_t head = 0;
+    std::vector<Pending> pending;   // in ring order
+    std::vector<hipEvent_t> spare;
+};
+
+Ring &ring(int d) {
+    static Ring *r = new Ring[kMaxDev];   // never destroyed: uploads may run at exit
+    return r[d];
+}
+}  // namespace
+
+void upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    const int d = current_device();
+    Ring &r = ring(d);
+    std::unique_lock<std::mutex> lock(r.mu);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(s, &cap);
+    if (!r.base && !r.failed && hipHostMalloc((void **)&r.base, kRing, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        r.base = nullptr;
+        r.failed = true;
+    }
+    if (!r.base || bytes > kRingMax || cap != hipStreamCaptureStatusNone) {
+        lock.unlock();
+        IG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+        return;
+    }
+    const size_t want = align_up(bytes, 256);
+    size_t lo = r.head;
+    if (lo + want > kRing) lo = 0;
+    const size_t hi = lo + want;
+    // wait for the uploads that used [lo, hi), oldest first
+    for (size_t i = 0; i < r.pending.size();) {
+        Pending &q = r.pending[i];
+        if (q.lo < hi && lo < q.hi) {
+            IG_HIP(hipEventSynchronize(q.ev));
+            r.spare.push_back(q.ev);
+            r.pending.erase(r.pending.begin() + (ptrdiff_t)i);
+        } else {
+            ++i;
+        }
+    }
+    std::memcpy(r.base + lo, src, bytes);
+    IG_HIP(hipMemcpyAsync(dst, r.base + lo, bytes, hipMemcpyHostToDevice, s));
+    hipEvent_t ev = nullptr;
+    if (!r.spare.empty()) {
+        ev = r.spare.back();
+        r.spare.pop_back();
+    } else {
+        IG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    IG_HIP(hipEventRecord(ev, s));
+    r.pending.push_back({lo, hi, ev});
+    r.head = hi;
 }
 
 void release_memory() {

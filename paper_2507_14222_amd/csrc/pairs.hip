@@ -307,9 +307,13 @@ __global__ void k_seg_counts(const uint64_t *__restrict__ keys, size_t m, const 
 }
 
 __global__ void k_compact(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
-                          const uint32_t *__restrict__ vals, size_t m, uint32_t *__restrict__ out) {
+                          const uint32_t *__restrict__ vals, size_t m, uint32_t *__restrict__ out,
+                          uint32_t *__restrict__ idx) {
     size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < m && flags[e]) out[pos[e]] = vals[e];
+    if (e < m && flags[e]) {
+        out[pos[e]] = vals[e];
+        if (idx) idx[pos[e]] = (uint32_t)e;
+    }
 }
 
 // key of word k of candidate q (for ordering): x_i[k] AND x_j[k]
@@ -406,12 +410,13 @@ __global__ void k_compact_rows(const uint64_t *__restrict__ W, const uint32_t *_
 // out [m][KD] = the first KD <= KS words of rows ids[e] of W [.][KS]
 __global__ void k_gather_rows(const uint64_t *__restrict__ W, const uint32_t *__restrict__ ids, size_t m,
                               uint32_t KS, uint32_t KD, uint64_t *__restrict__ out, const uint32_t *__restrict__ fin,
-                              uint32_t *__restrict__ fout) {
+                              uint32_t *__restrict__ fout, const uint32_t *__restrict__ ids2) {
     size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= m * KD) return;
     size_t e = g / KD, k = g % KD;
-    out[g] = W[(size_t)ids[e] * KS + k];
-    if (fin && k == 0) fout[e] = fin[ids[e]];
+    const uint32_t r = ids2 ? ids2[ids[e]] : ids[e];
+    out[g] = W[(size_t)r * KS + k];
+    if (fin && k == 0) fout[e] = fin[r];
 }
 
 __global__ void k_row_word(const uint64_t *__restrict__ W, const uint32_t *__restrict__ ids, size_t m, uint32_t KS,
@@ -537,9 +542,9 @@ void fill_rows_of_seg(void *dst, const uint64_t *X, uint32_t n, uint32_t KS, uin
 }
 
 void launch_compact(const uint32_t *flags, const uint32_t *pos, const uint32_t *vals, size_t m, uint32_t *out,
-                    hipStream_t s) {
+                    hipStream_t s, uint32_t *idx) {
     if (!m) return;
-    hipLaunchKernelGGL(k_compact, blocks_for(m), dim3(256), 0, s, flags, pos, vals, m, out);
+    hipLaunchKernelGGL(k_compact, blocks_for(m), dim3(256), 0, s, flags, pos, vals, m, out, idx);
     IG_HIP(hipGetLastError());
 }
 
@@ -580,10 +585,10 @@ void launch_compact_rows(const uint64_t *W, const uint32_t *flags, const uint32_
 }
 
 void launch_gather_rows(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t KS, uint32_t KD, uint64_t *out,
-                        const uint32_t *fin, uint32_t *fout, hipStream_t s) {
+                        const uint32_t *fin, uint32_t *fout, hipStream_t s, const uint32_t *ids2) {
     if (!m) return;
     IG_REQUIRE(KD >= 1 && KD <= KS, IG_E_INVAL, "gathered rows wider than the stored rows");
-    hipLaunchKernelGGL(k_gather_rows, blocks_for(m * KD), dim3(256), 0, s, W, ids, m, KS, KD, out, fin, fout);
+    hipLaunchKernelGGL(k_gather_rows, blocks_for(m * KD), dim3(256), 0, s, W, ids, m, KS, KD, out, fin, fout, ids2);
     IG_HIP(hipGetLastError());
 }
 

@@ -414,6 +414,40 @@ __device__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh) {
     return incl - v;
 }
 
+// Work units of a pruned contraction over nb buckets of grouped candidates (first
+// [nb + 1]: bucket starts, bucket u holding first[u + 1] - first[u] of them):
+// uoff[u] = the first unit of bucket u, an exclusive scan of ceil(count_u / cols)
+// (uoff[nb] = the total); *tests += sum over u of count_u * nrec[u], the
+// (candidate, record) pairs the contraction examines.  One workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_contain_plan(const uint32_t *__restrict__ first,
+                                                       const uint32_t *__restrict__ nrec, uint32_t nb, uint32_t cols,
+                                                       uint32_t *__restrict__ uoff,
+                                                       unsigned long long *__restrict__ tests) {
+    __shared__ uint32_t sh[1024];
+    const uint32_t tid = threadIdx.x, per = (nb + 1023) / 1024, b = tid * per;
+    auto units = [&](uint32_t u) { return (first[u + 1] - first[u] + cols - 1) / cols; };
+    uint32_t sum = 0;
+    unsigned long long t = 0;
+    for (uint32_t u = b; u < b + per && u < nb; ++u) {
+        sum += units(u);
+        t += (unsigned long long)(first[u + 1] - first[u]) * nrec[u];
+    }
+    uint32_t run = block_excl_scan(sum, sh);
+    for (uint32_t u = b; u < b + per && u < nb; ++u) {
+        uoff[u] = run;
+        run += units(u);
+    }
+    if (tid == 1023) uoff[nb] = run;   // the last thread's run ends at the total
+    if (t) atomicAdd(tests, t);
+}
+
+void launch_contain_plan(const uint32_t *first, const uint32_t *nrec, uint32_t nb, uint32_t cols, uint32_t *uoff,
+                         unsigned long long *tests, hipStream_t s) {
+    IG_REQUIRE(nb >= 1 && cols >= 1, IG_E_INVAL, "empty bucket plan");
+    hipLaunchKernelGGL(k_contain_plan, dim3(1), dim3(1024), 0, s, first, nrec, nb, cols, uoff, tests);
+    IG_HIP(hipGetLastError());
+}
+
 // One workgroup of 1024 threads.  foff = exclusive scan of cnt (L entries, plus the
 // total); cursor = foff; units of (class c, bucket u), index c * L + u:
 // ceil(tiles / rt) * ceil(cnt[u] / cols), 0 when either is 0; uoff = their

@@ -634,6 +634,22 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
     }
 }
 
+// The entry (bucket) that owns work unit `unit`: the last i < n2 with uoff[i] <= unit
+// (uoff ascends from uoff[0] = 0, and that entry's range is not empty).  The 64
+// lanes of one wave (all active, unit uniform) probe every stride-th entry, then
+// the entries of the block found: two rounds of loads instead of a binary search.
+__device__ __forceinline__ uint32_t unit_owner(const uint32_t *__restrict__ uoff, uint32_t n2, uint32_t unit) {
+    const uint32_t lane = threadIdx.x & 63, stride = (n2 + 63) / 64;
+    const uint32_t p = lane * stride;
+    const uint32_t k = (uint32_t)__popcll(__ballot(p < n2 && uoff[p] <= unit)) - 1u;
+    uint32_t cnt = 0;
+    for (uint32_t c = 0; c < stride; c += 64) {
+        const uint32_t q = k * stride + c + lane;
+        cnt += (uint32_t)__popcll(__ballot(c + lane < stride && q < n2 && uoff[q] <= unit));
+    }
+    return k * stride + cnt - 1u;
+}
+
 // The same contraction pruned by token buckets (ternary rows only).  A record can
 // contain a candidate only when it holds every token of it, in particular the
 // candidate's bucket token u (one of its tokens, chosen by the caller); the
@@ -643,7 +659,8 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma(const
 // Workgroup `unit` takes the candidates of bucket u with uoff[u] <= unit <
 // uoff[u + 1], block unit - uoff[u] of mf_cols<FB>() of them, against the tiles of
 // bucket u only: the results are those of k_contain_mfma against all records.
-
+// Workgroups at or past uoff[nb] (the grid is a bound set before the units are
+// counted on the device) end at once.
 template <int KS, bool COUNT, int FB>
 __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_pruned(const uint64_t *__restrict__ B,
                                                                                 const uint4 *__restrict__ frag,
@@ -653,7 +670,8 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
     __shared__ uint4 lds[ring_lds<KS * 64, G, MF_NB>()];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     const uint32_t unit = blockIdx.x;
-    const uint32_t u = k.ub[unit];   // uoff[u] <= unit < uoff[u + 1]
+    if (unit >= k.uoff[k.nb]) return;   // the grid is a bound on the units
+    const uint32_t u = unit_owner(k.uoff, k.nb, unit);   // uoff[u] <= unit < uoff[u + 1]
     const uint32_t c0 = k.cs[u] + (unit - k.uoff[u]) * mf_cols<FB>(), c1 = k.cs[u + 1];
     const uint32_t t0 = k.bt[u], t1 = k.bt[u + 1];
     v8i_t b[FB][KS];
@@ -664,14 +682,20 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
         const uint32_t e = c0 + wave * (FB * 32) + f * 32 + col;
         act[f] = e < c1;
         r[f] = act[f] ? (k.perm ? k.perm[e] : e) : 0u;
-        contain_operand<KS, true>(B, r[f], act[f], half, b[f]);
         best[f] = 0u;
     }
     // a wave without candidates only helps to stream the tiles (same loads and barriers)
     if (__builtin_amdgcn_readfirstlane(c0 + wave * (FB * 32) < c1 ? 1 : 0)) {
-        stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, t0, t1, lds, [&](const uint4 *tf) __attribute__((always_inline)) {
-            contain_tile<KS, COUNT, FB, true>(tf, lane, b, best, 1u);
-        });
+        // the candidates' operands are built while the first tiles load
+        stream_tiles_after<KS * 64, G, MF_NB, MF_NT>(
+            frag, t0, t1, lds,
+            [&]() __attribute__((always_inline)) {
+#pragma unroll
+                for (int f = 0; f < FB; ++f) contain_operand<KS, true>(B, r[f], act[f], half, b[f]);
+            },
+            [&](const uint4 *tf) __attribute__((always_inline)) {
+                contain_tile<KS, COUNT, FB, true>(tf, lane, b, best, 1u);
+            });
     } else {
         stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, t0, t1, lds, [&](const uint4 *) __attribute__((always_inline)) {});
     }
@@ -758,7 +782,7 @@ void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uin
     if (!units) return;
     IG_REQUIRE(KO >= 1 && KO <= 16, IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
     IG_REQUIRE(sets >= 0 && sets <= 3, IG_E_INVAL, "column sets per wave must be 0 (default) to 3");
-    IG_REQUIRE(k.nb >= 1 && k.cs && k.uoff && k.ub && k.bt && k.brec, IG_E_INVAL,
+    IG_REQUIRE(k.nb >= 1 && k.cs && k.uoff && k.bt && k.brec, IG_E_INVAL,
                "incomplete bucket tables");
     const int fb = pruned_sets(KO, sets);
 #define IG_CMP(V)                                                                             \
@@ -1161,22 +1185,6 @@ __global__ __launch_bounds__(256) void k_flow_operands(ScoreMfmaArgs a, uint4 *_
 #pragma unroll
     for (int k = 0; k < KS; ++k)
         ops[(size_t)g * KS + k] = uint4{(uint32_t)b[k][0], (uint32_t)b[k][1], (uint32_t)b[k][2], (uint32_t)b[k][3]};
-}
-
-// The (class, bucket) entry that owns `unit`: the last i < n2 with uoff[i] <= unit
-// (uoff ascends from uoff[0] = 0, and that entry's range is not empty).  The 64
-// lanes of one wave (all active, unit uniform) probe every stride-th entry, then
-// the entries of the block found: two rounds of loads instead of a binary search.
-__device__ __forceinline__ uint32_t unit_owner(const uint32_t *__restrict__ uoff, uint32_t n2, uint32_t unit) {
-    const uint32_t lane = threadIdx.x & 63, stride = (n2 + 63) / 64;
-    const uint32_t p = lane * stride;
-    const uint32_t k = (uint32_t)__popcll(__ballot(p < n2 && uoff[p] <= unit)) - 1u;
-    uint32_t cnt = 0;
-    for (uint32_t c = 0; c < stride; c += 64) {
-        const uint32_t q = k * stride + c + lane;
-        cnt += (uint32_t)__popcll(__ballot(c + lane < stride && q < n2 && uoff[q] <= unit));
-    }
-    return k * stride + cnt - 1u;
 }
 
 template <int KS, int SF>
