@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <deque>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -387,10 +388,12 @@ static void check_nbins(const uint16_t *h_nbins, uint32_t d, uint32_t &L, uint32
     K = (L + 63) / 64;
 }
 
+// n words from the device after the work queued on s (a copy that returns when it
+// is done, so the stream has reached it: no separate synchronisation)
 static std::vector<uint32_t> host_read_u32(const uint32_t *d, size_t n, hipStream_t s) {
     std::vector<uint32_t> h(n);
-    if (n) IG_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    IG_HIP(hipStreamSynchronize(s));
+    if (n) IG_HIP(hipMemcpyWithStream(h.data(), d, n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    else IG_HIP(hipStreamSynchronize(s));
     return h;
 }
 
@@ -544,7 +547,7 @@ struct KernelClock {
         hipEvent_t a = nullptr, b = nullptr;
         float *to = nullptr;
     };
-    std::vector<Item> items;
+    std::deque<Item> items;   // references to items stay valid as more are opened
     std::vector<std::vector<uint32_t>> keep;
     Item &open(hipStream_t s, float *to) {
         items.emplace_back();
@@ -1003,15 +1006,13 @@ static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr, co
     m.score_factored = sv.KF > 0;
     m.score_ternary = tern;
     m.score_spare = spare;
-    IG_HIP(hipStreamSynchronize(s));
 }
 
 static void finish_weights(DevModel &m, hipStream_t s, PatternRows *pr = nullptr, const ClassRows *cls = nullptr) {
     Scratch<unsigned long long> ms(4, s);
     for (int c = 0; c < 2; ++c) launch_reduce_maxsum(m.S[c], m.np[c], ms.get() + 2 * c, s);
     unsigned long long h[4];
-    IG_HIP(hipMemcpyAsync(h, ms.get(), sizeof(h), hipMemcpyDeviceToHost, s));
-    IG_HIP(hipStreamSynchronize(s));
+    IG_HIP(hipMemcpyWithStream(h, ms.get(), sizeof(h), hipMemcpyDeviceToHost, s));
     for (int c = 0; c < 2; ++c) {
         m.maxS[c] = (int64_t)h[2 * c];
         // A(x) and N(x) are sums of a subset of one class's weights (Eq. 4)
@@ -1316,7 +1317,8 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
             }
         }
         if (use_mfma) {
-            IG_HIP(hipEventRecord(e[3], s));
+            // stage time read when the fit ends (no synchronisation here)
+            KernelClock::Item &coh_it = mf.clock.open(s, &ms_coh);
             for (int c = 0; c < 2; ++c) {
                 const uint32_t *cc = cand.get() + (c == 0 ? 0 : hc[0]);
                 // one chunk: keep the survivors' operand rows for support and scoring
@@ -1325,11 +1327,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
                                                &m.stats.kernel_ms[0], s, keep_rows ? &surv_rows[c] : nullptr,
                                                keep_rows ? &surv_idx[c] : nullptr, tu.coh_sets, &mfma_tests[c]);
             }
-            IG_HIP(hipEventRecord(e[4], s));
-            IG_HIP(hipStreamSynchronize(s));
-            float tm34;
-            IG_HIP(hipEventElapsedTime(&tm34, e[3], e[4]));
-            ms_coh += tm34;
+            mf.clock.close(coh_it, s);
             continue;
         }
         // coherence in phases over the other class's records (input order); the
@@ -1395,8 +1393,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     tm.mark(4);
     std::vector<uint32_t> hn = host_read_u32(counters.get(), 2, s);
     unsigned long long ht[2];
-    IG_HIP(hipMemcpyAsync(ht, tests.get(), sizeof(ht), hipMemcpyDeviceToHost, s));
-    IG_HIP(hipStreamSynchronize(s));
+    IG_HIP(hipMemcpyWithStream(ht, tests.get(), sizeof(ht), hipMemcpyDeviceToHost, s));
     if (use_mfma)
         for (int c = 0; c < 2; ++c) {
             hn[c] = (uint32_t)mfma_surv[c];
@@ -1582,6 +1579,7 @@ DevModel *import_patterns(const uint16_t *const h_codes[2], const uint32_t *cons
         IG_REQUIRE(dup[0] == 0, IG_E_INVAL, "pattern set of class " + std::to_string(c) + " has repeated patterns");
     }
     finish_weights(*m, s);
+    IG_HIP(hipStreamSynchronize(s));   // the model is complete when it is returned
     return m.release();
 }
 
