@@ -961,7 +961,7 @@ static void bucketed_operands(DevModel &m, int c, const uint64_t *rows, uint32_t
     if (P) IG_HIP(hipMemcpyAsync(m.bperm[c], P, np * 4, hipMemcpyDeviceToDevice, s));
     else launch_iota(m.bperm[c], np, s);
     m.ftiles[c] = ntiles;
-    m.frag[c] = dev_alloc<uint4>((size_t)std::max<uint32_t>(ntiles, 1) * (KO + 1) * 64);
+    m.frag[c] = dev_alloc<uint4>((size_t)std::max<uint32_t>(ntiles, 1) * score_tile_words(KO));
     launch_mfma_patterns(rows, m.S[c], (uint32_t)np, KO, spare, tern, m.frag[c], s, P, m.btile[c], m.brow[c], L,
                          ntiles);
 }
@@ -1000,7 +1000,7 @@ static void build_score_operands(DevModel &m, hipStream_t s, PatternRows *pr, co
         }
         const uint64_t ntiles = (m.np[c] + 31) / 32;
         m.ftiles[c] = (uint32_t)ntiles;
-        m.frag[c] = dev_alloc<uint4>(std::max<uint64_t>(ntiles, 1) * (KO + 1) * 64);
+        m.frag[c] = dev_alloc<uint4>(std::max<uint64_t>(ntiles, 1) * score_tile_words(KO));
         launch_mfma_patterns(rows, m.S[c], (uint32_t)m.np[c], KO, spare, tern, m.frag[c], s);
     }
     m.score_factored = sv.KF > 0;

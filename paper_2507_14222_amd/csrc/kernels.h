@@ -297,10 +297,12 @@ PruneWork prune_work(uint32_t *ws, uint32_t L, uint32_t n_flows, uint32_t d);
 void launch_prune_lists(const uint16_t *codes, uint32_t n, uint32_t d, const uint32_t *off, const uint16_t *nbins,
                         uint32_t L, const uint32_t *bt0, const uint32_t *bt1, uint32_t rt, uint32_t cols,
                         int64_t *out, PruneWork &w, hipStream_t s);
+// uint4 per 32-pattern tile of the scoring operands at KO operand words
+constexpr uint32_t score_tile_words(uint32_t KO) { return KO * 64 + 8; }
 // Scoring on the matrix cores (KO <= 8, every weight < 2^28): each 32-pattern tile
 // of frag holds the patterns' operand rows (KO * 64 uint4, tokens as -1.0) and the
-// int8 operand of their 7-bit weight chunks (64 uint4): ceil(m/32) * (KO + 1) * 64
-// uint4 from launch_mfma_patterns.  Flows given as codes are factored like the
+// non-zero lanes of the int8 operand of their 7-bit weight chunks (8 uint4):
+// ceil(m/32) * score_tile_words(KO) uint4 from launch_mfma_patterns.  Flows given as codes are factored like the
 // patterns; flows given as words need one-hot operands (fv.KF = 0).
 // spare: the last token of the last word is used by no row; it then carries the
 // +1 that starts each containment count (flows hold 1 there), so the accumulators

@@ -419,6 +419,21 @@ __global__ void k_gather_rows(const uint64_t *__restrict__ W, const uint32_t *__
     if (fin && k == 0) fout[e] = fin[r];
 }
 
+// Whole rows of an even number of words, one thread per 16-byte piece (P pieces
+// per row): consecutive lanes read a row's pieces together and write contiguously.
+template <int P>
+__global__ void k_gather_rows16(const uint4 *__restrict__ W, const uint32_t *__restrict__ ids, size_t m,
+                                uint4 *__restrict__ out, const uint32_t *__restrict__ fin, uint32_t *__restrict__ fout,
+                                const uint32_t *__restrict__ ids2) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= m * P) return;
+    const size_t e = g / P;
+    const uint32_t k = (uint32_t)(g % P);
+    const uint32_t r = ids2 ? ids2[ids[e]] : ids[e];
+    out[g] = W[(size_t)r * P + k];
+    if (fin && k == 0) fout[e] = fin[r];
+}
+
 __global__ void k_row_word(const uint64_t *__restrict__ W, const uint32_t *__restrict__ ids, size_t m, uint32_t KS,
                            uint32_t k, uint64_t *__restrict__ keys) {
     size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -588,6 +603,21 @@ void launch_gather_rows(const uint64_t *W, const uint32_t *ids, size_t m, uint32
                         const uint32_t *fin, uint32_t *fout, hipStream_t s, const uint32_t *ids2) {
     if (!m) return;
     IG_REQUIRE(KD >= 1 && KD <= KS, IG_E_INVAL, "gathered rows wider than the stored rows");
+    if (KD == KS && KS % 2 == 0 && KS <= 32) {
+        const uint4 *W4 = reinterpret_cast<const uint4 *>(W);
+        uint4 *o4 = reinterpret_cast<uint4 *>(out);
+        switch (KS / 2) {
+#define IG_GR(P)                                                                                                   \
+    case P:                                                                                                        \
+        hipLaunchKernelGGL(k_gather_rows16<P>, blocks_for(m * P), dim3(256), 0, s, W4, ids, m, o4, fin, fout, ids2); \
+        IG_HIP(hipGetLastError());                                                                                 \
+        return;
+            IG_GR(1) IG_GR(2) IG_GR(3) IG_GR(4) IG_GR(5) IG_GR(6) IG_GR(7) IG_GR(8)
+            IG_GR(9) IG_GR(10) IG_GR(11) IG_GR(12) IG_GR(13) IG_GR(14) IG_GR(15) IG_GR(16)
+#undef IG_GR
+            default: break;
+        }
+    }
     hipLaunchKernelGGL(k_gather_rows, blocks_for(m * KD), dim3(256), 0, s, W, ids, m, KS, KD, out, fin, fout, ids2);
     IG_HIP(hipGetLastError());
 }

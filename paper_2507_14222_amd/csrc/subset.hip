@@ -250,19 +250,23 @@ __device__ __forceinline__ void wait_loads() {
     asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// LDS (uint4) of a ring: NB buffers of G tiles of TW uint4, plus the scratch slot
+// LDS (uint4) of a ring: NB buffers of G tiles of TW uint4 (each buffer rounded up
+// to whole 64-uint4 wave slices), plus the scratch slot
 template <int TW, int G, int NB>
-constexpr int ring_lds() { return NB * G * TW + 64; }
+constexpr int ring_stride() { return (G * TW + 63) / 64 * 64; }
+template <int TW, int G, int NB>
+constexpr int ring_lds() { return NB * ring_stride<TW, G, NB>() + 64; }
 
 template <int TW, int G, int NB, int NT, class Pre, class Body>
 __device__ __forceinline__ void stream_tiles_after(const uint4 *__restrict__ frag_in, uint32_t t0, uint32_t t1,
                                                    uint4 *lds_in, Pre pre, Body body) {
-    constexpr int N = G * TW;                 // uint4 per group
-    constexpr int PER = (N + NT - 1) / NT;    // loads per thread per group
+    constexpr int N = G * TW;                          // uint4 per group
+    constexpr int NS = ring_stride<TW, G, NB>();       // LDS uint4 per buffer (a whole number of slices)
+    constexpr int PER = (N + NT - 1) / NT;             // loads per thread per group
     static_assert(NB >= 2 && NB <= 4 && (NB - 2) * PER <= 63, "ring depth");
     const v4u_t *frag = reinterpret_cast<const v4u_t *>(frag_in);
     v4u_t *lds = reinterpret_cast<v4u_t *>(lds_in);
-    v4u_t *dummy = lds + NB * N;
+    v4u_t *dummy = lds + NB * NS;
     const uint32_t lane = threadIdx.x & 63, wave_base = threadIdx.x & ~63u;
     const uint32_t ng = (t1 - t0 + G - 1) / G;
     auto issue = [&](uint32_t gi) __attribute__((always_inline)) {
@@ -270,7 +274,7 @@ __device__ __forceinline__ void stream_tiles_after(const uint4 *__restrict__ fra
         const uint32_t avail = (t1 - t) * TW;
         const uint32_t last = (avail < (uint32_t)N ? avail : (uint32_t)N) - 1;
         const v4u_t *src = frag + (size_t)t * TW;
-        v4u_t *buf = lds + (gi % NB) * N;
+        v4u_t *buf = lds + (gi % NB) * NS;   // a slice that starts below N ends inside the buffer
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const uint32_t q0 = wave_base + i * NT;   // first slot of this wave's slice
@@ -295,7 +299,7 @@ __device__ __forceinline__ void stream_tiles_after(const uint4 *__restrict__ fra
         if (g + NB - 1 < ng) issue(g + NB - 1);
         const uint32_t t = t0 + g * G;
         const uint32_t nt = t1 - t < (uint32_t)G ? t1 - t : (uint32_t)G;
-        const uint4 *cur = lds_in + (g % NB) * N;
+        const uint4 *cur = lds_in + (g % NB) * NS;
         for (uint32_t j = 0; j < nt; ++j) body(cur + j * TW);
     }
 }
@@ -454,6 +458,26 @@ constexpr int MF_WAVES_PER_SIMD = 4;
 constexpr int MF_NB = IG_MF_NB;   // LDS ring depth
 template <int KS>
 constexpr int mf_group() { return IG_MF_GTOK / KS > 0 ? IG_MF_GTOK / KS : 1; }   // tiles per LDS buffer
+// The pruned contraction's workgroups: a work unit streams only its bucket's few
+// tiles, so a smaller ring and workgroup let more units overlap their set-up (4
+// waves and 4 tiles per buffer at 3 words: four workgroups per CU; measured at 15k
+// against 8 waves and 10 tiles: coherence 0.92 against 1.00 ms, support 0.68
+// against 0.72 ms)
+#ifndef IG_MFP_NT
+#define IG_MFP_NT 256
+#endif
+#ifndef IG_MFP_GTOK
+#define IG_MFP_GTOK 12
+#endif
+#ifndef IG_MFP_NB
+#define IG_MFP_NB IG_MF_NB
+#endif
+constexpr int MP_NT = IG_MFP_NT;
+constexpr int MP_NB = IG_MFP_NB;
+template <int KS>
+constexpr int mp_group() { return IG_MFP_GTOK / KS > 0 ? IG_MFP_GTOK / KS : 1; }
+template <int FB>
+constexpr int mp_cols() { return MP_NT / 64 * FB * 32; }
 
 // Bits [lo, hi) of a 128-bit string, as its 32-bit word j.
 __device__ __forceinline__ uint32_t bit_range_word(int lo, int hi, int j) {
@@ -657,22 +681,22 @@ __device__ __forceinline__ uint32_t unit_owner(const uint32_t *__restrict__ uoff
 // launch_bucket_tiles), and the candidates of bucket u are positions
 // [cs[u], cs[u + 1]) of the order perm (position -> row of B and of out).
 // Workgroup `unit` takes the candidates of bucket u with uoff[u] <= unit <
-// uoff[u + 1], block unit - uoff[u] of mf_cols<FB>() of them, against the tiles of
+// uoff[u + 1], block unit - uoff[u] of mp_cols<FB>() of them, against the tiles of
 // bucket u only: the results are those of k_contain_mfma against all records.
 // Workgroups at or past uoff[nb] (the grid is a bound set before the units are
 // counted on the device) end at once.
 template <int KS, bool COUNT, int FB>
-__global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_pruned(const uint64_t *__restrict__ B,
+__global__ __launch_bounds__(MP_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_pruned(const uint64_t *__restrict__ B,
                                                                                 const uint4 *__restrict__ frag,
                                                                                 ContainBuckets k,
                                                                                 uint32_t *__restrict__ out) {
-    constexpr int G = mf_group<KS>();
-    __shared__ uint4 lds[ring_lds<KS * 64, G, MF_NB>()];
+    constexpr int G = mp_group<KS>();
+    __shared__ uint4 lds[ring_lds<KS * 64, G, MP_NB>()];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     const uint32_t unit = blockIdx.x;
     if (unit >= k.uoff[k.nb]) return;   // the grid is a bound on the units
     const uint32_t u = unit_owner(k.uoff, k.nb, unit);   // uoff[u] <= unit < uoff[u + 1]
-    const uint32_t c0 = k.cs[u] + (unit - k.uoff[u]) * mf_cols<FB>(), c1 = k.cs[u + 1];
+    const uint32_t c0 = k.cs[u] + (unit - k.uoff[u]) * mp_cols<FB>(), c1 = k.cs[u + 1];
     const uint32_t t0 = k.bt[u], t1 = k.bt[u + 1];
     v8i_t b[FB][KS];
     uint32_t r[FB], best[FB];
@@ -687,7 +711,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
     // a wave without candidates only helps to stream the tiles (same loads and barriers)
     if (__builtin_amdgcn_readfirstlane(c0 + wave * (FB * 32) < c1 ? 1 : 0)) {
         // the candidates' operands are built while the first tiles load
-        stream_tiles_after<KS * 64, G, MF_NB, MF_NT>(
+        stream_tiles_after<KS * 64, G, MP_NB, MP_NT>(
             frag, t0, t1, lds,
             [&]() __attribute__((always_inline)) {
 #pragma unroll
@@ -697,7 +721,7 @@ __global__ __launch_bounds__(MF_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
                 contain_tile<KS, COUNT, FB, true>(tf, lane, b, best, 1u);
             });
     } else {
-        stream_tiles<KS * 64, G, MF_NB, MF_NT>(frag, t0, t1, lds, [&](const uint4 *) __attribute__((always_inline)) {});
+        stream_tiles<KS * 64, G, MP_NB, MP_NT>(frag, t0, t1, lds, [&](const uint4 *) __attribute__((always_inline)) {});
     }
     const uint32_t nrec = k.brec[u];
 #pragma unroll
@@ -766,15 +790,15 @@ static int pruned_sets(int KO, int sets) {
     return fb;
 }
 
-uint32_t contain_pruned_cols(int KO, int sets) { return (uint32_t)(MF_NT / 64 * 32 * pruned_sets(KO, sets)); }
+uint32_t contain_pruned_cols(int KO, int sets) { return (uint32_t)(MP_NT / 64 * 32 * pruned_sets(KO, sets)); }
 
 template <int V, int F>
 static void launch_cmp(bool count, const uint64_t *B, const uint4 *frag, const ContainBuckets &k, uint32_t units,
                        uint32_t *out, hipStream_t s) {
     if (count)
-        hipLaunchKernelGGL((k_contain_mfma_pruned<V, true, F>), dim3(units), dim3(MF_NT), 0, s, B, frag, k, out);
+        hipLaunchKernelGGL((k_contain_mfma_pruned<V, true, F>), dim3(units), dim3(MP_NT), 0, s, B, frag, k, out);
     else
-        hipLaunchKernelGGL((k_contain_mfma_pruned<V, false, F>), dim3(units), dim3(MF_NT), 0, s, B, frag, k, out);
+        hipLaunchKernelGGL((k_contain_mfma_pruned<V, false, F>), dim3(units), dim3(MP_NT), 0, s, B, frag, k, out);
 }
 
 void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uint4 *frag, const ContainBuckets &k,
@@ -809,8 +833,9 @@ void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uin
 // (r / 4) * 8 + 4 h + r % 4 of the 32-row tile.
 __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return (r >> 2) * 8 + half * 4 + (r & 3); }
 
-// Scoring operands of a pattern set: (KS + 1) * 64 uint4 per 32-row tile.
-//  words w < KS, frag[(tile * (KS + 1) + w) * 64 + lane]: the nibbles of half
+// Scoring operands of a pattern set: KS * 64 + 8 uint4 per 32-row tile
+// (score_tile_words).
+//  words w < KS, frag[tile * (KS * 64 + 8) + w * 64 + lane]: the nibbles of half
 //    (lane/32) of word w of row tile*32 + lane%32, as -1.0 (e2m1 0xA) per token
 //    (empty past m), so that an accumulator started at 1.0 ends at 1 - V: 1
 //    exactly when the pattern lies inside, at most 0 otherwise.  Ternary rows
@@ -818,12 +843,13 @@ __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return 
 //    ternary contraction instead, bias slots included, against flows on the
 //    record side: an accumulator started at 0 ends at 1 exactly when the pattern
 //    lies inside, at most -1 otherwise, and at 0 on the rows past m;
-//  slice KS, frag[(tile * (KS + 1) + KS) * 64 + lane]: the A operand of the
-//    weighting product (v_mfma_i32_32x32x32_i8): for lane%32 = c < 4 and half h,
-//    byte j holds 7-bit chunk c of the weight of the row in accumulator j of half h
-//    (0 past m); other lanes zero.
+//  then 8 uint4, frag[tile * (KS * 64 + 8) + KS * 64 + 4 h + c]: the lanes of the
+//    A operand of the weighting product (v_mfma_i32_32x32x32_i8) that are not
+//    zero, lane 32 h + c for c < 4: byte j holds 7-bit chunk c of the weight of the
+//    row in accumulator j of half h (0 past m); every other lane of that operand
+//    is zero.
 // One wave per 32-row tile (four per workgroup): lane l takes row l % 32 and half
-// l / 32 of every word, and each slice is one contiguous 1 KB store.  The weight
+// l / 32 of every word, and each word is one contiguous 1 KB store.  The weight
 // slice gathers the 16 rows of a lane's accumulators with lane shuffles.
 // With buckets, the tiles of bucket u are [bt[u], bt[u + 1]) and hold positions
 // [brow[u], brow[u + 1]) of the order perm (position e is row perm[e]), 32 per
@@ -847,7 +873,7 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
         in = pos < brow[u + 1];
     }
     const uint32_t row = in ? (perm ? perm[pos] : pos) : 0u;
-    uint4 *dst = frag + (size_t)tile * (KS + 1) * 64;
+    uint4 *dst = frag + (size_t)tile * score_tile_words(KS);
     const uint32_t RW = tern ? 2 * KS : KS;   // words per row
     const uint32_t *rw = reinterpret_cast<const uint32_t *>(W + (size_t)row * RW) + half;
     uint32_t np = 0;   // ternary: |P| of the row (both halves of the wave hold it)
@@ -895,7 +921,7 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
         const uint32_t chunk = r < 4 ? (uint32_t)(v >> (7 * r)) & 127u : 0u;
         q[j / 4] |= chunk << (8 * (j % 4));
     }
-    dst[KS * 64 + lane] = make_uint4(q[0], q[1], q[2], q[3]);
+    if (r < 4) dst[KS * 64 + half * 4 + r] = make_uint4(q[0], q[1], q[2], q[3]);
 }
 
 // tb[t] = the bucket u of tile t: bt[u] <= t < bt[u + 1] (the last such u).
@@ -1075,9 +1101,11 @@ __device__ __forceinline__ void score_tile(const uint4 *tile, int lane, const v8
         for (int f = 0; f < MF_FB; ++f)
             acc[f] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, b[f][w], acc[f], 4, 4, 0, 127, 0, 127);
     }
-    // weight chunks of this tile as the A operand (rows c < 4; other rows zero)
-    const uint4 q = tile[KS * 64 + lane];
-    const v4i_t wa = {(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+    // weight chunks of this tile as the A operand (lanes 32 h + c, c < 4; the
+    // other lanes zero)
+    const uint4 q = tile[KS * 64 + (lane >> 5) * 4 + (lane & 3)];
+    const bool wl = (lane & 31) < 4;
+    const v4i_t wa = {wl ? (int)q.x : 0, wl ? (int)q.y : 0, wl ? (int)q.z : 0, wl ? (int)q.w : 0};
 #pragma unroll
     for (int f = 0; f < MF_FB; ++f) {
         // inside = max(acc, 0) as a byte (1 or 0), accumulator r -> byte r
@@ -1118,7 +1146,7 @@ __device__ __forceinline__ void score_flush(int64_t *out, int cls, int half, con
 template <int KS, int SF>
 __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma(ScoreMfmaArgs a) {
     constexpr int G = sc_group<KS>();
-    constexpr int TW = (KS + 1) * 64;
+    constexpr int TW = KS * 64 + 8;
     __shared__ uint4 lds[ring_lds<TW, G, SC_NB>()];
     const uint32_t id = blockIdx.x, xcd = id % 8, seq = id / 8;
     const uint32_t range = (seq / a.fblocks) * 8 + xcd, fb = seq % a.fblocks;
@@ -1190,7 +1218,7 @@ __global__ __launch_bounds__(256) void k_flow_operands(ScoreMfmaArgs a, uint4 *_
 template <int KS, int SF>
 __global__ __launch_bounds__(SC_NT, SC_WPS) void k_score_mfma_pruned(ScoreMfmaArgs a, PruneArgs p) {
     constexpr int G = sp_group<KS>();
-    constexpr int TW = (KS + 1) * 64;
+    constexpr int TW = KS * 64 + 8;
     __shared__ uint4 lds[ring_lds<TW, G, SP_NB>()];
     __shared__ uint32_t s_unit[2], s_owner[2];
     const uint32_t total = p.uoff[2 * p.L];
