@@ -191,12 +191,21 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
 // entry (a scalar load) serves R rows.
 // TERN: ternary rows (P then V, 2 KO words): the pair keeps P_i AND P_j on the
 // features where V_i and V_j agree, and V_i on those.
+// With k.key: also each pair's bucket key, as k_cand_keys_rank computes it (the
+// pair is decoded and its records read here anyway).
+struct PairKeys {
+    const uint64_t *Xr;   // [n][KSr]: the records' tokens renumbered by rank
+    const uint16_t *inv;  // renumbered token -> token
+    uint32_t *key;        // [m] (null: no keys)
+    uint32_t KSr, L;
+};
+
 template <int KO, int R, bool TERN>
 __global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__restrict__ FR, uint32_t n,
                                                            const uint32_t *__restrict__ ids, size_t m,
                                                            const uint4 *__restrict__ wfe,
                                                            const uint32_t *__restrict__ wbeg,
-                                                           uint64_t *__restrict__ out) {
+                                                           uint64_t *__restrict__ out, PairKeys k) {
     constexpr int RW = TERN ? 2 * KO : KO;   // words per row
     const size_t T = (size_t)gridDim.x * blockDim.x;
     for (size_t e0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < m; e0 += T * R) {
@@ -207,18 +216,47 @@ __global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__re
             const size_t e = e0 + r * T;
             uint32_t i = 0, j = 0;
             if (e < m) decode_pair(ids[e], n, i, j);
+            if (TERN) {
+                // both rows as 16-byte loads (2 KO words each; rows are 16-byte aligned):
+                // half as many scattered loads as word by word
+                uint64_t wi[RW], wj[RW];
+                const uint4 *ri = reinterpret_cast<const uint4 *>(FR + (size_t)i * RW);
+                const uint4 *rj = reinterpret_cast<const uint4 *>(FR + (size_t)j * RW);
 #pragma unroll
-            for (int o = 0; o < KO; ++o) {
-                if (TERN) {
-                    const uint64_t va = FR[(size_t)i * RW + KO + o], vb = FR[(size_t)j * RW + KO + o];
-                    x[r][o] = va ^ vb;
-                    keep[r][o] = FR[(size_t)i * RW + o] & FR[(size_t)j * RW + o];
-                    val[r][TERN ? o : 0] = va;
-                } else {
+                for (int q = 0; q < KO; ++q) {
+                    const uint4 a = ri[q], b = rj[q];
+                    wi[2 * q] = (uint64_t)a.y << 32 | a.x;
+                    wi[2 * q + 1] = (uint64_t)a.w << 32 | a.z;
+                    wj[2 * q] = (uint64_t)b.y << 32 | b.x;
+                    wj[2 * q + 1] = (uint64_t)b.w << 32 | b.z;
+                }
+#pragma unroll
+                for (int o = 0; o < KO; ++o) {
+                    x[r][o] = wi[KO + o] ^ wj[KO + o];
+                    keep[r][o] = wi[o] & wj[o];
+                    val[r][TERN ? o : 0] = wi[KO + o];
+                }
+            } else {
+#pragma unroll
+                for (int o = 0; o < KO; ++o) {
                     const uint64_t a = FR[(size_t)i * KO + o], b = FR[(size_t)j * KO + o];
                     x[r][o] = a ^ b;
                     keep[r][o] = a & b;
                 }
+            }
+            if (k.key && e < m) {
+                // the token of lowest rank both records hold (L: none; after the row
+                // loads, so that both are in flight together)
+                const uint64_t *xi = k.Xr + (size_t)i * k.KSr, *xj = k.Xr + (size_t)j * k.KSr;
+                uint32_t best = k.L;
+                for (uint32_t w = 0; w < k.KSr; ++w) {
+                    const uint64_t a = xi[w] & xj[w];
+                    if (a) {
+                        best = k.inv[64 * w + (uint32_t)__builtin_ctzll(a)];
+                        break;
+                    }
+                }
+                k.key[e] = best;
             }
             D[r] = 0;
         }
@@ -256,20 +294,23 @@ __global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__re
 }
 
 void launch_pair_rows_factored(const uint64_t *FR, uint32_t n, const uint32_t *ids, size_t m, const FactorView &fv,
-                               uint64_t *out, hipStream_t s) {
+                               uint64_t *out, hipStream_t s, const uint64_t *Xr, uint32_t KSr, uint32_t L,
+                               const uint16_t *inv, uint32_t *key) {
     if (!m) return;
     IG_REQUIRE(fv.KF >= 1 && fv.KF <= 16 && fv.wfe && fv.wbeg && n > 0, IG_E_DEVICE,
                "factored pair rows without a token-range table");
     const size_t cap = (size_t)device_cus() * 8;
+    IG_REQUIRE(!key || (Xr && inv && KSr * 64 >= L), IG_E_INVAL, "pair keys need ranked records");
+    const PairKeys pk{Xr, inv, key, KSr, L};
 #define IG_PR(V, RR)                                                                                               \
     case V: {                                                                                                      \
         const dim3 grid((unsigned)std::min<size_t>((m + 256 * RR - 1) / (256 * RR), cap));                       \
         if (fv.ternary)                                                                                            \
             hipLaunchKernelGGL((k_pair_rows_factored<V, RR, true>), grid, dim3(256), 0, s, FR, n, ids, m, fv.wfe,  \
-                               fv.wbeg, out);                                                                      \
+                               fv.wbeg, out, pk);                                                                  \
         else                                                                                                       \
             hipLaunchKernelGGL((k_pair_rows_factored<V, RR, false>), grid, dim3(256), 0, s, FR, n, ids, m, fv.wfe, \
-                               fv.wbeg, out);                                                                      \
+                               fv.wbeg, out, pk);                                                                  \
         break;                                                                                                     \
     }
     switch (fv.KF) {

@@ -62,17 +62,44 @@ struct RowsOfSeg {
     uint32_t n, KS, K;
 };
 
+// b[u] = xi[k0 + u] AND xj[k0 + u] for the words k0 + u < K of two rows (0 past K;
+// k0 a multiple of 8).  vec (rows of an even number of words, so 16-byte aligned):
+// two words per load, half as many scattered loads (a word past K that is loaded
+// with its pair is still inside the row).
+__device__ __forceinline__ void rows_and8(const uint64_t *xi, const uint64_t *xj, uint32_t k0, uint32_t K, bool vec,
+                                          uint64_t (&b)[8]) {
+    if (vec) {
+        const uint4 *vi = reinterpret_cast<const uint4 *>(xi + k0), *vj = reinterpret_cast<const uint4 *>(xj + k0);
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            uint4 a = make_uint4(0, 0, 0, 0), c = a;
+            if (k0 + 2 * u < K) {
+                a = vi[u];
+                c = vj[u];
+            }
+            b[2 * u] = ((uint64_t)a.y << 32 | a.x) & ((uint64_t)c.y << 32 | c.x);
+            b[2 * u + 1] = k0 + 2 * u + 1 < K ? ((uint64_t)a.w << 32 | a.z) & ((uint64_t)c.w << 32 | c.z) : 0ull;
+        }
+    } else {
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) b[u] = k0 + u < K ? xi[k0 + u] & xj[k0 + u] : 0ull;
+    }
+}
+
 __device__ __forceinline__ bool same_candidate(const RowsOfSeg &r, uint32_t qa, uint32_t qb) {
     uint32_t ia, ja, ib, jb;
     decode_pair(qa, r.n, ia, ja);
     decode_pair(qb, r.n, ib, jb);
     const uint64_t *a0 = r.X + (size_t)ia * r.KS, *a1 = r.X + (size_t)ja * r.KS;
     const uint64_t *b0 = r.X + (size_t)ib * r.KS, *b1 = r.X + (size_t)jb * r.KS;
+    const bool vec = (r.KS & 1u) == 0;
     for (uint32_t k0 = 0; k0 < r.K; k0 += 8) {
-        uint64_t diff = 0;   // eight words of the four rows loaded together
+        uint64_t x[8], y[8];   // eight words of the four rows loaded together
+        rows_and8(a0, a1, k0, r.K, vec, x);
+        rows_and8(b0, b1, k0, r.K, vec, y);
+        uint64_t diff = 0;
 #pragma unroll
-        for (uint32_t u = 0; u < 8; ++u)
-            if (k0 + u < r.K) diff |= (a0[k0 + u] & a1[k0 + u]) ^ (b0[k0 + u] & b1[k0 + u]);
+        for (uint32_t u = 0; u < 8; ++u) diff |= x[u] ^ y[u];
         if (diff) return false;
     }
     return true;
@@ -143,10 +170,10 @@ __global__ __launch_bounds__(256) void k_pair_hash64(DedupArgs a, uint64_t items
     const uint64_t *xi = r.X + (size_t)i * r.KS, *xj = r.X + (size_t)j * r.KS;
     uint64_t hh = 0x9e3779b97f4a7c15ull ^ r.K;
     uint64_t any = 0;
+    const bool vec = (r.KS & 1u) == 0;
     for (uint32_t k0 = 0; k0 < r.K; k0 += 8) {
         uint64_t b[8];
-#pragma unroll
-        for (uint32_t u = 0; u < 8; ++u) b[u] = k0 + u < r.K ? xi[k0 + u] & xj[k0 + u] : 0ull;
+        rows_and8(xi, xj, k0, r.K, vec, b);
 #pragma unroll
         for (uint32_t u = 0; u < 8; ++u)
             if (k0 + u < r.K) {

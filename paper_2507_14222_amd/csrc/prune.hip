@@ -108,12 +108,15 @@ void launch_bucket_first(const uint64_t *key, size_t m, uint32_t *first, hipStre
 }
 
 // ---------------------------------------------------- fit contractions ----
-// Elements are grouped by key with one histogram per workgroup of BK_E elements
+// Elements are grouped by key with one histogram per workgroup of BK_T * iters elements
 // (whist, key-major: [key][workgroup]), whose exclusive scan gives each
 // (key, workgroup) its first output position; k_bucket_place then puts each
 // workgroup's elements there (their order inside a key is not fixed, and no
 // result depends on it).
-constexpr uint32_t BK_T = 256, BK_I = 8, BK_E = BK_T * BK_I;
+constexpr uint32_t BK_T = 256;
+// elements per thread: more for large inputs, so that there are fewer (key,
+// workgroup) cells to write, scan and read back
+static uint32_t bucket_iters(size_t m) { return m >= (1u << 22) ? 32u : 8u; }
 
 __device__ __forceinline__ void bucket_hist_out(uint32_t *h, uint32_t L, uint32_t *whist, uint32_t nwg) {
     __syncthreads();
@@ -171,34 +174,37 @@ __global__ void k_rank_rows(const uint64_t *__restrict__ X, uint32_t n, uint32_t
 
 // key[e] = the bucket of candidate e, the pair id ids[e] of records i, j: the
 // token inv[q] of the lowest renumbered token q both hold in Xr (L when none: the
-// empty set); per-workgroup histogram in whist.
-__global__ __launch_bounds__(BK_T) void k_cand_keys_rank(const uint64_t *__restrict__ Xr, uint32_t n, uint32_t KSr,
-                                                         const uint32_t *__restrict__ ids, size_t m, uint32_t L,
-                                                         const uint16_t *__restrict__ inv, uint32_t *__restrict__ key,
-                                                         uint32_t *__restrict__ whist, uint32_t nwg) {
+// empty set).  One thread per candidate (its loads wait on each other, so many
+// candidates in flight hide them); the histogram is a pass of its own.
+__global__ __launch_bounds__(256) void k_cand_keys_rank(const uint64_t *__restrict__ Xr, uint32_t n, uint32_t KSr,
+                                                        const uint32_t *__restrict__ ids, size_t m, uint32_t L,
+                                                        const uint16_t *__restrict__ inv, uint32_t *__restrict__ key) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    uint32_t i, j, best = L;
+    decode_pair(ids[e], n, i, j);
+    const uint64_t *xi = Xr + (size_t)i * KSr, *xj = Xr + (size_t)j * KSr;
+    for (uint32_t w = 0; w < KSr; ++w) {
+        const uint64_t x = xi[w] & xj[w];
+        if (x) {
+            best = inv[64 * w + (uint32_t)__builtin_ctzll(x)];
+            break;
+        }
+    }
+    key[e] = best;
+}
+
+// Per-workgroup histogram of the keys (key <= L) into whist.
+__global__ __launch_bounds__(BK_T) void k_key_hist(const uint32_t *__restrict__ key, size_t m, uint32_t L,
+                                                   uint32_t *__restrict__ whist, uint32_t nwg, uint32_t iters) {
     __shared__ uint32_t h[kMaxBuckets + 1];
     for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
     __syncthreads();
-    const size_t base = (size_t)blockIdx.x * BK_E;
-#pragma unroll 2
-    for (uint32_t it = 0; it < BK_I; ++it) {
+    const size_t base = (size_t)blockIdx.x * BK_T * iters;
+    for (uint32_t it = 0; it < iters; ++it) {
         const size_t e = base + (size_t)it * BK_T + threadIdx.x;
         const bool act = e < m;
-        uint32_t best = L;
-        if (act) {
-            uint32_t i, j;
-            decode_pair(ids[e], n, i, j);
-            const uint64_t *xi = Xr + (size_t)i * KSr, *xj = Xr + (size_t)j * KSr;
-            for (uint32_t w = 0; w < KSr; ++w) {
-                const uint64_t x = xi[w] & xj[w];
-                if (x) {
-                    best = inv[64 * w + (uint32_t)__builtin_ctzll(x)];
-                    break;
-                }
-            }
-            key[e] = best;
-        }
-        group_add(h, best, act);
+        group_add(h, act ? key[e] : L, act);
     }
     bucket_hist_out(h, L, whist, nwg);
 }
@@ -207,14 +213,14 @@ __global__ __launch_bounds__(BK_T) void k_cand_keys_rank(const uint64_t *__restr
 __global__ __launch_bounds__(BK_T) void k_row_keys_rank(const uint64_t *__restrict__ W, size_t m, uint32_t KS,
                                                         uint32_t L, const uint16_t *__restrict__ rank,
                                                         const uint16_t *__restrict__ inv, uint32_t *__restrict__ key,
-                                                        uint32_t *__restrict__ whist, uint32_t nwg) {
+                                                        uint32_t *__restrict__ whist, uint32_t nwg, uint32_t iters) {
     __shared__ uint32_t h[kMaxBuckets + 1];
     __shared__ uint16_t rk[kMaxBuckets];
     for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
     for (uint32_t u = threadIdx.x; u < L; u += BK_T) rk[u] = rank[u];
     __syncthreads();
-    const size_t base = (size_t)blockIdx.x * BK_E;
-    for (uint32_t it = 0; it < BK_I; ++it) {
+    const size_t base = (size_t)blockIdx.x * BK_T * iters;
+    for (uint32_t it = 0; it < iters; ++it) {
         const size_t e = base + (size_t)it * BK_T + threadIdx.x;
         const bool act = e < m;
         uint32_t best = L;
@@ -240,12 +246,12 @@ __global__ __launch_bounds__(BK_T) void k_row_keys_rank(const uint64_t *__restri
 // per-workgroup histogram in whist.
 __global__ __launch_bounds__(BK_T) void k_record_keys(const uint64_t *__restrict__ X, uint32_t n, uint32_t KS,
                                                       uint32_t L, uint32_t d, uint32_t *__restrict__ key,
-                                                      uint32_t *__restrict__ whist, uint32_t nwg) {
+                                                      uint32_t *__restrict__ whist, uint32_t nwg, uint32_t iters) {
     __shared__ uint32_t h[kMaxBuckets + 1];
     for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
     __syncthreads();
-    const size_t base = (size_t)blockIdx.x * BK_E, m = (size_t)n * d;
-    for (uint32_t it = 0; it < BK_I; ++it) {
+    const size_t base = (size_t)blockIdx.x * BK_T * iters, m = (size_t)n * d;
+    for (uint32_t it = 0; it < iters; ++it) {
         const size_t e = base + (size_t)it * BK_T + threadIdx.x;
         if (e >= m) break;
         const uint32_t r = (uint32_t)(e / d), k = (uint32_t)(e % d);
@@ -270,22 +276,22 @@ __global__ __launch_bounds__(BK_T) void k_record_keys(const uint64_t *__restrict
 }
 
 // out[pos[key][wg] + place] = e / div for the elements e of workgroup wg (pos:
-// the exclusive scan of whist), and out2 there = src[e] when src is given.
+// the exclusive scan of whist), and out2 there = src[e] when src is given.  The
+// workgroup's cursors start at its column of pos, so the place is the cursor.
 __global__ __launch_bounds__(BK_T) void k_bucket_place(const uint32_t *__restrict__ key, size_t m, uint32_t L,
                                                        const uint32_t *__restrict__ pos, uint32_t nwg, uint32_t div,
                                                        uint32_t *__restrict__ out, const uint32_t *__restrict__ src,
-                                                       uint32_t *__restrict__ out2) {
+                                                       uint32_t *__restrict__ out2, uint32_t iters) {
     __shared__ uint32_t h[kMaxBuckets + 1];
-    for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = 0;
+    for (uint32_t u = threadIdx.x; u <= L; u += BK_T) h[u] = pos[(size_t)u * nwg + blockIdx.x];
     __syncthreads();
-    const size_t base = (size_t)blockIdx.x * BK_E;
-    for (uint32_t it = 0; it < BK_I; ++it) {
+    const size_t base = (size_t)blockIdx.x * BK_T * iters;
+    for (uint32_t it = 0; it < iters; ++it) {
         const size_t e = base + (size_t)it * BK_T + threadIdx.x;
         const bool act = e < m;
         const uint32_t k = act ? key[e] : L;
-        const uint32_t r = group_add(h, k, act);
+        const uint32_t p = group_add(h, k, act);
         if (act) {
-            const size_t p = pos[(size_t)k * nwg + blockIdx.x] + r;
             out[p] = (uint32_t)(e / div);
             if (src) out2[p] = src[e];
         }
@@ -300,7 +306,10 @@ __global__ void k_bucket_starts(const uint32_t *__restrict__ pos, uint32_t nwg, 
     if (u == L + 1) first[u] = m;
 }
 
-uint32_t bucket_groups(size_t m) { return (uint32_t)((m + BK_E - 1) / BK_E); }
+uint32_t bucket_groups(size_t m) {
+    const size_t e = (size_t)BK_T * bucket_iters(m);
+    return (uint32_t)((m + e - 1) / e);
+}
 
 size_t bucket_ws_words(size_t m, uint32_t L) {
     const size_t cells = (size_t)(L + 1) * std::max<uint32_t>(bucket_groups(m), 1);
@@ -319,7 +328,9 @@ static void bucket_group(const uint32_t *key, size_t m, uint32_t L, uint32_t *wh
     scan_exclusive_u32(whist, pos, cells, nullptr, s, ws + 2 * cells);
     hipLaunchKernelGGL(k_bucket_starts, dim3((L + 2 + 255) / 256), dim3(256), 0, s, pos, nwg, L, (uint32_t)m, first);
     IG_HIP(hipGetLastError());
-    if (m) hipLaunchKernelGGL(k_bucket_place, dim3(nwg), dim3(BK_T), 0, s, key, m, L, pos, nwg, div, out, src, out2);
+    if (m)
+        hipLaunchKernelGGL(k_bucket_place, dim3(nwg), dim3(BK_T), 0, s, key, m, L, pos, nwg, div, out, src, out2,
+                           bucket_iters(m));
     IG_HIP(hipGetLastError());
 }
 
@@ -337,19 +348,24 @@ void launch_rank_rows(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, co
 void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const uint32_t *ids, const uint64_t *W,
                              uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, const uint16_t *inv,
                              uint32_t *key, uint32_t *perm, uint32_t *first, uint32_t *ws, hipStream_t s,
-                             uint32_t *ids_out) {
+                             uint32_t *ids_out, bool keys_given) {
     IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
-    IG_REQUIRE(inv && ((ids && Xr) || (!ids && W && rank)), IG_E_INVAL,
+    IG_REQUIRE(keys_given || (inv && ((ids && Xr) || (!ids && W && rank))), IG_E_INVAL,
                "candidates need pair ids and ranked records, or rows");
     const uint32_t nwg = std::max<uint32_t>(bucket_groups(m), 1);
     uint32_t *whist = ws;
     if (!m) {
         launch_fill_u32(whist, 0u, (size_t)(L + 1) * nwg, s);
+    } else if (keys_given) {
+        hipLaunchKernelGGL(k_key_hist, dim3(nwg), dim3(BK_T), 0, s, key, m, L, whist, nwg, bucket_iters(m));
     } else if (ids) {
-        hipLaunchKernelGGL(k_cand_keys_rank, dim3(nwg), dim3(BK_T), 0, s, Xr, n, KSr, ids, m, L, inv, key, whist,
-                           nwg);
+        hipLaunchKernelGGL(k_cand_keys_rank, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, Xr, n, KSr, ids, m,
+                           L, inv, key);
+        IG_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_key_hist, dim3(nwg), dim3(BK_T), 0, s, key, m, L, whist, nwg, bucket_iters(m));
     } else {
-        hipLaunchKernelGGL(k_row_keys_rank, dim3(nwg), dim3(BK_T), 0, s, W, m, KS, L, rank, inv, key, whist, nwg);
+        hipLaunchKernelGGL(k_row_keys_rank, dim3(nwg), dim3(BK_T), 0, s, W, m, KS, L, rank, inv, key, whist, nwg,
+                           bucket_iters(m));
     }
     IG_HIP(hipGetLastError());
     bucket_group(key, m, L, whist, 1, perm, first, ws, s, ids_out ? ids : nullptr, ids_out);
@@ -362,7 +378,9 @@ void launch_group_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L
     const uint32_t nwg = std::max<uint32_t>(bucket_groups(m), 1);
     uint32_t *whist = ws;
     if (!m) launch_fill_u32(whist, 0u, (size_t)(L + 1) * nwg, s);
-    else hipLaunchKernelGGL(k_record_keys, dim3(nwg), dim3(BK_T), 0, s, X, n, KS, L, d, key, whist, nwg);
+    else
+        hipLaunchKernelGGL(k_record_keys, dim3(nwg), dim3(BK_T), 0, s, X, n, KS, L, d, key, whist, nwg,
+                           bucket_iters(m));
     IG_HIP(hipGetLastError());
     bucket_group(key, m, L, whist, d, list, first, ws, s);
 }
