@@ -727,14 +727,12 @@ static void pruned_contain(MfmaFit &mf, const FitBuckets &b, const uint32_t *per
     const uint64_t bound = (m + cols - 1) / cols + L + 1;
     IG_REQUIRE(bound < (1ull << 31), IG_E_UNSUPPORTED, "too many work units in one contraction");
     Scratch<uint32_t> uo(L + 2, s);
-    launch_contain_plan(first, b.tab.get() + L + 2, L + 1, cols, uo.get(), tests, s);
+    Scratch<uint4> desc(2 * bound, s);
+    launch_contain_plan(first, b.tab.get() + L + 2, L + 1, cols, uo.get(), tests, s, b.tab.get(), (uint32_t)bound,
+                        desc.get());
     ContainBuckets k{};
     k.perm = perm;
-    k.cs = first;
-    k.uoff = uo.get();
-    k.bt = b.tab.get();
-    k.brec = b.tab.get() + L + 2;
-    k.nb = L + 1;
+    k.desc = desc.get();
     KernelClock::Item &it = mf.clock.open(s, kernel_ms);
     launch_contain_mfma_pruned((int)mf.KO, count, B, b.frag.get(), k, (uint32_t)bound, out, s, sets);
     mf.clock.close(it, s);

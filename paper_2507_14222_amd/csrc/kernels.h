@@ -223,8 +223,8 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
 // [bt[u], bt[u + 1]) of bucket u (brec[u] real records), u < nb.  units =
 // uoff[nb].  out as launch_contain_mfma's.
 struct ContainBuckets {
-    const uint32_t *perm, *cs, *uoff, *bt, *brec;
-    uint32_t nb;                // buckets
+    const uint32_t *perm;       // position -> candidate (null: the identity)
+    const uint4 *desc;          // [2 units]: each work unit's ranges (launch_contain_plan)
 };
 uint32_t contain_pruned_cols(int KO, int sets);
 // units: the grid, at least uoff[nb] (workgroups past it end at once)
@@ -232,9 +232,11 @@ void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uin
                                 uint32_t units, uint32_t *out, hipStream_t s, int sets = 0);
 // uoff [nb + 1] of the pruned contraction's work units from the bucket starts first
 // [nb + 1] and cols candidates per unit; *tests += the pairs it examines (nrec [nb]:
-// records per bucket)
+// records per bucket); with desc, the ranges of each of `bound` units (candidates,
+// record tiles bt [nb + 1], records), 2 uint4 per unit, empty past the last unit.
 void launch_contain_plan(const uint32_t *first, const uint32_t *nrec, uint32_t nb, uint32_t cols, uint32_t *uoff,
-                         unsigned long long *tests, hipStream_t s);
+                         unsigned long long *tests, hipStream_t s, const uint32_t *bt = nullptr, uint32_t bound = 0,
+                         uint4 *desc = nullptr);
 
 // Support f and weight S of m ordered patterns W [m][KS] against the complemented
 // rows NX [n][KS] of their class.

@@ -459,11 +459,40 @@ __global__ __launch_bounds__(1024) void k_contain_plan(const uint32_t *__restric
     if (t) atomicAdd(tests, t);
 }
 
+// desc[2 unit], desc[2 unit + 1] = the work unit's candidates [c0, c1), tiles
+// [t0, t1) and real records nrec, as (c0, c1, t0, t1), (nrec, 0, 0, 0); units at or
+// past uoff[nb] get c0 = c1 = 0 (nothing to do).  One thread per unit of the bound.
+__global__ void k_contain_units(const uint32_t *__restrict__ uoff, uint32_t nb, const uint32_t *__restrict__ first,
+                                const uint32_t *__restrict__ bt, const uint32_t *__restrict__ nrec, uint32_t cols,
+                                uint32_t bound, uint4 *__restrict__ desc) {
+    const uint32_t unit = blockIdx.x * blockDim.x + threadIdx.x;
+    if (unit >= bound) return;
+    if (unit >= uoff[nb]) {
+        desc[2 * (size_t)unit] = make_uint4(0, 0, 0, 0);
+        desc[2 * (size_t)unit + 1] = make_uint4(0, 0, 0, 0);
+        return;
+    }
+    uint32_t lo = 0, hi = nb;   // the last u with uoff[u] <= unit (its range is not empty)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (uoff[mid] <= unit) lo = mid;
+        else hi = mid;
+    }
+    const uint32_t c0 = first[lo] + (unit - uoff[lo]) * cols;
+    desc[2 * (size_t)unit] = make_uint4(c0, first[lo + 1], bt[lo], bt[lo + 1]);
+    desc[2 * (size_t)unit + 1] = make_uint4(nrec[lo], 0, 0, 0);
+}
+
 void launch_contain_plan(const uint32_t *first, const uint32_t *nrec, uint32_t nb, uint32_t cols, uint32_t *uoff,
-                         unsigned long long *tests, hipStream_t s) {
+                         unsigned long long *tests, hipStream_t s, const uint32_t *bt, uint32_t bound, uint4 *desc) {
     IG_REQUIRE(nb >= 1 && cols >= 1, IG_E_INVAL, "empty bucket plan");
     hipLaunchKernelGGL(k_contain_plan, dim3(1), dim3(1024), 0, s, first, nrec, nb, cols, uoff, tests);
     IG_HIP(hipGetLastError());
+    if (desc && bound) {
+        hipLaunchKernelGGL(k_contain_units, dim3((bound + 255) / 256), dim3(256), 0, s, uoff, nb, first, bt, nrec,
+                           cols, bound, desc);
+        IG_HIP(hipGetLastError());
+    }
 }
 
 // One workgroup of 1024 threads.  foff = exclusive scan of cnt (L entries, plus the

@@ -682,9 +682,10 @@ __device__ __forceinline__ uint32_t unit_owner(const uint32_t *__restrict__ uoff
 // [cs[u], cs[u + 1]) of the order perm (position -> row of B and of out).
 // Workgroup `unit` takes the candidates of bucket u with uoff[u] <= unit <
 // uoff[u + 1], block unit - uoff[u] of mp_cols<FB>() of them, against the tiles of
-// bucket u only: the results are those of k_contain_mfma against all records.
-// Workgroups at or past uoff[nb] (the grid is a bound set before the units are
-// counted on the device) end at once.
+// bucket u only: the results are those of k_contain_mfma against all records.  The
+// ranges of every unit are precomputed (desc, launch_contain_plan), so a workgroup
+// starts with one load; workgroups past the last unit (the grid is a bound set
+// before the units are counted on the device) find an empty range and end.
 template <int KS, bool COUNT, int FB>
 __global__ __launch_bounds__(MP_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_pruned(const uint64_t *__restrict__ B,
                                                                                 const uint4 *__restrict__ frag,
@@ -693,11 +694,9 @@ __global__ __launch_bounds__(MP_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
     constexpr int G = mp_group<KS>();
     __shared__ uint4 lds[ring_lds<KS * 64, G, MP_NB>()];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
-    const uint32_t unit = blockIdx.x;
-    if (unit >= k.uoff[k.nb]) return;   // the grid is a bound on the units
-    const uint32_t u = unit_owner(k.uoff, k.nb, unit);   // uoff[u] <= unit < uoff[u + 1]
-    const uint32_t c0 = k.cs[u] + (unit - k.uoff[u]) * mp_cols<FB>(), c1 = k.cs[u + 1];
-    const uint32_t t0 = k.bt[u], t1 = k.bt[u + 1];
+    const uint4 d = k.desc[2 * (size_t)blockIdx.x];
+    const uint32_t c0 = d.x, c1 = d.y, t0 = d.z, t1 = d.w;
+    if (c0 >= c1) return;   // past the last unit (the grid is a bound on the units)
     v8i_t b[FB][KS];
     uint32_t r[FB], best[FB];
     bool act[FB];
@@ -723,7 +722,7 @@ __global__ __launch_bounds__(MP_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
     } else {
         stream_tiles<KS * 64, G, MP_NB, MP_NT>(frag, t0, t1, lds, [&](const uint4 *) __attribute__((always_inline)) {});
     }
-    const uint32_t nrec = k.brec[u];
+    const uint32_t nrec = k.desc[2 * (size_t)blockIdx.x + 1].x;
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
         const uint32_t o = (uint32_t)__shfl_xor((int)best[f], 32, 64);
@@ -806,8 +805,7 @@ void launch_contain_mfma_pruned(int KO, bool count, const uint64_t *B, const uin
     if (!units) return;
     IG_REQUIRE(KO >= 1 && KO <= 16, IG_E_UNSUPPORTED, "the matrix-core subset tests handle up to 16 operand words");
     IG_REQUIRE(sets >= 0 && sets <= 3, IG_E_INVAL, "column sets per wave must be 0 (default) to 3");
-    IG_REQUIRE(k.nb >= 1 && k.cs && k.uoff && k.bt && k.brec, IG_E_INVAL,
-               "incomplete bucket tables");
+    IG_REQUIRE(k.desc != nullptr, IG_E_INVAL, "no work-unit ranges");
     const int fb = pruned_sets(KO, sets);
 #define IG_CMP(V)                                                                             \
     case V:                                                                                   \
