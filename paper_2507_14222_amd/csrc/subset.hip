@@ -858,17 +858,17 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
                                                       bool tern, const uint32_t *__restrict__ perm,
                                                       const uint32_t *__restrict__ bt,
                                                       const uint32_t *__restrict__ brow,
-                                                      const uint32_t *__restrict__ tb, uint4 *__restrict__ frag) {
+                                                      const uint2 *__restrict__ tr, uint4 *__restrict__ frag) {
     const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;   // uniform over the wave
     const uint32_t lane = threadIdx.x & 63, half = lane >> 5, r = lane & 31;
     uint32_t pos = tile * 32 + r;
     bool in = pos < m;
     if (bt) {
-        // the bucket u of the tile: bt[u] <= tile < bt[u + 1] (bt[0] = 0, bt[L] = ntiles)
-        const uint32_t u = tb[tile];
-        pos = brow[u] + (tile - bt[u]) * 32 + r;
-        in = pos < brow[u + 1];
+        // the tile's first position and the end of its bucket's positions
+        const uint2 t = tr[tile];
+        pos = t.x + r;
+        in = pos < t.y;
     }
     const uint32_t row = in ? (perm ? perm[pos] : pos) : 0u;
     uint4 *dst = frag + (size_t)tile * score_tile_words(KS);
@@ -923,16 +923,18 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
 }
 
 // tb[t] = the bucket u of tile t: bt[u] <= t < bt[u + 1] (the last such u).
-__global__ void k_tile_bucket(const uint32_t *__restrict__ bt, uint32_t L, uint32_t ntiles, uint32_t *__restrict__ tb) {
+__global__ void k_tile_bucket(const uint32_t *__restrict__ bt, const uint32_t *__restrict__ brow, uint32_t L,
+                              uint32_t ntiles, uint2 *__restrict__ tr) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
+    // the bucket u of the tile: bt[u] <= t < bt[u + 1] (bt[0] = 0, bt[L] = ntiles)
     uint32_t lo = 0, hi = L;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) / 2;
         if (bt[mid] <= t) lo = mid;
         else hi = mid;
     }
-    tb[t] = lo;
+    tr[t] = make_uint2(brow[lo] + (t - bt[lo]) * 32, brow[lo + 1]);
 }
 
 // Scoring workgroups: SC_NT threads, at most SC_WPS waves per SIMD (the weighting
@@ -1294,14 +1296,14 @@ void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint3
     IG_REQUIRE(KS >= 1 && KS <= 8, IG_E_UNSUPPORTED, "matrix-core scoring operands of more than 8 words");
     IG_REQUIRE(!bt || (brow && L >= 1), IG_E_INVAL, "bucket tiles without bucket rows");
     IG_REQUIRE(!(spare && tern), IG_E_INVAL, "ternary scoring operands take no spare token");
-    Scratch<uint32_t> tb;
+    Scratch<uint2> tr;
     if (bt) {
-        tb.reset(ntiles, s);
-        hipLaunchKernelGGL(k_tile_bucket, dim3((ntiles + 255) / 256), dim3(256), 0, s, bt, L, ntiles, tb.get());
+        tr.reset(ntiles, s);
+        hipLaunchKernelGGL(k_tile_bucket, dim3((ntiles + 255) / 256), dim3(256), 0, s, bt, brow, L, ntiles, tr.get());
         IG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_mfma_patterns, dim3((ntiles + 3) / 4), dim3(256), 0, s, W, S, m, KS, ntiles, spare, tern,
-                       perm, bt, brow, tb.get(), frag);
+                       perm, bt, brow, tr.get(), frag);
     IG_HIP(hipGetLastError());
 }
 
