@@ -717,7 +717,7 @@ static void group_candidates(const MfmaFit &mf, const FitBuckets &b, const uint6
 // are added to *tests (device), the contraction's device time to *kernel_ms.
 static void pruned_contain(MfmaFit &mf, const FitBuckets &b, const uint32_t *perm, const uint32_t *first, size_t m,
                            const uint64_t *B, bool count, uint32_t *out, int sets, unsigned long long *tests,
-                           float *kernel_ms, hipStream_t s) {
+                           float *kernel_ms, hipStream_t s, bool by_position = false) {
     // the support count takes 8 per record lacking a candidate in 32 bits
     IG_REQUIRE(b.cnt.back() < (1u << 28), IG_E_UNSUPPORTED, "more than 2^28 records in one class");
     if (!m) return;
@@ -733,6 +733,7 @@ static void pruned_contain(MfmaFit &mf, const FitBuckets &b, const uint32_t *per
     ContainBuckets k{};
     k.perm = perm;
     k.desc = desc.get();
+    k.by_position = by_position;
     KernelClock::Item &it = mf.clock.open(s, kernel_ms);
     launch_contain_mfma_pruned((int)mf.KO, count, B, b.frag.get(), k, (uint32_t)bound, out, s, sets);
     mf.clock.close(it, s);
@@ -1123,11 +1124,13 @@ static uint32_t mfma_coherence(MfmaFit &mf, const ClassRows cls[2], int c, uint3
         CandGroups g;
         group_candidates(mf, mf.bk[1 - c], mf.xr_coh[c].get(), cls[c].n, KS, cand, nullptr, ncand, g, s, nullptr,
                          ckey.get());
+        // flags in bucket order (coalesced stores); the coherent ids come out in that order
         pruned_contain(mf, mf.bk[1 - c], g.perm.get(), g.first.get(), ncand, B.get(), false, keep.get(), sets,
-                       mf.dtests.get() + c, kernel_ms, s);
+                       mf.dtests.get() + c, kernel_ms, s, true);
         scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
         if (rows_out) idx_out->reset(ncand, s);
-        launch_compact(keep.get(), kpos.get(), cand, ncand, out, s, rows_out ? idx_out->get() : nullptr);
+        launch_compact(keep.get(), kpos.get(), cand, ncand, out, s, rows_out ? idx_out->get() : nullptr,
+                       g.perm.get());
         const uint32_t kept = host_read_u32(ktot.get(), 1, s)[0];
         if (rows_out) *rows_out = std::move(B);
         return kept;

@@ -40,9 +40,10 @@ void launch_dedup_flags(const uint64_t *keys, const uint32_t *vals, size_t m, co
 // distinct candidates per segment from the exclusive scan `pos` (and its total)
 void launch_seg_counts(const uint64_t *keys, size_t m, const uint32_t *pos, const uint32_t *total, int segbits,
                        uint32_t nseg, uint32_t *seg_counts, hipStream_t s, uint32_t *seg_offsets = nullptr);
-// out[pos[e]] = vals[e] for the flagged e (and idx[pos[e]] = e when idx is given)
+// out[pos[e]] = vals[e] for the flagged e (and idx[pos[e]] = e when idx is given);
+// with perm, element e stands for perm[e]: out[pos[e]] = vals[perm[e]], idx = perm[e]
 void launch_compact(const uint32_t *flags, const uint32_t *pos, const uint32_t *vals, size_t m, uint32_t *out,
-                    hipStream_t s, uint32_t *idx = nullptr);
+                    hipStream_t s, uint32_t *idx = nullptr, const uint32_t *perm = nullptr);
 void launch_gather_word(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t k, const uint32_t *ids, size_t m,
                         uint64_t *keys, hipStream_t s);
 void launch_word_range(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, const uint32_t *ids, size_t m,
@@ -225,6 +226,7 @@ void launch_contain_mfma(int KO, bool count, const uint64_t *B, size_t m, const 
 struct ContainBuckets {
     const uint32_t *perm;       // position -> candidate (null: the identity)
     const uint4 *desc;          // [2 units]: each work unit's ranges (launch_contain_plan)
+    bool by_position;           // out[position] instead of out[candidate] (coalesced stores)
 };
 uint32_t contain_pruned_cols(int KO, int sets);
 // units: the grid, at least uoff[nb] (workgroups past it end at once)

@@ -335,11 +335,12 @@ __global__ void k_seg_counts(const uint64_t *__restrict__ keys, size_t m, const 
 
 __global__ void k_compact(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
                           const uint32_t *__restrict__ vals, size_t m, uint32_t *__restrict__ out,
-                          uint32_t *__restrict__ idx) {
+                          uint32_t *__restrict__ idx, const uint32_t *__restrict__ perm) {
     size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < m && flags[e]) {
-        out[pos[e]] = vals[e];
-        if (idx) idx[pos[e]] = (uint32_t)e;
+        const uint32_t v = perm ? perm[e] : (uint32_t)e;
+        out[pos[e]] = vals[v];
+        if (idx) idx[pos[e]] = v;
     }
 }
 
@@ -584,9 +585,9 @@ void fill_rows_of_seg(void *dst, const uint64_t *X, uint32_t n, uint32_t KS, uin
 }
 
 void launch_compact(const uint32_t *flags, const uint32_t *pos, const uint32_t *vals, size_t m, uint32_t *out,
-                    hipStream_t s, uint32_t *idx) {
+                    hipStream_t s, uint32_t *idx, const uint32_t *perm) {
     if (!m) return;
-    hipLaunchKernelGGL(k_compact, blocks_for(m), dim3(256), 0, s, flags, pos, vals, m, out, idx);
+    hipLaunchKernelGGL(k_compact, blocks_for(m), dim3(256), 0, s, flags, pos, vals, m, out, idx, perm);
     IG_HIP(hipGetLastError());
 }
 

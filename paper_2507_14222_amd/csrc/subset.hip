@@ -699,11 +699,13 @@ __global__ __launch_bounds__(MP_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
     if (c0 >= c1) return;   // past the last unit (the grid is a bound on the units)
     v8i_t b[FB][KS];
     uint32_t r[FB], best[FB];
+    uint32_t pos[FB];
     bool act[FB];
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
         const uint32_t e = c0 + wave * (FB * 32) + f * 32 + col;
         act[f] = e < c1;
+        pos[f] = e;
         r[f] = act[f] ? (k.perm ? k.perm[e] : e) : 0u;
         best[f] = 0u;
     }
@@ -727,7 +729,7 @@ __global__ __launch_bounds__(MP_NT, MF_WAVES_PER_SIMD) void k_contain_mfma_prune
     for (int f = 0; f < FB; ++f) {
         const uint32_t o = (uint32_t)__shfl_xor((int)best[f], 32, 64);
         const uint32_t h = COUNT ? nrec - (best[f] + o) / 8u : (max((int)best[f], (int)o) > 0 ? 0u : 1u);
-        if (half == 0 && act[f]) out[r[f]] = h;
+        if (half == 0 && act[f]) out[k.by_position ? pos[f] : r[f]] = h;
     }
 }
 
