@@ -45,24 +45,24 @@ HBM_PEAK_GBS = 8000.0
 
 
 def counted_traffic(path, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
-    or None when the summary is missing, covers another kernel, or the kernel
-    source changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (a line "bytes_per_launch[<kernel>]: N" per kernel), or None when the summary is
+    missing, does not cover the kernel, or the kernel source changed since the
+    counters were taken."""
     import hashlib
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line and not line.startswith(" "):
+        if ":" in line and not line.startswith(" ") and not line.startswith("|"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_2507_14222_amd", "csrc", "subset.hip")
     now = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if vals.get("kernel_source_sha256_16") != now or "bytes_per_launch" not in vals:
+    if vals.get("kernel_source_sha256_16") != now:
         return None
-    if vals.get("kernel") != kernel:
-        return None
-    return int(vals["bytes_per_launch"])
+    v = vals.get("bytes_per_launch[%s]" % kernel)
+    return int(v) if v else None
 
 
 def measure_batch():
