@@ -608,9 +608,11 @@ struct MfmaFit {
     // pairs the pruned contractions examined: coherence of class 0, 1, support of 0, 1
     Scratch<unsigned long long> dtests;
     unsigned long long htests[4] = {};
-    // queues the copy of dtests to htests (read it after the stream has synchronised)
-    void queue_tests(hipStream_t s) {
-        if (pruned) IG_HIP(hipMemcpyAsync(htests, dtests.get(), sizeof(htests), hipMemcpyDeviceToHost, s));
+    // waits for the stream: copies dtests to htests when pruned (a copy that
+    // returns when the stream has reached it), else synchronises
+    void finish(hipStream_t s) {
+        if (pruned) IG_HIP(hipMemcpyWithStream(htests, dtests.get(), sizeof(htests), hipMemcpyDeviceToHost, s));
+        else IG_HIP(hipStreamSynchronize(s));
     }
     void put_tests(DevModel &m) const {
         if (!pruned) return;
@@ -676,10 +678,13 @@ static void build_fit_buckets(const DevModel &m, const ClassRows cls[2], MfmaFit
     for (int t = 0; t < 2; ++t) {
         FitBuckets &b = mf.bk[t];
         const uint32_t *base = dup.get() + t * per;
+        const uint32_t *hbase = up.data() + t * per;
         b.rank.reset(2 * (size_t)L, s);
         b.tab.reset(2 * (size_t)L + 3, s);
-        IG_HIP(hipMemcpyAsync(b.rank.get(), base, 2 * (size_t)L * 2, hipMemcpyDeviceToDevice, s));
-        IG_HIP(hipMemcpyAsync(b.tab.get(), base + L + L + 2, (2 * (size_t)L + 3) * 4, hipMemcpyDeviceToDevice, s));
+        // from the host tables through the staging ring (a device-to-device copy
+        // here cost as much host time as a synchronisation)
+        upload(b.rank.get(), hbase, 2 * (size_t)L * 2, s);
+        upload(b.tab.get(), hbase + L + L + 2, (2 * (size_t)L + 3) * 4, s);
         b.frag.reset(std::max<size_t>((size_t)ntiles[t] * mf.KO * 64, 1), s);
         launch_mfma_records_ternary_lists(mf.fr[t].get(), mf.KO, m.tern_tokens, list[t].get(), base + L, b.tab.get(),
                                           b.tab.get() + L + 2, L + 1, ntiles[t], b.frag.get(), s);
@@ -1424,8 +1429,7 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
     tm.mark(6);
     finish_weights(m, s, &prow, cls);
     tm.mark(7);
-    mf.queue_tests(s);
-    IG_HIP(hipStreamSynchronize(s));
+    mf.finish(s);
     mf.clock.collect();
     mf.put_tests(m);
     m.stats.ms[1] = ms_pairs;
@@ -1785,8 +1789,7 @@ static void run_group(std::vector<BProb *> &G, const ig_fit_opts *opts, hipStrea
         tm.mark(6);
         finish_weights(m, s, &prow, G[g]->cls);
         tm.mark(7);
-        mf[g].queue_tests(s);
-        IG_HIP(hipStreamSynchronize(s));
+        mf[g].finish(s);
         mf[g].put_tests(m);
         record_times(m, tm);
         // the group's captured stages, split by this problem's share of the pairs
