@@ -189,7 +189,10 @@ __global__ __launch_bounds__(256) void k_pair_hash64(DedupArgs a, uint64_t items
     vals[g] = any ? (uint32_t)g : ~0u;
 }
 
-constexpr uint32_t kPartBits = 16;          // partitions: the top bits of the hash
+#ifndef IG_PART_BITS
+#define IG_PART_BITS 16
+#endif
+constexpr uint32_t kPartBits = IG_PART_BITS;   // partitions: the top bits of the hash (14 to 16)
 constexpr uint32_t kPartSlots = 2048;       // LDS hash table of a partition (distinct hashes)
 
 // starts[p] = the first sorted position of partition p (starts[2^16] = m).
