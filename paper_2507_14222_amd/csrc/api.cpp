@@ -767,13 +767,20 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
     // materialised, so that support and the scoring tiles (which take the same
     // buckets) read them in order
     CandGroups sg;
+    Scratch<uint64_t> built;   // operand rows built here in the grouped order
     const bool grouped = pmf && pmf->pruned && own_frag && !may_repeat;
     if (grouped) {
         sorted_ids.reset(count, s);
         group_candidates(*pmf, pmf->bk[c], pmf->xr_sup[c].get(), cls.n, KS, ids, nullptr, count, sg, s,
                          sorted_ids.get());
         vcur = sorted_ids.get();
-        if (pre_rows) {
+        if (mfma_view.KF && pmf->fr[c].get()) {
+            // the pairs' operand rows in this order, from the class's factored rows (as
+            // the coherence step built them): cheaper than gathering those at random
+            built.reset(count * (mfma_view.ternary ? 2 * mfma_view.KF : mfma_view.KF), s);
+            launch_pair_rows_factored(pmf->fr[c].get(), cls.n, vcur, count, mfma_view, built.get(), s);
+            pre_idx = nullptr;
+        } else if (pre_rows) {
             // row of position p: pre_rows[pre_idx[perm[p]]] (pre_idx: the coherent
             // candidates' rows among all of the coherence step's), or pre_rows[perm[p]]
             const uint32_t RWp = mfma_view.ternary ? 2 * mfma_view.KF : (mfma_view.KF ? mfma_view.KF : KS);
@@ -822,7 +829,9 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         const uint32_t KO = mfma_view.KF ? mfma_view.KF : KS;
         const uint32_t RW = mfma_view.ternary ? 2 * KO : KO;
         Scratch<uint64_t> B;
-        if (pre_rows && !may_repeat && pre_idx) {
+        if (built.get()) {
+            B = std::move(built);
+        } else if (pre_rows && !may_repeat && pre_idx) {
             // the coherence step's rows of these patterns, picked out in their order
             B.reset(final_count * RW, s);
             launch_gather_rows(pre_rows->get(), pre_idx, final_count, RW, RW, B.get(), nullptr, nullptr, s);
@@ -1334,7 +1343,8 @@ static void fit_from_rows(DevModel &m, ClassRows cls[2], const ig_fit_opts *opts
             for (int c = 0; c < 2; ++c) {
                 const uint32_t *cc = cand.get() + (c == 0 ? 0 : hc[0]);
                 // one chunk: keep the survivors' operand rows for support and scoring
-                const bool keep_rows = chunks.size() == 1;
+                // (on token buckets support builds them again in its own order)
+                const bool keep_rows = chunks.size() == 1 && !mf.pruned;
                 mfma_surv[c] += mfma_coherence(mf, cls, c, KS, cc, hc[c], surv[c].get() + mfma_surv[c],
                                                &m.stats.kernel_ms[0], s, keep_rows ? &surv_rows[c] : nullptr,
                                                keep_rows ? &surv_idx[c] : nullptr, tu.coh_sets, &mfma_tests[c]);
