@@ -701,17 +701,16 @@ struct CandGroups {
 // Groups m candidates (pair ids `ids` of the records Xr [n][KSr], renumbered by the
 // ranks of the buckets b, or rows W [m][KS] of one-hot words when ids is null) by
 // bucket.
-// keys: the candidates' buckets when already known (else computed here).
 static void group_candidates(const MfmaFit &mf, const FitBuckets &b, const uint64_t *Xr, uint32_t n, uint32_t KS,
                              const uint32_t *ids, const uint64_t *W, size_t m, CandGroups &g, hipStream_t s,
-                             uint32_t *ids_out = nullptr, uint32_t *keys = nullptr) {
+                             uint32_t *ids_out = nullptr) {
     IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 candidates in one contraction");
     const uint32_t L = mf.L;
-    Scratch<uint32_t> key(keys ? 0 : std::max<size_t>(m, 1), s), ws(bucket_ws_words(m, L), s);
+    Scratch<uint32_t> key(std::max<size_t>(m, 1), s), ws(bucket_ws_words(m, L), s);
     g.perm.reset(std::max<size_t>(m, 1), s);
     g.first.reset(L + 2, s);
-    launch_group_candidates(Xr, n, mf.KSr, ids, W, KS, m, L, b.rank.get(), b.inv(), keys ? keys : key.get(),
-                            g.perm.get(), g.first.get(), ws.get(), s, ids_out, keys != nullptr);
+    launch_group_candidates(Xr, n, mf.KSr, ids, W, KS, m, L, b.rank.get(), b.inv(), key.get(), g.perm.get(),
+                            g.first.get(), ws.get(), s, ids_out);
 }
 
 // The m grouped candidates (perm: position -> row of B and of out, null for the
@@ -1125,30 +1124,33 @@ static uint32_t mfma_coherence(MfmaFit &mf, const ClassRows cls[2], int c, uint3
     if (!ncand) return 0;
     Scratch<uint32_t> keep(ncand, s), kpos(ncand, s), ktot(1, s);
     Scratch<uint64_t> B((size_t)ncand * mf.RW, s);
-    // on token buckets the pair rows kernel also finds each candidate's bucket
-    Scratch<uint32_t> ckey(mf.pruned && mf.view.KF ? (size_t)ncand : 0, s);
-    if (mf.view.KF)
-        launch_pair_rows_factored(mf.fr[c].get(), cls[c].n, cand, ncand, mf.view, B.get(), s,
-                                  mf.pruned ? mf.xr_coh[c].get() : nullptr, mf.KSr, mf.L,
-                                  mf.pruned ? mf.bk[1 - c].inv() : nullptr, ckey.get());
-    else
-        launch_operand_rows(cls[c].X.get(), cls[c].n, cand, nullptr, KS, ncand, mf.view, false, B.get(), s);
     if (mf.pruned) {
-        // the candidates against the other class's records that hold their bucket token
+        // the candidates against the other class's records that hold their bucket
+        // token: grouped by bucket first, so that their operand rows are built in
+        // bucket order (the contraction then reads them in order), flags in bucket
+        // order too (coalesced stores); the coherent ids come out in that order
         CandGroups g;
-        group_candidates(mf, mf.bk[1 - c], mf.xr_coh[c].get(), cls[c].n, KS, cand, nullptr, ncand, g, s, nullptr,
-                         ckey.get());
-        // flags in bucket order (coalesced stores); the coherent ids come out in that order
-        pruned_contain(mf, mf.bk[1 - c], g.perm.get(), g.first.get(), ncand, B.get(), false, keep.get(), sets,
+        Scratch<uint32_t> sids(ncand, s);
+        group_candidates(mf, mf.bk[1 - c], mf.xr_coh[c].get(), cls[c].n, KS, cand, nullptr, ncand, g, s,
+                         sids.get());
+        if (mf.view.KF)
+            launch_pair_rows_factored(mf.fr[c].get(), cls[c].n, sids.get(), ncand, mf.view, B.get(), s);
+        else
+            launch_operand_rows(cls[c].X.get(), cls[c].n, sids.get(), nullptr, KS, ncand, mf.view, false, B.get(),
+                                s);
+        pruned_contain(mf, mf.bk[1 - c], nullptr, g.first.get(), ncand, B.get(), false, keep.get(), sets,
                        mf.dtests.get() + c, kernel_ms, s, true);
         scan_exclusive_u32(keep.get(), kpos.get(), ncand, ktot.get(), s);
         if (rows_out) idx_out->reset(ncand, s);
-        launch_compact(keep.get(), kpos.get(), cand, ncand, out, s, rows_out ? idx_out->get() : nullptr,
-                       g.perm.get());
+        launch_compact(keep.get(), kpos.get(), sids.get(), ncand, out, s, rows_out ? idx_out->get() : nullptr);
         const uint32_t kept = host_read_u32(ktot.get(), 1, s)[0];
         if (rows_out) *rows_out = std::move(B);
         return kept;
     }
+    if (mf.view.KF)
+        launch_pair_rows_factored(mf.fr[c].get(), cls[c].n, cand, ncand, mf.view, B.get(), s);
+    else
+        launch_operand_rows(cls[c].X.get(), cls[c].n, cand, nullptr, KS, ncand, mf.view, false, B.get(), s);
     if (tests) *tests += (uint64_t)ncand * cls[1 - c].n;
     hipEvent_t ke[2];
     IG_HIP(hipEventCreate(&ke[0]));

@@ -191,21 +191,12 @@ __global__ __launch_bounds__(256) void k_operand_rows_reg(const uint64_t *__rest
 // entry (a scalar load) serves R rows.
 // TERN: ternary rows (P then V, 2 KO words): the pair keeps P_i AND P_j on the
 // features where V_i and V_j agree, and V_i on those.
-// With k.key: also each pair's bucket key, as k_cand_keys_rank computes it (the
-// pair is decoded and its records read here anyway).
-struct PairKeys {
-    const uint64_t *Xr;   // [n][KSr]: the records' tokens renumbered by rank
-    const uint16_t *inv;  // renumbered token -> token
-    uint32_t *key;        // [m] (null: no keys)
-    uint32_t KSr, L;
-};
-
 template <int KO, int R, bool TERN>
 __global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__restrict__ FR, uint32_t n,
                                                            const uint32_t *__restrict__ ids, size_t m,
                                                            const uint4 *__restrict__ wfe,
                                                            const uint32_t *__restrict__ wbeg,
-                                                           uint64_t *__restrict__ out, PairKeys k) {
+                                                           uint64_t *__restrict__ out) {
     constexpr int RW = TERN ? 2 * KO : KO;   // words per row
     const size_t T = (size_t)gridDim.x * blockDim.x;
     for (size_t e0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < m; e0 += T * R) {
@@ -244,20 +235,6 @@ __global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__re
                     keep[r][o] = a & b;
                 }
             }
-            if (k.key && e < m) {
-                // the token of lowest rank both records hold (L: none; after the row
-                // loads, so that both are in flight together)
-                const uint64_t *xi = k.Xr + (size_t)i * k.KSr, *xj = k.Xr + (size_t)j * k.KSr;
-                uint32_t best = k.L;
-                for (uint32_t w = 0; w < k.KSr; ++w) {
-                    const uint64_t a = xi[w] & xj[w];
-                    if (a) {
-                        best = k.inv[64 * w + (uint32_t)__builtin_ctzll(a)];
-                        break;
-                    }
-                }
-                k.key[e] = best;
-            }
             D[r] = 0;
         }
 #pragma unroll
@@ -294,23 +271,20 @@ __global__ __launch_bounds__(256) void k_pair_rows_factored(const uint64_t *__re
 }
 
 void launch_pair_rows_factored(const uint64_t *FR, uint32_t n, const uint32_t *ids, size_t m, const FactorView &fv,
-                               uint64_t *out, hipStream_t s, const uint64_t *Xr, uint32_t KSr, uint32_t L,
-                               const uint16_t *inv, uint32_t *key) {
+                               uint64_t *out, hipStream_t s) {
     if (!m) return;
     IG_REQUIRE(fv.KF >= 1 && fv.KF <= 16 && fv.wfe && fv.wbeg && n > 0, IG_E_DEVICE,
                "factored pair rows without a token-range table");
     const size_t cap = (size_t)device_cus() * 8;
-    IG_REQUIRE(!key || (Xr && inv && KSr * 64 >= L), IG_E_INVAL, "pair keys need ranked records");
-    const PairKeys pk{Xr, inv, key, KSr, L};
 #define IG_PR(V, RR)                                                                                               \
     case V: {                                                                                                      \
         const dim3 grid((unsigned)std::min<size_t>((m + 256 * RR - 1) / (256 * RR), cap));                       \
         if (fv.ternary)                                                                                            \
             hipLaunchKernelGGL((k_pair_rows_factored<V, RR, true>), grid, dim3(256), 0, s, FR, n, ids, m, fv.wfe,  \
-                               fv.wbeg, out, pk);                                                                  \
+                               fv.wbeg, out);                                                                      \
         else                                                                                                       \
             hipLaunchKernelGGL((k_pair_rows_factored<V, RR, false>), grid, dim3(256), 0, s, FR, n, ids, m, fv.wfe, \
-                               fv.wbeg, out, pk);                                                                  \
+                               fv.wbeg, out);                                                                      \
         break;                                                                                                     \
     }
     switch (fv.KF) {

@@ -151,11 +151,8 @@ void launch_operand_rows(const uint64_t *X, uint32_t n, const uint32_t *ids, con
 // Factored operand rows of record pairs from the records' own factored rows FR
 // [n][fv.KF]: row e (pair id ids[e]) is FR[i] AND FR[j] with the tokens of every
 // feature on which the two records differ cleared (a one-bin-per-feature fit).
-// With key: key[e] = the pair's bucket, inv[q] for the lowest renumbered token q
-// both records hold in Xr [n][KSr] (L when none), as launch_group_candidates finds it.
 void launch_pair_rows_factored(const uint64_t *FR, uint32_t n, const uint32_t *ids, size_t m, const FactorView &fv,
-                               uint64_t *out, hipStream_t s, const uint64_t *Xr = nullptr, uint32_t KSr = 0,
-                               uint32_t L = 0, const uint16_t *inv = nullptr, uint32_t *key = nullptr);
+                               uint64_t *out, hipStream_t s);
 
 // subset.hip -- the subset-test kernels (Eq. 6 inside Eq. 3, Eq. 2 and Eq. 4)
 struct CohSeg {                 // one (problem, class) for one coherence phase
@@ -289,11 +286,10 @@ void launch_rank_rows(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, co
 // [n][KSr] (their intersection), or row e of W [m][KS] (one-hot words, renumbered
 // through rank); L for a candidate without a token.  perm [m]: candidate indices;
 // ids_out [m] (optional, with ids): the ids in the same order.
-// keys_given: key [m] already holds the buckets (Xr, W, rank and inv unused).
 void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const uint32_t *ids, const uint64_t *W,
                              uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, const uint16_t *inv,
                              uint32_t *key, uint32_t *perm, uint32_t *first, uint32_t *ws, hipStream_t s,
-                             uint32_t *ids_out = nullptr, bool keys_given = false);
+                             uint32_t *ids_out = nullptr);
 // The records of X [n][KS] (d tokens each) under each token they hold: list
 // [n d] of record indices, key [n d] scratch; ws: bucket_ws_words(n d, L) u32.
 void launch_group_records(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, uint32_t d, uint32_t *key,

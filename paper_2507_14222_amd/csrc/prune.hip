@@ -348,16 +348,14 @@ void launch_rank_rows(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, co
 void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const uint32_t *ids, const uint64_t *W,
                              uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, const uint16_t *inv,
                              uint32_t *key, uint32_t *perm, uint32_t *first, uint32_t *ws, hipStream_t s,
-                             uint32_t *ids_out, bool keys_given) {
+                             uint32_t *ids_out) {
     IG_REQUIRE(L >= 1 && L <= kMaxBuckets, IG_E_UNSUPPORTED, "token buckets need 1 to 4096 tokens");
-    IG_REQUIRE(keys_given || (inv && ((ids && Xr) || (!ids && W && rank))), IG_E_INVAL,
+    IG_REQUIRE(inv && ((ids && Xr) || (!ids && W && rank)), IG_E_INVAL,
                "candidates need pair ids and ranked records, or rows");
     const uint32_t nwg = std::max<uint32_t>(bucket_groups(m), 1);
     uint32_t *whist = ws;
     if (!m) {
         launch_fill_u32(whist, 0u, (size_t)(L + 1) * nwg, s);
-    } else if (keys_given) {
-        hipLaunchKernelGGL(k_key_hist, dim3(nwg), dim3(BK_T), 0, s, key, m, L, whist, nwg, bucket_iters(m));
     } else if (ids) {
         hipLaunchKernelGGL(k_cand_keys_rank, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, Xr, n, KSr, ids, m,
                            L, inv, key);
