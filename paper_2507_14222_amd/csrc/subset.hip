@@ -855,11 +855,11 @@ __device__ __forceinline__ uint32_t acc_row(uint32_t half, uint32_t r) { return 
 // [brow[u], brow[u + 1]) of the order perm (position e is row perm[e]), 32 per
 // tile, the last tile of a bucket padded with empty rows: every tile holds the
 // patterns of one bucket only.  Without, tile t holds rows [32 t, 32 t + 32).
+template <int KS>
 __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restrict__ W, const int64_t *__restrict__ S,
-                                                      uint32_t m, uint32_t KS, uint32_t ntiles, bool spare,
-                                                      bool tern, const uint32_t *__restrict__ perm,
+                                                      uint32_t m, uint32_t ntiles, bool spare, bool tern,
+                                                      const uint32_t *__restrict__ perm,
                                                       const uint32_t *__restrict__ bt,
-                                                      const uint32_t *__restrict__ brow,
                                                       const uint2 *__restrict__ tr, uint4 *__restrict__ frag) {
     const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;   // uniform over the wave
@@ -876,25 +876,38 @@ __global__ __launch_bounds__(256) void k_mfma_patterns(const uint64_t *__restric
     uint4 *dst = frag + (size_t)tile * score_tile_words(KS);
     const uint32_t RW = tern ? 2 * KS : KS;   // words per row
     const uint32_t *rw = reinterpret_cast<const uint32_t *>(W + (size_t)row * RW) + half;
+    // ternary rows (P then V, 2 KS words, 16-byte aligned) as 16-byte loads; this
+    // lane's 32-bit half of each word picked from them
+    uint32_t ph[KS], vh[KS];
     uint32_t np = 0;   // ternary: |P| of the row (both halves of the wave hold it)
     if (tern) {
+        const uint4 *r4 = reinterpret_cast<const uint4 *>(W + (size_t)row * RW);
+        uint32_t x[4 * KS];
 #pragma unroll
-        for (uint32_t w = 0; w < 8; ++w) {
-            if (w >= KS) break;
-            np += __popc(in ? rw[2 * w] : 0u);
+        for (int q = 0; q < KS; ++q) {
+            const uint4 v = in ? r4[q] : make_uint4(0, 0, 0, 0);
+            x[4 * q] = v.x;
+            x[4 * q + 1] = v.y;
+            x[4 * q + 2] = v.z;
+            x[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int w = 0; w < KS; ++w) {
+            ph[w] = half ? x[2 * w + 1] : x[2 * w];
+            vh[w] = half ? x[2 * (KS + w) + 1] : x[2 * (KS + w)];
+            np += __popc(ph[w]);
         }
         np += (uint32_t)__shfl_xor((int)np, 32, 64);
     }
 #pragma unroll
-    for (uint32_t w = 0; w < 8; ++w) {
-        if (w >= KS) break;
-        const uint32_t d = in ? rw[2 * w] : 0u;
+    for (int w = 0; w < KS; ++w) {
+        const uint32_t d = tern ? ph[w] : (in ? rw[2 * w] : 0u);
         uint4 v;
         if (tern) {
             // the candidate side of the ternary contraction (k_contain_mfma): +1.0
             // on P AND NOT V, -1.0 on P AND V, and the row's bias nibbles (1 - |P|;
             // rows past m have none) in the upper half of the last word
-            const uint32_t V = in ? rw[2 * (KS + w)] : 0u;
+            const uint32_t V = vh[w];
             v = make_uint4(spread8(d) | spread8(V) * 4u, spread8(d >> 8) | spread8(V >> 8) * 4u,
                            spread8(d >> 16) | spread8(V >> 16) * 4u, spread8(d >> 24) | spread8(V >> 24) * 4u);
             if (in && half && w == KS - 1) {
@@ -1304,8 +1317,17 @@ void launch_mfma_patterns(const uint64_t *W, const int64_t *S, uint32_t m, uint3
         hipLaunchKernelGGL(k_tile_bucket, dim3((ntiles + 255) / 256), dim3(256), 0, s, bt, brow, L, ntiles, tr.get());
         IG_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_mfma_patterns, dim3((ntiles + 3) / 4), dim3(256), 0, s, W, S, m, KS, ntiles, spare, tern,
-                       perm, bt, brow, tr.get(), frag);
+    const dim3 grid((ntiles + 3) / 4);
+    switch (KS) {
+#define IG_MP(V)                                                                                                  \
+    case V:                                                                                                       \
+        hipLaunchKernelGGL(k_mfma_patterns<V>, grid, dim3(256), 0, s, W, S, m, ntiles, spare, tern, perm, bt, tr.get(), \
+                           frag);                                                                                 \
+        break;
+        IG_MP(1) IG_MP(2) IG_MP(3) IG_MP(4) IG_MP(5) IG_MP(6) IG_MP(7) IG_MP(8)
+#undef IG_MP
+        default: break;
+    }
     IG_HIP(hipGetLastError());
 }
 
