@@ -428,6 +428,19 @@ __global__ __launch_bounds__(256) void k_materialize_words(const uint64_t *__res
     W[e * KS + k] = X[(size_t)i * KS + k] & X[(size_t)j * KS + k];
 }
 
+// The same for rows of an even number of words, two words (16 bytes) per thread.
+__global__ __launch_bounds__(256) void k_materialize_words16(const uint4 *__restrict__ X, uint32_t n, uint32_t K2,
+                                                            const uint32_t *__restrict__ ids, size_t m,
+                                                            uint4 *__restrict__ W) {
+    const uint32_t per = 256u / K2, lr = threadIdx.x / K2, k = threadIdx.x - lr * K2;
+    const size_t e = (size_t)blockIdx.x * per + lr;
+    if (lr >= per || e >= m) return;
+    uint32_t i, j;
+    decode_pair(ids[e], n, i, j);
+    const uint4 a = X[(size_t)i * K2 + k], b = X[(size_t)j * K2 + k];
+    W[e * K2 + k] = make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
+}
+
 // out[pos[e]] = W[e] for flagged e (row copy)
 __global__ void k_compact_rows(const uint64_t *__restrict__ W, const uint32_t *__restrict__ flags,
                                const uint32_t *__restrict__ pos, size_t m, uint32_t KS, uint64_t *__restrict__ out) {
@@ -613,7 +626,13 @@ void launch_word_range(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, c
 void launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m, uint64_t *W,
                         uint32_t *newflag, hipStream_t s) {
     if (!m) return;
-    if (!newflag && KS <= 256) {
+    if (!newflag && KS % 2 == 0 && KS <= 512) {
+        // rows are 16-byte aligned: two words per thread
+        const uint32_t K2 = KS / 2;
+        const size_t per = 256 / K2;
+        hipLaunchKernelGGL(k_materialize_words16, dim3((unsigned)((m + per - 1) / per)), dim3(256), 0, s,
+                           reinterpret_cast<const uint4 *>(X), n, K2, ids, m, reinterpret_cast<uint4 *>(W));
+    } else if (!newflag && KS <= 256) {
         const size_t per = 256 / KS;
         hipLaunchKernelGGL(k_materialize_words, dim3((unsigned)((m + per - 1) / per)), dim3(256), 0, s, X, n, KS, ids,
                            m, W);
