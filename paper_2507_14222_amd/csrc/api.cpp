@@ -701,13 +701,16 @@ struct CandGroups {
 // Groups m candidates (pair ids `ids` of the records Xr [n][KSr], renumbered by the
 // ranks of the buckets b, or rows W [m][KS] of one-hot words when ids is null) by
 // bucket.
+// need_perm: also the permutation (position -> candidate); without it only the
+// grouped ids (ids_out) and the bucket starts.
 static void group_candidates(const MfmaFit &mf, const FitBuckets &b, const uint64_t *Xr, uint32_t n, uint32_t KS,
                              const uint32_t *ids, const uint64_t *W, size_t m, CandGroups &g, hipStream_t s,
-                             uint32_t *ids_out = nullptr) {
+                             uint32_t *ids_out = nullptr, bool need_perm = true) {
     IG_REQUIRE(m < (1ull << 32), IG_E_UNSUPPORTED, "more than 2^32 candidates in one contraction");
+    IG_REQUIRE(need_perm || ids_out, IG_E_INVAL, "grouping with neither a permutation nor grouped ids");
     const uint32_t L = mf.L;
     Scratch<uint32_t> key(std::max<size_t>(m, 1), s), ws(bucket_ws_words(m, L), s);
-    g.perm.reset(std::max<size_t>(m, 1), s);
+    if (need_perm) g.perm.reset(std::max<size_t>(m, 1), s);
     g.first.reset(L + 2, s);
     launch_group_candidates(Xr, n, mf.KSr, ids, W, KS, m, L, b.rank.get(), b.inv(), key.get(), g.perm.get(),
                             g.first.get(), ws.get(), s, ids_out);
@@ -770,10 +773,13 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
     const bool grouped = pmf && pmf->pruned && own_frag && !may_repeat;
     if (grouped) {
         sorted_ids.reset(count, s);
+        // the rows are built in the grouped order below when the view is factored; the
+        // permutation is needed only to gather the coherence step's rows otherwise
+        const bool build_rows = mfma_view.KF && pmf->fr[c].get();
         group_candidates(*pmf, pmf->bk[c], pmf->xr_sup[c].get(), cls.n, KS, ids, nullptr, count, sg, s,
-                         sorted_ids.get());
+                         sorted_ids.get(), !build_rows);
         vcur = sorted_ids.get();
-        if (mfma_view.KF && pmf->fr[c].get()) {
+        if (build_rows) {
             // the pairs' operand rows in this order, from the class's factored rows (as
             // the coherence step built them): cheaper than gathering those at random
             built.reset(count * (mfma_view.ternary ? 2 * mfma_view.KF : mfma_view.KF), s);
@@ -1132,7 +1138,7 @@ static uint32_t mfma_coherence(MfmaFit &mf, const ClassRows cls[2], int c, uint3
         CandGroups g;
         Scratch<uint32_t> sids(ncand, s);
         group_candidates(mf, mf.bk[1 - c], mf.xr_coh[c].get(), cls[c].n, KS, cand, nullptr, ncand, g, s,
-                         sids.get());
+                         sids.get(), false);
         if (mf.view.KF)
             launch_pair_rows_factored(mf.fr[c].get(), cls[c].n, sids.get(), ncand, mf.view, B.get(), s);
         else

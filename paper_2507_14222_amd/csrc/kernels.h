@@ -284,8 +284,9 @@ void launch_rank_rows(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t L, co
 // Candidates grouped by bucket, the token inv[q] of the lowest renumbered token q
 // they hold: candidate e is the pair id ids[e] of the renumbered records Xr
 // [n][KSr] (their intersection), or row e of W [m][KS] (one-hot words, renumbered
-// through rank); L for a candidate without a token.  perm [m]: candidate indices;
-// ids_out [m] (optional, with ids): the ids in the same order.
+// through rank); L for a candidate without a token.  perm [m]: candidate indices
+// (may be null when ids_out is given); ids_out [m] (optional, with ids): the ids in
+// the same order.
 void launch_group_candidates(const uint64_t *Xr, uint32_t n, uint32_t KSr, const uint32_t *ids, const uint64_t *W,
                              uint32_t KS, size_t m, uint32_t L, const uint16_t *rank, const uint16_t *inv,
                              uint32_t *key, uint32_t *perm, uint32_t *first, uint32_t *ws, hipStream_t s,

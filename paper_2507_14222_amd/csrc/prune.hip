@@ -276,7 +276,8 @@ __global__ __launch_bounds__(BK_T) void k_record_keys(const uint64_t *__restrict
 }
 
 // out[pos[key][wg] + place] = e / div for the elements e of workgroup wg (pos:
-// the exclusive scan of whist), and out2 there = src[e] when src is given.  The
+// the exclusive scan of whist; out may be null), and out2 there = src[e] when src
+// is given.  The
 // workgroup's cursors start at its column of pos, so the place is the cursor.
 __global__ __launch_bounds__(BK_T) void k_bucket_place(const uint32_t *__restrict__ key, size_t m, uint32_t L,
                                                        const uint32_t *__restrict__ pos, uint32_t nwg, uint32_t div,
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(BK_T) void k_bucket_place(const uint32_t *__restric
         const uint32_t k = act ? key[e] : L;
         const uint32_t p = group_add(h, k, act);
         if (act) {
-            out[p] = (uint32_t)(e / div);
+            if (out) out[p] = (uint32_t)(e / div);
             if (src) out2[p] = src[e];
         }
     }
