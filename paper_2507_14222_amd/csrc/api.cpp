@@ -805,7 +805,8 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
         vcur = sorted_ids.get();
     }
     Scratch<uint64_t> Wtmp;
-    Scratch<uint32_t> flag;
+    Scratch<uint32_t> flag, plen;   // plen: the patterns' token counts, for S = f |b|^2
+    bool have_len = false;
     uint64_t *Wd = dev_alloc<uint64_t>(count * KS);
     size_t final_count = count;
     try {
@@ -818,7 +819,8 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
             launch_compact_rows(Wtmp.get(), flag.get(), pos.get(), count, KS, Wd, s);
             final_count = host_read_u32(tot.get(), 1, s)[0];
         } else {
-            launch_materialize(cls.X.get(), cls.n, KS, vcur, count, Wd, nullptr, s);
+            plen.reset(count, s);
+            have_len = launch_materialize(cls.X.get(), cls.n, KS, vcur, count, Wd, nullptr, s, plen.get());
         }
         m.W[c] = Wd;
         m.np[c] = final_count;
@@ -859,7 +861,8 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
                 group_candidates(*pmf, pmf->bk[c], nullptr, cls.n, KS, nullptr, m.W[c], final_count, sg, s);
             pruned_contain(*pmf, pmf->bk[c], grouped ? nullptr : sg.perm.get(), sg.first.get(), final_count,
                            B.get(), true, m.f[c], tu.sup_sets, pmf->dtests.get() + 2 + c, &m.stats.kernel_ms[1], s);
-            launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
+            if (have_len) launch_weights_len(m.f[c], plen.get(), final_count, m.S[c], s);
+            else launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
             // the scoring tiles take these buckets when the patterns are in their order
             if (grouped) m.sgroup[c] = host_read_u32(sg.first.get(), pmf->L + 2, s);
         } else {
@@ -868,7 +871,8 @@ static void order_and_weigh(DevModel &m, int c, const ClassRows &cls, uint32_t *
             launch_contain_mfma((int)KO, true, B.get(), final_count, own_frag, cls.n, m.f[c], s, tu.sup_sets,
                                 mfma_view.ternary != 0);
             IG_HIP(hipEventRecord(ke[1], s));
-            launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
+            if (have_len) launch_weights_len(m.f[c], plen.get(), final_count, m.S[c], s);
+            else launch_weights(m.W[c], m.f[c], final_count, KS, m.S[c], s);
             er = hipEventSynchronize(ke[1]);
             if (er == hipSuccess) (void)hipEventElapsedTime(&tk, ke[0], ke[1]);
             (void)hipEventDestroy(ke[0]);

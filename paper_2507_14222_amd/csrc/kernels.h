@@ -48,8 +48,10 @@ void launch_gather_word(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t k, 
                         uint64_t *keys, hipStream_t s);
 void launch_word_range(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, const uint32_t *ids, size_t m,
                        unsigned long long *orv, unsigned long long *andv, hipStream_t s);
-void launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m, uint64_t *W,
-                        uint32_t *newflag, hipStream_t s);
+// With len (no newflag): also the token count of each row when the row width allows
+// (returns whether len was written).
+bool launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m, uint64_t *W,
+                        uint32_t *newflag, hipStream_t s, uint32_t *len = nullptr);
 void launch_compact_rows(const uint64_t *W, const uint32_t *flags, const uint32_t *pos, size_t m, uint32_t KS,
                          uint64_t *out, hipStream_t s);
 // out row e = the first KD words of row r of W [.][KS], r = ids[e] (or ids2[ids[e]]);
@@ -84,6 +86,8 @@ void launch_permute_u32(const uint32_t *src, const uint32_t *perm, size_t m, uin
 void launch_adjacent_equal(const uint64_t *W, size_t m, uint32_t KS, uint32_t *d_count, hipStream_t s);
 // S = f * popcount^2 (Eq. 2) for given rows and supports
 void launch_weights(const uint64_t *W, const uint32_t *f, size_t m, uint32_t KS, int64_t *S, hipStream_t s);
+// S = f |b|^2 from token counts len [m]
+void launch_weights_len(const uint32_t *f, const uint32_t *len, size_t m, int64_t *S, hipStream_t s);
 
 // factor.hip -- factored tokens for the matrix-core operands.
 // A feature with nb bins takes m = ceil(log2 nb) bit tokens and one or two presence

@@ -428,17 +428,38 @@ __global__ __launch_bounds__(256) void k_materialize_words(const uint64_t *__res
     W[e * KS + k] = X[(size_t)i * KS + k] & X[(size_t)j * KS + k];
 }
 
-// The same for rows of an even number of words, two words (16 bytes) per thread.
+// The same for rows of an even number of words, two words (16 bytes) per thread;
+// len[e] (when given) = the number of tokens of row e, |b| of Eq. 2.
 __global__ __launch_bounds__(256) void k_materialize_words16(const uint4 *__restrict__ X, uint32_t n, uint32_t K2,
                                                             const uint32_t *__restrict__ ids, size_t m,
-                                                            uint4 *__restrict__ W) {
+                                                            uint4 *__restrict__ W, uint32_t *__restrict__ len) {
+    __shared__ uint32_t cnt[256];
     const uint32_t per = 256u / K2, lr = threadIdx.x / K2, k = threadIdx.x - lr * K2;
     const size_t e = (size_t)blockIdx.x * per + lr;
-    if (lr >= per || e >= m) return;
-    uint32_t i, j;
-    decode_pair(ids[e], n, i, j);
-    const uint4 a = X[(size_t)i * K2 + k], b = X[(size_t)j * K2 + k];
-    W[e * K2 + k] = make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
+    const bool act = lr < per && e < m;
+    if (len) {
+        cnt[threadIdx.x] = 0;
+        __syncthreads();
+    }
+    if (act) {
+        uint32_t i, j;
+        decode_pair(ids[e], n, i, j);
+        const uint4 a = X[(size_t)i * K2 + k], b = X[(size_t)j * K2 + k];
+        const uint4 v = make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
+        W[e * K2 + k] = v;
+        if (len) atomicAdd(&cnt[lr], (uint32_t)(__popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w)));
+    }
+    if (len) {
+        __syncthreads();
+        if (act && k == 0) len[e] = cnt[lr];
+    }
+}
+
+// S[e] = f[e] |b_e|^2 from the rows' token counts (Eq. 2)
+__global__ void k_weights_len(const uint32_t *__restrict__ f, const uint32_t *__restrict__ len, size_t m,
+                              int64_t *__restrict__ S) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) S[e] = (int64_t)f[e] * (int64_t)len[e] * (int64_t)len[e];
 }
 
 // out[pos[e]] = W[e] for flagged e (row copy)
@@ -623,15 +644,17 @@ void launch_word_range(const uint64_t *X, uint32_t n, uint32_t KS, uint32_t K, c
     IG_HIP(hipGetLastError());
 }
 
-void launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m, uint64_t *W,
-                        uint32_t *newflag, hipStream_t s) {
-    if (!m) return;
+bool launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32_t *ids, size_t m, uint64_t *W,
+                        uint32_t *newflag, hipStream_t s, uint32_t *len) {
+    if (!m) return len != nullptr;
     if (!newflag && KS % 2 == 0 && KS <= 512) {
         // rows are 16-byte aligned: two words per thread
         const uint32_t K2 = KS / 2;
         const size_t per = 256 / K2;
         hipLaunchKernelGGL(k_materialize_words16, dim3((unsigned)((m + per - 1) / per)), dim3(256), 0, s,
-                           reinterpret_cast<const uint4 *>(X), n, K2, ids, m, reinterpret_cast<uint4 *>(W));
+                           reinterpret_cast<const uint4 *>(X), n, K2, ids, m, reinterpret_cast<uint4 *>(W), len);
+        IG_HIP(hipGetLastError());
+        return len != nullptr;
     } else if (!newflag && KS <= 256) {
         const size_t per = 256 / KS;
         hipLaunchKernelGGL(k_materialize_words, dim3((unsigned)((m + per - 1) / per)), dim3(256), 0, s, X, n, KS, ids,
@@ -640,6 +663,7 @@ void launch_materialize(const uint64_t *X, uint32_t n, uint32_t KS, const uint32
         hipLaunchKernelGGL(k_materialize, blocks_for(m), dim3(256), 0, s, X, n, KS, ids, m, W, newflag);
     }
     IG_HIP(hipGetLastError());
+    return false;
 }
 
 void launch_compact_rows(const uint64_t *W, const uint32_t *flags, const uint32_t *pos, size_t m, uint32_t KS,
@@ -682,6 +706,12 @@ void launch_row_word(const uint64_t *W, const uint32_t *ids, size_t m, uint32_t 
 void launch_adjacent_equal(const uint64_t *W, size_t m, uint32_t KS, uint32_t *d_count, hipStream_t s) {
     if (m < 2) return;
     hipLaunchKernelGGL(k_adjacent_equal, blocks_for(m), dim3(256), 0, s, W, m, KS, d_count);
+    IG_HIP(hipGetLastError());
+}
+
+void launch_weights_len(const uint32_t *f, const uint32_t *len, size_t m, int64_t *S, hipStream_t s) {
+    if (!m) return;
+    hipLaunchKernelGGL(k_weights_len, blocks_for(m), dim3(256), 0, s, f, len, m, S);
     IG_HIP(hipGetLastError());
 }
 
