@@ -72,34 +72,72 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const uint32_t *in, size
 }
 
 // exclusive scan of each tile, offset by the (already scanned) tile prefix
+// vec: in and out are 16-byte aligned, so a thread's values move as 16-byte loads
+// and stores (a quarter of the scattered accesses) wherever all SCAN_I are in range.
 __global__ __launch_bounds__(SCAN_T) void k_scan_tiles(const uint32_t *in, uint32_t *out, size_t n,
-                                                      const uint32_t *tile_prefix, uint32_t *d_total) {
+                                                      const uint32_t *tile_prefix, uint32_t *d_total, bool vec) {
     __shared__ uint32_t sh[4];
     __shared__ uint32_t carry;
     size_t base = (size_t)blockIdx.x * SCAN_TILE;
     if (threadIdx.x == 0) carry = tile_prefix ? tile_prefix[blockIdx.x] : 0u;
     __syncthreads();
     // each thread owns SCAN_I consecutive values: thread-local sums, then one block scan
+    static_assert(SCAN_I % 4 == 0, "whole 16-byte pieces per thread");
     uint32_t loc[SCAN_I];
     uint32_t s = 0;
     size_t tb = base + (size_t)threadIdx.x * SCAN_I;
+    const bool full = vec && tb + SCAN_I <= n;
+    if (full) {
+        const uint4 *v4 = reinterpret_cast<const uint4 *>(in + tb);
 #pragma unroll
-    for (int it = 0; it < SCAN_I; ++it) {
-        size_t e = tb + it;
-        loc[it] = (e < n) ? in[e] : 0u;
-        s += loc[it];
+        for (int q = 0; q < SCAN_I / 4; ++q) {
+            const uint4 v = v4[q];
+            loc[4 * q] = v.x;
+            loc[4 * q + 1] = v.y;
+            loc[4 * q + 2] = v.z;
+            loc[4 * q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < SCAN_I; ++it) {
+            size_t e = tb + it;
+            loc[it] = (e < n) ? in[e] : 0u;
+        }
     }
+#pragma unroll
+    for (int it = 0; it < SCAN_I; ++it) s += loc[it];
     uint32_t tot;
     uint32_t incl = block_incl_scan(s, sh, tot);
     uint32_t run = carry + incl - s;
+    if (full) {
+        uint4 *o4 = reinterpret_cast<uint4 *>(out + tb);
 #pragma unroll
-    for (int it = 0; it < SCAN_I; ++it) {
-        size_t e = tb + it;
-        uint32_t v = loc[it];
-        if (e < n) out[e] = run;
-        run += v;
+        for (int q = 0; q < SCAN_I / 4; ++q) {
+            uint4 v;
+            v.x = run;
+            run += loc[4 * q];
+            v.y = run;
+            run += loc[4 * q + 1];
+            v.z = run;
+            run += loc[4 * q + 2];
+            v.w = run;
+            run += loc[4 * q + 3];
+            o4[q] = v;
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < SCAN_I; ++it) {
+            size_t e = tb + it;
+            uint32_t v = loc[it];
+            if (e < n) out[e] = run;
+            run += v;
+        }
     }
     if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) *d_total = run;
+}
+
+static bool aligned16(const void *a, const void *b) {
+    return (((uintptr_t)a | (uintptr_t)b) & 15u) == 0;
 }
 
 size_t scan_ws_size(size_t n) {
@@ -120,7 +158,7 @@ static void scan_with_ws(const uint32_t *in, uint32_t *out, size_t n, uint32_t *
     size_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (tiles == 1) {
         hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_T), 0, s, in, out, n, (const uint32_t *)nullptr,
-                           d_total);
+                           d_total, aligned16(in, out));
         IG_HIP(hipGetLastError());
         return;
     }
@@ -129,7 +167,7 @@ static void scan_with_ws(const uint32_t *in, uint32_t *out, size_t n, uint32_t *
     IG_HIP(hipGetLastError());
     scan_with_ws(sums, sums, tiles, nullptr, ws + tiles, s);
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, in, out, n, (const uint32_t *)sums,
-                       d_total);
+                       d_total, aligned16(in, out));
     IG_HIP(hipGetLastError());
 }
 
